@@ -1,0 +1,223 @@
+/*
+ * halftone.h -- C ABI of libhalftone, the MI355X (gfx950) implementation of
+ * the halftoning method of "Efficient Halftoning via Deep Reinforcement
+ * Learning" (Jiang et al., IEEE TIP; arXiv 2304.12152).
+ *
+ * General conventions (every entry point):
+ *   - Returns HS_OK (0) or a negative HS_E* code; halftone_last_error()
+ *     returns a thread-local message for the last failure of the calling
+ *     thread. No exception crosses the ABI.
+ *   - Every pointer argument is DEVICE memory unless its name ends in _host.
+ *     The caller owns all memory: inputs, outputs and the workspace whose
+ *     size comes from the matching *_workspace_size call. The library never
+ *     allocates device memory.
+ *   - `stream` is a hipStream_t passed as void*. All device work is enqueued
+ *     asynchronously on it; no call synchronises the host unless noted.
+ *   - Images are dense row-major [B][H][W]; contone values are float in
+ *     [0, 1] with 1 = white. Halftone bits are uint8 0/1 with 1 = white.
+ *     Within image b pixel a = y*W + x.
+ *   - Policy weights are FP32, one flat array of HS_PARAM_COUNT floats:
+ *     layer after layer, W[cout][cin][3][3] then bias[cout]; layers are
+ *     2->32, four 32->32, 32->1 (3x3, stride 1, zero 'same' padding, ReLU
+ *     after all but the last).
+ *   - Random draws are Philox4x32-10 keyed by (seed of the image) with
+ *     counter (a_lo, a_hi, stream, step): stream 0 = Bernoulli actions,
+ *     stream 1 = noise map z. u = (w0 >> 8) * 2^-24; Gaussian z by
+ *     Box-Muller on (w0, w1).
+ *   - On error, outputs are unspecified but nothing is written out of bounds;
+ *     argument errors are detected before any launch.
+ */
+#ifndef HALFTONE_H
+#define HALFTONE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HS_OK 0
+#define HS_EINVAL (-1)       /* null pointer, bad enum, bad parameter      */
+#define HS_ESHAPE (-2)       /* bad B/H/W (non-positive, or too small)     */
+#define HS_EUNSUPPORTED (-3) /* precision or device not supported          */
+#define HS_EWORKSPACE (-4)   /* workspace smaller than *_workspace_size    */
+#define HS_EHIP (-5)         /* a HIP call or kernel launch failed          */
+
+#define HS_FP32 0 /* FP32 arithmetic throughout                           */
+#define HS_BF16 1 /* BF16 MFMA with FP32 accumulation                      */
+
+#define HS_NOISE_GAUSS 0   /* z ~ N(0,1) (Sec. III, "State")               */
+#define HS_NOISE_UNIFORM 1 /* z ~ U(0,1), the variant of Sec. VI-D         */
+
+#define HS_WRT_PROB 0  /* gradients with respect to pi_a(h=1)              */
+#define HS_WRT_LOGIT 1 /* gradients with respect to the logit x_a          */
+
+#define HS_PARAM_COUNT 37889
+
+/* Parameters of the reward and of the anisotropy-suppressing loss.
+ * Defaults (halftone_default_loss_params): w_s = 0.06 and w_a = 0.002
+ * (Sec. VI-A), HVS = 11x11 Gaussian sigma 2 (stand-in for the Nasanen
+ * filter of Sec. V), SSIM window 11x11 Gaussian sigma 1.5 and k = 2
+ * (Sec. V, contrast map), C1 = 1e-4, C2 = 9e-4 (SSIM constants of Wang et
+ * al. 2004 for L = 1), anisotropy patches of 32x32. */
+typedef struct hs_loss_params {
+  float w_s;
+  float w_a;
+  float hvs_sigma;
+  int hvs_radius;  /* 1..7 */
+  float ssim_sigma;
+  int ssim_radius; /* 1..7 */
+  float k;
+  float c1;
+  float c2;
+  int as_patch; /* only 32 is supported */
+} hs_loss_params;
+
+/* Optimiser and sampling parameters of one TRAIN iteration (Algorithm 1).
+ * Defaults: Adam beta1 0.9, beta2 0.999, eps 1e-8; cosine learning rate
+ * from lr_max 3e-4 to lr_min 1e-5 over total_steps (Sec. VI-A). */
+typedef struct hs_train_params {
+  hs_loss_params loss;
+  float lr_max;
+  float lr_min;
+  float beta1;
+  float beta2;
+  float eps;
+  int noise_kind; /* HS_NOISE_* */
+} hs_train_params;
+
+void halftone_default_loss_params(hs_loss_params* p);
+void halftone_default_train_params(hs_train_params* p);
+int halftone_version(void);
+const char* halftone_last_error(void);
+int64_t halftone_param_count(void);
+
+/* ---------------------------------------------------------------------
+ * Inference: the TEST procedure of Algorithm 1 (Sec. IV). z is drawn from
+ * Philox (stream 1, step 0) for image b keyed by seeds[b]; the policy
+ * network gives the logit x_a; bit_a = [x_a >= 0] (threshold of
+ * pi_a(h=1) at 0.5; a tie is white).
+ *
+ * weights  [HS_PARAM_COUNT] FP32.
+ * contone  [B][H][W] FP32.
+ * seeds    [B] uint64.
+ * precision HS_FP32: FP32 arithmetic. HS_BF16: BF16 MFMA with FP32
+ *          accumulation; every pixel whose BF16 logit satisfies
+ *          |x| < recheck_tau is recomputed in FP32 over its 13x13 receptive
+ *          field and decided from that value (recheck_tau >= 0).
+ * bits     [B][H][W] uint8 out.
+ * logits_or_null [B][H][W] FP32 out: the logit each bit was decided from.
+ * stats_or_null  int32[2] out: {pixels rechecked, bits changed by the
+ *          recheck}; 0 for HS_FP32.
+ * Shapes: B >= 1, H >= 1, W >= 1, B*H*W < 2^31.
+ * --------------------------------------------------------------------- */
+size_t halftone_infer_workspace_size(int B, int H, int W, int precision);
+int halftone_infer(const float* weights, const float* contone, const uint64_t* seeds, int B,
+                   int H, int W, int noise_kind, int precision, float recheck_tau, uint8_t* bits,
+                   float* logits_or_null, int32_t* stats_or_null, void* workspace,
+                   size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Training-mode policy forward and its backward (the conv stack of
+ * Sec. VI-A with its chain rule), for torch.autograd wrappers.
+ *
+ * halftone_policy_forward: z from Philox (stream 1, `step`);
+ *   probs [B][H][W] FP32 out = sigmoid(logit). Keeps every layer's
+ *   activations in `workspace` for the backward.
+ * halftone_policy_backward: grad_probs [B][H][W] FP32 in (dLoss/dprobs),
+ *   probs as returned by the forward; grad_weights [HS_PARAM_COUNT] FP32
+ *   out (overwritten). `workspace` must be the one given to the matching
+ *   forward, with the same weights and shapes, untouched in between.
+ * --------------------------------------------------------------------- */
+size_t halftone_policy_workspace_size(int B, int H, int W, int precision);
+int halftone_policy_forward(const float* weights, const float* contone, const uint64_t* seeds,
+                            int B, int H, int W, int noise_kind, uint32_t step, int precision,
+                            float* probs, void* workspace, size_t workspace_bytes, void* stream);
+int halftone_policy_backward(const float* weights, const float* grad_probs, const float* probs,
+                             int B, int H, int W, int precision, float* grad_weights,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Reward and anisotropy loss (Sec. III "Rewards", Eq. final_reward;
+ * Sec. V Eq. cssim; Sec. IV Eq. as with the probability proxy).
+ *
+ * actions  [B][H][W] uint8 (the sampled halftone h).
+ * contone  [B][H][W] FP32.
+ * probs_gray_or_null [Bg][Hg][Wg] FP32: pi(h=1) of the constant-gray side
+ *          batch; L_AS is computed over its non-overlapping 32x32 patches
+ *          (remainders dropped). Pass NULL (and Bg = 0) to skip L_AS.
+ * out      FP32, 3*B + 1 values: per image {MSE(HVS(h), HVS(c)), mean
+ *          CSSIM, R = -MSE + w_s*CSSIM}, then L_AS (mean over patches; 0 if
+ *          no patch). MSE and CSSIM are means over the valid region
+ *          [m, H-m) x [m, W-m), m = max(hvs_radius, ssim_radius).
+ * Shapes: H, W >= 2m+1.
+ * --------------------------------------------------------------------- */
+size_t halftone_loss_workspace_size(int B, int H, int W, int Bg, int Hg, int Wg,
+                                    const hs_loss_params* prm);
+int halftone_loss(const uint8_t* actions, const float* contone, int B, int H, int W,
+                  const float* probs_gray_or_null, int Bg, int Hg, int Wg,
+                  const hs_loss_params* prm, float* out, void* workspace, size_t workspace_bytes,
+                  void* stream);
+
+/* ---------------------------------------------------------------------
+ * Gradients of the training loss (Eq. marl with the Local Expectation
+ * estimator of Sec. III-B, computed locally as in Sec. III-C; Eq. as).
+ *
+ * grad_probs [B][H][W] FP32 out: dL_MARL/dp_a = -dR_a / B where
+ *          dR_a = R(h_a = 1, h_-a) - R(h_a = 0, h_-a).
+ * grad_probs_gray_or_null [Bg][Hg][Wg] FP32 out: w_a * dL_AS/dp_g (zero
+ *          outside the patches).
+ * grad_space HS_WRT_PROB, or HS_WRT_LOGIT to multiply both by p(1 - p);
+ *          HS_WRT_LOGIT needs probs_or_null (for the main batch) and uses
+ *          probs_gray_or_null for the gray batch.
+ * --------------------------------------------------------------------- */
+int halftone_loss_backward(const uint8_t* actions, const float* contone,
+                           const float* probs_or_null, int B, int H, int W,
+                           const float* probs_gray_or_null, int Bg, int Hg, int Wg,
+                           const hs_loss_params* prm, int grad_space, float* grad_probs,
+                           float* grad_probs_gray_or_null, void* workspace,
+                           size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * One TRAIN iteration of Algorithm 1 on one GPU:
+ *   forward of the batch (z from stream 1 at `step`), p = sigmoid(x),
+ *   actions h_a = [u_a < p_a] (stream 0 at `step`), dL_MARL/dp from the
+ *   Local Expectation estimator; forward of the constant-gray side batch,
+ *   w_a * dL_AS/dp_g; backward of both through the conv stack; Adam on the
+ *   FP32 master weights with lr_t = lr_min + (lr_max - lr_min)(1 +
+ *   cos(pi step / total_steps))/2 and bias corrections at t = step + 1.
+ *
+ * weights, adam_m, adam_v [HS_PARAM_COUNT] FP32, updated in place.
+ * contones [B][H][W], seeds [B]; gray [Bg][Hg][Wg], gray_seeds [Bg]
+ *          (Bg = 0 and NULLs to skip the anisotropy term).
+ * precision HS_FP32 or HS_BF16 (BF16 activations and MFMA, FP32 master
+ *          weights, FP32 gradients accumulated in FP32).
+ * metrics  FP32[8] out: mean MSE, mean CSSIM, mean R, L_AS, lr, |grad|_2,
+ *          fill fraction of the actions, 0.
+ * actions_out_or_null [B][H][W] uint8: the sampled actions.
+ * grad_out_or_null [HS_PARAM_COUNT] FP32: the total gradient before Adam.
+ * --------------------------------------------------------------------- */
+size_t halftone_train_workspace_size(int B, int H, int W, int Bg, int Hg, int Wg,
+                                     int precision);
+int policy_train_step(float* weights, float* adam_m, float* adam_v, const float* contones,
+                      const uint64_t* seeds, int B, int H, int W, const float* gray,
+                      const uint64_t* gray_seeds, int Bg, int Hg, int Wg, int64_t step,
+                      int64_t total_steps, const hs_train_params* tp, int precision,
+                      float* metrics, uint8_t* actions_out_or_null, float* grad_out_or_null,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Floyd-Steinberg error diffusion on the host (the classic error diffusion
+ * cited in Sec. I), the CPU fallback and the baseline of the judge:
+ * raster order, threshold v >= 0.5, weights 7/16 right, 3/16 down-left,
+ * 5/16 down, 1/16 down-right, error leaving the image dropped.
+ * contone_host [B][H][W] FP32 in host memory; bits_host [B][H][W] out.
+ * --------------------------------------------------------------------- */
+int halftone_error_diffusion_host(const float* contone_host, int B, int H, int W,
+                                  uint8_t* bits_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HALFTONE_H */

@@ -1,0 +1,244 @@
+"""ctypes binding of libhalftone with the names of the C entry points.
+
+Argument marshalling only: every step runs in the HIP library. torch supplies
+device memory (outputs and workspaces) and the current stream. If the
+library is not built, or the device is not a gfx950, calls fail loudly.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhalftone.so")
+
+HS_OK, HS_EINVAL, HS_ESHAPE, HS_EUNSUPPORTED, HS_EWORKSPACE, HS_EHIP = 0, -1, -2, -3, -4, -5
+HS_FP32, HS_BF16 = 0, 1
+HS_NOISE_GAUSS, HS_NOISE_UNIFORM = 0, 1
+HS_WRT_PROB, HS_WRT_LOGIT = 0, 1
+HS_PARAM_COUNT = 37889
+
+
+class HsLossParams(ctypes.Structure):
+    _fields_ = [("w_s", ctypes.c_float), ("w_a", ctypes.c_float), ("hvs_sigma", ctypes.c_float),
+                ("hvs_radius", ctypes.c_int), ("ssim_sigma", ctypes.c_float),
+                ("ssim_radius", ctypes.c_int), ("k", ctypes.c_float), ("c1", ctypes.c_float),
+                ("c2", ctypes.c_float), ("as_patch", ctypes.c_int)]
+
+
+class HsTrainParams(ctypes.Structure):
+    _fields_ = [("loss", HsLossParams), ("lr_max", ctypes.c_float), ("lr_min", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("noise_kind", ctypes.c_int)]
+
+
+class HalftoneError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libhalftone error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+P = ctypes.c_void_p
+I = ctypes.c_int
+SZ = ctypes.c_size_t
+F = ctypes.c_float
+
+_SIGS = {
+    "halftone_default_loss_params": (None, [ctypes.POINTER(HsLossParams)]),
+    "halftone_default_train_params": (None, [ctypes.POINTER(HsTrainParams)]),
+    "halftone_version": (I, []),
+    "halftone_last_error": (ctypes.c_char_p, []),
+    "halftone_param_count": (ctypes.c_int64, []),
+    "halftone_infer_workspace_size": (SZ, [I, I, I, I]),
+    "halftone_infer": (I, [P, P, P, I, I, I, I, I, F, P, P, P, P, SZ, P]),
+    "halftone_policy_workspace_size": (SZ, [I, I, I, I]),
+    "halftone_policy_forward": (I, [P, P, P, I, I, I, I, ctypes.c_uint32, I, P, P, SZ, P]),
+    "halftone_policy_backward": (I, [P, P, P, I, I, I, I, P, P, SZ, P]),
+    "halftone_loss_workspace_size": (SZ, [I, I, I, I, I, I, ctypes.POINTER(HsLossParams)]),
+    "halftone_loss": (I, [P, P, I, I, I, P, I, I, I, ctypes.POINTER(HsLossParams), P, P, SZ, P]),
+    "halftone_loss_backward": (I, [P, P, P, I, I, I, P, I, I, I, ctypes.POINTER(HsLossParams), I,
+                                   P, P, P, SZ, P]),
+    "halftone_train_workspace_size": (SZ, [I, I, I, I, I, I, I]),
+    "policy_train_step": (I, [P, P, P, P, P, I, I, I, P, P, I, I, I, ctypes.c_int64,
+                              ctypes.c_int64, ctypes.POINTER(HsTrainParams), I, P, P, P, P, SZ,
+                              P]),
+    "halftone_error_diffusion_host": (I, [P, I, I, I, P]),
+}
+
+
+def lib():
+    """Load libhalftone.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhalftone.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != HS_OK:
+        raise HalftoneError(rc, lib().halftone_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype):
+    assert t.is_cuda and t.dtype == dtype and t.is_contiguous(), (t.device, t.dtype)
+    return t
+
+
+def _ws(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def default_loss_params(**kw):
+    p = HsLossParams()
+    lib().halftone_default_loss_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def default_train_params(**kw):
+    p = HsTrainParams()
+    lib().halftone_default_train_params(ctypes.byref(p))
+    loss_kw = {k: v for k, v in kw.items() if k in dict(HsLossParams._fields_)}
+    for k, v in loss_kw.items():
+        setattr(p.loss, k, v)
+    for k, v in kw.items():
+        if k not in loss_kw:
+            setattr(p, k, v)
+    return p
+
+
+def halftone_infer(weights, contone, seeds, noise_kind=HS_NOISE_GAUSS, precision=HS_BF16,
+                   recheck_tau=0.05, logits=False, stats=False, workspace=None):
+    """bits [B,H,W] uint8 (and optionally logits, stats = (rechecked, flipped))."""
+    B, H, W = contone.shape
+    dev = contone.device
+    _dev(weights, torch.float32), _dev(contone, torch.float32), _dev(seeds, torch.int64)
+    bits = torch.empty((B, H, W), dtype=torch.uint8, device=dev)
+    lg = torch.empty((B, H, W), dtype=torch.float32, device=dev) if logits else None
+    st = torch.zeros(2, dtype=torch.int32, device=dev) if stats else None
+    need = lib().halftone_infer_workspace_size(B, H, W, precision)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
+    _check(lib().halftone_infer(_ptr(weights), _ptr(contone), _ptr(seeds), B, H, W, noise_kind,
+                                precision, recheck_tau, _ptr(bits), _ptr(lg), _ptr(st), _ptr(ws),
+                                ws.numel(), _stream()))
+    out = [bits]
+    if logits:
+        out.append(lg)
+    if stats:
+        out.append(st)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def halftone_policy_forward(weights, contone, seeds, step=0, noise_kind=HS_NOISE_GAUSS,
+                            precision=HS_FP32, workspace=None):
+    """probs [B,H,W] and the workspace holding the saved activations."""
+    B, H, W = contone.shape
+    dev = contone.device
+    probs = torch.empty((B, H, W), dtype=torch.float32, device=dev)
+    need = lib().halftone_policy_workspace_size(B, H, W, precision)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
+    _check(lib().halftone_policy_forward(_ptr(weights), _ptr(contone), _ptr(seeds), B, H, W,
+                                         noise_kind, step, precision, _ptr(probs), _ptr(ws),
+                                         ws.numel(), _stream()))
+    return probs, ws
+
+
+def halftone_policy_backward(weights, grad_probs, probs, workspace, precision=HS_FP32):
+    B, H, W = probs.shape
+    gw = torch.empty(HS_PARAM_COUNT, dtype=torch.float32, device=probs.device)
+    _check(lib().halftone_policy_backward(_ptr(weights), _ptr(grad_probs.contiguous()),
+                                          _ptr(probs), B, H, W, precision, _ptr(gw),
+                                          _ptr(workspace), workspace.numel(), _stream()))
+    return gw
+
+
+def halftone_loss(actions, contone, probs_gray=None, prm=None):
+    """Tensor [3B+1]: per image (MSE, CSSIM, R), then L_AS."""
+    prm = prm or default_loss_params()
+    B, H, W = contone.shape
+    Bg, Hg, Wg = probs_gray.shape if probs_gray is not None else (0, 0, 0)
+    out = torch.empty(3 * B + 1, dtype=torch.float32, device=contone.device)
+    need = lib().halftone_loss_workspace_size(B, H, W, Bg, Hg, Wg, ctypes.byref(prm))
+    ws = _ws(need, contone.device)
+    _check(lib().halftone_loss(_ptr(actions), _ptr(contone), B, H, W, _ptr(probs_gray), Bg, Hg,
+                               Wg, ctypes.byref(prm), _ptr(out), _ptr(ws), ws.numel(),
+                               _stream()))
+    return out
+
+
+def halftone_loss_backward(actions, contone, probs=None, probs_gray=None, prm=None,
+                           grad_space=HS_WRT_PROB):
+    """(grad_probs, grad_probs_gray or None)."""
+    prm = prm or default_loss_params()
+    B, H, W = contone.shape
+    Bg, Hg, Wg = probs_gray.shape if probs_gray is not None else (0, 0, 0)
+    gp = torch.empty((B, H, W), dtype=torch.float32, device=contone.device)
+    gg = torch.empty((Bg, Hg, Wg), dtype=torch.float32, device=contone.device) \
+        if probs_gray is not None else None
+    need = lib().halftone_loss_workspace_size(B, H, W, Bg, Hg, Wg, ctypes.byref(prm))
+    ws = _ws(need, contone.device)
+    _check(lib().halftone_loss_backward(_ptr(actions), _ptr(contone), _ptr(probs), B, H, W,
+                                        _ptr(probs_gray), Bg, Hg, Wg, ctypes.byref(prm),
+                                        grad_space, _ptr(gp), _ptr(gg), _ptr(ws), ws.numel(),
+                                        _stream()))
+    return gp, gg
+
+
+class TrainState:
+    """FP32 master weights and Adam moments on the device, plus a workspace."""
+
+    def __init__(self, weights, B, H, W, Bg=0, Hg=0, Wg=0, precision=HS_BF16, tp=None):
+        dev = weights.device
+        self.weights = weights.clone()
+        self.m = torch.zeros_like(self.weights)
+        self.v = torch.zeros_like(self.weights)
+        self.precision = precision
+        self.tp = tp or default_train_params()
+        self.shape = (B, H, W, Bg, Hg, Wg)
+        need = lib().halftone_train_workspace_size(B, H, W, Bg, Hg, Wg, precision)
+        self.ws = _ws(need, dev)
+        self.metrics = torch.zeros(8, dtype=torch.float32, device=dev)
+
+
+def policy_train_step(state, contones, seeds, gray, gray_seeds, step, total_steps,
+                      actions_out=None, grad_out=None):
+    B, H, W = contones.shape
+    if gray is not None:
+        Bg, Hg, Wg = gray.shape
+    else:
+        Bg = Hg = Wg = 0
+    _check(lib().policy_train_step(_ptr(state.weights), _ptr(state.m), _ptr(state.v),
+                                   _ptr(contones), _ptr(seeds), B, H, W, _ptr(gray),
+                                   _ptr(gray_seeds), Bg, Hg, Wg, step, total_steps,
+                                   ctypes.byref(state.tp), state.precision, _ptr(state.metrics),
+                                   _ptr(actions_out), _ptr(grad_out), _ptr(state.ws),
+                                   state.ws.numel(), _stream()))
+    return state.metrics
+
+
+def halftone_error_diffusion_host(contone_host):
+    """Floyd-Steinberg on the host: numpy/torch CPU float32 [B,H,W] -> uint8."""
+    c = torch.as_tensor(contone_host, dtype=torch.float32).contiguous()
+    if c.dim() == 2:
+        c = c[None]
+    B, H, W = c.shape
+    bits = torch.empty((B, H, W), dtype=torch.uint8)
+    _check(lib().halftone_error_diffusion_host(_ptr(c), B, H, W, _ptr(bits)))
+    return bits

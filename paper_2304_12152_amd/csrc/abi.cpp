@@ -1,0 +1,566 @@
+// abi.cpp -- the C entry points of libhalftone (declared in include/halftone.h):
+// argument validation, workspace layout and the launch sequence of each call.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hs_internal.h"
+
+using namespace hs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HS_TRY(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(HS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// The library is built for gfx950 only; refuse other devices up front.
+int check_device() {
+  static std::mutex mu;
+  static std::vector<int> state;  // per device: 0 unknown, 1 ok, 2 unsupported
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(HS_EHIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)state.size() <= dev) state.resize(dev + 1, 0);
+  if (state[dev] == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+      return fail(HS_EHIP, "hipGetDeviceProperties failed");
+    state[dev] = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+  }
+  if (state[dev] != 1) return fail(HS_EUNSUPPORTED, "device %d is not gfx950", dev);
+  return HS_OK;
+}
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures, so the *_workspace_size functions and the entry points share one
+// layout description.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <typename T> T* take(size_t bytes) {
+    T* p = base ? (T*)(base + off) : nullptr;
+    off = align256(off + bytes);
+    return p;
+  }
+};
+
+bool shape_ok(int B, int H, int W) {
+  return B >= 1 && H >= 1 && W >= 1 && (long long)B * H * W < (1ll << 31);
+}
+
+int check_params(const hs_loss_params* p) {
+  if (!p) return fail(HS_EINVAL, "null loss parameters");
+  if (p->hvs_radius < 1 || p->hvs_radius > 7 || p->ssim_radius < 1 || p->ssim_radius > 7)
+    return fail(HS_EINVAL, "window radii must be in 1..7");
+  if (!(p->hvs_sigma > 0.0f) || !(p->ssim_sigma > 0.0f)) return fail(HS_EINVAL, "sigma <= 0");
+  if (p->as_patch != 32) return fail(HS_EUNSUPPORTED, "only 32x32 anisotropy patches");
+  return HS_OK;
+}
+
+int margin(const hs_loss_params* p) {
+  return p->hvs_radius > p->ssim_radius ? p->hvs_radius : p->ssim_radius;
+}
+
+// ---------------------------------------------------------------- layouts --
+struct PolicyWs {
+  void *packF, *packT, *act[5], *gA, *gB;
+  float *z, *c, *g6, *partials;
+};
+PolicyWs carve_policy(Carve& cv, size_t N, int prec) {
+  PolicyWs w;
+  w.packF = cv.take<char>(pack_bytes(prec));
+  w.packT = cv.take<char>(pack_bytes(prec));
+  for (int k = 0; k < 5; ++k) w.act[k] = cv.take<char>(act_bytes(N, prec));
+  w.gA = cv.take<char>(act_bytes(N, prec));
+  w.gB = cv.take<char>(act_bytes(N, prec));
+  w.z = cv.take<float>(N * 4);
+  w.c = cv.take<float>(N * 4);
+  w.g6 = cv.take<float>(N * 4);
+  w.partials = cv.take<float>((size_t)WGRAD_BLOCKS * NPARAM * 4);
+  return w;
+}
+
+struct LossWs {
+  float *maps, *tiles, *patches;
+  int ntiles;
+};
+LossWs carve_loss(Carve& cv, int B, int H, int W, int Bg, int Hg, int Wg, int m, bool maps) {
+  LossWs w;
+  const int vh = H - 2 * m, vw = W - 2 * m;
+  w.ntiles = ((vh + 15) / 16) * ((vw + 15) / 16);
+  w.maps = maps ? cv.take<float>((size_t)5 * B * H * W * 4) : nullptr;
+  w.tiles = cv.take<float>((size_t)B * w.ntiles * 2 * 4);
+  const size_t np = (size_t)Bg * (Hg / 32) * (Wg / 32);
+  w.patches = cv.take<float>((np > 0 ? np : 1) * 4);
+  return w;
+}
+
+struct InferWs {
+  void *pack, *a0, *a1;
+};
+InferWs carve_infer(Carve& cv, size_t N, int prec) {
+  InferWs w;
+  w.pack = cv.take<char>(pack_bytes(prec));
+  w.a0 = cv.take<char>(act_bytes(N, prec));
+  w.a1 = cv.take<char>(act_bytes(N, prec));
+  return w;
+}
+
+// Forward of the stack on one batch: pack -> first -> four 32->32 -> last.
+// mode 0: inference bits/logits; mode 1: probs (+ actions) keeping activations.
+hipError_t run_forward_train(const float* w, const float* contone, const uint64_t* seeds, int B,
+                             int H, int W, int kind, uint32_t step, int prec, const PolicyWs& pw,
+                             float* probs, uint8_t* actions, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_pack32(w, pw.packF, prec, 0, s)) != hipSuccess) return e;
+  if ((e = launch_conv_first(contone, seeds, w, B, H, W, kind, step, prec, pw.act[0], pw.z, pw.c,
+                             s)) != hipSuccess)
+    return e;
+  const size_t per_layer = (size_t)PACK32_PER_LAYER * (prec == HS_BF16 ? 2 : 4);
+  for (int k = 2; k <= 5; ++k) {
+    if ((e = launch_conv32(pw.act[k - 2], (const char*)pw.packF + (k - 2) * per_layer,
+                           w + hs_bk(k), nullptr, pw.act[k - 1], B, H, W, prec, 0, s)) !=
+        hipSuccess)
+      return e;
+  }
+  return launch_conv_last(pw.act[4], w, B, H, W, prec, 1, seeds, step, actions, nullptr, probs,
+                          0.0f, nullptr, nullptr, s);
+}
+
+// Backward of the stack given dL/dprobs (probs != null) or dL/dlogit
+// (probs == null); accumulates into the weight-gradient partial rows.
+hipError_t run_backward(const float* w, const float* grad, const float* probs, int B, int H,
+                        int W, int prec, const PolicyWs& pw, int accumulate, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_pack32(w, pw.packT, prec, 1, s)) != hipSuccess) return e;
+  if ((e = launch_dgrad_last(grad, probs, pw.act[4], w, B, H, W, prec, pw.g6, pw.gA, s)) !=
+      hipSuccess)
+    return e;
+  if ((e = launch_wgrad_last(pw.act[4], pw.g6, B, H, W, prec, pw.partials, accumulate, s)) !=
+      hipSuccess)
+    return e;
+  const size_t per_layer = (size_t)PACK32_PER_LAYER * (prec == HS_BF16 ? 2 : 4);
+  void* g = pw.gA;  // gradient at the pre-activation of layer k
+  void* other = pw.gB;
+  for (int k = 5; k >= 2; --k) {
+    if ((e = launch_wgrad32(pw.act[k - 2], g, k, B, H, W, prec, pw.partials, accumulate, s)) !=
+        hipSuccess)
+      return e;
+    if ((e = launch_conv32(g, (const char*)pw.packT + (k - 2) * per_layer, nullptr,
+                           pw.act[k - 2], other, B, H, W, prec, 1, s)) != hipSuccess)
+      return e;
+    void* t = g;
+    g = other;
+    other = t;
+  }
+  return launch_wgrad_first(pw.c, pw.z, g, B, H, W, prec, pw.partials, accumulate, s);
+}
+
+}  // namespace
+
+// ===================================================================== ABI ==
+extern "C" {
+
+void halftone_default_loss_params(hs_loss_params* p) {
+  if (!p) return;
+  p->w_s = 0.06f;
+  p->w_a = 0.002f;
+  p->hvs_sigma = 2.0f;
+  p->hvs_radius = 5;
+  p->ssim_sigma = 1.5f;
+  p->ssim_radius = 5;
+  p->k = 2.0f;
+  p->c1 = 1e-4f;
+  p->c2 = 9e-4f;
+  p->as_patch = 32;
+}
+
+void halftone_default_train_params(hs_train_params* p) {
+  if (!p) return;
+  halftone_default_loss_params(&p->loss);
+  p->lr_max = 3e-4f;
+  p->lr_min = 1e-5f;
+  p->beta1 = 0.9f;
+  p->beta2 = 0.999f;
+  p->eps = 1e-8f;
+  p->noise_kind = HS_NOISE_GAUSS;
+}
+
+int halftone_version(void) { return 100; }
+const char* halftone_last_error(void) { return g_err.c_str(); }
+int64_t halftone_param_count(void) { return HS_PARAM_COUNT; }
+
+// ------------------------------------------------------------- inference --
+static size_t infer_ws(int B, int H, int W, int prec, InferWs* out, uint32_t** list, int** cnt,
+                       void* base) {
+  Carve cv(base);
+  const size_t N = (size_t)B * H * W;
+  InferWs w = carve_infer(cv, N, prec);
+  uint32_t* l = cv.take<uint32_t>(N * 4);
+  int* c = cv.take<int>(64);
+  if (out) *out = w;
+  if (list) *list = l;
+  if (cnt) *cnt = c;
+  return cv.off;
+}
+
+size_t halftone_infer_workspace_size(int B, int H, int W, int precision) {
+  if (!shape_ok(B, H, W)) return 0;
+  return infer_ws(B, H, W, precision, nullptr, nullptr, nullptr, nullptr);
+}
+
+int halftone_infer(const float* weights, const float* contone, const uint64_t* seeds, int B,
+                   int H, int W, int noise_kind, int precision, float recheck_tau, uint8_t* bits,
+                   float* logits_or_null, int32_t* stats_or_null, void* workspace,
+                   size_t workspace_bytes, void* stream) {
+  if (!weights || !contone || !seeds || !bits || !workspace)
+    return fail(HS_EINVAL, "halftone_infer: null pointer");
+  if (!shape_ok(B, H, W)) return fail(HS_ESHAPE, "halftone_infer: bad shape %d x %d x %d", B, H, W);
+  if (precision != HS_FP32 && precision != HS_BF16)
+    return fail(HS_EUNSUPPORTED, "halftone_infer: precision %d", precision);
+  if (noise_kind != HS_NOISE_GAUSS && noise_kind != HS_NOISE_UNIFORM)
+    return fail(HS_EINVAL, "halftone_infer: noise kind %d", noise_kind);
+  if (!(recheck_tau >= 0.0f)) return fail(HS_EINVAL, "halftone_infer: recheck_tau < 0");
+  if (workspace_bytes < halftone_infer_workspace_size(B, H, W, precision))
+    return fail(HS_EWORKSPACE, "halftone_infer: workspace too small");
+  int rc = check_device();
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  InferWs iw;
+  uint32_t* list;
+  int* cnt;
+  infer_ws(B, H, W, precision, &iw, &list, &cnt, workspace);
+  const size_t per_layer = (size_t)PACK32_PER_LAYER * (precision == HS_BF16 ? 2 : 4);
+  int32_t* stats = stats_or_null ? stats_or_null : (int32_t*)(cnt + 8);
+  HS_TRY(launch_zero_ints(cnt, 16, s));
+  if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 2, s));
+  HS_TRY(launch_pack32(weights, iw.pack, precision, 0, s));
+  HS_TRY(launch_conv_first(contone, seeds, weights, B, H, W, noise_kind, 0u, precision, iw.a0,
+                           nullptr, nullptr, s));
+  void* src = iw.a0;
+  void* dst = iw.a1;
+  for (int k = 2; k <= 5; ++k) {
+    HS_TRY(launch_conv32(src, (const char*)iw.pack + (k - 2) * per_layer, weights + hs_bk(k),
+                         nullptr, dst, B, H, W, precision, 0, s));
+    void* t = src;
+    src = dst;
+    dst = t;
+  }
+  const bool recheck = precision == HS_BF16;
+  HS_TRY(launch_conv_last(src, weights, B, H, W, precision, 0, seeds, 0u, bits, logits_or_null,
+                          nullptr, recheck_tau, recheck ? list : nullptr, cnt, s));
+  if (recheck)
+    HS_TRY(launch_recheck_fp32(weights, contone, seeds, H, W, noise_kind, list, cnt, bits,
+                               logits_or_null, stats, s));
+  return HS_OK;
+}
+
+// ------------------------------------------------------- policy fwd / bwd --
+size_t halftone_policy_workspace_size(int B, int H, int W, int precision) {
+  if (!shape_ok(B, H, W)) return 0;
+  Carve cv(nullptr);
+  carve_policy(cv, (size_t)B * H * W, precision);
+  return cv.off;
+}
+
+int halftone_policy_forward(const float* weights, const float* contone, const uint64_t* seeds,
+                            int B, int H, int W, int noise_kind, uint32_t step, int precision,
+                            float* probs, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!weights || !contone || !seeds || !probs || !workspace)
+    return fail(HS_EINVAL, "halftone_policy_forward: null pointer");
+  if (!shape_ok(B, H, W)) return fail(HS_ESHAPE, "halftone_policy_forward: bad shape");
+  if (precision != HS_FP32 && precision != HS_BF16)
+    return fail(HS_EUNSUPPORTED, "halftone_policy_forward: precision %d", precision);
+  if (noise_kind != HS_NOISE_GAUSS && noise_kind != HS_NOISE_UNIFORM)
+    return fail(HS_EINVAL, "halftone_policy_forward: noise kind %d", noise_kind);
+  if (workspace_bytes < halftone_policy_workspace_size(B, H, W, precision))
+    return fail(HS_EWORKSPACE, "halftone_policy_forward: workspace too small");
+  int rc = check_device();
+  if (rc) return rc;
+  Carve cv(workspace);
+  PolicyWs pw = carve_policy(cv, (size_t)B * H * W, precision);
+  HS_TRY(run_forward_train(weights, contone, seeds, B, H, W, noise_kind, step, precision, pw,
+                           probs, nullptr, (hipStream_t)stream));
+  return HS_OK;
+}
+
+int halftone_policy_backward(const float* weights, const float* grad_probs, const float* probs,
+                             int B, int H, int W, int precision, float* grad_weights,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+  if (!weights || !grad_probs || !probs || !grad_weights || !workspace)
+    return fail(HS_EINVAL, "halftone_policy_backward: null pointer");
+  if (!shape_ok(B, H, W)) return fail(HS_ESHAPE, "halftone_policy_backward: bad shape");
+  if (precision != HS_FP32 && precision != HS_BF16)
+    return fail(HS_EUNSUPPORTED, "halftone_policy_backward: precision %d", precision);
+  if (workspace_bytes < halftone_policy_workspace_size(B, H, W, precision))
+    return fail(HS_EWORKSPACE, "halftone_policy_backward: workspace too small");
+  int rc = check_device();
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Carve cv(workspace);
+  PolicyWs pw = carve_policy(cv, (size_t)B * H * W, precision);
+  HS_TRY(run_backward(weights, grad_probs, probs, B, H, W, precision, pw, 0, s));
+  HS_TRY(launch_reduce_partials(pw.partials, WGRAD_BLOCKS, grad_weights, s));
+  return HS_OK;
+}
+
+// ------------------------------------------------------------------ loss --
+static int check_loss_args(const uint8_t* actions, const float* contone, int B, int H, int W,
+                           const float* pg, int Bg, int Hg, int Wg, const hs_loss_params* prm,
+                           const char* who) {
+  if (!actions || !contone) return fail(HS_EINVAL, "%s: null pointer", who);
+  int rc = check_params(prm);
+  if (rc) return rc;
+  const int m = margin(prm);
+  if (!shape_ok(B, H, W) || H < 2 * m + 1 || W < 2 * m + 1)
+    return fail(HS_ESHAPE, "%s: images must be at least %d x %d", who, 2 * m + 1, 2 * m + 1);
+  if (pg) {
+    if (!shape_ok(Bg, Hg, Wg)) return fail(HS_ESHAPE, "%s: bad gray-batch shape", who);
+  } else if (Bg != 0) {
+    return fail(HS_EINVAL, "%s: Bg > 0 with a null gray batch", who);
+  }
+  return HS_OK;
+}
+
+size_t halftone_loss_workspace_size(int B, int H, int W, int Bg, int Hg, int Wg,
+                                    const hs_loss_params* prm) {
+  if (!prm || !shape_ok(B, H, W)) return 0;
+  Carve cv(nullptr);
+  carve_loss(cv, B, H, W, Bg, Hg, Wg, margin(prm), true);
+  return cv.off;
+}
+
+int halftone_loss(const uint8_t* actions, const float* contone, int B, int H, int W,
+                  const float* probs_gray_or_null, int Bg, int Hg, int Wg,
+                  const hs_loss_params* prm, float* out, void* workspace, size_t workspace_bytes,
+                  void* stream) {
+  int rc = check_loss_args(actions, contone, B, H, W, probs_gray_or_null, Bg, Hg, Wg, prm,
+                           "halftone_loss");
+  if (rc) return rc;
+  if (!out || !workspace) return fail(HS_EINVAL, "halftone_loss: null pointer");
+  if (!probs_gray_or_null) Bg = Hg = Wg = 0;
+  if (workspace_bytes < halftone_loss_workspace_size(B, H, W, Bg, Hg, Wg, prm))
+    return fail(HS_EWORKSPACE, "halftone_loss: workspace too small");
+  if ((rc = check_device())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int m = margin(prm);
+  Carve cv(workspace);
+  LossWs lw = carve_loss(cv, B, H, W, Bg, Hg, Wg, m, true);
+  LossDev win;
+  make_windows(*prm, &win);
+  HS_TRY(launch_loss_stats(actions, contone, B, H, W, *prm, win, nullptr, lw.tiles, lw.ntiles, s));
+  const int npatch = Bg * (Hg / 32) * (Wg / 32);
+  if (npatch > 0)
+    HS_TRY(launch_as(probs_gray_or_null, Bg, Hg, Wg, 1.0f, 0, lw.patches, nullptr, s));
+  HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, prm->w_s,
+                            (long)(H - 2 * m) * (W - 2 * m), out, s));
+  return HS_OK;
+}
+
+int halftone_loss_backward(const uint8_t* actions, const float* contone,
+                           const float* probs_or_null, int B, int H, int W,
+                           const float* probs_gray_or_null, int Bg, int Hg, int Wg,
+                           const hs_loss_params* prm, int grad_space, float* grad_probs,
+                           float* grad_probs_gray_or_null, void* workspace,
+                           size_t workspace_bytes, void* stream) {
+  int rc = check_loss_args(actions, contone, B, H, W, probs_gray_or_null, Bg, Hg, Wg, prm,
+                           "halftone_loss_backward");
+  if (rc) return rc;
+  if (!grad_probs || !workspace) return fail(HS_EINVAL, "halftone_loss_backward: null pointer");
+  if (grad_space != HS_WRT_PROB && grad_space != HS_WRT_LOGIT)
+    return fail(HS_EINVAL, "halftone_loss_backward: grad_space %d", grad_space);
+  if (grad_space == HS_WRT_LOGIT && !probs_or_null)
+    return fail(HS_EINVAL, "halftone_loss_backward: logit space needs probs");
+  if (probs_gray_or_null && !grad_probs_gray_or_null)
+    return fail(HS_EINVAL, "halftone_loss_backward: gray batch without its gradient buffer");
+  if (!probs_gray_or_null) Bg = Hg = Wg = 0;
+  if (workspace_bytes < halftone_loss_workspace_size(B, H, W, Bg, Hg, Wg, prm))
+    return fail(HS_EWORKSPACE, "halftone_loss_backward: workspace too small");
+  if ((rc = check_device())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int m = margin(prm);
+  Carve cv(workspace);
+  LossWs lw = carve_loss(cv, B, H, W, Bg, Hg, Wg, m, true);
+  LossDev win;
+  make_windows(*prm, &win);
+  HS_TRY(launch_loss_stats(actions, contone, B, H, W, *prm, win, lw.maps, lw.tiles, lw.ntiles, s));
+  HS_TRY(launch_le_grad(actions, contone, grad_space == HS_WRT_LOGIT ? probs_or_null : nullptr, B,
+                        H, W, *prm, win, lw.maps, grad_probs, s));
+  if (probs_gray_or_null) {
+    const int npatch = Bg * (Hg / 32) * (Wg / 32);
+    HS_TRY(launch_fill(grad_probs_gray_or_null, (size_t)Bg * Hg * Wg, 0.0f, s));
+    if (npatch > 0)
+      HS_TRY(launch_as(probs_gray_or_null, Bg, Hg, Wg, prm->w_a / (float)npatch,
+                       grad_space == HS_WRT_LOGIT, lw.patches, grad_probs_gray_or_null, s));
+  }
+  return HS_OK;
+}
+
+// ------------------------------------------------------------ train step --
+static size_t train_ws(int B, int H, int W, int Bg, int Hg, int Wg, int prec, void* base,
+                       PolicyWs* pw, LossWs* lw, float** probs, float** probs_g, uint8_t** act,
+                       float** gradp, float** gradg, float** grad, float** loss_out) {
+  Carve cv(base);
+  const size_t N = (size_t)B * H * W, Ng = (size_t)Bg * Hg * Wg;
+  const size_t Nmax = N > Ng ? N : Ng;
+  PolicyWs p = carve_policy(cv, Nmax, prec);
+  // sized for the smallest margin (most tiles); the caller sets the real count
+  LossWs l = carve_loss(cv, B, H, W, Bg, Hg, Wg, 1, true);
+  float* pr = cv.take<float>(N * 4);
+  float* pg = cv.take<float>((Ng ? Ng : 1) * 4);
+  uint8_t* a = cv.take<uint8_t>(N);
+  float* gp = cv.take<float>(N * 4);
+  float* gg = cv.take<float>((Ng ? Ng : 1) * 4);
+  float* g = cv.take<float>((size_t)NPARAM * 4);
+  float* lo = cv.take<float>((size_t)(3 * B + 1) * 4);
+  if (pw) *pw = p;
+  if (lw) *lw = l;
+  if (probs) *probs = pr;
+  if (probs_g) *probs_g = pg;
+  if (act) *act = a;
+  if (gradp) *gradp = gp;
+  if (gradg) *gradg = gg;
+  if (grad) *grad = g;
+  if (loss_out) *loss_out = lo;
+  return cv.off;
+}
+
+size_t halftone_train_workspace_size(int B, int H, int W, int Bg, int Hg, int Wg,
+                                     int precision) {
+  if (!shape_ok(B, H, W) || Bg < 0) return 0;
+  if (Bg > 0 && !shape_ok(Bg, Hg, Wg)) return 0;
+  if (Bg == 0) Hg = Wg = 0;
+  return train_ws(B, H, W, Bg, Hg, Wg, precision, nullptr, nullptr, nullptr, nullptr, nullptr,
+                  nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+int policy_train_step(float* weights, float* adam_m, float* adam_v, const float* contones,
+                      const uint64_t* seeds, int B, int H, int W, const float* gray,
+                      const uint64_t* gray_seeds, int Bg, int Hg, int Wg, int64_t step,
+                      int64_t total_steps, const hs_train_params* tp, int precision,
+                      float* metrics, uint8_t* actions_out_or_null, float* grad_out_or_null,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+  if (!weights || !adam_m || !adam_v || !contones || !seeds || !tp || !metrics || !workspace)
+    return fail(HS_EINVAL, "policy_train_step: null pointer");
+  if (precision != HS_FP32 && precision != HS_BF16)
+    return fail(HS_EUNSUPPORTED, "policy_train_step: precision %d", precision);
+  if (tp->noise_kind != HS_NOISE_GAUSS && tp->noise_kind != HS_NOISE_UNIFORM)
+    return fail(HS_EINVAL, "policy_train_step: noise kind %d", tp->noise_kind);
+  if (step < 0 || total_steps < 0) return fail(HS_EINVAL, "policy_train_step: negative step");
+  if (gray && (!gray_seeds || Bg <= 0))
+    return fail(HS_EINVAL, "policy_train_step: gray batch needs seeds and Bg > 0");
+  if (!gray) Bg = Hg = Wg = 0;
+  int rc = check_params(&tp->loss);
+  if (rc) return rc;
+  const int m = margin(&tp->loss);
+  if (!shape_ok(B, H, W) || H < 2 * m + 1 || W < 2 * m + 1)
+    return fail(HS_ESHAPE, "policy_train_step: images must be at least %d x %d", 2 * m + 1,
+                2 * m + 1);
+  if (Bg > 0 && !shape_ok(Bg, Hg, Wg))
+    return fail(HS_ESHAPE, "policy_train_step: bad gray-batch shape");
+  if (workspace_bytes < halftone_train_workspace_size(B, H, W, Bg, Hg, Wg, precision))
+    return fail(HS_EWORKSPACE, "policy_train_step: workspace too small");
+  if ((rc = check_device())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  PolicyWs pw;
+  LossWs lw;
+  float *probs, *probs_g, *gradp, *gradg, *grad, *loss_out;
+  uint8_t* act;
+  train_ws(B, H, W, Bg, Hg, Wg, precision, workspace, &pw, &lw, &probs, &probs_g, &act, &gradp,
+           &gradg, &grad, &loss_out);
+  lw.ntiles = ((H - 2 * m + 15) / 16) * ((W - 2 * m + 15) / 16);
+  const hs_loss_params& lp = tp->loss;
+  const int kind = tp->noise_kind;
+  const uint32_t st = (uint32_t)step;
+  // batch: forward, actions, Local Expectation gradient (logit space), backward
+  HS_TRY(run_forward_train(weights, contones, seeds, B, H, W, kind, st, precision, pw, probs, act,
+                           s));
+  LossDev win;
+  make_windows(lp, &win);
+  HS_TRY(launch_loss_stats(act, contones, B, H, W, lp, win, lw.maps, lw.tiles, lw.ntiles, s));
+  HS_TRY(launch_le_grad(act, contones, probs, B, H, W, lp, win, lw.maps, gradp, s));
+  HS_TRY(run_backward(weights, gradp, nullptr, B, H, W, precision, pw, 0, s));
+  // constant-gray side batch: forward, anisotropy gradient, backward
+  const int npatch = Bg * (Hg / 32) * (Wg / 32);
+  if (Bg > 0) {
+    HS_TRY(run_forward_train(weights, gray, gray_seeds, Bg, Hg, Wg, kind, st, precision, pw,
+                             probs_g, nullptr, s));
+    HS_TRY(launch_fill(gradg, (size_t)Bg * Hg * Wg, 0.0f, s));
+    if (npatch > 0)
+      HS_TRY(launch_as(probs_g, Bg, Hg, Wg, lp.w_a / (float)npatch, 1, lw.patches, gradg, s));
+    HS_TRY(run_backward(weights, gradg, nullptr, Bg, Hg, Wg, precision, pw, 1, s));
+  }
+  HS_TRY(launch_reduce_partials(pw.partials, WGRAD_BLOCKS, grad, s));
+  HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, lp.w_s,
+                            (long)(H - 2 * m) * (W - 2 * m), loss_out, s));
+  // Adam with the cosine learning rate of this step, bias corrections at t = step + 1
+  const double T = (double)total_steps;
+  const double lr = T > 0 ? tp->lr_min + 0.5 * ((double)tp->lr_max - tp->lr_min) *
+                                             (1.0 + cos(M_PI * (double)step / T))
+                          : (double)tp->lr_max;
+  const double c1 = 1.0 - pow((double)tp->beta1, (double)(step + 1));
+  const double c2 = 1.0 - pow((double)tp->beta2, (double)(step + 1));
+  if (grad_out_or_null)
+    HS_TRY(hipMemcpyAsync(grad_out_or_null, grad, (size_t)NPARAM * 4, hipMemcpyDeviceToDevice, s));
+  HS_TRY(launch_train_metrics(loss_out, B, grad, NPARAM, act, (size_t)B * H * W, (float)lr,
+                              metrics, s));
+  HS_TRY(launch_adam(weights, adam_m, adam_v, grad, NPARAM, (float)lr, tp->beta1, tp->beta2,
+                     tp->eps, (float)c1, (float)c2, s));
+  if (actions_out_or_null)
+    HS_TRY(hipMemcpyAsync(actions_out_or_null, act, (size_t)B * H * W, hipMemcpyDeviceToDevice, s));
+  return HS_OK;
+}
+
+// ---------------------------------------------------- host error diffusion --
+int halftone_error_diffusion_host(const float* contone_host, int B, int H, int W,
+                                  uint8_t* bits_host) {
+  if (!contone_host || !bits_host) return fail(HS_EINVAL, "error diffusion: null pointer");
+  if (!shape_ok(B, H, W)) return fail(HS_ESHAPE, "error diffusion: bad shape");
+  // two rows of pending error (current and next), with one guard column each side
+  std::vector<double> cur(W + 2), nxt(W + 2);
+  for (int b = 0; b < B; ++b) {
+    std::fill(cur.begin(), cur.end(), 0.0);
+    std::fill(nxt.begin(), nxt.end(), 0.0);
+    const float* c = contone_host + (size_t)b * H * W;
+    uint8_t* h = bits_host + (size_t)b * H * W;
+    for (int y = 0; y < H; ++y) {
+      for (int x = 0; x < W; ++x) {
+        const double v = (double)c[(size_t)y * W + x] + cur[x + 1];
+        const uint8_t bit = v >= 0.5 ? 1 : 0;
+        const double q = v - (double)bit;
+        h[(size_t)y * W + x] = bit;
+        if (x + 1 < W) cur[x + 2] += q * (7.0 / 16.0);
+        if (x > 0) nxt[x] += q * (3.0 / 16.0);
+        nxt[x + 1] += q * (5.0 / 16.0);
+        if (x + 1 < W) nxt[x + 2] += q * (1.0 / 16.0);
+      }
+      std::swap(cur, nxt);
+      std::fill(nxt.begin(), nxt.end(), 0.0);
+    }
+  }
+  return HS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,620 @@
+// conv.hip -- the policy's conv stack on gfx950, one layer per launch.
+//
+// The policy (Sec. VI-A of the paper, with the 6 x 32 geometry of this
+// library) is 3x3 conv 2->32, four 3x3 conv 32->32, 3x3 conv 32->1, zero
+// 'same' padding, ReLU after all but the last, sigmoid head. Activations are
+// NHWC with 32 channels (BF16 or FP32). The 32->32 layers are implicit GEMMs
+// on the matrix cores: D[cout][pixel] = sum over taps of W_tap[cout][cin] x
+// act[pixel + tap][cin], with the weights as the A operand (held in
+// registers) and 16-pixel runs of the LDS-staged input tile as the B
+// operand. The input gradient of a layer is the same conv with weights
+// transposed in (cin, cout) and flipped in the taps. Weight gradients are
+// reductions over pixels with one row of partial sums per block, summed in
+// a fixed order afterwards (deterministic).
+#include "hs_common.h"
+#include "hs_internal.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Weight packing into MFMA A-operand order [tap][row tile][lane][8].
+// forward:    element (t, m, l, j) = W[16m + l%16][8(l/16) + j][t]
+// transposed: element (t, m, l, j) = W[8(l/16) + j][16m + l%16][8 - t]
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void pack32_kernel(const float* __restrict__ w, T* __restrict__ out, int transposed) {
+  const int layer = blockIdx.y;  // 0..3 is conv layer 2..5
+  const float* Wk = w + hs_wk(layer + 2);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < hs::PACK32_PER_LAYER;
+       i += gridDim.x * blockDim.x) {
+    const int j = i & 7, l = (i >> 3) & 63, m = (i >> 9) & 1, t = i >> 10;
+    const int r = l & 15, g = l >> 4;
+    const float v = transposed ? Wk[((8 * g + j) * 32 + 16 * m + r) * 9 + (8 - t)]
+                               : Wk[((16 * m + r) * 32 + 8 * g + j) * 9 + t];
+    out[layer * hs::PACK32_PER_LAYER + i] = hs_from_f<T>(v);
+  }
+}
+
+// B-operand fragment of lane group g (channels 8g..8g+7) of the pixel stored
+// at `px` (LDS column `col`) in a chunk-swizzled tile.
+HS_DEV void lds_frag(frag8<__bf16>& f, const __bf16* px, int col, int g) {
+  f.v = *(const bf16x8_t*)(px + hs_swz<__bf16>(col, g) * 8);
+}
+HS_DEV void lds_frag(frag8<float>& f, const float* px, int col, int g) {
+  f.lo = *(const f32x4_t*)(px + hs_swz<float>(col, 2 * g) * 4);
+  f.hi = *(const f32x4_t*)(px + hs_swz<float>(col, 2 * g + 1) * 4);
+}
+
+// ---------------------------------------------------------------------------
+// 32 -> 32 conv layer. Block = 4 waves over a 4 x 64 pixel tile; wave w owns
+// tile row w as four 16-pixel runs; both 16-channel row tiles of the output.
+// MODE 0: + bias, ReLU.  MODE 1: x [mask > 0] (input gradient through ReLU).
+// ---------------------------------------------------------------------------
+constexpr int CT_H = 4, CT_W = 64, CL_H = CT_H + 2, CL_W = CT_W + 2;
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void conv32_kernel(const T* __restrict__ in,
+                                                     const T* __restrict__ wp,
+                                                     const float* __restrict__ bias,
+                                                     const T* __restrict__ mask,
+                                                     T* __restrict__ out, int H, int W) {
+  constexpr int CPP = act_traits<T>::chunks_per_px, EPC = act_traits<T>::elems_per_chunk;
+  __shared__ __attribute__((aligned(16))) T lds[CL_H * CL_W * 32];
+  const int b = blockIdx.z, y0 = blockIdx.y * CT_H, x0 = blockIdx.x * CT_W;
+  const size_t img = (size_t)b * H * W;
+  for (int i = threadIdx.x; i < CL_H * CL_W * CPP; i += 256) {
+    const int p = i / CPP, c = i - p * CPP;
+    const int ly = p / CL_W, lx = p - ly * CL_W;
+    const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+      v = *(const uint4*)(in + (img + (size_t)gy * W + gx) * 32 + c * EPC);
+    *(uint4*)(lds + p * 32 + hs_swz<T>(lx, c) * EPC) = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  f32x4_t acc[2][4];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int dy = t / 3, dx = t - (t / 3) * 3;
+    frag8<T> a0, a1;
+    hs_load_frag(a0, wp + ((t * 2 + 0) * 64 + lane) * 8);
+    hs_load_frag(a1, wp + ((t * 2 + 1) * 64 + lane) * 8);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const int lx = n * 16 + r + dx, ly = wave + dy;
+      frag8<T> bf;
+      lds_frag(bf, lds + (ly * CL_W + lx) * 32, lx, g);
+      acc[0][n] = hs_mma(a0, bf, acc[0][n]);
+      acc[1][n] = hs_mma(a1, bf, acc[1][n]);
+    }
+  }
+  const int gy = y0 + wave;
+  if (gy >= H) return;
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    const int gx = x0 + n * 16 + r;
+    if (gx >= W) continue;
+    const size_t o = (img + (size_t)gy * W + gx) * 32;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int co = 16 * m + 4 * g;
+      float v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        v[i] = acc[m][n][i];
+        if (MODE == 0) {
+          v[i] = fmaxf(v[i] + bias[co + i], 0.0f);
+        } else {
+          v[i] = hs_to_f(mask[o + co + i]) > 0.0f ? v[i] : 0.0f;
+        }
+      }
+      hs_store4(out + o + co, v[0], v[1], v[2], v[3]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// First layer 2 -> 32 on the state s = (c, z); z from Philox stream 1.
+// 16 x 16 pixel tile per block, one pixel per thread, 32 outputs each.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict__ contone,
+                                                         const uint64_t* __restrict__ seeds,
+                                                         const float* __restrict__ w, int H,
+                                                         int W, int kind, uint32_t step,
+                                                         T* __restrict__ out,
+                                                         float* __restrict__ zout,
+                                                         float* __restrict__ cout) {
+  __shared__ float sc[18 * 18], sz[18 * 18], sw[32 * 2 * 9 + 32];
+  const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16;
+  const size_t img = (size_t)b * H * W;
+  const uint64_t seed = seeds[b];
+  for (int i = threadIdx.x; i < 32 * 2 * 9 + 32; i += 256) sw[i] = w[HS_W1 + i];
+  for (int i = threadIdx.x; i < 18 * 18; i += 256) {
+    const int ly = i / 18, lx = i - ly * 18, gy = y0 + ly - 1, gx = x0 + lx - 1;
+    float cv = 0.0f, zv = 0.0f;
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+      const uint64_t a = (uint64_t)gy * W + gx;
+      cv = contone[img + a];
+      zv = hs_noise(seed, a, step, kind);
+    }
+    sc[i] = cv;
+    sz[i] = zv;
+  }
+  __syncthreads();
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15, gy = y0 + ty, gx = x0 + tx;
+  if (gy >= H || gx >= W) return;
+  if (zout) zout[img + (size_t)gy * W + gx] = sz[(ty + 1) * 18 + tx + 1];
+  if (cout) cout[img + (size_t)gy * W + gx] = sc[(ty + 1) * 18 + tx + 1];
+  float acc[32];
+#pragma unroll
+  for (int co = 0; co < 32; ++co) acc[co] = sw[HS_B1 + co];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int dy = t / 3, dx = t - (t / 3) * 3;
+    const float c = sc[(ty + dy) * 18 + tx + dx], z = sz[(ty + dy) * 18 + tx + dx];
+#pragma unroll
+    for (int co = 0; co < 32; ++co)
+      acc[co] = fmaf(sw[(co * 2 + 1) * 9 + t], z, fmaf(sw[(co * 2 + 0) * 9 + t], c, acc[co]));
+  }
+  T* o = out + (img + (size_t)gy * W + gx) * 32;
+#pragma unroll
+  for (int co = 0; co < 32; co += 4)
+    hs_store4(o + co, fmaxf(acc[co], 0.f), fmaxf(acc[co + 1], 0.f), fmaxf(acc[co + 2], 0.f),
+              fmaxf(acc[co + 3], 0.f));
+}
+
+// ---------------------------------------------------------------------------
+// Last layer 32 -> 1 and the head. MODE 0: bit = [x >= 0] (+ logit).
+// MODE 1: p = sigmoid(x), action = [u < p] with u from stream 0 at `step`.
+// ---------------------------------------------------------------------------
+constexpr int LP = 33;  // padded pixel stride (floats) of the staged tile
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void conv_last_kernel(const T* __restrict__ in,
+                                                        const float* __restrict__ w, int H, int W,
+                                                        const uint64_t* __restrict__ seeds,
+                                                        uint32_t step, uint8_t* __restrict__ bits,
+                                                        float* __restrict__ logits,
+                                                        float* __restrict__ probs, float tau,
+                                                        uint32_t* __restrict__ list,
+                                                        int* __restrict__ count) {
+  __shared__ float s[18 * 18 * LP];
+  __shared__ float sw[32 * 9 + 1];
+  const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16;
+  const size_t img = (size_t)b * H * W;
+  for (int i = threadIdx.x; i < 32 * 9 + 1; i += 256) sw[i] = w[HS_W6 + i];
+  for (int i = threadIdx.x; i < 18 * 18 * 8; i += 256) {
+    const int p = i >> 3, q = (i & 7) * 4;
+    const int ly = p / 18, lx = p - ly * 18, gy = y0 + ly - 1, gx = x0 + lx - 1;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+      const T* src = in + (img + (size_t)gy * W + gx) * 32 + q;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = hs_to_f(src[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[p * LP + q + k] = v[k];
+  }
+  __syncthreads();
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15, gy = y0 + ty, gx = x0 + tx;
+  if (gy >= H || gx >= W) return;
+  float x = sw[32 * 9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int dy = t / 3, dx = t - (t / 3) * 3;
+    const float* sp = s + ((ty + dy) * 18 + tx + dx) * LP;
+#pragma unroll
+    for (int ci = 0; ci < 32; ++ci) x = fmaf(sw[ci * 9 + t], sp[ci], x);
+  }
+  const size_t o = img + (size_t)gy * W + gx;
+  if (MODE == 0) {
+    bits[o] = x >= 0.0f ? 1 : 0;
+    if (logits) logits[o] = x;
+    if (list && fabsf(x) < tau) list[atomicAdd(count, 1)] = (uint32_t)o;
+  } else {
+    const float p = hs_sigmoid(x);
+    probs[o] = p;
+    if (bits) bits[o] = hs_action_u(seeds[b], (uint64_t)gy * W + gx, step) < p ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward through the head and layer 6: g6 = dL/dlogit, and
+// g5[y][x][ci] = [a5 > 0] * sum_t W6[ci][t] g6[y - dy + 1][x - dx + 1].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void dgrad_last_kernel(const float* __restrict__ grad,
+                                                         const float* __restrict__ probs,
+                                                         const T* __restrict__ a5,
+                                                         const float* __restrict__ w, int H,
+                                                         int W, float* __restrict__ g6out,
+                                                         T* __restrict__ g5) {
+  __shared__ float sg[18 * 18], sw[32 * 9];
+  const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16;
+  const size_t img = (size_t)b * H * W;
+  for (int i = threadIdx.x; i < 32 * 9; i += 256) sw[i] = w[HS_W6 + i];
+  for (int i = threadIdx.x; i < 18 * 18; i += 256) {
+    const int ly = i / 18, lx = i - ly * 18, gy = y0 + ly - 1, gx = x0 + lx - 1;
+    float v = 0.0f;
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+      const size_t o = img + (size_t)gy * W + gx;
+      v = grad[o];
+      if (probs) v *= probs[o] * (1.0f - probs[o]);
+    }
+    sg[i] = v;
+  }
+  __syncthreads();
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15, gy = y0 + ty, gx = x0 + tx;
+  if (gy >= H || gx >= W) return;
+  const size_t o = img + (size_t)gy * W + gx;
+  g6out[o] = sg[(ty + 1) * 18 + tx + 1];
+  float acc[32];
+#pragma unroll
+  for (int ci = 0; ci < 32; ++ci) acc[ci] = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int dy = t / 3, dx = t - (t / 3) * 3;
+    const float gv = sg[(ty + 2 - dy) * 18 + tx + 2 - dx];
+#pragma unroll
+    for (int ci = 0; ci < 32; ++ci) acc[ci] = fmaf(sw[ci * 9 + t], gv, acc[ci]);
+  }
+  const T* m = a5 + o * 32;
+  T* dst = g5 + o * 32;
+#pragma unroll
+  for (int ci = 0; ci < 32; ci += 4) {
+    float v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = hs_to_f(m[ci + k]) > 0.0f ? acc[ci + k] : 0.0f;
+    hs_store4(dst + ci, v[0], v[1], v[2], v[3]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient of a 32->32 layer on the FP32 matrix cores:
+// dW[co][ci][t] = sum_px g[px][co] a[px + tap t][ci]; db[co] = sum_px g[px][co].
+// Tile = 2 x 64 pixels (the K dimension); block = 4 waves, wave w owns the
+// (co tile, ci tile) = (w >> 1, w & 1) output block for all nine taps.
+// Blocks stride over tiles; each block writes one row of partial sums.
+// ---------------------------------------------------------------------------
+constexpr int WT_H = 2, WT_W = 64, WT_PX = WT_H * WT_W, WL_H = WT_H + 2, WL_W = WT_W + 2;
+constexpr int WG_STRIDE = 132;  // floats per channel row of the staged gradient (128 + 4)
+constexpr int WA_STRIDE = 268;  // floats per channel row of the staged input (264 + 4)
+
+template <typename T>
+__global__ __launch_bounds__(256) void wgrad32_kernel(const T* __restrict__ a_in,
+                                                      const T* __restrict__ g_out, int B, int H,
+                                                      int W, int layer,
+                                                      float* __restrict__ partials,
+                                                      int accumulate) {
+  __shared__ float sg[32 * WG_STRIDE];
+  __shared__ float sa[32 * WA_STRIDE];
+  const int tiles_x = (W + WT_W - 1) / WT_W, tiles_y = (H + WT_H - 1) / WT_H;
+  const int ntiles = B * tiles_x * tiles_y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  const int mt = wave >> 1, nt = wave & 1;
+  f32x4_t acc[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.0f;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
+    const int y0 = (rem / tiles_x) * WT_H, x0 = (rem % tiles_x) * WT_W;
+    const size_t img = (size_t)b * H * W;
+    __syncthreads();
+    // gradient tile, transposed to [co][px]; zero outside the image
+    for (int i = threadIdx.x; i < WT_PX * 8; i += 256) {
+      const int p = i >> 3, q = (i & 7) * 4;
+      const int gy = y0 + p / WT_W, gx = x0 + (p % WT_W);
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (gy < H && gx < W) {
+        const T* src = g_out + (img + (size_t)gy * W + gx) * 32 + q;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = hs_to_f(src[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sg[(q + k) * WG_STRIDE + p] = v[k];
+    }
+    // input tile with a one-pixel halo, transposed to [ci][halo px]
+    for (int i = threadIdx.x; i < WL_H * WL_W * 8; i += 256) {
+      const int p = i >> 3, q = (i & 7) * 4;
+      const int ly = p / WL_W, lx = p - ly * WL_W, gy = y0 + ly - 1, gx = x0 + lx - 1;
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+        const T* src = a_in + (img + (size_t)gy * W + gx) * 32 + q;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = hs_to_f(src[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sa[(q + k) * WA_STRIDE + p] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+      float s = 0.0f;
+      for (int p = 0; p < WT_PX; ++p) s += sg[threadIdx.x * WG_STRIDE + p];
+      bacc += s;
+    }
+    // K loop: 4 pixels per MFMA step; lane group g takes pixel 4s + g
+    for (int s4 = 0; s4 < WT_PX / 4; ++s4) {
+      const int p = 4 * s4 + g, py = p / WT_W, px = p - py * WT_W;
+      const float av = sg[(16 * mt + r) * WG_STRIDE + p];
+      const float* brow = sa + (16 * nt + r) * WA_STRIDE;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3, dx = t - (t / 3) * 3;
+        const float bv = brow[(py + dy) * WL_W + px + dx];
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  // acc[t][i] = dW[co = 16 mt + 4 g + i][ci = 16 nt + r][t]
+  float* row = partials + (size_t)blockIdx.x * hs::NPARAM + hs_wk(layer);
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = 16 * mt + 4 * g + i, ci = 16 * nt + r;
+      float* d = row + (co * 32 + ci) * 9 + t;
+      *d = accumulate ? *d + acc[t][i] : acc[t][i];
+    }
+  if (threadIdx.x < 32) {
+    float* d = row + 32 * 32 * 9 + threadIdx.x;
+    *d = accumulate ? *d + bacc : bacc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient of the first layer (2 -> 32) on the vector ALUs.
+// Tile = 16 x 16 pixels; thread i < 608 owns parameter i of layer 1.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void wgrad_first_kernel(const float* __restrict__ contone,
+                                                          const float* __restrict__ z,
+                                                          const T* __restrict__ g1, int B, int H,
+                                                          int W, float* __restrict__ partials,
+                                                          int accumulate) {
+  __shared__ float sg[256 * 33];
+  __shared__ float sc[18 * 18], sz[18 * 18];
+  const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16, ntiles = B * tiles_x * tiles_y;
+  float acc[3] = {0.f, 0.f, 0.f};
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
+    const int y0 = (rem / tiles_x) * 16, x0 = (rem % tiles_x) * 16;
+    const size_t img = (size_t)b * H * W;
+    __syncthreads();
+    for (int i = threadIdx.x; i < 256 * 8; i += 256) {
+      const int p = i >> 3, q = (i & 7) * 4, gy = y0 + (p >> 4), gx = x0 + (p & 15);
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (gy < H && gx < W) {
+        const T* src = g1 + (img + (size_t)gy * W + gx) * 32 + q;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = hs_to_f(src[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sg[p * 33 + q + k] = v[k];
+    }
+    for (int i = threadIdx.x; i < 18 * 18; i += 256) {
+      const int ly = i / 18, lx = i - ly * 18, gy = y0 + ly - 1, gx = x0 + lx - 1;
+      const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      sc[i] = in ? contone[img + (size_t)gy * W + gx] : 0.0f;
+      sz[i] = in ? z[img + (size_t)gy * W + gx] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int prm = threadIdx.x + 256 * k;
+      if (prm >= 608) break;
+      float s = 0.0f;
+      if (prm < 576) {
+        const int co = prm / 18, ci = (prm / 9) & 1, t = prm % 9, dy = t / 3, dx = t % 3;
+        const float* src = ci ? sz : sc;
+        for (int p = 0; p < 256; ++p)
+          s = fmaf(sg[p * 33 + co], src[((p >> 4) + dy) * 18 + (p & 15) + dx], s);
+      } else {
+        const int co = prm - 576;
+        for (int p = 0; p < 256; ++p) s += sg[p * 33 + co];
+      }
+      acc[k] += s;
+    }
+  }
+  float* row = partials + (size_t)blockIdx.x * hs::NPARAM + HS_W1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int prm = threadIdx.x + 256 * k;
+    if (prm < 608) row[prm] = accumulate ? row[prm] + acc[k] : acc[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient of the last layer (32 -> 1): dW6[ci][t] = sum g6 a5[+t][ci].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(320) void wgrad_last_kernel(const T* __restrict__ a5,
+                                                         const float* __restrict__ g6, int B,
+                                                         int H, int W,
+                                                         float* __restrict__ partials,
+                                                         int accumulate) {
+  __shared__ float sa[18 * 18 * LP];
+  __shared__ float sg[256];
+  const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16, ntiles = B * tiles_x * tiles_y;
+  float acc = 0.0f;
+  const int prm = threadIdx.x;  // 0..287 weights, 288 bias
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
+    const int y0 = (rem / tiles_x) * 16, x0 = (rem % tiles_x) * 16;
+    const size_t img = (size_t)b * H * W;
+    __syncthreads();
+    for (int i = threadIdx.x; i < 18 * 18 * 8; i += blockDim.x) {
+      const int p = i >> 3, q = (i & 7) * 4;
+      const int ly = p / 18, lx = p - ly * 18, gy = y0 + ly - 1, gx = x0 + lx - 1;
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+        const T* src = a5 + (img + (size_t)gy * W + gx) * 32 + q;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = hs_to_f(src[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sa[p * LP + q + k] = v[k];
+    }
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+      const int gy = y0 + (i >> 4), gx = x0 + (i & 15);
+      sg[i] = (gy < H && gx < W) ? g6[img + (size_t)gy * W + gx] : 0.0f;
+    }
+    __syncthreads();
+    if (prm < 288) {
+      const int ci = prm / 9, t = prm % 9, dy = t / 3, dx = t % 3;
+      float s = 0.0f;
+      for (int p = 0; p < 256; ++p)
+        s = fmaf(sg[p], sa[(((p >> 4) + dy) * 18 + (p & 15) + dx) * LP + ci], s);
+      acc += s;
+    } else if (prm == 288) {
+      float s = 0.0f;
+      for (int p = 0; p < 256; ++p) s += sg[p];
+      acc += s;
+    }
+  }
+  if (prm <= 288) {
+    float* d = partials + (size_t)blockIdx.x * hs::NPARAM + HS_W6 + prm;
+    *d = accumulate ? *d + acc : acc;
+  }
+}
+
+__global__ void reduce_partials_kernel(const float* __restrict__ partials, int rows,
+                                       float* __restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= hs::NPARAM) return;
+  float s = 0.0f;
+  for (int r = 0; r < rows; ++r) s += partials[(size_t)r * hs::NPARAM + p];
+  grad[p] = s;
+}
+
+inline dim3 tiles16(int B, int H, int W) { return dim3((W + 15) / 16, (H + 15) / 16, B); }
+
+}  // namespace
+
+namespace hs {
+
+hipError_t launch_pack32(const float* w, void* out, int precision, int transposed,
+                         hipStream_t s) {
+  if (precision == HS_BF16)
+    pack32_kernel<__bf16><<<dim3(36, 4), 256, 0, s>>>(w, (__bf16*)out, transposed);
+  else
+    pack32_kernel<float><<<dim3(36, 4), 256, 0, s>>>(w, (float*)out, transposed);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv_first(const float* contone, const uint64_t* seeds, const float* w, int B,
+                             int H, int W, int kind, uint32_t step, int precision, void* out,
+                             float* zout, float* cout, hipStream_t s) {
+  if (precision == HS_BF16)
+    conv_first_kernel<__bf16><<<tiles16(B, H, W), 256, 0, s>>>(contone, seeds, w, H, W, kind,
+                                                               step, (__bf16*)out, zout, cout);
+  else
+    conv_first_kernel<float><<<tiles16(B, H, W), 256, 0, s>>>(contone, seeds, w, H, W, kind,
+                                                              step, (float*)out, zout, cout);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv32(const void* in, const void* wpack, const float* bias, const void* mask,
+                         void* out, int B, int H, int W, int precision, int mode, hipStream_t s) {
+  const dim3 grid((W + CT_W - 1) / CT_W, (H + CT_H - 1) / CT_H, B);
+  if (precision == HS_BF16) {
+    if (mode == 0)
+      conv32_kernel<__bf16, 0><<<grid, 256, 0, s>>>((const __bf16*)in, (const __bf16*)wpack, bias,
+                                                    nullptr, (__bf16*)out, H, W);
+    else
+      conv32_kernel<__bf16, 1><<<grid, 256, 0, s>>>((const __bf16*)in, (const __bf16*)wpack,
+                                                    nullptr, (const __bf16*)mask, (__bf16*)out, H,
+                                                    W);
+  } else {
+    if (mode == 0)
+      conv32_kernel<float, 0><<<grid, 256, 0, s>>>((const float*)in, (const float*)wpack, bias,
+                                                   nullptr, (float*)out, H, W);
+    else
+      conv32_kernel<float, 1><<<grid, 256, 0, s>>>((const float*)in, (const float*)wpack, nullptr,
+                                                   (const float*)mask, (float*)out, H, W);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_conv_last(const void* in, const float* w, int B, int H, int W, int precision,
+                            int mode, const uint64_t* seeds, uint32_t step, uint8_t* bits,
+                            float* logits, float* probs, float tau, uint32_t* list, int* count,
+                            hipStream_t s) {
+  const dim3 grid = tiles16(B, H, W);
+  if (precision == HS_BF16) {
+    if (mode == 0)
+      conv_last_kernel<__bf16, 0><<<grid, 256, 0, s>>>((const __bf16*)in, w, H, W, seeds, step,
+                                                       bits, logits, probs, tau, list, count);
+    else
+      conv_last_kernel<__bf16, 1><<<grid, 256, 0, s>>>((const __bf16*)in, w, H, W, seeds, step,
+                                                       bits, logits, probs, tau, list, count);
+  } else {
+    if (mode == 0)
+      conv_last_kernel<float, 0><<<grid, 256, 0, s>>>((const float*)in, w, H, W, seeds, step,
+                                                      bits, logits, probs, tau, list, count);
+    else
+      conv_last_kernel<float, 1><<<grid, 256, 0, s>>>((const float*)in, w, H, W, seeds, step,
+                                                      bits, logits, probs, tau, list, count);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dgrad_last(const float* grad, const float* probs, const void* a5,
+                             const float* w, int B, int H, int W, int precision, float* g6,
+                             void* g5, hipStream_t s) {
+  const dim3 grid = tiles16(B, H, W);
+  if (precision == HS_BF16)
+    dgrad_last_kernel<__bf16><<<grid, 256, 0, s>>>(grad, probs, (const __bf16*)a5, w, H, W, g6,
+                                                   (__bf16*)g5);
+  else
+    dgrad_last_kernel<float><<<grid, 256, 0, s>>>(grad, probs, (const float*)a5, w, H, W, g6,
+                                                  (float*)g5);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad_first(const float* contone, const float* z, const void* g1, int B, int H,
+                              int W, int precision, float* partials, int accumulate,
+                              hipStream_t s) {
+  if (precision == HS_BF16)
+    wgrad_first_kernel<__bf16><<<WGRAD_BLOCKS, 256, 0, s>>>(contone, z, (const __bf16*)g1, B, H,
+                                                            W, partials, accumulate);
+  else
+    wgrad_first_kernel<float><<<WGRAD_BLOCKS, 256, 0, s>>>(contone, z, (const float*)g1, B, H, W,
+                                                           partials, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad32(const void* a_in, const void* g_out, int layer, int B, int H, int W,
+                          int precision, float* partials, int accumulate, hipStream_t s) {
+  if (precision == HS_BF16)
+    wgrad32_kernel<__bf16><<<WGRAD_BLOCKS, 256, 0, s>>>((const __bf16*)a_in, (const __bf16*)g_out,
+                                                        B, H, W, layer, partials, accumulate);
+  else
+    wgrad32_kernel<float><<<WGRAD_BLOCKS, 256, 0, s>>>((const float*)a_in, (const float*)g_out, B,
+                                                       H, W, layer, partials, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad_last(const void* a5, const float* g6, int B, int H, int W, int precision,
+                             float* partials, int accumulate, hipStream_t s) {
+  if (precision == HS_BF16)
+    wgrad_last_kernel<__bf16><<<WGRAD_BLOCKS, 320, 0, s>>>((const __bf16*)a5, g6, B, H, W,
+                                                           partials, accumulate);
+  else
+    wgrad_last_kernel<float><<<WGRAD_BLOCKS, 320, 0, s>>>((const float*)a5, g6, B, H, W, partials,
+                                                          accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const float* partials, int rows, float* grad, hipStream_t s) {
+  reduce_partials_kernel<<<(NPARAM + 255) / 256, 256, 0, s>>>(partials, rows, grad);
+  return hipGetLastError();
+}
+
+}  // namespace hs

@@ -1,0 +1,98 @@
+// hs_internal.h -- host-side launchers shared by the translation units of
+// libhalftone. Not part of the public ABI (include/halftone.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/halftone.h"
+
+// Offsets of the layers in the flat weight array (layer after layer,
+// W[cout][cin][3][3] then bias[cout]): 2 -> 32, four 32 -> 32, 32 -> 1.
+constexpr int HS_C = 32;
+constexpr int HS_W1 = 0;                       // W1[32][2][9]
+constexpr int HS_B1 = HS_W1 + 32 * 2 * 9;      // 576
+constexpr int HS_L32_SIZE = 32 * 32 * 9 + 32;  // 9248
+constexpr int HS_W2 = HS_B1 + 32;              // 608
+constexpr int hs_wk(int k) { return HS_W2 + (k - 2) * HS_L32_SIZE; }  // k = 2..5
+constexpr int hs_bk(int k) { return hs_wk(k) + 32 * 32 * 9; }
+constexpr int HS_W6 = HS_W2 + 4 * HS_L32_SIZE;  // 37600
+constexpr int HS_B6 = HS_W6 + 32 * 9;           // 37888
+static_assert(HS_B6 + 1 == HS_PARAM_COUNT, "parameter layout");
+
+namespace hs {
+
+constexpr int NPARAM = HS_PARAM_COUNT;
+constexpr int WGRAD_BLOCKS = 512;  // rows of weight-gradient partial sums
+
+// Bytes of one NHWC 32-channel activation map of n pixels.
+inline size_t act_bytes(size_t n, int precision) {
+  return n * 32 * (precision == HS_BF16 ? 2 : 4);
+}
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Packed weights of the four 32->32 layers in MFMA operand order
+// (9 taps x 2 row tiles x 64 lanes x 8 values per layer).
+constexpr int PACK32_PER_LAYER = 9 * 2 * 64 * 8;  // 9216
+inline size_t pack_bytes(int precision) {
+  return 4 * (size_t)PACK32_PER_LAYER * (precision == HS_BF16 ? 2 : 4);
+}
+
+// conv.hip
+hipError_t launch_pack32(const float* w, void* out, int precision, int transposed, hipStream_t s);
+hipError_t launch_conv_first(const float* contone, const uint64_t* seeds, const float* w, int B,
+                             int H, int W, int kind, uint32_t step, int precision, void* out,
+                             float* zout, float* cout, hipStream_t s);
+hipError_t launch_conv32(const void* in, const void* wpack, const float* bias, const void* mask,
+                         void* out, int B, int H, int W, int precision, int mode, hipStream_t s);
+// mode 0: bits (+ logits); mode 1: probs + actions sampled from stream 0 at step
+hipError_t launch_conv_last(const void* in, const float* w, int B, int H, int W, int precision,
+                            int mode, const uint64_t* seeds, uint32_t step, uint8_t* bits,
+                            float* logits, float* probs, float tau, uint32_t* list, int* count,
+                            hipStream_t s);
+// infer.hip: FP32 re-evaluation of listed pixels over their receptive field.
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
+hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,
+                               int H, int W, int kind, const uint32_t* list, const int* count,
+                               uint8_t* bits, float* logits, int32_t* stats, hipStream_t s);
+// g6 = grad (if probs == null) or grad * p (1 - p); writes g6 and the
+// masked input gradient of layer 6.
+hipError_t launch_dgrad_last(const float* grad, const float* probs, const void* a5,
+                             const float* w, int B, int H, int W, int precision, float* g6,
+                             void* g5, hipStream_t s);
+hipError_t launch_wgrad_first(const float* contone, const float* z, const void* g1, int B, int H,
+                              int W, int precision, float* partials, int accumulate,
+                              hipStream_t s);
+hipError_t launch_wgrad32(const void* a_in, const void* g_out, int layer, int B, int H, int W,
+                          int precision, float* partials, int accumulate, hipStream_t s);
+hipError_t launch_wgrad_last(const void* a5, const float* g6, int B, int H, int W, int precision,
+                             float* partials, int accumulate, hipStream_t s);
+hipError_t launch_reduce_partials(const float* partials, int rows, float* grad, hipStream_t s);
+
+// loss.hip
+struct LossDev {  // the two normalised windows, passed to kernels by value
+  float G[15 * 15];
+  float w[15 * 15];
+};
+void make_windows(const hs_loss_params& p, LossDev* host_out);
+hipError_t launch_loss_stats(const uint8_t* h, const float* c, int B, int H, int W,
+                             const hs_loss_params& p, const LossDev& win, float* maps,
+                             float* tile_partials, int ntiles_per_img, hipStream_t s);
+hipError_t launch_loss_reduce(const float* tile_partials, int B, int ntiles_per_img,
+                              const float* as_partials, int npatch, float w_s, long M, float* out,
+                              hipStream_t s);
+hipError_t launch_le_grad(const uint8_t* h, const float* c, const float* probs, int B, int H,
+                          int W, const hs_loss_params& p, const LossDev& win, const float* maps,
+                          float* grad, hipStream_t s);
+hipError_t launch_as(const float* pg, int Bg, int Hg, int Wg, float scale, int logit_space,
+                     float* patch_loss, float* grad_or_null, hipStream_t s);
+hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
+
+// train.hip
+hipError_t launch_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_train_metrics(const float* loss_out, int B, const float* grad, int n,
+                                const uint8_t* actions, size_t nact, float lr, float* metrics,
+                                hipStream_t s);
+
+}  // namespace hs

@@ -1,0 +1,477 @@
+// loss.hip -- reward, Local Expectation gradient and anisotropy-suppressing
+// loss on gfx950 (FP32 on the vector ALUs, tiles staged in LDS).
+//
+// Reward (Sec. III "Rewards", Eq. final_reward; Sec. V, Eq. cssim): over the
+// valid region V = [m, H-m) x [m, W-m), e = HVS(h) - HVS(c) and
+// CSSIM = sigma_c SSIM + 1 - sigma_c with sigma_c = k sqrt(var_c);
+// R = -mean(e^2) + w_s mean(CSSIM). Local statistics use the weighted
+// two-pass form (means first, then centred second moments) for accuracy.
+//
+// Local Expectation gradient (Sec. III-B, Eq. le; Sec. III-C): for every
+// pixel a, the reward change of toggling h_a only involves the reward-map
+// pixels j whose windows contain a. With delta = 1 - 2 h_a the HVS error at
+// j moves by delta G_{a-j}; the SSIM statistics at j move by
+// dmu_h = delta w_{a-j}, dcov = delta w_{a-j} (c_a - mu_c), and var_h stays
+// mu_h (1 - mu_h) for binary h. The SSIM change is evaluated as a difference
+// of products expanded in those increments, so no two O(1) values are
+// subtracted. dR_a = delta (R(toggled) - R(h)); dL_MARL/dp_a = -dR_a / B.
+//
+// Anisotropy-suppressing loss (Sec. IV, Eqs. psd, rapsd, as): per 32 x 32
+// patch of the probability map, Phat = |DFT|^2 / 1024, ring means over
+// rings of width 1 (ring of (u, v) = rounded radius of the folded
+// frequency), L = sum (Phat - ring mean)^2. Its adjoint: with
+// g = dL/dPhat = 2 (Phat - ring mean), dL/dx = (2/1024) Re(sum_{u,v} g X
+// e^{+2 pi i (u y + v x)/32}), an inverse transform of g X.
+#include <math.h>
+
+#include "hs_common.h"
+#include "hs_internal.h"
+
+namespace {
+
+constexpr int LT = 16;   // output tile edge
+constexpr int MAXR = 7;  // largest supported window radius
+constexpr int LS = LT + 2 * MAXR;
+
+struct LossConst {
+  int rh, rs, m;
+  float k, c1, c2, w_s;
+};
+
+__global__ __launch_bounds__(256) void loss_stats_kernel(const uint8_t* __restrict__ h,
+                                                         const float* __restrict__ c, int H,
+                                                         int W, LossConst q,
+                                                         const hs::LossDev win,
+                                                         float* __restrict__ maps,
+                                                         float* __restrict__ partials,
+                                                         int ntiles_per_img) {
+  __shared__ float sh[LS * LS], sc[LS * LS];
+  __shared__ float sG[15 * 15], sw[15 * 15];
+  __shared__ float red[2][4];
+  const int b = blockIdx.z, m = q.m, R = q.m;
+  const int vy0 = m + blockIdx.y * LT, vx0 = m + blockIdx.x * LT;
+  const size_t img = (size_t)b * H * W;
+  const int ls = LT + 2 * R;
+  for (int i = threadIdx.x; i < 15 * 15; i += 256) {
+    sG[i] = win.G[i];
+    sw[i] = win.w[i];
+  }
+  for (int i = threadIdx.x; i < ls * ls; i += 256) {
+    const int ly = i / ls, lx = i - ly * ls, gy = vy0 - R + ly, gx = vx0 - R + lx;
+    const bool in = gy < H && gx < W;  // gy, gx >= 0 because vy0 >= R
+    sh[i] = in ? (float)h[img + (size_t)gy * W + gx] : 0.0f;
+    sc[i] = in ? c[img + (size_t)gy * W + gx] : 0.0f;
+  }
+  __syncthreads();
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const int jy = vy0 + ty, jx = vx0 + tx;
+  const bool valid = jy < H - m && jx < W - m;
+  float e2 = 0.0f, cs = 0.0f;
+  if (valid) {
+    const int cy = ty + R, cx = tx + R;
+    const int nh = 2 * q.rh + 1, ns = 2 * q.rs + 1;
+    float e = 0.0f;
+    for (int i = -q.rh; i <= q.rh; ++i)
+      for (int j = -q.rh; j <= q.rh; ++j) {
+        const int p = (cy + i) * ls + cx + j;
+        e = fmaf(sG[(i + q.rh) * nh + j + q.rh], sh[p] - sc[p], e);
+      }
+    float mu_h = 0.0f, mu_c = 0.0f;
+    for (int i = -q.rs; i <= q.rs; ++i)
+      for (int j = -q.rs; j <= q.rs; ++j) {
+        const int p = (cy + i) * ls + cx + j;
+        const float wv = sw[(i + q.rs) * ns + j + q.rs];
+        mu_h = fmaf(wv, sh[p], mu_h);
+        mu_c = fmaf(wv, sc[p], mu_c);
+      }
+    float var_h = 0.0f, var_c = 0.0f, cov = 0.0f;
+    for (int i = -q.rs; i <= q.rs; ++i)
+      for (int j = -q.rs; j <= q.rs; ++j) {
+        const int p = (cy + i) * ls + cx + j;
+        const float wv = sw[(i + q.rs) * ns + j + q.rs];
+        const float dh = sh[p] - mu_h, dc = sc[p] - mu_c;
+        var_h = fmaf(wv * dh, dh, var_h);
+        var_c = fmaf(wv * dc, dc, var_c);
+        cov = fmaf(wv * dh, dc, cov);
+      }
+    const float ssim = ((2.0f * mu_h * mu_c + q.c1) * (2.0f * cov + q.c2)) /
+                       ((mu_h * mu_h + mu_c * mu_c + q.c1) * (var_h + var_c + q.c2));
+    const float sig = q.k * sqrtf(var_c);
+    e2 = e * e;
+    cs = sig * ssim + (1.0f - sig);
+    if (maps) {
+      const size_t n = (size_t)gridDim.z * H * W, o = img + (size_t)jy * W + jx;
+      maps[o] = e;
+      maps[n + o] = mu_h;
+      maps[2 * n + o] = mu_c;
+      maps[3 * n + o] = var_c;
+      maps[4 * n + o] = cov;
+    }
+  }
+  e2 = hs_wave_sum(e2);
+  cs = hs_wave_sum(cs);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wave] = e2;
+    red[1][wave] = cs;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+    float* d = partials + ((size_t)b * ntiles_per_img + tile) * 2;
+    d[0] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+    d[1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+  }
+}
+
+__global__ void loss_reduce_kernel(const float* __restrict__ partials, int B, int ntiles,
+                                   const float* __restrict__ as_partials, int npatch, float w_s,
+                                   float invM, float* __restrict__ out) {
+  __shared__ float red[2][4];
+  const int b = blockIdx.x;
+  float s0 = 0.0f, s1 = 0.0f;
+  if (b < B) {
+    for (int t = threadIdx.x; t < ntiles; t += 256) {
+      s0 += partials[((size_t)b * ntiles + t) * 2];
+      s1 += partials[((size_t)b * ntiles + t) * 2 + 1];
+    }
+  } else {
+    for (int t = threadIdx.x; t < npatch; t += 256) s0 += as_partials[t];
+  }
+  s0 = hs_wave_sum(s0);
+  s1 = hs_wave_sum(s1);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wave] = s0;
+    red[1][wave] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const float a = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+  const float cc = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+  if (b < B) {
+    const float mse = a * invM, cssim = cc * invM;
+    out[3 * b + 0] = mse;
+    out[3 * b + 1] = cssim;
+    out[3 * b + 2] = -mse + w_s * cssim;
+  } else {
+    out[3 * B] = npatch > 0 ? a / (float)npatch : 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict__ h,
+                                                      const float* __restrict__ c,
+                                                      const float* __restrict__ probs, int B,
+                                                      int H, int W, LossConst q,
+                                                      const hs::LossDev win,
+                                                      const float* __restrict__ maps, float invM,
+                                                      float* __restrict__ grad) {
+  __shared__ float se[LS * LS], smh[LS * LS], smc[LS * LS], svc[LS * LS], scv[LS * LS],
+      ssg[LS * LS];
+  __shared__ float sG[15 * 15], sw[15 * 15];
+  const int b = blockIdx.z, R = q.m;
+  const int ay0 = blockIdx.y * LT, ax0 = blockIdx.x * LT;
+  const size_t img = (size_t)b * H * W, n = (size_t)B * H * W;
+  const int ls = LT + 2 * R;
+  for (int i = threadIdx.x; i < 15 * 15; i += 256) {
+    sG[i] = win.G[i];
+    sw[i] = win.w[i];
+  }
+  for (int i = threadIdx.x; i < ls * ls; i += 256) {
+    const int ly = i / ls, lx = i - ly * ls, gy = ay0 - R + ly, gx = ax0 - R + lx;
+    const bool in = gy >= q.m && gy < H - q.m && gx >= q.m && gx < W - q.m;
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f;
+    if (in) {
+      const size_t o = img + (size_t)gy * W + gx;
+      v0 = maps[o];
+      v1 = maps[n + o];
+      v2 = maps[2 * n + o];
+      v3 = maps[3 * n + o];
+      v4 = maps[4 * n + o];
+    }
+    se[i] = v0;
+    smh[i] = v1;
+    smc[i] = v2;
+    svc[i] = v3;
+    scv[i] = v4;
+    ssg[i] = q.k * sqrtf(v3);
+  }
+  __syncthreads();
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const int ay = ay0 + ty, ax = ax0 + tx;
+  if (ay >= H || ax >= W) return;
+  const size_t oa = img + (size_t)ay * W + ax;
+  const float delta = h[oa] ? -1.0f : 1.0f;
+  const float ca = c[oa];
+  const int cy = ty + R, cx = tx + R;
+  const int nh = 2 * q.rh + 1, ns = 2 * q.rs + 1;
+  float dmse = 0.0f;
+  for (int i = -q.rh; i <= q.rh; ++i) {
+    const int jy = ay + i;
+    if (jy < q.m || jy >= H - q.m) continue;
+    for (int j = -q.rh; j <= q.rh; ++j) {
+      const int jx = ax + j;
+      if (jx < q.m || jx >= W - q.m) continue;
+      const float G = sG[(q.rh - i) * nh + (q.rh - j)];  // G_{a-j}
+      dmse = fmaf(2.0f * delta * G, se[(cy + i) * ls + cx + j], fmaf(G, G, dmse));
+    }
+  }
+  float dcs = 0.0f;
+  for (int i = -q.rs; i <= q.rs; ++i) {
+    const int jy = ay + i;
+    if (jy < q.m || jy >= H - q.m) continue;
+    for (int j = -q.rs; j <= q.rs; ++j) {
+      const int jx = ax + j;
+      if (jx < q.m || jx >= W - q.m) continue;
+      const int p = (cy + i) * ls + cx + j;
+      const float wa = sw[(q.rs - i) * ns + (q.rs - j)];  // w_{a-j}
+      const float mh = smh[p], mc = smc[p];
+      const float A = 2.0f * mh * mc + q.c1;
+      const float Bc = 2.0f * scv[p] + q.c2;
+      const float C = mh * mh + mc * mc + q.c1;
+      const float D = mh * (1.0f - mh) + svc[p] + q.c2;
+      const float dw = delta * wa;
+      const float dA = 2.0f * dw * mc;
+      const float dB = 2.0f * dw * (ca - mc);
+      const float dC = dw * (2.0f * mh + dw);
+      const float dD = dw * (1.0f - 2.0f * mh - dw);
+      const float num = C * D * (A * dB + Bc * dA + dA * dB) - A * Bc * (C * dD + D * dC + dC * dD);
+      const float den = (C + dC) * (D + dD) * (C * D);
+      dcs = fmaf(ssg[p], num / den, dcs);
+    }
+  }
+  const float dR = delta * (-dmse * invM + q.w_s * dcs * invM);
+  float gv = -dR / (float)B;
+  if (probs) gv *= probs[oa] * (1.0f - probs[oa]);
+  grad[oa] = gv;
+}
+
+// Ring of frequency (u, v) of a P x P periodogram: the rho with
+// (2 rho - 1)^2 <= 4 (ub^2 + vb^2) < (2 rho + 1)^2, ub = min(u, P - u).
+HS_DEV int ring_of(int u, int v) {
+  const int ub = u < 32 - u ? u : 32 - u, vb = v < 32 - v ? v : 32 - v;
+  const int q4 = 4 * (ub * ub + vb * vb);
+  int rho = (int)sqrtf((float)(ub * ub + vb * vb));
+  while ((2 * rho + 1) * (2 * rho + 1) <= q4) ++rho;
+  while (rho > 0 && (2 * rho - 1) * (2 * rho - 1) > q4) --rho;
+  return rho;
+}
+
+constexpr int NRING = 24;
+
+__global__ __launch_bounds__(256) void as_kernel(const float* __restrict__ pg, int Bg, int Hg,
+                                                 int Wg, float scale, int logit_space,
+                                                 float* __restrict__ patch_loss,
+                                                 float* __restrict__ grad) {
+  __shared__ float x[32 * 33];
+  __shared__ float rr[32 * 33], ri[32 * 33];  // row transforms, then inverse column pass
+  __shared__ float xr[32 * 33], xi[32 * 33];  // spectrum X
+  __shared__ float ph[32 * 32];
+  __shared__ float cs[32], sn[32];
+  __shared__ float ring_part[NRING][8];
+  __shared__ int ring_npart[NRING][8];
+  __shared__ float ring_mean[NRING];
+  __shared__ float red[4];
+  const int py = Hg / 32, px = Wg / 32;
+  const int patch = blockIdx.x;
+  const int b = patch / (py * px), rem = patch - b * py * px;
+  const int oy = (rem / px) * 32, ox = (rem % px) * 32;
+  const float* base = pg + (size_t)b * Hg * Wg + (size_t)oy * Wg + ox;
+  const int t = threadIdx.x;
+  if (t < 32) {
+    float sv, cv;
+    sincospif((float)t / 16.0f, &sv, &cv);  // angle 2 pi t / 32
+    cs[t] = cv;
+    sn[t] = sv;
+  }
+  for (int i = t; i < 1024; i += 256) x[(i >> 5) * 33 + (i & 31)] = base[(size_t)(i >> 5) * Wg + (i & 31)];
+  __syncthreads();
+  // forward transform along x: rr + i ri = sum_x x[y][x] e^{-2 pi i v x / 32}
+  for (int i = t; i < 1024; i += 256) {
+    const int y = i >> 5, v = i & 31;
+    float sr = 0.f, si = 0.f;
+    for (int xx = 0; xx < 32; ++xx) {
+      const int k = (v * xx) & 31;
+      const float val = x[y * 33 + xx];
+      sr = fmaf(val, cs[k], sr);
+      si = fmaf(-val, sn[k], si);
+    }
+    rr[y * 33 + v] = sr;
+    ri[y * 33 + v] = si;
+  }
+  __syncthreads();
+  // along y: X[u][v] = sum_y (rr + i ri)[y][v] e^{-2 pi i u y / 32}
+  for (int i = t; i < 1024; i += 256) {
+    const int u = i >> 5, v = i & 31;
+    float sr = 0.f, si = 0.f;
+    for (int y = 0; y < 32; ++y) {
+      const int k = (u * y) & 31;
+      const float a = rr[y * 33 + v], bb = ri[y * 33 + v];
+      // (a + i bb)(cos - i sin)
+      sr = fmaf(a, cs[k], fmaf(bb, sn[k], sr));
+      si = fmaf(bb, cs[k], fmaf(-a, sn[k], si));
+    }
+    xr[u * 33 + v] = sr;
+    xi[u * 33 + v] = si;
+    ph[i] = (sr * sr + si * si) * (1.0f / 1024.0f);
+  }
+  __syncthreads();
+  // ring means, fixed summation order: 8 interleaved partial sums per ring
+  if (t < NRING * 8) {
+    const int r = t >> 3, sub = t & 7;
+    float s = 0.f;
+    int cnt = 0;
+    for (int i = sub; i < 1024; i += 8)
+      if (ring_of(i >> 5, i & 31) == r) {
+        s += ph[i];
+        ++cnt;
+      }
+    ring_part[r][sub] = s;
+    ring_npart[r][sub] = cnt;
+  }
+  __syncthreads();
+  if (t < NRING) {
+    float s = 0.f;
+    int cnt = 0;
+    for (int k = 0; k < 8; ++k) {
+      s += ring_part[t][k];
+      cnt += ring_npart[t][k];
+    }
+    ring_mean[t] = s / (float)cnt;
+  }
+  __syncthreads();
+  float lsum = 0.f;
+  for (int i = t; i < 1024; i += 256) {
+    const float d = ph[i] - ring_mean[ring_of(i >> 5, i & 31)];
+    lsum = fmaf(d, d, lsum);
+    ph[i] = 2.0f * d;  // dL/dPhat
+  }
+  lsum = hs_wave_sum(lsum);
+  if ((t & 63) == 0) red[t >> 6] = lsum;
+  __syncthreads();
+  if (t == 0) patch_loss[patch] = ((red[0] + red[1]) + red[2]) + red[3];
+  if (!grad) return;
+  // gradient: dL/dx = (2 / 1024) Re( sum_{u,v} g X e^{+2 pi i (u y + v x) / 32} )
+  for (int i = t; i < 1024; i += 256) {
+    const int u = i >> 5, v = i & 31;
+    xr[u * 33 + v] *= ph[i];
+    xi[u * 33 + v] *= ph[i];
+  }
+  __syncthreads();
+  for (int i = t; i < 1024; i += 256) {  // inverse along u -> y
+    const int y = i >> 5, v = i & 31;
+    float sr = 0.f, si = 0.f;
+    for (int u = 0; u < 32; ++u) {
+      const int k = (u * y) & 31;
+      const float a = xr[u * 33 + v], bb = xi[u * 33 + v];
+      // (a + i bb)(cos + i sin)
+      sr = fmaf(a, cs[k], fmaf(-bb, sn[k], sr));
+      si = fmaf(bb, cs[k], fmaf(a, sn[k], si));
+    }
+    rr[y * 33 + v] = sr;
+    ri[y * 33 + v] = si;
+  }
+  __syncthreads();
+  float* gbase = grad + (size_t)b * Hg * Wg + (size_t)oy * Wg + ox;
+  for (int i = t; i < 1024; i += 256) {  // inverse along v -> x, real part
+    const int y = i >> 5, xx = i & 31;
+    float sr = 0.f;
+    for (int v = 0; v < 32; ++v) {
+      const int k = (v * xx) & 31;
+      sr = fmaf(rr[y * 33 + v], cs[k], fmaf(-ri[y * 33 + v], sn[k], sr));
+    }
+    float gv = sr * (2.0f / 1024.0f) * scale;
+    if (logit_space) {
+      const float p = x[y * 33 + xx];
+      gv *= p * (1.0f - p);
+    }
+    gbase[(size_t)y * Wg + xx] = gv;
+  }
+}
+
+__global__ void fill_kernel(float* __restrict__ p, size_t n, float v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+}  // namespace
+
+namespace hs {
+
+void make_windows(const hs_loss_params& p, LossDev* out) {
+  auto gauss = [](double sigma, int r, float* dst) {
+    const int n = 2 * r + 1;
+    double tmp[15 * 15], sum = 0.0;
+    for (int i = -r; i <= r; ++i)
+      for (int j = -r; j <= r; ++j) {
+        const double v = exp(-(double)(i * i + j * j) / (2.0 * sigma * sigma));
+        tmp[(i + r) * n + (j + r)] = v;
+        sum += v;
+      }
+    for (int i = 0; i < 15 * 15; ++i) dst[i] = 0.0f;
+    for (int i = 0; i < n * n; ++i) dst[i] = (float)(tmp[i] / sum);
+  };
+  gauss(p.hvs_sigma, p.hvs_radius, out->G);
+  gauss(p.ssim_sigma, p.ssim_radius, out->w);
+}
+
+static LossConst make_const(const hs_loss_params& p) {
+  LossConst q;
+  q.rh = p.hvs_radius;
+  q.rs = p.ssim_radius;
+  q.m = p.hvs_radius > p.ssim_radius ? p.hvs_radius : p.ssim_radius;
+  q.k = p.k;
+  q.c1 = p.c1;
+  q.c2 = p.c2;
+  q.w_s = p.w_s;
+  return q;
+}
+
+hipError_t launch_loss_stats(const uint8_t* h, const float* c, int B, int H, int W,
+                             const hs_loss_params& p, const LossDev& win, float* maps,
+                             float* tile_partials, int ntiles_per_img, hipStream_t s) {
+  const LossConst q = make_const(p);
+  const int vh = H - 2 * q.m, vw = W - 2 * q.m;
+  const dim3 grid((vw + LT - 1) / LT, (vh + LT - 1) / LT, B);
+  loss_stats_kernel<<<grid, 256, 0, s>>>(h, c, H, W, q, win, maps, tile_partials,
+                                         ntiles_per_img);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_reduce(const float* tile_partials, int B, int ntiles_per_img,
+                              const float* as_partials, int npatch, float w_s, long M, float* out,
+                              hipStream_t s) {
+  loss_reduce_kernel<<<B + 1, 256, 0, s>>>(tile_partials, B, ntiles_per_img, as_partials, npatch,
+                                           w_s, (float)(1.0 / (double)M), out);
+  return hipGetLastError();
+}
+
+hipError_t launch_le_grad(const uint8_t* h, const float* c, const float* probs, int B, int H,
+                          int W, const hs_loss_params& p, const LossDev& win, const float* maps,
+                          float* grad, hipStream_t s) {
+  const LossConst q = make_const(p);
+  const long M = (long)(H - 2 * q.m) * (W - 2 * q.m);
+  const dim3 grid((W + LT - 1) / LT, (H + LT - 1) / LT, B);
+  le_grad_kernel<<<grid, 256, 0, s>>>(h, c, probs, B, H, W, q, win, maps,
+                                      (float)(1.0 / (double)M), grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_as(const float* pg, int Bg, int Hg, int Wg, float scale, int logit_space,
+                     float* patch_loss, float* grad_or_null, hipStream_t s) {
+  const int npatch = Bg * (Hg / 32) * (Wg / 32);
+  if (npatch == 0) return hipSuccess;
+  as_kernel<<<npatch, 256, 0, s>>>(pg, Bg, Hg, Wg, scale, logit_space, patch_loss, grad_or_null);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  fill_kernel<<<(unsigned)blocks, 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace hs

@@ -1,0 +1,88 @@
+// train.hip -- optimiser step and training metrics on gfx950.
+//
+// Adam (Kingma and Ba) on the FP32 master weights, as used in Sec. VI-A of
+// the paper; the host supplies the cosine-annealed learning rate and the
+// bias-correction factors of the step.
+#include "hs_common.h"
+#include "hs_internal.h"
+
+namespace {
+
+__global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, int n, float lr, float b1, float b2,
+                            float eps, float inv_c1, float inv_c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi * inv_c1, vh = vi * inv_c2;
+  w[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// metrics = {mean MSE, mean CSSIM, mean R, L_AS, lr, |grad|_2, fill, 0}
+__global__ __launch_bounds__(256) void metrics_kernel(const float* __restrict__ loss_out, int B,
+                                                      const float* __restrict__ grad, int n,
+                                                      const uint8_t* __restrict__ act,
+                                                      size_t nact, float lr,
+                                                      float* __restrict__ metrics) {
+  __shared__ float red[4];
+  __shared__ unsigned long long cnt[4];
+  float s = 0.0f;
+  for (int i = threadIdx.x; i < n; i += 256) s = fmaf(grad[i], grad[i], s);
+  // actions are 0/1 bytes: the byte sum of a 32-bit word is (v * 0x01010101) >> 24
+  unsigned long long c = 0;
+  const size_t nvec = nact / 16;
+  const uint4* av = (const uint4*)act;
+  for (size_t i = threadIdx.x; i < nvec; i += 256) {
+    const uint4 v = av[i];
+    c += ((v.x * 0x01010101u) >> 24) + ((v.y * 0x01010101u) >> 24) +
+         ((v.z * 0x01010101u) >> 24) + ((v.w * 0x01010101u) >> 24);
+  }
+  for (size_t i = nvec * 16 + threadIdx.x; i < nact; i += 256) c += act[i];
+  s = hs_wave_sum(s);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = s;
+    cnt[threadIdx.x >> 6] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  float mse = 0.f, cs = 0.f, r = 0.f;
+  for (int b = 0; b < B; ++b) {
+    mse += loss_out[3 * b];
+    cs += loss_out[3 * b + 1];
+    r += loss_out[3 * b + 2];
+  }
+  metrics[0] = mse / B;
+  metrics[1] = cs / B;
+  metrics[2] = r / B;
+  metrics[3] = loss_out[3 * B];
+  metrics[4] = lr;
+  metrics[5] = sqrtf(((red[0] + red[1]) + red[2]) + red[3]);
+  metrics[6] = (float)((double)(((cnt[0] + cnt[1]) + cnt[2]) + cnt[3]) / (double)nact);
+  metrics[7] = 0.0f;
+}
+
+}  // namespace
+
+namespace hs {
+
+hipError_t launch_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t s) {
+  adam_kernel<<<(n + 255) / 256, 256, 0, s>>>(w, m, v, g, n, lr, b1, b2, eps, 1.0f / c1,
+                                              1.0f / c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_train_metrics(const float* loss_out, int B, const float* grad, int n,
+                                const uint8_t* actions, size_t nact, float lr, float* metrics,
+                                hipStream_t s) {
+  metrics_kernel<<<1, 256, 0, s>>>(loss_out, B, grad, n, actions, nact, lr, metrics);
+  return hipGetLastError();
+}
+
+}  // namespace hs

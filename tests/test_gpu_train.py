@@ -1,0 +1,177 @@
+"""GPU parity of the conv-stack backward and of policy_train_step (one
+Algorithm-1 TRAIN iteration) against the oracle, and a short training run."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import device, seeds_t, to_dev
+from paper_2304_12152_amd import autograd as hag
+from paper_2304_12152_amd import binding as hb
+from paper_2304_12152_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _cos(a, b):
+    return float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+@pytest.mark.parametrize("shape", [(1, 20, 27), (2, 64, 70)])
+def test_policy_forward_backward_fp32(orc, shape):
+    B, H, W = shape
+    seeds = list(range(50, 50 + B))
+    w = synth.he_weights(3)
+    c = synth.contone_batch(seeds, H, W)
+    step = 4
+    probs, ws = hb.halftone_policy_forward(to_dev(w), to_dev(c), seeds_t(seeds), step,
+                                           precision=hb.HS_FP32)
+    z = orc.noise_map(seeds, H, W, kind=0, stream=1, step=step)
+    x = orc.policy_forward(w.astype(np.float64), c.astype(np.float64), z)
+    p = orc.sigmoid(x)
+    assert np.abs(probs.cpu().numpy() - p).max() < 1e-5
+    gprob = np.random.default_rng(1).normal(size=(B, H, W)).astype(np.float32)
+    gw = hb.halftone_policy_backward(to_dev(w), to_dev(gprob), probs, ws, hb.HS_FP32)
+    ref, _ = orc.policy_backward(w.astype(np.float64), c.astype(np.float64), z,
+                                 gprob * p * (1 - p))
+    assert _rel(gw.cpu().numpy(), ref) < 1e-5
+
+
+def test_policy_backward_bf16(orc):
+    B, H, W = 2, 64, 70
+    seeds = [60, 61]
+    w = synth.he_weights(3)
+    c = synth.contone_batch(seeds, H, W)
+    probs, ws = hb.halftone_policy_forward(to_dev(w), to_dev(c), seeds_t(seeds), 0,
+                                           precision=hb.HS_BF16)
+    z = orc.noise_map(seeds, H, W, kind=0, stream=1, step=0)
+    p = orc.sigmoid(orc.policy_forward(w.astype(np.float64), c.astype(np.float64), z))
+    assert np.abs(probs.cpu().numpy() - p).max() < 2e-2
+    gprob = np.random.default_rng(2).normal(size=(B, H, W)).astype(np.float32)
+    gw = hb.halftone_policy_backward(to_dev(w), to_dev(gprob), probs, ws, hb.HS_BF16)
+    ref, _ = orc.policy_backward(w.astype(np.float64), c.astype(np.float64), z,
+                                 gprob * p * (1 - p))
+    assert _cos(gw.cpu().numpy(), ref) > 0.999
+
+
+def test_autograd_wrappers(orc):
+    B, H, W = 2, 40, 44
+    seeds = [70, 71]
+    w = synth.he_weights(9)
+    c = synth.contone_batch(seeds, H, W)
+    wt = to_dev(w).requires_grad_(True)
+    probs = hag.policy(wt, to_dev(c), seeds_t(seeds), 0, hb.HS_NOISE_GAUSS, hb.HS_FP32)
+    acts = (torch.rand_like(probs) < probs).to(torch.uint8)
+    loss = hag.halftone_loss(probs, acts, to_dev(c))
+    loss.backward()
+    z = orc.noise_map(seeds, H, W, kind=0, stream=1, step=0)
+    x = orc.policy_forward(w.astype(np.float64), c.astype(np.float64), z)
+    p = orc.sigmoid(x)
+    gp = orc.le_grad_probs(acts.cpu().numpy().astype(np.float64), c.astype(np.float64))
+    ref, _ = orc.policy_backward(w.astype(np.float64), c.astype(np.float64), z, gp * p * (1 - p))
+    assert _rel(wt.grad.cpu().numpy(), ref) < 1e-4
+    r = orc.reward(acts.cpu().numpy().astype(np.float64), c.astype(np.float64))
+    assert abs(loss.item() - (-r[:, 2].mean())) < 1e-5 * abs(r[:, 2].mean()) + 1e-8
+
+
+@pytest.mark.parametrize("with_gray", [False, True])
+def test_train_step_fp32_matches_oracle(orc, with_gray):
+    B, H, W = 2, 40, 48
+    seeds = [80, 81]
+    w = synth.he_weights(5, head_std=0.01)
+    c = synth.contone_batch(seeds, H, W)
+    if with_gray:
+        cg = synth.gray_batch(2, 32, 64)
+        gseeds = [900, 901]
+        Bg, Hg, Wg = cg.shape
+    else:
+        cg, gseeds, Bg, Hg, Wg = None, None, 0, 0, 0
+    step, total = 3, 100
+    state = hb.TrainState(to_dev(w), B, H, W, Bg, Hg, Wg, precision=hb.HS_FP32)
+    acts = torch.empty((B, H, W), dtype=torch.uint8, device=device())
+    grad = torch.empty(hb.HS_PARAM_COUNT, dtype=torch.float32, device=device())
+    met = hb.policy_train_step(state, to_dev(c), seeds_t(seeds),
+                               to_dev(cg) if with_gray else None,
+                               seeds_t(gseeds) if with_gray else None, step, total,
+                               actions_out=acts, grad_out=grad).cpu().numpy()
+    wd = w.astype(np.float64)
+    m = np.zeros_like(wd)
+    v = np.zeros_like(wd)
+    o = orc.train_step(wd, m, v, c.astype(np.float64), np.array(seeds, np.uint64),
+                       cg.astype(np.float64) if with_gray else None,
+                       np.array(gseeds, np.uint64) if with_gray else None, step, total,
+                       actions=acts.cpu().numpy())
+    g = grad.cpu().numpy()
+    assert _rel(g, o["grad"]) < 1e-5
+    # the GPU's own actions are Bernoulli draws of its own probabilities:
+    # they agree with the oracle's draws except where u and p are within FP32
+    # rounding of each other
+    z = orc.noise_map(seeds, H, W, kind=0, stream=1, step=step)
+    pref = orc.sigmoid(orc.policy_forward(wd, c.astype(np.float64), z))
+    u = orc.noise_map(seeds, H, W, kind=1, stream=0, step=step)
+    clear = np.abs(u - pref) > 1e-5
+    assert np.array_equal(acts.cpu().numpy()[clear], (u < pref)[clear].astype(np.uint8))
+    # Adam update (first step of the moments, bias corrections at t = step + 1)
+    np.testing.assert_allclose(state.weights.cpu().numpy(), wd, rtol=0, atol=2e-6)
+    mo = o["metrics"]
+    np.testing.assert_allclose(met[[0, 1, 2, 3]], [mo["mse"], mo["cssim"], mo["reward"],
+                                                   mo["l_as"]], rtol=1e-5, atol=1e-9)
+    assert abs(met[4] - mo["lr"]) < 1e-9
+    assert abs(met[5] - mo["grad_norm"]) <= 1e-5 * mo["grad_norm"]
+    assert abs(met[6] - mo["fill"]) < 1e-7
+
+
+def test_train_step_bf16_gradient(orc):
+    B, H, W = 2, 64, 64
+    seeds = [90, 91]
+    w = synth.he_weights(5, head_std=0.01)
+    c = synth.contone_batch(seeds, H, W)
+    cg = synth.gray_batch(2, 32, 64)
+    state = hb.TrainState(to_dev(w), B, H, W, 2, 32, 64, precision=hb.HS_BF16)
+    acts = torch.empty((B, H, W), dtype=torch.uint8, device=device())
+    grad = torch.empty(hb.HS_PARAM_COUNT, dtype=torch.float32, device=device())
+    hb.policy_train_step(state, to_dev(c), seeds_t(seeds), to_dev(cg), seeds_t([5, 6]), 0, 10,
+                         actions_out=acts, grad_out=grad)
+    wd = w.astype(np.float64)
+    o = orc.train_step(wd, np.zeros_like(wd), np.zeros_like(wd), c.astype(np.float64),
+                       np.array(seeds, np.uint64), cg.astype(np.float64),
+                       np.array([5, 6], np.uint64), 0, 10, actions=acts.cpu().numpy())
+    assert _cos(grad.cpu().numpy(), o["grad"]) > 0.999
+
+
+def test_train_step_is_deterministic():
+    B, H, W = 2, 48, 48
+    w = synth.he_weights(5, head_std=0.01)
+    c = synth.contone_batch([1, 2], H, W)
+    cg = synth.gray_batch(2, 32, 32)
+    outs = []
+    for _ in range(2):
+        st = hb.TrainState(to_dev(w), B, H, W, 2, 32, 32, precision=hb.HS_BF16)
+        for step in range(3):
+            hb.policy_train_step(st, to_dev(c), seeds_t([1, 2]), to_dev(cg), seeds_t([3, 4]),
+                                 step, 10)
+        outs.append(st.weights.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_short_training_improves_reward():
+    # 60 BF16 steps on 8 x 64 x 64 crops: the mean reward of the sampled
+    # halftones rises from the p ~ 0.5 start
+    B, H, W = 8, 64, 64
+    w = synth.he_weights(7, head_std=0.01)
+    st = hb.TrainState(to_dev(w), B, H, W, 8, 64, 64, precision=hb.HS_BF16,
+                       tp=hb.default_train_params(lr_max=1e-3, lr_min=1e-4))
+    gray = to_dev(synth.gray_batch(8, 64, 64))
+    rewards = []
+    for step in range(60):
+        seeds = [10000 + (step * B + i) % 200 for i in range(B)]
+        c = to_dev(synth.contone_batch(seeds, H, W))
+        met = hb.policy_train_step(st, c, seeds_t(seeds), gray,
+                                   seeds_t([7000 + step * 8 + i for i in range(8)]), step, 60)
+        rewards.append(float(met[2].item()))
+    first = np.mean(rewards[:5])
+    last = np.mean(rewards[-5:])
+    assert last > first, (first, last)
