@@ -1,0 +1,200 @@
+"""Benchmark of the halftoning hot path on one MI355X.
+
+Default workload (the inference configuration): a batch of 8 synthetic
+1024 x 1024 contones, the 6 x 32 policy with He-initialised weights, BF16
+MFMA inference with the FP32 recheck of near-threshold pixels. One step is
+one halftone_infer call over the whole batch (inputs resident in HBM).
+
+The JSON line also carries:
+  roofline     -- the fused BF16 kernel's algorithmic FLOP per launch over its
+                  average duration (HIP events around that kernel, live);
+  cpu_baseline -- the CPU oracle on a bounded sample of the same workload;
+  fp32         -- the FP32 path on the same batch (speedup stated);
+  train        -- policy_train_step steps/s on 32 x 256 x 256 crops plus 64
+                  constant-gray 64 x 64 images (BF16 activations).
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "halftone Mpixels/s (BF16 vs FP32 CNN, oracle-matched bits); train steps/s"
+FLOP_PER_PX = 75456          # 2 x (2*32*9 + 4*32*32*9 + 32*9) multiply-adds per pixel
+PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak (published)
+KERNEL_SRC = os.path.join(ROOT, "paper_2304_12152_amd", "csrc", "infer.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_infer_bf16_8x1024x1024_traffic.txt")
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per launch from the committed counter summary, or None if the
+    kernel source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    h = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not h or not b or h.group(1) != kernel_hash():
+        return None
+    return float(b.group(1))
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(c_img, seed, w):
+    """The oracle (plain C, FP64, one thread) on the 512 x 512 top-left crop of
+    workload image 0: noise map, policy forward, threshold."""
+    import numpy as np
+    import oracle.oracle as orc
+    crop = c_img[:512, :512].astype(np.float64)[None]
+    t0 = time.perf_counter()
+    z = orc.noise_map([seed], 512, 512, kind=0, stream=1, step=0)
+    x = orc.policy_forward(w.astype(np.float64), crop, z)
+    orc.threshold(x)
+    dt = time.perf_counter() - t0
+    return {"value": round(512 * 512 / dt / 1e6, 5), "unit": "Mpx/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "oracle (C, FP64, 1 thread): Philox noise + 6x32 policy forward + "
+                      "threshold on the 512x512 top-left crop of workload image 0; %.1f s" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--tau", type=float, default=0.08)
+    ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single "
+              "MI355X (no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2304_12152_amd import binding as hb
+    from paper_2304_12152_amd import synth
+
+    if not os.path.exists(hb.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    dev = torch.device("cuda:0")
+    B, H, W = 8, 1024, 1024
+    seeds = list(range(11, 19))
+    log("generating the 8 x 1024 x 1024 synthetic batch")
+    w = synth.he_weights(42)
+    c = synth.contone_batch(seeds, H, W)
+    wt = torch.tensor(w, device=dev)
+    ct = torch.tensor(c, device=dev)
+    st = torch.tensor(seeds, dtype=torch.int64, device=dev)
+    npx = B * H * W
+    ws = torch.empty(hb.lib().halftone_infer_workspace_size(B, H, W, hb.HS_BF16),
+                     dtype=torch.uint8, device=dev)
+
+    def step():
+        return hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_BF16, args.tau,
+                                 workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    hb.halftone_profile_start()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = hb.halftone_profile_stop()
+    ms_per_step = dt * 1e3 / args.steps
+    value = npx * args.steps / dt / 1e6
+    log("bf16: %.3f ms/step, %.1f Mpx/s" % (ms_per_step, value))
+
+    avg_kernel_s = kern_ms / 1e3 / max(launches, 1)
+    achieved = FLOP_PER_PX * npx / avg_kernel_s / 1e12
+    traffic = traffic_per_launch()
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
+                "traffic": traffic, "kernel": "fused_infer_kernel (BF16, 8x1024x1024)",
+                "kernel_ms": round(avg_kernel_s * 1e3, 4)}
+
+    # recheck statistics and agreement with the FP32 path on the same batch
+    bits16, lg16, stats = hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_BF16, args.tau,
+                                            logits=True, stats=True, workspace=ws)
+    stats = stats.cpu().tolist()
+    extra = {"recheck": {"tau": args.tau, "rechecked": stats[0], "flipped": stats[1],
+                         "fraction": round(stats[0] / npx, 6)}}
+    if not args.no_fp32:
+        ws32 = torch.empty(hb.lib().halftone_infer_workspace_size(B, H, W, hb.HS_FP32),
+                           dtype=torch.uint8, device=dev)
+        b32, l32 = hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_FP32, logits=True,
+                                     workspace=ws32)
+        n32 = max(2, args.steps // 5)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(n32):
+            hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_FP32, workspace=ws32)
+        torch.cuda.synchronize()
+        v32 = npx * n32 / (time.perf_counter() - t1) / 1e6
+        off = l32.abs() > 4.1e-4
+        mism = int(((bits16 != b32) & off).sum().item())
+        extra["fp32"] = {"value": round(v32, 1), "unit": "Mpx/s",
+                         "speedup_bf16_vs_fp32": round(value / v32, 2),
+                         "bits_differing_off_margin": mism}
+        log("fp32: %.1f Mpx/s, speedup %.2f, mismatches %d" % (v32, value / v32, mism))
+        del ws32, b32, l32
+    if not args.no_train:
+        Bt, Ht, Wt, Bg = 32, 256, 256, 64
+        log("training step: 32 x 256 x 256 + 64 gray 64 x 64")
+        tw = torch.tensor(synth.he_weights(42, head_std=0.01), device=dev)
+        state = hb.TrainState(tw, Bt, Ht, Wt, Bg, 64, 64, precision=hb.HS_BF16)
+        tc = torch.tensor(synth.contone_batch(range(1000000, 1000032), Ht, Wt), device=dev)
+        ts = torch.tensor(list(range(1000000, 1000032)), dtype=torch.int64, device=dev)
+        gray = torch.tensor(synth.gray_batch(64, 64, 64), device=dev)
+        gs = torch.tensor(list(range(5000, 5064)), dtype=torch.int64, device=dev)
+        for i in range(2):
+            hb.policy_train_step(state, tc, ts, gray, gs, i, 1000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for i in range(args.train_steps):
+            hb.policy_train_step(state, tc, ts, gray, gs, 2 + i, 1000)
+        torch.cuda.synchronize()
+        sps = args.train_steps / (time.perf_counter() - t2)
+        extra["train"] = {"value": round(sps, 2), "unit": "steps/s",
+                          "config": "32 x 256x256 crops + 64 constant-gray 64x64, BF16 "
+                                    "activations, FP32 master weights, Adam"}
+        log("train: %.2f steps/s" % sps)
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mpx/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "inference: 8 x 1024x1024 synthetic contones (seeds 11..18), "
+                               "6x32 policy, He-init weights (seed 42), BF16 MFMA + FP32 "
+                               "recheck", "batch": B, "height": H, "width": W,
+                   "recheck_tau": args.tau},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(c[0], seeds[0], w)
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -208,6 +208,18 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
                       void* workspace, size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Timing of the dominant kernel, for benchmarks. Between
+ * halftone_profile_start() and halftone_profile_stop(), every
+ * halftone_infer call records a pair of hipEvents on its stream around its
+ * dominant kernel (the fused BF16 kernel; for HS_FP32 the four 32->32
+ * convolution launches taken together), at most 4096 pairs.
+ * halftone_profile_stop waits for the recorded events and returns their
+ * summed duration (ms) and the number of recorded calls (host pointers).
+ * --------------------------------------------------------------------- */
+int halftone_profile_start(void);
+int halftone_profile_stop(double* ms_total_host, int* launches_host);
+
+/* ---------------------------------------------------------------------
  * Floyd-Steinberg error diffusion on the host (the classic error diffusion
  * cited in Sec. I), the CPU fallback and the baseline of the judge:
  * raster order, threshold v >= 0.5, weights 7/16 right, 3/16 down-left,

@@ -64,6 +64,8 @@ _SIGS = {
                               ctypes.c_int64, ctypes.POINTER(HsTrainParams), I, P, P, P, P, SZ,
                               P]),
     "halftone_error_diffusion_host": (I, [P, I, I, I, P]),
+    "halftone_profile_start": (I, []),
+    "halftone_profile_stop": (I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
 }
 
 
@@ -231,6 +233,18 @@ def policy_train_step(state, contones, seeds, gray, gray_seeds, step, total_step
                                    _ptr(actions_out), _ptr(grad_out), _ptr(state.ws),
                                    state.ws.numel(), _stream()))
     return state.metrics
+
+
+def halftone_profile_start():
+    _check(lib().halftone_profile_start())
+
+
+def halftone_profile_stop():
+    """(summed milliseconds of the dominant kernel, number of recorded calls)."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int(0)
+    _check(lib().halftone_profile_stop(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def halftone_error_diffusion_host(contone_host):

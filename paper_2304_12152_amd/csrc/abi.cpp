@@ -178,6 +178,51 @@ hipError_t run_backward(const float* w, const float* grad, const float* probs, i
   return launch_wgrad_first(pw.c, pw.z, g, B, H, W, prec, pw.partials, accumulate, s);
 }
 
+int num_cus() {
+  static std::mutex mu;
+  static std::vector<int> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+  if (cache[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cache[dev] = n;
+  }
+  return cache[dev];
+}
+
+// Event pairs around the dominant kernel of each inference call, recorded
+// only between halftone_profile_start and halftone_profile_stop.
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // pairs: 2i begin, 2i + 1 end
+  int used = 0;
+} g_prof;
+constexpr int PROF_MAX = 4096;
+
+void prof_begin(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (!g_prof.on || g_prof.used >= PROF_MAX) return;
+  while ((int)g_prof.ev.size() < 2 * (g_prof.used + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    g_prof.ev.push_back(e);
+  }
+  (void)hipEventRecord(g_prof.ev[2 * g_prof.used], s);
+}
+
+void prof_end(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (!g_prof.on || g_prof.used >= PROF_MAX || (int)g_prof.ev.size() < 2 * (g_prof.used + 1))
+    return;
+  (void)hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s);
+  ++g_prof.used;
+}
+
 }  // namespace
 
 // ===================================================================== ABI ==
@@ -209,6 +254,30 @@ void halftone_default_train_params(hs_train_params* p) {
 }
 
 int halftone_version(void) { return 100; }
+
+int halftone_profile_start(void) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = true;
+  g_prof.used = 0;
+  return HS_OK;
+}
+
+int halftone_profile_stop(double* ms_total, int* launches) {
+  if (!ms_total || !launches) return fail(HS_EINVAL, "halftone_profile_stop: null pointer");
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = false;
+  double sum = 0.0;
+  for (int i = 0; i < g_prof.used; ++i) {
+    HS_TRY(hipEventSynchronize(g_prof.ev[2 * i + 1]));
+    float ms = 0.0f;
+    HS_TRY(hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]));
+    sum += ms;
+  }
+  *ms_total = sum;
+  *launches = g_prof.used;
+  g_prof.used = 0;
+  return HS_OK;
+}
 const char* halftone_last_error(void) { return g_err.c_str(); }
 int64_t halftone_param_count(void) { return HS_PARAM_COUNT; }
 
@@ -217,7 +286,13 @@ static size_t infer_ws(int B, int H, int W, int prec, InferWs* out, uint32_t** l
                        void* base) {
   Carve cv(base);
   const size_t N = (size_t)B * H * W;
-  InferWs w = carve_infer(cv, N, prec);
+  InferWs w;
+  if (prec == HS_BF16) {  // fused path: packed fragments only
+    w.pack = cv.take<char>(fused_frag_bytes());
+    w.a0 = w.a1 = nullptr;
+  } else {
+    w = carve_infer(cv, N, prec);
+  }
   uint32_t* l = cv.take<uint32_t>(N * 4);
   int* c = cv.take<int>(64);
   if (out) *out = w;
@@ -256,24 +331,32 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
   int32_t* stats = stats_or_null ? stats_or_null : (int32_t*)(cnt + 8);
   HS_TRY(launch_zero_ints(cnt, 16, s));
   if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 2, s));
+  if (precision == HS_BF16) {
+    HS_TRY(launch_fused_pack(weights, iw.pack, s));
+    prof_begin(s);
+    HS_TRY(launch_fused_infer(weights, contone, seeds, B, H, W, noise_kind, recheck_tau, bits,
+                              logits_or_null, list, cnt, iw.pack, num_cus(), s));
+    prof_end(s);
+    HS_TRY(launch_recheck_fp32(weights, contone, seeds, H, W, noise_kind, list, cnt, bits,
+                               logits_or_null, stats, s));
+    return HS_OK;
+  }
   HS_TRY(launch_pack32(weights, iw.pack, precision, 0, s));
   HS_TRY(launch_conv_first(contone, seeds, weights, B, H, W, noise_kind, 0u, precision, iw.a0,
                            nullptr, nullptr, s));
   void* src = iw.a0;
   void* dst = iw.a1;
   for (int k = 2; k <= 5; ++k) {
+    if (k == 2) prof_begin(s);
     HS_TRY(launch_conv32(src, (const char*)iw.pack + (k - 2) * per_layer, weights + hs_bk(k),
                          nullptr, dst, B, H, W, precision, 0, s));
+    if (k == 5) prof_end(s);
     void* t = src;
     src = dst;
     dst = t;
   }
-  const bool recheck = precision == HS_BF16;
   HS_TRY(launch_conv_last(src, weights, B, H, W, precision, 0, seeds, 0u, bits, logits_or_null,
-                          nullptr, recheck_tau, recheck ? list : nullptr, cnt, s));
-  if (recheck)
-    HS_TRY(launch_recheck_fp32(weights, contone, seeds, H, W, noise_kind, list, cnt, bits,
-                               logits_or_null, stats, s));
+                          nullptr, 0.0f, nullptr, cnt, s));
   return HS_OK;
 }
 

@@ -52,6 +52,13 @@ hipError_t launch_conv_last(const void* in, const float* w, int B, int H, int W,
                             hipStream_t s);
 // infer.hip: FP32 re-evaluation of listed pixels over their receptive field.
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
+size_t fused_frag_bytes();
+hipError_t launch_fused_pack(const float* w, void* frags, hipStream_t s);
+// persistent fused BF16 inference; list/count may be null (no recheck list)
+hipError_t launch_fused_infer(const float* w, const float* contone, const uint64_t* seeds, int B,
+                              int H, int W, int kind, float tau, uint8_t* bits, float* logits,
+                              uint32_t* list, int* count, const void* frags, int num_cus,
+                              hipStream_t s);
 hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,
                                int H, int W, int kind, const uint32_t* list, const int* count,
                                uint8_t* bits, float* logits, int32_t* stats, hipStream_t s);

@@ -54,7 +54,15 @@ def test_policy_backward_bf16(orc):
     gw = hb.halftone_policy_backward(to_dev(w), to_dev(gprob), probs, ws, hb.HS_BF16)
     ref, _ = orc.policy_backward(w.astype(np.float64), c.astype(np.float64), z,
                                  gprob * p * (1 - p))
-    assert _cos(gw.cpu().numpy(), ref) > 0.999
+    # BF16 rounding of the forward activations and weights alone moves this
+    # gradient to cosine 0.9967 (layer-1 normwise error 0.115) in a CPU
+    # emulation of the same rounding points; gradient rounding adds ~3e-6.
+    # Bound: cosine > 0.99 overall and < 0.3 normwise error per layer.
+    g = gw.cpu().numpy()
+    assert _cos(g, ref) > 0.99
+    for lo, hi in [(0, 608), (608, 9856), (9856, 19104), (19104, 28352), (28352, 37600),
+                   (37600, 37889)]:
+        assert _rel(g[lo:hi], ref[lo:hi]) < 0.3
 
 
 def test_autograd_wrappers(orc):
@@ -110,7 +118,7 @@ def test_train_step_fp32_matches_oracle(orc, with_gray):
     # they agree with the oracle's draws except where u and p are within FP32
     # rounding of each other
     z = orc.noise_map(seeds, H, W, kind=0, stream=1, step=step)
-    pref = orc.sigmoid(orc.policy_forward(wd, c.astype(np.float64), z))
+    pref = orc.sigmoid(orc.policy_forward(w.astype(np.float64), c.astype(np.float64), z))
     u = orc.noise_map(seeds, H, W, kind=1, stream=0, step=step)
     clear = np.abs(u - pref) > 1e-5
     assert np.array_equal(acts.cpu().numpy()[clear], (u < pref)[clear].astype(np.uint8))
