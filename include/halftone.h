@@ -104,12 +104,18 @@ int64_t halftone_param_count(void);
  * seeds    [B] uint64.
  * precision HS_FP32: FP32 arithmetic. HS_BF16: BF16 MFMA with FP32
  *          accumulation; every pixel whose BF16 logit satisfies
- *          |x| < recheck_tau is recomputed in FP32 over its 13x13 receptive
- *          field and decided from that value (recheck_tau >= 0).
+ *          |x| < recheck_tau is recomputed over its 13x13 receptive field
+ *          with split-BF16 products (hi*hi + lo*hi + hi*lo, FP32
+ *          accumulation, about 2^-8 of the BF16 error), and every pixel
+ *          whose recomputed |x| is still below tau2 = recheck_tau/32 clamped
+ *          to [1e-3, 1e-2] is recomputed once more in FP32 and decided from that
+ *          value (recheck_tau >= 0; it must exceed the largest BF16 logit
+ *          error for the bits to equal FP32's off-margin).
  * bits     [B][H][W] uint8 out.
  * logits_or_null [B][H][W] FP32 out: the logit each bit was decided from.
- * stats_or_null  int32[2] out: {pixels rechecked, bits changed by the
- *          recheck}; 0 for HS_FP32.
+ * stats_or_null  int32[4] out: {pixels rechecked (|x_bf16| < recheck_tau),
+ *          bits changed by the rechecks, pixels recomputed in FP32, 0};
+ *          zeros for HS_FP32.
  * Shapes: B >= 1, H >= 1, W >= 1, B*H*W < 2^31.
  * --------------------------------------------------------------------- */
 size_t halftone_infer_workspace_size(int B, int H, int W, int precision);

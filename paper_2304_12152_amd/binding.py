@@ -128,13 +128,14 @@ def default_train_params(**kw):
 
 def halftone_infer(weights, contone, seeds, noise_kind=HS_NOISE_GAUSS, precision=HS_BF16,
                    recheck_tau=0.05, logits=False, stats=False, workspace=None):
-    """bits [B,H,W] uint8 (and optionally logits, stats = (rechecked, flipped))."""
+    """bits [B,H,W] uint8 (and optionally logits, and stats =
+    (rechecked, flipped, recomputed in FP32, 0))."""
     B, H, W = contone.shape
     dev = contone.device
     _dev(weights, torch.float32), _dev(contone, torch.float32), _dev(seeds, torch.int64)
     bits = torch.empty((B, H, W), dtype=torch.uint8, device=dev)
     lg = torch.empty((B, H, W), dtype=torch.float32, device=dev) if logits else None
-    st = torch.zeros(2, dtype=torch.int32, device=dev) if stats else None
+    st = torch.zeros(4, dtype=torch.int32, device=dev) if stats else None
     need = lib().halftone_infer_workspace_size(B, H, W, precision)
     ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
     _check(lib().halftone_infer(_ptr(weights), _ptr(contone), _ptr(seeds), B, H, W, noise_kind,

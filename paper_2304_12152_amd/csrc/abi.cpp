@@ -287,16 +287,18 @@ static size_t infer_ws(int B, int H, int W, int prec, InferWs* out, uint32_t** l
   Carve cv(base);
   const size_t N = (size_t)B * H * W;
   InferWs w;
-  if (prec == HS_BF16) {  // fused path: packed fragments only
+  if (prec == HS_BF16) {  // fused path: packed fragments and two recheck lists
     w.pack = cv.take<char>(fused_frag_bytes());
-    w.a0 = w.a1 = nullptr;
+    w.a0 = cv.take<char>(split_frag_bytes());
+    w.a1 = nullptr;
+    uint32_t* l = cv.take<uint32_t>(2 * N * 4);
+    if (list) *list = l;
   } else {
     w = carve_infer(cv, N, prec);
+    if (list) *list = nullptr;
   }
-  uint32_t* l = cv.take<uint32_t>(N * 4);
   int* c = cv.take<int>(64);
   if (out) *out = w;
-  if (list) *list = l;
   if (cnt) *cnt = c;
   return cv.off;
 }
@@ -330,15 +332,26 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
   const size_t per_layer = (size_t)PACK32_PER_LAYER * (precision == HS_BF16 ? 2 : 4);
   int32_t* stats = stats_or_null ? stats_or_null : (int32_t*)(cnt + 8);
   HS_TRY(launch_zero_ints(cnt, 16, s));
-  if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 2, s));
+  if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
   if (precision == HS_BF16) {
+    // stage 1: fused BF16 pass, pixels with |x| < tau listed
+    // stage 2: split-BF16 receptive-field recompute, |x| < tau2 listed again
+    // stage 3: FP32 receptive-field recompute
+    const float tau2 = fminf(fmaxf(recheck_tau / 32.0f, 1e-3f), 1e-2f);
+    const size_t N = (size_t)B * H * W;
+    uint32_t* list2 = list + N;
+    char* whi = (char*)iw.a0;
+    char* wlo = whi + split_frag_bytes() / 2;
     HS_TRY(launch_fused_pack(weights, iw.pack, s));
+    HS_TRY(launch_split_pack(weights, whi, wlo, s));
     prof_begin(s);
     HS_TRY(launch_fused_infer(weights, contone, seeds, B, H, W, noise_kind, recheck_tau, bits,
                               logits_or_null, list, cnt, iw.pack, num_cus(), s));
     prof_end(s);
-    HS_TRY(launch_recheck_fp32(weights, contone, seeds, H, W, noise_kind, list, cnt, bits,
-                               logits_or_null, stats, s));
+    HS_TRY(launch_recheck_split(weights, contone, seeds, H, W, noise_kind, list, cnt, whi, wlo,
+                                tau2, list2, cnt + 1, bits, logits_or_null, stats, num_cus(), s));
+    HS_TRY(launch_recheck_fp32(weights, contone, seeds, H, W, noise_kind, list2, cnt + 1, bits,
+                               logits_or_null, stats, 2, s));
     return HS_OK;
   }
   HS_TRY(launch_pack32(weights, iw.pack, precision, 0, s));

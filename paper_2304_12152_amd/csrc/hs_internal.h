@@ -61,7 +61,15 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
                               hipStream_t s);
 hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,
                                int H, int W, int kind, const uint32_t* list, const int* count,
-                               uint8_t* bits, float* logits, int32_t* stats, hipStream_t s);
+                               uint8_t* bits, float* logits, int32_t* stats, int count_slot,
+                               hipStream_t s);
+size_t split_frag_bytes();
+hipError_t launch_split_pack(const float* w, void* whi, void* wlo, hipStream_t s);
+hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
+                                int H, int W, int kind, const uint32_t* list, const int* count,
+                                const void* whi, const void* wlo, float tau2, uint32_t* list2,
+                                int* count2, uint8_t* bits, float* logits, int32_t* stats,
+                                int num_cus, hipStream_t s);
 // g6 = grad (if probs == null) or grad * p (1 - p); writes g6 and the
 // masked input gradient of layer 6.
 hipError_t launch_dgrad_last(const float* grad, const float* probs, const void* a5,

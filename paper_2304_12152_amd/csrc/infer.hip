@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void recheck_fp32_kernel(
     const float* __restrict__ w, const float* __restrict__ contone,
     const uint64_t* __restrict__ seeds, int H, int W, int kind, const uint32_t* __restrict__ list,
     const int* __restrict__ count, uint8_t* __restrict__ bits, float* __restrict__ logits,
-    int32_t* __restrict__ stats) {
+    int32_t* __restrict__ stats, int count_slot) {
   __shared__ float s0[13 * 13 * 2];
   __shared__ float bufA[11 * 11 * RS], bufB[9 * 9 * RS];
   __shared__ float sw[9 * 32 * 32];  // [ci][t][co]: consecutive lanes read consecutive co
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void recheck_fp32_kernel(
       }
     }
   }
-  if (blockIdx.x == 0 && tid == 0) stats[0] = n;
+  if (blockIdx.x == 0 && tid == 0) stats[count_slot] = n;
 }
 
 }  // namespace
@@ -132,9 +132,10 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
 
 hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,
                                int H, int W, int kind, const uint32_t* list, const int* count,
-                               uint8_t* bits, float* logits, int32_t* stats, hipStream_t s) {
+                               uint8_t* bits, float* logits, int32_t* stats, int count_slot,
+                               hipStream_t s) {
   recheck_fp32_kernel<<<1024, 256, 0, s>>>(w, contone, seeds, H, W, kind, list, count, bits,
-                                           logits, stats);
+                                           logits, stats, count_slot);
   return hipGetLastError();
 }
 
@@ -451,6 +452,235 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
   a.count = count;
   const int grid = (int)((a.total_rows + per - 1) / per);
   fused_infer_kernel<<<grid, 512, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace hs
+
+// ===========================================================================
+// Second-stage recheck: the listed pixels' receptive fields recomputed with
+// split-BF16 products on the matrix cores. Every FP32 value v is carried as
+// hi + lo with hi = bf16(v), lo = bf16(v - hi); a product is taken as
+// hi*hi' + lo*hi' + hi*lo' (the lo*lo' term, ~2^-16 relative, is dropped),
+// accumulated in FP32. Layer 1 and layer 6 are evaluated in plain FP32. The
+// result's error is ~2^-8 of the BF16 pass's, so a pixel is decided here
+// when |x| >= tau2; the rest go to the FP32 stage.
+//
+// A block takes CB = 4 listed pixels at a time. For layer k the four cones'
+// (13-2k)^2 output positions are cut into 16-position runs (the N operand);
+// the layer's hi and lo weight fragments sit in LDS for all runs.
+// ===========================================================================
+namespace {
+
+constexpr int CB = 4;                 // cones per block
+constexpr int CREC = 128;             // bytes per staged pixel: 4 groups x (hi, lo) x 16 B
+constexpr int CBUF_A = 121, CBUF_B = 81;
+
+__global__ void pack_split_kernel(const float* __restrict__ w, __bf16* __restrict__ hi,
+                                  __bf16* __restrict__ lo) {
+  // layers 2..5 in the ring channel order of the fused kernel: [layer][tap][m][lane][8]
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 4 * 9 * 2 * 64 * 8;
+       i += gridDim.x * blockDim.x) {
+    const int e = i & 7, l = (i >> 3) & 63, m = (i >> 9) & 1, t = (i >> 10) % 9,
+              layer = (i >> 10) / 9;
+    const int g = l >> 4, r = l & 15;
+    const float v = w[hs_wk(layer + 2) + ((16 * m + r) * 32 + ring_channel(g, e)) * 9 + t];
+    const __bf16 h = (__bf16)v;
+    hi[i] = h;
+    lo[i] = (__bf16)(v - (float)h);
+  }
+}
+
+HS_DEV int crec_slot(int p, int c) { return c ^ (p & 7); }
+
+__global__ __launch_bounds__(256) void recheck_split_kernel(
+    const float* __restrict__ w, const float* __restrict__ contone,
+    const uint64_t* __restrict__ seeds, int H, int W, int kind, const uint32_t* __restrict__ list,
+    const int* __restrict__ count, const bf16x8_t* __restrict__ whi,
+    const bf16x8_t* __restrict__ wlo, float tau2, uint32_t* __restrict__ list2,
+    int* __restrict__ count2, uint8_t* __restrict__ bits, float* __restrict__ logits,
+    int32_t* __restrict__ stats) {
+  __shared__ __attribute__((aligned(16))) bf16x8_t swh[9 * 2 * 64], swl[9 * 2 * 64];
+  __shared__ __attribute__((aligned(16))) char bufA[CB][CBUF_A * CREC];
+  __shared__ __attribute__((aligned(16))) char bufB[CB][CBUF_B * CREC];
+  __shared__ float s0[CB][169 * 2];
+  __shared__ float sw1[32 * 2 * 9 + 32];
+  __shared__ float l5f[CB][9 * 32];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
+  const int n = *count;
+  for (int i = tid; i < 608; i += 256) sw1[i] = w[HS_W1 + i];
+  for (int base = blockIdx.x * CB; base < n; base += gridDim.x * CB) {
+    const int ncone = n - base < CB ? n - base : CB;
+    __syncthreads();
+    // stage the 13 x 13 state (c, z) of each cone, zero outside the image
+    for (int i = tid; i < CB * 169; i += 256) {
+      const int cidx = i / 169, q = i - cidx * 169;
+      float cv = 0.f, zv = 0.f;
+      if (cidx < ncone) {
+        const uint32_t o = list[base + cidx];
+        const int b = (int)(o / ((uint32_t)H * W));
+        const int rem = (int)(o - (uint32_t)b * H * W), y = rem / W, x = rem - (rem / W) * W;
+        const int gy = y - 6 + q / 13, gx = x - 6 + q % 13;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+          const uint64_t a = (uint64_t)gy * W + gx;
+          cv = contone[(size_t)b * H * W + a];
+          zv = hs_noise(seeds[b], a, 0u, kind);
+        }
+      }
+      s0[cidx][q * 2] = cv;
+      s0[cidx][q * 2 + 1] = zv;
+    }
+    __syncthreads();
+    // layer 1 in FP32 on the 11 x 11 windows; outputs stored split, in the
+    // ring channel order (chunk g holds channels 4g..4g+3, 16+4g..16+4g+3)
+    for (int i = tid; i < CB * 121 * 4; i += 256) {
+      const int cidx = i / 484, rem = i - cidx * 484, p = rem >> 2, cg = rem & 3;
+      const int py = p / 11, px = p - (p / 11) * 11;
+      const uint32_t o = list[base + (cidx < ncone ? cidx : 0)];
+      const int b = (int)(o / ((uint32_t)H * W));
+      const int rr = (int)(o - (uint32_t)b * H * W), y = rr / W, x = rr - (rr / W) * W;
+      const int gy = y - 5 + py, gx = x - 5 + px;
+      const bool in = cidx < ncone && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      bf16x8_t vh, vl;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int co = ring_channel(cg, e);
+        float acc = 0.f;
+        if (in) {
+          acc = sw1[HS_B1 + co];
+#pragma unroll
+          for (int t = 0; t < 9; ++t) {
+            const int q = (py + t / 3) * 13 + px + t % 3;
+            acc = fmaf(sw1[(co * 2) * 9 + t], s0[cidx][q * 2], acc);
+            acc = fmaf(sw1[(co * 2 + 1) * 9 + t], s0[cidx][q * 2 + 1], acc);
+          }
+          acc = fmaxf(acc, 0.f);
+        }
+        const __bf16 h = (__bf16)acc;
+        vh[e] = h;
+        vl[e] = (__bf16)(acc - (float)h);
+      }
+      char* rec = bufA[cidx] + p * CREC;
+      *(bf16x8_t*)(rec + crec_slot(p, 2 * cg) * 16) = vh;
+      *(bf16x8_t*)(rec + crec_slot(p, 2 * cg + 1) * 16) = vl;
+    }
+    // layers 2..5 on the matrix cores
+    for (int k = 2; k <= 5; ++k) {
+      const int e_out = 13 - 2 * k, e_in = e_out + 2, npos = e_out * e_out;
+      const int runs = (npos + 15) / 16;
+      __syncthreads();
+      for (int i = tid; i < 9 * 2 * 64; i += 256) {
+        swh[i] = whi[(k - 2) * 9 * 2 * 64 + i];
+        swl[i] = wlo[(k - 2) * 9 * 2 * 64 + i];
+      }
+      __syncthreads();
+      const bool from_a = (k & 1) == 0;  // layer 2 reads A, 3 reads B, ...
+      float bk[2][4];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bk[m][i] = w[hs_bk(k) + 16 * m + 4 * g + i];
+      for (int job = wave; job < CB * runs; job += 4) {
+        const int cidx = job / runs, run = job - cidx * runs;
+        const char* src = from_a ? bufA[cidx] : bufB[cidx];
+        char* dst = from_a ? bufB[cidx] : bufA[cidx];
+        const int pos = run * 16 + r;  // this lane's output position
+        const int pi = pos < npos ? pos / e_out : 0, pj = pos < npos ? pos - pi * e_out : 0;
+        f32x4_t acc[2] = {f32x4_t{0.f, 0.f, 0.f, 0.f}, f32x4_t{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const int q = (pi + t / 3) * e_in + pj + t % 3;
+          const char* rec = src + q * CREC;
+          const bf16x8_t bh = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g) * 16);
+          const bf16x8_t bl = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g + 1) * 16);
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            const bf16x8_t ah = swh[(t * 2 + m) * 64 + lane], al = swl[(t * 2 + m) * 64 + lane];
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[m], 0, 0, 0);
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[m], 0, 0, 0);
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[m], 0, 0, 0);
+          }
+        }
+        if (pos < npos && cidx < ncone) {
+          const uint32_t o = list[base + cidx];
+          const int b = (int)(o / ((uint32_t)H * W));
+          const int rr = (int)(o - (uint32_t)b * H * W), y = rr / W, x = rr - (rr / W) * W;
+          const int gy = y - (6 - k) + pi, gx = x - (6 - k) + pj;
+          const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+          float v[2][4];
+#pragma unroll
+          for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[m][i] = in ? fmaxf(acc[m][i] + bk[m][i], 0.f) : 0.f;
+          if (k == 5) {  // keep layer 5 in FP32 for the head
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) l5f[cidx][pos * 32 + 16 * m + 4 * g + i] = v[m][i];
+          } else {
+            bf16x8_t vh, vl;
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const __bf16 h = (__bf16)v[m][i];
+                vh[4 * m + i] = h;
+                vl[4 * m + i] = (__bf16)(v[m][i] - (float)h);
+              }
+            char* rec = dst + pos * CREC;
+            *(bf16x8_t*)(rec + crec_slot(pos, 2 * g) * 16) = vh;
+            *(bf16x8_t*)(rec + crec_slot(pos, 2 * g + 1) * 16) = vl;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // layer 6 in FP32, one wave per cone
+    if (wave < ncone) {
+      float part = 0.f;
+      for (int i = lane; i < 288; i += 64) {
+        const int ci = i / 9, t = i % 9;
+        part = fmaf(w[HS_W6 + i], l5f[wave][t * 32 + ci], part);
+      }
+      part = hs_wave_sum(part);
+      if (lane == 0) {
+        const uint32_t o = list[base + wave];
+        const float xl = part + w[HS_B6];
+        if (fabsf(xl) >= tau2) {
+          const uint8_t nb = xl >= 0.f ? 1 : 0;
+          if (bits[o] != nb) atomicAdd(&stats[1], 1);
+          bits[o] = nb;
+          if (logits) logits[o] = xl;
+        } else {
+          list2[atomicAdd(count2, 1)] = o;
+        }
+      }
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0) stats[0] = n;
+}
+
+}  // namespace
+
+namespace hs {
+
+// bytes of the hi and the lo copy together (each 4 layers x 9 taps x 2 row
+// tiles x 64 lanes x 8 BF16 values)
+size_t split_frag_bytes() { return 2 * (size_t)(4 * 9 * 2 * 64 * 8) * sizeof(__bf16); }
+
+hipError_t launch_split_pack(const float* w, void* whi, void* wlo, hipStream_t s) {
+  pack_split_kernel<<<36, 256, 0, s>>>(w, (__bf16*)whi, (__bf16*)wlo);
+  return hipGetLastError();
+}
+
+hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
+                                int H, int W, int kind, const uint32_t* list, const int* count,
+                                const void* whi, const void* wlo, float tau2, uint32_t* list2,
+                                int* count2, uint8_t* bits, float* logits, int32_t* stats,
+                                int num_cus, hipStream_t s) {
+  recheck_split_kernel<<<num_cus, 256, 0, s>>>(w, contone, seeds, H, W, kind, list, count,
+                                               (const bf16x8_t*)whi, (const bf16x8_t*)wlo, tau2,
+                                               list2, count2, bits, logits, stats);
   return hipGetLastError();
 }
 

@@ -51,17 +51,21 @@ def test_bf16_with_recheck_matches_oracle(orc, shape):
     _say("infer bf16", shape)
     w, c = inputs(seeds, H, W)
     ref = _oracle_logits(orc, w, c, seeds, 0)
-    tau = 0.08
+    tau = 0.055
     bits, lg, st = hb.halftone_infer(to_dev(w), to_dev(c), seeds_t(seeds), 0, hb.HS_BF16, tau,
                                      logits=True, stats=True)
     bits, lg, st = bits.cpu().numpy(), lg.cpu().numpy(), st.cpu().numpy()
     m = parity_mask(orc, ref)
     assert np.array_equal(bits[m], (ref >= 0)[m].astype(np.uint8))
-    # rechecked pixels carry the FP32 logit; the others a BF16 logit
+    # rechecked pixels carry the split-BF16 logit (error ~2^-8 of BF16's) or,
+    # within tau2 of the threshold, the FP32 one; the others a BF16 logit
     near = np.abs(lg) < tau
-    assert np.abs(lg[near] - ref[near]).max(initial=0.0) <= 2e-5 * max(1.0, np.abs(ref).max())
+    assert np.abs(lg[near] - ref[near]).max(initial=0.0) <= 5e-4
+    tau2 = min(max(tau / 32, 1e-3), 1e-2)
+    nearer = np.abs(lg) < tau2
+    assert np.abs(lg[nearer] - ref[nearer]).max(initial=0.0) <= 2e-5 * max(1.0, np.abs(ref).max())
     assert np.abs(lg - ref).max() < tau
-    assert st[0] >= near.sum() and st[1] >= 0 and st[1] <= st[0]
+    assert st[0] >= near.sum() and 0 <= st[1] <= st[0] and 0 <= st[2] <= st[0]
 
 
 def test_infer_is_deterministic(orc):
@@ -82,7 +86,7 @@ def test_c2_full_size_sampled(orc):
     w, c = inputs(seeds, H, W)
     wt, ct, st = to_dev(w), to_dev(c), seeds_t(seeds)
     b32, l32 = hb.halftone_infer(wt, ct, st, 0, hb.HS_FP32, logits=True)
-    b16, l16, stats = hb.halftone_infer(wt, ct, st, 0, hb.HS_BF16, 0.08, logits=True, stats=True)
+    b16, l16, stats = hb.halftone_infer(wt, ct, st, 0, hb.HS_BF16, 0.055, logits=True, stats=True)
     b32, l32, b16 = b32.cpu().numpy(), l32.cpu().numpy(), b16.cpu().numpy()
     rng = np.random.default_rng(0)
     wd = w.astype(np.float64)
