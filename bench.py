@@ -100,6 +100,10 @@ def calibrate(hb, synth, torch, dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--calibrate", action="store_true")
+    ap.add_argument("--probe", choices=["infer", "copy"], default=None,
+                    help="a minimal run for hardware-counter passes: one inference call "
+                         "on the workload, or a plain 512 MiB device copy (the reference "
+                         "for scaling the memory-traffic counters)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -128,6 +132,14 @@ def main():
     if args.calibrate:
         calibrate(hb, synth, torch, dev)
         return
+    if args.probe == "copy":
+        a = torch.ones(128 << 20, dtype=torch.float32, device=dev)  # 512 MiB
+        bcopy = torch.empty_like(a)
+        for _ in range(3):
+            bcopy.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 3 x 512 MiB")
+        return
     B, H, W = 8, 1024, 1024
     seeds = list(range(11, 19))
     log("generating the 8 x 1024 x 1024 synthetic batch")
@@ -143,6 +155,12 @@ def main():
     def step():
         return hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_BF16, args.tau,
                                  workspace=ws)
+
+    if args.probe == "infer":
+        step()
+        torch.cuda.synchronize()
+        log("one inference call")
+        return
 
     for _ in range(args.warmup):
         step()

@@ -86,7 +86,8 @@ int margin(const hs_loss_params* p) {
 // ---------------------------------------------------------------- layouts --
 struct PolicyWs {
   void *packF, *packT, *act[5], *gA, *gB;
-  float *z, *c, *g6, *partials;
+  float *z, *c, *g6, *partials, *rtmp;
+  unsigned long long* counter;
 };
 PolicyWs carve_policy(Carve& cv, size_t N, int prec) {
   PolicyWs w;
@@ -99,6 +100,8 @@ PolicyWs carve_policy(Carve& cv, size_t N, int prec) {
   w.c = cv.take<float>(N * 4);
   w.g6 = cv.take<float>(N * 4);
   w.partials = cv.take<float>((size_t)WGRAD_BLOCKS * NPARAM * 4);
+  w.rtmp = cv.take<float>((size_t)REDUCE_GROUPS * NPARAM * 4);
+  w.counter = cv.take<unsigned long long>(64);
   return w;
 }
 
@@ -287,12 +290,15 @@ static size_t infer_ws(int B, int H, int W, int prec, InferWs* out, uint32_t** l
   Carve cv(base);
   const size_t N = (size_t)B * H * W;
   InferWs w;
-  if (prec == HS_BF16) {  // fused path: packed fragments and two recheck lists
+  if (prec == HS_BF16) {  // fused path: packed fragments, the segmented list,
+                          // its counts, and the dense FP32-stage list
     w.pack = cv.take<char>(fused_frag_bytes());
     w.a0 = cv.take<char>(split_frag_bytes());
-    w.a1 = nullptr;
-    uint32_t* l = cv.take<uint32_t>(2 * N * 4);
+    const size_t ne = fused_list_entries(B, H, W, num_cus());
+    w.a1 = cv.take<char>(ne * 4);                      // segmented list
+    uint32_t* l = cv.take<uint32_t>(N * 4);            // FP32-stage list
     if (list) *list = l;
+    cv.take<int>(2 * (size_t)num_cus() * 4 + 64);      // segment counts (tail of a1 area)
   } else {
     w = carve_infer(cv, N, prec);
     if (list) *list = nullptr;
@@ -338,18 +344,23 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
     // stage 2: split-BF16 receptive-field recompute, |x| < tau2 listed again
     // stage 3: FP32 receptive-field recompute
     const float tau2 = fminf(fmaxf(recheck_tau / 32.0f, 1e-3f), 1e-2f);
-    const size_t N = (size_t)B * H * W;
-    uint32_t* list2 = list + N;
+    uint32_t* list2 = list;
+    uint32_t* seglist = (uint32_t*)iw.a1;
+    int* seg_count = (int*)((char*)list + align256((size_t)B * H * W * 4));
     char* whi = (char*)iw.a0;
     char* wlo = whi + split_frag_bytes() / 2;
     HS_TRY(launch_fused_pack(weights, iw.pack, s));
     HS_TRY(launch_split_pack(weights, whi, wlo, s));
+    int nseg = 0;
+    long long seg_cap = 0;
     prof_begin(s);
     HS_TRY(launch_fused_infer(weights, contone, seeds, B, H, W, noise_kind, recheck_tau, bits,
-                              logits_or_null, list, cnt, iw.pack, num_cus(), s));
+                              logits_or_null, seglist, seg_count, &nseg, &seg_cap, iw.pack,
+                              num_cus(), s));
     prof_end(s);
-    HS_TRY(launch_recheck_split(weights, contone, seeds, H, W, noise_kind, list, cnt, whi, wlo,
-                                tau2, list2, cnt + 1, bits, logits_or_null, stats, num_cus(), s));
+    HS_TRY(launch_recheck_split(weights, contone, seeds, H, W, noise_kind, seglist, seg_count, nseg,
+                                seg_cap, whi, wlo, tau2, list2, cnt + 1, bits, logits_or_null,
+                                stats, num_cus(), s));
     HS_TRY(launch_recheck_fp32(weights, contone, seeds, H, W, noise_kind, list2, cnt + 1, bits,
                                logits_or_null, stats, 2, s));
     return HS_OK;
@@ -418,7 +429,7 @@ int halftone_policy_backward(const float* weights, const float* grad_probs, cons
   Carve cv(workspace);
   PolicyWs pw = carve_policy(cv, (size_t)B * H * W, precision);
   HS_TRY(run_backward(weights, grad_probs, probs, B, H, W, precision, pw, 0, s));
-  HS_TRY(launch_reduce_partials(pw.partials, WGRAD_BLOCKS, grad_weights, s));
+  HS_TRY(launch_reduce_partials(pw.partials, WGRAD_BLOCKS, pw.rtmp, grad_weights, s));
   return HS_OK;
 }
 
@@ -608,7 +619,7 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
       HS_TRY(launch_as(probs_g, Bg, Hg, Wg, lp.w_a / (float)npatch, 1, lw.patches, gradg, s));
     HS_TRY(run_backward(weights, gradg, nullptr, Bg, Hg, Wg, precision, pw, 1, s));
   }
-  HS_TRY(launch_reduce_partials(pw.partials, WGRAD_BLOCKS, grad, s));
+  HS_TRY(launch_reduce_partials(pw.partials, WGRAD_BLOCKS, pw.rtmp, grad, s));
   HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, lp.w_s,
                             (long)(H - 2 * m) * (W - 2 * m), loss_out, s));
   // Adam with the cosine learning rate of this step, bias corrections at t = step + 1
@@ -621,7 +632,7 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   if (grad_out_or_null)
     HS_TRY(hipMemcpyAsync(grad_out_or_null, grad, (size_t)NPARAM * 4, hipMemcpyDeviceToDevice, s));
   HS_TRY(launch_train_metrics(loss_out, B, grad, NPARAM, act, (size_t)B * H * W, (float)lr,
-                              metrics, s));
+                              metrics, pw.counter, s));
   HS_TRY(launch_adam(weights, adam_m, adam_v, grad, NPARAM, (float)lr, tp->beta1, tp->beta2,
                      tp->eps, (float)c1, (float)c2, s));
   if (actions_out_or_null)

@@ -369,6 +369,113 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(const T* __restrict__ a_in
 }
 
 // ---------------------------------------------------------------------------
+// Weight gradient of a 32->32 layer on the BF16 matrix cores (FP32
+// accumulation). K is the pixel dimension: a lane's 8 K-values are 8
+// consecutive pixels of one row. The output gradient is staged transposed,
+// gT[co][px]; the input tile is staged as three transposed copies shifted by
+// dx = 0, 1, 2 columns, aS[dx][ci][row][col] = a[y0-1+row][x0-1+col+dx][ci],
+// so the K-slice of every tap is one aligned 16-byte read. Tile = 2 x 64
+// pixels; wave w owns the (co tile, ci tile) = (w >> 1, w & 1) block of all
+// nine taps; the bias gradient is one more MFMA against a ones operand.
+// ---------------------------------------------------------------------------
+constexpr int WB_H = 2, WB_W = 64, WB_PX = WB_H * WB_W;
+constexpr int WB_GS = WB_PX + 8;           // gT channel stride (17 x 16 B: odd)
+constexpr int WB_RS = WB_W + 8;            // aS row stride
+constexpr int WB_CS = (WB_H + 2) * WB_RS + 8;  // aS channel stride (37 x 16 B: odd)
+
+__global__ __launch_bounds__(256) void wgrad32_bf16_kernel(const __bf16* __restrict__ a_in,
+                                                           const __bf16* __restrict__ g_out,
+                                                           int B, int H, int W, int layer,
+                                                           float* __restrict__ partials,
+                                                           int accumulate) {
+  __shared__ __attribute__((aligned(16))) __bf16 gT[32 * WB_GS];
+  __shared__ __attribute__((aligned(16))) __bf16 aS[3 * 32 * WB_CS];
+  const int tiles_x = (W + WB_W - 1) / WB_W, tiles_y = (H + WB_H - 1) / WB_H;
+  const int ntiles = B * tiles_x * tiles_y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  const int mt = wave >> 1, nt = wave & 1;
+  f32x4_t acc[9], accb = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  bf16x8_t ones;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
+    const int y0 = (rem / tiles_x) * WB_H, x0 = (rem % tiles_x) * WB_W;
+    const size_t img = (size_t)b * H * W;
+    __syncthreads();
+    // one operation = 4 consecutive pixels x 8 channels -> 8 stores of 4 values
+    for (int op = threadIdx.x; op < 3 * (WB_H + 2) * (WB_W / 4) * 4 + WB_H * (WB_W / 4) * 4;
+         op += 256) {
+      const bool is_g = op >= 3 * (WB_H + 2) * (WB_W / 4) * 4;
+      int q = is_g ? op - 3 * (WB_H + 2) * (WB_W / 4) * 4 : op;
+      const int c8 = q & 3;
+      q >>= 2;
+      const int j4 = (q % (WB_W / 4)) * 4;
+      q /= WB_W / 4;
+      int row, dx = 0;
+      if (is_g) {
+        row = q;  // 0..WB_H-1
+      } else {
+        row = q % (WB_H + 2);
+        dx = q / (WB_H + 2);
+      }
+      const int gy = is_g ? y0 + row : y0 - 1 + row;
+      const __bf16* src = is_g ? g_out : a_in;
+      bf16x8_t v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int gx = is_g ? x0 + j4 + u : x0 - 1 + j4 + u + dx;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+          v[u] = *(const bf16x8_t*)(src + (img + (size_t)gy * W + gx) * 32 + 8 * c8);
+        else
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[u][e] = (__bf16)0.0f;
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        bf16x4_t w4 = bf16x4_t{v[0][e], v[1][e], v[2][e], v[3][e]};
+        __bf16* dst = is_g ? gT + (8 * c8 + e) * WB_GS + row * WB_W + j4
+                           : aS + (dx * 32 + 8 * c8 + e) * WB_CS + row * WB_RS + j4;
+        *(bf16x4_t*)dst = w4;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kc = 0; kc < WB_PX / 32; ++kc) {
+      const int py = kc / (WB_W / 32), pc = (kc % (WB_W / 32)) * 32 + 8 * g;
+      const bf16x8_t af = *(const bf16x8_t*)(gT + (16 * mt + r) * WB_GS + py * WB_W + pc);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3, dx = t - (t / 3) * 3;
+        const bf16x8_t bfr =
+            *(const bf16x8_t*)(aS + (dx * 32 + 16 * nt + r) * WB_CS + (py + dy) * WB_RS + pc);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc[t], 0, 0, 0);
+      }
+      if (nt == 0) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, ones, accb, 0, 0, 0);
+    }
+  }
+  // acc[t][i] = dW[co = 16 mt + 4 g + i][ci = 16 nt + r][t]
+  float* row = partials + (size_t)blockIdx.x * hs::NPARAM + hs_wk(layer);
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = 16 * mt + 4 * g + i, ci = 16 * nt + r;
+      float* d = row + (co * 32 + ci) * 9 + t;
+      *d = accumulate ? *d + acc[t][i] : acc[t][i];
+    }
+  if (nt == 0 && r == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float* d = row + 32 * 32 * 9 + 16 * mt + 4 * g + i;
+      *d = accumulate ? *d + accb[i] : accb[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient of the first layer (2 -> 32) on the vector ALUs.
 // Tile = 16 x 16 pixels; thread i < 608 owns parameter i of layer 1.
 // ---------------------------------------------------------------------------
@@ -484,12 +591,22 @@ __global__ __launch_bounds__(320) void wgrad_last_kernel(const T* __restrict__ a
   }
 }
 
+// Two-level fixed-order sum of the partial rows: group gi sums rows
+// gi, gi + G, gi + 2G, ... into tmp[gi]; then the G group sums in order.
 __global__ void reduce_partials_kernel(const float* __restrict__ partials, int rows,
-                                       float* __restrict__ grad) {
+                                       float* __restrict__ tmp) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x, gi = blockIdx.y;
+  if (p >= hs::NPARAM) return;
+  float s = 0.0f;
+  for (int r = gi; r < rows; r += hs::REDUCE_GROUPS) s += partials[(size_t)r * hs::NPARAM + p];
+  tmp[(size_t)gi * hs::NPARAM + p] = s;
+}
+
+__global__ void reduce_groups_kernel(const float* __restrict__ tmp, float* __restrict__ grad) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= hs::NPARAM) return;
   float s = 0.0f;
-  for (int r = 0; r < rows; ++r) s += partials[(size_t)r * hs::NPARAM + p];
+  for (int gi = 0; gi < hs::REDUCE_GROUPS; ++gi) s += tmp[(size_t)gi * hs::NPARAM + p];
   grad[p] = s;
 }
 
@@ -593,8 +710,8 @@ hipError_t launch_wgrad_first(const float* contone, const float* z, const void* 
 hipError_t launch_wgrad32(const void* a_in, const void* g_out, int layer, int B, int H, int W,
                           int precision, float* partials, int accumulate, hipStream_t s) {
   if (precision == HS_BF16)
-    wgrad32_kernel<__bf16><<<WGRAD_BLOCKS, 256, 0, s>>>((const __bf16*)a_in, (const __bf16*)g_out,
-                                                        B, H, W, layer, partials, accumulate);
+    wgrad32_bf16_kernel<<<WGRAD_BLOCKS, 256, 0, s>>>((const __bf16*)a_in, (const __bf16*)g_out, B,
+                                                     H, W, layer, partials, accumulate);
   else
     wgrad32_kernel<float><<<WGRAD_BLOCKS, 256, 0, s>>>((const float*)a_in, (const float*)g_out, B,
                                                        H, W, layer, partials, accumulate);
@@ -612,8 +729,11 @@ hipError_t launch_wgrad_last(const void* a5, const float* g6, int B, int H, int 
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_partials(const float* partials, int rows, float* grad, hipStream_t s) {
-  reduce_partials_kernel<<<(NPARAM + 255) / 256, 256, 0, s>>>(partials, rows, grad);
+hipError_t launch_reduce_partials(const float* partials, int rows, float* tmp, float* grad,
+                                  hipStream_t s) {
+  reduce_partials_kernel<<<dim3((NPARAM + 255) / 256, REDUCE_GROUPS), 256, 0, s>>>(partials, rows,
+                                                                                  tmp);
+  reduce_groups_kernel<<<(NPARAM + 255) / 256, 256, 0, s>>>(tmp, grad);
   return hipGetLastError();
 }
 

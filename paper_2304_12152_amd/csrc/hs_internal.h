@@ -54,11 +54,13 @@ hipError_t launch_conv_last(const void* in, const float* w, int B, int H, int W,
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 size_t fused_frag_bytes();
 hipError_t launch_fused_pack(const float* w, void* frags, hipStream_t s);
-// persistent fused BF16 inference; list/count may be null (no recheck list)
+// persistent fused BF16 inference; the recheck list is segmented (two
+// segments per workgroup, counts in seg_count; list may be null)
+size_t fused_list_entries(int B, int H, int W, int num_cus);
 hipError_t launch_fused_infer(const float* w, const float* contone, const uint64_t* seeds, int B,
                               int H, int W, int kind, float tau, uint8_t* bits, float* logits,
-                              uint32_t* list, int* count, const void* frags, int num_cus,
-                              hipStream_t s);
+                              uint32_t* list, int* seg_count, int* nseg, long long* seg_cap,
+                              const void* frags, int num_cus, hipStream_t s);
 hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,
                                int H, int W, int kind, const uint32_t* list, const int* count,
                                uint8_t* bits, float* logits, int32_t* stats, int count_slot,
@@ -66,7 +68,8 @@ hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint6
 size_t split_frag_bytes();
 hipError_t launch_split_pack(const float* w, void* whi, void* wlo, hipStream_t s);
 hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
-                                int H, int W, int kind, const uint32_t* list, const int* count,
+                                int H, int W, int kind, const uint32_t* seglist,
+                                const int* seg_count, int nseg, long long seg_cap,
                                 const void* whi, const void* wlo, float tau2, uint32_t* list2,
                                 int* count2, uint8_t* bits, float* logits, int32_t* stats,
                                 int num_cus, hipStream_t s);
@@ -82,7 +85,11 @@ hipError_t launch_wgrad32(const void* a_in, const void* g_out, int layer, int B,
                           int precision, float* partials, int accumulate, hipStream_t s);
 hipError_t launch_wgrad_last(const void* a5, const float* g6, int B, int H, int W, int precision,
                              float* partials, int accumulate, hipStream_t s);
-hipError_t launch_reduce_partials(const float* partials, int rows, float* grad, hipStream_t s);
+// sums `rows` rows of NPARAM partial sums in a fixed order; `tmp` holds
+// REDUCE_GROUPS * NPARAM floats
+constexpr int REDUCE_GROUPS = 16;
+hipError_t launch_reduce_partials(const float* partials, int rows, float* tmp, float* grad,
+                                  hipStream_t s);
 
 // loss.hip
 struct LossDev {  // the two normalised windows, passed to kernels by value
@@ -108,6 +115,6 @@ hipError_t launch_adam(float* w, float* m, float* v, const float* g, int n, floa
                        float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_train_metrics(const float* loss_out, int B, const float* grad, int n,
                                 const uint8_t* actions, size_t nact, float lr, float* metrics,
-                                hipStream_t s);
+                                unsigned long long* counter, hipStream_t s);
 
 }  // namespace hs

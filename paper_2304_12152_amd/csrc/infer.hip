@@ -147,32 +147,48 @@ hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint6
 //
 // A strip is FW = 128 computed columns, of which the central FS = 116 are
 // valid outputs (the 13 x 13 receptive field eats 6 columns on each side).
-// Every layer keeps a ring of three rows of its output in LDS (BF16, 32
-// channels, 64 B per pixel), so activations never leave the chip. Each step
-// advances every stage by one row: the input stage (contone + Philox noise),
-// conv layers 1..5, the per-tap partial sums T of layer 6 (one MFMA gives the
-// nine taps' 32-channel dot products of a pixel), and the output stage (the
-// nine-tap shift-add of T, the threshold and the recheck flag). A stage reads
-// rows written at earlier steps only (phase A), then all stages write their
-// new row (phase B); so consecutive stages lag by two rows (one for T).
+// Each step advances every stage by one row, with a single barrier per step:
+//   input stage   contone + Philox noise of one row -> input ring (4 slots)
+//   layer 1       three input rows -> one output row (MFMA, K = 9 taps x 2)
+//   layers 2..5   ONE new input row per step: its three tap rows dy = 0, 1, 2
+//                 feed three accumulator sets (output rows q+1, q, q-1), so
+//                 each set sees its three input rows on consecutive steps and
+//                 every input row is read from LDS once. The set finished in
+//                 a step is stored in the next one, so the store never waits
+//                 on the MFMA pipeline.
+//   layer 6       layer 5's finished row goes straight from registers into
+//                 one MFMA giving, per pixel, the nine taps' 32-channel dot
+//                 products T; the output stage slides the same way over T
+//                 rows, adds the bias, thresholds and flags near-ties.
+// A row is written into a slot that no stage reads in the same step, and
+// read in the next step, so the rings of layers 1..4 and T hold two rows.
 //
 // Work per step: eight waves; conv layer k (2..5) belongs to waves
 // 2(k-2), 2(k-2)+1, each owning four 16-pixel runs of the row and holding
-// its layer's weights in registers for the whole kernel. Layer 1 runs on
-// waves 0-1, the T stage on waves 6-7, the input stage on waves 2-3 and the
-// output stage on waves 4-5.
+// its layer's weights in registers for the whole kernel. Besides that,
+// waves 0-1 run layer 1, waves 2-3 the input stage, waves 4-5 the output
+// stage and waves 6-7 (layer 5) the layer-6 taps.
 //
 // Channel order in the rings: the MFMA result of lane (g, r) holds output
 // channels {4g..4g+3, 16+4g..16+4g+3} of pixel r; those eight channels are
 // stored as the lane's 16-byte chunk and read back as the same lane group's
-// K-slice by the next layer, whose weights are packed in that order.
+// K-slice by the next layer, whose weights are packed in that order. A ring
+// row is [column][chunk][16 B] with the chunk index XOR-ed by bits 1..2 of
+// the column, which makes the 16-byte reads and writes of a wave free of LDS
+// bank conflicts; runs of 16 columns are immediate offsets from one base.
 // ===========================================================================
 namespace {
 
-constexpr int FW = 128, FS = FW - 12, RWID = FW + 2, FNT = FW / 16;
-constexpr int LAG_OUT = 19;  // steps from input row Y0-6 to output row Y0
+constexpr int FW = 128, FS = FW - 12, RWID = FW + 2;
+constexpr int LAG_OUT = 22;  // steps from the first input row Y0-6 to output row Y0
 constexpr int FRAG_L1 = 0, FRAG_L32 = 128, FRAG_T = 128 + 4 * 9 * 2 * 64;
 constexpr int FRAG_TOTAL = FRAG_T + 64;
+constexpr int FUSED_NW = 2;  // waves per conv layer in the fused kernel
+constexpr int ROWE = RWID * 32;         // elements per ring row
+constexpr int RUNE = 16 * 32;           // elements per 16-column run
+
+// element offset of chunk g of column col in a ring row
+HS_DEV int ring_off(int col, int g) { return (col * 4 + (g ^ ((col >> 1) & 3))) * 8; }
 
 // channel held by slot e of lane group g in the ring order
 HS_DEV int ring_channel(int g, int e) { return e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4); }
@@ -182,10 +198,10 @@ __global__ void pack_fused_kernel(const float* __restrict__ w, __bf16* __restric
        i += gridDim.x * blockDim.x) {
     const int f = i >> 3, e = i & 7;
     float v = 0.0f;
-    if (f < FRAG_L32) {  // layer 1: slot j = 8g + e holds (tap j/2, channel j%2)
+    if (f < FRAG_L32) {  // layer 1: lane group g = kernel row dy, slot e = (dx = e/2, channel e%2)
       const int m = f >> 6, l = f & 63, g = l >> 4, r = l & 15;
-      const int j = 8 * g + e, co = 16 * m + r;
-      if (j < 18) v = w[HS_W1 + (co * 2 + (j & 1)) * 9 + (j >> 1)];
+      const int co = 16 * m + r;
+      if (g < 3 && e < 6) v = w[HS_W1 + (co * 2 + (e & 1)) * 9 + g * 3 + (e >> 1)];
     } else if (f < FRAG_T) {  // layers 2..5: [layer][tap][m][lane]
       const int q = f - FRAG_L32, l = q & 63, m = (q >> 6) & 1, t = (q >> 7) % 9,
                 layer = (q >> 7) / 9;
@@ -205,214 +221,297 @@ struct FusedArgs {
   const bf16x8_t* frags;
   const float* w;
   int B, H, W, kind, nstrip;
-  long long total_rows, rows_per_wg;
+  int total_rows, rows_per_wg;
   float tau;
   uint8_t* bits;
   float* logits;
-  uint32_t* list;
-  int* count;
+  uint32_t* list;     // per output wave a segment of seg_cap entries
+  int* seg_count;     // entries written per segment
+  long long seg_cap;
 };
 
-HS_DEV int slot3(int row) { return ((row % 3) + 3) % 3; }
+template <int V>
+struct StepIndex {
+  static constexpr int value = V;
+};
 
-__global__ __launch_bounds__(512, 1) void fused_infer_kernel(FusedArgs a) {
-  __shared__ __attribute__((aligned(16))) __bf16 ring[5 * 3 * RWID * 32];
-  __shared__ uint32_t inring[3 * RWID];
-  __shared__ __attribute__((aligned(16))) float tring[3 * RWID * 12];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
-  const int half = wave & 1, k = 2 + (wave >> 1);  // conv layer owned by this wave
-  for (int i = tid; i < 5 * 3 * RWID * 32 / 8; i += 512) ((uint4*)ring)[i] = make_uint4(0, 0, 0, 0);
-  for (int i = tid; i < 3 * RWID; i += 512) inring[i] = 0u;
-  for (int i = tid; i < 3 * RWID * 12; i += 512) tring[i] = 0.0f;
-  // weights of the owned layer (A operands) and its bias for this lane's channels
-  bf16x8_t wA[9][2];
+// two floats -> packed BF16 pair (round to nearest even), then ReLU on the
+// packed bits: a BF16 with its sign bit set is a negative int16, so a 16-bit
+// integer max with 0 is the ReLU (and equals ReLU before rounding)
+HS_DEV uint32_t relu_bf16x2(float lo, float hi) {
+  const f32x2_t v = {lo, hi};
+  const bf16x2_t h = __builtin_convertvector(v, bf16x2_t);
+  i16x2_t q;
+  __builtin_memcpy(&q, &h, 4);
+  q = __builtin_elementwise_max(q, (i16x2_t){0, 0});
+  uint32_t u;
+  __builtin_memcpy(&u, &q, 4);
+  return u;
+}
+
+// ReLU + BF16 of one finished 16-pixel run in the ring channel order; zero
+// where the pixel lies outside the image (the next layer's zero padding)
+HS_DEV bf16x8_t relu_bf16(const f32x4_t (&acc)[2], bool in) {
+  uint32_t u[4];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    u[2 * m] = in ? relu_bf16x2(acc[m][0], acc[m][1]) : 0u;
+    u[2 * m + 1] = in ? relu_bf16x2(acc[m][2], acc[m][3]) : 0u;
+  }
+  bf16x8_t v;
+  __builtin_memcpy(&v, u, 16);
+  return v;
+}
+
+// Workgroup barrier that orders LDS only. The waves of a workgroup never
+// read each other's global writes, so the per-step barrier need not wait for
+// the bits, logits and list stores (nor the contone prefetch) to complete.
+HS_DEV void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int NW>
+__global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a) {
+  constexpr int RPW = 8 / NW, NT = 64 * 4 * NW, HPW = 2 / NW;  // runs, threads, 64-px halves per wave
+  __shared__ __attribute__((aligned(16))) __bf16 ring[4 * 2 * ROWE];   // layers 1..4
+  // input rows as per-column records [(c, z) of columns j, j+1, j+2, 0],
+  // each (c, z) a BF16 pair: one record is a layer-1 operand row
+  __shared__ __attribute__((aligned(16))) uint32_t inring[4 * RWID * 4];
+  __shared__ __attribute__((aligned(16))) float tring[2 * RWID * 12];  // T, 12 floats per column
+  __shared__ bf16x8_t cfrag[3 * 64];  // layer-1 A operands (m = 0, 1), layer-6 tap matrix
+  __shared__ __attribute__((aligned(16))) float cbias[5 * 32];  // biases of layers 1..5
+  __shared__ float osum[3][FW];  // the output stage's running sums, per strip column
+  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, r = lane & 15;
+  // wave-uniform values are kept in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int part = wave % NW, role = wave / NW, k = 2 + role;  // conv layer owned by this wave
+  for (int i = tid; i < 4 * 2 * ROWE / 8; i += NT) ((uint4*)ring)[i] = make_uint4(0, 0, 0, 0);
+  for (int i = tid; i < 4 * RWID * 4; i += NT) inring[i] = 0u;
+  for (int i = tid; i < 2 * RWID * 12; i += NT) tring[i] = 0.0f;
+  for (int i = tid; i < 3 * FW; i += NT) osum[i / FW][i % FW] = 0.0f;
+  // weights of the owned layer stay in registers (A operands, [dy][dx][m]);
+  // the biases and the role operands (layer 1's two A operands, the layer-6
+  // tap matrix) are read from LDS where they are used
+  bf16x8_t wA[3][3][2];
 #pragma unroll
   for (int t = 0; t < 9; ++t)
 #pragma unroll
-    for (int m = 0; m < 2; ++m) wA[t][m] = a.frags[FRAG_L32 + (((k - 2) * 9 + t) * 2 + m) * 64 + lane];
-  float bk[2][4];
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) bk[m][i] = a.w[hs_bk(k) + 16 * m + 4 * g + i];
-  // role-specific operands share registers: waves 0-1 hold layer 1's two A
-  // operands and bias, waves 6-7 the layer-6 tap matrix
-  bf16x8_t wx[2];
-  float b1[2][4];
-  if (wave < 2) {
-    wx[0] = a.frags[FRAG_L1 + lane];
-    wx[1] = a.frags[FRAG_L1 + 64 + lane];
-#pragma unroll
     for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) b1[m][i] = a.w[HS_B1 + 16 * m + 4 * g + i];
-  } else {
-    wx[0] = a.frags[FRAG_T + lane];
-    wx[1] = wx[0];
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) b1[m][i] = 0.0f;
-  }
+      wA[t / 3][t % 3][m] = a.frags[FRAG_L32 + (((k - 2) * 9 + t) * 2 + m) * 64 + lane];
+  for (int i = tid; i < 3 * 64; i += NT)
+    cfrag[i] = a.frags[i < 128 ? FRAG_L1 + i : FRAG_T + (i - 128)];
+  for (int i = tid; i < 5 * 32; i += NT) cbias[i] = a.w[i < 32 ? HS_B1 + i : hs_bk(2 + (i - 32) / 32) + (i & 31)];
   const float b6 = a.w[HS_B6];
+  // this lane's element offset in a ring row: chunk g, first column of its
+  // runs (tap dx and run n are added as immediates)
+  const int col0 = 16 * RPW * part;  // first strip column of this wave's runs
+  // three accumulator sets of the owned layer, and the output stage's three
+  // running sums per 64-pixel half
+  f32x4_t S[3][RPW][2];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int n = 0; n < RPW; ++n) S[j][n][0] = S[j][n][1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  int nflag[HPW];
+#pragma unroll
+  for (int h = 0; h < HPW; ++h) nflag[h] = 0;
   __syncthreads();
 
-  const long long Lbeg = (long long)blockIdx.x * a.rows_per_wg;
-  const long long Lend = Lbeg + a.rows_per_wg < a.total_rows ? Lbeg + a.rows_per_wg : a.total_rows;
+  // strip rows [Lbeg, Lend) of the sequence (image, strip, row); the
+  // divisions are wave-uniform and kept scalar
+  const int Lbeg = blockIdx.x * a.rows_per_wg;
+  const int Lend = min(Lbeg + a.rows_per_wg, a.total_rows);
   const int H = a.H, W = a.W;
-  for (long long L = Lbeg; L < Lend;) {
-    const long long strip_id = L / H;
-    const int Y0 = (int)(L - strip_id * H);
-    const long long seg_end = (strip_id + 1) * H < Lend ? (strip_id + 1) * H : Lend;
-    const int Y1 = Y0 + (int)(seg_end - L);
-    const int b = (int)(strip_id / a.nstrip), s = (int)(strip_id % a.nstrip);
-    const int X = s * FS - 6;
+  for (int L = Lbeg; L < Lend;) {
+    const int strip_id = __builtin_amdgcn_readfirstlane(L / H);
+    const int Y0 = L - strip_id * H;
+    const int seg_end = min((strip_id + 1) * H, Lend);
+    const int Y1 = Y0 + (seg_end - L);
+    const int b = __builtin_amdgcn_readfirstlane(strip_id / a.nstrip);
+    const int X = (strip_id - b * a.nstrip) * FS - 6;
+    const bool cols_inside = X >= 0 && X + FW <= W;  // no column of the strip is padding
     const size_t img = (size_t)b * H * W;
     const uint64_t seed = a.seeds[b];
-    const int nsteps = (Y1 - Y0) + LAG_OUT;
-    for (int t = 0; t < nsteps; ++t) {
-      // ------------------------------------------------------------ phase A
-      const int rk = Y0 - 6 - 2 * k + t;  // row of the owned conv layer
-      f32x4_t acc[4][2];
-      const int rin = rk - 1;  // first input row of the owned layer
-      const __bf16* src = ring + (size_t)(k - 2) * 3 * RWID * 32;
+    const int A = Y0 - 6;  // input row of step 0
+    const int nsteps = ((Y1 - Y0) + LAG_OUT + 2) / 3 * 3;
+
+    auto step = [&](const int t, auto jc) {
+      constexpr int J = decltype(jc)::value;  // == t % 3
+      constexpr int M1 = (J + 2) % 3, M2 = (J + 1) % 3;
+      const int cur = t & 1, prev = cur ^ 1;
+      // per-lane offsets are rebuilt in every step from the lane number (a
+      // few VALU operations) instead of being held in registers across the
+      // loop; the volatile statement keeps the compiler from hoisting them
+      int ln;
+      asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+      const int lr = ln & 15, lg = ln >> 4;
+      // this lane's chunk of its first column written (tap centre) and read
+      const int woff = ring_off(col0 + lr + 1, lg);
+      // ---- the input waves issue their contone loads first and use them
+      // after their MFMAs, which hide the latency
+      float cin[HPW];
+      if (role == 1) {
+        const int ri = A + t;
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        acc[n][0] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-        acc[n][1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-      }
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy) {
-        const __bf16* rowp = src + (size_t)slot3(rin + dy) * RWID * 32;
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-#pragma unroll
-          for (int n = 0; n < 4; ++n) {
-            const int col = 16 * (4 * half + n) + r + dx;
-            const bf16x8_t bf = *(const bf16x8_t*)(rowp + col * 32 + hs_swz<__bf16>(col, g) * 8);
-            acc[n][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wA[dy * 3 + dx][0], bf, acc[n][0], 0, 0, 0);
-            acc[n][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wA[dy * 3 + dx][1], bf, acc[n][1], 0, 0, 0);
-          }
+        for (int h = 0; h < HPW; ++h) {
+          const int xin = X + 64 * (HPW * part + h) + ln;
+          cin[h] = 0.f;
+          if (xin >= 0 && xin < W && ri >= 0 && ri < H) cin[h] = a.contone[img + (size_t)ri * W + xin];
         }
       }
-      // extra duty of each wave pair
-      f32x4_t accx[4][2];  // layer 1 (waves 0-1) or the T stage (waves 6-7, [n][0])
-      float cval = 0.f, zval = 0.f;
-      const int r1 = Y0 - 8 + t, r0 = Y0 - 6 + t, r6 = Y0 - 17 + t, r7 = Y0 - 19 + t;
-      if (wave < 2) {  // layer 1 from the input ring
+      // ---- output stage (waves 2NW..3NW-1), first in the step so that its
+      // global stores have drained before anything in a later step waits on
+      // the vector memory counter: T row q = A+t-15 finishes output row q-1
+      if (role == 2) {
+        const int y = A + t - 16;
+        const bool row_out = y >= Y0 && y < Y1;
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          const int c0 = 16 * (4 * half + n) + r;  // column of tap dx = 0
-          uint32_t u[4] = {0u, 0u, 0u, 0u};
+        for (int h = 0; h < HPW; ++h) {
+          const int Lx = 64 * (HPW * part + h) + ln, x = X + Lx;
+          const float* trow = tring + (size_t)prev * RWID * 12 + Lx * 12;
+          float sdy[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int tap = 4 * g + e;
-            if (tap < 9) {
-              const int dy = tap / 3, dx = tap - 3 * (tap / 3);
-              u[e] = inring[slot3(r1 - 1 + dy) * RWID + c0 + dx];
+          for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) sdy[dy] += trow[dx * 12 + dy * 3 + dx];
+          const float xl = osum[M2][Lx] + sdy[2] + b6;
+          osum[M1][Lx] += sdy[1];
+          osum[J][Lx] = sdy[0];
+          if (row_out) {
+            const bool valid = Lx >= 6 && Lx < 6 + FS && x < W;
+            bool flag = false;
+            size_t o = 0;
+            if (valid) {
+              o = img + (size_t)y * W + x;
+              a.bits[o] = xl >= 0.0f ? 1 : 0;
+              if (a.logits) a.logits[o] = xl;
+              flag = a.list && fabsf(xl) < a.tau;
+            }
+            const uint64_t mask = __ballot(flag);
+            if (mask) {
+              if (flag) {
+                // flagged lanes below this one
+                const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                const long long seg = 2LL * blockIdx.x + HPW * part + h;
+                a.list[seg * a.seg_cap + nflag[h] + below] = (uint32_t)o;
+              }
+              nflag[h] += __popcll(mask);
             }
           }
-          bf16x8_t bf;
-          __builtin_memcpy(&bf, u, 16);
-          accx[n][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wx[0], bf, f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-          accx[n][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wx[1], bf, f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        }
-      } else if (wave < 4) {  // input stage: contone and noise of row r0
-        const int Lx = (wave - 2) * 64 + lane, x = X + Lx;
-        if (r0 >= 0 && r0 < H && x >= 0 && x < W) {
-          const uint64_t ap = (uint64_t)r0 * W + x;
-          cval = a.contone[img + ap];
-          zval = hs_noise(seed, ap, 0u, a.kind);
-        }
-      } else if (wave < 6) {  // output stage: row r7
-        const int Lx = (wave - 4) * 64 + lane, x = X + Lx;
-        const bool valid = Lx >= 6 && Lx < 6 + FS && x < W && r7 >= Y0 && r7 < Y1;
-        bool flag = false;
-        size_t o = 0;
-        if (valid) {
-          float xl = b6;
-#pragma unroll
-          for (int dy = 0; dy < 3; ++dy) {
-            const float* trow = tring + (size_t)slot3(r7 - 1 + dy) * RWID * 12;
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) xl += trow[(Lx + dx) * 12 + dy * 3 + dx];
-          }
-          o = img + (size_t)r7 * W + x;
-          a.bits[o] = xl >= 0.0f ? 1 : 0;
-          if (a.logits) a.logits[o] = xl;
-          flag = a.list && fabsf(xl) < a.tau;
-        }
-        const uint64_t mask = __ballot(flag);
-        if (mask) {
-          const int cnt = __popcll(mask);
-          int base = 0;
-          const int leader = __ffsll((unsigned long long)mask) - 1;
-          if (lane == leader) base = atomicAdd(a.count, cnt);
-          base = __shfl(base, leader, 64);
-          if (flag) {
-            const uint64_t lower = lane ? (mask & ((~0ull) >> (64 - lane))) : 0ull;
-            a.list[base + __popcll(lower)] = (uint32_t)o;
-          }
-        }
-      } else {  // T stage: nine taps of layer 6 on row r6 of layer 5
-        const __bf16* rowp = ring + ((size_t)4 * 3 + slot3(r6)) * RWID * 32;
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          const int col = 16 * (4 * half + n) + r + 1;
-          const bf16x8_t bf = *(const bf16x8_t*)(rowp + col * 32 + hs_swz<__bf16>(col, g) * 8);
-          accx[n][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wx[0], bf, f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
         }
       }
-      __syncthreads();
-      // ------------------------------------------------------------ phase B
+      // ---- the set finished in the previous step (row rs) leaves the registers
+      if (k < 5) {
+        const int rs = A + t + 1 - 3 * k;
+        const bool row_in = rs >= 0 && rs < H;
+        __bf16* dst = ring + ((size_t)(k - 1) * 2 + cur) * ROWE + woff;
+#pragma unroll
+        for (int n = 0; n < RPW; ++n) {
+          const int x = X + col0 + 16 * n + lr;
+          const bool in = row_in && (cols_inside || (x >= 0 && x < W));
+          *(bf16x8_t*)(dst + n * RUNE) = relu_bf16(S[J][n], in);
+        }
+      } else {  // layer 5: the nine layer-6 taps of row rs into the T ring
+        const int rs = A + t - 14;
+        const bool row_in = rs >= 0 && rs < H;
+        float* trow = tring + (size_t)cur * RWID * 12;
+        const bf16x8_t w6 = cfrag[128 + ln];
+#pragma unroll
+        for (int n = 0; n < RPW; ++n) {
+          const int c = col0 + 16 * n + lr, x = X + c;
+          const bool in = row_in && (cols_inside || (x >= 0 && x < W));
+          const f32x4_t tv = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              w6, relu_bf16(S[J][n], in), f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+          if (lg < 3) *(f32x4_t*)(trow + (c + 1) * 12 + 4 * lg) = tv;
+        }
+      }
       {
-        __bf16* dst = ring + ((size_t)(k - 1) * 3 + slot3(rk)) * RWID * 32;
-        const bool row_in = rk >= 0 && rk < H;
+        const f32x4_t bk0 = *(const f32x4_t*)(cbias + 32 * (k - 1) + 4 * lg);
+        const f32x4_t bk1 = *(const f32x4_t*)(cbias + 32 * (k - 1) + 16 + 4 * lg);
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          const int col = 16 * (4 * half + n) + r + 1, x = X + col - 1;
-          const bool in = row_in && x >= 0 && x < W;
-          bf16x8_t v;
-#pragma unroll
-          for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              v[4 * m + i] = (__bf16)(in ? fmaxf(acc[n][m][i] + bk[m][i], 0.0f) : 0.0f);
-          *(bf16x8_t*)(dst + col * 32 + hs_swz<__bf16>(col, g) * 8) = v;
+        for (int n = 0; n < RPW; ++n) {
+          S[J][n][0] = bk0;
+          S[J][n][1] = bk1;
         }
       }
-      if (wave < 2) {
-        __bf16* dst = ring + (size_t)slot3(r1) * RWID * 32;
+      // ---- one input row q (written by layer k-1 in the previous step)
+      const __bf16* src = ring + ((size_t)(k - 2) * 2 + prev) * ROWE;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const __bf16* srcd = src + ring_off(col0 + lr + dx, lg);
+#pragma unroll
+        for (int n = 0; n < RPW; ++n) {
+          const bf16x8_t bf = *(const bf16x8_t*)(srcd + n * RUNE);
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            S[J][n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wA[0][dx][m], bf, S[J][n][m], 0, 0, 0);
+            S[M1][n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wA[1][dx][m], bf, S[M1][n][m], 0, 0, 0);
+            S[M2][n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wA[2][dx][m], bf, S[M2][n][m], 0, 0, 0);
+          }
+        }
+      }
+      // ---- layer 1 (waves 0..NW-1), after their MFMAs: the wave sharing the
+      // SIMD runs the output stage before its own, so the two stages overlap
+      // the other wave's matrix-core work. Output row A+t-2 from input rows
+      // A+t-3 .. A+t-1
+      if (role == 0) {
+        const int r1 = A + t - 2;
         const bool row_in = r1 >= 0 && r1 < H;
+        // lane group g reads kernel row dy = g (group 3 meets zero weights)
+        const int dyl = lg < 3 ? lg : 2;
+        const uint4* rec = (const uint4*)inring + ((t + 1 + dyl) & 3) * RWID + col0 + lr;
+        __bf16* dst = ring + (size_t)cur * ROWE + woff;
+        const bf16x8_t w10 = cfrag[ln], w11 = cfrag[64 + ln];
+        const f32x4_t b10 = *(const f32x4_t*)(cbias + 4 * lg), b11 = *(const f32x4_t*)(cbias + 16 + 4 * lg);
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          const int col = 16 * (4 * half + n) + r + 1, x = X + col - 1;
-          const bool in = row_in && x >= 0 && x < W;
-          bf16x8_t v;
-#pragma unroll
-          for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              v[4 * m + i] = (__bf16)(in ? fmaxf(accx[n][m][i] + b1[m][i], 0.0f) : 0.0f);
-          *(bf16x8_t*)(dst + col * 32 + hs_swz<__bf16>(col, g) * 8) = v;
-        }
-      } else if (wave < 4) {
-        const int Lx = (wave - 2) * 64 + lane;
-        const __bf16 cz[2] = {(__bf16)cval, (__bf16)zval};
-        uint32_t u;
-        __builtin_memcpy(&u, cz, 4);
-        inring[slot3(r0) * RWID + Lx + 1] = u;
-      } else if (wave >= 6) {
-        float* trow = tring + (size_t)slot3(r6) * RWID * 12;
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          const int col = 16 * (4 * half + n) + r + 1;
-          if (g < 3) *(f32x4_t*)(trow + col * 12 + 4 * g) = accx[n][0];
+        for (int n = 0; n < RPW; ++n) {
+          const int c0 = col0 + 16 * n + lr;  // column of tap dx = 0
+          const uint4 u = rec[16 * n];
+          bf16x8_t bf;
+          __builtin_memcpy(&bf, &u, 16);
+          f32x4_t l1[2];
+          l1[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w10, bf, b10, 0, 0, 0);
+          l1[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w11, bf, b11, 0, 0, 0);
+          const int x = X + c0;
+          *(bf16x8_t*)(dst + n * RUNE) = relu_bf16(l1, row_in && x >= 0 && x < W);
         }
       }
-      __syncthreads();
+      // ---- input stage (waves NW..2NW-1): row A+t into slot t % 4
+      if (role == 1) {
+        const int ri = A + t;
+#pragma unroll
+        for (int h = 0; h < HPW; ++h) {
+          const int Lx = 64 * (HPW * part + h) + ln, xin = X + Lx;
+          const bool xin_ok = xin >= 0 && xin < W;
+          const float cval = cin[h];
+          float zval = 0.f;
+          if (xin_ok && ri >= 0 && ri < H) zval = hs_noise(seed, (uint64_t)ri * W + xin, 0u, a.kind);
+          const bf16x2_t cz = __builtin_convertvector((f32x2_t){cval, zval}, bf16x2_t);
+          uint32_t u;
+          __builtin_memcpy(&u, &cz, 4);
+          // column j = Lx + 1 is element e of the record of column j - e
+          uint32_t* rrow = inring + (t & 3) * RWID * 4;
+          rrow[(Lx + 1) * 4] = u;
+          rrow[Lx * 4 + 1] = u;
+          if (Lx >= 1) rrow[(Lx - 1) * 4 + 2] = u;
+        }
+      }
+      lds_barrier();
+    };
+    for (int t = 0; t < nsteps; t += 3) {
+      step(t, StepIndex<0>{});
+      step(t + 1, StepIndex<1>{});
+      step(t + 2, StepIndex<2>{});
     }
     L = seg_end;
+  }
+  // recheck list: the output stage's 64-pixel halves each own a segment
+  if (role == 2 && lane == 0 && a.seg_count) {
+#pragma unroll
+    for (int h = 0; h < HPW; ++h) a.seg_count[2 * blockIdx.x + HPW * part + h] = nflag[h];
   }
 }
 
@@ -427,10 +526,29 @@ hipError_t launch_fused_pack(const float* w, void* frags, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Geometry of the persistent launch: workgroups and strip-rows per workgroup.
+void fused_geometry(int B, int H, int W, int num_cus, int* grid, long long* rows_per_wg) {
+  const int nstrip = (W + FS - 1) / FS;
+  const long long total = (long long)B * nstrip * H;
+  long long per = (total + num_cus - 1) / num_cus;
+  if (per < 32) per = 32;
+  *rows_per_wg = per;
+  *grid = (int)((total + per - 1) / per);
+}
+
+// Entries of the segmented recheck list: two segments per workgroup, each
+// able to hold every pixel its wave writes.
+size_t fused_list_entries(int B, int H, int W, int num_cus) {
+  int grid;
+  long long per;
+  fused_geometry(B, H, W, num_cus, &grid, &per);
+  return (size_t)grid * 2 * (size_t)per * 64;
+}
+
 hipError_t launch_fused_infer(const float* w, const float* contone, const uint64_t* seeds, int B,
                               int H, int W, int kind, float tau, uint8_t* bits, float* logits,
-                              uint32_t* list, int* count, const void* frags, int num_cus,
-                              hipStream_t s) {
+                              uint32_t* list, int* seg_count, int* nseg, long long* seg_cap,
+                              const void* frags, int num_cus, hipStream_t s) {
   FusedArgs a;
   a.contone = contone;
   a.seeds = seeds;
@@ -441,17 +559,21 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
   a.W = W;
   a.kind = kind;
   a.nstrip = (W + FS - 1) / FS;
-  a.total_rows = (long long)B * a.nstrip * H;
-  long long per = (a.total_rows + num_cus - 1) / num_cus;
-  if (per < 32) per = 32;
-  a.rows_per_wg = per;
+  // nstrip <= W, so B * nstrip * H <= B * H * W < 2^31 (checked by the caller)
+  a.total_rows = (int)((long long)B * a.nstrip * H);
+  int grid;
+  long long per;
+  fused_geometry(B, H, W, num_cus, &grid, &per);
+  a.rows_per_wg = (int)per;
   a.tau = tau;
   a.bits = bits;
   a.logits = logits;
   a.list = list;
-  a.count = count;
-  const int grid = (int)((a.total_rows + per - 1) / per);
-  fused_infer_kernel<<<grid, 512, 0, s>>>(a);
+  a.seg_count = seg_count;
+  a.seg_cap = per * 64;
+  *nseg = 2 * grid;
+  *seg_cap = a.seg_cap;
+  fused_infer_kernel<FUSED_NW><<<grid, 64 * 4 * FUSED_NW, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -473,6 +595,7 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
 namespace {
 
 constexpr int CB = 4;                 // cones per block
+constexpr int SPLIT_MAXSEG = 1024;    // list segments the recheck accepts
 constexpr int CREC = 128;             // bytes per staged pixel: 4 groups x (hi, lo) x 16 B
 constexpr int CBUF_A = 121, CBUF_B = 81;
 
@@ -493,10 +616,11 @@ __global__ void pack_split_kernel(const float* __restrict__ w, __bf16* __restric
 
 HS_DEV int crec_slot(int p, int c) { return c ^ (p & 7); }
 
-__global__ __launch_bounds__(256) void recheck_split_kernel(
+__global__ __launch_bounds__(512) void recheck_split_kernel(
     const float* __restrict__ w, const float* __restrict__ contone,
-    const uint64_t* __restrict__ seeds, int H, int W, int kind, const uint32_t* __restrict__ list,
-    const int* __restrict__ count, const bf16x8_t* __restrict__ whi,
+    const uint64_t* __restrict__ seeds, int H, int W, int kind, const uint32_t* __restrict__ seglist,
+    const int* __restrict__ seg_count, int nseg, long long seg_cap,
+    const bf16x8_t* __restrict__ whi,
     const bf16x8_t* __restrict__ wlo, float tau2, uint32_t* __restrict__ list2,
     int* __restrict__ count2, uint8_t* __restrict__ bits, float* __restrict__ logits,
     int32_t* __restrict__ stats) {
@@ -506,18 +630,57 @@ __global__ __launch_bounds__(256) void recheck_split_kernel(
   __shared__ float s0[CB][169 * 2];
   __shared__ float sw1[32 * 2 * 9 + 32];
   __shared__ float l5f[CB][9 * 32];
+  __shared__ int spre[SPLIT_MAXSEG + 1];  // exclusive prefix of the segment counts
+  __shared__ uint32_t list[CB];           // the batch's pixels
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
-  const int n = *count;
-  for (int i = tid; i < 608; i += 256) sw1[i] = w[HS_W1 + i];
-  for (int base = blockIdx.x * CB; base < n; base += gridDim.x * CB) {
-    const int ncone = n - base < CB ? n - base : CB;
+  for (int i = tid; i < 608; i += 512) sw1[i] = w[HS_W1 + i];
+  // the segments are concatenated into one sequence dealt in CB-cone
+  // batches to the blocks; wave 0 scans the counts (per lane a chunk of
+  // consecutive segments, then a wave-wide scan of the chunk sums)
+  if (wave == 0) {
+    constexpr int PER = (SPLIT_MAXSEG + 63) / 64;
+    int cs = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int q = lane * PER + j;
+      cs += q < nseg ? seg_count[q] : 0;
+    }
+    int incl = cs;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    int run = incl - cs;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int q = lane * PER + j;
+      if (q <= nseg) spre[q] = run;
+      run += q < nseg ? seg_count[q] : 0;
+    }
+  }
+  __syncthreads();
+  const int total = spre[nseg];
+  for (int base = blockIdx.x * CB; base < total; base += gridDim.x * CB) {
+    const int ncone = total - base < CB ? total - base : CB;
+    __syncthreads();
+    if (tid < ncone) {  // segment of entry base + tid: the last with spre <= entry
+      const int e = base + tid;
+      int lo = 0, hi = nseg - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (spre[mid] <= e) lo = mid;
+        else hi = mid - 1;
+      }
+      list[tid] = seglist[(size_t)lo * seg_cap + (e - spre[lo])];
+    }
     __syncthreads();
     // stage the 13 x 13 state (c, z) of each cone, zero outside the image
-    for (int i = tid; i < CB * 169; i += 256) {
+    for (int i = tid; i < CB * 169; i += 512) {
       const int cidx = i / 169, q = i - cidx * 169;
       float cv = 0.f, zv = 0.f;
       if (cidx < ncone) {
-        const uint32_t o = list[base + cidx];
+        const uint32_t o = list[cidx];
         const int b = (int)(o / ((uint32_t)H * W));
         const int rem = (int)(o - (uint32_t)b * H * W), y = rem / W, x = rem - (rem / W) * W;
         const int gy = y - 6 + q / 13, gx = x - 6 + q % 13;
@@ -533,10 +696,10 @@ __global__ __launch_bounds__(256) void recheck_split_kernel(
     __syncthreads();
     // layer 1 in FP32 on the 11 x 11 windows; outputs stored split, in the
     // ring channel order (chunk g holds channels 4g..4g+3, 16+4g..16+4g+3)
-    for (int i = tid; i < CB * 121 * 4; i += 256) {
+    for (int i = tid; i < CB * 121 * 4; i += 512) {
       const int cidx = i / 484, rem = i - cidx * 484, p = rem >> 2, cg = rem & 3;
       const int py = p / 11, px = p - (p / 11) * 11;
-      const uint32_t o = list[base + (cidx < ncone ? cidx : 0)];
+      const uint32_t o = list[cidx < ncone ? cidx : 0];
       const int b = (int)(o / ((uint32_t)H * W));
       const int rr = (int)(o - (uint32_t)b * H * W), y = rr / W, x = rr - (rr / W) * W;
       const int gy = y - 5 + py, gx = x - 5 + px;
@@ -569,7 +732,7 @@ __global__ __launch_bounds__(256) void recheck_split_kernel(
       const int e_out = 13 - 2 * k, e_in = e_out + 2, npos = e_out * e_out;
       const int runs = (npos + 15) / 16;
       __syncthreads();
-      for (int i = tid; i < 9 * 2 * 64; i += 256) {
+      for (int i = tid; i < 9 * 2 * 64; i += 512) {
         swh[i] = whi[(k - 2) * 9 * 2 * 64 + i];
         swl[i] = wlo[(k - 2) * 9 * 2 * 64 + i];
       }
@@ -580,29 +743,54 @@ __global__ __launch_bounds__(256) void recheck_split_kernel(
       for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int i = 0; i < 4; ++i) bk[m][i] = w[hs_bk(k) + 16 * m + 4 * g + i];
-      for (int job = wave; job < CB * runs; job += 4) {
-        const int cidx = job / runs, run = job - cidx * runs;
-        const char* src = from_a ? bufA[cidx] : bufB[cidx];
-        char* dst = from_a ? bufB[cidx] : bufA[cidx];
-        const int pos = run * 16 + r;  // this lane's output position
+      // jobs (cone, 16-position run) are dealt to the eight waves; the tap loop
+      // is outermost so each tap's weight fragments are read once per wave
+      constexpr int MAXJ = 3;  // layer 2: 4 cones x 6 runs over 8 waves
+      const int njob = CB * runs;
+      f32x4_t acc[MAXJ][2];
+      int jq[MAXJ];
+#pragma unroll
+      for (int j = 0; j < MAXJ; ++j) {
+        acc[j][0] = acc[j][1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        const int job = wave + 8 * j;
+        const int run = job < njob ? job % runs : 0;
+        const int pos = run * 16 + r;
         const int pi = pos < npos ? pos / e_out : 0, pj = pos < npos ? pos - pi * e_out : 0;
-        f32x4_t acc[2] = {f32x4_t{0.f, 0.f, 0.f, 0.f}, f32x4_t{0.f, 0.f, 0.f, 0.f}};
+        jq[j] = pi * e_in + pj;  // input position of tap (0, 0)
+      }
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-          const int q = (pi + t / 3) * e_in + pj + t % 3;
-          const char* rec = src + q * CREC;
-          const bf16x8_t bh = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g) * 16);
-          const bf16x8_t bl = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g + 1) * 16);
+      for (int t = 0; t < 9; ++t) {
+        const bf16x8_t ah0 = swh[(t * 2 + 0) * 64 + lane], al0 = swl[(t * 2 + 0) * 64 + lane];
+        const bf16x8_t ah1 = swh[(t * 2 + 1) * 64 + lane], al1 = swl[(t * 2 + 1) * 64 + lane];
 #pragma unroll
-          for (int m = 0; m < 2; ++m) {
-            const bf16x8_t ah = swh[(t * 2 + m) * 64 + lane], al = swl[(t * 2 + m) * 64 + lane];
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[m], 0, 0, 0);
+        for (int j = 0; j < MAXJ; ++j) {
+          const int job = wave + 8 * j;
+          if (job < njob) {
+            const int cidx = job / runs;
+            const char* src = from_a ? bufA[cidx] : bufB[cidx];
+            const int q = jq[j] + (t / 3) * e_in + t % 3;
+            const char* rec = src + q * CREC;
+            const bf16x8_t bh = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g) * 16);
+            const bf16x8_t bl = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g + 1) * 16);
+            acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, acc[j][0], 0, 0, 0);
+            acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, acc[j][0], 0, 0, 0);
+            acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, acc[j][0], 0, 0, 0);
+            acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, acc[j][1], 0, 0, 0);
+            acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, acc[j][1], 0, 0, 0);
+            acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, acc[j][1], 0, 0, 0);
           }
         }
+      }
+#pragma unroll
+      for (int j = 0; j < MAXJ; ++j) {
+        const int job = wave + 8 * j;
+        if (job >= njob) continue;
+        const int cidx = job / runs, run = job - cidx * runs;
+        char* dst = from_a ? bufB[cidx] : bufA[cidx];
+        const int pos = run * 16 + r;
+        const int pi = pos < npos ? pos / e_out : 0, pj = pos < npos ? pos - pi * e_out : 0;
         if (pos < npos && cidx < ncone) {
-          const uint32_t o = list[base + cidx];
+          const uint32_t o = list[cidx];
           const int b = (int)(o / ((uint32_t)H * W));
           const int rr = (int)(o - (uint32_t)b * H * W), y = rr / W, x = rr - (rr / W) * W;
           const int gy = y - (6 - k) + pi, gx = x - (6 - k) + pj;
@@ -611,7 +799,7 @@ __global__ __launch_bounds__(256) void recheck_split_kernel(
 #pragma unroll
           for (int m = 0; m < 2; ++m)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) v[m][i] = in ? fmaxf(acc[m][i] + bk[m][i], 0.f) : 0.f;
+            for (int i = 0; i < 4; ++i) v[m][i] = in ? fmaxf(acc[j][m][i] + bk[m][i], 0.f) : 0.f;
           if (k == 5) {  // keep layer 5 in FP32 for the head
 #pragma unroll
             for (int m = 0; m < 2; ++m)
@@ -644,7 +832,7 @@ __global__ __launch_bounds__(256) void recheck_split_kernel(
       }
       part = hs_wave_sum(part);
       if (lane == 0) {
-        const uint32_t o = list[base + wave];
+        const uint32_t o = list[wave];
         const float xl = part + w[HS_B6];
         if (fabsf(xl) >= tau2) {
           const uint8_t nb = xl >= 0.f ? 1 : 0;
@@ -657,7 +845,7 @@ __global__ __launch_bounds__(256) void recheck_split_kernel(
       }
     }
   }
-  if (blockIdx.x == 0 && tid == 0) stats[0] = n;
+  if (blockIdx.x == 0 && tid == 0) stats[0] = total;
 }
 
 }  // namespace
@@ -674,11 +862,14 @@ hipError_t launch_split_pack(const float* w, void* whi, void* wlo, hipStream_t s
 }
 
 hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
-                                int H, int W, int kind, const uint32_t* list, const int* count,
+                                int H, int W, int kind, const uint32_t* seglist,
+                                const int* seg_count, int nseg, long long seg_cap,
                                 const void* whi, const void* wlo, float tau2, uint32_t* list2,
                                 int* count2, uint8_t* bits, float* logits, int32_t* stats,
                                 int num_cus, hipStream_t s) {
-  recheck_split_kernel<<<num_cus, 256, 0, s>>>(w, contone, seeds, H, W, kind, list, count,
+  if (nseg < 1 || nseg > SPLIT_MAXSEG) return hipErrorInvalidValue;
+  recheck_split_kernel<<<num_cus, 512, 0, s>>>(w, contone, seeds, H, W, kind, seglist, seg_count,
+                                               nseg, seg_cap,
                                                (const bf16x8_t*)whi, (const bf16x8_t*)wlo, tau2,
                                                list2, count2, bits, logits, stats);
   return hipGetLastError();

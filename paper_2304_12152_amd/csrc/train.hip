@@ -22,33 +22,41 @@ __global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float*
   w[i] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// metrics = {mean MSE, mean CSSIM, mean R, L_AS, lr, |grad|_2, fill, 0}
-__global__ __launch_bounds__(256) void metrics_kernel(const float* __restrict__ loss_out, int B,
-                                                      const float* __restrict__ grad, int n,
-                                                      const uint8_t* __restrict__ act,
-                                                      size_t nact, float lr,
-                                                      float* __restrict__ metrics) {
-  __shared__ float red[4];
-  __shared__ unsigned long long cnt[4];
-  float s = 0.0f;
-  for (int i = threadIdx.x; i < n; i += 256) s = fmaf(grad[i], grad[i], s);
-  // actions are 0/1 bytes: the byte sum of a 32-bit word is (v * 0x01010101) >> 24
+// Number of white actions (0/1 bytes). Each block sums a slice with 16-byte
+// loads (the byte sum of a 32-bit word v of 0/1 bytes is (v * 0x01010101) >> 24)
+// and adds it to a 64-bit counter; integer sums are order-independent.
+__global__ __launch_bounds__(256) void count_ones_kernel(const uint8_t* __restrict__ act,
+                                                         size_t nact,
+                                                         unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long part[4];
   unsigned long long c = 0;
   const size_t nvec = nact / 16;
   const uint4* av = (const uint4*)act;
-  for (size_t i = threadIdx.x; i < nvec; i += 256) {
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < nvec; i += (size_t)gridDim.x * 256) {
     const uint4 v = av[i];
     c += ((v.x * 0x01010101u) >> 24) + ((v.y * 0x01010101u) >> 24) +
          ((v.z * 0x01010101u) >> 24) + ((v.w * 0x01010101u) >> 24);
   }
-  for (size_t i = nvec * 16 + threadIdx.x; i < nact; i += 256) c += act[i];
-  s = hs_wave_sum(s);
+  if (blockIdx.x == 0)
+    for (size_t i = nvec * 16 + threadIdx.x; i < nact; i += 256) c += act[i];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-  if ((threadIdx.x & 63) == 0) {
-    red[threadIdx.x >> 6] = s;
-    cnt[threadIdx.x >> 6] = c;
-  }
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
+// metrics = {mean MSE, mean CSSIM, mean R, L_AS, lr, |grad|_2, fill, 0}
+__global__ __launch_bounds__(256) void metrics_kernel(const float* __restrict__ loss_out, int B,
+                                                      const float* __restrict__ grad, int n,
+                                                      const unsigned long long* __restrict__ ones,
+                                                      size_t nact, float lr,
+                                                      float* __restrict__ metrics) {
+  __shared__ float red[4];
+  float s = 0.0f;
+  for (int i = threadIdx.x; i < n; i += 256) s = fmaf(grad[i], grad[i], s);
+  s = hs_wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x != 0) return;
   float mse = 0.f, cs = 0.f, r = 0.f;
@@ -63,9 +71,11 @@ __global__ __launch_bounds__(256) void metrics_kernel(const float* __restrict__ 
   metrics[3] = loss_out[3 * B];
   metrics[4] = lr;
   metrics[5] = sqrtf(((red[0] + red[1]) + red[2]) + red[3]);
-  metrics[6] = (float)((double)(((cnt[0] + cnt[1]) + cnt[2]) + cnt[3]) / (double)nact);
+  metrics[6] = (float)((double)*ones / (double)nact);
   metrics[7] = 0.0f;
 }
+
+__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
 
 }  // namespace
 
@@ -80,8 +90,13 @@ hipError_t launch_adam(float* w, float* m, float* v, const float* g, int n, floa
 
 hipError_t launch_train_metrics(const float* loss_out, int B, const float* grad, int n,
                                 const uint8_t* actions, size_t nact, float lr, float* metrics,
-                                hipStream_t s) {
-  metrics_kernel<<<1, 256, 0, s>>>(loss_out, B, grad, n, actions, nact, lr, metrics);
+                                unsigned long long* counter, hipStream_t s) {
+  zero_u64_kernel<<<1, 1, 0, s>>>(counter);
+  size_t blocks = (nact / 16 + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 1024) blocks = 1024;
+  count_ones_kernel<<<(unsigned)blocks, 256, 0, s>>>(actions, nact, counter);
+  metrics_kernel<<<1, 256, 0, s>>>(loss_out, B, grad, n, counter, nact, lr, metrics);
   return hipGetLastError();
 }
 
