@@ -127,7 +127,7 @@ def default_train_params(**kw):
 
 
 def halftone_infer(weights, contone, seeds, noise_kind=HS_NOISE_GAUSS, precision=HS_BF16,
-                   recheck_tau=0.05, logits=False, stats=False, workspace=None):
+                   recheck_tau=0.055, logits=False, stats=False, workspace=None):
     """bits [B,H,W] uint8 (and optionally logits, and stats =
     (rechecked, flipped, recomputed in FP32, 0))."""
     B, H, W = contone.shape

@@ -584,13 +584,16 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
 // split-BF16 products on the matrix cores. Every FP32 value v is carried as
 // hi + lo with hi = bf16(v), lo = bf16(v - hi); a product is taken as
 // hi*hi' + lo*hi' + hi*lo' (the lo*lo' term, ~2^-16 relative, is dropped),
-// accumulated in FP32. Layer 1 and layer 6 are evaluated in plain FP32. The
-// result's error is ~2^-8 of the BF16 pass's, so a pixel is decided here
-// when |x| >= tau2; the rest go to the FP32 stage.
+// accumulated in FP32 (each of the three products in its own accumulator).
+// Layers 1..5 run this way (layer 1 with K = 9 taps x 2 channels padded to
+// 32); layer 6 is evaluated in plain FP32. The result's error is ~2^-8 of
+// the BF16 pass's, so a pixel is decided here when |x| >= tau2; the rest go
+// to the FP32 stage.
 //
 // A block takes CB = 4 listed pixels at a time. For layer k the four cones'
 // (13-2k)^2 output positions are cut into 16-position runs (the N operand);
-// the layer's hi and lo weight fragments sit in LDS for all runs.
+// the layer's hi and lo weight fragments sit in LDS for all runs, and the
+// next layer's are loaded into registers while this one computes.
 // ===========================================================================
 namespace {
 
@@ -632,8 +635,35 @@ __global__ __launch_bounds__(512) void recheck_split_kernel(
   __shared__ float l5f[CB][9 * 32];
   __shared__ int spre[SPLIT_MAXSEG + 1];  // exclusive prefix of the segment counts
   __shared__ uint32_t list[CB];           // the batch's pixels
+  __shared__ int cone_byx[CB][3];         // and their (image, row, column)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
   for (int i = tid; i < 608; i += 512) sw1[i] = w[HS_W1 + i];
+  // hi and lo weight fragments of one 32->32 layer: 2 x 1152 per layer; each
+  // thread carries its share of the NEXT layer's in registers while the
+  // current layer computes, so the L2 latency is hidden
+  constexpr int NWF = 2 * 9 * 2 * 64, WPT = (NWF + 511) / 512;
+  bf16x8_t pw[WPT];
+  auto fetch_weights = [&](int layer) {
+#pragma unroll
+    for (int j = 0; j < WPT; ++j) {
+      const int i = tid + 512 * j;
+      if (i < NWF) pw[j] = i < NWF / 2 ? whi[(layer - 2) * (NWF / 2) + i] : wlo[(layer - 2) * (NWF / 2) + i - NWF / 2];
+    }
+  };
+  fetch_weights(2);
+  // layer 1's A operands (hi and lo, both 16-channel row tiles), built once:
+  // lane (g, r) of tile m holds channel 16m + r, slot e = (dx = e / 2,
+  // input channel e % 2) of kernel row g; zero in the padding slots
+  bf16x8_t w1h[2], w1l[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float v = (g < 3 && e < 6) ? w[HS_W1 + ((16 * m + r) * 2 + (e & 1)) * 9 + g * 3 + (e >> 1)] : 0.0f;
+      const __bf16 h = (__bf16)v;
+      w1h[m][e] = h;
+      w1l[m][e] = (__bf16)(v - (float)h);
+    }
   // the segments are concatenated into one sequence dealt in CB-cone
   // batches to the blocks; wave 0 scans the counts (per lane a chunk of
   // consecutive segments, then a wave-wide scan of the chunk sums)
@@ -672,7 +702,13 @@ __global__ __launch_bounds__(512) void recheck_split_kernel(
         if (spre[mid] <= e) lo = mid;
         else hi = mid - 1;
       }
-      list[tid] = seglist[(size_t)lo * seg_cap + (e - spre[lo])];
+      const uint32_t o = seglist[(size_t)lo * seg_cap + (e - spre[lo])];
+      list[tid] = o;
+      const int b = (int)(o / ((uint32_t)H * W));
+      const int rem = (int)(o - (uint32_t)b * H * W);
+      cone_byx[tid][0] = b;
+      cone_byx[tid][1] = rem / W;
+      cone_byx[tid][2] = rem - (rem / W) * W;
     }
     __syncthreads();
     // stage the 13 x 13 state (c, z) of each cone, zero outside the image
@@ -680,9 +716,7 @@ __global__ __launch_bounds__(512) void recheck_split_kernel(
       const int cidx = i / 169, q = i - cidx * 169;
       float cv = 0.f, zv = 0.f;
       if (cidx < ncone) {
-        const uint32_t o = list[cidx];
-        const int b = (int)(o / ((uint32_t)H * W));
-        const int rem = (int)(o - (uint32_t)b * H * W), y = rem / W, x = rem - (rem / W) * W;
+        const int b = cone_byx[cidx][0], y = cone_byx[cidx][1], x = cone_byx[cidx][2];
         const int gy = y - 6 + q / 13, gx = x - 6 + q % 13;
         if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
           const uint64_t a = (uint64_t)gy * W + gx;
@@ -694,48 +728,63 @@ __global__ __launch_bounds__(512) void recheck_split_kernel(
       s0[cidx][q * 2 + 1] = zv;
     }
     __syncthreads();
-    // layer 1 in FP32 on the 11 x 11 windows; outputs stored split, in the
-    // ring channel order (chunk g holds channels 4g..4g+3, 16+4g..16+4g+3)
-    for (int i = tid; i < CB * 121 * 4; i += 512) {
-      const int cidx = i / 484, rem = i - cidx * 484, p = rem >> 2, cg = rem & 3;
-      const int py = p / 11, px = p - (p / 11) * 11;
-      const uint32_t o = list[cidx < ncone ? cidx : 0];
-      const int b = (int)(o / ((uint32_t)H * W));
-      const int rr = (int)(o - (uint32_t)b * H * W), y = rr / W, x = rr - (rr / W) * W;
-      const int gy = y - 5 + py, gx = x - 5 + px;
-      const bool in = cidx < ncone && gy >= 0 && gy < H && gx >= 0 && gx < W;
-      bf16x8_t vh, vl;
+    // layer 1 on the matrix cores, split BF16 like layers 2..5: K = 9 taps x
+    // 2 channels with lane group g = kernel row dy and slot e = (dx = e / 2,
+    // channel e % 2), so a lane's operand is six consecutive (c, z) floats;
+    // outputs stored split in the ring channel order
+    for (int job = wave; job < CB * 8; job += 8) {
+      const int cidx = job >> 3, run = job & 7;
+      const int pos = run * 16 + r;
+      const int pi = pos < 121 ? pos / 11 : 0, pj = pos < 121 ? pos - pi * 11 : 0;
+      const float* sp = &s0[cidx][((pi + (g < 3 ? g : 2)) * 13 + pj) * 2];
+      bf16x8_t bh, bl;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int co = ring_channel(cg, e);
-        float acc = 0.f;
-        if (in) {
-          acc = sw1[HS_B1 + co];
-#pragma unroll
-          for (int t = 0; t < 9; ++t) {
-            const int q = (py + t / 3) * 13 + px + t % 3;
-            acc = fmaf(sw1[(co * 2) * 9 + t], s0[cidx][q * 2], acc);
-            acc = fmaf(sw1[(co * 2 + 1) * 9 + t], s0[cidx][q * 2 + 1], acc);
-          }
-          acc = fmaxf(acc, 0.f);
-        }
-        const __bf16 h = (__bf16)acc;
-        vh[e] = h;
-        vl[e] = (__bf16)(acc - (float)h);
+        const float v = e < 6 ? sp[e] : 0.0f;
+        const __bf16 h = (__bf16)v;
+        bh[e] = h;
+        bl[e] = (__bf16)(v - (float)h);
       }
-      char* rec = bufA[cidx] + p * CREC;
-      *(bf16x8_t*)(rec + crec_slot(p, 2 * cg) * 16) = vh;
-      *(bf16x8_t*)(rec + crec_slot(p, 2 * cg + 1) * 16) = vl;
+      f32x4_t acc1[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const f32x4_t z4 = {0.f, 0.f, 0.f, 0.f};
+        const f32x4_t p0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1h[m], bh, z4, 0, 0, 0);
+        const f32x4_t p1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1l[m], bh, z4, 0, 0, 0);
+        const f32x4_t p2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1h[m], bl, z4, 0, 0, 0);
+        acc1[m] = p0 + (p1 + p2);
+      }
+      if (pos < 121 && cidx < ncone) {
+        const int y = cone_byx[cidx][1], x = cone_byx[cidx][2];
+        const int gy = y - 5 + pi, gx = x - 5 + pj;
+        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+        bf16x8_t vh, vl;
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float v = in ? fmaxf(acc1[m][i] + sw1[HS_B1 + 16 * m + 4 * g + i], 0.f) : 0.f;
+            const __bf16 h = (__bf16)v;
+            vh[4 * m + i] = h;
+            vl[4 * m + i] = (__bf16)(v - (float)h);
+          }
+        char* rec = bufA[cidx] + pos * CREC;
+        *(bf16x8_t*)(rec + crec_slot(pos, 2 * g) * 16) = vh;
+        *(bf16x8_t*)(rec + crec_slot(pos, 2 * g + 1) * 16) = vl;
+      }
     }
     // layers 2..5 on the matrix cores
     for (int k = 2; k <= 5; ++k) {
       const int e_out = 13 - 2 * k, e_in = e_out + 2, npos = e_out * e_out;
       const int runs = (npos + 15) / 16;
       __syncthreads();
-      for (int i = tid; i < 9 * 2 * 64; i += 512) {
-        swh[i] = whi[(k - 2) * 9 * 2 * 64 + i];
-        swl[i] = wlo[(k - 2) * 9 * 2 * 64 + i];
+#pragma unroll
+      for (int j = 0; j < WPT; ++j) {
+        const int i = tid + 512 * j;
+        if (i < NWF / 2) swh[i] = pw[j];
+        else if (i < NWF) swl[i - NWF / 2] = pw[j];
       }
+      fetch_weights(k == 5 ? 2 : k + 1);  // in flight during this layer
       __syncthreads();
       const bool from_a = (k & 1) == 0;  // layer 2 reads A, 3 reads B, ...
       float bk[2][4];
@@ -747,11 +796,14 @@ __global__ __launch_bounds__(512) void recheck_split_kernel(
       // is outermost so each tap's weight fragments are read once per wave
       constexpr int MAXJ = 3;  // layer 2: 4 cones x 6 runs over 8 waves
       const int njob = CB * runs;
-      f32x4_t acc[MAXJ][2];
+      // the three products hi*hi, lo*hi, hi*lo accumulate separately (three
+      // independent MFMA chains) and are summed at the end
+      f32x4_t acc[MAXJ][2], acl[MAXJ][2], ach[MAXJ][2];
       int jq[MAXJ];
 #pragma unroll
       for (int j = 0; j < MAXJ; ++j) {
         acc[j][0] = acc[j][1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        acl[j][0] = acl[j][1] = ach[j][0] = ach[j][1] = acc[j][0];
         const int job = wave + 8 * j;
         const int run = job < njob ? job % runs : 0;
         const int pos = run * 16 + r;
@@ -773,14 +825,18 @@ __global__ __launch_bounds__(512) void recheck_split_kernel(
             const bf16x8_t bh = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g) * 16);
             const bf16x8_t bl = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g + 1) * 16);
             acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, acc[j][0], 0, 0, 0);
-            acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, acc[j][0], 0, 0, 0);
-            acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, acc[j][0], 0, 0, 0);
+            acl[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, acl[j][0], 0, 0, 0);
+            ach[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, ach[j][0], 0, 0, 0);
             acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, acc[j][1], 0, 0, 0);
-            acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, acc[j][1], 0, 0, 0);
-            acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, acc[j][1], 0, 0, 0);
+            acl[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, acl[j][1], 0, 0, 0);
+            ach[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, ach[j][1], 0, 0, 0);
           }
         }
       }
+#pragma unroll
+      for (int j = 0; j < MAXJ; ++j)
+#pragma unroll
+        for (int m = 0; m < 2; ++m) acc[j][m] += acl[j][m] + ach[j][m];
 #pragma unroll
       for (int j = 0; j < MAXJ; ++j) {
         const int job = wave + 8 * j;
@@ -790,9 +846,7 @@ __global__ __launch_bounds__(512) void recheck_split_kernel(
         const int pos = run * 16 + r;
         const int pi = pos < npos ? pos / e_out : 0, pj = pos < npos ? pos - pi * e_out : 0;
         if (pos < npos && cidx < ncone) {
-          const uint32_t o = list[cidx];
-          const int b = (int)(o / ((uint32_t)H * W));
-          const int rr = (int)(o - (uint32_t)b * H * W), y = rr / W, x = rr - (rr / W) * W;
+          const int y = cone_byx[cidx][1], x = cone_byx[cidx][2];
           const int gy = y - (6 - k) + pi, gx = x - (6 - k) + pj;
           const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
           float v[2][4];
