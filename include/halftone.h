@@ -53,6 +53,10 @@ extern "C" {
 #define HS_WRT_PROB 0  /* gradients with respect to pi_a(h=1)              */
 #define HS_WRT_LOGIT 1 /* gradients with respect to the logit x_a          */
 
+#define HS_EST_LE 0   /* Local Expectation estimator (Sec. III-B, Eq. le)    */
+#define HS_EST_COMA 1 /* REINFORCE with the COMA baseline (Sec. III-A,
+                         Eqs. baseline and coma)                            */
+
 #define HS_PARAM_COUNT 37889
 
 /* Parameters of the reward and of the anisotropy-suppressing loss.
@@ -60,7 +64,8 @@ extern "C" {
  * (Sec. VI-A), HVS = 11x11 Gaussian sigma 2 (stand-in for the Nasanen
  * filter of Sec. V), SSIM window 11x11 Gaussian sigma 1.5 and k = 2
  * (Sec. V, contrast map), C1 = 1e-4, C2 = 9e-4 (SSIM constants of Wang et
- * al. 2004 for L = 1), anisotropy patches of 32x32. */
+ * al. 2004 for L = 1), anisotropy patches of 32x32, the Local Expectation
+ * estimator. */
 typedef struct hs_loss_params {
   float w_s;
   float w_a;
@@ -71,7 +76,8 @@ typedef struct hs_loss_params {
   float k;
   float c1;
   float c2;
-  int as_patch; /* only 32 is supported */
+  int as_patch;  /* only 32 is supported */
+  int estimator; /* HS_EST_LE or HS_EST_COMA */
 } hs_loss_params;
 
 /* Optimiser and sampling parameters of one TRAIN iteration (Algorithm 1).
@@ -107,8 +113,8 @@ int64_t halftone_param_count(void);
  *          |x| < recheck_tau is recomputed over its 13x13 receptive field
  *          with split-BF16 products (hi*hi + lo*hi + hi*lo, FP32
  *          accumulation, about 2^-8 of the BF16 error), and every pixel
- *          whose recomputed |x| is still below tau2 = recheck_tau/32 clamped
- *          to [1e-3, 1e-2] is recomputed once more in FP32 and decided from that
+ *          whose recomputed |x| is still below tau2 = recheck_tau/64 clamped
+ *          to [5e-4, 1e-2] is recomputed once more in FP32 and decided from that
  *          value (recheck_tau >= 0; it must exceed the largest BF16 logit
  *          error for the bits to equal FP32's off-margin).
  * bits     [B][H][W] uint8 out.
@@ -171,10 +177,17 @@ int halftone_loss(const uint8_t* actions, const float* contone, int B, int H, in
  * estimator of Sec. III-B, computed locally as in Sec. III-C; Eq. as).
  *
  * grad_probs [B][H][W] FP32 out: dL_MARL/dp_a = -dR_a / B where
- *          dR_a = R(h_a = 1, h_-a) - R(h_a = 0, h_-a).
+ *          dR_a = R(h_a = 1, h_-a) - R(h_a = 0, h_-a) (prm->estimator =
+ *          HS_EST_LE). With HS_EST_COMA: the one-sample COMA estimate
+ *          -(d/dp_a log pi_a(h_a)) (R(h) - b_a) / B, b_a = p_a R(h_a = 1,
+ *          h_-a) + (1 - p_a) R(h_a = 0, h_-a), i.e. -dR_a (1-p_a)/p_a / B
+ *          where h_a = 1 and -dR_a p_a/(1-p_a) / B where h_a = 0; it needs
+ *          probs_or_null in both gradient spaces.
  * grad_probs_gray_or_null [Bg][Hg][Wg] FP32 out: w_a * dL_AS/dp_g (zero
  *          outside the patches).
- * grad_space HS_WRT_PROB, or HS_WRT_LOGIT to multiply both by p(1 - p);
+ * grad_space HS_WRT_PROB, or HS_WRT_LOGIT to multiply both by p(1 - p)
+ *          (for COMA: -dR_a (1-p_a)^2 / B where h_a = 1, -dR_a p_a^2 / B
+ *          where h_a = 0);
  *          HS_WRT_LOGIT needs probs_or_null (for the main batch) and uses
  *          probs_gray_or_null for the gray batch.
  * --------------------------------------------------------------------- */
@@ -189,7 +202,7 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
  * One TRAIN iteration of Algorithm 1 on one GPU:
  *   forward of the batch (z from stream 1 at `step`), p = sigmoid(x),
  *   actions h_a = [u_a < p_a] (stream 0 at `step`), dL_MARL/dp from the
- *   Local Expectation estimator; forward of the constant-gray side batch,
+ *   estimator tp->loss.estimator (Local Expectation or COMA); forward of the constant-gray side batch,
  *   w_a * dL_AS/dp_g; backward of both through the conv stack; Adam on the
  *   FP32 master weights with lr_t = lr_min + (lr_max - lr_min)(1 +
  *   cos(pi step / total_steps))/2 and bias corrections at t = step + 1.

@@ -297,7 +297,7 @@ void or_policy_backward(const double* w, const int* ch, int L, const double* c,
  *          as_patch}.
  * ---------------------------------------------------------------------- */
 enum { P_WS, P_WA, P_HVS_SIGMA, P_HVS_R, P_SSIM_SIGMA, P_SSIM_R, P_K, P_C1,
-       P_C2, P_AS_PATCH };
+       P_C2, P_AS_PATCH, P_ESTIMATOR };
 
 /* (2r+1)^2 Gaussian window, exp(-(i^2+j^2)/(2 sigma^2)) normalised to sum 1.
  * Used as the HVS low-pass filter (BASELINE's Gaussian sigma = 2 stands in
@@ -520,6 +520,35 @@ void or_le_delta_local(const double* h, const double* c, int B, int H, int W,
 }
 
 /* ------------------------------------------------------------------------
+ * REINFORCE with the counterfactual (COMA) baseline (Sec. III-A, Eqs.
+ * baseline and coma), the estimator the Local Expectation one is compared
+ * with. For the sampled h and every agent a:
+ *   b_a = sum over h'_a of pi_a(h'_a) R({h'_a, h_-a})
+ *       = p_a R(h^1) + (1 - p_a) R(h^0),   h^v = h with h_a := v,
+ *   g_a = d/dx_a log pi_a(h_a) * (R(h) - b_a),
+ * where pi_a(1) = p_a = sigmoid(x_a), so d/dx_a log pi_a(h_a) = h_a - p_a.
+ * R(h^1) - R(h^0) is the toggle difference dR of the Local Expectation
+ * estimator and R(h) is R(h^{h_a}), so R(h) - b_a needs no further reward
+ * evaluation. Output: dL/dx_a = -g_a / B (the loss is -J, averaged over the
+ * batch).
+ * ---------------------------------------------------------------------- */
+void or_coma_grad_logit(const double* h, const double* c, const double* p, int B, int H,
+                        int W, const double* prm, double* grad) {
+  size_t N = (size_t)B * H * W;
+  double* dR = (double*)malloc(sizeof(double) * N);
+  or_le_delta_local(h, c, B, H, W, prm, dR);
+  for (size_t a = 0; a < N; ++a) {
+    /* R(h^1) = R0 + dR and R(h^0) = R0 for any common R0, which cancels */
+    double r1 = dR[a], r0 = 0.0;
+    double r_h = h[a] != 0.0 ? r1 : r0;
+    double b_a = p[a] * r1 + (1.0 - p[a]) * r0;
+    double dlogpi = h[a] - p[a];
+    grad[a] = -dlogpi * (r_h - b_a) / (double)B;
+  }
+  free(dR);
+}
+
+/* ------------------------------------------------------------------------
  * Anisotropy-suppressing loss (Sec. IV, Eqs. psd, rapsd, as; the probability
  * proxy of Sec. IV). Readings where the paper is silent: the map is cut into
  * non-overlapping P x P patches from (0,0) (remainders dropped); the
@@ -676,8 +705,9 @@ void or_adam_step(double* theta, double* m, double* v, const double* g, long n,
  * One TRAIN iteration of Algorithm 1:
  *   z ~ N(0, I) (stream 1, this step); p = sigmoid(CNN(c, z));
  *   h ~ Bernoulli(p) (stream 0, this step) unless `actions_in` is given;
- *   dL_MARL/dp = -dR/B (Local Expectation); back through the sigmoid and the
- *   conv stack;
+ *   dL_MARL/dp = -dR/B (Local Expectation), or the COMA estimator's
+ *   dL/dx when prm[P_ESTIMATOR] = 1; back through the sigmoid and the conv
+ *   stack;
  *   the constant-gray side batch: p_g = sigmoid(CNN(c_g, z_g)),
  *   dL_AS/dp_g, back through the sigmoid and the conv stack, weighted by w_a;
  *   Adam step with the cosine learning rate of `step` (0-based) out of
@@ -711,9 +741,13 @@ void or_train_step(double* w, double* m, double* v, const int* ch, int L,
   for (size_t i = 0; i < N; ++i) { hd[i] = h[i]; fill += h[i]; }
   double* rew = (double*)malloc(sizeof(double) * 3 * B);
   or_reward(hd, c, B, H, W, prm, rew);
-  or_le_delta_local(hd, c, B, H, W, prm, dR);
-  /* dL/dx_a = dL/dp_a * p_a (1 - p_a), dL/dp_a = -dR_a / B */
-  for (size_t i = 0; i < N; ++i) dR[i] = (-dR[i] / B) * p[i] * (1.0 - p[i]);
+  if ((int)prm[P_ESTIMATOR] == 1) {
+    or_coma_grad_logit(hd, c, p, B, H, W, prm, dR);
+  } else {
+    or_le_delta_local(hd, c, B, H, W, prm, dR);
+    /* dL/dx_a = dL/dp_a * p_a (1 - p_a), dL/dp_a = -dR_a / B */
+    for (size_t i = 0; i < N; ++i) dR[i] = (-dR[i] / B) * p[i] * (1.0 - p[i]);
+  }
   or_policy_backward(w, ch, L, c, z, B, H, W, dR, grad, NULL);
   double las = 0.0;
   if (Bg > 0) {

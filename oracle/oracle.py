@@ -24,10 +24,11 @@ CH = (2, 32, 32, 32, 32, 32, 1)
 # Loss parameters (Sec. VI-A: w_s = 0.06, w_a = 0.002; Sec. V: k = 2 and the
 # 11x11 sigma = 1.5 SSIM window; the 11x11 Gaussian sigma = 2 HVS filter;
 # SSIM constants from Wang et al. 2004 with K1 = 0.01, K2 = 0.03, L = 1).
+# estimator: 0 = Local Expectation (Eq. le), 1 = COMA (Eq. coma).
 DEFAULT_PRM = dict(w_s=0.06, w_a=0.002, hvs_sigma=2.0, hvs_r=5, ssim_sigma=1.5,
-                   ssim_r=5, k=2.0, C1=1e-4, C2=9e-4, as_patch=32)
+                   ssim_r=5, k=2.0, C1=1e-4, C2=9e-4, as_patch=32, estimator=0)
 PRM_ORDER = ("w_s", "w_a", "hvs_sigma", "hvs_r", "ssim_sigma", "ssim_r", "k",
-             "C1", "C2", "as_patch")
+             "C1", "C2", "as_patch", "estimator")
 # Optimiser (Sec. VI-A: Adam, cosine 3e-4 -> 1e-5; textbook Adam constants).
 DEFAULT_TRAIN = dict(lr_max=3e-4, lr_min=1e-5, beta1=0.9, beta2=0.999, eps=1e-8)
 
@@ -73,6 +74,7 @@ def lib():
             "or_reward": (None, [D, D, c_int, c_int, c_int, D, D]),
             "or_le_delta_brute": (None, [D, D, c_int, c_int, c_int, D, D]),
             "or_le_delta_local": (None, [D, D, c_int, c_int, c_int, D, D]),
+            "or_coma_grad_logit": (None, [D, D, D, c_int, c_int, c_int, D, D]),
             "or_ring_index": (c_int, [c_int, c_int, c_int]),
             "or_as_loss": (c_double, [D, c_int, c_int, c_int, c_int, D]),
             "or_anisotropy": (None, [D, c_int, D, D]),
@@ -254,6 +256,18 @@ def le_grad_probs(h, c, prm=None):
     """dL_MARL/dp_a = -dR_a / B (Eq. marl, mini-batch mean)."""
     d = le_delta(h, c, prm)
     return -d / d.shape[0]
+
+
+def coma_grad_logits(h, c, p, prm=None):
+    """dL/dx_a of the COMA estimator (Eqs. baseline, coma), batch mean."""
+    B, H, W = _bhw(c)
+    h, hp = _d(np.reshape(h, (B, H, W)))
+    c, cp = _d(np.reshape(c, (B, H, W)))
+    p, pxp = _d(np.reshape(p, (B, H, W)))
+    q, qp = _prm(prm)
+    g, gp = _d(np.zeros((B, H, W)))
+    lib().or_coma_grad_logit(hp, cp, pxp, B, H, W, qp, gp)
+    return g
 
 
 def ring_index(u, v, P=32):

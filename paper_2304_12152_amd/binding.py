@@ -16,6 +16,7 @@ HS_OK, HS_EINVAL, HS_ESHAPE, HS_EUNSUPPORTED, HS_EWORKSPACE, HS_EHIP = 0, -1, -2
 HS_FP32, HS_BF16 = 0, 1
 HS_NOISE_GAUSS, HS_NOISE_UNIFORM = 0, 1
 HS_WRT_PROB, HS_WRT_LOGIT = 0, 1
+HS_EST_LE, HS_EST_COMA = 0, 1
 HS_PARAM_COUNT = 37889
 
 
@@ -23,7 +24,7 @@ class HsLossParams(ctypes.Structure):
     _fields_ = [("w_s", ctypes.c_float), ("w_a", ctypes.c_float), ("hvs_sigma", ctypes.c_float),
                 ("hvs_radius", ctypes.c_int), ("ssim_sigma", ctypes.c_float),
                 ("ssim_radius", ctypes.c_int), ("k", ctypes.c_float), ("c1", ctypes.c_float),
-                ("c2", ctypes.c_float), ("as_patch", ctypes.c_int)]
+                ("c2", ctypes.c_float), ("as_patch", ctypes.c_int), ("estimator", ctypes.c_int)]
 
 
 class HsTrainParams(ctypes.Structure):

@@ -76,6 +76,8 @@ int check_params(const hs_loss_params* p) {
     return fail(HS_EINVAL, "window radii must be in 1..7");
   if (!(p->hvs_sigma > 0.0f) || !(p->ssim_sigma > 0.0f)) return fail(HS_EINVAL, "sigma <= 0");
   if (p->as_patch != 32) return fail(HS_EUNSUPPORTED, "only 32x32 anisotropy patches");
+  if (p->estimator != HS_EST_LE && p->estimator != HS_EST_COMA)
+    return fail(HS_EINVAL, "estimator %d", p->estimator);
   return HS_OK;
 }
 
@@ -122,6 +124,7 @@ LossWs carve_loss(Carve& cv, int B, int H, int W, int Bg, int Hg, int Wg, int m,
 
 struct InferWs {
   void *pack, *a0, *a1;
+  int* seg_count = nullptr;   // BF16 path: entries per recheck-list segment
 };
 InferWs carve_infer(Carve& cv, size_t N, int prec) {
   InferWs w;
@@ -243,6 +246,7 @@ void halftone_default_loss_params(hs_loss_params* p) {
   p->c1 = 1e-4f;
   p->c2 = 9e-4f;
   p->as_patch = 32;
+  p->estimator = HS_EST_LE;
 }
 
 void halftone_default_train_params(hs_train_params* p) {
@@ -290,15 +294,16 @@ static size_t infer_ws(int B, int H, int W, int prec, InferWs* out, uint32_t** l
   Carve cv(base);
   const size_t N = (size_t)B * H * W;
   InferWs w;
-  if (prec == HS_BF16) {  // fused path: packed fragments, the segmented list,
-                          // its counts, and the dense FP32-stage list
+  if (prec == HS_BF16) {  // fused path (sizes in bytes): packed fragments, the
+                          // segmented list and its counts, the dense FP32-stage
+                          // list
     w.pack = cv.take<char>(fused_frag_bytes());
-    w.a0 = cv.take<char>(split_frag_bytes());
+    w.a0 = cv.take<char>(split_frag_bytes() + fp32_pack_bytes());
     const size_t ne = fused_list_entries(B, H, W, num_cus());
-    w.a1 = cv.take<char>(ne * 4);                      // segmented list
-    uint32_t* l = cv.take<uint32_t>(N * 4);            // FP32-stage list
+    w.a1 = cv.take<char>(ne * sizeof(uint32_t));                        // segmented list
+    w.seg_count = cv.take<int>((2 * (size_t)num_cus() + 16) * sizeof(int));  // its counts
+    uint32_t* l = cv.take<uint32_t>(N * sizeof(uint32_t));              // FP32-stage list
     if (list) *list = l;
-    cv.take<int>(2 * (size_t)num_cus() * 4 + 64);      // segment counts (tail of a1 area)
   } else {
     w = carve_infer(cv, N, prec);
     if (list) *list = nullptr;
@@ -343,14 +348,15 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
     // stage 1: fused BF16 pass, pixels with |x| < tau listed
     // stage 2: split-BF16 receptive-field recompute, |x| < tau2 listed again
     // stage 3: FP32 receptive-field recompute
-    const float tau2 = fminf(fmaxf(recheck_tau / 32.0f, 1e-3f), 1e-2f);
+    const float tau2 = fminf(fmaxf(recheck_tau / 64.0f, 5e-4f), 1e-2f);
     uint32_t* list2 = list;
     uint32_t* seglist = (uint32_t*)iw.a1;
-    int* seg_count = (int*)((char*)list + align256((size_t)B * H * W * 4));
+    int* seg_count = iw.seg_count;
     char* whi = (char*)iw.a0;
     char* wlo = whi + split_frag_bytes() / 2;
+    char* wt = whi + split_frag_bytes();
     HS_TRY(launch_fused_pack(weights, iw.pack, s));
-    HS_TRY(launch_split_pack(weights, whi, wlo, s));
+    HS_TRY(launch_split_pack(weights, whi, wlo, wt, s));
     int nseg = 0;
     long long seg_cap = 0;
     prof_begin(s);
@@ -361,8 +367,8 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
     HS_TRY(launch_recheck_split(weights, contone, seeds, H, W, noise_kind, seglist, seg_count, nseg,
                                 seg_cap, whi, wlo, tau2, list2, cnt + 1, bits, logits_or_null,
                                 stats, num_cus(), s));
-    HS_TRY(launch_recheck_fp32(weights, contone, seeds, H, W, noise_kind, list2, cnt + 1, bits,
-                               logits_or_null, stats, 2, s));
+    HS_TRY(launch_recheck_fp32(weights, contone, seeds, H, W, noise_kind, list2, cnt + 1, wt,
+                               bits, logits_or_null, stats, 2, num_cus(), s));
     return HS_OK;
   }
   HS_TRY(launch_pack32(weights, iw.pack, precision, 0, s));
@@ -500,6 +506,8 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
     return fail(HS_EINVAL, "halftone_loss_backward: grad_space %d", grad_space);
   if (grad_space == HS_WRT_LOGIT && !probs_or_null)
     return fail(HS_EINVAL, "halftone_loss_backward: logit space needs probs");
+  if (prm->estimator == HS_EST_COMA && !probs_or_null)
+    return fail(HS_EINVAL, "halftone_loss_backward: the COMA estimator needs probs");
   if (probs_gray_or_null && !grad_probs_gray_or_null)
     return fail(HS_EINVAL, "halftone_loss_backward: gray batch without its gradient buffer");
   if (!probs_gray_or_null) Bg = Hg = Wg = 0;
@@ -513,8 +521,8 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
   LossDev win;
   make_windows(*prm, &win);
   HS_TRY(launch_loss_stats(actions, contone, B, H, W, *prm, win, lw.maps, lw.tiles, lw.ntiles, s));
-  HS_TRY(launch_le_grad(actions, contone, grad_space == HS_WRT_LOGIT ? probs_or_null : nullptr, B,
-                        H, W, *prm, win, lw.maps, grad_probs, s));
+  HS_TRY(launch_le_grad(actions, contone, probs_or_null, grad_space == HS_WRT_LOGIT, B, H, W,
+                        *prm, win, lw.maps, grad_probs, s));
   if (probs_gray_or_null) {
     const int npatch = Bg * (Hg / 32) * (Wg / 32);
     HS_TRY(launch_fill(grad_probs_gray_or_null, (size_t)Bg * Hg * Wg, 0.0f, s));
@@ -601,13 +609,13 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   const hs_loss_params& lp = tp->loss;
   const int kind = tp->noise_kind;
   const uint32_t st = (uint32_t)step;
-  // batch: forward, actions, Local Expectation gradient (logit space), backward
+  // batch: forward, actions, policy gradient (logit space), backward
   HS_TRY(run_forward_train(weights, contones, seeds, B, H, W, kind, st, precision, pw, probs, act,
                            s));
   LossDev win;
   make_windows(lp, &win);
   HS_TRY(launch_loss_stats(act, contones, B, H, W, lp, win, lw.maps, lw.tiles, lw.ntiles, s));
-  HS_TRY(launch_le_grad(act, contones, probs, B, H, W, lp, win, lw.maps, gradp, s));
+  HS_TRY(launch_le_grad(act, contones, probs, 1, B, H, W, lp, win, lw.maps, gradp, s));
   HS_TRY(run_backward(weights, gradp, nullptr, B, H, W, precision, pw, 0, s));
   // constant-gray side batch: forward, anisotropy gradient, backward
   const int npatch = Bg * (Hg / 32) * (Wg / 32);

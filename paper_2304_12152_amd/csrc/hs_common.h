@@ -129,6 +129,23 @@ HS_DEV void hs_store4(__bf16* p, float a, float b, float c, float d) {
 
 HS_DEV float hs_sigmoid(float x) { return 1.0f / (1.0f + expf(-x)); }
 
+// Channel order of the matrix-core convolutions: the 16x16 MFMA result of
+// lane (g, r) holds channels 4g..4g+3 of both 16-channel row tiles for
+// pixel r; those eight channels, stored as the lane's 16-byte chunk, are the
+// next layer's K-slice for lane group g. Slot e of that chunk holds channel
+// hs_ring_channel(g, e), and the next layer's weights are packed to match.
+HS_DEV int hs_ring_channel(int g, int e) { return e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4); }
+
+// Workgroup barrier that orders LDS accesses only: unlike __syncthreads()
+// it does not wait for the wave's outstanding global loads and stores, so a
+// load issued for a later step stays in flight across it. Only for kernels
+// whose waves do not communicate through global memory within a launch.
+HS_DEV void hs_lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Wave-wide sum (64 lanes) with a fixed reduction order.
 HS_DEV float hs_wave_sum(float v) {
 #pragma unroll

@@ -50,23 +50,27 @@ hipError_t launch_conv_last(const void* in, const float* w, int B, int H, int W,
                             int mode, const uint64_t* seeds, uint32_t step, uint8_t* bits,
                             float* logits, float* probs, float tau, uint32_t* list, int* count,
                             hipStream_t s);
-// infer.hip: FP32 re-evaluation of listed pixels over their receptive field.
+// infer.hip: the fused BF16 pass
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 size_t fused_frag_bytes();
 hipError_t launch_fused_pack(const float* w, void* frags, hipStream_t s);
 // persistent fused BF16 inference; the recheck list is segmented (two
-// segments per workgroup, counts in seg_count; list may be null)
+// segments per workgroup, counts in seg_count; list may be null); a list
+// entry carries the bit written for the pixel in its top bit
 size_t fused_list_entries(int B, int H, int W, int num_cus);
 hipError_t launch_fused_infer(const float* w, const float* contone, const uint64_t* seeds, int B,
                               int H, int W, int kind, float tau, uint8_t* bits, float* logits,
                               uint32_t* list, int* seg_count, int* nseg, long long* seg_cap,
                               const void* frags, int num_cus, hipStream_t s);
+// recheck.hip: re-evaluation of listed pixels over their receptive field
+// (wt: layers 2..5 transposed for the FP32 stage, fp32_pack_bytes())
 hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,
                                int H, int W, int kind, const uint32_t* list, const int* count,
-                               uint8_t* bits, float* logits, int32_t* stats, int count_slot,
-                               hipStream_t s);
+                               const void* wt, uint8_t* bits, float* logits, int32_t* stats,
+                               int count_slot, int num_cus, hipStream_t s);
 size_t split_frag_bytes();
-hipError_t launch_split_pack(const float* w, void* whi, void* wlo, hipStream_t s);
+size_t fp32_pack_bytes();
+hipError_t launch_split_pack(const float* w, void* whi, void* wlo, void* wt, hipStream_t s);
 hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
                                 int H, int W, int kind, const uint32_t* seglist,
                                 const int* seg_count, int nseg, long long seg_cap,
@@ -103,9 +107,11 @@ hipError_t launch_loss_stats(const uint8_t* h, const float* c, int B, int H, int
 hipError_t launch_loss_reduce(const float* tile_partials, int B, int ntiles_per_img,
                               const float* as_partials, int npatch, float w_s, long M, float* out,
                               hipStream_t s);
-hipError_t launch_le_grad(const uint8_t* h, const float* c, const float* probs, int B, int H,
-                          int W, const hs_loss_params& p, const LossDev& win, const float* maps,
-                          float* grad, hipStream_t s);
+// per-pixel policy gradient from the toggle differences dR (Local Expectation
+// or COMA, p.estimator); probs may be null only for LE in probability space
+hipError_t launch_le_grad(const uint8_t* h, const float* c, const float* probs, int logit_space,
+                          int B, int H, int W, const hs_loss_params& p, const LossDev& win,
+                          const float* maps, float* grad, hipStream_t s);
 hipError_t launch_as(const float* pg, int Bg, int Hg, int Wg, float scale, int logit_space,
                      float* patch_loss, float* grad_or_null, hipStream_t s);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);

@@ -1,124 +1,15 @@
-// infer.hip -- the TEST procedure of Algorithm 1 on gfx950: FP32
-// re-evaluation of the pixels whose low-precision logit falls near the 0.5
-// threshold.
-//
-// A listed pixel is recomputed exactly as the FP32 network would compute it,
-// over its 13 x 13 receptive field only: layer k is evaluated on the
-// (13 - 2k) x (13 - 2k) window centred on the pixel, with every activation
-// outside the image forced to zero (the zero 'same' padding of each layer).
+// infer.hip -- the TEST procedure of Algorithm 1 on gfx950: the fused BF16
+// pass of the policy network over whole images, with each pixel's logit
+// thresholded at 0 (p = 0.5) and the near-threshold pixels listed for the
+// recheck stages (recheck.hip).
 #include "hs_common.h"
 #include "hs_internal.h"
 
 namespace {
 
-constexpr int RS = 33;  // padded channel stride of a staged pixel (floats)
-
 __global__ void zero_ints_kernel(int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
-}
-
-// One block re-evaluates one listed pixel at a time (grid-stride over the
-// list, whose length is read on the device).
-__global__ __launch_bounds__(256) void recheck_fp32_kernel(
-    const float* __restrict__ w, const float* __restrict__ contone,
-    const uint64_t* __restrict__ seeds, int H, int W, int kind, const uint32_t* __restrict__ list,
-    const int* __restrict__ count, uint8_t* __restrict__ bits, float* __restrict__ logits,
-    int32_t* __restrict__ stats, int count_slot) {
-  __shared__ float s0[13 * 13 * 2];
-  __shared__ float bufA[11 * 11 * RS], bufB[9 * 9 * RS];
-  __shared__ float sw[9 * 32 * 32];  // [ci][t][co]: consecutive lanes read consecutive co
-  __shared__ float sb[32];
-  const int n = *count;
-  const int tid = threadIdx.x;
-  for (int it = blockIdx.x; it < n; it += gridDim.x) {
-    const uint32_t o = list[it];
-    const int b = (int)(o / ((uint32_t)H * W));
-    const int rem = (int)(o - (uint32_t)b * H * W), y = rem / W, x = rem - (rem / W) * W;
-    const size_t img = (size_t)b * H * W;
-    __syncthreads();
-    for (int i = tid; i < 169; i += 256) {
-      const int gy = y - 6 + i / 13, gx = x - 6 + i % 13;
-      float cv = 0.f, zv = 0.f;
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-        const uint64_t a = (uint64_t)gy * W + gx;
-        cv = contone[img + a];
-        zv = hs_noise(seeds[b], a, 0u, kind);
-      }
-      s0[i * 2] = cv;
-      s0[i * 2 + 1] = zv;
-    }
-    for (int i = tid; i < 32 * 2 * 9; i += 256) {
-      const int co = i / 18, ci = (i / 9) & 1, t = i % 9;
-      sw[(ci * 9 + t) * 32 + co] = w[HS_W1 + i];
-    }
-    if (tid < 32) sb[tid] = w[HS_B1 + tid];
-    __syncthreads();
-    // layer 1 on the 11 x 11 window
-    for (int i = tid; i < 121 * 32; i += 256) {
-      const int co = i & 31, p = i >> 5, py = p / 11, px = p % 11;
-      const int gy = y - 5 + py, gx = x - 5 + px;
-      float acc = 0.f;
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-        acc = sb[co];
-        for (int t = 0; t < 9; ++t) {
-          const int q = (py + t / 3) * 13 + px + t % 3;
-          acc = fmaf(sw[(0 * 9 + t) * 32 + co], s0[q * 2], acc);
-          acc = fmaf(sw[(1 * 9 + t) * 32 + co], s0[q * 2 + 1], acc);
-        }
-        acc = fmaxf(acc, 0.f);
-      }
-      bufA[p * RS + co] = acc;
-    }
-    // layers 2..5: window edges 9, 7, 5, 3
-    for (int k = 2; k <= 5; ++k) {
-      const int e_in = 13 - 2 * (k - 1), e_out = 13 - 2 * k;
-      const float* src = (k & 1) ? bufB : bufA;
-      float* dst = (k & 1) ? bufA : bufB;
-      __syncthreads();
-      const float* Wk = w + hs_wk(k);
-      for (int i = tid; i < 9 * 32 * 32; i += 256) {
-        const int co = i / 288, ci = (i / 9) & 31, t = i % 9;
-        sw[(ci * 9 + t) * 32 + co] = Wk[i];
-      }
-      if (tid < 32) sb[tid] = w[hs_bk(k) + tid];
-      __syncthreads();
-      for (int i = tid; i < e_out * e_out * 32; i += 256) {
-        const int co = i & 31, p = i >> 5, py = p / e_out, px = p % e_out;
-        const int gy = y - (6 - k) + py, gx = x - (6 - k) + px;
-        float acc = 0.f;
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-          acc = sb[co];
-          for (int t = 0; t < 9; ++t) {
-            const float* sp = src + ((py + t / 3) * e_in + px + t % 3) * RS;
-            const float* wp = sw + t * 32 + co;
-#pragma unroll 8
-            for (int ci = 0; ci < 32; ++ci) acc = fmaf(wp[ci * 9 * 32], sp[ci], acc);
-          }
-          acc = fmaxf(acc, 0.f);
-        }
-        dst[p * RS + co] = acc;
-      }
-    }
-    __syncthreads();
-    // layer 6 at the centre of the 3 x 3 window (in bufA)
-    if (tid < 64) {
-      float part = 0.f;
-      for (int i = tid; i < 288; i += 64) {
-        const int ci = i / 9, t = i % 9;
-        part = fmaf(w[HS_W6 + i], bufA[((t / 3) * 3 + t % 3) * RS + ci], part);
-      }
-      part = hs_wave_sum(part);
-      if (tid == 0) {
-        const float xl = part + w[HS_B6];
-        const uint8_t nb = xl >= 0.f ? 1 : 0;
-        if (bits[o] != nb) atomicAdd(&stats[1], 1);
-        bits[o] = nb;
-        if (logits) logits[o] = xl;
-      }
-    }
-  }
-  if (blockIdx.x == 0 && tid == 0) stats[count_slot] = n;
 }
 
 }  // namespace
@@ -127,15 +18,6 @@ namespace hs {
 
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
   zero_ints_kernel<<<(n + 255) / 256, 256, 0, s>>>(p, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,
-                               int H, int W, int kind, const uint32_t* list, const int* count,
-                               uint8_t* bits, float* logits, int32_t* stats, int count_slot,
-                               hipStream_t s) {
-  recheck_fp32_kernel<<<1024, 256, 0, s>>>(w, contone, seeds, H, W, kind, list, count, bits,
-                                           logits, stats, count_slot);
   return hipGetLastError();
 }
 
@@ -181,6 +63,11 @@ namespace {
 
 constexpr int FW = 128, FS = FW - 12, RWID = FW + 2;
 constexpr int LAG_OUT = 22;  // steps from the first input row Y0-6 to output row Y0
+// A strip segment costs its rows plus about FILL steps of pipeline fill, so
+// the workgroups split a sequence in which every strip is preceded by FILL
+// virtual rows into equal parts: each workgroup then runs about the same
+// number of steps, whether or not its rows cross a strip boundary.
+constexpr int FILL = LAG_OUT + 2;
 constexpr int FRAG_L1 = 0, FRAG_L32 = 128, FRAG_T = 128 + 4 * 9 * 2 * 64;
 constexpr int FRAG_TOTAL = FRAG_T + 64;
 constexpr int FUSED_NW = 2;  // waves per conv layer in the fused kernel
@@ -190,8 +77,7 @@ constexpr int RUNE = 16 * 32;           // elements per 16-column run
 // element offset of chunk g of column col in a ring row
 HS_DEV int ring_off(int col, int g) { return (col * 4 + (g ^ ((col >> 1) & 3))) * 8; }
 
-// channel held by slot e of lane group g in the ring order
-HS_DEV int ring_channel(int g, int e) { return e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4); }
+HS_DEV int ring_channel(int g, int e) { return hs_ring_channel(g, e); }
 
 __global__ void pack_fused_kernel(const float* __restrict__ w, __bf16* __restrict__ out) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < FRAG_TOTAL * 8;
@@ -221,7 +107,7 @@ struct FusedArgs {
   const bf16x8_t* frags;
   const float* w;
   int B, H, W, kind, nstrip;
-  int total_rows, rows_per_wg;
+  long long vtotal;   // strips x (H + FILL): the balanced partition's extent
   float tau;
   uint8_t* bits;
   float* logits;
@@ -263,14 +149,9 @@ HS_DEV bf16x8_t relu_bf16(const f32x4_t (&acc)[2], bool in) {
   return v;
 }
 
-// Workgroup barrier that orders LDS only. The waves of a workgroup never
-// read each other's global writes, so the per-step barrier need not wait for
+// The waves of a workgroup never read each other's global writes, so the
+// per-step barrier orders LDS only (hs_lds_barrier): it need not wait for
 // the bits, logits and list stores (nor the contone prefetch) to complete.
-HS_DEV void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 template <int NW>
 __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a) {
@@ -319,11 +200,17 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
   for (int h = 0; h < HPW; ++h) nflag[h] = 0;
   __syncthreads();
 
-  // strip rows [Lbeg, Lend) of the sequence (image, strip, row); the
+  // strip rows [Lbeg, Lend) of the sequence (image, strip, row): the real
+  // rows of this workgroup's equal share of the virtual sequence; the
   // divisions are wave-uniform and kept scalar
-  const int Lbeg = blockIdx.x * a.rows_per_wg;
-  const int Lend = min(Lbeg + a.rows_per_wg, a.total_rows);
   const int H = a.H, W = a.W;
+  auto real_row = [&](long long v) {
+    const long long sid = v / (H + FILL);
+    const int rv = (int)(v - sid * (H + FILL));
+    return (int)(sid * H) + max(rv - FILL, 0);
+  };
+  const int Lbeg = real_row((long long)blockIdx.x * a.vtotal / gridDim.x);
+  const int Lend = real_row((long long)(blockIdx.x + 1) * a.vtotal / gridDim.x);
   for (int L = Lbeg; L < Lend;) {
     const int strip_id = __builtin_amdgcn_readfirstlane(L / H);
     const int Y0 = L - strip_id * H;
@@ -396,7 +283,9 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
                 const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                 const long long seg = 2LL * blockIdx.x + HPW * part + h;
-                a.list[seg * a.seg_cap + nflag[h] + below] = (uint32_t)o;
+                // the entry carries the bit written here in its top bit
+                a.list[seg * a.seg_cap + nflag[h] + below] =
+                    (uint32_t)o | (xl >= 0.0f ? 0x80000000u : 0u);
               }
               nflag[h] += __popcll(mask);
             }
@@ -499,7 +388,7 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
           if (Lx >= 1) rrow[(Lx - 1) * 4 + 2] = u;
         }
       }
-      lds_barrier();
+      hs_lds_barrier();
     };
     for (int t = 0; t < nsteps; t += 3) {
       step(t, StepIndex<0>{});
@@ -526,23 +415,27 @@ hipError_t launch_fused_pack(const float* w, void* frags, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Geometry of the persistent launch: workgroups and strip-rows per workgroup.
-void fused_geometry(int B, int H, int W, int num_cus, int* grid, long long* rows_per_wg) {
+// Geometry of the persistent launch: workgroups (one per CU, fewer when
+// there are under 32 strip rows per CU) and an upper bound on the real strip
+// rows of one workgroup's share.
+void fused_geometry(int B, int H, int W, int num_cus, int* grid, long long* max_rows) {
   const int nstrip = (W + FS - 1) / FS;
   const long long total = (long long)B * nstrip * H;
   long long per = (total + num_cus - 1) / num_cus;
   if (per < 32) per = 32;
-  *rows_per_wg = per;
-  *grid = (int)((total + per - 1) / per);
+  const int g = (int)((total + per - 1) / per);
+  const long long vtotal = (long long)B * nstrip * (H + FILL);
+  *grid = g;
+  *max_rows = (vtotal + g - 1) / g + 1;
 }
 
 // Entries of the segmented recheck list: two segments per workgroup, each
 // able to hold every pixel its wave writes.
 size_t fused_list_entries(int B, int H, int W, int num_cus) {
   int grid;
-  long long per;
-  fused_geometry(B, H, W, num_cus, &grid, &per);
-  return (size_t)grid * 2 * (size_t)per * 64;
+  long long rows;
+  fused_geometry(B, H, W, num_cus, &grid, &rows);
+  return (size_t)grid * 2 * (size_t)rows * 64;
 }
 
 hipError_t launch_fused_infer(const float* w, const float* contone, const uint64_t* seeds, int B,
@@ -560,11 +453,10 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
   a.kind = kind;
   a.nstrip = (W + FS - 1) / FS;
   // nstrip <= W, so B * nstrip * H <= B * H * W < 2^31 (checked by the caller)
-  a.total_rows = (int)((long long)B * a.nstrip * H);
+  a.vtotal = (long long)B * a.nstrip * (H + FILL);
   int grid;
   long long per;
   fused_geometry(B, H, W, num_cus, &grid, &per);
-  a.rows_per_wg = (int)per;
   a.tau = tau;
   a.bits = bits;
   a.logits = logits;
@@ -579,354 +471,3 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
 
 }  // namespace hs
 
-// ===========================================================================
-// Second-stage recheck: the listed pixels' receptive fields recomputed with
-// split-BF16 products on the matrix cores. Every FP32 value v is carried as
-// hi + lo with hi = bf16(v), lo = bf16(v - hi); a product is taken as
-// hi*hi' + lo*hi' + hi*lo' (the lo*lo' term, ~2^-16 relative, is dropped),
-// accumulated in FP32 (each of the three products in its own accumulator).
-// Layers 1..5 run this way (layer 1 with K = 9 taps x 2 channels padded to
-// 32); layer 6 is evaluated in plain FP32. The result's error is ~2^-8 of
-// the BF16 pass's, so a pixel is decided here when |x| >= tau2; the rest go
-// to the FP32 stage.
-//
-// A block takes CB = 4 listed pixels at a time. For layer k the four cones'
-// (13-2k)^2 output positions are cut into 16-position runs (the N operand);
-// the layer's hi and lo weight fragments sit in LDS for all runs, and the
-// next layer's are loaded into registers while this one computes.
-// ===========================================================================
-namespace {
-
-constexpr int CB = 4;                 // cones per block
-constexpr int SPLIT_MAXSEG = 1024;    // list segments the recheck accepts
-constexpr int CREC = 128;             // bytes per staged pixel: 4 groups x (hi, lo) x 16 B
-constexpr int CBUF_A = 121, CBUF_B = 81;
-
-__global__ void pack_split_kernel(const float* __restrict__ w, __bf16* __restrict__ hi,
-                                  __bf16* __restrict__ lo) {
-  // layers 2..5 in the ring channel order of the fused kernel: [layer][tap][m][lane][8]
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 4 * 9 * 2 * 64 * 8;
-       i += gridDim.x * blockDim.x) {
-    const int e = i & 7, l = (i >> 3) & 63, m = (i >> 9) & 1, t = (i >> 10) % 9,
-              layer = (i >> 10) / 9;
-    const int g = l >> 4, r = l & 15;
-    const float v = w[hs_wk(layer + 2) + ((16 * m + r) * 32 + ring_channel(g, e)) * 9 + t];
-    const __bf16 h = (__bf16)v;
-    hi[i] = h;
-    lo[i] = (__bf16)(v - (float)h);
-  }
-}
-
-HS_DEV int crec_slot(int p, int c) { return c ^ (p & 7); }
-
-__global__ __launch_bounds__(512) void recheck_split_kernel(
-    const float* __restrict__ w, const float* __restrict__ contone,
-    const uint64_t* __restrict__ seeds, int H, int W, int kind, const uint32_t* __restrict__ seglist,
-    const int* __restrict__ seg_count, int nseg, long long seg_cap,
-    const bf16x8_t* __restrict__ whi,
-    const bf16x8_t* __restrict__ wlo, float tau2, uint32_t* __restrict__ list2,
-    int* __restrict__ count2, uint8_t* __restrict__ bits, float* __restrict__ logits,
-    int32_t* __restrict__ stats) {
-  __shared__ __attribute__((aligned(16))) bf16x8_t swh[9 * 2 * 64], swl[9 * 2 * 64];
-  __shared__ __attribute__((aligned(16))) char bufA[CB][CBUF_A * CREC];
-  __shared__ __attribute__((aligned(16))) char bufB[CB][CBUF_B * CREC];
-  __shared__ float s0[CB][169 * 2];
-  __shared__ float sw1[32 * 2 * 9 + 32];
-  __shared__ float l5f[CB][9 * 32];
-  __shared__ int spre[SPLIT_MAXSEG + 1];  // exclusive prefix of the segment counts
-  __shared__ uint32_t list[CB];           // the batch's pixels
-  __shared__ int cone_byx[CB][3];         // and their (image, row, column)
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
-  for (int i = tid; i < 608; i += 512) sw1[i] = w[HS_W1 + i];
-  // hi and lo weight fragments of one 32->32 layer: 2 x 1152 per layer; each
-  // thread carries its share of the NEXT layer's in registers while the
-  // current layer computes, so the L2 latency is hidden
-  constexpr int NWF = 2 * 9 * 2 * 64, WPT = (NWF + 511) / 512;
-  bf16x8_t pw[WPT];
-  auto fetch_weights = [&](int layer) {
-#pragma unroll
-    for (int j = 0; j < WPT; ++j) {
-      const int i = tid + 512 * j;
-      if (i < NWF) pw[j] = i < NWF / 2 ? whi[(layer - 2) * (NWF / 2) + i] : wlo[(layer - 2) * (NWF / 2) + i - NWF / 2];
-    }
-  };
-  fetch_weights(2);
-  // layer 1's A operands (hi and lo, both 16-channel row tiles), built once:
-  // lane (g, r) of tile m holds channel 16m + r, slot e = (dx = e / 2,
-  // input channel e % 2) of kernel row g; zero in the padding slots
-  bf16x8_t w1h[2], w1l[2];
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float v = (g < 3 && e < 6) ? w[HS_W1 + ((16 * m + r) * 2 + (e & 1)) * 9 + g * 3 + (e >> 1)] : 0.0f;
-      const __bf16 h = (__bf16)v;
-      w1h[m][e] = h;
-      w1l[m][e] = (__bf16)(v - (float)h);
-    }
-  // the segments are concatenated into one sequence dealt in CB-cone
-  // batches to the blocks; wave 0 scans the counts (per lane a chunk of
-  // consecutive segments, then a wave-wide scan of the chunk sums)
-  if (wave == 0) {
-    constexpr int PER = (SPLIT_MAXSEG + 63) / 64;
-    int cs = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int q = lane * PER + j;
-      cs += q < nseg ? seg_count[q] : 0;
-    }
-    int incl = cs;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int v = __shfl_up(incl, d);
-      if (lane >= d) incl += v;
-    }
-    int run = incl - cs;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int q = lane * PER + j;
-      if (q <= nseg) spre[q] = run;
-      run += q < nseg ? seg_count[q] : 0;
-    }
-  }
-  __syncthreads();
-  const int total = spre[nseg];
-  for (int base = blockIdx.x * CB; base < total; base += gridDim.x * CB) {
-    const int ncone = total - base < CB ? total - base : CB;
-    __syncthreads();
-    if (tid < ncone) {  // segment of entry base + tid: the last with spre <= entry
-      const int e = base + tid;
-      int lo = 0, hi = nseg - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (spre[mid] <= e) lo = mid;
-        else hi = mid - 1;
-      }
-      const uint32_t o = seglist[(size_t)lo * seg_cap + (e - spre[lo])];
-      list[tid] = o;
-      const int b = (int)(o / ((uint32_t)H * W));
-      const int rem = (int)(o - (uint32_t)b * H * W);
-      cone_byx[tid][0] = b;
-      cone_byx[tid][1] = rem / W;
-      cone_byx[tid][2] = rem - (rem / W) * W;
-    }
-    __syncthreads();
-    // stage the 13 x 13 state (c, z) of each cone, zero outside the image
-    for (int i = tid; i < CB * 169; i += 512) {
-      const int cidx = i / 169, q = i - cidx * 169;
-      float cv = 0.f, zv = 0.f;
-      if (cidx < ncone) {
-        const int b = cone_byx[cidx][0], y = cone_byx[cidx][1], x = cone_byx[cidx][2];
-        const int gy = y - 6 + q / 13, gx = x - 6 + q % 13;
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-          const uint64_t a = (uint64_t)gy * W + gx;
-          cv = contone[(size_t)b * H * W + a];
-          zv = hs_noise(seeds[b], a, 0u, kind);
-        }
-      }
-      s0[cidx][q * 2] = cv;
-      s0[cidx][q * 2 + 1] = zv;
-    }
-    __syncthreads();
-    // layer 1 on the matrix cores, split BF16 like layers 2..5: K = 9 taps x
-    // 2 channels with lane group g = kernel row dy and slot e = (dx = e / 2,
-    // channel e % 2), so a lane's operand is six consecutive (c, z) floats;
-    // outputs stored split in the ring channel order
-    for (int job = wave; job < CB * 8; job += 8) {
-      const int cidx = job >> 3, run = job & 7;
-      const int pos = run * 16 + r;
-      const int pi = pos < 121 ? pos / 11 : 0, pj = pos < 121 ? pos - pi * 11 : 0;
-      const float* sp = &s0[cidx][((pi + (g < 3 ? g : 2)) * 13 + pj) * 2];
-      bf16x8_t bh, bl;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float v = e < 6 ? sp[e] : 0.0f;
-        const __bf16 h = (__bf16)v;
-        bh[e] = h;
-        bl[e] = (__bf16)(v - (float)h);
-      }
-      f32x4_t acc1[2];
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const f32x4_t z4 = {0.f, 0.f, 0.f, 0.f};
-        const f32x4_t p0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1h[m], bh, z4, 0, 0, 0);
-        const f32x4_t p1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1l[m], bh, z4, 0, 0, 0);
-        const f32x4_t p2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1h[m], bl, z4, 0, 0, 0);
-        acc1[m] = p0 + (p1 + p2);
-      }
-      if (pos < 121 && cidx < ncone) {
-        const int y = cone_byx[cidx][1], x = cone_byx[cidx][2];
-        const int gy = y - 5 + pi, gx = x - 5 + pj;
-        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-        bf16x8_t vh, vl;
-#pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float v = in ? fmaxf(acc1[m][i] + sw1[HS_B1 + 16 * m + 4 * g + i], 0.f) : 0.f;
-            const __bf16 h = (__bf16)v;
-            vh[4 * m + i] = h;
-            vl[4 * m + i] = (__bf16)(v - (float)h);
-          }
-        char* rec = bufA[cidx] + pos * CREC;
-        *(bf16x8_t*)(rec + crec_slot(pos, 2 * g) * 16) = vh;
-        *(bf16x8_t*)(rec + crec_slot(pos, 2 * g + 1) * 16) = vl;
-      }
-    }
-    // layers 2..5 on the matrix cores
-    for (int k = 2; k <= 5; ++k) {
-      const int e_out = 13 - 2 * k, e_in = e_out + 2, npos = e_out * e_out;
-      const int runs = (npos + 15) / 16;
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < WPT; ++j) {
-        const int i = tid + 512 * j;
-        if (i < NWF / 2) swh[i] = pw[j];
-        else if (i < NWF) swl[i - NWF / 2] = pw[j];
-      }
-      fetch_weights(k == 5 ? 2 : k + 1);  // in flight during this layer
-      __syncthreads();
-      const bool from_a = (k & 1) == 0;  // layer 2 reads A, 3 reads B, ...
-      float bk[2][4];
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) bk[m][i] = w[hs_bk(k) + 16 * m + 4 * g + i];
-      // jobs (cone, 16-position run) are dealt to the eight waves; the tap loop
-      // is outermost so each tap's weight fragments are read once per wave
-      constexpr int MAXJ = 3;  // layer 2: 4 cones x 6 runs over 8 waves
-      const int njob = CB * runs;
-      // the three products hi*hi, lo*hi, hi*lo accumulate separately (three
-      // independent MFMA chains) and are summed at the end
-      f32x4_t acc[MAXJ][2], acl[MAXJ][2], ach[MAXJ][2];
-      int jq[MAXJ];
-#pragma unroll
-      for (int j = 0; j < MAXJ; ++j) {
-        acc[j][0] = acc[j][1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-        acl[j][0] = acl[j][1] = ach[j][0] = ach[j][1] = acc[j][0];
-        const int job = wave + 8 * j;
-        const int run = job < njob ? job % runs : 0;
-        const int pos = run * 16 + r;
-        const int pi = pos < npos ? pos / e_out : 0, pj = pos < npos ? pos - pi * e_out : 0;
-        jq[j] = pi * e_in + pj;  // input position of tap (0, 0)
-      }
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const bf16x8_t ah0 = swh[(t * 2 + 0) * 64 + lane], al0 = swl[(t * 2 + 0) * 64 + lane];
-        const bf16x8_t ah1 = swh[(t * 2 + 1) * 64 + lane], al1 = swl[(t * 2 + 1) * 64 + lane];
-#pragma unroll
-        for (int j = 0; j < MAXJ; ++j) {
-          const int job = wave + 8 * j;
-          if (job < njob) {
-            const int cidx = job / runs;
-            const char* src = from_a ? bufA[cidx] : bufB[cidx];
-            const int q = jq[j] + (t / 3) * e_in + t % 3;
-            const char* rec = src + q * CREC;
-            const bf16x8_t bh = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g) * 16);
-            const bf16x8_t bl = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g + 1) * 16);
-            acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, acc[j][0], 0, 0, 0);
-            acl[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, acl[j][0], 0, 0, 0);
-            ach[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, ach[j][0], 0, 0, 0);
-            acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, acc[j][1], 0, 0, 0);
-            acl[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, acl[j][1], 0, 0, 0);
-            ach[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, ach[j][1], 0, 0, 0);
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < MAXJ; ++j)
-#pragma unroll
-        for (int m = 0; m < 2; ++m) acc[j][m] += acl[j][m] + ach[j][m];
-#pragma unroll
-      for (int j = 0; j < MAXJ; ++j) {
-        const int job = wave + 8 * j;
-        if (job >= njob) continue;
-        const int cidx = job / runs, run = job - cidx * runs;
-        char* dst = from_a ? bufB[cidx] : bufA[cidx];
-        const int pos = run * 16 + r;
-        const int pi = pos < npos ? pos / e_out : 0, pj = pos < npos ? pos - pi * e_out : 0;
-        if (pos < npos && cidx < ncone) {
-          const int y = cone_byx[cidx][1], x = cone_byx[cidx][2];
-          const int gy = y - (6 - k) + pi, gx = x - (6 - k) + pj;
-          const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-          float v[2][4];
-#pragma unroll
-          for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[m][i] = in ? fmaxf(acc[j][m][i] + bk[m][i], 0.f) : 0.f;
-          if (k == 5) {  // keep layer 5 in FP32 for the head
-#pragma unroll
-            for (int m = 0; m < 2; ++m)
-#pragma unroll
-              for (int i = 0; i < 4; ++i) l5f[cidx][pos * 32 + 16 * m + 4 * g + i] = v[m][i];
-          } else {
-            bf16x8_t vh, vl;
-#pragma unroll
-            for (int m = 0; m < 2; ++m)
-#pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const __bf16 h = (__bf16)v[m][i];
-                vh[4 * m + i] = h;
-                vl[4 * m + i] = (__bf16)(v[m][i] - (float)h);
-              }
-            char* rec = dst + pos * CREC;
-            *(bf16x8_t*)(rec + crec_slot(pos, 2 * g) * 16) = vh;
-            *(bf16x8_t*)(rec + crec_slot(pos, 2 * g + 1) * 16) = vl;
-          }
-        }
-      }
-    }
-    __syncthreads();
-    // layer 6 in FP32, one wave per cone
-    if (wave < ncone) {
-      float part = 0.f;
-      for (int i = lane; i < 288; i += 64) {
-        const int ci = i / 9, t = i % 9;
-        part = fmaf(w[HS_W6 + i], l5f[wave][t * 32 + ci], part);
-      }
-      part = hs_wave_sum(part);
-      if (lane == 0) {
-        const uint32_t o = list[wave];
-        const float xl = part + w[HS_B6];
-        if (fabsf(xl) >= tau2) {
-          const uint8_t nb = xl >= 0.f ? 1 : 0;
-          if (bits[o] != nb) atomicAdd(&stats[1], 1);
-          bits[o] = nb;
-          if (logits) logits[o] = xl;
-        } else {
-          list2[atomicAdd(count2, 1)] = o;
-        }
-      }
-    }
-  }
-  if (blockIdx.x == 0 && tid == 0) stats[0] = total;
-}
-
-}  // namespace
-
-namespace hs {
-
-// bytes of the hi and the lo copy together (each 4 layers x 9 taps x 2 row
-// tiles x 64 lanes x 8 BF16 values)
-size_t split_frag_bytes() { return 2 * (size_t)(4 * 9 * 2 * 64 * 8) * sizeof(__bf16); }
-
-hipError_t launch_split_pack(const float* w, void* whi, void* wlo, hipStream_t s) {
-  pack_split_kernel<<<36, 256, 0, s>>>(w, (__bf16*)whi, (__bf16*)wlo);
-  return hipGetLastError();
-}
-
-hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
-                                int H, int W, int kind, const uint32_t* seglist,
-                                const int* seg_count, int nseg, long long seg_cap,
-                                const void* whi, const void* wlo, float tau2, uint32_t* list2,
-                                int* count2, uint8_t* bits, float* logits, int32_t* stats,
-                                int num_cus, hipStream_t s) {
-  if (nseg < 1 || nseg > SPLIT_MAXSEG) return hipErrorInvalidValue;
-  recheck_split_kernel<<<num_cus, 512, 0, s>>>(w, contone, seeds, H, W, kind, seglist, seg_count,
-                                               nseg, seg_cap,
-                                               (const bf16x8_t*)whi, (const bf16x8_t*)wlo, tau2,
-                                               list2, count2, bits, logits, stats);
-  return hipGetLastError();
-}
-
-}  // namespace hs

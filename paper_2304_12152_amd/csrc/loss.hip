@@ -36,6 +36,7 @@ constexpr int LS = LT + 2 * MAXR;
 struct LossConst {
   int rh, rs, m;
   float k, c1, c2, w_s;
+  int est;
 };
 
 __global__ __launch_bounds__(256) void loss_stats_kernel(const uint8_t* __restrict__ h,
@@ -161,8 +162,9 @@ __global__ void loss_reduce_kernel(const float* __restrict__ partials, int B, in
 
 __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict__ h,
                                                       const float* __restrict__ c,
-                                                      const float* __restrict__ probs, int B,
-                                                      int H, int W, LossConst q,
+                                                      const float* __restrict__ probs,
+                                                      int logit_space, int B, int H, int W,
+                                                      LossConst q,
                                                       const hs::LossDev win,
                                                       const float* __restrict__ maps, float invM,
                                                       float* __restrict__ grad) {
@@ -242,7 +244,17 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
   }
   const float dR = delta * (-dmse * invM + q.w_s * dcs * invM);
   float gv = -dR / (float)B;
-  if (probs) gv *= probs[oa] * (1.0f - probs[oa]);
+  if (q.est == HS_EST_COMA) {
+    // score function times (R(h) - b_a) = (h_a ? (1 - p) : -p) dR: in logit
+    // space (h_a - p)(R(h) - b_a), in probability space divided by p (h_a = 1)
+    // or 1 - p (h_a = 0); a sampled h_a = 1 implies p > 0 and h_a = 0, p < 1
+    const float pa = probs[oa];
+    const bool one = h[oa] != 0;
+    if (logit_space) gv *= one ? (1.0f - pa) * (1.0f - pa) : pa * pa;
+    else gv *= one ? (1.0f - pa) / pa : pa / (1.0f - pa);
+  } else if (logit_space) {
+    gv *= probs[oa] * (1.0f - probs[oa]);
+  }
   grad[oa] = gv;
 }
 
@@ -425,6 +437,7 @@ static LossConst make_const(const hs_loss_params& p) {
   q.c1 = p.c1;
   q.c2 = p.c2;
   q.w_s = p.w_s;
+  q.est = p.estimator;
   return q;
 }
 
@@ -447,13 +460,13 @@ hipError_t launch_loss_reduce(const float* tile_partials, int B, int ntiles_per_
   return hipGetLastError();
 }
 
-hipError_t launch_le_grad(const uint8_t* h, const float* c, const float* probs, int B, int H,
-                          int W, const hs_loss_params& p, const LossDev& win, const float* maps,
-                          float* grad, hipStream_t s) {
+hipError_t launch_le_grad(const uint8_t* h, const float* c, const float* probs, int logit_space,
+                          int B, int H, int W, const hs_loss_params& p, const LossDev& win,
+                          const float* maps, float* grad, hipStream_t s) {
   const LossConst q = make_const(p);
   const long M = (long)(H - 2 * q.m) * (W - 2 * q.m);
   const dim3 grid((W + LT - 1) / LT, (H + LT - 1) / LT, B);
-  le_grad_kernel<<<grid, 256, 0, s>>>(h, c, probs, B, H, W, q, win, maps,
+  le_grad_kernel<<<grid, 256, 0, s>>>(h, c, probs, logit_space, B, H, W, q, win, maps,
                                       (float)(1.0 / (double)M), grad);
   return hipGetLastError();
 }

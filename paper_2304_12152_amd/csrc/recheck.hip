@@ -1,0 +1,687 @@
+// recheck.hip -- the exact decision of near-threshold pixels (the TEST
+// procedure of Algorithm 1 at p = 0.5) after the fused BF16 pass.
+//
+// A listed pixel is recomputed over its 13 x 13 receptive field only: layer
+// k is evaluated on the (13 - 2k) x (13 - 2k) window centred on the pixel
+// (its "cone"), with every activation outside the image forced to zero (the
+// zero 'same' padding of each layer). Two stages:
+//   split stage  every pixel the fused pass listed (|x_bf16| < tau); layers
+//                1..5 with split-BF16 products on the matrix cores, layer 6
+//                in FP32. Pixels with |x| >= tau2 are decided here, the
+//                rest listed again.
+//   FP32 stage   the pixels listed by the split stage, in plain FP32.
+#include "hs_common.h"
+#include "hs_internal.h"
+
+namespace {
+
+// ===========================================================================
+// Split stage. Every FP32 value v is carried as hi + lo with hi = bf16(v)
+// and lo = bf16(v - hi); a product is taken as hi*hi' + lo*hi' + hi*lo'
+// (lo*lo', ~2^-16 relative, is dropped), each of the three in its own FP32
+// accumulator. The result's error is ~2^-8 of the BF16 pass's.
+//
+// The kernel is a pipeline over the listed pixels, one cone per step. Each
+// wave owns one layer (its hi weight fragments stay in registers for the
+// whole kernel, the lo fragments of all four layers sit in LDS) and up to two
+// of that layer's 16-position runs, which it computes together (twelve
+// independent MFMA chains, the next tap's operands loaded while a tap's
+// MFMAs run). In step t the stage of
+// layer k works on cone t - k:
+//   stage 0    the (c, z) state of the 13 x 13 window (z drawn from Philox
+//              exactly as the fused pass drew it)
+//   stage 1-5  layers 1..5 (layer 5's output kept in FP32)
+//   stage 6    layer 6 in FP32 and the decision
+// Stage k reads the buffer stage k-1 wrote in the previous step and writes
+// its own; every buffer has two slots (cone parity), so one barrier per step
+// orders all of it. The barrier orders LDS only: the global loads issued for
+// a later step (list entries, window values) stay in flight across it.
+//
+// Waves (w and w+4 share a SIMD), balanced by their measured step times:
+//   w0, w1, w2  layer 2, runs 0-1 / 2-3 / 4-5; layer 1, run 0 / 1 / 2
+//   w3          layer 3, runs 0-1; staging of window positions 0-63; layer 6
+//   w4          layer 3, runs 2-3
+//   w5          layer 4, runs 0-1
+//   w6          layer 5, run 0; layer 1, runs 3-5
+//   w7          layer 1, runs 6-7; staging of positions 64-168; the cone list
+// (a layer-1 run is 6 MFMAs; a layer-2..5 run 54)
+// ===========================================================================
+constexpr int SPLIT_MAXSEG = 1024;    // list segments the stage accepts
+constexpr int CREC = 128;             // bytes per staged position: 4 groups x (hi, lo) x 16 B
+constexpr int NSTAGE = 7;             // staging, layers 1..5, layer 6
+constexpr int SPLIT_THREADS = 512;
+
+HS_DEV int crec_slot(int p, int c) { return c ^ (p & 7); }  // bank-spreading swizzle
+
+// A list entry is a pixel index (< 2^31) with the bit decided so far in its
+// top bit.
+constexpr uint32_t BIT_FLAG = 0x80000000u;
+
+constexpr int win_edge(int k) { return 13 - 2 * k; }           // layer k's output window edge
+constexpr int win_pos(int k) { return win_edge(k) * win_edge(k); }
+constexpr int win_runs(int k) { return (win_pos(k) + 15) / 16; }
+static_assert(win_runs(1) == 8 && win_runs(2) == 6 && win_runs(3) == 4 && win_runs(4) == 2 &&
+                  win_runs(5) == 1,
+              "wave roles assume these run counts");
+
+__global__ void pack_split_kernel(const float* __restrict__ w, __bf16* __restrict__ hi,
+                                  __bf16* __restrict__ lo) {
+  // layers 2..5 in the ring channel order: [layer][tap][m][lane][8]
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 4 * 9 * 2 * 64 * 8;
+       i += gridDim.x * blockDim.x) {
+    const int e = i & 7, l = (i >> 3) & 63, m = (i >> 9) & 1, t = (i >> 10) % 9,
+              layer = (i >> 10) / 9;
+    const int g = l >> 4, r = l & 15;
+    const float v = w[hs_wk(layer + 2) + ((16 * m + r) * 32 + hs_ring_channel(g, e)) * 9 + t];
+    const __bf16 h = (__bf16)v;
+    hi[i] = h;
+    lo[i] = (__bf16)(v - (float)h);
+  }
+}
+
+struct SplitArgs {
+  const float* w;
+  const float* contone;
+  const uint64_t* seeds;
+  int H, W, kind, nseg;
+  const uint32_t* seglist;
+  const int* seg_count;
+  long long seg_cap;
+  const bf16x8_t* whi;
+  const bf16x8_t* wlo;
+  float tau2;
+  uint32_t* list2;
+  int* count2;
+  uint8_t* bits;
+  float* logits;
+  int32_t* stats;
+};
+
+struct SplitSmem {
+  __attribute__((aligned(16))) float s0[2][169 * 2];  // (c, z) of the 13 x 13 window
+  __attribute__((aligned(16))) char b1[2][121 * CREC];  // layer outputs, split BF16
+  __attribute__((aligned(16))) char b2[2][81 * CREC];
+  __attribute__((aligned(16))) char b3[2][49 * CREC];
+  __attribute__((aligned(16))) char b4[2][25 * CREC];
+  float l5[2][9 * 32];                                   // layer 5 in FP32
+  bf16x8_t wlo[4][9][2][64];                             // layers 2..5, lo parts
+  bf16x8_t w1[2][2][64];                                 // layer 1: [hi, lo][m][lane]
+  float w6[288];                                         // layer 6, [channel][tap]
+  __attribute__((aligned(16))) float b1v[32];           // layer 1 bias
+  int spre[SPLIT_MAXSEG + 1];                            // exclusive prefix of the segment counts
+  int cinfo[16][5];  // per cone: pixel (-1: none), image, row, column, bit of the fused pass
+};
+
+HS_DEV void split_store(char* rec_base, int p, int g, const float (&v)[2][4]) {
+  bf16x8_t vh, vl;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const __bf16 h = (__bf16)v[m][i];
+      vh[4 * m + i] = h;
+      vl[4 * m + i] = (__bf16)(v[m][i] - (float)h);
+    }
+  char* rec = rec_base + p * CREC;
+  *(bf16x8_t*)(rec + crec_slot(p, 2 * g) * 16) = vh;
+  *(bf16x8_t*)(rec + crec_slot(p, 2 * g + 1) * 16) = vl;
+}
+
+// Layer K (2..5) on runs run0 .. run0 + NR - 1 of one cone (ci); src / dst
+// are the cone's input and output slots.
+template <int K, int NR>
+HS_DEV void split_layer(const bf16x8_t (&wh)[9][2], const bf16x8_t (*wl)[2][64],
+                        const f32x4_t (&bias)[2], const char* src, char* dst, float* dst5,
+                        const int* ci, int run0, int H, int W, int lane) {
+  constexpr int EO = win_edge(K), EI = EO + 2, NP = EO * EO;
+  const int g = lane >> 4, r = lane & 15;
+  int ln = lane;
+  asm volatile("" : "+v"(ln));
+  int p[NR], q0[NR];
+  f32x4_t a0[NR][2], a1[NR][2], a2[NR][2];
+  // the per-tap LDS addresses are recomputed in every call (a few VALU
+  // operations) rather than hoisted out of the step loop, where they would
+  // occupy registers for the whole kernel; the empty asm hides q0's value
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const int P = (run0 + j) * 16 + r;
+    p[j] = P < NP ? P : -1;
+    const int pp = P < NP ? P : 0;
+    q0[j] = (pp / EO) * EI + pp % EO;
+    asm volatile("" : "+v"(q0[j]));
+#pragma unroll
+    for (int m = 0; m < 2; ++m) a0[j][m] = a1[j][m] = a2[j][m] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  }
+  // the operands of tap t + 1 are loaded while tap t's MFMAs run; the
+  // scheduling barrier at the end of each tap keeps the compiler from
+  // hoisting every tap's loads to the top (which would exhaust the registers)
+  bf16x8_t bh[2][NR], bl[2][NR], wlo[2][2];
+  auto load_tap = [&](int t, int s) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      const int q = q0[j] + (t / 3) * EI + t % 3;
+      const char* rec = src + q * CREC;
+      bh[s][j] = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g) * 16);
+      bl[s][j] = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g + 1) * 16);
+    }
+    wlo[s][0] = wl[t][0][ln];
+    wlo[s][1] = wl[t][1][ln];
+  };
+  load_tap(0, 0);
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int s = t & 1;
+    if (t < 8) load_tap(t + 1, s ^ 1);
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        a0[j][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[t][m], bh[s][j], a0[j][m], 0, 0, 0);
+        a1[j][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo[s][m], bh[s][j], a1[j][m], 0, 0, 0);
+        a2[j][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[t][m], bl[s][j], a2[j][m], 0, 0, 0);
+      }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const bool cone = ci[0] >= 0;
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    if (p[j] < 0) continue;
+    const int pi = p[j] / EO, pj = p[j] % EO;
+    const int gy = ci[2] - (6 - K) + pi, gx = ci[3] - (6 - K) + pj;
+    const bool in_img = cone && gy >= 0 && gy < H && gx >= 0 && gx < W;
+    float v[2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const f32x4_t s = a0[j][m] + (a1[j][m] + a2[j][m]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[m][i] = in_img ? fmaxf(s[i] + bias[m][i], 0.f) : 0.f;
+    }
+    if (K < 5) {
+      split_store(dst, p[j], g, v);
+    } else {
+      float* d = dst5 + p[j] * 32;
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) d[16 * m + 4 * g + i] = v[m][i];
+    }
+  }
+}
+
+__global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitArgs a) {
+  __shared__ SplitSmem sm;
+  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, r = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int H = a.H, W = a.W;
+  // ---- wave roles (see the table above); wave 7 owns no layer
+  const int K = wave < 3 ? 2 : wave < 5 ? 3 : wave == 5 ? 4 : wave == 6 ? 5 : 0;
+  const int run0 = (wave < 3) ? 2 * wave : (wave == 4) ? 2 : 0;
+  const bool stager = wave == 3 || wave == 7;
+  // the owned layer's hi A operands and biases, for the whole kernel; the
+  // lo A operands of all four layers in LDS
+  bf16x8_t wh[9][2];
+  f32x4_t bias[2];
+  for (int i = tid; i < 4 * 9 * 2 * 64; i += SPLIT_THREADS) (&sm.wlo[0][0][0][0])[i] = a.wlo[i];
+  {
+    const int kk = K ? K : 2;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) wh[t][m] = a.whi[(((kk - 2) * 9 + t) * 2 + m) * 64 + lane];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bias[m][i] = a.w[hs_bk(kk) + 16 * m + 4 * g + i];
+  }
+  // layer 1's A operands in LDS: K = 9 taps x 2 channels, lane group g =
+  // kernel row, slot e = (dx = e / 2, channel e % 2); zero in the padding slots
+  if (wave < 2) {
+    const int m = wave;
+    bf16x8_t vh, vl;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float v =
+          (g < 3 && e < 6) ? a.w[HS_W1 + ((16 * m + r) * 2 + (e & 1)) * 9 + g * 3 + (e >> 1)] : 0.0f;
+      const __bf16 h = (__bf16)v;
+      vh[e] = h;
+      vl[e] = (__bf16)(v - (float)h);
+    }
+    sm.w1[0][m][lane] = vh;
+    sm.w1[1][m][lane] = vl;
+  }
+  if (tid < 32) sm.b1v[tid] = a.w[HS_B1 + tid];
+  // ---- concatenate the segments: wave 0 scans the counts (per lane a
+  // chunk of consecutive segments, then a wave-wide scan of the chunk sums)
+  if (wave == 0) {
+    constexpr int PER = (SPLIT_MAXSEG + 63) / 64;
+    int cs = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int q = lane * PER + j;
+      cs += q < a.nseg ? a.seg_count[q] : 0;
+    }
+    int incl = cs;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    int run = incl - cs;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int q = lane * PER + j;
+      if (q <= a.nseg) sm.spre[q] = run;
+      run += q < a.nseg ? a.seg_count[q] : 0;
+    }
+  }
+  __syncthreads();
+  const int total = sm.spre[a.nseg];
+  const int cb0 = (int)((long long)blockIdx.x * total / gridDim.x);
+  const int cb1 = (int)((long long)(blockIdx.x + 1) * total / gridDim.x);
+  const int nloc = cb1 - cb0;
+  if (blockIdx.x == 0 && tid == 0) a.stats[0] = total;
+  if (nloc <= 0) return;  // uniform over the block
+
+  // Cone i's coordinates go to cinfo[i % 16] (wave 7, lane 0). Its list
+  // entry is loaded one step before it is decoded, and its window values one
+  // step before they are staged, so no wave waits on global memory inside a
+  // step.
+  // the segment of entry e is the last with spre <= e; entries are taken in
+  // order, so the segment pointer only moves forward
+  int seg = 0;
+  auto load_entry = [&](int i) -> uint32_t {
+    const int e = cb0 + i;
+    while (seg + 1 < a.nseg && sm.spre[seg + 1] <= e) ++seg;
+    return a.seglist[(size_t)seg * a.seg_cap + (e - sm.spre[seg])];
+  };
+  auto put_cone = [&](int i, uint32_t u) {
+    int* d = sm.cinfo[i & 15];
+    if (i >= nloc) {
+      d[0] = -1;
+      d[1] = d[2] = d[3] = d[4] = 0;
+      return;
+    }
+    const uint32_t o = u & ~BIT_FLAG;
+    const int b = (int)(o / ((uint32_t)H * W));
+    const int rem = (int)(o - (uint32_t)b * H * W);
+    d[0] = (int)o;
+    d[1] = b;
+    d[2] = rem / W;
+    d[3] = rem - (rem / W) * W;
+    d[4] = (u & BIT_FLAG) ? 1 : 0;
+  };
+  // staging: window position j = lane (wave 3), 64 + lane + 64 k (wave 7);
+  // the contone values and the image seed are loaded a step ahead
+  constexpr int NSTG = 2;
+  auto stage_pos = [&](int k) { return wave == 3 ? (k == 0 ? lane : 999) : 64 + lane + 64 * k; };
+  float pcv[NSTG];
+  uint64_t psd = 0;
+  auto prefetch_window = [&](int i) {
+    const int* ci = sm.cinfo[i & 15];
+#pragma unroll
+    for (int k = 0; k < NSTG; ++k) {
+      const int j = stage_pos(k);
+      pcv[k] = 0.f;
+      if (j < 169 && i < nloc) {
+        const int gy = ci[2] - 6 + j / 13, gx = ci[3] - 6 + j % 13;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+          pcv[k] = a.contone[((size_t)ci[1] * H + gy) * W + gx];
+      }
+    }
+    if (i < nloc && ci[0] >= 0) psd = a.seeds[ci[1]];
+  };
+  for (int i = tid; i < 288; i += SPLIT_THREADS) sm.w6[i] = a.w[HS_W6 + i];
+  const float b6 = a.w[HS_B6];
+  // prologue: cones 0..2 decoded, cone 3's entry in flight, cone 0's window
+  // values in flight
+  uint32_t pend_u = 0;
+  if (wave == 7 && lane == 0) {
+    for (int i = 0; i < 3; ++i) put_cone(i, i < nloc ? load_entry(i) : 0u);
+    if (3 < nloc) pend_u = load_entry(3);
+  }
+  __syncthreads();
+  if (stager) prefetch_window(0);
+
+  for (int t = 0; t < nloc + NSTAGE - 1; ++t) {
+    // ---- stage 0: the (c, z) window of cone t from the prefetched values,
+    // then the loads of cone t + 1's window
+    if (stager) {
+      if (t < nloc) {
+        const int* ci = sm.cinfo[t & 15];
+#pragma unroll
+        for (int k = 0; k < NSTG; ++k) {
+          const int j = stage_pos(k);
+          if (j < 169) {
+            const int gy = ci[2] - 6 + j / 13, gx = ci[3] - 6 + j % 13;
+            float zv = 0.f;
+            if (ci[0] >= 0 && gy >= 0 && gy < H && gx >= 0 && gx < W)
+              zv = hs_noise(psd, (uint64_t)gy * W + gx, 0u, a.kind);
+            sm.s0[t & 1][j * 2] = pcv[k];
+            sm.s0[t & 1][j * 2 + 1] = zv;
+          }
+        }
+      }
+      prefetch_window(t + 1);
+    }
+    // ---- cone t + 3 decoded, cone t + 4's entry loaded
+    if (wave == 7 && lane == 0) {
+      put_cone(t + 3, pend_u);
+      if (t + 4 < nloc) pend_u = load_entry(t + 4);
+    }
+    // ---- stage 1: layer 1 of cone t - 1, one run at a time (waves 0-2 one
+    // run each, wave 6 three, wave 7 two)
+    const int l1run0 = wave < 3 ? wave : wave == 6 ? 3 : 6;
+    const int l1runs = wave < 3 ? 1 : wave == 6 ? 3 : wave == 7 ? 2 : 0;
+    if (l1runs && t >= 1 && t - 1 < nloc) {
+      const int i = t - 1, sl = i & 1;
+      const int* ci = sm.cinfo[i & 15];
+      const bool cone = ci[0] >= 0;
+      const bf16x8_t ah0 = sm.w1[0][0][lane], al0 = sm.w1[1][0][lane];
+      const bf16x8_t ah1 = sm.w1[0][1][lane], al1 = sm.w1[1][1][lane];
+      const f32x4_t bb0 = *(const f32x4_t*)&sm.b1v[4 * g];
+      const f32x4_t bb1 = *(const f32x4_t*)&sm.b1v[16 + 4 * g];
+      for (int run = l1run0; run < l1run0 + l1runs; ++run) {
+        const int P = run * 16 + r;
+        const int p = P < 121 ? P : 0;
+        const int pi = p / 11, pj = p - (p / 11) * 11;
+        // six consecutive floats: (c, z) of columns pj .. pj + 2 of row pi + dy
+        const f32x2_t* sp = (const f32x2_t*)&sm.s0[sl][((pi + (g < 3 ? g : 2)) * 13 + pj) * 2];
+        const f32x2_t v0 = sp[0], v1 = sp[1], v2 = sp[2];
+        const float vv[8] = {v0[0], v0[1], v1[0], v1[1], v2[0], v2[1], 0.f, 0.f};
+        bf16x8_t bh, bl;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const __bf16 h = (__bf16)vv[e];
+          bh[e] = h;
+          bl[e] = (__bf16)(vv[e] - (float)h);
+        }
+        const f32x4_t z4 = {0.f, 0.f, 0.f, 0.f};
+        const f32x4_t s0v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, z4, 0, 0, 0) +
+                            (__builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, z4, 0, 0, 0) +
+                             __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, z4, 0, 0, 0));
+        const f32x4_t s1v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, z4, 0, 0, 0) +
+                            (__builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, z4, 0, 0, 0) +
+                             __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, z4, 0, 0, 0));
+        const int gy = ci[2] - 5 + pi, gx = ci[3] - 5 + pj;
+        const bool in_img = cone && gy >= 0 && gy < H && gx >= 0 && gx < W;
+        float v[2][4];
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          v[0][ii] = in_img ? fmaxf(s0v[ii] + bb0[ii], 0.f) : 0.f;
+          v[1][ii] = in_img ? fmaxf(s1v[ii] + bb1[ii], 0.f) : 0.f;
+        }
+        if (P < 121) split_store(sm.b1[sl], p, g, v);
+      }
+    }
+    // ---- stages 2..5: the owned layer on cone t - K
+    if (K) {
+      const int i = t - K;
+      if (i >= 0 && i < nloc) {
+        const int sl = i & 1;
+        const int* ci = sm.cinfo[i & 15];
+        switch (K) {
+          case 2:
+            split_layer<2, 2>(wh, sm.wlo[0], bias, sm.b1[sl], sm.b2[sl], nullptr, ci, run0, H, W,
+                                lane);
+            break;
+          case 3:
+            split_layer<3, 2>(wh, sm.wlo[1], bias, sm.b2[sl], sm.b3[sl], nullptr, ci, run0, H, W,
+                                lane);
+            break;
+          case 4:
+            split_layer<4, 2>(wh, sm.wlo[2], bias, sm.b3[sl], sm.b4[sl], nullptr, ci, run0, H, W,
+                                lane);
+            break;
+          default:
+            split_layer<5, 1>(wh, sm.wlo[3], bias, sm.b4[sl], nullptr, sm.l5[sl], ci, run0, H, W,
+                              lane);
+            break;
+        }
+      }
+    }
+    // ---- stage 6 (wave 3): layer 6 in FP32 and the decision
+    if (wave == 3 && t >= 6 && t - 6 < nloc) {
+      const int i = t - 6;
+      const int* ci = sm.cinfo[i & 15];
+      const int o = ci[0];
+      if (o >= 0) {
+        const float* l5 = sm.l5[i & 1];
+        float part = 0.f;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const int j = lane + 64 * k;
+          if (j < 288) part = fmaf(sm.w6[j], l5[(j % 9) * 32 + j / 9], part);
+        }
+        part = hs_wave_sum(part);
+        if (lane == 0) {
+          const float xl = part + b6;
+          if (fabsf(xl) >= a.tau2) {
+            const int nb = xl >= 0.f ? 1 : 0;
+            if (ci[4] != nb) atomicAdd(&a.stats[1], 1);
+            a.bits[o] = (uint8_t)nb;
+            if (a.logits) a.logits[o] = xl;
+          } else {
+            a.list2[atomicAdd(a.count2, 1)] = (uint32_t)o | (ci[4] ? BIT_FLAG : 0u);
+          }
+        }
+      }
+    }
+    hs_lds_barrier();
+  }
+}
+
+// ===========================================================================
+// FP32 stage: one workgroup per listed pixel (grid-stride over the list,
+// whose length is read on the device). Layer k's window outputs are
+// register-blocked: thread (cg, pg) computes channels 4cg..4cg+3 of the
+// window positions pg, pg + 32, ..., so each weight quad read from LDS
+// feeds several positions and each activation read feeds four channels.
+// The next layer's weights are loaded into registers while a layer computes.
+// ===========================================================================
+constexpr int RS = 33;  // padded channel stride of a staged position (floats)
+constexpr int F32_THREADS = 256;
+constexpr int F32_LAYER = 9 * 32 * 32;                // weights of one 32 -> 32 layer
+constexpr int F32_VPT = F32_LAYER / 4 / F32_THREADS;  // 16-byte vectors per thread per layer
+
+// layers 2..5 as [layer][tap][ci][co] FP32, so a thread's four output
+// channels are one 16-byte read
+__global__ void pack_fp32_kernel(const float* __restrict__ w, float* __restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 4 * F32_LAYER;
+       i += gridDim.x * blockDim.x) {
+    const int layer = i / F32_LAYER, rem = i - layer * F32_LAYER;
+    const int t = rem / 1024, ci = (rem >> 5) & 31, co = rem & 31;
+    out[i] = w[hs_wk(layer + 2) + (co * 32 + ci) * 9 + t];
+  }
+}
+
+template <int K>
+HS_DEV void fp32_layer(const float* __restrict__ src, float* __restrict__ dst,
+                       const float* __restrict__ sw, const float* __restrict__ sb, int y, int x,
+                       int H, int W, int tid) {
+  constexpr int EO = win_edge(K), EI = EO + 2, NP = EO * EO, J = (NP + 31) / 32;
+  const int cg = tid & 7, pg = tid >> 3;
+  int q0[J];
+  float acc[J][4];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int p = pg + 32 * j < NP ? pg + 32 * j : 0;
+    q0[j] = (p / EO) * EI + p % EO;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[j][i] = sb[4 * cg + i];
+  }
+#pragma unroll 1
+  for (int t = 0; t < 9; ++t) {
+    const int dq = (t / 3) * EI + t % 3;
+#pragma unroll 4
+    for (int ci = 0; ci < 32; ++ci) {
+      const f32x4_t wv = *(const f32x4_t*)(sw + (t * 32 + ci) * 32 + 4 * cg);
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const float av = src[(q0[j] + dq) * RS + ci];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[j][i] = fmaf(wv[i], av, acc[j][i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int p = pg + 32 * j;
+    if (p < NP) {
+      const int gy = y - (6 - K) + p / EO, gx = x - (6 - K) + p % EO;
+      const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dst[p * RS + 4 * cg + i] = in ? fmaxf(acc[j][i], 0.f) : 0.f;
+    }
+  }
+}
+
+__global__ __launch_bounds__(F32_THREADS, 2) void recheck_fp32_kernel(
+    const float* __restrict__ w, const float* __restrict__ contone,
+    const uint64_t* __restrict__ seeds, int H, int W, int kind, const uint32_t* __restrict__ list,
+    const int* __restrict__ count, const f32x4_t* __restrict__ wt, uint8_t* __restrict__ bits,
+    float* __restrict__ logits, int32_t* __restrict__ stats, int count_slot) {
+  __shared__ float s0[13 * 13 * 2];
+  __shared__ float bufA[11 * 11 * RS], bufB[9 * 9 * RS];
+  __shared__ __attribute__((aligned(16))) float sw[F32_LAYER];  // [t][ci][co]
+  __shared__ float sb[32];
+  __shared__ float w1[32 * 2 * 9 + 32];
+  const int n = *count;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) stats[count_slot] = n;
+  // the next layer's weights travel in registers while a layer computes
+  f32x4_t pw[F32_VPT];
+  auto fetch = [&](int k) {
+#pragma unroll
+    for (int j = 0; j < F32_VPT; ++j) pw[j] = wt[(k - 2) * (F32_LAYER / 4) + tid + F32_THREADS * j];
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int j = 0; j < F32_VPT; ++j) ((f32x4_t*)sw)[tid + F32_THREADS * j] = pw[j];
+  };
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const uint32_t u = list[it], o = u & ~BIT_FLAG;
+    const int b = (int)(o / ((uint32_t)H * W));
+    const int rem = (int)(o - (uint32_t)b * H * W), y = rem / W, x = rem - (rem / W) * W;
+    const size_t img = (size_t)b * H * W;
+    fetch(2);
+    __syncthreads();
+    for (int i = tid; i < 169; i += F32_THREADS) {
+      const int gy = y - 6 + i / 13, gx = x - 6 + i % 13;
+      float cv = 0.f, zv = 0.f;
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+        const uint64_t a = (uint64_t)gy * W + gx;
+        cv = contone[img + a];
+        zv = hs_noise(seeds[b], a, 0u, kind);
+      }
+      s0[i * 2] = cv;
+      s0[i * 2 + 1] = zv;
+    }
+    for (int i = tid; i < 32 * 2 * 9 + 32; i += F32_THREADS) w1[i] = w[HS_W1 + i];
+    __syncthreads();
+    // layer 1 on the 11 x 11 window
+    for (int i = tid; i < 121 * 32; i += F32_THREADS) {
+      const int co = i & 31, p = i >> 5, py = p / 11, px = p % 11;
+      const int gy = y - 5 + py, gx = x - 5 + px;
+      float acc = 0.f;
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+        acc = w1[HS_B1 + co];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const int q = (py + t / 3) * 13 + px + t % 3;
+          acc = fmaf(w1[(co * 2) * 9 + t], s0[q * 2], acc);
+          acc = fmaf(w1[(co * 2 + 1) * 9 + t], s0[q * 2 + 1], acc);
+        }
+        acc = fmaxf(acc, 0.f);
+      }
+      bufA[p * RS + co] = acc;
+    }
+    // layers 2..5: bufA -> bufB -> bufA -> bufB -> bufA
+    for (int k = 2; k <= 5; ++k) {
+      __syncthreads();
+      commit();
+      if (tid < 32) sb[tid] = w[hs_bk(k) + tid];
+      __syncthreads();
+      if (k < 5) fetch(k + 1);
+      switch (k) {
+        case 2: fp32_layer<2>(bufA, bufB, sw, sb, y, x, H, W, tid); break;
+        case 3: fp32_layer<3>(bufB, bufA, sw, sb, y, x, H, W, tid); break;
+        case 4: fp32_layer<4>(bufA, bufB, sw, sb, y, x, H, W, tid); break;
+        default: fp32_layer<5>(bufB, bufA, sw, sb, y, x, H, W, tid); break;
+      }
+    }
+    __syncthreads();
+    // layer 6 at the centre of the 3 x 3 window (in bufA)
+    if (tid < 64) {
+      float part = 0.f;
+      for (int i = tid; i < 288; i += 64) {
+        const int ci = i / 9, t = i % 9;
+        part = fmaf(w[HS_W6 + i], bufA[t * RS + ci], part);
+      }
+      part = hs_wave_sum(part);
+      if (tid == 0) {
+        const float xl = part + w[HS_B6];
+        const uint32_t nb = xl >= 0.f ? 1u : 0u;
+        if (nb != (u >> 31)) atomicAdd(&stats[1], 1);
+        bits[o] = (uint8_t)nb;
+        if (logits) logits[o] = xl;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+namespace hs {
+
+// bytes of the hi and the lo copy together (each 4 layers x 9 taps x 2 row
+// tiles x 64 lanes x 8 BF16 values)
+size_t split_frag_bytes() { return 2 * (size_t)(4 * 9 * 2 * 64 * 8) * sizeof(__bf16); }
+size_t fp32_pack_bytes() { return (size_t)4 * F32_LAYER * sizeof(float); }
+
+hipError_t launch_split_pack(const float* w, void* whi, void* wlo, void* wt, hipStream_t s) {
+  pack_split_kernel<<<36, 256, 0, s>>>(w, (__bf16*)whi, (__bf16*)wlo);
+  pack_fp32_kernel<<<36, 256, 0, s>>>(w, (float*)wt);
+  return hipGetLastError();
+}
+
+hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
+                                int H, int W, int kind, const uint32_t* seglist,
+                                const int* seg_count, int nseg, long long seg_cap,
+                                const void* whi, const void* wlo, float tau2, uint32_t* list2,
+                                int* count2, uint8_t* bits, float* logits, int32_t* stats,
+                                int num_cus, hipStream_t s) {
+  if (nseg < 1 || nseg > SPLIT_MAXSEG) return hipErrorInvalidValue;
+  SplitArgs a;
+  a.w = w;
+  a.contone = contone;
+  a.seeds = seeds;
+  a.H = H;
+  a.W = W;
+  a.kind = kind;
+  a.nseg = nseg;
+  a.seglist = seglist;
+  a.seg_count = seg_count;
+  a.seg_cap = seg_cap;
+  a.whi = (const bf16x8_t*)whi;
+  a.wlo = (const bf16x8_t*)wlo;
+  a.tau2 = tau2;
+  a.list2 = list2;
+  a.count2 = count2;
+  a.bits = bits;
+  a.logits = logits;
+  a.stats = stats;
+  recheck_split_kernel<<<num_cus, SPLIT_THREADS, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,
+                               int H, int W, int kind, const uint32_t* list, const int* count,
+                               const void* wt, uint8_t* bits, float* logits, int32_t* stats,
+                               int count_slot, int num_cus, hipStream_t s) {
+  recheck_fp32_kernel<<<2 * num_cus, F32_THREADS, 0, s>>>(w, contone, seeds, H, W, kind, list,
+                                                          count, (const f32x4_t*)wt, bits, logits,
+                                                          stats, count_slot);
+  return hipGetLastError();
+}
+
+}  // namespace hs

@@ -153,6 +153,8 @@ def main(argv=None):
     ap.add_argument("--ws", type=float, default=None,
                     help="CSSIM weight w_s of the reward (default 0.06; 0 = HVS-MSE only)")
     ap.add_argument("--wa", type=float, default=None, help="anisotropy weight w_a (default 0.002)")
+    ap.add_argument("--estimator", choices=["le", "coma"], default="le",
+                    help="policy-gradient estimator: Local Expectation (Eq. le) or COMA (Eq. coma)")
     ap.add_argument("--judge-every", type=int, default=0,
                     help="steps between held-out evaluations of the policy during training")
     ap.add_argument("--out", default=None, help="write the trained weights (.npy)")
@@ -176,6 +178,7 @@ def main(argv=None):
         kw["w_s"] = args.ws
     if args.wa is not None:
         kw["w_a"] = args.wa
+    kw["estimator"] = hb.HS_EST_COMA if args.estimator == "coma" else hb.HS_EST_LE
     tp = hb.default_train_params(**kw)
     tr = Trainer(pool, args.steps, batch=args.batch, run_seed=args.run_seed,
                  weight_seed=args.weight_seed, precision=prec, tp=tp)
@@ -208,7 +211,7 @@ def main(argv=None):
     if args.out:
         np.save(args.out, tr.weights.cpu().numpy())
     res = {"steps": args.steps, "batch": args.batch, "pool": args.pool, "size": args.size,
-           "w_s": tp.loss.w_s, "w_a": tp.loss.w_a,
+           "w_s": tp.loss.w_s, "w_a": tp.loss.w_a, "estimator": args.estimator,
            "precision": "fp32" if args.fp32 else "bf16", "train_seconds": round(train_s, 2),
            "steps_per_s": round(args.steps / train_s, 2), "judge_images": args.judge,
            "untrained": before, "trained": after, "judge_curve": curve,

@@ -69,14 +69,16 @@ def test_workspace_sizes_positive_and_monotone(lib):
         lib.halftone_train_workspace_size(4, 64, 64, 0, 0, 0, hb.HS_BF16)
 
 
-def test_bf16_infer_workspace_holds_all_weight_copies(lib):
-    # fused-kernel fragments (4800 x 16 B) plus the split hi and lo copies of
-    # the four 32->32 layers (2 x 36864 BF16) plus two recheck lists and
-    # counters, even for a single pixel
-    need = 4800 * 16 + 2 * 36864 * 2 + 2 * 4 + 64
-    assert lib.halftone_infer_workspace_size(1, 1, 1, hb.HS_BF16) >= need
-    assert lib.halftone_infer_workspace_size(2, 64, 64, hb.HS_BF16) >= \
-        4800 * 16 + 2 * 36864 * 2 + 2 * 4 * 2 * 64 * 64 + 64
+def test_bf16_infer_workspace_holds_all_buffers(lib):
+    # fused-kernel fragments (4800 x 16 B), the split hi and lo copies of the
+    # four 32->32 layers (2 x 36864 BF16) and their FP32 transposes (4 x 9216
+    # floats), plus per pixel: a segmented-list entry and an FP32-stage list
+    # entry (4 B each), plus the segment counts and counters
+    weights = 4800 * 16 + 2 * 36864 * 2 + 4 * 9216 * 4
+    for shape in [(1, 1, 1), (1, 37, 45), (2, 64, 64), (8, 1024, 1024)]:
+        n = shape[0] * shape[1] * shape[2]
+        assert lib.halftone_infer_workspace_size(*shape, hb.HS_BF16) >= \
+            weights + 2 * 4 * n + 2 * 256 * 4 + 64
 
 
 def _fake(n=64):

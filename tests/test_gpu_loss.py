@@ -100,3 +100,27 @@ def test_loss_backward_is_deterministic(orc):
     a, _ = hb.halftone_loss_backward(to_dev(h), to_dev(c))
     b, _ = hb.halftone_loss_backward(to_dev(h), to_dev(c))
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prm", [dict(), dict(w_s=1.0)])
+def test_coma_gradient_matches_oracle(orc, prm):
+    """The COMA estimator (Eqs. baseline, coma) in both gradient spaces."""
+    B, H, W = 3, 48, 61
+    c, p, h = _case([41, 42, 43], H, W, pseed=4)
+    ref = orc.coma_grad_logits(h.astype(np.float64), c.astype(np.float64),
+                               p.astype(np.float64), dict(prm, estimator=1))
+    lp = hb.default_loss_params(estimator=hb.HS_EST_COMA, **prm)
+    gl, _ = hb.halftone_loss_backward(to_dev(h), to_dev(c), to_dev(p), prm=lp,
+                                      grad_space=hb.HS_WRT_LOGIT)
+    assert np.abs(gl.cpu().numpy() - ref).max() <= 1e-4 * np.abs(ref).max()
+    gp, _ = hb.halftone_loss_backward(to_dev(h), to_dev(c), to_dev(p), prm=lp,
+                                      grad_space=hb.HS_WRT_PROB)
+    refp = ref / (p.astype(np.float64) * (1 - p.astype(np.float64)))
+    assert np.abs(gp.cpu().numpy() - refp).max() <= 1e-4 * np.abs(refp).max()
+
+
+def test_coma_needs_probs():
+    c, p, h = _case([44], 16, 16)
+    lp = hb.default_loss_params(estimator=hb.HS_EST_COMA)
+    with pytest.raises(hb.HalftoneError):
+        hb.halftone_loss_backward(to_dev(h), to_dev(c), None, prm=lp)

@@ -132,6 +132,27 @@ def test_train_step_fp32_matches_oracle(orc, with_gray):
     assert abs(met[6] - mo["fill"]) < 1e-7
 
 
+def test_train_step_coma_matches_oracle(orc):
+    """One TRAIN iteration with the COMA estimator in place of Local
+    Expectation, given the GPU's own actions."""
+    B, H, W = 2, 40, 48
+    seeds = [82, 83]
+    w = synth.he_weights(6, head_std=0.01)
+    c = synth.contone_batch(seeds, H, W)
+    step, total = 1, 50
+    tp = hb.default_train_params(estimator=hb.HS_EST_COMA)
+    state = hb.TrainState(to_dev(w), B, H, W, 0, 0, 0, precision=hb.HS_FP32, tp=tp)
+    acts = torch.empty((B, H, W), dtype=torch.uint8, device=device())
+    grad = torch.empty(hb.HS_PARAM_COUNT, dtype=torch.float32, device=device())
+    hb.policy_train_step(state, to_dev(c), seeds_t(seeds), None, None, step, total,
+                         actions_out=acts, grad_out=grad)
+    wd = w.astype(np.float64)
+    o = orc.train_step(wd, np.zeros_like(wd), np.zeros_like(wd), c.astype(np.float64),
+                       np.array(seeds, np.uint64), None, None, step, total,
+                       prm=dict(estimator=1), actions=acts.cpu().numpy())
+    assert _rel(grad.cpu().numpy(), o["grad"]) < 1e-5
+
+
 def test_train_step_bf16_gradient(orc):
     B, H, W = 2, 64, 64
     seeds = [90, 91]
