@@ -131,6 +131,30 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
                    size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Inference over pages of different sizes (the TEST procedure of
+ * Algorithm 1 on an uneven batch), with HS_BF16 in ONE persistent launch
+ * of the fused kernel whose workgroups split all pages' strips evenly,
+ * followed by the same two recheck stages as halftone_infer; with HS_FP32
+ * page by page.
+ *
+ * shapes_host [npages][2] int32 in HOST memory: (H, W) of each page; read
+ *          during the call only.
+ * contone  FP32, the pages concatenated: page p at offset
+ *          sum_{q < p} H_q W_q, row-major within the page.
+ * seeds    [npages] uint64: page p's noise map is keyed by seeds[p]
+ *          (pixel a = y W_p + x within the page).
+ * bits, logits_or_null: the same concatenated layout; stats_or_null as for
+ *          halftone_infer. Every page at least 1 x 1; total < 2^31 pixels.
+ * --------------------------------------------------------------------- */
+size_t halftone_infer_pages_workspace_size(int npages, const int32_t* shapes_host,
+                                           int precision);
+int halftone_infer_pages(const float* weights, const float* contone, const uint64_t* seeds,
+                         int npages, const int32_t* shapes_host, int noise_kind, int precision,
+                         float recheck_tau, uint8_t* bits, float* logits_or_null,
+                         int32_t* stats_or_null, void* workspace, size_t workspace_bytes,
+                         void* stream);
+
+/* ---------------------------------------------------------------------
  * Training-mode policy forward and its backward (the conv stack of
  * Sec. VI-A with its chain rule), for torch.autograd wrappers.
  *

@@ -53,6 +53,8 @@ _SIGS = {
     "halftone_param_count": (ctypes.c_int64, []),
     "halftone_infer_workspace_size": (SZ, [I, I, I, I]),
     "halftone_infer": (I, [P, P, P, I, I, I, I, I, F, P, P, P, P, SZ, P]),
+    "halftone_infer_pages_workspace_size": (SZ, [I, P, I]),
+    "halftone_infer_pages": (I, [P, P, P, I, P, I, I, F, P, P, P, P, SZ, P]),
     "halftone_policy_workspace_size": (SZ, [I, I, I, I]),
     "halftone_policy_forward": (I, [P, P, P, I, I, I, I, ctypes.c_uint32, I, P, P, SZ, P]),
     "halftone_policy_backward": (I, [P, P, P, I, I, I, I, P, P, SZ, P]),
@@ -142,6 +144,43 @@ def halftone_infer(weights, contone, seeds, noise_kind=HS_NOISE_GAUSS, precision
     _check(lib().halftone_infer(_ptr(weights), _ptr(contone), _ptr(seeds), B, H, W, noise_kind,
                                 precision, recheck_tau, _ptr(bits), _ptr(lg), _ptr(st), _ptr(ws),
                                 ws.numel(), _stream()))
+    out = [bits]
+    if logits:
+        out.append(lg)
+    if stats:
+        out.append(st)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def page_shapes_array(shapes):
+    """int32 [npages][2] host array of (H, W) pairs."""
+    import numpy as np
+    return np.ascontiguousarray(np.asarray(shapes, dtype=np.int32).reshape(-1, 2))
+
+
+def halftone_infer_pages(weights, contone, seeds, shapes, noise_kind=HS_NOISE_GAUSS,
+                         precision=HS_BF16, recheck_tau=0.055, logits=False, stats=False,
+                         workspace=None):
+    """Pages of different sizes in one call. contone: flat FP32 device tensor
+    of the pages concatenated (page p at offset sum of the earlier H*W);
+    shapes: (H, W) per page; returns flat bits (and logits, stats)."""
+    sh = page_shapes_array(shapes)
+    n = sh.shape[0]
+    N = int((sh[:, 0].astype("int64") * sh[:, 1]).sum())
+    dev = contone.device
+    _dev(weights, torch.float32), _dev(contone, torch.float32), _dev(seeds, torch.int64)
+    assert contone.numel() == N and seeds.numel() == n, (contone.numel(), N, seeds.numel(), n)
+    bits = torch.empty(N, dtype=torch.uint8, device=dev)
+    lg = torch.empty(N, dtype=torch.float32, device=dev) if logits else None
+    st = torch.zeros(4, dtype=torch.int32, device=dev) if stats else None
+    shp = sh.ctypes.data_as(ctypes.c_void_p)
+    need = lib().halftone_infer_pages_workspace_size(n, shp, precision)
+    if need == 0:
+        raise HalftoneError(HS_ESHAPE, "bad page shapes")
+    ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
+    _check(lib().halftone_infer_pages(_ptr(weights), _ptr(contone), _ptr(seeds), n, shp,
+                                      noise_kind, precision, recheck_tau, _ptr(bits), _ptr(lg),
+                                      _ptr(st), _ptr(ws), ws.numel(), _stream()))
     out = [bits]
     if logits:
         out.append(lg)

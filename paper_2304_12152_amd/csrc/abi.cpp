@@ -124,7 +124,6 @@ LossWs carve_loss(Carve& cv, int B, int H, int W, int Bg, int Hg, int Wg, int m,
 
 struct InferWs {
   void *pack, *a0, *a1;
-  int* seg_count = nullptr;   // BF16 path: entries per recheck-list segment
 };
 InferWs carve_infer(Carve& cv, size_t N, int prec) {
   InferWs w;
@@ -289,104 +288,226 @@ const char* halftone_last_error(void) { return g_err.c_str(); }
 int64_t halftone_param_count(void) { return HS_PARAM_COUNT; }
 
 // ------------------------------------------------------------- inference --
-static size_t infer_ws(int B, int H, int W, int prec, InferWs* out, uint32_t** list, int** cnt,
-                       void* base) {
+// Workspace of the BF16 path (sizes in bytes) for pages of the given shapes:
+// packed fragments, the split and FP32 weight copies, the page table, the
+// segmented recheck list and its counts, the FP32-stage list, counters.
+struct Bf16Ws {
+  char *pack, *split;
+  Page* pages;
+  uint64_t *seglist, *list2;
+  int *seg_count, *cnt;
+};
+static size_t bf16_ws(const int* shapes, int npages, size_t N, Bf16Ws* out, void* base) {
   Carve cv(base);
-  const size_t N = (size_t)B * H * W;
-  InferWs w;
-  if (prec == HS_BF16) {  // fused path (sizes in bytes): packed fragments, the
-                          // segmented list and its counts, the dense FP32-stage
-                          // list
-    w.pack = cv.take<char>(fused_frag_bytes());
-    w.a0 = cv.take<char>(split_frag_bytes() + fp32_pack_bytes());
-    const size_t ne = fused_list_entries(B, H, W, num_cus());
-    w.a1 = cv.take<char>(ne * sizeof(uint32_t));                        // segmented list
-    w.seg_count = cv.take<int>((2 * (size_t)num_cus() + 16) * sizeof(int));  // its counts
-    uint32_t* l = cv.take<uint32_t>(N * sizeof(uint32_t));              // FP32-stage list
-    if (list) *list = l;
-  } else {
-    w = carve_infer(cv, N, prec);
-    if (list) *list = nullptr;
-  }
+  Bf16Ws w;
+  w.pack = cv.take<char>(fused_frag_bytes());
+  w.split = cv.take<char>(split_frag_bytes() + fp32_pack_bytes());
+  w.pages = cv.take<Page>((size_t)npages * sizeof(Page));
+  const size_t ne = fused_list_entries(shapes, npages, num_cus());
+  w.seglist = cv.take<uint64_t>(ne * sizeof(uint64_t));
+  w.seg_count = cv.take<int>((2 * (size_t)num_cus() + 16) * sizeof(int));
+  w.list2 = cv.take<uint64_t>(N * sizeof(uint64_t));
+  w.cnt = cv.take<int>(64);
+  if (out) *out = w;
+  return cv.off;
+}
+
+// Workspace of the FP32 path for one batch of B images of H x W.
+static size_t fp32_ws(int B, int H, int W, InferWs* out, int** cnt, void* base) {
+  Carve cv(base);
+  InferWs w = carve_infer(cv, (size_t)B * H * W, HS_FP32);
   int* c = cv.take<int>(64);
   if (out) *out = w;
   if (cnt) *cnt = c;
   return cv.off;
 }
 
-size_t halftone_infer_workspace_size(int B, int H, int W, int precision) {
-  if (!shape_ok(B, H, W)) return 0;
-  return infer_ws(B, H, W, precision, nullptr, nullptr, nullptr, nullptr);
+static std::vector<int> uniform_shapes(int B, int H, int W) {
+  std::vector<int> s(2 * (size_t)B);
+  for (int b = 0; b < B; ++b) {
+    s[2 * b] = H;
+    s[2 * b + 1] = W;
+  }
+  return s;
 }
 
-int halftone_infer(const float* weights, const float* contone, const uint64_t* seeds, int B,
-                   int H, int W, int noise_kind, int precision, float recheck_tau, uint8_t* bits,
-                   float* logits_or_null, int32_t* stats_or_null, void* workspace,
-                   size_t workspace_bytes, void* stream) {
-  if (!weights || !contone || !seeds || !bits || !workspace)
-    return fail(HS_EINVAL, "halftone_infer: null pointer");
-  if (!shape_ok(B, H, W)) return fail(HS_ESHAPE, "halftone_infer: bad shape %d x %d x %d", B, H, W);
-  if (precision != HS_FP32 && precision != HS_BF16)
-    return fail(HS_EUNSUPPORTED, "halftone_infer: precision %d", precision);
-  if (noise_kind != HS_NOISE_GAUSS && noise_kind != HS_NOISE_UNIFORM)
-    return fail(HS_EINVAL, "halftone_infer: noise kind %d", noise_kind);
-  if (!(recheck_tau >= 0.0f)) return fail(HS_EINVAL, "halftone_infer: recheck_tau < 0");
-  if (workspace_bytes < halftone_infer_workspace_size(B, H, W, precision))
-    return fail(HS_EWORKSPACE, "halftone_infer: workspace too small");
-  int rc = check_device();
-  if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  InferWs iw;
-  uint32_t* list;
-  int* cnt;
-  infer_ws(B, H, W, precision, &iw, &list, &cnt, workspace);
-  const size_t per_layer = (size_t)PACK32_PER_LAYER * (precision == HS_BF16 ? 2 : 4);
-  int32_t* stats = stats_or_null ? stats_or_null : (int32_t*)(cnt + 8);
-  HS_TRY(launch_zero_ints(cnt, 16, s));
-  if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
+size_t halftone_infer_workspace_size(int B, int H, int W, int precision) {
+  if (!shape_ok(B, H, W)) return 0;
   if (precision == HS_BF16) {
-    // stage 1: fused BF16 pass, pixels with |x| < tau listed
-    // stage 2: split-BF16 receptive-field recompute, |x| < tau2 listed again
-    // stage 3: FP32 receptive-field recompute
-    const float tau2 = fminf(fmaxf(recheck_tau / 64.0f, 5e-4f), 1e-2f);
-    uint32_t* list2 = list;
-    uint32_t* seglist = (uint32_t*)iw.a1;
-    int* seg_count = iw.seg_count;
-    char* whi = (char*)iw.a0;
-    char* wlo = whi + split_frag_bytes() / 2;
-    char* wt = whi + split_frag_bytes();
-    HS_TRY(launch_fused_pack(weights, iw.pack, s));
-    HS_TRY(launch_split_pack(weights, whi, wlo, wt, s));
-    int nseg = 0;
-    long long seg_cap = 0;
-    prof_begin(s);
-    HS_TRY(launch_fused_infer(weights, contone, seeds, B, H, W, noise_kind, recheck_tau, bits,
-                              logits_or_null, seglist, seg_count, &nseg, &seg_cap, iw.pack,
-                              num_cus(), s));
-    prof_end(s);
-    HS_TRY(launch_recheck_split(weights, contone, seeds, H, W, noise_kind, seglist, seg_count, nseg,
-                                seg_cap, whi, wlo, tau2, list2, cnt + 1, bits, logits_or_null,
-                                stats, num_cus(), s));
-    HS_TRY(launch_recheck_fp32(weights, contone, seeds, H, W, noise_kind, list2, cnt + 1, wt,
-                               bits, logits_or_null, stats, 2, num_cus(), s));
-    return HS_OK;
+    const std::vector<int> sh = uniform_shapes(B, H, W);
+    return bf16_ws(sh.data(), B, (size_t)B * H * W, nullptr, nullptr);
   }
-  HS_TRY(launch_pack32(weights, iw.pack, precision, 0, s));
-  HS_TRY(launch_conv_first(contone, seeds, weights, B, H, W, noise_kind, 0u, precision, iw.a0,
+  return fp32_ws(B, H, W, nullptr, nullptr, nullptr);
+}
+
+// The BF16 path over a page table (one persistent fused launch for all pages):
+//   stage 1: fused BF16 pass, pixels with |x| < tau listed
+//   stage 2: split-BF16 receptive-field recompute, |x| < tau2 listed again
+//   stage 3: FP32 receptive-field recompute
+// The page table is built on the device (uniform batch) or from pages_host.
+static int infer_bf16(const float* weights, const float* contone, const uint64_t* seeds,
+                      const int* shapes, int npages, size_t N, const Page* pages_host,
+                      int noise_kind, float recheck_tau, uint8_t* bits, float* logits,
+                      int32_t* stats_or_null, void* workspace, hipStream_t s) {
+  Bf16Ws w;
+  bf16_ws(shapes, npages, N, &w, workspace);
+  int32_t* stats = stats_or_null ? stats_or_null : (int32_t*)(w.cnt + 8);
+  HS_TRY(launch_zero_ints(w.cnt, 16, s));
+  if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
+  if (pages_host) HS_TRY(launch_put_pages(w.pages, pages_host, npages, s));
+  else HS_TRY(launch_uniform_pages(w.pages, npages, shapes[0], shapes[1], s));
+  const float tau2 = fminf(fmaxf(recheck_tau / 64.0f, 5e-4f), 1e-2f);
+  char* whi = w.split;
+  char* wlo = whi + split_frag_bytes() / 2;
+  char* wt = whi + split_frag_bytes();
+  HS_TRY(launch_fused_pack(weights, w.pack, s));
+  HS_TRY(launch_split_pack(weights, whi, wlo, wt, s));
+  int nseg = 0;
+  long long seg_cap = 0;
+  prof_begin(s);
+  HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
+                            recheck_tau, bits, logits, w.seglist, w.seg_count, &nseg, &seg_cap,
+                            w.pack, num_cus(), s));
+  prof_end(s);
+  HS_TRY(launch_recheck_split(weights, contone, seeds, w.pages, noise_kind, w.seglist,
+                              w.seg_count, nseg, seg_cap, whi, wlo, tau2, w.list2, w.cnt + 1,
+                              bits, logits, stats, num_cus(), s));
+  HS_TRY(launch_recheck_fp32(weights, contone, seeds, w.pages, noise_kind, w.list2, w.cnt + 1,
+                             wt, bits, logits, stats, 2, num_cus(), s));
+  return HS_OK;
+}
+
+// The FP32 path (per-layer kernels) on one uniform batch.
+static int infer_fp32(const float* weights, const float* contone, const uint64_t* seeds, int B,
+                      int H, int W, int noise_kind, uint8_t* bits, float* logits, void* workspace,
+                      hipStream_t s) {
+  InferWs iw;
+  int* cnt;
+  fp32_ws(B, H, W, &iw, &cnt, workspace);
+  const size_t per_layer = (size_t)PACK32_PER_LAYER * 4;
+  HS_TRY(launch_zero_ints(cnt, 16, s));
+  HS_TRY(launch_pack32(weights, iw.pack, HS_FP32, 0, s));
+  HS_TRY(launch_conv_first(contone, seeds, weights, B, H, W, noise_kind, 0u, HS_FP32, iw.a0,
                            nullptr, nullptr, s));
   void* src = iw.a0;
   void* dst = iw.a1;
   for (int k = 2; k <= 5; ++k) {
     if (k == 2) prof_begin(s);
     HS_TRY(launch_conv32(src, (const char*)iw.pack + (k - 2) * per_layer, weights + hs_bk(k),
-                         nullptr, dst, B, H, W, precision, 0, s));
+                         nullptr, dst, B, H, W, HS_FP32, 0, s));
     if (k == 5) prof_end(s);
     void* t = src;
     src = dst;
     dst = t;
   }
-  HS_TRY(launch_conv_last(src, weights, B, H, W, precision, 0, seeds, 0u, bits, logits_or_null,
-                          nullptr, 0.0f, nullptr, cnt, s));
+  HS_TRY(launch_conv_last(src, weights, B, H, W, HS_FP32, 0, seeds, 0u, bits, logits, nullptr,
+                          0.0f, nullptr, cnt, s));
+  return HS_OK;
+}
+
+static int check_infer_args(const float* weights, const float* contone, const uint64_t* seeds,
+                            const uint8_t* bits, const void* workspace, int noise_kind,
+                            int precision, float recheck_tau, const char* who) {
+  if (!weights || !contone || !seeds || !bits || !workspace)
+    return fail(HS_EINVAL, "%s: null pointer", who);
+  if (precision != HS_FP32 && precision != HS_BF16)
+    return fail(HS_EUNSUPPORTED, "%s: precision %d", who, precision);
+  if (noise_kind != HS_NOISE_GAUSS && noise_kind != HS_NOISE_UNIFORM)
+    return fail(HS_EINVAL, "%s: noise kind %d", who, noise_kind);
+  if (!(recheck_tau >= 0.0f)) return fail(HS_EINVAL, "%s: recheck_tau < 0", who);
+  return HS_OK;
+}
+
+int halftone_infer(const float* weights, const float* contone, const uint64_t* seeds, int B,
+                   int H, int W, int noise_kind, int precision, float recheck_tau, uint8_t* bits,
+                   float* logits_or_null, int32_t* stats_or_null, void* workspace,
+                   size_t workspace_bytes, void* stream) {
+  int rc = check_infer_args(weights, contone, seeds, bits, workspace, noise_kind, precision,
+                            recheck_tau, "halftone_infer");
+  if (rc) return rc;
+  if (!shape_ok(B, H, W)) return fail(HS_ESHAPE, "halftone_infer: bad shape %d x %d x %d", B, H, W);
+  if (workspace_bytes < halftone_infer_workspace_size(B, H, W, precision))
+    return fail(HS_EWORKSPACE, "halftone_infer: workspace too small");
+  if ((rc = check_device())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == HS_BF16) {
+    const std::vector<int> sh = uniform_shapes(B, H, W);
+    return infer_bf16(weights, contone, seeds, sh.data(), B, (size_t)B * H * W, nullptr,
+                      noise_kind, recheck_tau, bits, logits_or_null, stats_or_null, workspace, s);
+  }
+  if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
+  return infer_fp32(weights, contone, seeds, B, H, W, noise_kind, bits, logits_or_null,
+                    workspace, s);
+}
+
+// Page shapes: every page at least 1 x 1 and the total under 2^31 pixels.
+static bool pages_ok(int npages, const int32_t* shapes, size_t* N) {
+  if (npages < 1 || !shapes) return false;
+  long long n = 0;
+  for (int p = 0; p < npages; ++p) {
+    if (shapes[2 * p] < 1 || shapes[2 * p + 1] < 1) return false;
+    n += (long long)shapes[2 * p] * shapes[2 * p + 1];
+    if (n >= (1ll << 31)) return false;
+  }
+  *N = (size_t)n;
+  return true;
+}
+
+size_t halftone_infer_pages_workspace_size(int npages, const int32_t* shapes_host,
+                                           int precision) {
+  size_t N = 0;
+  if (!pages_ok(npages, shapes_host, &N)) return 0;
+  if (precision == HS_BF16) return bf16_ws(shapes_host, npages, N, nullptr, nullptr);
+  size_t m = 0;  // the FP32 path runs page by page
+  for (int p = 0; p < npages; ++p) {
+    const size_t b = fp32_ws(1, shapes_host[2 * p], shapes_host[2 * p + 1], nullptr, nullptr,
+                             nullptr);
+    if (b > m) m = b;
+  }
+  return m;
+}
+
+int halftone_infer_pages(const float* weights, const float* contone, const uint64_t* seeds,
+                         int npages, const int32_t* shapes_host, int noise_kind, int precision,
+                         float recheck_tau, uint8_t* bits, float* logits_or_null,
+                         int32_t* stats_or_null, void* workspace, size_t workspace_bytes,
+                         void* stream) {
+  int rc = check_infer_args(weights, contone, seeds, bits, workspace, noise_kind, precision,
+                            recheck_tau, "halftone_infer_pages");
+  if (rc) return rc;
+  size_t N = 0;
+  if (!pages_ok(npages, shapes_host, &N))
+    return fail(HS_ESHAPE, "halftone_infer_pages: bad page shapes or more than 2^31 pixels");
+  if (workspace_bytes < halftone_infer_pages_workspace_size(npages, shapes_host, precision))
+    return fail(HS_EWORKSPACE, "halftone_infer_pages: workspace too small");
+  if ((rc = check_device())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == HS_BF16) {
+    std::vector<Page> pages(npages);
+    long long off = 0, vstart = 0;
+    for (int p = 0; p < npages; ++p) {
+      const int H = shapes_host[2 * p], W = shapes_host[2 * p + 1];
+      pages[p].off = off;
+      pages[p].vstart = vstart;
+      pages[p].H = H;
+      pages[p].W = W;
+      pages[p].nstrip = fused_strips(W);
+      pages[p].pad = 0;
+      off += (long long)H * W;
+      vstart += (long long)fused_strips(W) * (H + fused_fill());
+    }
+    return infer_bf16(weights, contone, seeds, shapes_host, npages, N, pages.data(), noise_kind,
+                      recheck_tau, bits, logits_or_null, stats_or_null, workspace, s);
+  }
+  if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
+  long long off = 0;
+  for (int p = 0; p < npages; ++p) {
+    const int H = shapes_host[2 * p], W = shapes_host[2 * p + 1];
+    rc = infer_fp32(weights, contone + off, seeds + p, 1, H, W, noise_kind, bits + off,
+                    logits_or_null ? logits_or_null + off : nullptr, workspace, s);
+    if (rc) return rc;
+    off += (long long)H * W;
+  }
   return HS_OK;
 }
 

@@ -23,6 +23,21 @@ static_assert(HS_B6 + 1 == HS_PARAM_COUNT, "parameter layout");
 namespace hs {
 
 constexpr int NPARAM = HS_PARAM_COUNT;
+
+// One page (image) of an inference call: pixels [off, off + H W) of the
+// concatenated buffers, its first virtual strip row in the fused kernel's
+// work partition, and its strip count. Its seed is seeds[page].
+struct Page {
+  long long off;
+  long long vstart;
+  int H, W, nstrip, pad;
+};
+// A recheck-list entry: pixel index (bits 0-30), page (31-62), the bit
+// decided so far (63).
+constexpr uint64_t ENTRY_PIXEL = 0x7FFFFFFFull;
+inline __host__ __device__ uint32_t entry_pixel(uint64_t e) { return (uint32_t)(e & ENTRY_PIXEL); }
+inline __host__ __device__ int entry_page(uint64_t e) { return (int)((e >> 31) & 0xFFFFFFFFull); }
+inline __host__ __device__ int entry_bit(uint64_t e) { return (int)(e >> 63); }
 constexpr int WGRAD_BLOCKS = 512;  // rows of weight-gradient partial sums
 
 // Bytes of one NHWC 32-channel activation map of n pixels.
@@ -54,27 +69,33 @@ hipError_t launch_conv_last(const void* in, const float* w, int B, int H, int W,
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 size_t fused_frag_bytes();
 hipError_t launch_fused_pack(const float* w, void* frags, hipStream_t s);
-// persistent fused BF16 inference; the recheck list is segmented (two
-// segments per workgroup, counts in seg_count; list may be null); a list
-// entry carries the bit written for the pixel in its top bit
-size_t fused_list_entries(int B, int H, int W, int num_cus);
-hipError_t launch_fused_infer(const float* w, const float* contone, const uint64_t* seeds, int B,
-                              int H, int W, int kind, float tau, uint8_t* bits, float* logits,
-                              uint32_t* list, int* seg_count, int* nseg, long long* seg_cap,
-                              const void* frags, int num_cus, hipStream_t s);
+// persistent fused BF16 inference over pages (one launch for all of them;
+// shapes_host = [npages][H, W] as in the device page table); the recheck
+// list is segmented (two segments per workgroup, counts in seg_count; list
+// may be null)
+int fused_strips(int W);
+int fused_fill();
+hipError_t launch_uniform_pages(Page* pages, int B, int H, int W, hipStream_t s);
+hipError_t launch_put_pages(Page* dst, const Page* src_host, int n, hipStream_t s);
+size_t fused_list_entries(const int* shapes_host, int npages, int num_cus);
+hipError_t launch_fused_infer(const float* w, const float* contone, const uint64_t* seeds,
+                              const Page* pages, const int* shapes_host, int npages, int kind,
+                              float tau, uint8_t* bits, float* logits, uint64_t* list,
+                              int* seg_count, int* nseg, long long* seg_cap, const void* frags,
+                              int num_cus, hipStream_t s);
 // recheck.hip: re-evaluation of listed pixels over their receptive field
 // (wt: layers 2..5 transposed for the FP32 stage, fp32_pack_bytes())
 hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,
-                               int H, int W, int kind, const uint32_t* list, const int* count,
-                               const void* wt, uint8_t* bits, float* logits, int32_t* stats,
-                               int count_slot, int num_cus, hipStream_t s);
+                               const Page* pages, int kind, const uint64_t* list,
+                               const int* count, const void* wt, uint8_t* bits, float* logits,
+                               int32_t* stats, int count_slot, int num_cus, hipStream_t s);
 size_t split_frag_bytes();
 size_t fp32_pack_bytes();
 hipError_t launch_split_pack(const float* w, void* whi, void* wlo, void* wt, hipStream_t s);
 hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
-                                int H, int W, int kind, const uint32_t* seglist,
+                                const Page* pages, int kind, const uint64_t* seglist,
                                 const int* seg_count, int nseg, long long seg_cap,
-                                const void* whi, const void* wlo, float tau2, uint32_t* list2,
+                                const void* whi, const void* wlo, float tau2, uint64_t* list2,
                                 int* count2, uint8_t* bits, float* logits, int32_t* stats,
                                 int num_cus, hipStream_t s);
 // g6 = grad (if probs == null) or grad * p (1 - p); writes g6 and the

@@ -106,12 +106,13 @@ struct FusedArgs {
   const uint64_t* seeds;
   const bf16x8_t* frags;
   const float* w;
-  int B, H, W, kind, nstrip;
-  long long vtotal;   // strips x (H + FILL): the balanced partition's extent
+  const hs::Page* pages;
+  int npages, kind;
+  long long vtotal;   // sum over pages of strips x (H + FILL): the partition's extent
   float tau;
   uint8_t* bits;
   float* logits;
-  uint32_t* list;     // per output wave a segment of seg_cap entries
+  uint64_t* list;     // per output wave a segment of seg_cap entries
   int* seg_count;     // entries written per segment
   long long seg_cap;
 };
@@ -200,27 +201,38 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
   for (int h = 0; h < HPW; ++h) nflag[h] = 0;
   __syncthreads();
 
-  // strip rows [Lbeg, Lend) of the sequence (image, strip, row): the real
-  // rows of this workgroup's equal share of the virtual sequence; the
-  // divisions are wave-uniform and kept scalar
-  const int H = a.H, W = a.W;
-  auto real_row = [&](long long v) {
-    const long long sid = v / (H + FILL);
-    const int rv = (int)(v - sid * (H + FILL));
-    return (int)(sid * H) + max(rv - FILL, 0);
-  };
-  const int Lbeg = real_row((long long)blockIdx.x * a.vtotal / gridDim.x);
-  const int Lend = real_row((long long)(blockIdx.x + 1) * a.vtotal / gridDim.x);
-  for (int L = Lbeg; L < Lend;) {
-    const int strip_id = __builtin_amdgcn_readfirstlane(L / H);
-    const int Y0 = L - strip_id * H;
-    const int seg_end = min((strip_id + 1) * H, Lend);
-    const int Y1 = Y0 + (seg_end - L);
-    const int b = __builtin_amdgcn_readfirstlane(strip_id / a.nstrip);
-    const int X = (strip_id - b * a.nstrip) * FS - 6;
+  // This workgroup's equal share [v, vend) of the virtual sequence (page,
+  // strip, row), in which every strip has FILL virtual rows before its H
+  // real ones; it is cut into segments of one strip each. The divisions and
+  // the page lookup are wave-uniform and kept scalar.
+  long long v = (long long)blockIdx.x * a.vtotal / gridDim.x;
+  const long long vend = (long long)(blockIdx.x + 1) * a.vtotal / gridDim.x;
+  while (v < vend) {
+    int pg = 0;  // the last page with vstart <= v
+    {
+      int hi = a.npages - 1;
+      while (pg < hi) {
+        const int mid = (pg + hi + 1) >> 1;
+        if (a.pages[mid].vstart <= v) pg = mid;
+        else hi = mid - 1;
+      }
+    }
+    pg = __builtin_amdgcn_readfirstlane(pg);
+    const hs::Page P = a.pages[pg];
+    const int H = P.H, W = P.W;
+    const long long local = v - P.vstart;
+    const int strip = (int)(local / (H + FILL));
+    const long long sv0 = P.vstart + (long long)strip * (H + FILL);  // the strip's first virtual row
+    const long long sv1 = min(sv0 + H + FILL, vend);
+    const int Y0 = max((int)(v - sv0) - FILL, 0);
+    const int Y1 = max((int)(sv1 - sv0) - FILL, 0);
+    v = sv1;
+    if (Y1 <= Y0) continue;
+    const int X = strip * FS - 6;
     const bool cols_inside = X >= 0 && X + FW <= W;  // no column of the strip is padding
-    const size_t img = (size_t)b * H * W;
-    const uint64_t seed = a.seeds[b];
+    const size_t img = (size_t)P.off;
+    const uint64_t pgbits = (uint64_t)pg << 31;
+    const uint64_t seed = a.seeds[pg];
     const int A = Y0 - 6;  // input row of step 0
     const int nsteps = ((Y1 - Y0) + LAG_OUT + 2) / 3 * 3;
 
@@ -283,9 +295,9 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
                 const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                 const long long seg = 2LL * blockIdx.x + HPW * part + h;
-                // the entry carries the bit written here in its top bit
+                // entry: pixel (bits 0-30), page (31-62), the bit written (63)
                 a.list[seg * a.seg_cap + nflag[h] + below] =
-                    (uint32_t)o | (xl >= 0.0f ? 0x80000000u : 0u);
+                    (uint64_t)o | pgbits | (xl >= 0.0f ? (1ull << 63) : 0ull);
               }
               nflag[h] += __popcll(mask);
             }
@@ -395,13 +407,38 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
       step(t + 1, StepIndex<1>{});
       step(t + 2, StepIndex<2>{});
     }
-    L = seg_end;
   }
   // recheck list: the output stage's 64-pixel halves each own a segment
   if (role == 2 && lane == 0 && a.seg_count) {
 #pragma unroll
     for (int h = 0; h < HPW; ++h) a.seg_count[2 * blockIdx.x + HPW * part + h] = nflag[h];
   }
+}
+
+// A page table travels to the device in kernel arguments, 48 pages at a
+// time (no host buffer has to outlive the call).
+constexpr int PAGE_CHUNK = 48;
+struct PageChunk {
+  hs::Page p[PAGE_CHUNK];
+  int first, n;
+};
+__global__ void put_pages_kernel(hs::Page* pages, PageChunk c) {
+  if ((int)threadIdx.x < c.n) pages[c.first + threadIdx.x] = c.p[threadIdx.x];
+}
+
+// Pages of a uniform batch: B images of H x W.
+__global__ void uniform_pages_kernel(hs::Page* pages, int B, int H, int W) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const int nstrip = (W + FS - 1) / FS;
+  hs::Page p;
+  p.off = (long long)b * H * W;
+  p.vstart = (long long)b * nstrip * (H + FILL);
+  p.H = H;
+  p.W = W;
+  p.nstrip = nstrip;
+  p.pad = 0;
+  pages[b] = p;
 }
 
 }  // namespace
@@ -415,54 +452,78 @@ hipError_t launch_fused_pack(const float* w, void* frags, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Geometry of the persistent launch: workgroups (one per CU, fewer when
-// there are under 32 strip rows per CU) and an upper bound on the real strip
-// rows of one workgroup's share.
-void fused_geometry(int B, int H, int W, int num_cus, int* grid, long long* max_rows) {
-  const int nstrip = (W + FS - 1) / FS;
-  const long long total = (long long)B * nstrip * H;
+int fused_strips(int W) { return (W + FS - 1) / FS; }
+int fused_fill() { return FILL; }
+
+hipError_t launch_put_pages(Page* dst, const Page* src_host, int n, hipStream_t s) {
+  for (int first = 0; first < n; first += PAGE_CHUNK) {
+    PageChunk c;
+    c.first = first;
+    c.n = n - first < PAGE_CHUNK ? n - first : PAGE_CHUNK;
+    for (int i = 0; i < c.n; ++i) c.p[i] = src_host[first + i];
+    put_pages_kernel<<<1, 64, 0, s>>>(dst, c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_uniform_pages(Page* pages, int B, int H, int W, hipStream_t s) {
+  uniform_pages_kernel<<<(B + 255) / 256, 256, 0, s>>>(pages, B, H, W);
+  return hipGetLastError();
+}
+
+// Geometry of the persistent launch over pages of the given shapes:
+// workgroups (one per CU, fewer when there are under 32 strip rows per CU),
+// the virtual extent, and an upper bound on the real strip rows of one
+// workgroup's share.
+void fused_geometry(const int* shapes_host, int npages, int num_cus, int* grid,
+                    long long* vtotal, long long* max_rows) {
+  long long total = 0, vt = 0;
+  for (int p = 0; p < npages; ++p) {
+    const int H = shapes_host[2 * p], W = shapes_host[2 * p + 1];
+    total += (long long)fused_strips(W) * H;
+    vt += (long long)fused_strips(W) * (H + FILL);
+  }
   long long per = (total + num_cus - 1) / num_cus;
   if (per < 32) per = 32;
   const int g = (int)((total + per - 1) / per);
-  const long long vtotal = (long long)B * nstrip * (H + FILL);
   *grid = g;
-  *max_rows = (vtotal + g - 1) / g + 1;
+  *vtotal = vt;
+  *max_rows = (vt + g - 1) / g + 1;
 }
 
 // Entries of the segmented recheck list: two segments per workgroup, each
 // able to hold every pixel its wave writes.
-size_t fused_list_entries(int B, int H, int W, int num_cus) {
+size_t fused_list_entries(const int* shapes_host, int npages, int num_cus) {
   int grid;
-  long long rows;
-  fused_geometry(B, H, W, num_cus, &grid, &rows);
+  long long vt, rows;
+  fused_geometry(shapes_host, npages, num_cus, &grid, &vt, &rows);
   return (size_t)grid * 2 * (size_t)rows * 64;
 }
 
-hipError_t launch_fused_infer(const float* w, const float* contone, const uint64_t* seeds, int B,
-                              int H, int W, int kind, float tau, uint8_t* bits, float* logits,
-                              uint32_t* list, int* seg_count, int* nseg, long long* seg_cap,
-                              const void* frags, int num_cus, hipStream_t s) {
+hipError_t launch_fused_infer(const float* w, const float* contone, const uint64_t* seeds,
+                              const Page* pages, const int* shapes_host, int npages, int kind,
+                              float tau, uint8_t* bits, float* logits, uint64_t* list,
+                              int* seg_count, int* nseg, long long* seg_cap, const void* frags,
+                              int num_cus, hipStream_t s) {
   FusedArgs a;
   a.contone = contone;
   a.seeds = seeds;
   a.frags = (const bf16x8_t*)frags;
   a.w = w;
-  a.B = B;
-  a.H = H;
-  a.W = W;
+  a.pages = pages;
+  a.npages = npages;
   a.kind = kind;
-  a.nstrip = (W + FS - 1) / FS;
-  // nstrip <= W, so B * nstrip * H <= B * H * W < 2^31 (checked by the caller)
-  a.vtotal = (long long)B * a.nstrip * (H + FILL);
   int grid;
-  long long per;
-  fused_geometry(B, H, W, num_cus, &grid, &per);
+  long long rows;
+  fused_geometry(shapes_host, npages, num_cus, &grid, &a.vtotal, &rows);
   a.tau = tau;
   a.bits = bits;
   a.logits = logits;
   a.list = list;
   a.seg_count = seg_count;
-  a.seg_cap = per * 64;
+  a.seg_cap = rows * 64;
   *nseg = 2 * grid;
   *seg_cap = a.seg_cap;
   fused_infer_kernel<FUSED_NW><<<grid, 64 * 4 * FUSED_NW, 0, s>>>(a);

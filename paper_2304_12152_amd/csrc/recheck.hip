@@ -53,9 +53,9 @@ constexpr int SPLIT_THREADS = 512;
 
 HS_DEV int crec_slot(int p, int c) { return c ^ (p & 7); }  // bank-spreading swizzle
 
-// A list entry is a pixel index (< 2^31) with the bit decided so far in its
-// top bit.
-constexpr uint32_t BIT_FLAG = 0x80000000u;
+// cone record: pixel (-1: none), row, column, bit of the fused pass, page,
+// page height and width, seed (two words)
+enum { CI_O, CI_Y, CI_X, CI_BIT, CI_PG, CI_H, CI_W, CI_SLO, CI_SHI, CI_N };
 
 constexpr int win_edge(int k) { return 13 - 2 * k; }           // layer k's output window edge
 constexpr int win_pos(int k) { return win_edge(k) * win_edge(k); }
@@ -83,14 +83,15 @@ struct SplitArgs {
   const float* w;
   const float* contone;
   const uint64_t* seeds;
-  int H, W, kind, nseg;
-  const uint32_t* seglist;
+  const hs::Page* pages;
+  int kind, nseg;
+  const uint64_t* seglist;
   const int* seg_count;
   long long seg_cap;
   const bf16x8_t* whi;
   const bf16x8_t* wlo;
   float tau2;
-  uint32_t* list2;
+  uint64_t* list2;
   int* count2;
   uint8_t* bits;
   float* logits;
@@ -109,7 +110,7 @@ struct SplitSmem {
   float w6[288];                                         // layer 6, [channel][tap]
   __attribute__((aligned(16))) float b1v[32];           // layer 1 bias
   int spre[SPLIT_MAXSEG + 1];                            // exclusive prefix of the segment counts
-  int cinfo[16][5];  // per cone: pixel (-1: none), image, row, column, bit of the fused pass
+  int cinfo[16][CI_N];  // per cone, the CI_* fields
 };
 
 HS_DEV void split_store(char* rec_base, int p, int g, const float (&v)[2][4]) {
@@ -132,8 +133,9 @@ HS_DEV void split_store(char* rec_base, int p, int g, const float (&v)[2][4]) {
 template <int K, int NR>
 HS_DEV void split_layer(const bf16x8_t (&wh)[9][2], const bf16x8_t (*wl)[2][64],
                         const f32x4_t (&bias)[2], const char* src, char* dst, float* dst5,
-                        const int* ci, int run0, int H, int W, int lane) {
+                        const int* ci, int run0, int lane) {
   constexpr int EO = win_edge(K), EI = EO + 2, NP = EO * EO;
+  const int H = ci[CI_H], W = ci[CI_W];
   const int g = lane >> 4, r = lane & 15;
   int ln = lane;
   asm volatile("" : "+v"(ln));
@@ -182,12 +184,12 @@ HS_DEV void split_layer(const bf16x8_t (&wh)[9][2], const bf16x8_t (*wl)[2][64],
       }
     __builtin_amdgcn_sched_barrier(0);
   }
-  const bool cone = ci[0] >= 0;
+  const bool cone = ci[CI_O] >= 0;
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
     if (p[j] < 0) continue;
     const int pi = p[j] / EO, pj = p[j] % EO;
-    const int gy = ci[2] - (6 - K) + pi, gx = ci[3] - (6 - K) + pj;
+    const int gy = ci[CI_Y] - (6 - K) + pi, gx = ci[CI_X] - (6 - K) + pj;
     const bool in_img = cone && gy >= 0 && gy < H && gx >= 0 && gx < W;
     float v[2][4];
 #pragma unroll
@@ -212,7 +214,6 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
   __shared__ SplitSmem sm;
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, r = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int H = a.H, W = a.W;
   // ---- wave roles (see the table above); wave 7 owns no layer
   const int K = wave < 3 ? 2 : wave < 5 ? 3 : wave == 5 ? 4 : wave == 6 ? 5 : 0;
   const int run0 = (wave < 3) ? 2 * wave : (wave == 4) ? 2 : 0;
@@ -282,59 +283,70 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
   if (blockIdx.x == 0 && tid == 0) a.stats[0] = total;
   if (nloc <= 0) return;  // uniform over the block
 
-  // Cone i's coordinates go to cinfo[i % 16] (wave 7, lane 0). Its list
-  // entry is loaded one step before it is decoded, and its window values one
-  // step before they are staged, so no wave waits on global memory inside a
-  // step.
-  // the segment of entry e is the last with spre <= e; entries are taken in
-  // order, so the segment pointer only moves forward
-  int seg = 0;
-  auto load_entry = [&](int i) -> uint32_t {
+  // Cone i's record goes to cinfo[i % 16] (wave 7, lane 0). Its list entry
+  // is loaded one step before it is decoded, and its window values one step
+  // before they are staged, so no wave waits on global memory inside a step
+  // (except for the page record, which is loaded when the page changes).
+  // The segment of entry e is the last with spre <= e; entries are taken in
+  // order, so the segment pointer only moves forward.
+  int seg = 0, cpage = -1;
+  hs::Page cp = {};
+  uint64_t cseed = 0;
+  auto load_entry = [&](int i) -> uint64_t {
     const int e = cb0 + i;
     while (seg + 1 < a.nseg && sm.spre[seg + 1] <= e) ++seg;
     return a.seglist[(size_t)seg * a.seg_cap + (e - sm.spre[seg])];
   };
-  auto put_cone = [&](int i, uint32_t u) {
+  auto put_cone = [&](int i, uint64_t u) {
     int* d = sm.cinfo[i & 15];
     if (i >= nloc) {
-      d[0] = -1;
-      d[1] = d[2] = d[3] = d[4] = 0;
+      d[CI_O] = -1;
+      d[CI_Y] = d[CI_X] = d[CI_BIT] = d[CI_PG] = d[CI_SLO] = d[CI_SHI] = 0;
+      d[CI_H] = d[CI_W] = 1;
       return;
     }
-    const uint32_t o = u & ~BIT_FLAG;
-    const int b = (int)(o / ((uint32_t)H * W));
-    const int rem = (int)(o - (uint32_t)b * H * W);
-    d[0] = (int)o;
-    d[1] = b;
-    d[2] = rem / W;
-    d[3] = rem - (rem / W) * W;
-    d[4] = (u & BIT_FLAG) ? 1 : 0;
+    const int page = hs::entry_page(u);
+    if (page != cpage) {
+      cpage = page;
+      cp = a.pages[page];
+      cseed = a.seeds[page];
+    }
+    const int o = (int)hs::entry_pixel(u);
+    const int local = (int)(o - cp.off);
+    d[CI_O] = o;
+    d[CI_Y] = local / cp.W;
+    d[CI_X] = local - (local / cp.W) * cp.W;
+    d[CI_BIT] = hs::entry_bit(u);
+    d[CI_PG] = page;
+    d[CI_H] = cp.H;
+    d[CI_W] = cp.W;
+    d[CI_SLO] = (int)(uint32_t)cseed;
+    d[CI_SHI] = (int)(uint32_t)(cseed >> 32);
   };
   // staging: window position j = lane (wave 3), 64 + lane + 64 k (wave 7);
   // the contone values and the image seed are loaded a step ahead
   constexpr int NSTG = 2;
   auto stage_pos = [&](int k) { return wave == 3 ? (k == 0 ? lane : 999) : 64 + lane + 64 * k; };
   float pcv[NSTG];
-  uint64_t psd = 0;
   auto prefetch_window = [&](int i) {
     const int* ci = sm.cinfo[i & 15];
+    const int H = ci[CI_H], W = ci[CI_W];
 #pragma unroll
     for (int k = 0; k < NSTG; ++k) {
       const int j = stage_pos(k);
       pcv[k] = 0.f;
-      if (j < 169 && i < nloc) {
-        const int gy = ci[2] - 6 + j / 13, gx = ci[3] - 6 + j % 13;
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-          pcv[k] = a.contone[((size_t)ci[1] * H + gy) * W + gx];
+      if (j < 169 && i < nloc && ci[CI_O] >= 0) {
+        const int dy = j / 13 - 6, dx = j % 13 - 6;
+        const int gy = ci[CI_Y] + dy, gx = ci[CI_X] + dx;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) pcv[k] = a.contone[ci[CI_O] + dy * W + dx];
       }
     }
-    if (i < nloc && ci[0] >= 0) psd = a.seeds[ci[1]];
   };
   for (int i = tid; i < 288; i += SPLIT_THREADS) sm.w6[i] = a.w[HS_W6 + i];
   const float b6 = a.w[HS_B6];
   // prologue: cones 0..2 decoded, cone 3's entry in flight, cone 0's window
   // values in flight
-  uint32_t pend_u = 0;
+  uint64_t pend_u = 0;
   if (wave == 7 && lane == 0) {
     for (int i = 0; i < 3; ++i) put_cone(i, i < nloc ? load_entry(i) : 0u);
     if (3 < nloc) pend_u = load_entry(3);
@@ -348,14 +360,16 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
     if (stager) {
       if (t < nloc) {
         const int* ci = sm.cinfo[t & 15];
+        const int H = ci[CI_H], W = ci[CI_W];
+        const uint64_t sd = (uint64_t)(uint32_t)ci[CI_SLO] | ((uint64_t)(uint32_t)ci[CI_SHI] << 32);
 #pragma unroll
         for (int k = 0; k < NSTG; ++k) {
           const int j = stage_pos(k);
           if (j < 169) {
-            const int gy = ci[2] - 6 + j / 13, gx = ci[3] - 6 + j % 13;
+            const int gy = ci[CI_Y] - 6 + j / 13, gx = ci[CI_X] - 6 + j % 13;
             float zv = 0.f;
-            if (ci[0] >= 0 && gy >= 0 && gy < H && gx >= 0 && gx < W)
-              zv = hs_noise(psd, (uint64_t)gy * W + gx, 0u, a.kind);
+            if (ci[CI_O] >= 0 && gy >= 0 && gy < H && gx >= 0 && gx < W)
+              zv = hs_noise(sd, (uint64_t)gy * W + gx, 0u, a.kind);
             sm.s0[t & 1][j * 2] = pcv[k];
             sm.s0[t & 1][j * 2 + 1] = zv;
           }
@@ -375,7 +389,8 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
     if (l1runs && t >= 1 && t - 1 < nloc) {
       const int i = t - 1, sl = i & 1;
       const int* ci = sm.cinfo[i & 15];
-      const bool cone = ci[0] >= 0;
+      const bool cone = ci[CI_O] >= 0;
+      const int H = ci[CI_H], W = ci[CI_W];
       const bf16x8_t ah0 = sm.w1[0][0][lane], al0 = sm.w1[1][0][lane];
       const bf16x8_t ah1 = sm.w1[0][1][lane], al1 = sm.w1[1][1][lane];
       const f32x4_t bb0 = *(const f32x4_t*)&sm.b1v[4 * g];
@@ -402,7 +417,7 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
         const f32x4_t s1v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, z4, 0, 0, 0) +
                             (__builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, z4, 0, 0, 0) +
                              __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, z4, 0, 0, 0));
-        const int gy = ci[2] - 5 + pi, gx = ci[3] - 5 + pj;
+        const int gy = ci[CI_Y] - 5 + pi, gx = ci[CI_X] - 5 + pj;
         const bool in_img = cone && gy >= 0 && gy < H && gx >= 0 && gx < W;
         float v[2][4];
 #pragma unroll
@@ -421,20 +436,16 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
         const int* ci = sm.cinfo[i & 15];
         switch (K) {
           case 2:
-            split_layer<2, 2>(wh, sm.wlo[0], bias, sm.b1[sl], sm.b2[sl], nullptr, ci, run0, H, W,
-                                lane);
+            split_layer<2, 2>(wh, sm.wlo[0], bias, sm.b1[sl], sm.b2[sl], nullptr, ci, run0, lane);
             break;
           case 3:
-            split_layer<3, 2>(wh, sm.wlo[1], bias, sm.b2[sl], sm.b3[sl], nullptr, ci, run0, H, W,
-                                lane);
+            split_layer<3, 2>(wh, sm.wlo[1], bias, sm.b2[sl], sm.b3[sl], nullptr, ci, run0, lane);
             break;
           case 4:
-            split_layer<4, 2>(wh, sm.wlo[2], bias, sm.b3[sl], sm.b4[sl], nullptr, ci, run0, H, W,
-                                lane);
+            split_layer<4, 2>(wh, sm.wlo[2], bias, sm.b3[sl], sm.b4[sl], nullptr, ci, run0, lane);
             break;
           default:
-            split_layer<5, 1>(wh, sm.wlo[3], bias, sm.b4[sl], nullptr, sm.l5[sl], ci, run0, H, W,
-                              lane);
+            split_layer<5, 1>(wh, sm.wlo[3], bias, sm.b4[sl], nullptr, sm.l5[sl], ci, run0, lane);
             break;
         }
       }
@@ -443,7 +454,7 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
     if (wave == 3 && t >= 6 && t - 6 < nloc) {
       const int i = t - 6;
       const int* ci = sm.cinfo[i & 15];
-      const int o = ci[0];
+      const int o = ci[CI_O];
       if (o >= 0) {
         const float* l5 = sm.l5[i & 1];
         float part = 0.f;
@@ -457,11 +468,13 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
           const float xl = part + b6;
           if (fabsf(xl) >= a.tau2) {
             const int nb = xl >= 0.f ? 1 : 0;
-            if (ci[4] != nb) atomicAdd(&a.stats[1], 1);
+            if (ci[CI_BIT] != nb) atomicAdd(&a.stats[1], 1);
             a.bits[o] = (uint8_t)nb;
             if (a.logits) a.logits[o] = xl;
           } else {
-            a.list2[atomicAdd(a.count2, 1)] = (uint32_t)o | (ci[4] ? BIT_FLAG : 0u);
+            a.list2[atomicAdd(a.count2, 1)] = (uint64_t)(uint32_t)o |
+                                              ((uint64_t)(uint32_t)ci[CI_PG] << 31) |
+                                              ((uint64_t)ci[CI_BIT] << 63);
           }
         }
       }
@@ -537,8 +550,9 @@ HS_DEV void fp32_layer(const float* __restrict__ src, float* __restrict__ dst,
 
 __global__ __launch_bounds__(F32_THREADS, 2) void recheck_fp32_kernel(
     const float* __restrict__ w, const float* __restrict__ contone,
-    const uint64_t* __restrict__ seeds, int H, int W, int kind, const uint32_t* __restrict__ list,
-    const int* __restrict__ count, const f32x4_t* __restrict__ wt, uint8_t* __restrict__ bits,
+    const uint64_t* __restrict__ seeds, const hs::Page* __restrict__ pages, int kind,
+    const uint64_t* __restrict__ list, const int* __restrict__ count,
+    const f32x4_t* __restrict__ wt, uint8_t* __restrict__ bits,
     float* __restrict__ logits, int32_t* __restrict__ stats, int count_slot) {
   __shared__ float s0[13 * 13 * 2];
   __shared__ float bufA[11 * 11 * RS], bufB[9 * 9 * RS];
@@ -559,10 +573,14 @@ __global__ __launch_bounds__(F32_THREADS, 2) void recheck_fp32_kernel(
     for (int j = 0; j < F32_VPT; ++j) ((f32x4_t*)sw)[tid + F32_THREADS * j] = pw[j];
   };
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
-    const uint32_t u = list[it], o = u & ~BIT_FLAG;
-    const int b = (int)(o / ((uint32_t)H * W));
-    const int rem = (int)(o - (uint32_t)b * H * W), y = rem / W, x = rem - (rem / W) * W;
-    const size_t img = (size_t)b * H * W;
+    const uint64_t u = list[it];
+    const uint32_t o = hs::entry_pixel(u);
+    const int page = hs::entry_page(u);
+    const hs::Page P = pages[page];
+    const int H = P.H, W = P.W;
+    const int rem = (int)(o - P.off), y = rem / W, x = rem - (rem / W) * W;
+    const size_t img = (size_t)P.off;
+    const uint64_t seed = seeds[page];
     fetch(2);
     __syncthreads();
     for (int i = tid; i < 169; i += F32_THREADS) {
@@ -571,7 +589,7 @@ __global__ __launch_bounds__(F32_THREADS, 2) void recheck_fp32_kernel(
       if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
         const uint64_t a = (uint64_t)gy * W + gx;
         cv = contone[img + a];
-        zv = hs_noise(seeds[b], a, 0u, kind);
+        zv = hs_noise(seed, a, 0u, kind);
       }
       s0[i * 2] = cv;
       s0[i * 2 + 1] = zv;
@@ -620,8 +638,8 @@ __global__ __launch_bounds__(F32_THREADS, 2) void recheck_fp32_kernel(
       part = hs_wave_sum(part);
       if (tid == 0) {
         const float xl = part + w[HS_B6];
-        const uint32_t nb = xl >= 0.f ? 1u : 0u;
-        if (nb != (u >> 31)) atomicAdd(&stats[1], 1);
+        const int nb = xl >= 0.f ? 1 : 0;
+        if (nb != hs::entry_bit(u)) atomicAdd(&stats[1], 1);
         bits[o] = (uint8_t)nb;
         if (logits) logits[o] = xl;
       }
@@ -645,9 +663,9 @@ hipError_t launch_split_pack(const float* w, void* whi, void* wlo, void* wt, hip
 }
 
 hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
-                                int H, int W, int kind, const uint32_t* seglist,
+                                const Page* pages, int kind, const uint64_t* seglist,
                                 const int* seg_count, int nseg, long long seg_cap,
-                                const void* whi, const void* wlo, float tau2, uint32_t* list2,
+                                const void* whi, const void* wlo, float tau2, uint64_t* list2,
                                 int* count2, uint8_t* bits, float* logits, int32_t* stats,
                                 int num_cus, hipStream_t s) {
   if (nseg < 1 || nseg > SPLIT_MAXSEG) return hipErrorInvalidValue;
@@ -655,8 +673,7 @@ hipError_t launch_recheck_split(const float* w, const float* contone, const uint
   a.w = w;
   a.contone = contone;
   a.seeds = seeds;
-  a.H = H;
-  a.W = W;
+  a.pages = pages;
   a.kind = kind;
   a.nseg = nseg;
   a.seglist = seglist;
@@ -675,10 +692,10 @@ hipError_t launch_recheck_split(const float* w, const float* contone, const uint
 }
 
 hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,
-                               int H, int W, int kind, const uint32_t* list, const int* count,
-                               const void* wt, uint8_t* bits, float* logits, int32_t* stats,
-                               int count_slot, int num_cus, hipStream_t s) {
-  recheck_fp32_kernel<<<2 * num_cus, F32_THREADS, 0, s>>>(w, contone, seeds, H, W, kind, list,
+                               const Page* pages, int kind, const uint64_t* list,
+                               const int* count, const void* wt, uint8_t* bits, float* logits,
+                               int32_t* stats, int count_slot, int num_cus, hipStream_t s) {
+  recheck_fp32_kernel<<<2 * num_cus, F32_THREADS, 0, s>>>(w, contone, seeds, pages, kind, list,
                                                           count, (const f32x4_t*)wt, bits, logits,
                                                           stats, count_slot);
   return hipGetLastError();

@@ -59,6 +59,38 @@ def contone(seed, H, W):
     return np.clip(img, 0.0, 1.0).astype(np.float32)
 
 
+def contone_torch(seed, H, W, device):
+    """The contone recipe of `contone` on a torch device, for page-sized
+    inputs: the same ramp and edge parameters (numpy's generator), the
+    texture noise drawn from torch's generator seeded with `seed` instead of
+    numpy's, so the texture realisation differs from `contone`'s."""
+    import torch
+    prm = _rng(seed, 3)
+    a0 = prm.uniform(0.25, 0.75)
+    a1, a2 = prm.uniform(-0.25, 0.25, size=2)
+    s = prm.uniform(-0.15, 0.15, size=8)
+    phi = prm.uniform(0.0, 2.0 * np.pi, size=8)
+    px = prm.uniform(0.0, W, size=8)
+    py = prm.uniform(0.0, H, size=8)
+    f64 = torch.float64
+    y = torch.arange(H, dtype=f64, device=device)[:, None]
+    x = torch.arange(W, dtype=f64, device=device)[None, :]
+    img = a0 + a1 * x / max(W - 1, 1) + a2 * y / max(H - 1, 1)
+    for k in range(8):
+        img = img + s[k] * (((x - px[k]) * np.cos(phi[k]) + (y - py[k]) * np.sin(phi[k])) >= 0)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) & ((1 << 63) - 1))
+    n = torch.rand((H, W), generator=gen, dtype=torch.float32, device=device).to(f64) - 0.5
+    g = torch.tensor(_blur_kernel(), dtype=f64, device=device)
+    r = (g.numel() - 1) // 2
+    p = torch.nn.functional.pad(n[None, None], (0, 0, r, r), mode="replicate")
+    n = torch.nn.functional.conv2d(p, g.view(1, 1, -1, 1))
+    p = torch.nn.functional.pad(n, (r, r, 0, 0), mode="replicate")
+    n = torch.nn.functional.conv2d(p, g.view(1, 1, 1, -1))[0, 0]
+    img = img + 4.0 * n
+    return img.clamp(0.0, 1.0).to(torch.float32)
+
+
 def contone_batch(seeds, H, W):
     return np.stack([contone(s, H, W) for s in seeds]).astype(np.float32)
 

@@ -108,6 +108,36 @@ def test_infer_argument_errors(lib):
     assert lib.halftone_infer(*a) == hb.HS_EWORKSPACE
 
 
+def test_pages_argument_errors(lib):
+    import numpy as np
+    p = _fake()
+    sh = hb.page_shapes_array([(8, 8), (3, 20)])
+    shp = sh.ctypes.data_as(ctypes.c_void_p)
+    ws = lib.halftone_infer_pages_workspace_size(2, shp, hb.HS_BF16)
+    assert ws > lib.halftone_infer_workspace_size(1, 8, 8, hb.HS_BF16) > 0
+    assert lib.halftone_infer_pages_workspace_size(0, shp, hb.HS_BF16) == 0
+    bad = hb.page_shapes_array([(8, 8), (0, 20)])
+    assert lib.halftone_infer_pages_workspace_size(2, bad.ctypes.data_as(ctypes.c_void_p),
+                                                   hb.HS_BF16) == 0
+    huge = hb.page_shapes_array([(65536, 32768)])  # 2^31 pixels
+    assert lib.halftone_infer_pages_workspace_size(1, huge.ctypes.data_as(ctypes.c_void_p),
+                                                   hb.HS_BF16) == 0
+    args = [p, p, p, 2, shp, 0, hb.HS_BF16, 0.05, p, None, None, p, ws, None]
+    a = list(args); a[1] = None
+    assert lib.halftone_infer_pages(*a) == hb.HS_EINVAL
+    a = list(args); a[4] = bad.ctypes.data_as(ctypes.c_void_p)
+    assert lib.halftone_infer_pages(*a) == hb.HS_ESHAPE
+    a = list(args); a[3] = 0
+    assert lib.halftone_infer_pages(*a) == hb.HS_ESHAPE
+    a = list(args); a[6] = 9
+    assert lib.halftone_infer_pages(*a) == hb.HS_EUNSUPPORTED
+    a = list(args); a[12] = ws - 1
+    assert lib.halftone_infer_pages(*a) == hb.HS_EWORKSPACE
+    # the FP32 path runs page by page in the workspace of the largest page
+    ws32 = lib.halftone_infer_pages_workspace_size(2, shp, hb.HS_FP32)
+    assert ws32 == lib.halftone_infer_workspace_size(1, 8, 8, hb.HS_FP32)
+
+
 def test_loss_argument_errors(lib):
     p = _fake()
     prm = hb.default_loss_params()

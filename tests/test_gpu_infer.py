@@ -10,6 +10,7 @@ import torch
 
 from gpu_common import P_MARGIN, device, inputs, parity_mask, seeds_t, to_dev
 from paper_2304_12152_amd import binding as hb
+from paper_2304_12152_amd import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -149,3 +150,98 @@ def window_logit(orc, wd, cimg, seed, y, x):
     cc = cimg[y0:y1, x0:x1].astype(np.float64)
     return float(orc.policy_forward_window(wd, cc, zc, y - y0, y - y0 + 1, x - x0,
                                            x - x0 + 1)[0, 0])
+
+
+PAGES = [(1, 1), (3, 200), (37, 45), (150, 90), (64, 300), (13, 13), (130, 117)]
+
+
+def _pages_inputs(shapes, seed0):
+    w = synth.he_weights(42)
+    seeds = [seed0 + i for i in range(len(shapes))]
+    cs = [synth.contone(s, h, ww) for s, (h, ww) in zip(seeds, shapes)]
+    flat = np.concatenate([c.ravel() for c in cs]).astype(np.float32)
+    return w, seeds, cs, flat
+
+
+@pytest.mark.parametrize("prec", [hb.HS_BF16, hb.HS_FP32])
+def test_pages_match_oracle(orc, prec):
+    """Pages of different sizes in one call (one fused launch for BF16):
+    every page's bits equal the oracle's off the margin."""
+    _say("infer pages", prec)
+    w, seeds, cs, flat = _pages_inputs(PAGES, 41)
+    bits, lg, st = hb.halftone_infer_pages(to_dev(w), to_dev(flat), seeds_t(seeds), PAGES,
+                                           precision=prec, recheck_tau=0.055, logits=True,
+                                           stats=True)
+    bits, lg, st = bits.cpu().numpy(), lg.cpu().numpy(), st.cpu().numpy()
+    off = 0
+    nnear = 0
+    for (h, ww), s, c in zip(PAGES, seeds, cs):
+        ref = _oracle_logits(orc, w, c[None], [s], 0)[0]
+        b = bits[off:off + h * ww].reshape(h, ww)
+        l = lg[off:off + h * ww].reshape(h, ww)
+        m = parity_mask(orc, ref)
+        assert np.array_equal(b[m], (ref >= 0)[m].astype(np.uint8)), (h, ww)
+        if prec == hb.HS_BF16:
+            near = np.abs(l) < 0.055
+            nnear += int(near.sum())
+            assert np.abs(l[near] - ref[near]).max(initial=0.0) <= 5e-4, (h, ww)
+            assert np.abs(l - ref).max() < 0.055
+        else:
+            assert np.abs(l - ref).max() <= 2e-5 * max(1.0, np.abs(ref).max())
+        off += h * ww
+    if prec == hb.HS_BF16:
+        assert st[0] >= nnear > 0
+
+
+def test_pages_of_one_size_equal_the_batch_call(orc):
+    """B equal pages through the pages entry point give exactly the bits and
+    logits of the uniform batch call (same kernels, same page table)."""
+    B, H, W = 3, 70, 150
+    seeds = [61, 62, 63]
+    w, c = inputs(seeds, H, W)
+    b1, l1 = hb.halftone_infer(to_dev(w), to_dev(c), seeds_t(seeds), 0, hb.HS_BF16, 0.055,
+                               logits=True)
+    b2, l2 = hb.halftone_infer_pages(to_dev(w), to_dev(c.ravel()), seeds_t(seeds),
+                                     [(H, W)] * B, precision=hb.HS_BF16, recheck_tau=0.055,
+                                     logits=True)
+    assert torch.equal(b1.reshape(-1), b2) and torch.equal(l1.reshape(-1), l2)
+
+
+def test_c5_pages_full_size_sampled(orc):
+    """The uneven-batch workload at its full size: 48 pages of 600..4960 x
+    800..7016 (about 0.5 Gpx) in one call; the oracle is evaluated one
+    receptive field at a time on sampled pixels of every page (corners,
+    centre, random points)."""
+    shapes = synth.page_sizes(3_000_000)
+    seeds = [3_000_000 + i for i in range(len(shapes))]
+    dev = device()
+    _say("infer C5 pages", sum(h * w for h, w in shapes))
+    flat = torch.cat([synth.contone_torch(s, h, w, dev).reshape(-1)
+                      for s, (h, w) in zip(seeds, shapes)])
+    w = synth.he_weights(42)
+    bits, lg, st = hb.halftone_infer_pages(to_dev(w), flat, seeds_t(seeds), shapes,
+                                           precision=hb.HS_BF16, recheck_tau=0.055,
+                                           logits=True, stats=True)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert st[0] > 0 and 0 <= st[2] <= st[0]
+    rng = np.random.default_rng(5)
+    wd = w.astype(np.float64)
+    off = 0
+    for (h, ww), s in zip(shapes, seeds):
+        pts = [(0, 0), (0, ww - 1), (h - 1, 0), (h - 1, ww - 1), (h // 2, ww // 2)]
+        pts += [tuple(int(v) for v in p) for p in rng.integers(0, [h, ww], size=(4, 2))]
+        for (y, x) in pts:
+            y0, y1, x0, x1 = max(0, y - 6), min(h, y + 7), max(0, x - 6), min(ww, x + 7)
+            rows = [flat[off + yy * ww + x0: off + yy * ww + x1] for yy in range(y0, y1)]
+            cimg = torch.stack(rows).cpu().numpy()
+            zc = np.array([[orc.normal(s, yy * ww + xx, 1, 0) for xx in range(x0, x1)]
+                           for yy in range(y0, y1)])
+            ref = float(orc.policy_forward_window(wd, cimg.astype(np.float64), zc, y - y0,
+                                                  y - y0 + 1, x - x0, x - x0 + 1)[0, 0])
+            o = off + y * ww + x
+            if abs(orc.sigmoid(ref) - 0.5) > P_MARGIN:
+                assert int(bits[o]) == int(ref >= 0), ((h, ww), y, x, ref)
+            lo = float(lg[o])
+            assert abs(lo - ref) < (5e-4 if abs(lo) < 0.055 else 0.055), ((h, ww), y, x)
+        off += h * ww
