@@ -11,7 +11,11 @@ The JSON line also carries:
   cpu_baseline -- the CPU oracle on a bounded sample of the same workload;
   fp32         -- the FP32 path on the same batch (speedup stated);
   train        -- policy_train_step steps/s on 32 x 256 x 256 crops plus 64
-                  constant-gray 64 x 64 images (BF16 activations).
+                  constant-gray 64 x 64 images (BF16 activations), with the
+                  conv FLOP rate against the BF16 matrix peak;
+  pages        -- the uneven batch: 48 pages of 600..4960 x 800..7016 in one
+                  halftone_infer_pages call (BF16 + recheck), Mpx/s and the
+                  fused launch's FLOP rate.
 """
 import argparse
 import hashlib
@@ -69,6 +73,47 @@ def cpu_baseline(c_img, seed, w):
                       "threshold on the 512x512 top-left crop of workload image 0; %.1f s" % dt}
 
 
+def bench_pages(hb, synth, torch, dev, wt, steps, tau):
+    """The uneven batch: 48 pages (sizes from seed 3,000,000, page seeds
+    3,000,000 + i), contones made on the device with the same recipe."""
+    shapes = synth.page_sizes(3_000_000)
+    seeds = [3_000_000 + i for i in range(len(shapes))]
+    log("generating the 48-page batch")
+    flat = torch.cat([synth.contone_torch(s, h, w, dev).reshape(-1)
+                      for s, (h, w) in zip(seeds, shapes)])
+    st = torch.tensor(seeds, dtype=torch.int64, device=dev)
+    npx = flat.numel()
+    sh = hb.page_shapes_array(shapes)
+    ws = torch.empty(hb.lib().halftone_infer_pages_workspace_size(
+        len(shapes), sh.ctypes.data_as(hb.ctypes.c_void_p), hb.HS_BF16), dtype=torch.uint8,
+        device=dev)
+
+    def run(stats=False):
+        return hb.halftone_infer_pages(wt, flat, st, shapes, precision=hb.HS_BF16,
+                                       recheck_tau=tau, stats=stats, workspace=ws)
+
+    run()
+    torch.cuda.synchronize()
+    hb.halftone_profile_start()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kern_ms, launches = hb.halftone_profile_stop()
+    kern_s = kern_ms / 1e3 / max(launches, 1)
+    _, stats = run(stats=True)
+    stats = stats.cpu().tolist()
+    ach = FLOP_PER_PX * npx / kern_s / 1e12
+    log("pages: %.3f ms, %.1f Mpx/s" % (dt * 1e3, npx / dt / 1e6))
+    return {"value": round(npx / dt / 1e6, 1), "unit": "Mpx/s", "pages": len(shapes),
+            "mpx": round(npx / 1e6, 2), "ms_per_call": round(dt * 1e3, 3),
+            "fused_kernel_ms": round(kern_s * 1e3, 3), "fused_tflops": round(ach, 1),
+            "fused_mfma_frac": round(ach / PEAK_BF16_TFLOPS, 4),
+            "rechecked": stats[0], "fp32_recomputed": stats[2],
+            "recheck_fraction": round(stats[0] / npx, 6)}
+
+
 def calibrate(hb, synth, torch, dev):
     """Logit error of the BF16 pass and of the split-BF16 recheck against the
     FP32 path, on calibration seeds disjoint from the benchmark's."""
@@ -114,6 +159,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--train-steps", type=int, default=5)
+    ap.add_argument("--no-pages", action="store_true")
+    ap.add_argument("--page-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the hot path on a single "
@@ -226,10 +273,17 @@ def main():
             hb.policy_train_step(state, tc, ts, gray, gs, 2 + i, 1000)
         torch.cuda.synchronize()
         sps = args.train_steps / (time.perf_counter() - t2)
+        # conv work per step: forward 75,456 + input gradient 74,304 + weight
+        # gradient 75,456 FLOP per pixel of the batch and of the gray side batch
+        conv_flop = (Bt * Ht * Wt + Bg * 64 * 64) * (75456 + 74304 + 75456)
         extra["train"] = {"value": round(sps, 2), "unit": "steps/s",
+                          "conv_tflops": round(conv_flop * sps / 1e12, 1),
+                          "mfma_frac": round(conv_flop * sps / 1e12 / PEAK_BF16_TFLOPS, 4),
                           "config": "32 x 256x256 crops + 64 constant-gray 64x64, BF16 "
                                     "activations, FP32 master weights, Adam"}
         log("train: %.2f steps/s" % sps)
+    if not args.no_pages:
+        extra["pages"] = bench_pages(hb, synth, torch, dev, wt, args.page_steps, args.tau)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpx/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
