@@ -184,11 +184,15 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T* __restrict__ in
                                                         float* __restrict__ probs, float tau,
                                                         uint32_t* __restrict__ list,
                                                         int* __restrict__ count) {
-  __shared__ float s[18 * 18 * LP];
-  __shared__ float sw[32 * 9 + 1];
+  // staged positions 16-byte aligned (stride LQ = 36 floats: the 16 lanes of
+  // a tile row read 16 distinct groups of 4 banks), weights as [tap][ci]
+  constexpr int LQ = 36;
+  __shared__ __attribute__((aligned(16))) float s[18 * 18 * LQ];
+  __shared__ __attribute__((aligned(16))) float sw[9 * 32 + 4];
   const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16;
   const size_t img = (size_t)b * H * W;
-  for (int i = threadIdx.x; i < 32 * 9 + 1; i += 256) sw[i] = w[HS_W6 + i];
+  for (int i = threadIdx.x; i < 32 * 9; i += 256) sw[(i % 9) * 32 + i / 9] = w[HS_W6 + i];
+  if (threadIdx.x == 0) sw[9 * 32] = w[HS_B6];
   for (int i = threadIdx.x; i < 18 * 18 * 8; i += 256) {
     const int p = i >> 3, q = (i & 7) * 4;
     const int ly = p / 18, lx = p - ly * 18, gy = y0 + ly - 1, gx = x0 + lx - 1;
@@ -198,8 +202,7 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T* __restrict__ in
 #pragma unroll
       for (int k = 0; k < 4; ++k) v[k] = hs_to_f(src[k]);
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) s[p * LP + q + k] = v[k];
+    *(f32x4_t*)(s + p * LQ + q) = f32x4_t{v[0], v[1], v[2], v[3]};
   }
   __syncthreads();
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15, gy = y0 + ty, gx = x0 + tx;
@@ -208,9 +211,16 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T* __restrict__ in
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
     const int dy = t / 3, dx = t - (t / 3) * 3;
-    const float* sp = s + ((ty + dy) * 18 + tx + dx) * LP;
+    const float* sp = s + ((ty + dy) * 18 + tx + dx) * LQ;
 #pragma unroll
-    for (int ci = 0; ci < 32; ++ci) x = fmaf(sw[ci * 9 + t], sp[ci], x);
+    for (int c4 = 0; c4 < 32; c4 += 4) {
+      const f32x4_t a = *(const f32x4_t*)(sp + c4);
+      const f32x4_t wv = *(const f32x4_t*)(sw + t * 32 + c4);
+      x = fmaf(wv[0], a[0], x);
+      x = fmaf(wv[1], a[1], x);
+      x = fmaf(wv[2], a[2], x);
+      x = fmaf(wv[3], a[3], x);
+    }
   }
   const size_t o = img + (size_t)gy * W + gx;
   if (MODE == 0) {
@@ -479,6 +489,11 @@ __global__ __launch_bounds__(256) void wgrad32_bf16_kernel(const __bf16* __restr
 // Weight gradient of the first layer (2 -> 32) on the vector ALUs.
 // Tile = 16 x 16 pixels; thread i < 608 owns parameter i of layer 1.
 // ---------------------------------------------------------------------------
+// Weight gradient of layer 1 (2 -> 32): thread (co = tid % 32, pixel group
+// pg = tid / 32) of a 16 x 16 tile owns the 18 weights (channel, tap) of
+// output channel co and its bias over the tile's rows 2 pg, 2 pg + 1, sliding
+// 3 x 3 register windows of c and z along each row. The eight pixel groups
+// are summed in a fixed order at the end.
 template <typename T>
 __global__ __launch_bounds__(256) void wgrad_first_kernel(const float* __restrict__ contone,
                                                           const float* __restrict__ z,
@@ -487,8 +502,12 @@ __global__ __launch_bounds__(256) void wgrad_first_kernel(const float* __restric
                                                           int accumulate) {
   __shared__ float sg[256 * 33];
   __shared__ float sc[18 * 18], sz[18 * 18];
+  __shared__ float sred[8][609];
   const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16, ntiles = B * tiles_x * tiles_y;
-  float acc[3] = {0.f, 0.f, 0.f};
+  const int co = threadIdx.x & 31, pg = threadIdx.x >> 5;
+  float ac[9], az[9], accb = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) ac[t] = az[t] = 0.0f;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
     const int y0 = (rem / tiles_x) * 16, x0 = (rem % tiles_x) * 16;
@@ -513,44 +532,76 @@ __global__ __launch_bounds__(256) void wgrad_first_kernel(const float* __restric
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int prm = threadIdx.x + 256 * k;
-      if (prm >= 608) break;
-      float s = 0.0f;
-      if (prm < 576) {
-        const int co = prm / 18, ci = (prm / 9) & 1, t = prm % 9, dy = t / 3, dx = t % 3;
-        const float* src = ci ? sz : sc;
-        for (int p = 0; p < 256; ++p)
-          s = fmaf(sg[p * 33 + co], src[((p >> 4) + dy) * 18 + (p & 15) + dx], s);
-      } else {
-        const int co = prm - 576;
-        for (int p = 0; p < 256; ++p) s += sg[p * 33 + co];
+    for (int rr = 0; rr < 2; ++rr) {
+      const int py = 2 * pg + rr;
+      float wc[3][3], wz[3][3];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          wc[dy][dx + 1] = sc[(py + dy) * 18 + dx];
+          wz[dy][dx + 1] = sz[(py + dy) * 18 + dx];
+        }
+      for (int px = 0; px < 16; ++px) {
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          wc[dy][0] = wc[dy][1];
+          wc[dy][1] = wc[dy][2];
+          wc[dy][2] = sc[(py + dy) * 18 + px + 2];
+          wz[dy][0] = wz[dy][1];
+          wz[dy][1] = wz[dy][2];
+          wz[dy][2] = sz[(py + dy) * 18 + px + 2];
+        }
+        const float gv = sg[(py * 16 + px) * 33 + co];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          ac[t] = fmaf(gv, wc[t / 3][t % 3], ac[t]);
+          az[t] = fmaf(gv, wz[t / 3][t % 3], az[t]);
+        }
+        accb += gv;
       }
-      acc[k] += s;
     }
   }
-  float* row = partials + (size_t)blockIdx.x * hs::NPARAM + HS_W1;
+  // W1[co][ci][t] at co * 18 + ci * 9 + t, then the biases at 576 + co
+  __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int prm = threadIdx.x + 256 * k;
-    if (prm < 608) row[prm] = accumulate ? row[prm] + acc[k] : acc[k];
+  for (int t = 0; t < 9; ++t) {
+    sred[pg][co * 18 + t] = ac[t];
+    sred[pg][co * 18 + 9 + t] = az[t];
+  }
+  sred[pg][576 + co] = accb;
+  __syncthreads();
+  float* row = partials + (size_t)blockIdx.x * hs::NPARAM + HS_W1;
+  for (int prm = threadIdx.x; prm < 608; prm += 256) {
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += sred[k][prm];
+    row[prm] = accumulate ? row[prm] + s : s;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Weight gradient of the last layer (32 -> 1): dW6[ci][t] = sum g6 a5[+t][ci].
 // ---------------------------------------------------------------------------
+// Thread (ci = tid % 32, pixel group pg = tid / 32) of a 16 x 16 tile owns
+// the nine taps of input channel ci over the tile's rows 2 pg, 2 pg + 1; it
+// slides a 3 x 3 register window of the staged activations along each row
+// (three new LDS reads per pixel for nine FMAs). The eight pixel groups are
+// summed in a fixed order at the end.
 template <typename T>
-__global__ __launch_bounds__(320) void wgrad_last_kernel(const T* __restrict__ a5,
+__global__ __launch_bounds__(256) void wgrad_last_kernel(const T* __restrict__ a5,
                                                          const float* __restrict__ g6, int B,
                                                          int H, int W,
                                                          float* __restrict__ partials,
                                                          int accumulate) {
   __shared__ float sa[18 * 18 * LP];
   __shared__ float sg[256];
+  __shared__ float sred[8][289];
   const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16, ntiles = B * tiles_x * tiles_y;
-  float acc = 0.0f;
-  const int prm = threadIdx.x;  // 0..287 weights, 288 bias
+  const int ci = threadIdx.x & 31, pg = threadIdx.x >> 5;
+  float acc[9], accb = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[t] = 0.0f;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
     const int y0 = (rem / tiles_x) * 16, x0 = (rem % tiles_x) * 16;
@@ -573,21 +624,40 @@ __global__ __launch_bounds__(320) void wgrad_last_kernel(const T* __restrict__ a
       sg[i] = (gy < H && gx < W) ? g6[img + (size_t)gy * W + gx] : 0.0f;
     }
     __syncthreads();
-    if (prm < 288) {
-      const int ci = prm / 9, t = prm % 9, dy = t / 3, dx = t % 3;
-      float s = 0.0f;
-      for (int p = 0; p < 256; ++p)
-        s = fmaf(sg[p], sa[(((p >> 4) + dy) * 18 + (p & 15) + dx) * LP + ci], s);
-      acc += s;
-    } else if (prm == 288) {
-      float s = 0.0f;
-      for (int p = 0; p < 256; ++p) s += sg[p];
-      acc += s;
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      const int py = 2 * pg + rr;
+      // window columns px .. px + 2 of staged rows py .. py + 2
+      float win[3][3];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) win[dy][dx + 1] = sa[((py + dy) * 18 + dx) * LP + ci];
+      for (int px = 0; px < 16; ++px) {
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          win[dy][0] = win[dy][1];
+          win[dy][1] = win[dy][2];
+          win[dy][2] = sa[((py + dy) * 18 + px + 2) * LP + ci];
+        }
+        const float gv = sg[py * 16 + px];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[t] = fmaf(gv, win[t / 3][t % 3], acc[t]);
+        accb += gv;
+      }
     }
   }
-  if (prm <= 288) {
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < 9; ++t) sred[pg][ci * 9 + t] = acc[t];
+  if (ci == 0) sred[pg][288] = accb;
+  __syncthreads();
+  for (int prm = threadIdx.x; prm <= 288; prm += blockDim.x) {
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += sred[k][prm];
     float* d = partials + (size_t)blockIdx.x * hs::NPARAM + HS_W6 + prm;
-    *d = accumulate ? *d + acc : acc;
+    *d = accumulate ? *d + s : s;
   }
 }
 
@@ -721,10 +791,10 @@ hipError_t launch_wgrad32(const void* a_in, const void* g_out, int layer, int B,
 hipError_t launch_wgrad_last(const void* a5, const float* g6, int B, int H, int W, int precision,
                              float* partials, int accumulate, hipStream_t s) {
   if (precision == HS_BF16)
-    wgrad_last_kernel<__bf16><<<WGRAD_BLOCKS, 320, 0, s>>>((const __bf16*)a5, g6, B, H, W,
+    wgrad_last_kernel<__bf16><<<WGRAD_BLOCKS, 256, 0, s>>>((const __bf16*)a5, g6, B, H, W,
                                                            partials, accumulate);
   else
-    wgrad_last_kernel<float><<<WGRAD_BLOCKS, 320, 0, s>>>((const float*)a5, g6, B, H, W, partials,
+    wgrad_last_kernel<float><<<WGRAD_BLOCKS, 256, 0, s>>>((const float*)a5, g6, B, H, W, partials,
                                                           accumulate);
   return hipGetLastError();
 }

@@ -239,7 +239,8 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
       const float dD = dw * (1.0f - 2.0f * mh - dw);
       const float num = C * D * (A * dB + Bc * dA + dA * dB) - A * Bc * (C * dD + D * dC + dC * dD);
       const float den = (C + dC) * (D + dD) * (C * D);
-      dcs = fmaf(ssg[p], num / den, dcs);
+      // hardware reciprocal (1 ulp) instead of the IEEE division sequence
+      dcs = fmaf(ssg[p], num * __builtin_amdgcn_rcpf(den), dcs);
     }
   }
   const float dR = delta * (-dmse * invM + q.w_s * dcs * invM);
