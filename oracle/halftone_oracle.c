@@ -645,22 +645,28 @@ double or_as_loss(const double* xmap, int Bg, int Hg, int Wg, int P,
   return npatch ? total / (double)npatch : 0.0;
 }
 
-/* Anisotropy A(f_rho) of one P x P patch (Eq. anis), for the blue-noise
- * evaluation: out[rho] for every ring (rings with one sample get 0). */
-void or_anisotropy(const double* patch, int P, double* rapsd, double* anis) {
-  int N = P * P, nrings = or_ring_index(P / 2, P / 2, P) + 1;
-  double* ph = (double*)malloc(sizeof(double) * N);
+/* Periodogram of one P x P patch (Eq. psd): |DFT|^2 / P^2 by the direct sum. */
+static void periodogram(const double* patch, int ld, int P, double* ph) {
+  int N = P * P;
   for (int u = 0; u < P; ++u)
     for (int v = 0; v < P; ++v) {
       double sr = 0.0, si = 0.0;
       for (int y = 0; y < P; ++y)
         for (int x = 0; x < P; ++x) {
           double t = 2.0 * M_PI * (double)((u * y + v * x) % P) / P;
-          sr += patch[y * P + x] * cos(t);
-          si -= patch[y * P + x] * sin(t);
+          sr += patch[(size_t)y * ld + x] * cos(t);
+          si -= patch[(size_t)y * ld + x] * sin(t);
         }
       ph[u * P + v] = (sr * sr + si * si) / N;
     }
+}
+
+/* RAPSD (Eq. rapsd) and anisotropy (Eq. anis) of a power spectrum estimate:
+ * for every ring rho, the mean of the estimate over the ring and the
+ * variance about it over the squared mean, with n - 1 in the denominator
+ * (rings with one sample, or zero mean, get anisotropy 0). */
+static void ring_stats(const double* ph, int P, double* rapsd, double* anis) {
+  int nrings = or_ring_index(P / 2, P / 2, P) + 1;
   for (int r = 0; r < nrings; ++r) {
     double s = 0.0;
     int n = 0;
@@ -677,7 +683,39 @@ void or_anisotropy(const double* patch, int P, double* rapsd, double* anis) {
     rapsd[r] = mean;
     anis[r] = (n > 1 && mean != 0.0) ? a / ((n - 1) * mean * mean) : 0.0;
   }
+}
+
+/* Anisotropy A(f_rho) of one P x P patch (Eq. anis), for the blue-noise
+ * evaluation: out[rho] for every ring (rings with one sample get 0). */
+void or_anisotropy(const double* patch, int P, double* rapsd, double* anis) {
+  double* ph = (double*)malloc(sizeof(double) * P * P);
+  periodogram(patch, P, P, ph);
+  ring_stats(ph, P, rapsd, anis);
   free(ph);
+}
+
+/* Blue-noise evaluation of halftones (the spectral measures of Sec. IV,
+ * Eqs. psd, rapsd, anis): the power spectrum is estimated as the mean of the
+ * periodograms of all non-overlapping P x P patches of the B images (from
+ * (0, 0), remainders dropped), then reduced to RAPSD and anisotropy per
+ * ring. Returns the number of patches. */
+int or_spectrum(const double* img, int B, int H, int W, int P, double* rapsd, double* anis) {
+  int py = H / P, px = W / P, np = B * py * px;
+  double* ph = (double*)malloc(sizeof(double) * P * P);
+  double* avg = (double*)calloc((size_t)P * P, sizeof(double));
+  for (int b = 0; b < B; ++b)
+    for (int ty = 0; ty < py; ++ty)
+      for (int tx = 0; tx < px; ++tx) {
+        periodogram(img + (size_t)b * H * W + (size_t)ty * P * W + tx * P, W, P, ph);
+        for (int i = 0; i < P * P; ++i) avg[i] += ph[i];
+      }
+  if (np > 0) {
+    for (int i = 0; i < P * P; ++i) avg[i] /= np;
+    ring_stats(avg, P, rapsd, anis);
+  }
+  free(ph);
+  free(avg);
+  return np;
 }
 
 /* ------------------------------------------------------------------------

@@ -78,6 +78,7 @@ def lib():
             "or_ring_index": (c_int, [c_int, c_int, c_int]),
             "or_as_loss": (c_double, [D, c_int, c_int, c_int, c_int, D]),
             "or_anisotropy": (None, [D, c_int, D, D]),
+            "or_spectrum": (c_int, [D, c_int, c_int, c_int, c_int, D, D]),
             "or_lr_cosine": (c_double, [c_long, c_long, c_double, c_double]),
             "or_adam_step": (None, [D, D, D, D, c_long, c_long, c_double, c_double, c_double,
                                     c_double]),
@@ -293,6 +294,18 @@ def anisotropy(patch):
     r, rp = _d(np.zeros(n))
     a, ap = _d(np.zeros(n))
     lib().or_anisotropy(pp, P, rp, ap)
+    return r, a
+
+
+def spectrum(img, P=32):
+    """(RAPSD, anisotropy) per ring of the mean periodogram over the P x P
+    patches of img ([B][H][W] or [H][W])."""
+    B, H, W = _bhw(img)
+    x, xp = _d(np.reshape(img, (B, H, W)))
+    n = ring_index(P // 2, P // 2, P) + 1
+    r, rp = _d(np.zeros(n))
+    a, ap = _d(np.zeros(n))
+    lib().or_spectrum(xp, B, H, W, P, rp, ap)
     return r, a
 
 
