@@ -263,6 +263,31 @@ int halftone_profile_start(void);
 int halftone_profile_stop(double* ms_total_host, int* launches_host);
 
 /* ---------------------------------------------------------------------
+ * Blue-noise evaluation (Sec. IV, Eqs. psd, rapsd, anis): the power spectrum
+ * of a batch of halftones estimated as the mean of the periodograms
+ * |DFT|^2 / P^2 (no mean removal) of all non-overlapping P x P patches of the
+ * B images, tiled from (0, 0) with the remainders dropped; then per ring rho
+ * (frequency (u, v) folded to ub = min(u, P-u), vb = min(v, P-v), rho the
+ * unique integer with (2rho-1)^2 <= 4(ub^2+vb^2) < (2rho+1)^2, the DC term is
+ * ring 0) the radially averaged power RAPSD[rho] (mean over the ring) and
+ * the anisotropy anis[rho] = sum (P(f) - RAPSD)^2 / ((n-1) RAPSD^2), 0 for
+ * rings with one frequency or zero power.
+ *   bits [B][H][W] uint8 in device memory, each 0 or 1 (any byte value is
+ *        taken as its number);
+ *   P    32 or 64 (HS_EUNSUPPORTED otherwise); H >= P and W >= P
+ *        (HS_ESHAPE otherwise);
+ *   rapsd_out, anis_out: device FP32 arrays of halftone_spectrum_rings(P)
+ *        entries (24 for P = 32, 46 for P = 64).
+ * Rings are in linear power; the caller takes 10 log10 for dB. The mean over
+ * patches runs in a fixed order, so results are deterministic. Workspace
+ * from halftone_spectrum_workspace_size (0 for invalid shapes).
+ * --------------------------------------------------------------------- */
+int halftone_spectrum_rings(int P);
+size_t halftone_spectrum_workspace_size(int B, int H, int W, int P);
+int halftone_spectrum(const uint8_t* bits, int B, int H, int W, int P, float* rapsd_out,
+                      float* anis_out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
  * Floyd-Steinberg error diffusion on the host (the classic error diffusion
  * cited in Sec. I), the CPU fallback and the baseline of the judge:
  * raster order, threshold v >= 0.5, weights 7/16 right, 3/16 down-left,

@@ -67,6 +67,9 @@ _SIGS = {
                               ctypes.c_int64, ctypes.POINTER(HsTrainParams), I, P, P, P, P, SZ,
                               P]),
     "halftone_error_diffusion_host": (I, [P, I, I, I, P]),
+    "halftone_spectrum_rings": (I, [I]),
+    "halftone_spectrum_workspace_size": (SZ, [I, I, I, I]),
+    "halftone_spectrum": (I, [P, I, I, I, I, P, P, P, SZ, P]),
     "halftone_profile_start": (I, []),
     "halftone_profile_stop": (I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
 }
@@ -274,6 +277,22 @@ def policy_train_step(state, contones, seeds, gray, gray_seeds, step, total_step
                                    _ptr(actions_out), _ptr(grad_out), _ptr(state.ws),
                                    state.ws.numel(), _stream()))
     return state.metrics
+
+
+def halftone_spectrum(bits, P=32):
+    """(RAPSD, anisotropy) per ring of the mean periodogram over the P x P
+    patches of bits (uint8 [B][H][W] or [H][W] on the GPU), FP32 tensors."""
+    _dev(bits, torch.uint8)
+    B, H, W = bits.shape if bits.dim() == 3 else (1, *bits.shape)
+    n = lib().halftone_spectrum_rings(P)
+    if n <= 0:
+        raise HalftoneError(HS_EUNSUPPORTED, f"halftone_spectrum: P={P}")
+    r = torch.empty(n, dtype=torch.float32, device=bits.device)
+    a = torch.empty(n, dtype=torch.float32, device=bits.device)
+    ws = _ws(lib().halftone_spectrum_workspace_size(B, H, W, P), bits.device)
+    _check(lib().halftone_spectrum(_ptr(bits), B, H, W, P, _ptr(r), _ptr(a), _ptr(ws), ws.numel(),
+                                   _stream()))
+    return r, a
 
 
 def halftone_profile_start():

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhalftone.so")
-SOURCES = ["abi.cpp", "conv.hip", "loss.hip", "train.hip", "infer.hip", "recheck.hip"]
+SOURCES = ["abi.cpp", "conv.hip", "loss.hip", "train.hip", "infer.hip", "recheck.hip", "spectrum.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -769,6 +769,39 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   return HS_OK;
 }
 
+// ------------------------------------------------------------- spectrum --
+int halftone_spectrum_rings(int P) { return (P == 32 || P == 64) ? spectrum_rings(P) : 0; }
+
+static bool spectrum_shape_ok(int B, int H, int W, int P) {
+  return (P == 32 || P == 64) && shape_ok(B, H, W) && H >= P && W >= P;
+}
+
+size_t halftone_spectrum_workspace_size(int B, int H, int W, int P) {
+  if (!spectrum_shape_ok(B, H, W, P)) return 0;
+  Carve cv(nullptr);
+  cv.take<float>(spectrum_patches(B, H, W, P) * P * P * sizeof(float));
+  cv.take<float>((size_t)P * P * sizeof(float));
+  return cv.off;
+}
+
+int halftone_spectrum(const uint8_t* bits, int B, int H, int W, int P, float* rapsd_out,
+                      float* anis_out, void* workspace, size_t workspace_bytes, void* stream) {
+  if (P != 32 && P != 64) return fail(HS_EUNSUPPORTED, "halftone_spectrum: P=%d (32 or 64)", P);
+  if (!spectrum_shape_ok(B, H, W, P))
+    return fail(HS_ESHAPE, "halftone_spectrum: bad shape %dx%dx%d for P=%d", B, H, W, P);
+  if (!bits || !rapsd_out || !anis_out || !workspace)
+    return fail(HS_EINVAL, "halftone_spectrum: null pointer");
+  if (workspace_bytes < halftone_spectrum_workspace_size(B, H, W, P))
+    return fail(HS_EWORKSPACE, "halftone_spectrum: workspace too small");
+  int rc = check_device();
+  if (rc) return rc;
+  Carve cv(workspace);
+  float* spec = cv.take<float>(spectrum_patches(B, H, W, P) * P * P * sizeof(float));
+  float* avg = cv.take<float>((size_t)P * P * sizeof(float));
+  HS_TRY(launch_spectrum(bits, B, H, W, P, spec, avg, rapsd_out, anis_out, (hipStream_t)stream));
+  return HS_OK;
+}
+
 // ---------------------------------------------------- host error diffusion --
 int halftone_error_diffusion_host(const float* contone_host, int B, int H, int W,
                                   uint8_t* bits_host) {

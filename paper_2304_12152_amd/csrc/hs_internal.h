@@ -144,4 +144,10 @@ hipError_t launch_train_metrics(const float* loss_out, int B, const float* grad,
                                 const uint8_t* actions, size_t nact, float lr, float* metrics,
                                 unsigned long long* counter, hipStream_t s);
 
+// spectrum.hip
+int spectrum_rings(int P);
+size_t spectrum_patches(int B, int H, int W, int P);
+hipError_t launch_spectrum(const uint8_t* bits, int B, int H, int W, int P, float* spec,
+                           float* avg, float* rapsd, float* anis, hipStream_t s);
+
 }  // namespace hs

@@ -191,3 +191,25 @@ def test_host_error_diffusion_matches_oracle(orc, lib):
     assert np.array_equal(got, want)
     assert np.array_equal(hb.halftone_error_diffusion_host(np.full((6, 6), 0.5, np.float32))[0].numpy(),
                           orc.floyd_steinberg(np.full((1, 6, 6), 0.5))[0])
+
+
+def test_spectrum_argument_errors(lib):
+    p = _fake()
+    assert lib.halftone_spectrum_rings(32) == 24
+    assert lib.halftone_spectrum_rings(64) == 46
+    assert lib.halftone_spectrum_rings(48) == 0
+    ws = lib.halftone_spectrum_workspace_size(2, 70, 90, 32)
+    assert ws >= (2 * 2 * 2 * 32 * 32 + 32 * 32) * 4
+    assert lib.halftone_spectrum_workspace_size(2, 31, 90, 32) == 0
+    assert lib.halftone_spectrum_workspace_size(2, 70, 90, 16) == 0
+    args = [p, 2, 70, 90, 32, p, p, p, ws, None]
+    a = list(args); a[4] = 48
+    assert lib.halftone_spectrum(*a) == hb.HS_EUNSUPPORTED
+    a = list(args); a[3] = 31
+    assert lib.halftone_spectrum(*a) == hb.HS_ESHAPE
+    a = list(args); a[1] = 0
+    assert lib.halftone_spectrum(*a) == hb.HS_ESHAPE
+    a = list(args); a[0] = None
+    assert lib.halftone_spectrum(*a) == hb.HS_EINVAL
+    a = list(args); a[8] = ws - 1
+    assert lib.halftone_spectrum(*a) == hb.HS_EWORKSPACE
