@@ -15,7 +15,12 @@ averaged power and the anisotropy per ring. Reported per method and gray:
               power report -inf);
   anis_mean_db the mean of anis_db over those rings;
   low_power   the share of the AC power in rings below the principal
-              frequency sqrt(min(g, 1 - g)) (in cycles per pixel, times P).
+              frequency sqrt(min(g, 1 - g)) (in cycles per pixel, times P);
+  policy only: logit_hist, the fraction of pixels whose logit magnitude
+              |x| falls in the decades [0, 1e-4), [1e-4, 1e-3), ...,
+              [10, inf) -- a bimodal policy keeps almost all of them in the
+              top decades -- and recheck / fp32, the fractions the BF16
+              path recomputed with split-BF16 and in FP32.
 With K periodograms averaged, an isotropic spectrum has anisotropy about
 1 / K, so -10 log10(K) dB is the floor the figures are read against.
 
@@ -32,6 +37,7 @@ import numpy as np
 from . import synth
 
 GRAYS = (15, 80, 100, 127)
+LOGIT_DECADES = (1e-4, 1e-3, 1e-2, 1e-1, 1.0, 10.0)
 
 
 def _summary(bits, c, g, P, hb):
@@ -85,7 +91,16 @@ def bluenoise(weights, grays=GRAYS, B=8, H=512, W=512, P=64, precision=None, wit
         g = gi / 255.0
         c = torch.full((B, H, W), g, dtype=torch.float32, device=dev)
         s = torch.arange(seed + B * gi, seed + B * gi + B, dtype=torch.int64, device=dev)
-        rec = {"policy": _summary(hb.halftone_infer(w, c, s, precision=prec), c, g, P, hb)}
+        bits, x, st = hb.halftone_infer(w, c, s, precision=prec, logits=True, stats=True)
+        rec = {"policy": _summary(bits, c, g, P, hb)}
+        n = float(B * H * W)
+        edges = torch.tensor(LOGIT_DECADES, dtype=torch.float32, device=dev)
+        cnt = torch.bucketize(x.abs().flatten(), edges, right=True).bincount(
+            minlength=len(LOGIT_DECADES) + 1)
+        rec["policy"]["logit_hist"] = [round(float(v) / n, 6) for v in cnt.cpu()]
+        st = st.cpu().numpy()
+        rec["policy"]["recheck"] = float(st[0]) / n
+        rec["policy"]["fp32"] = float(st[2]) / n
         if with_fs:
             fs = hb.halftone_error_diffusion_host(np.full((B, H, W), g, dtype=np.float32))
             rec["fs"] = _summary(fs.to(dev), c, g, P, hb)
@@ -106,9 +121,10 @@ def main(argv=None):
     res = bluenoise(w, B=a.batch, H=a.size, W=a.size, P=a.P, with_fs=not a.no_fs)
     for gi in GRAYS:
         for m, r in res[str(gi)].items():
+            am = r["anis_mean_db"]
             print(f"g={gi:3d}/255 {m:6s} fill={r['fill']:.4f} hvs_mse={r['hvs_mse']:.3e} "
-                  f"anis_mean={r['anis_mean_db']:.2f} dB low_power={r['low_power']:.3f}",
-                  flush=True)
+                  f"anis_mean={am if am is None else round(am, 2)} dB "
+                  f"low_power={r['low_power']:.3f}", flush=True)
     line = json.dumps(res)
     if a.out:
         with open(a.out, "w") as f:

@@ -120,6 +120,12 @@ def gray_batch(n_levels=64, H=64, W=64):
     return np.broadcast_to(lv[:, None, None], (n_levels, H, W)).astype(np.float32).copy()
 
 
+def flat_contones(seed, n, H, W):
+    """n constant images with gray levels drawn uniformly from [0, 1]."""
+    lv = _rng(seed, 8).uniform(0.0, 1.0, size=n)
+    return np.broadcast_to(lv[:, None, None], (n, H, W)).astype(np.float32).copy()
+
+
 def seeds_array(seeds):
     return np.asarray(list(seeds), dtype=np.uint64)
 

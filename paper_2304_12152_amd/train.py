@@ -8,11 +8,17 @@ Expectation gradient of the reward (Sec. III-B/C), the anisotropy gradient
 batches and seeds.
 
 Training data: a pool of synthetic contones (the seeded generator of
-`synth.contone`, standing in for the paper's photograph crops) and the 64
-constant grays (k + 1/2) / 64 of the side batch. The judge halftones
+`synth.contone`, standing in for the paper's photograph crops), a share of
+which (--flat-frac, default 1/4) are constant grays drawn uniformly from
+[0, 1] -- photographs hold flat areas at every gray, the textured generator
+only at its clamps, and a policy that never sees a mid-gray flat under the
+reward is free to render it black, which also zeroes the anisotropy loss of
+the side batch -- and the 64 constant grays (k + 1/2) / 64 of the side
+batch. The judge halftones
 held-out contones with the policy (bits = [p >= 0.5], Alg. 1 TEST) and with
 Floyd-Steinberg error diffusion, and scores both by the HVS-filtered MSE of
-`halftone_loss` (Gaussian sigma = 2, 11 x 11, valid region).
+`halftone_loss` (Gaussian sigma = 2, 11 x 11, valid region); a second judge
+does the same on 16 constant grays (k + 1/2) / 16.
 
 Command line (prints a progress line every few seconds and one JSON line
 at the end):
@@ -146,6 +152,8 @@ def main(argv=None):
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--judge", type=int, default=256, help="held-out contones")
+    ap.add_argument("--flat-frac", type=float, default=0.25,
+                    help="share of the pool made of constant grays drawn from U(0, 1)")
     ap.add_argument("--run-seed", type=int, default=0)
     ap.add_argument("--weight-seed", type=int, default=42)
     ap.add_argument("--log-every", type=float, default=10.0, help="seconds between progress lines")
@@ -164,9 +172,14 @@ def main(argv=None):
         print(msg, flush=True)
 
     t0 = time.perf_counter()
-    pool = contone_pool(range(TRAIN_SEED0, TRAIN_SEED0 + args.pool), args.size, args.size)
+    nflat = int(round(args.flat_frac * args.pool))
+    pool = contone_pool(range(TRAIN_SEED0, TRAIN_SEED0 + args.pool - nflat), args.size, args.size)
+    if nflat:
+        pool = np.concatenate([pool, synth.flat_contones(TRAIN_SEED0, nflat, args.size, args.size)])
     held = contone_pool(range(JUDGE_SEED0, JUDGE_SEED0 + args.judge), args.size, args.size)
     hseeds = np.arange(JUDGE_SEED0, JUDGE_SEED0 + args.judge, dtype=np.uint64)
+    gheld = synth.gray_batch(16, args.size, args.size)
+    gseeds = np.arange(JUDGE_SEED0 + args.judge, JUDGE_SEED0 + args.judge + 16, dtype=np.uint64)
     log("pool: %d + %d contones %dx%d in %.1f s" % (args.pool, args.judge, args.size, args.size,
                                                   time.perf_counter() - t0))
 
@@ -185,6 +198,8 @@ def main(argv=None):
     w0 = tr.weights.clone()
     before = judge(w0, held, hseeds)
     log("untrained: " + json.dumps(before))
+    gbefore = judge(w0, gheld, gseeds)
+    log("untrained, constant grays: " + json.dumps(gbefore))
     t1 = time.perf_counter()
     last = t1
     hist = []
@@ -208,13 +223,17 @@ def main(argv=None):
     train_s = time.perf_counter() - t1
     after = judge(tr.weights, held, hseeds)
     log("trained: " + json.dumps(after))
+    gafter = judge(tr.weights, gheld, gseeds)
+    log("trained, constant grays: " + json.dumps(gafter))
     if args.out:
         np.save(args.out, tr.weights.cpu().numpy())
     res = {"steps": args.steps, "batch": args.batch, "pool": args.pool, "size": args.size,
            "w_s": tp.loss.w_s, "w_a": tp.loss.w_a, "estimator": args.estimator,
            "precision": "fp32" if args.fp32 else "bf16", "train_seconds": round(train_s, 2),
            "steps_per_s": round(args.steps / train_s, 2), "judge_images": args.judge,
+           "flat_frac": args.flat_frac,
            "untrained": before, "trained": after, "judge_curve": curve,
+           "untrained_gray": gbefore, "trained_gray": gafter,
            "trained_beats_fs": after["policy_hvs_mse"] < after["fs_hvs_mse"]}
     print(json.dumps(res), flush=True)
     return res
