@@ -294,10 +294,10 @@ void or_policy_backward(const double* w, const int* ch, int L, const double* c,
 /* ------------------------------------------------------------------------
  * Halftone metrics (Sec. III "Rewards"; Sec. V).
  * prm[] = {w_s, w_a, hvs_sigma, hvs_r, ssim_sigma, ssim_r, k, C1, C2,
- *          as_patch}.
+ *          as_patch, estimator, levels}.
  * ---------------------------------------------------------------------- */
 enum { P_WS, P_WA, P_HVS_SIGMA, P_HVS_R, P_SSIM_SIGMA, P_SSIM_R, P_K, P_C1,
-       P_C2, P_AS_PATCH, P_ESTIMATOR };
+       P_C2, P_AS_PATCH, P_ESTIMATOR, P_LEVELS };
 
 /* (2r+1)^2 Gaussian window, exp(-(i^2+j^2)/(2 sigma^2)) normalised to sum 1.
  * Used as the HVS low-pass filter (BASELINE's Gaussian sigma = 2 stands in
@@ -514,6 +514,162 @@ void or_le_delta_local(const double* h, const double* c, int B, int H, int W,
           }
         dR[b * HW + a] =
             delta * (-dmse / (double)M + prm[P_WS] * dcs / (double)M);
+      }
+  }
+  free(G); free(w); free(e); free(st); free(ssim); free(sig);
+}
+
+/* ------------------------------------------------------------------------
+ * Multitoning (Sec. VII, the deep multitoning prototype). There are L ink
+ * levels l_k = k Delta, k = 0..L-1, Delta = 1/(L-1). The network keeps its
+ * single sigmoid output v_a, and agent a chooses between the two levels
+ * around v_a: the upper one with probability (v_a - floor(v_a)) / Delta and
+ * the lower one otherwise (Eq. multitone). So every agent still has two
+ * actions, and E[h_a] = v_a.
+ * Readings where the paper is silent:
+ *   - the pair around v is (k_f, k_f + 1) with k_f = min(floor(v / Delta),
+ *     L - 2), so v = 1 picks level L-1 with probability one;
+ *   - the test phase rounds v to the nearest level, a tie going up (the
+ *     binary threshold at 0.5 is the case L = 2);
+ *   - the anisotropy proxy is v itself, the expectation of the rounding;
+ *   - a level is stored as its index k (one byte), the image value is k Delta.
+ * With L = 2 each function below is the binary one.
+ * ---------------------------------------------------------------------- */
+static int pair_low(double v, int L) {
+  int k = (int)floor(v * (L - 1));
+  if (k > L - 2) k = L - 2;
+  if (k < 0) k = 0;
+  return k;
+}
+
+/* Actions h_a = l_{k_f} or l_{k_f + 1}; the upper one iff u_a < q_a with
+ * q_a = v_a (L-1) - k_f and u_a the stream-0 uniform of or_bernoulli. */
+void or_multitone_actions(const double* v, const uint64_t* seeds, int B, int H, int W,
+                          int L, uint32_t step, uint8_t* k) {
+  for (int b = 0; b < B; ++b)
+    for (int y = 0; y < H; ++y)
+      for (int x = 0; x < W; ++x) {
+        uint64_t a = (uint64_t)y * (uint64_t)W + (uint64_t)x;
+        size_t i = ((size_t)b * H + y) * W + x;
+        int kf = pair_low(v[i], L);
+        double q = v[i] * (L - 1) - kf;
+        k[i] = (uint8_t)(kf + (or_uniform(seeds[b], a, 0, step) < q ? 1 : 0));
+      }
+}
+
+/* Test phase: the level nearest to v = sigmoid(x), a tie going up. The
+ * sigmoid is monotone, so this is the number of midpoints (j + 1/2) Delta,
+ * j = 0..L-2, that v reaches, decided on the logit against
+ * logit((j + 1/2) Delta) = log((2j + 1) / (2L - 3 - 2j)); for L = 2 that is
+ * the binary threshold x >= 0 exactly. */
+void or_multitone_levels(const double* logits, long n, int L, uint8_t* k) {
+  for (long i = 0; i < n; ++i) {
+    int kk = 0;
+    for (int j = 0; j + 1 < L; ++j)
+      if (logits[i] >= log((2.0 * j + 1.0) / (2.0 * L - 3.0 - 2.0 * j))) ++kk;
+    k[i] = (uint8_t)kk;
+  }
+}
+
+/* The Local Expectation difference of the two actions of every agent:
+ * dR[a] = R({h_a = l_{k_f+1}, h_-a}) - R({h_a = l_{k_f}, h_-a}), with k_f
+ * from v_a; then dE[R]/dv_a = dR[a] / Delta. h holds image values.
+ * (i) Brute force: both rewards from scratch. */
+void or_multitone_delta_brute(const double* h, const double* c, const double* v, int B,
+                              int H, int W, int L, const double* prm, double* dR) {
+  size_t HW = (size_t)H * W;
+  double* t = (double*)malloc(sizeof(double) * HW);
+  double r1[3], r0[3];
+  for (int b = 0; b < B; ++b) {
+    memcpy(t, h + b * HW, sizeof(double) * HW);
+    for (size_t a = 0; a < HW; ++a) {
+      double keep = t[a];
+      int kf = pair_low(v[b * HW + a], L);
+      t[a] = (double)(kf + 1) / (L - 1);
+      or_reward(t, c + b * HW, 1, H, W, prm, r1);
+      t[a] = (double)kf / (L - 1);
+      or_reward(t, c + b * HW, 1, H, W, prm, r0);
+      t[a] = keep;
+      dR[b * HW + a] = r1[2] - r0[2];
+    }
+  }
+  free(t);
+}
+
+/* (ii) The local toggle of Sec. III-C with a step of one level: h_a is one
+ * of the pair (k_f, k_f + 1) and moves to the other one, by d = +Delta
+ * (from the lower) or -Delta (from the upper). At a reward-map pixel j
+ * whose window holds a:
+ *   HVS error e_j moves by d G_{a-j}: the squared error by 2 d G e + d^2 G^2;
+ *   mu_h,j moves by d w_{a-j}; the weighted second moment of h by
+ *   w_{a-j} ((h_a + d)^2 - h_a^2), so var_h' = var_h + w d (2 h_a + d)
+ *   - (mu_h'^2 - mu_h^2) (binary h keeps var_h = mu_h (1 - mu_h));
+ *   cov_j moves by d w_{a-j} (c_a - mu_c,j); var_c and sigma_c stay.
+ * dR[a] = sign(d) (R(moved) - R(h)). Agents whose h_a is not in the pair
+ * are not defined here (the sampled actions always are). */
+void or_multitone_delta_local(const double* h, const double* c, const double* v, int B,
+                              int H, int W, int L, const double* prm, double* dR) {
+  int rh = (int)prm[P_HVS_R], rs = (int)prm[P_SSIM_R], m = valid_margin(prm);
+  int nh = 2 * rh + 1, ns = 2 * rs + 1;
+  double* G = (double*)malloc(sizeof(double) * nh * nh);
+  double* w = (double*)malloc(sizeof(double) * ns * ns);
+  or_gauss_window(prm[P_HVS_SIGMA], rh, G);
+  or_gauss_window(prm[P_SSIM_SIGMA], rs, w);
+  size_t HW = (size_t)H * W;
+  double* e = (double*)calloc(HW, sizeof(double));
+  ssim_stats* st = (ssim_stats*)calloc(HW, sizeof(ssim_stats));
+  double* ssim = (double*)calloc(HW, sizeof(double));
+  double* sig = (double*)calloc(HW, sizeof(double));
+  double C1 = prm[P_C1], C2 = prm[P_C2], step = 1.0 / (L - 1);
+  long M = (long)(H - 2 * m) * (W - 2 * m);
+  for (int b = 0; b < B; ++b) {
+    const double* hb = h + b * HW;
+    const double* cb = c + b * HW;
+    for (int y = m; y < H - m; ++y)
+      for (int x = m; x < W - m; ++x) {
+        double fh = 0.0, fc = 0.0;
+        for (int i = -rh; i <= rh; ++i)
+          for (int j = -rh; j <= rh; ++j) {
+            double g = G[(i + rh) * nh + (j + rh)];
+            fh += g * hb[(size_t)(y + i) * W + (x + j)];
+            fc += g * cb[(size_t)(y + i) * W + (x + j)];
+          }
+        size_t p = (size_t)y * W + x;
+        e[p] = fh - fc;
+        st[p] = window_stats(hb, cb, W, y, x, w, rs);
+        ssim[p] = ssim_from(st[p].mu_h, st[p].mu_c, st[p].var_h, st[p].var_c,
+                            st[p].cov, C1, C2);
+        sig[p] = prm[P_K] * sqrt(st[p].var_c);
+      }
+    for (int ay = 0; ay < H; ++ay)
+      for (int ax = 0; ax < W; ++ax) {
+        size_t a = (size_t)ay * W + ax;
+        int kf = pair_low(v[b * HW + a], L);
+        double lo = kf * step;
+        /* from the lower level up, else from the upper level down */
+        double d = fabs(hb[a] - lo) < 0.5 * step ? step : -step;
+        double ha = hb[a];
+        double dmse = 0.0, dcs = 0.0;
+        for (int jy = ay - rh; jy <= ay + rh; ++jy)
+          for (int jx = ax - rh; jx <= ax + rh; ++jx) {
+            if (jy < m || jy >= H - m || jx < m || jx >= W - m) continue;
+            double g = G[(ay - jy + rh) * nh + (ax - jx + rh)];
+            dmse += 2.0 * d * g * e[(size_t)jy * W + jx] + d * d * g * g;
+          }
+        for (int jy = ay - rs; jy <= ay + rs; ++jy)
+          for (int jx = ax - rs; jx <= ax + rs; ++jx) {
+            if (jy < m || jy >= H - m || jx < m || jx >= W - m) continue;
+            size_t j = (size_t)jy * W + jx;
+            double wa = w[(ay - jy + rs) * ns + (ax - jx + rs)];
+            double mu_h = st[j].mu_h + d * wa;
+            double var_h = st[j].var_h + wa * d * (2.0 * ha + d) -
+                           (mu_h * mu_h - st[j].mu_h * st[j].mu_h);
+            double cov = st[j].cov + d * wa * (cb[a] - st[j].mu_c);
+            double s1 = ssim_from(mu_h, st[j].mu_c, var_h, st[j].var_c, cov, C1, C2);
+            dcs += sig[j] * (s1 - ssim[j]);
+          }
+        double sgn = d > 0.0 ? 1.0 : -1.0;
+        dR[b * HW + a] = sgn * (-dmse / (double)M + prm[P_WS] * dcs / (double)M);
       }
   }
   free(G); free(w); free(e); free(st); free(ssim); free(sig);
@@ -746,12 +902,17 @@ void or_adam_step(double* theta, double* m, double* v, const double* g, long n,
  *   dL_MARL/dp = -dR/B (Local Expectation), or the COMA estimator's
  *   dL/dx when prm[P_ESTIMATOR] = 1; back through the sigmoid and the conv
  *   stack;
+ *   with prm[P_LEVELS] = L > 2 (multitoning): actions are level indices
+ *   drawn by or_multitone_actions, the reward is taken on h = k / (L-1), and
+ *   dL_MARL/dv = -dR (L-1) / B with dR from or_multitone_delta_local (Local
+ *   Expectation only);
  *   the constant-gray side batch: p_g = sigmoid(CNN(c_g, z_g)),
  *   dL_AS/dp_g, back through the sigmoid and the conv stack, weighted by w_a;
  *   Adam step with the cosine learning rate of `step` (0-based) out of
  *   `total`.
  * tprm[] = {lr_max, lr_min, beta1, beta2, eps}.
- * metrics[] = {mean MSE, mean CSSIM, mean R, L_AS, lr, |grad|, fill}.
+ * metrics[] = {mean MSE, mean CSSIM, mean R, L_AS, lr, |grad|, fill}, fill
+ * being the mean of h.
  * ---------------------------------------------------------------------- */
 void or_train_step(double* w, double* m, double* v, const int* ch, int L,
                    const double* c, const uint64_t* seeds, int B, int H, int W,
@@ -772,14 +933,21 @@ void or_train_step(double* w, double* m, double* v, const int* ch, int L,
   or_noise_map(seeds, B, H, W, noise_kind, 1, (uint32_t)step, z);
   or_policy_forward(w, ch, L, c, z, B, H, W, x);
   for (size_t i = 0; i < N; ++i) p[i] = 1.0 / (1.0 + exp(-x[i]));
+  int levels = (int)prm[P_LEVELS];
+  if (levels < 2) levels = 2;
   if (actions_in) memcpy(h, actions_in, N);
+  else if (levels > 2) or_multitone_actions(p, seeds, B, H, W, levels, (uint32_t)step, h);
   else or_bernoulli(p, seeds, B, H, W, (uint32_t)step, h);
   if (actions_out) memcpy(actions_out, h, N);
-  long fill = 0;
-  for (size_t i = 0; i < N; ++i) { hd[i] = h[i]; fill += h[i]; }
+  double fill = 0.0;
+  for (size_t i = 0; i < N; ++i) { hd[i] = (double)h[i] / (levels - 1); fill += hd[i]; }
   double* rew = (double*)malloc(sizeof(double) * 3 * B);
   or_reward(hd, c, B, H, W, prm, rew);
-  if ((int)prm[P_ESTIMATOR] == 1) {
+  if (levels > 2) {
+    or_multitone_delta_local(hd, c, p, B, H, W, levels, prm, dR);
+    /* dL/dx_a = dL/dv_a * v_a (1 - v_a), dL/dv_a = -dR_a (L-1) / B */
+    for (size_t i = 0; i < N; ++i) dR[i] = (-dR[i] * (levels - 1) / B) * p[i] * (1.0 - p[i]);
+  } else if ((int)prm[P_ESTIMATOR] == 1) {
     or_coma_grad_logit(hd, c, p, B, H, W, prm, dR);
   } else {
     or_le_delta_local(hd, c, B, H, W, prm, dR);
@@ -815,7 +983,7 @@ void or_train_step(double* w, double* m, double* v, const int* ch, int L,
   metrics[3] = las;
   metrics[4] = lr;
   metrics[5] = sqrt(gn);
-  metrics[6] = (double)fill / (double)N;
+  metrics[6] = fill / (double)N;
   free(z); free(x); free(p); free(hd); free(dR); free(h); free(grad); free(rew);
 }
 

@@ -26,9 +26,9 @@ CH = (2, 32, 32, 32, 32, 32, 1)
 # SSIM constants from Wang et al. 2004 with K1 = 0.01, K2 = 0.03, L = 1).
 # estimator: 0 = Local Expectation (Eq. le), 1 = COMA (Eq. coma).
 DEFAULT_PRM = dict(w_s=0.06, w_a=0.002, hvs_sigma=2.0, hvs_r=5, ssim_sigma=1.5,
-                   ssim_r=5, k=2.0, C1=1e-4, C2=9e-4, as_patch=32, estimator=0)
+                   ssim_r=5, k=2.0, C1=1e-4, C2=9e-4, as_patch=32, estimator=0, levels=2)
 PRM_ORDER = ("w_s", "w_a", "hvs_sigma", "hvs_r", "ssim_sigma", "ssim_r", "k",
-             "C1", "C2", "as_patch", "estimator")
+             "C1", "C2", "as_patch", "estimator", "levels")
 # Optimiser (Sec. VI-A: Adam, cosine 3e-4 -> 1e-5; textbook Adam constants).
 DEFAULT_TRAIN = dict(lr_max=3e-4, lr_min=1e-5, beta1=0.9, beta2=0.999, eps=1e-8)
 
@@ -75,6 +75,10 @@ def lib():
             "or_le_delta_brute": (None, [D, D, c_int, c_int, c_int, D, D]),
             "or_le_delta_local": (None, [D, D, c_int, c_int, c_int, D, D]),
             "or_coma_grad_logit": (None, [D, D, D, c_int, c_int, c_int, D, D]),
+            "or_multitone_actions": (None, [D, U64, c_int, c_int, c_int, c_int, c_u32, U8]),
+            "or_multitone_levels": (None, [D, c_long, c_int, U8]),
+            "or_multitone_delta_brute": (None, [D, D, D, c_int, c_int, c_int, c_int, D, D]),
+            "or_multitone_delta_local": (None, [D, D, D, c_int, c_int, c_int, c_int, D, D]),
             "or_ring_index": (c_int, [c_int, c_int, c_int]),
             "or_as_loss": (c_double, [D, c_int, c_int, c_int, c_int, D]),
             "or_anisotropy": (None, [D, c_int, D, D]),
@@ -257,6 +261,37 @@ def le_grad_probs(h, c, prm=None):
     """dL_MARL/dp_a = -dR_a / B (Eq. marl, mini-batch mean)."""
     d = le_delta(h, c, prm)
     return -d / d.shape[0]
+
+
+def multitone_actions(v, seeds, L, step=0):
+    """Level indices k_a in {k_f, k_f + 1} around v_a (Sec. VII, Eq. multitone)."""
+    B, H, W = _bhw(v)
+    v, vp = _d(np.reshape(v, (B, H, W)))
+    s, sp = _u64(seeds)
+    k, kp = _u8(np.zeros((B, H, W)))
+    lib().or_multitone_actions(vp, sp, B, H, W, L, step, kp)
+    return k
+
+
+def multitone_levels(logits, L):
+    """Test phase: index of the level nearest to sigmoid(x), ties up."""
+    x, xp = _d(logits)
+    k, kp = _u8(np.zeros(x.shape))
+    lib().or_multitone_levels(xp, x.size, L, kp)
+    return k
+
+
+def multitone_delta(h, c, v, L, prm=None, brute=False):
+    """dR_a = R(h_a = l_{k_f+1}) - R(h_a = l_{k_f}); h holds image values."""
+    B, H, W = _bhw(c)
+    h, hp = _d(np.reshape(h, (B, H, W)))
+    c, cp = _d(np.reshape(c, (B, H, W)))
+    v, vp = _d(np.reshape(v, (B, H, W)))
+    p, pp = _prm(prm)
+    d, dp = _d(np.zeros((B, H, W)))
+    fn = lib().or_multitone_delta_brute if brute else lib().or_multitone_delta_local
+    fn(hp, cp, vp, B, H, W, L, pp, dp)
+    return d
 
 
 def coma_grad_logits(h, c, p, prm=None):
