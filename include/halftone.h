@@ -58,6 +58,7 @@ extern "C" {
                          Eqs. baseline and coma)                            */
 
 #define HS_PARAM_COUNT 37889
+#define HS_MAX_LEVELS 8 /* most output levels of the multitoning variant  */
 
 /* Parameters of the reward and of the anisotropy-suppressing loss.
  * Defaults (halftone_default_loss_params): w_s = 0.06 and w_a = 0.002
@@ -65,7 +66,15 @@ extern "C" {
  * filter of Sec. V), SSIM window 11x11 Gaussian sigma 1.5 and k = 2
  * (Sec. V, contrast map), C1 = 1e-4, C2 = 9e-4 (SSIM constants of Wang et
  * al. 2004 for L = 1), anisotropy patches of 32x32, the Local Expectation
- * estimator. */
+ * estimator, 2 output levels (binary halftoning).
+ *
+ * levels > 2 selects the multitoning prototype of Sec. VII (Eq.
+ * multitone): the network keeps its one sigmoid output v, the L levels are
+ * k / (L-1), and agent a's two actions are the levels k_f and k_f + 1 around
+ * v_a (k_f = min(floor(v_a (L-1)), L-2)), the upper one drawn with
+ * probability v_a (L-1) - k_f. Actions are then level indices k (one byte,
+ * image value k / (L-1)); only the Local Expectation estimator is
+ * supported (HS_EUNSUPPORTED otherwise). */
 typedef struct hs_loss_params {
   float w_s;
   float w_a;
@@ -78,6 +87,7 @@ typedef struct hs_loss_params {
   float c2;
   int as_patch;  /* only 32 is supported */
   int estimator; /* HS_EST_LE or HS_EST_COMA */
+  int levels;    /* 2 (binary) .. HS_MAX_LEVELS (multitoning) */
 } hs_loss_params;
 
 /* Optimiser and sampling parameters of one TRAIN iteration (Algorithm 1).
@@ -155,6 +165,26 @@ int halftone_infer_pages(const float* weights, const float* contone, const uint6
                          void* stream);
 
 /* ---------------------------------------------------------------------
+ * Multitoning inference (Sec. VII, the TEST phase with L output levels):
+ * the level nearest to v = sigmoid(x), a tie going up, i.e. the number of
+ * thresholds logit((j + 1/2)/(L-1)), j = 0..L-2, that the logit x reaches
+ * (levels = 2 is halftone_infer_pages exactly). Arguments as for
+ * halftone_infer_pages, with
+ * levels   2..HS_MAX_LEVELS (HS_EINVAL otherwise);
+ * levels_out the level index k in 0..L-1 per pixel (image value k/(L-1)).
+ * With HS_BF16 the recheck band is |x - nearest threshold| < recheck_tau
+ * (the split stage: < tau2), so every level equals the FP32 one wherever v
+ * is farther than the BF16 error from the midpoints; stats as for
+ * halftone_infer ("bits changed" counts changed levels). Workspace from
+ * halftone_infer_pages_workspace_size.
+ * --------------------------------------------------------------------- */
+int halftone_infer_levels(const float* weights, const float* contone, const uint64_t* seeds,
+                          int npages, const int32_t* shapes_host, int levels, int noise_kind,
+                          int precision, float recheck_tau, uint8_t* levels_out,
+                          float* logits_or_null, int32_t* stats_or_null, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
  * Training-mode policy forward and its backward (the conv stack of
  * Sec. VI-A with its chain rule), for torch.autograd wrappers.
  *
@@ -178,7 +208,8 @@ int halftone_policy_backward(const float* weights, const float* grad_probs, cons
  * Reward and anisotropy loss (Sec. III "Rewards", Eq. final_reward;
  * Sec. V Eq. cssim; Sec. IV Eq. as with the probability proxy).
  *
- * actions  [B][H][W] uint8 (the sampled halftone h).
+ * actions  [B][H][W] uint8 (the sampled halftone h; level indices when
+ *          prm->levels > 2, image value k / (levels - 1)).
  * contone  [B][H][W] FP32.
  * probs_gray_or_null [Bg][Hg][Wg] FP32: pi(h=1) of the constant-gray side
  *          batch; L_AS is computed over its non-overlapping 32x32 patches
@@ -207,6 +238,10 @@ int halftone_loss(const uint8_t* actions, const float* contone, int B, int H, in
  *          h_-a) + (1 - p_a) R(h_a = 0, h_-a), i.e. -dR_a (1-p_a)/p_a / B
  *          where h_a = 1 and -dR_a p_a/(1-p_a) / B where h_a = 0; it needs
  *          probs_or_null in both gradient spaces.
+ *          With prm->levels = L > 2 (multitoning): dL_MARL/dv_a =
+ *          -dR_a (L-1) / B, dR_a = R(h_a = level k_f + 1) - R(h_a = level
+ *          k_f) with k_f from v_a = probs_or_null (required); each h_a must
+ *          be one of its two levels (the sampled actions are).
  * grad_probs_gray_or_null [Bg][Hg][Wg] FP32 out: w_a * dL_AS/dp_g (zero
  *          outside the patches).
  * grad_space HS_WRT_PROB, or HS_WRT_LOGIT to multiply both by p(1 - p)
@@ -225,7 +260,8 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
 /* ---------------------------------------------------------------------
  * One TRAIN iteration of Algorithm 1 on one GPU:
  *   forward of the batch (z from stream 1 at `step`), p = sigmoid(x),
- *   actions h_a = [u_a < p_a] (stream 0 at `step`), dL_MARL/dp from the
+ *   actions h_a = [u_a < p_a] (stream 0 at `step`; with tp->loss.levels
+ *   = L > 2 the level index k_f + [u_a < p_a (L-1) - k_f]), dL_MARL/dp from the
  *   estimator tp->loss.estimator (Local Expectation or COMA); forward of the constant-gray side batch,
  *   w_a * dL_AS/dp_g; backward of both through the conv stack; Adam on the
  *   FP32 master weights with lr_t = lr_min + (lr_max - lr_min)(1 +
@@ -237,7 +273,7 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
  * precision HS_FP32 or HS_BF16 (BF16 activations and MFMA, FP32 master
  *          weights, FP32 gradients accumulated in FP32).
  * metrics  FP32[8] out: mean MSE, mean CSSIM, mean R, L_AS, lr, |grad|_2,
- *          fill fraction of the actions, 0.
+ *          fill (the mean of h: the fraction of ones for binary actions), 0.
  * actions_out_or_null [B][H][W] uint8: the sampled actions.
  * grad_out_or_null [HS_PARAM_COUNT] FP32: the total gradient before Adam.
  * --------------------------------------------------------------------- */

@@ -18,13 +18,15 @@ HS_NOISE_GAUSS, HS_NOISE_UNIFORM = 0, 1
 HS_WRT_PROB, HS_WRT_LOGIT = 0, 1
 HS_EST_LE, HS_EST_COMA = 0, 1
 HS_PARAM_COUNT = 37889
+HS_MAX_LEVELS = 8
 
 
 class HsLossParams(ctypes.Structure):
     _fields_ = [("w_s", ctypes.c_float), ("w_a", ctypes.c_float), ("hvs_sigma", ctypes.c_float),
                 ("hvs_radius", ctypes.c_int), ("ssim_sigma", ctypes.c_float),
                 ("ssim_radius", ctypes.c_int), ("k", ctypes.c_float), ("c1", ctypes.c_float),
-                ("c2", ctypes.c_float), ("as_patch", ctypes.c_int), ("estimator", ctypes.c_int)]
+                ("c2", ctypes.c_float), ("as_patch", ctypes.c_int), ("estimator", ctypes.c_int),
+                ("levels", ctypes.c_int)]
 
 
 class HsTrainParams(ctypes.Structure):
@@ -55,6 +57,7 @@ _SIGS = {
     "halftone_infer": (I, [P, P, P, I, I, I, I, I, F, P, P, P, P, SZ, P]),
     "halftone_infer_pages_workspace_size": (SZ, [I, P, I]),
     "halftone_infer_pages": (I, [P, P, P, I, P, I, I, F, P, P, P, P, SZ, P]),
+    "halftone_infer_levels": (I, [P, P, P, I, P, I, I, I, F, P, P, P, P, SZ, P]),
     "halftone_policy_workspace_size": (SZ, [I, I, I, I]),
     "halftone_policy_forward": (I, [P, P, P, I, I, I, I, ctypes.c_uint32, I, P, P, SZ, P]),
     "halftone_policy_backward": (I, [P, P, P, I, I, I, I, P, P, SZ, P]),
@@ -163,10 +166,12 @@ def page_shapes_array(shapes):
 
 def halftone_infer_pages(weights, contone, seeds, shapes, noise_kind=HS_NOISE_GAUSS,
                          precision=HS_BF16, recheck_tau=0.055, logits=False, stats=False,
-                         workspace=None):
+                         workspace=None, levels=None):
     """Pages of different sizes in one call. contone: flat FP32 device tensor
     of the pages concatenated (page p at offset sum of the earlier H*W);
-    shapes: (H, W) per page; returns flat bits (and logits, stats)."""
+    shapes: (H, W) per page; returns flat bits (and logits, stats). With
+    `levels` (2..HS_MAX_LEVELS) the multitone call halftone_infer_levels:
+    level indices instead of bits."""
     sh = page_shapes_array(shapes)
     n = sh.shape[0]
     N = int((sh[:, 0].astype("int64") * sh[:, 1]).sum())
@@ -181,9 +186,15 @@ def halftone_infer_pages(weights, contone, seeds, shapes, noise_kind=HS_NOISE_GA
     if need == 0:
         raise HalftoneError(HS_ESHAPE, "bad page shapes")
     ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
-    _check(lib().halftone_infer_pages(_ptr(weights), _ptr(contone), _ptr(seeds), n, shp,
-                                      noise_kind, precision, recheck_tau, _ptr(bits), _ptr(lg),
-                                      _ptr(st), _ptr(ws), ws.numel(), _stream()))
+    if levels is None:
+        _check(lib().halftone_infer_pages(_ptr(weights), _ptr(contone), _ptr(seeds), n, shp,
+                                          noise_kind, precision, recheck_tau, _ptr(bits),
+                                          _ptr(lg), _ptr(st), _ptr(ws), ws.numel(), _stream()))
+    else:
+        _check(lib().halftone_infer_levels(_ptr(weights), _ptr(contone), _ptr(seeds), n, shp,
+                                           int(levels), noise_kind, precision, recheck_tau,
+                                           _ptr(bits), _ptr(lg), _ptr(st), _ptr(ws), ws.numel(),
+                                           _stream()))
     out = [bits]
     if logits:
         out.append(lg)

@@ -78,6 +78,10 @@ int check_params(const hs_loss_params* p) {
   if (p->as_patch != 32) return fail(HS_EUNSUPPORTED, "only 32x32 anisotropy patches");
   if (p->estimator != HS_EST_LE && p->estimator != HS_EST_COMA)
     return fail(HS_EINVAL, "estimator %d", p->estimator);
+  if (p->levels < 2 || p->levels > HS_MAX_LEVELS)
+    return fail(HS_EINVAL, "levels %d (2..%d)", p->levels, HS_MAX_LEVELS);
+  if (p->levels > 2 && p->estimator != HS_EST_LE)
+    return fail(HS_EUNSUPPORTED, "multitone levels need the Local Expectation estimator");
   return HS_OK;
 }
 
@@ -115,7 +119,7 @@ LossWs carve_loss(Carve& cv, int B, int H, int W, int Bg, int Hg, int Wg, int m,
   LossWs w;
   const int vh = H - 2 * m, vw = W - 2 * m;
   w.ntiles = ((vh + 15) / 16) * ((vw + 15) / 16);
-  w.maps = maps ? cv.take<float>((size_t)5 * B * H * W * 4) : nullptr;
+  w.maps = maps ? cv.take<float>((size_t)6 * B * H * W * 4) : nullptr;
   w.tiles = cv.take<float>((size_t)B * w.ntiles * 2 * 4);
   const size_t np = (size_t)Bg * (Hg / 32) * (Wg / 32);
   w.patches = cv.take<float>((np > 0 ? np : 1) * 4);
@@ -137,7 +141,7 @@ InferWs carve_infer(Carve& cv, size_t N, int prec) {
 // mode 0: inference bits/logits; mode 1: probs (+ actions) keeping activations.
 hipError_t run_forward_train(const float* w, const float* contone, const uint64_t* seeds, int B,
                              int H, int W, int kind, uint32_t step, int prec, const PolicyWs& pw,
-                             float* probs, uint8_t* actions, hipStream_t s) {
+                             float* probs, uint8_t* actions, int levels, hipStream_t s) {
   hipError_t e;
   if ((e = launch_pack32(w, pw.packF, prec, 0, s)) != hipSuccess) return e;
   if ((e = launch_conv_first(contone, seeds, w, B, H, W, kind, step, prec, pw.act[0], pw.z, pw.c,
@@ -151,7 +155,7 @@ hipError_t run_forward_train(const float* w, const float* contone, const uint64_
       return e;
   }
   return launch_conv_last(pw.act[4], w, B, H, W, prec, 1, seeds, step, actions, nullptr, probs,
-                          0.0f, nullptr, nullptr, s);
+                          0.0f, nullptr, nullptr, make_levels(levels), s);
 }
 
 // Backward of the stack given dL/dprobs (probs != null) or dL/dlogit
@@ -230,6 +234,18 @@ void prof_end(hipStream_t s) {
 
 }  // namespace
 
+namespace hs {
+// thr[j] = logit((j + 1/2) / (L - 1)) = log((2j + 1) / (2L - 3 - 2j)), in
+// double then rounded; L = 2 gives exactly {0}
+Levels make_levels(int L) {
+  Levels q;
+  q.n = L - 1;
+  for (int j = 0; j < MAX_LEVELS - 1; ++j)
+    q.thr[j] = j < q.n ? (float)log((2.0 * j + 1.0) / (2.0 * L - 3.0 - 2.0 * j)) : 0.0f;
+  return q;
+}
+}  // namespace hs
+
 // ===================================================================== ABI ==
 extern "C" {
 
@@ -246,6 +262,7 @@ void halftone_default_loss_params(hs_loss_params* p) {
   p->c2 = 9e-4f;
   p->as_patch = 32;
   p->estimator = HS_EST_LE;
+  p->levels = 2;
 }
 
 void halftone_default_train_params(hs_train_params* p) {
@@ -347,8 +364,8 @@ size_t halftone_infer_workspace_size(int B, int H, int W, int precision) {
 // The page table is built on the device (uniform batch) or from pages_host.
 static int infer_bf16(const float* weights, const float* contone, const uint64_t* seeds,
                       const int* shapes, int npages, size_t N, const Page* pages_host,
-                      int noise_kind, float recheck_tau, uint8_t* bits, float* logits,
-                      int32_t* stats_or_null, void* workspace, hipStream_t s) {
+                      int noise_kind, float recheck_tau, const Levels& lv, uint8_t* bits,
+                      float* logits, int32_t* stats_or_null, void* workspace, hipStream_t s) {
   Bf16Ws w;
   bf16_ws(shapes, npages, N, &w, workspace);
   int32_t* stats = stats_or_null ? stats_or_null : (int32_t*)(w.cnt + 8);
@@ -366,21 +383,21 @@ static int infer_bf16(const float* weights, const float* contone, const uint64_t
   long long seg_cap = 0;
   prof_begin(s);
   HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
-                            recheck_tau, bits, logits, w.seglist, w.seg_count, &nseg, &seg_cap,
-                            w.pack, num_cus(), s));
+                            recheck_tau, lv, bits, logits, w.seglist, w.seg_count, &nseg,
+                            &seg_cap, w.pack, num_cus(), s));
   prof_end(s);
   HS_TRY(launch_recheck_split(weights, contone, seeds, w.pages, noise_kind, w.seglist,
-                              w.seg_count, nseg, seg_cap, whi, wlo, tau2, w.list2, w.cnt + 1,
-                              bits, logits, stats, num_cus(), s));
+                              w.seg_count, nseg, seg_cap, whi, wlo, tau2, lv, w.list2,
+                              w.cnt + 1, bits, logits, stats, num_cus(), s));
   HS_TRY(launch_recheck_fp32(weights, contone, seeds, w.pages, noise_kind, w.list2, w.cnt + 1,
-                             wt, bits, logits, stats, 2, num_cus(), s));
+                             wt, lv, bits, logits, stats, 2, num_cus(), s));
   return HS_OK;
 }
 
 // The FP32 path (per-layer kernels) on one uniform batch.
 static int infer_fp32(const float* weights, const float* contone, const uint64_t* seeds, int B,
-                      int H, int W, int noise_kind, uint8_t* bits, float* logits, void* workspace,
-                      hipStream_t s) {
+                      int H, int W, int noise_kind, const Levels& lv, uint8_t* bits, float* logits,
+                      void* workspace, hipStream_t s) {
   InferWs iw;
   int* cnt;
   fp32_ws(B, H, W, &iw, &cnt, workspace);
@@ -401,7 +418,7 @@ static int infer_fp32(const float* weights, const float* contone, const uint64_t
     dst = t;
   }
   HS_TRY(launch_conv_last(src, weights, B, H, W, HS_FP32, 0, seeds, 0u, bits, logits, nullptr,
-                          0.0f, nullptr, cnt, s));
+                          0.0f, nullptr, cnt, lv, s));
   return HS_OK;
 }
 
@@ -433,11 +450,12 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
   if (precision == HS_BF16) {
     const std::vector<int> sh = uniform_shapes(B, H, W);
     return infer_bf16(weights, contone, seeds, sh.data(), B, (size_t)B * H * W, nullptr,
-                      noise_kind, recheck_tau, bits, logits_or_null, stats_or_null, workspace, s);
+                      noise_kind, recheck_tau, make_levels(2), bits, logits_or_null,
+                      stats_or_null, workspace, s);
   }
   if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
-  return infer_fp32(weights, contone, seeds, B, H, W, noise_kind, bits, logits_or_null,
-                    workspace, s);
+  return infer_fp32(weights, contone, seeds, B, H, W, noise_kind, make_levels(2), bits,
+                    logits_or_null, workspace, s);
 }
 
 // Page shapes: every page at least 1 x 1 and the total under 2^31 pixels.
@@ -467,21 +485,24 @@ size_t halftone_infer_pages_workspace_size(int npages, const int32_t* shapes_hos
   return m;
 }
 
-int halftone_infer_pages(const float* weights, const float* contone, const uint64_t* seeds,
-                         int npages, const int32_t* shapes_host, int noise_kind, int precision,
-                         float recheck_tau, uint8_t* bits, float* logits_or_null,
-                         int32_t* stats_or_null, void* workspace, size_t workspace_bytes,
-                         void* stream) {
-  int rc = check_infer_args(weights, contone, seeds, bits, workspace, noise_kind, precision,
-                            recheck_tau, "halftone_infer_pages");
+static int infer_pages(const float* weights, const float* contone, const uint64_t* seeds,
+                       int npages, const int32_t* shapes_host, int levels, int noise_kind,
+                       int precision, float recheck_tau, uint8_t* out, float* logits_or_null,
+                       int32_t* stats_or_null, void* workspace, size_t workspace_bytes,
+                       void* stream, const char* who) {
+  int rc = check_infer_args(weights, contone, seeds, out, workspace, noise_kind, precision,
+                            recheck_tau, who);
   if (rc) return rc;
+  if (levels < 2 || levels > HS_MAX_LEVELS)
+    return fail(HS_EINVAL, "%s: levels %d (2..%d)", who, levels, HS_MAX_LEVELS);
   size_t N = 0;
   if (!pages_ok(npages, shapes_host, &N))
-    return fail(HS_ESHAPE, "halftone_infer_pages: bad page shapes or more than 2^31 pixels");
+    return fail(HS_ESHAPE, "%s: bad page shapes or more than 2^31 pixels", who);
   if (workspace_bytes < halftone_infer_pages_workspace_size(npages, shapes_host, precision))
-    return fail(HS_EWORKSPACE, "halftone_infer_pages: workspace too small");
+    return fail(HS_EWORKSPACE, "%s: workspace too small", who);
   if ((rc = check_device())) return rc;
   hipStream_t s = (hipStream_t)stream;
+  const Levels lv = make_levels(levels);
   if (precision == HS_BF16) {
     std::vector<Page> pages(npages);
     long long off = 0, vstart = 0;
@@ -497,18 +518,38 @@ int halftone_infer_pages(const float* weights, const float* contone, const uint6
       vstart += (long long)fused_strips(W) * (H + fused_fill());
     }
     return infer_bf16(weights, contone, seeds, shapes_host, npages, N, pages.data(), noise_kind,
-                      recheck_tau, bits, logits_or_null, stats_or_null, workspace, s);
+                      recheck_tau, lv, out, logits_or_null, stats_or_null, workspace, s);
   }
   if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
   long long off = 0;
   for (int p = 0; p < npages; ++p) {
     const int H = shapes_host[2 * p], W = shapes_host[2 * p + 1];
-    rc = infer_fp32(weights, contone + off, seeds + p, 1, H, W, noise_kind, bits + off,
+    rc = infer_fp32(weights, contone + off, seeds + p, 1, H, W, noise_kind, lv, out + off,
                     logits_or_null ? logits_or_null + off : nullptr, workspace, s);
     if (rc) return rc;
     off += (long long)H * W;
   }
   return HS_OK;
+}
+
+int halftone_infer_pages(const float* weights, const float* contone, const uint64_t* seeds,
+                         int npages, const int32_t* shapes_host, int noise_kind, int precision,
+                         float recheck_tau, uint8_t* bits, float* logits_or_null,
+                         int32_t* stats_or_null, void* workspace, size_t workspace_bytes,
+                         void* stream) {
+  return infer_pages(weights, contone, seeds, npages, shapes_host, 2, noise_kind, precision,
+                     recheck_tau, bits, logits_or_null, stats_or_null, workspace,
+                     workspace_bytes, stream, "halftone_infer_pages");
+}
+
+int halftone_infer_levels(const float* weights, const float* contone, const uint64_t* seeds,
+                          int npages, const int32_t* shapes_host, int levels, int noise_kind,
+                          int precision, float recheck_tau, uint8_t* levels_out,
+                          float* logits_or_null, int32_t* stats_or_null, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+  return infer_pages(weights, contone, seeds, npages, shapes_host, levels, noise_kind, precision,
+                     recheck_tau, levels_out, logits_or_null, stats_or_null, workspace,
+                     workspace_bytes, stream, "halftone_infer_levels");
 }
 
 // ------------------------------------------------------- policy fwd / bwd --
@@ -536,7 +577,7 @@ int halftone_policy_forward(const float* weights, const float* contone, const ui
   Carve cv(workspace);
   PolicyWs pw = carve_policy(cv, (size_t)B * H * W, precision);
   HS_TRY(run_forward_train(weights, contone, seeds, B, H, W, noise_kind, step, precision, pw,
-                           probs, nullptr, (hipStream_t)stream));
+                           probs, nullptr, 2, (hipStream_t)stream));
   return HS_OK;
 }
 
@@ -629,6 +670,8 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
     return fail(HS_EINVAL, "halftone_loss_backward: logit space needs probs");
   if (prm->estimator == HS_EST_COMA && !probs_or_null)
     return fail(HS_EINVAL, "halftone_loss_backward: the COMA estimator needs probs");
+  if (prm->levels > 2 && !probs_or_null)
+    return fail(HS_EINVAL, "halftone_loss_backward: multitone levels need probs");
   if (probs_gray_or_null && !grad_probs_gray_or_null)
     return fail(HS_EINVAL, "halftone_loss_backward: gray batch without its gradient buffer");
   if (!probs_gray_or_null) Bg = Hg = Wg = 0;
@@ -732,7 +775,7 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   const uint32_t st = (uint32_t)step;
   // batch: forward, actions, policy gradient (logit space), backward
   HS_TRY(run_forward_train(weights, contones, seeds, B, H, W, kind, st, precision, pw, probs, act,
-                           s));
+                           lp.levels, s));
   LossDev win;
   make_windows(lp, &win);
   HS_TRY(launch_loss_stats(act, contones, B, H, W, lp, win, lw.maps, lw.tiles, lw.ntiles, s));
@@ -742,7 +785,7 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   const int npatch = Bg * (Hg / 32) * (Wg / 32);
   if (Bg > 0) {
     HS_TRY(run_forward_train(weights, gray, gray_seeds, Bg, Hg, Wg, kind, st, precision, pw,
-                             probs_g, nullptr, s));
+                             probs_g, nullptr, lp.levels, s));
     HS_TRY(launch_fill(gradg, (size_t)Bg * Hg * Wg, 0.0f, s));
     if (npatch > 0)
       HS_TRY(launch_as(probs_g, Bg, Hg, Wg, lp.w_a / (float)npatch, 1, lw.patches, gradg, s));
@@ -760,8 +803,8 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   const double c2 = 1.0 - pow((double)tp->beta2, (double)(step + 1));
   if (grad_out_or_null)
     HS_TRY(hipMemcpyAsync(grad_out_or_null, grad, (size_t)NPARAM * 4, hipMemcpyDeviceToDevice, s));
-  HS_TRY(launch_train_metrics(loss_out, B, grad, NPARAM, act, (size_t)B * H * W, (float)lr,
-                              metrics, pw.counter, s));
+  HS_TRY(launch_train_metrics(loss_out, B, grad, NPARAM, act, (size_t)B * H * W, lp.levels,
+                              (float)lr, metrics, pw.counter, s));
   HS_TRY(launch_adam(weights, adam_m, adam_v, grad, NPARAM, (float)lr, tp->beta1, tp->beta2,
                      tp->eps, (float)c1, (float)c2, s));
   if (actions_out_or_null)

@@ -170,8 +170,12 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Last layer 32 -> 1 and the head. MODE 0: bit = [x >= 0] (+ logit).
-// MODE 1: p = sigmoid(x), action = [u < p] with u from stream 0 at `step`.
+// Last layer 32 -> 1 and the head. MODE 0: bit = [x >= 0] (+ logit), or
+// with multitone levels (lv.n > 1) the level of x among lv's thresholds.
+// MODE 1: p = sigmoid(x), action = [u < p] with u from stream 0 at `step`;
+// with L = lv.n + 1 > 2 levels the index kf + [u < q] of the stochastic
+// rounding between the levels around p (Sec. VII, Eq. multitone):
+// kf = min(floor(p (L-1)), L-2), q = p (L-1) - kf.
 // ---------------------------------------------------------------------------
 constexpr int LP = 33;  // padded pixel stride (floats) of the staged tile
 
@@ -183,7 +187,8 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T* __restrict__ in
                                                         float* __restrict__ logits,
                                                         float* __restrict__ probs, float tau,
                                                         uint32_t* __restrict__ list,
-                                                        int* __restrict__ count) {
+                                                        int* __restrict__ count,
+                                                        const hs::Levels lv) {
   // staged positions 16-byte aligned (stride LQ = 36 floats: the 16 lanes of
   // a tile row read 16 distinct groups of 4 banks), weights as [tap][ci]
   constexpr int LQ = 36;
@@ -224,13 +229,24 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T* __restrict__ in
   }
   const size_t o = img + (size_t)gy * W + gx;
   if (MODE == 0) {
-    bits[o] = x >= 0.0f ? 1 : 0;
+    float dist;
+    int side;
+    bits[o] = (uint8_t)hs::level_of(lv, x, &dist, &side);
     if (logits) logits[o] = x;
-    if (list && fabsf(x) < tau) list[atomicAdd(count, 1)] = (uint32_t)o;
+    if (list && dist < tau) list[atomicAdd(count, 1)] = (uint32_t)o;
   } else {
     const float p = hs_sigmoid(x);
     probs[o] = p;
-    if (bits) bits[o] = hs_action_u(seeds[b], (uint64_t)gy * W + gx, step) < p ? 1 : 0;
+    if (bits) {
+      const float u = hs_action_u(seeds[b], (uint64_t)gy * W + gx, step);
+      if (lv.n == 1) {
+        bits[o] = u < p ? 1 : 0;
+      } else {
+        const float t = p * (float)lv.n;
+        const int kf = min((int)floorf(t), lv.n - 1);
+        bits[o] = (uint8_t)(kf + (u < t - (float)kf ? 1 : 0));
+      }
+    }
   }
 }
 
@@ -732,22 +748,22 @@ hipError_t launch_conv32(const void* in, const void* wpack, const float* bias, c
 hipError_t launch_conv_last(const void* in, const float* w, int B, int H, int W, int precision,
                             int mode, const uint64_t* seeds, uint32_t step, uint8_t* bits,
                             float* logits, float* probs, float tau, uint32_t* list, int* count,
-                            hipStream_t s) {
+                            const Levels& lv, hipStream_t s) {
   const dim3 grid = tiles16(B, H, W);
   if (precision == HS_BF16) {
     if (mode == 0)
       conv_last_kernel<__bf16, 0><<<grid, 256, 0, s>>>((const __bf16*)in, w, H, W, seeds, step,
-                                                       bits, logits, probs, tau, list, count);
+                                                       bits, logits, probs, tau, list, count, lv);
     else
       conv_last_kernel<__bf16, 1><<<grid, 256, 0, s>>>((const __bf16*)in, w, H, W, seeds, step,
-                                                       bits, logits, probs, tau, list, count);
+                                                       bits, logits, probs, tau, list, count, lv);
   } else {
     if (mode == 0)
       conv_last_kernel<float, 0><<<grid, 256, 0, s>>>((const float*)in, w, H, W, seeds, step,
-                                                      bits, logits, probs, tau, list, count);
+                                                      bits, logits, probs, tau, list, count, lv);
     else
       conv_last_kernel<float, 1><<<grid, 256, 0, s>>>((const float*)in, w, H, W, seeds, step,
-                                                      bits, logits, probs, tau, list, count);
+                                                      bits, logits, probs, tau, list, count, lv);
   }
   return hipGetLastError();
 }

@@ -40,6 +40,47 @@ inline __host__ __device__ int entry_page(uint64_t e) { return (int)((e >> 31) &
 inline __host__ __device__ int entry_bit(uint64_t e) { return (int)(e >> 63); }
 constexpr int WGRAD_BLOCKS = 512;  // rows of weight-gradient partial sums
 
+// Output levels of the test phase (Sec. VII multitoning; binary = 2 levels):
+// level = #{j : x >= thr[j]} over the logit midpoints
+// thr[j] = logit((j + 1/2) / (L - 1)), j = 0..L-2; binary: thr = {0}.
+constexpr int MAX_LEVELS = 8;
+struct Levels {
+  int n;  // L - 1 thresholds, ascending
+  float thr[MAX_LEVELS - 1];
+};
+Levels make_levels(int L);
+// level of logit x, the distance to the nearest threshold and the side of it
+inline __host__ __device__ int level_of(const Levels& q, float x, float* dist, int* side) {
+  int lev = 0;
+  float best = 3.0e38f;
+  int sd = 0;
+  for (int j = 0; j < q.n; ++j) {
+    const float d = x - q.thr[j];
+    lev += d >= 0.0f ? 1 : 0;
+    const float ad = d < 0.0f ? -d : d;
+    if (ad < best) {
+      best = ad;
+      sd = d >= 0.0f ? 1 : 0;
+    }
+  }
+  *dist = best;
+  *side = sd;
+  return lev;
+}
+// index of the threshold nearest to x
+inline __host__ __device__ int nearest_threshold(const Levels& q, float x) {
+  int k = 0;
+  float best = 3.0e38f;
+  for (int j = 0; j < q.n; ++j) {
+    const float d = x - q.thr[j], ad = d < 0.0f ? -d : d;
+    if (ad < best) {
+      best = ad;
+      k = j;
+    }
+  }
+  return k;
+}
+
 // Bytes of one NHWC 32-channel activation map of n pixels.
 inline size_t act_bytes(size_t n, int precision) {
   return n * 32 * (precision == HS_BF16 ? 2 : 4);
@@ -60,11 +101,12 @@ hipError_t launch_conv_first(const float* contone, const uint64_t* seeds, const 
                              float* zout, float* cout, hipStream_t s);
 hipError_t launch_conv32(const void* in, const void* wpack, const float* bias, const void* mask,
                          void* out, int B, int H, int W, int precision, int mode, hipStream_t s);
-// mode 0: bits (+ logits); mode 1: probs + actions sampled from stream 0 at step
+// mode 0: bits or levels (+ logits); mode 1: probs + actions sampled from
+// stream 0 at step (bits, or level indices when lv.n > 1)
 hipError_t launch_conv_last(const void* in, const float* w, int B, int H, int W, int precision,
                             int mode, const uint64_t* seeds, uint32_t step, uint8_t* bits,
                             float* logits, float* probs, float tau, uint32_t* list, int* count,
-                            hipStream_t s);
+                            const Levels& lv, hipStream_t s);
 // infer.hip: the fused BF16 pass
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 size_t fused_frag_bytes();
@@ -80,24 +122,25 @@ hipError_t launch_put_pages(Page* dst, const Page* src_host, int n, hipStream_t 
 size_t fused_list_entries(const int* shapes_host, int npages, int num_cus);
 hipError_t launch_fused_infer(const float* w, const float* contone, const uint64_t* seeds,
                               const Page* pages, const int* shapes_host, int npages, int kind,
-                              float tau, uint8_t* bits, float* logits, uint64_t* list,
-                              int* seg_count, int* nseg, long long* seg_cap, const void* frags,
-                              int num_cus, hipStream_t s);
+                              float tau, const Levels& lv, uint8_t* bits, float* logits,
+                              uint64_t* list, int* seg_count, int* nseg, long long* seg_cap,
+                              const void* frags, int num_cus, hipStream_t s);
 // recheck.hip: re-evaluation of listed pixels over their receptive field
 // (wt: layers 2..5 transposed for the FP32 stage, fp32_pack_bytes())
 hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,
                                const Page* pages, int kind, const uint64_t* list,
-                               const int* count, const void* wt, uint8_t* bits, float* logits,
-                               int32_t* stats, int count_slot, int num_cus, hipStream_t s);
+                               const int* count, const void* wt, const Levels& lv, uint8_t* bits,
+                               float* logits, int32_t* stats, int count_slot, int num_cus,
+                               hipStream_t s);
 size_t split_frag_bytes();
 size_t fp32_pack_bytes();
 hipError_t launch_split_pack(const float* w, void* whi, void* wlo, void* wt, hipStream_t s);
 hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
                                 const Page* pages, int kind, const uint64_t* seglist,
                                 const int* seg_count, int nseg, long long seg_cap,
-                                const void* whi, const void* wlo, float tau2, uint64_t* list2,
-                                int* count2, uint8_t* bits, float* logits, int32_t* stats,
-                                int num_cus, hipStream_t s);
+                                const void* whi, const void* wlo, float tau2, const Levels& lv,
+                                uint64_t* list2, int* count2, uint8_t* bits, float* logits,
+                                int32_t* stats, int num_cus, hipStream_t s);
 // g6 = grad (if probs == null) or grad * p (1 - p); writes g6 and the
 // masked input gradient of layer 6.
 hipError_t launch_dgrad_last(const float* grad, const float* probs, const void* a5,
@@ -141,8 +184,8 @@ hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1,
                        float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_train_metrics(const float* loss_out, int B, const float* grad, int n,
-                                const uint8_t* actions, size_t nact, float lr, float* metrics,
-                                unsigned long long* counter, hipStream_t s);
+                                const uint8_t* actions, size_t nact, int levels, float lr,
+                                float* metrics, unsigned long long* counter, hipStream_t s);
 
 // spectrum.hip
 int spectrum_rings(int P);

@@ -110,7 +110,8 @@ struct FusedArgs {
   int npages, kind;
   long long vtotal;   // sum over pages of strips x (H + FILL): the partition's extent
   float tau;
-  uint8_t* bits;
+  hs::Levels lv;      // thresholds of the multitone levels (MULTI only)
+  uint8_t* bits;      // bit, or level index (MULTI)
   float* logits;
   uint64_t* list;     // per output wave a segment of seg_cap entries
   int* seg_count;     // entries written per segment
@@ -154,7 +155,10 @@ HS_DEV bf16x8_t relu_bf16(const f32x4_t (&acc)[2], bool in) {
 // per-step barrier orders LDS only (hs_lds_barrier): it need not wait for
 // the bits, logits and list stores (nor the contone prefetch) to complete.
 
-template <int NW>
+// MULTI: the output is the level of the logit among a.lv's thresholds
+// (multitoning), and the recheck band is around the nearest threshold;
+// otherwise the bit [x >= 0] with the band around 0.
+template <int NW, bool MULTI>
 __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a) {
   constexpr int RPW = 8 / NW, NT = 64 * 4 * NW, HPW = 2 / NW;  // runs, threads, 64-px halves per wave
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * 2 * ROWE];   // layers 1..4
@@ -282,11 +286,18 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
             const bool valid = Lx >= 6 && Lx < 6 + FS && x < W;
             bool flag = false;
             size_t o = 0;
+            int side = xl >= 0.0f ? 1 : 0;
             if (valid) {
               o = img + (size_t)y * W + x;
-              a.bits[o] = xl >= 0.0f ? 1 : 0;
+              if constexpr (MULTI) {
+                float dist;
+                a.bits[o] = (uint8_t)hs::level_of(a.lv, xl, &dist, &side);
+                flag = a.list && dist < a.tau;
+              } else {
+                a.bits[o] = (uint8_t)side;
+                flag = a.list && fabsf(xl) < a.tau;
+              }
               if (a.logits) a.logits[o] = xl;
-              flag = a.list && fabsf(xl) < a.tau;
             }
             const uint64_t mask = __ballot(flag);
             if (mask) {
@@ -295,9 +306,10 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
                 const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                 const long long seg = 2LL * blockIdx.x + HPW * part + h;
-                // entry: pixel (bits 0-30), page (31-62), the bit written (63)
+                // entry: pixel (bits 0-30), page (31-62), the side of the
+                // (nearest) threshold written (63)
                 a.list[seg * a.seg_cap + nflag[h] + below] =
-                    (uint64_t)o | pgbits | (xl >= 0.0f ? (1ull << 63) : 0ull);
+                    (uint64_t)o | pgbits | (side ? (1ull << 63) : 0ull);
               }
               nflag[h] += __popcll(mask);
             }
@@ -504,9 +516,9 @@ size_t fused_list_entries(const int* shapes_host, int npages, int num_cus) {
 
 hipError_t launch_fused_infer(const float* w, const float* contone, const uint64_t* seeds,
                               const Page* pages, const int* shapes_host, int npages, int kind,
-                              float tau, uint8_t* bits, float* logits, uint64_t* list,
-                              int* seg_count, int* nseg, long long* seg_cap, const void* frags,
-                              int num_cus, hipStream_t s) {
+                              float tau, const Levels& lv, uint8_t* bits, float* logits,
+                              uint64_t* list, int* seg_count, int* nseg, long long* seg_cap,
+                              const void* frags, int num_cus, hipStream_t s) {
   FusedArgs a;
   a.contone = contone;
   a.seeds = seeds;
@@ -519,6 +531,7 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
   long long rows;
   fused_geometry(shapes_host, npages, num_cus, &grid, &a.vtotal, &rows);
   a.tau = tau;
+  a.lv = lv;
   a.bits = bits;
   a.logits = logits;
   a.list = list;
@@ -526,7 +539,10 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
   a.seg_cap = rows * 64;
   *nseg = 2 * grid;
   *seg_cap = a.seg_cap;
-  fused_infer_kernel<FUSED_NW><<<grid, 64 * 4 * FUSED_NW, 0, s>>>(a);
+  if (lv.n == 1 && lv.thr[0] == 0.0f)
+    fused_infer_kernel<FUSED_NW, false><<<grid, 64 * 4 * FUSED_NW, 0, s>>>(a);
+  else
+    fused_infer_kernel<FUSED_NW, true><<<grid, 64 * 4 * FUSED_NW, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -16,6 +16,15 @@
 // of products expanded in those increments, so no two O(1) values are
 // subtracted. dR_a = delta (R(toggled) - R(h)); dL_MARL/dp_a = -dR_a / B.
 //
+// Multitoning (Sec. VII, Eq. multitone; L levels spaced s = 1/(L-1)): an
+// action byte is a level index k, h = k s. Agent a's two actions are the
+// levels kf, kf + 1 around its output v_a (kf = min(floor(v (L-1)), L-2)),
+// and its toggle moves h_a by delta = +s (from kf) or -s (from kf + 1). Then
+// var_h is no longer mu_h (1 - mu_h): it is kept as a map, and moves by
+// w delta (2 h_a + delta) - (mu_h'^2 - mu_h^2) = dw (2 h_a + delta - 2 mu_h
+// - dw), dw = delta w_{a-j}. dR_a = R(kf + 1) - R(kf) and
+// dL_MARL/dv_a = -dR_a (L-1) / B.
+//
 // Anisotropy-suppressing loss (Sec. IV, Eqs. psd, rapsd, as): per 32 x 32
 // patch of the probability map, Phat = |DFT|^2 / 1024, ring means over
 // rings of width 1 (ring of (u, v) = rounded radius of the folded
@@ -37,6 +46,8 @@ struct LossConst {
   int rh, rs, m;
   float k, c1, c2, w_s;
   int est;
+  int levels;   // 2 = binary
+  float hstep;  // 1 / (levels - 1)
 };
 
 __global__ __launch_bounds__(256) void loss_stats_kernel(const uint8_t* __restrict__ h,
@@ -60,7 +71,7 @@ __global__ __launch_bounds__(256) void loss_stats_kernel(const uint8_t* __restri
   for (int i = threadIdx.x; i < ls * ls; i += 256) {
     const int ly = i / ls, lx = i - ly * ls, gy = vy0 - R + ly, gx = vx0 - R + lx;
     const bool in = gy < H && gx < W;  // gy, gx >= 0 because vy0 >= R
-    sh[i] = in ? (float)h[img + (size_t)gy * W + gx] : 0.0f;
+    sh[i] = in ? (float)h[img + (size_t)gy * W + gx] * q.hstep : 0.0f;
     sc[i] = in ? c[img + (size_t)gy * W + gx] : 0.0f;
   }
   __syncthreads();
@@ -107,6 +118,7 @@ __global__ __launch_bounds__(256) void loss_stats_kernel(const uint8_t* __restri
       maps[2 * n + o] = mu_c;
       maps[3 * n + o] = var_c;
       maps[4 * n + o] = cov;
+      if (q.levels > 2) maps[5 * n + o] = var_h;
     }
   }
   e2 = hs_wave_sum(e2);
@@ -169,7 +181,7 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
                                                       const float* __restrict__ maps, float invM,
                                                       float* __restrict__ grad) {
   __shared__ float se[LS * LS], smh[LS * LS], smc[LS * LS], svc[LS * LS], scv[LS * LS],
-      ssg[LS * LS];
+      ssg[LS * LS], svh[LS * LS];
   __shared__ float sG[15 * 15], sw[15 * 15];
   const int b = blockIdx.z, R = q.m;
   const int ay0 = blockIdx.y * LT, ax0 = blockIdx.x * LT;
@@ -182,7 +194,7 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
   for (int i = threadIdx.x; i < ls * ls; i += 256) {
     const int ly = i / ls, lx = i - ly * ls, gy = ay0 - R + ly, gx = ax0 - R + lx;
     const bool in = gy >= q.m && gy < H - q.m && gx >= q.m && gx < W - q.m;
-    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f;
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f;
     if (in) {
       const size_t o = img + (size_t)gy * W + gx;
       v0 = maps[o];
@@ -190,6 +202,7 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
       v2 = maps[2 * n + o];
       v3 = maps[3 * n + o];
       v4 = maps[4 * n + o];
+      if (q.levels > 2) v5 = maps[5 * n + o];
     }
     se[i] = v0;
     smh[i] = v1;
@@ -197,13 +210,21 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
     svc[i] = v3;
     scv[i] = v4;
     ssg[i] = q.k * sqrtf(v3);
+    svh[i] = v5;
   }
   __syncthreads();
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   const int ay = ay0 + ty, ax = ax0 + tx;
   if (ay >= H || ax >= W) return;
   const size_t oa = img + (size_t)ay * W + ax;
-  const float delta = h[oa] ? -1.0f : 1.0f;
+  const bool multi = q.levels > 2;
+  float delta = h[oa] ? -1.0f : 1.0f;
+  const float ha = (float)h[oa] * q.hstep;
+  if (multi) {
+    const float t = probs[oa] * (float)(q.levels - 1);
+    const int kf = min((int)floorf(t), q.levels - 2);
+    delta = (int)h[oa] == kf ? q.hstep : -q.hstep;
+  }
   const float ca = c[oa];
   const int cy = ty + R, cx = tx + R;
   const int nh = 2 * q.rh + 1, ns = 2 * q.rs + 1;
@@ -214,8 +235,8 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
     for (int j = -q.rh; j <= q.rh; ++j) {
       const int jx = ax + j;
       if (jx < q.m || jx >= W - q.m) continue;
-      const float G = sG[(q.rh - i) * nh + (q.rh - j)];  // G_{a-j}
-      dmse = fmaf(2.0f * delta * G, se[(cy + i) * ls + cx + j], fmaf(G, G, dmse));
+      const float dG = delta * sG[(q.rh - i) * nh + (q.rh - j)];  // delta G_{a-j}
+      dmse = fmaf(2.0f * dG, se[(cy + i) * ls + cx + j], fmaf(dG, dG, dmse));
     }
   }
   float dcs = 0.0f;
@@ -231,20 +252,23 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
       const float A = 2.0f * mh * mc + q.c1;
       const float Bc = 2.0f * scv[p] + q.c2;
       const float C = mh * mh + mc * mc + q.c1;
-      const float D = mh * (1.0f - mh) + svc[p] + q.c2;
+      const float D = (multi ? svh[p] : mh * (1.0f - mh)) + svc[p] + q.c2;
       const float dw = delta * wa;
       const float dA = 2.0f * dw * mc;
       const float dB = 2.0f * dw * (ca - mc);
       const float dC = dw * (2.0f * mh + dw);
-      const float dD = dw * (1.0f - 2.0f * mh - dw);
+      // binary: 2 h_a + delta = 1 for either toggle
+      const float dD = dw * ((multi ? 2.0f * ha + delta : 1.0f) - 2.0f * mh - dw);
       const float num = C * D * (A * dB + Bc * dA + dA * dB) - A * Bc * (C * dD + D * dC + dC * dD);
       const float den = (C + dC) * (D + dD) * (C * D);
       // hardware reciprocal (1 ulp) instead of the IEEE division sequence
       dcs = fmaf(ssg[p], num * __builtin_amdgcn_rcpf(den), dcs);
     }
   }
-  const float dR = delta * (-dmse * invM + q.w_s * dcs * invM);
-  float gv = -dR / (float)B;
+  // the sign of the toggle: dR = R(upper) - R(lower)
+  const float sgn = delta > 0.0f ? 1.0f : -1.0f;
+  const float dR = sgn * (-dmse * invM + q.w_s * dcs * invM);
+  float gv = -dR * (float)(q.levels - 1) / (float)B;
   if (q.est == HS_EST_COMA) {
     // score function times (R(h) - b_a) = (h_a ? (1 - p) : -p) dR: in logit
     // space (h_a - p)(R(h) - b_a), in probability space divided by p (h_a = 1)
@@ -439,6 +463,8 @@ static LossConst make_const(const hs_loss_params& p) {
   q.c2 = p.c2;
   q.w_s = p.w_s;
   q.est = p.estimator;
+  q.levels = p.levels < 2 ? 2 : p.levels;
+  q.hstep = 1.0f / (float)(q.levels - 1);
   return q;
 }
 

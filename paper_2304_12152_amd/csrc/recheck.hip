@@ -10,6 +10,8 @@
 //                in FP32. Pixels with |x| >= tau2 are decided here, the
 //                rest listed again.
 //   FP32 stage   the pixels listed by the split stage, in plain FP32.
+// With multitone levels (Sec. VII) the same holds with |x| replaced by the
+// distance to the nearest level threshold; the output is the level.
 #include "hs_common.h"
 #include "hs_internal.h"
 
@@ -91,6 +93,7 @@ struct SplitArgs {
   const bf16x8_t* whi;
   const bf16x8_t* wlo;
   float tau2;
+  hs::Levels lv;  // output thresholds (binary: {0})
   uint64_t* list2;
   int* count2;
   uint8_t* bits;
@@ -466,9 +469,13 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
         part = hs_wave_sum(part);
         if (lane == 0) {
           const float xl = part + b6;
-          if (fabsf(xl) >= a.tau2) {
-            const int nb = xl >= 0.f ? 1 : 0;
-            if (ci[CI_BIT] != nb) atomicAdd(&a.stats[1], 1);
+          float dist;
+          int side;
+          const int nb = hs::level_of(a.lv, xl, &dist, &side);
+          if (dist >= a.tau2) {
+            // the level decided before: the side of the same nearest threshold
+            const int old = hs::nearest_threshold(a.lv, xl) + ci[CI_BIT];
+            if (old != nb) atomicAdd(&a.stats[1], 1);
             a.bits[o] = (uint8_t)nb;
             if (a.logits) a.logits[o] = xl;
           } else {
@@ -552,7 +559,7 @@ __global__ __launch_bounds__(F32_THREADS, 2) void recheck_fp32_kernel(
     const float* __restrict__ w, const float* __restrict__ contone,
     const uint64_t* __restrict__ seeds, const hs::Page* __restrict__ pages, int kind,
     const uint64_t* __restrict__ list, const int* __restrict__ count,
-    const f32x4_t* __restrict__ wt, uint8_t* __restrict__ bits,
+    const f32x4_t* __restrict__ wt, const hs::Levels lv, uint8_t* __restrict__ bits,
     float* __restrict__ logits, int32_t* __restrict__ stats, int count_slot) {
   __shared__ float s0[13 * 13 * 2];
   __shared__ float bufA[11 * 11 * RS], bufB[9 * 9 * RS];
@@ -638,8 +645,10 @@ __global__ __launch_bounds__(F32_THREADS, 2) void recheck_fp32_kernel(
       part = hs_wave_sum(part);
       if (tid == 0) {
         const float xl = part + w[HS_B6];
-        const int nb = xl >= 0.f ? 1 : 0;
-        if (nb != hs::entry_bit(u)) atomicAdd(&stats[1], 1);
+        float dist;
+        int side;
+        const int nb = hs::level_of(lv, xl, &dist, &side);
+        if (nb != hs::nearest_threshold(lv, xl) + hs::entry_bit(u)) atomicAdd(&stats[1], 1);
         bits[o] = (uint8_t)nb;
         if (logits) logits[o] = xl;
       }
@@ -665,9 +674,9 @@ hipError_t launch_split_pack(const float* w, void* whi, void* wlo, void* wt, hip
 hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
                                 const Page* pages, int kind, const uint64_t* seglist,
                                 const int* seg_count, int nseg, long long seg_cap,
-                                const void* whi, const void* wlo, float tau2, uint64_t* list2,
-                                int* count2, uint8_t* bits, float* logits, int32_t* stats,
-                                int num_cus, hipStream_t s) {
+                                const void* whi, const void* wlo, float tau2, const Levels& lv,
+                                uint64_t* list2, int* count2, uint8_t* bits, float* logits,
+                                int32_t* stats, int num_cus, hipStream_t s) {
   if (nseg < 1 || nseg > SPLIT_MAXSEG) return hipErrorInvalidValue;
   SplitArgs a;
   a.w = w;
@@ -682,6 +691,7 @@ hipError_t launch_recheck_split(const float* w, const float* contone, const uint
   a.whi = (const bf16x8_t*)whi;
   a.wlo = (const bf16x8_t*)wlo;
   a.tau2 = tau2;
+  a.lv = lv;
   a.list2 = list2;
   a.count2 = count2;
   a.bits = bits;
@@ -693,11 +703,12 @@ hipError_t launch_recheck_split(const float* w, const float* contone, const uint
 
 hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,
                                const Page* pages, int kind, const uint64_t* list,
-                               const int* count, const void* wt, uint8_t* bits, float* logits,
-                               int32_t* stats, int count_slot, int num_cus, hipStream_t s) {
+                               const int* count, const void* wt, const Levels& lv, uint8_t* bits,
+                               float* logits, int32_t* stats, int count_slot, int num_cus,
+                               hipStream_t s) {
   recheck_fp32_kernel<<<2 * num_cus, F32_THREADS, 0, s>>>(w, contone, seeds, pages, kind, list,
-                                                          count, (const f32x4_t*)wt, bits, logits,
-                                                          stats, count_slot);
+                                                          count, (const f32x4_t*)wt, lv, bits,
+                                                          logits, stats, count_slot);
   return hipGetLastError();
 }
 

@@ -22,9 +22,10 @@ __global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float*
   w[i] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// Number of white actions (0/1 bytes). Each block sums a slice with 16-byte
-// loads (the byte sum of a 32-bit word v of 0/1 bytes is (v * 0x01010101) >> 24)
-// and adds it to a 64-bit counter; integer sums are order-independent.
+// Sum of the action bytes (bits, or level indices below 64). Each block sums
+// a slice with 16-byte loads (the byte sum of a 32-bit word v of such bytes
+// is (v * 0x01010101) >> 24: no partial sum reaches 256) and adds it to a
+// 64-bit counter; integer sums are order-independent.
 __global__ __launch_bounds__(256) void count_ones_kernel(const uint8_t* __restrict__ act,
                                                          size_t nact,
                                                          unsigned long long* __restrict__ out) {
@@ -46,11 +47,12 @@ __global__ __launch_bounds__(256) void count_ones_kernel(const uint8_t* __restri
   if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
 }
 
-// metrics = {mean MSE, mean CSSIM, mean R, L_AS, lr, |grad|_2, fill, 0}
+// metrics = {mean MSE, mean CSSIM, mean R, L_AS, lr, |grad|_2, fill, 0}; fill
+// is the mean of h = action / (levels - 1)
 __global__ __launch_bounds__(256) void metrics_kernel(const float* __restrict__ loss_out, int B,
                                                       const float* __restrict__ grad, int n,
                                                       const unsigned long long* __restrict__ ones,
-                                                      size_t nact, float lr,
+                                                      size_t nact, int levels, float lr,
                                                       float* __restrict__ metrics) {
   __shared__ float red[4];
   float s = 0.0f;
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(256) void metrics_kernel(const float* __restrict__ 
   metrics[3] = loss_out[3 * B];
   metrics[4] = lr;
   metrics[5] = sqrtf(((red[0] + red[1]) + red[2]) + red[3]);
-  metrics[6] = (float)((double)*ones / (double)nact);
+  metrics[6] = (float)((double)*ones / ((double)nact * (levels - 1)));
   metrics[7] = 0.0f;
 }
 
@@ -89,14 +91,14 @@ hipError_t launch_adam(float* w, float* m, float* v, const float* g, int n, floa
 }
 
 hipError_t launch_train_metrics(const float* loss_out, int B, const float* grad, int n,
-                                const uint8_t* actions, size_t nact, float lr, float* metrics,
-                                unsigned long long* counter, hipStream_t s) {
+                                const uint8_t* actions, size_t nact, int levels, float lr,
+                                float* metrics, unsigned long long* counter, hipStream_t s) {
   zero_u64_kernel<<<1, 1, 0, s>>>(counter);
   size_t blocks = (nact / 16 + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 1024) blocks = 1024;
   count_ones_kernel<<<(unsigned)blocks, 256, 0, s>>>(actions, nact, counter);
-  metrics_kernel<<<1, 256, 0, s>>>(loss_out, B, grad, n, counter, nact, lr, metrics);
+  metrics_kernel<<<1, 256, 0, s>>>(loss_out, B, grad, n, counter, nact, levels, lr, metrics);
   return hipGetLastError();
 }
 

@@ -213,3 +213,29 @@ def test_spectrum_argument_errors(lib):
     assert lib.halftone_spectrum(*a) == hb.HS_EINVAL
     a = list(args); a[8] = ws - 1
     assert lib.halftone_spectrum(*a) == hb.HS_EWORKSPACE
+
+
+def test_levels_argument_errors(lib):
+    p = _fake()
+    ws = 1 << 20
+    for bad, code in ((1, hb.HS_EINVAL), (hb.HS_MAX_LEVELS + 1, hb.HS_EINVAL)):
+        prm = hb.default_loss_params(levels=bad)
+        assert lib.halftone_loss(p, p, 1, 32, 32, None, 0, 0, 0, ctypes.byref(prm), p, p, ws,
+                                 None) == code
+    prm = hb.default_loss_params(levels=4, estimator=hb.HS_EST_COMA)
+    assert lib.halftone_loss(p, p, 1, 32, 32, None, 0, 0, 0, ctypes.byref(prm), p, p, ws,
+                             None) == hb.HS_EUNSUPPORTED
+    # multitone gradients need the probabilities (the pair of levels)
+    prm = hb.default_loss_params(levels=4)
+    b = [p, p, None, 1, 32, 32, None, 0, 0, 0, ctypes.byref(prm), hb.HS_WRT_PROB, p, None, p,
+         ws, None]
+    assert lib.halftone_loss_backward(*b) == hb.HS_EINVAL
+    sh = hb.page_shapes_array([(8, 8)])
+    shp = sh.ctypes.data_as(ctypes.c_void_p)
+    need = lib.halftone_infer_pages_workspace_size(1, shp, hb.HS_BF16)
+    args = [p, p, p, 1, shp, 4, 0, hb.HS_BF16, 0.05, p, None, None, p, need, None]
+    for bad in (0, 1, hb.HS_MAX_LEVELS + 1):
+        a = list(args); a[5] = bad
+        assert lib.halftone_infer_levels(*a) == hb.HS_EINVAL
+    a = list(args); a[13] = need - 1
+    assert lib.halftone_infer_levels(*a) == hb.HS_EWORKSPACE
