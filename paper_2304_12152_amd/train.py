@@ -117,10 +117,12 @@ class Trainer:
         return self.state.weights
 
 
-def judge(weights, contones, seeds, precision=None, with_fs=True):
+def judge(weights, contones, seeds, precision=None, with_fs=True, levels=2):
     """Mean HVS-MSE of the policy's halftones (and of Floyd-Steinberg's).
 
-    contones: float32 [N, H, W] (host); seeds: uint64 [N] noise keys."""
+    contones: float32 [N, H, W] (host); seeds: uint64 [N] noise keys. With
+    levels > 2 the policy's output is its multitone (nearest-level) image
+    and Floyd-Steinberg stays the binary reference."""
     import torch
     from . import binding as hb
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -131,11 +133,20 @@ def judge(weights, contones, seeds, precision=None, with_fs=True):
     prec = hb.HS_FP32 if precision is None else precision
     out = {}
     N = c.shape[0]
-    bits = hb.halftone_infer(w, c, s, precision=prec)
-    loss = hb.halftone_loss(bits, c)[:3 * N].view(N, 3).double()
+    if levels > 2:
+        H, W = c.shape[1:]
+        k = hb.halftone_infer_pages(w, c.reshape(-1), s, [(H, W)] * N, precision=prec,
+                                    levels=levels).view(N, H, W)
+        loss = hb.halftone_loss(k, c, prm=hb.default_loss_params(levels=levels))
+        fill = k.double().mean() / (levels - 1)
+    else:
+        bits = hb.halftone_infer(w, c, s, precision=prec)
+        loss = hb.halftone_loss(bits, c)
+        fill = bits.double().mean()
+    loss = loss[:3 * N].view(N, 3).double()
     out["policy_hvs_mse"] = float(loss[:, 0].mean())
     out["policy_cssim"] = float(loss[:, 1].mean())
-    out["policy_fill"] = float(bits.double().mean())
+    out["policy_fill"] = float(fill)
     if with_fs:
         fs = hb.halftone_error_diffusion_host(np.asarray(contones)).to(dev)
         lf = hb.halftone_loss(fs, c)[:3 * N].view(N, 3).double()
@@ -161,8 +172,12 @@ def main(argv=None):
     ap.add_argument("--ws", type=float, default=None,
                     help="CSSIM weight w_s of the reward (default 0.06; 0 = HVS-MSE only)")
     ap.add_argument("--wa", type=float, default=None, help="anisotropy weight w_a (default 0.002)")
+    ap.add_argument("--wa-from", type=int, default=0,
+                    help="first step with the anisotropy loss (w_a = 0 before it)")
     ap.add_argument("--estimator", choices=["le", "coma"], default="le",
                     help="policy-gradient estimator: Local Expectation (Eq. le) or COMA (Eq. coma)")
+    ap.add_argument("--levels", type=int, default=2,
+                    help="output levels: 2 = binary halftoning, 3..8 = multitoning (Sec. VII)")
     ap.add_argument("--judge-every", type=int, default=0,
                     help="steps between held-out evaluations of the policy during training")
     ap.add_argument("--out", default=None, help="write the trained weights (.npy)")
@@ -192,19 +207,26 @@ def main(argv=None):
     if args.wa is not None:
         kw["w_a"] = args.wa
     kw["estimator"] = hb.HS_EST_COMA if args.estimator == "coma" else hb.HS_EST_LE
+    kw["levels"] = args.levels
     tp = hb.default_train_params(**kw)
     tr = Trainer(pool, args.steps, batch=args.batch, run_seed=args.run_seed,
                  weight_seed=args.weight_seed, precision=prec, tp=tp)
     w0 = tr.weights.clone()
-    before = judge(w0, held, hseeds)
+    before = judge(w0, held, hseeds, levels=args.levels)
     log("untrained: " + json.dumps(before))
-    gbefore = judge(w0, gheld, gseeds)
+    gbefore = judge(w0, gheld, gseeds, levels=args.levels)
     log("untrained, constant grays: " + json.dumps(gbefore))
     t1 = time.perf_counter()
     last = t1
     hist = []
     curve = []
+    wa_full = tp.loss.w_a
+    if args.wa_from > 0:
+        tr.state.tp.loss.w_a = 0.0
     for i in range(args.steps):
+        if args.wa_from > 0 and i == args.wa_from:
+            tr.state.tp.loss.w_a = wa_full
+            log("step %d: anisotropy loss on (w_a = %g)" % (i, wa_full))
         m = tr.step()
         now = time.perf_counter()
         if now - last >= args.log_every or i == args.steps - 1:
@@ -215,15 +237,15 @@ def main(argv=None):
                    mv[5], mv[6]))
             last = now
         if args.judge_every and (i + 1) % args.judge_every == 0 and i + 1 < args.steps:
-            j = judge(tr.weights, held, hseeds, with_fs=False)
+            j = judge(tr.weights, held, hseeds, with_fs=False, levels=args.levels)
             curve.append([i + 1, j["policy_hvs_mse"], j["policy_fill"]])
             log("judge at step %d: policy HVS-MSE %.6g (FS %.6g) fill %.4f"
                 % (i + 1, j["policy_hvs_mse"], before["fs_hvs_mse"], j["policy_fill"]))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
-    after = judge(tr.weights, held, hseeds)
+    after = judge(tr.weights, held, hseeds, levels=args.levels)
     log("trained: " + json.dumps(after))
-    gafter = judge(tr.weights, gheld, gseeds)
+    gafter = judge(tr.weights, gheld, gseeds, levels=args.levels)
     log("trained, constant grays: " + json.dumps(gafter))
     if args.out:
         np.save(args.out, tr.weights.cpu().numpy())
@@ -231,7 +253,7 @@ def main(argv=None):
            "w_s": tp.loss.w_s, "w_a": tp.loss.w_a, "estimator": args.estimator,
            "precision": "fp32" if args.fp32 else "bf16", "train_seconds": round(train_s, 2),
            "steps_per_s": round(args.steps / train_s, 2), "judge_images": args.judge,
-           "flat_frac": args.flat_frac,
+           "flat_frac": args.flat_frac, "levels": args.levels, "wa_from": args.wa_from,
            "untrained": before, "trained": after, "judge_curve": curve,
            "untrained_gray": gbefore, "trained_gray": gafter,
            "trained_beats_fs": after["policy_hvs_mse"] < after["fs_hvs_mse"]}
