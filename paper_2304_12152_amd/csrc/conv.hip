@@ -62,14 +62,25 @@ __global__ __launch_bounds__(256) void conv32_kernel(const T* __restrict__ in,
   __shared__ __attribute__((aligned(16))) T lds[CL_H * CL_W * 32];
   const int b = blockIdx.z, y0 = blockIdx.y * CT_H, x0 = blockIdx.x * CT_W;
   const size_t img = (size_t)b * H * W;
-  for (int i = threadIdx.x; i < CL_H * CL_W * CPP; i += 256) {
+  // all of the tile's 16-byte loads are issued before the first LDS store
+  constexpr int NCH = CL_H * CL_W * CPP, NIT = (NCH + 255) / 256;
+  uint4 v[NIT];
+#pragma unroll
+  for (int k = 0; k < NIT; ++k) {
+    const int i = (int)threadIdx.x + 256 * k;
     const int p = i / CPP, c = i - p * CPP;
     const int ly = p / CL_W, lx = p - ly * CL_W;
     const int gy = y0 + ly - 1, gx = x0 + lx - 1;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-      v = *(const uint4*)(in + (img + (size_t)gy * W + gx) * 32 + c * EPC);
-    *(uint4*)(lds + p * 32 + hs_swz<T>(lx, c) * EPC) = v;
+    v[k] = make_uint4(0u, 0u, 0u, 0u);
+    if (i < NCH && gy >= 0 && gy < H && gx >= 0 && gx < W)
+      v[k] = *(const uint4*)(in + (img + (size_t)gy * W + gx) * 32 + c * EPC);
+  }
+#pragma unroll
+  for (int k = 0; k < NIT; ++k) {
+    const int i = (int)threadIdx.x + 256 * k;
+    const int p = i / CPP, c = i - p * CPP;
+    const int lx = p - (p / CL_W) * CL_W;
+    if (i < NCH) *(uint4*)(lds + p * 32 + hs_swz<T>(lx, c) * EPC) = v[k];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
@@ -398,16 +409,47 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(const T* __restrict__ a_in
 // Weight gradient of a 32->32 layer on the BF16 matrix cores (FP32
 // accumulation). K is the pixel dimension: a lane's 8 K-values are 8
 // consecutive pixels of one row. The output gradient is staged transposed,
-// gT[co][px]; the input tile is staged as three transposed copies shifted by
-// dx = 0, 1, 2 columns, aS[dx][ci][row][col] = a[y0-1+row][x0-1+col+dx][ci],
-// so the K-slice of every tap is one aligned 16-byte read. Tile = 2 x 64
-// pixels; wave w owns the (co tile, ci tile) = (w >> 1, w & 1) block of all
-// nine taps; the bias gradient is one more MFMA against a ones operand.
+// gT[co][px]; the input tile once, transposed, aS[ci][row][col] =
+// a[y0-1+row][x0-1+col][ci] for col = 0..67. The K-slice of tap dx starts
+// dx columns into an aligned 8-column group, so it is built from two
+// aligned 16-byte LDS reads: the first one (dx = 0), a 2-byte funnel shift
+// across the pair (dx = 1) or dwords 1..4 of the pair (dx = 2). Tile =
+// 2 x 64 pixels; wave w owns the (co tile, ci tile) = (w >> 1, w & 1) block
+// of all nine taps; the bias gradient is one more MFMA against a ones
+// operand.
+// Staging: "a" operations (4 consecutive columns x 8 channels of one row)
+// number (WB_H + 2) x 17 x 4 = 272, "g" operations WB_H x 16 x 4 = 128;
+// thread i owns operations i and i + 256 of the 400. All of a tile's global
+// loads are issued together into registers, and the next tile's loads are
+// in flight while the current tile's MFMAs run.
 // ---------------------------------------------------------------------------
 constexpr int WB_H = 2, WB_W = 64, WB_PX = WB_H * WB_W;
-constexpr int WB_GS = WB_PX + 8;           // gT channel stride (17 x 16 B: odd)
-constexpr int WB_RS = WB_W + 8;            // aS row stride
-constexpr int WB_CS = (WB_H + 2) * WB_RS + 8;  // aS channel stride (37 x 16 B: odd)
+constexpr int WB_GS = WB_PX + 8;                // gT channel stride (17 x 16 B: odd)
+constexpr int WB_AC = WB_W + 4;                 // staged input columns (68)
+constexpr int WB_RS = WB_W + 8;                 // aS row stride (72)
+constexpr int WB_CS = (WB_H + 2) * WB_RS + 8;   // aS channel stride (37 x 16 B: odd)
+constexpr int WB_AOPS = (WB_H + 2) * (WB_AC / 4) * 4;  // 272
+constexpr int WB_GOPS = WB_H * (WB_W / 4) * 4;          // 128
+static_assert(WB_AOPS + WB_GOPS <= 512 && WB_AOPS >= 256, "wgrad staging split");
+
+// 8 consecutive bf16 starting `dx` elements into the 16 loaded ones
+HS_DEV bf16x8_t shift_frag(const bf16x8_t lo, const bf16x8_t hi, int dx) {
+  uint32_t d[8], o[4];
+  __builtin_memcpy(d, &lo, 16);
+  __builtin_memcpy(d + 4, &hi, 16);
+  if (dx == 0) {
+    return lo;
+  } else if (dx == 1) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = __builtin_amdgcn_alignbyte(d[j + 1], d[j], 2);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = d[j + 1];
+  }
+  bf16x8_t v;
+  __builtin_memcpy(&v, o, 16);
+  return v;
+}
 
 __global__ __launch_bounds__(256) void wgrad32_bf16_kernel(const __bf16* __restrict__ a_in,
                                                            const __bf16* __restrict__ g_out,
@@ -415,7 +457,7 @@ __global__ __launch_bounds__(256) void wgrad32_bf16_kernel(const __bf16* __restr
                                                            float* __restrict__ partials,
                                                            int accumulate) {
   __shared__ __attribute__((aligned(16))) __bf16 gT[32 * WB_GS];
-  __shared__ __attribute__((aligned(16))) __bf16 aS[3 * 32 * WB_CS];
+  __shared__ __attribute__((aligned(16))) __bf16 aS[32 * WB_CS];
   const int tiles_x = (W + WB_W - 1) / WB_W, tiles_y = (H + WB_H - 1) / WB_H;
   const int ntiles = B * tiles_x * tiles_y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
@@ -426,58 +468,75 @@ __global__ __launch_bounds__(256) void wgrad32_bf16_kernel(const __bf16* __restr
   bf16x8_t ones;
 #pragma unroll
   for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  // operation k of this thread: kind (0 none, 1 a, 2 g), source row and
+  // first column relative to (y0, x0), channel group, LDS destination;
+  // identical for every tile
+  int o_kind[2], o_row[2], o_col[2], o_c8[2], o_dst[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    int q = (int)threadIdx.x + 256 * k;
+    o_kind[k] = q < WB_AOPS ? 1 : (q < WB_AOPS + WB_GOPS ? 2 : 0);
+    const bool is_g = o_kind[k] == 2;
+    if (is_g) q -= WB_AOPS;
+    const int c8 = q & 3;
+    q >>= 2;
+    const int ngrp = is_g ? WB_W / 4 : WB_AC / 4;
+    const int j4 = (q % ngrp) * 4, row = q / ngrp;
+    o_row[k] = is_g ? row : row - 1;
+    o_col[k] = is_g ? j4 : j4 - 1;
+    o_c8[k] = c8;
+    o_dst[k] = is_g ? (8 * c8) * WB_GS + row * WB_W + j4 : (8 * c8) * WB_CS + row * WB_RS + j4;
+  }
+  bf16x8_t v[2][4];
+  auto load = [&](int tile) {
     const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
     const int y0 = (rem / tiles_x) * WB_H, x0 = (rem % tiles_x) * WB_W;
     const size_t img = (size_t)b * H * W;
-    __syncthreads();
-    // one operation = 4 consecutive pixels x 8 channels -> 8 stores of 4 values
-    for (int op = threadIdx.x; op < 3 * (WB_H + 2) * (WB_W / 4) * 4 + WB_H * (WB_W / 4) * 4;
-         op += 256) {
-      const bool is_g = op >= 3 * (WB_H + 2) * (WB_W / 4) * 4;
-      int q = is_g ? op - 3 * (WB_H + 2) * (WB_W / 4) * 4 : op;
-      const int c8 = q & 3;
-      q >>= 2;
-      const int j4 = (q % (WB_W / 4)) * 4;
-      q /= WB_W / 4;
-      int row, dx = 0;
-      if (is_g) {
-        row = q;  // 0..WB_H-1
-      } else {
-        row = q % (WB_H + 2);
-        dx = q / (WB_H + 2);
-      }
-      const int gy = is_g ? y0 + row : y0 - 1 + row;
-      const __bf16* src = is_g ? g_out : a_in;
-      bf16x8_t v[4];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const __bf16* src = o_kind[k] == 2 ? g_out : a_in;
+      const int gy = y0 + o_row[k];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int gx = is_g ? x0 + j4 + u : x0 - 1 + j4 + u + dx;
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-          v[u] = *(const bf16x8_t*)(src + (img + (size_t)gy * W + gx) * 32 + 8 * c8);
+        const int gx = x0 + o_col[k] + u;
+        if (o_kind[k] != 0 && gy >= 0 && gy < H && gx >= 0 && gx < W)
+          v[k][u] = *(const bf16x8_t*)(src + (img + (size_t)gy * W + gx) * 32 + 8 * o_c8[k]);
         else
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[u][e] = (__bf16)0.0f;
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        bf16x4_t w4 = bf16x4_t{v[0][e], v[1][e], v[2][e], v[3][e]};
-        __bf16* dst = is_g ? gT + (8 * c8 + e) * WB_GS + row * WB_W + j4
-                           : aS + (dx * 32 + 8 * c8 + e) * WB_CS + row * WB_RS + j4;
-        *(bf16x4_t*)dst = w4;
+          for (int e = 0; e < 8; ++e) v[k][u][e] = (__bf16)0.0f;
       }
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (o_kind[k] == 0) continue;
+      __bf16* base = (o_kind[k] == 2 ? gT : aS) + o_dst[k];
+      const int cs = o_kind[k] == 2 ? WB_GS : WB_CS;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        *(bf16x4_t*)(base + e * cs) = bf16x4_t{v[k][0][e], v[k][1][e], v[k][2][e], v[k][3][e]};
+    }
+  };
+  if ((int)blockIdx.x < ntiles) load(blockIdx.x);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();  // the previous tile's MFMAs have read the LDS tiles
+    store();
     __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
 #pragma unroll
     for (int kc = 0; kc < WB_PX / 32; ++kc) {
       const int py = kc / (WB_W / 32), pc = (kc % (WB_W / 32)) * 32 + 8 * g;
       const bf16x8_t af = *(const bf16x8_t*)(gT + (16 * mt + r) * WB_GS + py * WB_W + pc);
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int dy = t / 3, dx = t - (t / 3) * 3;
-        const bf16x8_t bfr =
-            *(const bf16x8_t*)(aS + (dx * 32 + 16 * nt + r) * WB_CS + (py + dy) * WB_RS + pc);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc[t], 0, 0, 0);
+      for (int dy = 0; dy < 3; ++dy) {
+        const __bf16* rowp = aS + (16 * nt + r) * WB_CS + (py + dy) * WB_RS + pc;
+        const bf16x8_t lo = *(const bf16x8_t*)rowp;
+        const bf16x8_t hi = *(const bf16x8_t*)(rowp + 8);
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+          acc[dy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, shift_frag(lo, hi, dx),
+                                                                      acc[dy * 3 + dx], 0, 0, 0);
       }
       if (nt == 0) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, ones, accb, 0, 0, 0);
     }

@@ -172,6 +172,9 @@ __global__ void loss_reduce_kernel(const float* __restrict__ partials, int B, in
   }
 }
 
+// MULTI: multitone levels (q.levels > 2), with the var_h map; otherwise the
+// binary form, whose var_h is mu_h (1 - mu_h)
+template <bool MULTI>
 __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict__ h,
                                                       const float* __restrict__ c,
                                                       const float* __restrict__ probs,
@@ -181,7 +184,8 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
                                                       const float* __restrict__ maps, float invM,
                                                       float* __restrict__ grad) {
   __shared__ float se[LS * LS], smh[LS * LS], smc[LS * LS], svc[LS * LS], scv[LS * LS],
-      ssg[LS * LS], svh[LS * LS];
+      ssg[LS * LS];
+  __shared__ float svh[MULTI ? LS * LS : 1];
   __shared__ float sG[15 * 15], sw[15 * 15];
   const int b = blockIdx.z, R = q.m;
   const int ay0 = blockIdx.y * LT, ax0 = blockIdx.x * LT;
@@ -202,7 +206,7 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
       v2 = maps[2 * n + o];
       v3 = maps[3 * n + o];
       v4 = maps[4 * n + o];
-      if (q.levels > 2) v5 = maps[5 * n + o];
+      if (MULTI) v5 = maps[5 * n + o];
     }
     se[i] = v0;
     smh[i] = v1;
@@ -210,17 +214,16 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
     svc[i] = v3;
     scv[i] = v4;
     ssg[i] = q.k * sqrtf(v3);
-    svh[i] = v5;
+    if (MULTI) svh[i] = v5;
   }
   __syncthreads();
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   const int ay = ay0 + ty, ax = ax0 + tx;
   if (ay >= H || ax >= W) return;
   const size_t oa = img + (size_t)ay * W + ax;
-  const bool multi = q.levels > 2;
   float delta = h[oa] ? -1.0f : 1.0f;
   const float ha = (float)h[oa] * q.hstep;
-  if (multi) {
+  if (MULTI) {
     const float t = probs[oa] * (float)(q.levels - 1);
     const int kf = min((int)floorf(t), q.levels - 2);
     delta = (int)h[oa] == kf ? q.hstep : -q.hstep;
@@ -252,13 +255,13 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
       const float A = 2.0f * mh * mc + q.c1;
       const float Bc = 2.0f * scv[p] + q.c2;
       const float C = mh * mh + mc * mc + q.c1;
-      const float D = (multi ? svh[p] : mh * (1.0f - mh)) + svc[p] + q.c2;
+      const float D = (MULTI ? svh[p] : mh * (1.0f - mh)) + svc[p] + q.c2;
       const float dw = delta * wa;
       const float dA = 2.0f * dw * mc;
       const float dB = 2.0f * dw * (ca - mc);
       const float dC = dw * (2.0f * mh + dw);
       // binary: 2 h_a + delta = 1 for either toggle
-      const float dD = dw * ((multi ? 2.0f * ha + delta : 1.0f) - 2.0f * mh - dw);
+      const float dD = dw * ((MULTI ? 2.0f * ha + delta : 1.0f) - 2.0f * mh - dw);
       const float num = C * D * (A * dB + Bc * dA + dA * dB) - A * Bc * (C * dD + D * dC + dC * dD);
       const float den = (C + dC) * (D + dD) * (C * D);
       // hardware reciprocal (1 ulp) instead of the IEEE division sequence
@@ -493,7 +496,8 @@ hipError_t launch_le_grad(const uint8_t* h, const float* c, const float* probs, 
   const LossConst q = make_const(p);
   const long M = (long)(H - 2 * q.m) * (W - 2 * q.m);
   const dim3 grid((W + LT - 1) / LT, (H + LT - 1) / LT, B);
-  le_grad_kernel<<<grid, 256, 0, s>>>(h, c, probs, logit_space, B, H, W, q, win, maps,
+  auto kern = q.levels > 2 ? le_grad_kernel<true> : le_grad_kernel<false>;
+  kern<<<grid, 256, 0, s>>>(h, c, probs, logit_space, B, H, W, q, win, maps,
                                       (float)(1.0 / (double)M), grad);
   return hipGetLastError();
 }

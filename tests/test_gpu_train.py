@@ -63,6 +63,15 @@ def test_policy_backward_bf16(orc):
     for lo, hi in [(0, 608), (608, 9856), (9856, 19104), (19104, 28352), (28352, 37600),
                    (37600, 37889)]:
         assert _rel(g[lo:hi], ref[lo:hi]) < 0.3
+    # every tap of the four 32 -> 32 weight gradients on its own (a tap taken
+    # from the wrong column or row would be off by O(1))
+    for k in range(4):
+        lo = 608 + k * 9248
+        gw_k = g[lo:lo + 9216].reshape(32, 32, 9)
+        rw_k = ref[lo:lo + 9216].reshape(32, 32, 9)
+        errs = [_rel(gw_k[:, :, t], rw_k[:, :, t]) for t in range(9)]
+        print("layer", k + 2, "per-tap relative error", np.round(errs, 4), flush=True)
+        assert max(errs) < 0.3, (k, errs)
 
 
 def test_autograd_wrappers(orc):
