@@ -296,6 +296,21 @@ def main():
                           "config": "32 x 256x256 crops + 64 constant-gray 64x64, BF16 "
                                     "activations, FP32 master weights, Adam"}
         log("train: %.2f steps/s" % sps)
+        # the same steps with activation recomputation (two activation maps)
+        tpr = hb.default_train_params(recompute=1)
+        state_r = hb.TrainState(tw, Bt, Ht, Wt, Bg, 64, 64, precision=hb.HS_BF16, tp=tpr)
+        hb.policy_train_step(state_r, tc, ts, gray, gs, 0, 1000)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for i in range(args.train_steps):
+            hb.policy_train_step(state_r, tc, ts, gray, gs, 1 + i, 1000)
+        torch.cuda.synchronize()
+        sps_r = args.train_steps / (time.perf_counter() - t3)
+        extra["train"]["recompute"] = {"value": round(sps_r, 2), "unit": "steps/s",
+                                       "workspace_gb": round(state_r.ws.numel() / 1e9, 3),
+                                       "workspace_gb_without": round(state.ws.numel() / 1e9, 3)}
+        del state_r
+        log("train with recomputation: %.2f steps/s" % sps_r)
     if not args.no_pages:
         extra["pages"] = bench_pages(hb, synth, torch, dev, wt, args.page_steps, args.tau)
     out = {

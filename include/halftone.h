@@ -92,7 +92,14 @@ typedef struct hs_loss_params {
 
 /* Optimiser and sampling parameters of one TRAIN iteration (Algorithm 1).
  * Defaults: Adam beta1 0.9, beta2 0.999, eps 1e-8; cosine learning rate
- * from lr_max 3e-4 to lr_min 1e-5 over total_steps (Sec. VI-A). */
+ * from lr_max 3e-4 to lr_min 1e-5 over total_steps (Sec. VI-A); all
+ * activations kept for the backward (recompute = 0).
+ *
+ * recompute = 1 keeps two activation maps instead of five: the backward
+ * rebuilds the input of each 32->32 layer by re-running layers 1..k-1 on the
+ * same input and noise (the same kernels, so the same values and the same
+ * gradient), for large crops. It costs ten more layer launches per batch
+ * and saves three NHWC activation maps (3 x 64 B per pixel in BF16). */
 typedef struct hs_train_params {
   hs_loss_params loss;
   float lr_max;
@@ -101,6 +108,7 @@ typedef struct hs_train_params {
   float beta2;
   float eps;
   int noise_kind; /* HS_NOISE_* */
+  int recompute;  /* 0: keep activations; 1: recompute them in the backward */
 } hs_train_params;
 
 void halftone_default_loss_params(hs_loss_params* p);
@@ -279,6 +287,10 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
  * --------------------------------------------------------------------- */
 size_t halftone_train_workspace_size(int B, int H, int W, int Bg, int Hg, int Wg,
                                      int precision);
+/* the same for the given parameters (smaller with tp->recompute = 1; a NULL
+ * tp is the defaults) */
+size_t halftone_train_workspace_size_params(int B, int H, int W, int Bg, int Hg, int Wg,
+                                            int precision, const hs_train_params* tp);
 int policy_train_step(float* weights, float* adam_m, float* adam_v, const float* contones,
                       const uint64_t* seeds, int B, int H, int W, const float* gray,
                       const uint64_t* gray_seeds, int Bg, int Hg, int Wg, int64_t step,

@@ -32,7 +32,7 @@ class HsLossParams(ctypes.Structure):
 class HsTrainParams(ctypes.Structure):
     _fields_ = [("loss", HsLossParams), ("lr_max", ctypes.c_float), ("lr_min", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
-                ("noise_kind", ctypes.c_int)]
+                ("noise_kind", ctypes.c_int), ("recompute", ctypes.c_int)]
 
 
 class HalftoneError(RuntimeError):
@@ -66,6 +66,8 @@ _SIGS = {
     "halftone_loss_backward": (I, [P, P, P, I, I, I, P, I, I, I, ctypes.POINTER(HsLossParams), I,
                                    P, P, P, SZ, P]),
     "halftone_train_workspace_size": (SZ, [I, I, I, I, I, I, I]),
+    "halftone_train_workspace_size_params": (SZ, [I, I, I, I, I, I, I,
+                                                  ctypes.POINTER(HsTrainParams)]),
     "policy_train_step": (I, [P, P, P, P, P, I, I, I, P, P, I, I, I, ctypes.c_int64,
                               ctypes.c_int64, ctypes.POINTER(HsTrainParams), I, P, P, P, P, SZ,
                               P]),
@@ -269,7 +271,8 @@ class TrainState:
         self.precision = precision
         self.tp = tp or default_train_params()
         self.shape = (B, H, W, Bg, Hg, Wg)
-        need = lib().halftone_train_workspace_size(B, H, W, Bg, Hg, Wg, precision)
+        need = lib().halftone_train_workspace_size_params(B, H, W, Bg, Hg, Wg, precision,
+                                                          ctypes.byref(self.tp))
         self.ws = _ws(need, dev)
         self.metrics = torch.zeros(8, dtype=torch.float32, device=dev)
 

@@ -90,16 +90,23 @@ int margin(const hs_loss_params* p) {
 }
 
 // ---------------------------------------------------------------- layouts --
+// Activations of the training forward: act(j) is the output of layer j + 1
+// (j = 0..4). Kept in five buffers, or, with recomputation, in two that
+// alternate (act(j) in buffer j % 2): the backward then rebuilds act(j)
+// from the input by re-running layers 1..j+1 when it needs it.
 struct PolicyWs {
-  void *packF, *packT, *act[5], *gA, *gB;
+  void *packF, *packT, *buf[5], *gA, *gB;
   float *z, *c, *g6, *partials, *rtmp;
   unsigned long long* counter;
+  bool recompute;
+  void* act(int j) const { return buf[recompute ? j % 2 : j]; }
 };
-PolicyWs carve_policy(Carve& cv, size_t N, int prec) {
+PolicyWs carve_policy(Carve& cv, size_t N, int prec, bool recompute = false) {
   PolicyWs w;
+  w.recompute = recompute;
   w.packF = cv.take<char>(pack_bytes(prec));
   w.packT = cv.take<char>(pack_bytes(prec));
-  for (int k = 0; k < 5; ++k) w.act[k] = cv.take<char>(act_bytes(N, prec));
+  for (int k = 0; k < 5; ++k) w.buf[k] = k < (recompute ? 2 : 5) ? cv.take<char>(act_bytes(N, prec)) : nullptr;
   w.gA = cv.take<char>(act_bytes(N, prec));
   w.gB = cv.take<char>(act_bytes(N, prec));
   w.z = cv.take<float>(N * 4);
@@ -144,41 +151,70 @@ hipError_t run_forward_train(const float* w, const float* contone, const uint64_
                              float* probs, uint8_t* actions, int levels, hipStream_t s) {
   hipError_t e;
   if ((e = launch_pack32(w, pw.packF, prec, 0, s)) != hipSuccess) return e;
-  if ((e = launch_conv_first(contone, seeds, w, B, H, W, kind, step, prec, pw.act[0], pw.z, pw.c,
+  if ((e = launch_conv_first(contone, seeds, w, B, H, W, kind, step, prec, pw.act(0), pw.z, pw.c,
                              s)) != hipSuccess)
     return e;
   const size_t per_layer = (size_t)PACK32_PER_LAYER * (prec == HS_BF16 ? 2 : 4);
   for (int k = 2; k <= 5; ++k) {
-    if ((e = launch_conv32(pw.act[k - 2], (const char*)pw.packF + (k - 2) * per_layer,
-                           w + hs_bk(k), nullptr, pw.act[k - 1], B, H, W, prec, 0, s)) !=
+    if ((e = launch_conv32(pw.act(k - 2), (const char*)pw.packF + (k - 2) * per_layer,
+                           w + hs_bk(k), nullptr, pw.act(k - 1), B, H, W, prec, 0, s)) !=
         hipSuccess)
       return e;
   }
-  return launch_conv_last(pw.act[4], w, B, H, W, prec, 1, seeds, step, actions, nullptr, probs,
+  return launch_conv_last(pw.act(4), w, B, H, W, prec, 1, seeds, step, actions, nullptr, probs,
                           0.0f, nullptr, nullptr, make_levels(levels), s);
+}
+
+// Recomputation: act(j) again from the input (layers 1..j+1, the same
+// kernels and inputs as the forward, so the same values); z and c are kept.
+struct FwdInput {
+  const float* contone;
+  const uint64_t* seeds;
+  int kind;
+  uint32_t step;
+};
+hipError_t recompute_act(const float* w, const FwdInput& in, int j, int B, int H, int W, int prec,
+                         const PolicyWs& pw, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_conv_first(in.contone, in.seeds, w, B, H, W, in.kind, in.step, prec, pw.act(0),
+                             nullptr, nullptr, s)) != hipSuccess)
+    return e;
+  const size_t per_layer = (size_t)PACK32_PER_LAYER * (prec == HS_BF16 ? 2 : 4);
+  for (int k = 2; k <= j + 1; ++k) {
+    if ((e = launch_conv32(pw.act(k - 2), (const char*)pw.packF + (k - 2) * per_layer,
+                           w + hs_bk(k), nullptr, pw.act(k - 1), B, H, W, prec, 0, s)) !=
+        hipSuccess)
+      return e;
+  }
+  return hipSuccess;
 }
 
 // Backward of the stack given dL/dprobs (probs != null) or dL/dlogit
 // (probs == null); accumulates into the weight-gradient partial rows.
+// With pw.recompute, `in` must be the forward's input (act(4) is still in
+// its buffer from the forward; the others are rebuilt layer by layer).
 hipError_t run_backward(const float* w, const float* grad, const float* probs, int B, int H,
-                        int W, int prec, const PolicyWs& pw, int accumulate, hipStream_t s) {
+                        int W, int prec, const PolicyWs& pw, int accumulate, hipStream_t s,
+                        const FwdInput* in = nullptr) {
   hipError_t e;
   if ((e = launch_pack32(w, pw.packT, prec, 1, s)) != hipSuccess) return e;
-  if ((e = launch_dgrad_last(grad, probs, pw.act[4], w, B, H, W, prec, pw.g6, pw.gA, s)) !=
+  if ((e = launch_dgrad_last(grad, probs, pw.act(4), w, B, H, W, prec, pw.g6, pw.gA, s)) !=
       hipSuccess)
     return e;
-  if ((e = launch_wgrad_last(pw.act[4], pw.g6, B, H, W, prec, pw.partials, accumulate, s)) !=
+  if ((e = launch_wgrad_last(pw.act(4), pw.g6, B, H, W, prec, pw.partials, accumulate, s)) !=
       hipSuccess)
     return e;
   const size_t per_layer = (size_t)PACK32_PER_LAYER * (prec == HS_BF16 ? 2 : 4);
   void* g = pw.gA;  // gradient at the pre-activation of layer k
   void* other = pw.gB;
   for (int k = 5; k >= 2; --k) {
-    if ((e = launch_wgrad32(pw.act[k - 2], g, k, B, H, W, prec, pw.partials, accumulate, s)) !=
+    if (pw.recompute && (e = recompute_act(w, *in, k - 2, B, H, W, prec, pw, s)) != hipSuccess)
+      return e;
+    if ((e = launch_wgrad32(pw.act(k - 2), g, k, B, H, W, prec, pw.partials, accumulate, s)) !=
         hipSuccess)
       return e;
     if ((e = launch_conv32(g, (const char*)pw.packT + (k - 2) * per_layer, nullptr,
-                           pw.act[k - 2], other, B, H, W, prec, 1, s)) != hipSuccess)
+                           pw.act(k - 2), other, B, H, W, prec, 1, s)) != hipSuccess)
       return e;
     void* t = g;
     g = other;
@@ -274,6 +310,7 @@ void halftone_default_train_params(hs_train_params* p) {
   p->beta2 = 0.999f;
   p->eps = 1e-8f;
   p->noise_kind = HS_NOISE_GAUSS;
+  p->recompute = 0;
 }
 
 int halftone_version(void) { return 100; }
@@ -698,13 +735,14 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
 }
 
 // ------------------------------------------------------------ train step --
-static size_t train_ws(int B, int H, int W, int Bg, int Hg, int Wg, int prec, void* base,
-                       PolicyWs* pw, LossWs* lw, float** probs, float** probs_g, uint8_t** act,
-                       float** gradp, float** gradg, float** grad, float** loss_out) {
+static size_t train_ws(int B, int H, int W, int Bg, int Hg, int Wg, int prec, bool recompute,
+                       void* base, PolicyWs* pw, LossWs* lw, float** probs, float** probs_g,
+                       uint8_t** act, float** gradp, float** gradg, float** grad,
+                       float** loss_out) {
   Carve cv(base);
   const size_t N = (size_t)B * H * W, Ng = (size_t)Bg * Hg * Wg;
   const size_t Nmax = N > Ng ? N : Ng;
-  PolicyWs p = carve_policy(cv, Nmax, prec);
+  PolicyWs p = carve_policy(cv, Nmax, prec, recompute);
   // sized for the smallest margin (most tiles); the caller sets the real count
   LossWs l = carve_loss(cv, B, H, W, Bg, Hg, Wg, 1, true);
   float* pr = cv.take<float>(N * 4);
@@ -726,13 +764,18 @@ static size_t train_ws(int B, int H, int W, int Bg, int Hg, int Wg, int prec, vo
   return cv.off;
 }
 
-size_t halftone_train_workspace_size(int B, int H, int W, int Bg, int Hg, int Wg,
-                                     int precision) {
+size_t halftone_train_workspace_size_params(int B, int H, int W, int Bg, int Hg, int Wg,
+                                            int precision, const hs_train_params* tp) {
   if (!shape_ok(B, H, W) || Bg < 0) return 0;
   if (Bg > 0 && !shape_ok(Bg, Hg, Wg)) return 0;
   if (Bg == 0) Hg = Wg = 0;
-  return train_ws(B, H, W, Bg, Hg, Wg, precision, nullptr, nullptr, nullptr, nullptr, nullptr,
-                  nullptr, nullptr, nullptr, nullptr, nullptr);
+  return train_ws(B, H, W, Bg, Hg, Wg, precision, tp && tp->recompute, nullptr, nullptr, nullptr,
+                  nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+size_t halftone_train_workspace_size(int B, int H, int W, int Bg, int Hg, int Wg,
+                                     int precision) {
+  return halftone_train_workspace_size_params(B, H, W, Bg, Hg, Wg, precision, nullptr);
 }
 
 int policy_train_step(float* weights, float* adam_m, float* adam_v, const float* contones,
@@ -759,7 +802,9 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
                 2 * m + 1);
   if (Bg > 0 && !shape_ok(Bg, Hg, Wg))
     return fail(HS_ESHAPE, "policy_train_step: bad gray-batch shape");
-  if (workspace_bytes < halftone_train_workspace_size(B, H, W, Bg, Hg, Wg, precision))
+  if (tp->recompute != 0 && tp->recompute != 1)
+    return fail(HS_EINVAL, "policy_train_step: recompute %d", tp->recompute);
+  if (workspace_bytes < halftone_train_workspace_size_params(B, H, W, Bg, Hg, Wg, precision, tp))
     return fail(HS_EWORKSPACE, "policy_train_step: workspace too small");
   if ((rc = check_device())) return rc;
   hipStream_t s = (hipStream_t)stream;
@@ -767,8 +812,8 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   LossWs lw;
   float *probs, *probs_g, *gradp, *gradg, *grad, *loss_out;
   uint8_t* act;
-  train_ws(B, H, W, Bg, Hg, Wg, precision, workspace, &pw, &lw, &probs, &probs_g, &act, &gradp,
-           &gradg, &grad, &loss_out);
+  train_ws(B, H, W, Bg, Hg, Wg, precision, tp->recompute != 0, workspace, &pw, &lw, &probs,
+           &probs_g, &act, &gradp, &gradg, &grad, &loss_out);
   lw.ntiles = ((H - 2 * m + 15) / 16) * ((W - 2 * m + 15) / 16);
   const hs_loss_params& lp = tp->loss;
   const int kind = tp->noise_kind;
@@ -780,7 +825,8 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   make_windows(lp, &win);
   HS_TRY(launch_loss_stats(act, contones, B, H, W, lp, win, lw.maps, lw.tiles, lw.ntiles, s));
   HS_TRY(launch_le_grad(act, contones, probs, 1, B, H, W, lp, win, lw.maps, gradp, s));
-  HS_TRY(run_backward(weights, gradp, nullptr, B, H, W, precision, pw, 0, s));
+  const FwdInput fin{contones, seeds, kind, st};
+  HS_TRY(run_backward(weights, gradp, nullptr, B, H, W, precision, pw, 0, s, &fin));
   // constant-gray side batch: forward, anisotropy gradient, backward
   const int npatch = Bg * (Hg / 32) * (Wg / 32);
   if (Bg > 0) {
@@ -789,7 +835,8 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
     HS_TRY(launch_fill(gradg, (size_t)Bg * Hg * Wg, 0.0f, s));
     if (npatch > 0)
       HS_TRY(launch_as(probs_g, Bg, Hg, Wg, lp.w_a / (float)npatch, 1, lw.patches, gradg, s));
-    HS_TRY(run_backward(weights, gradg, nullptr, Bg, Hg, Wg, precision, pw, 1, s));
+    const FwdInput gin{gray, gray_seeds, kind, st};
+    HS_TRY(run_backward(weights, gradg, nullptr, Bg, Hg, Wg, precision, pw, 1, s, &gin));
   }
   HS_TRY(launch_reduce_partials(pw.partials, WGRAD_BLOCKS, pw.rtmp, grad, s));
   HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, lp.w_s,

@@ -46,11 +46,21 @@ HS_DEV void lds_frag(frag8<float>& f, const float* px, int col, int g) {
 }
 
 // ---------------------------------------------------------------------------
-// 32 -> 32 conv layer. Block = 4 waves over a 4 x 64 pixel tile; wave w owns
-// tile row w as four 16-pixel runs; both 16-channel row tiles of the output.
-// MODE 0: + bias, ReLU.  MODE 1: x [mask > 0] (input gradient through ReLU).
+// 32 -> 32 conv layer. Block = 4 waves over a (4 RPW) x 64 pixel tile; wave
+// w owns tile rows RPW w .. RPW w + RPW - 1 as four 16-pixel runs each, both
+// 16-channel row tiles of the output. With two rows per wave (BF16) every
+// staged input row fragment feeds both output rows (taps dy and dy - 1), so
+// a wave reads 4 x 3 x 4 fragments from LDS for 144 MFMAs instead of
+// 2 x 36 for the same work; each output still sums its taps in the order
+// t = 0..8. MODE 0: + bias, ReLU.  MODE 1: x [mask > 0] (input gradient
+// through ReLU).
 // ---------------------------------------------------------------------------
-constexpr int CT_H = 4, CT_W = 64, CL_H = CT_H + 2, CL_W = CT_W + 2;
+constexpr int CT_W = 64, CL_W = CT_W + 2;
+template <typename T>
+struct conv_rows {
+  static constexpr int RPW = sizeof(T) == 2 ? 2 : 1;  // output rows per wave
+  static constexpr int CT_H = 4 * RPW, CL_H = CT_H + 2;
+};
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void conv32_kernel(const T* __restrict__ in,
@@ -59,6 +69,7 @@ __global__ __launch_bounds__(256) void conv32_kernel(const T* __restrict__ in,
                                                      const T* __restrict__ mask,
                                                      T* __restrict__ out, int H, int W) {
   constexpr int CPP = act_traits<T>::chunks_per_px, EPC = act_traits<T>::elems_per_chunk;
+  constexpr int RPW = conv_rows<T>::RPW, CT_H = conv_rows<T>::CT_H, CL_H = conv_rows<T>::CL_H;
   __shared__ __attribute__((aligned(16))) T lds[CL_H * CL_W * 32];
   const int b = blockIdx.z, y0 = blockIdx.y * CT_H, x0 = blockIdx.x * CT_W;
   const size_t img = (size_t)b * H * W;
@@ -84,47 +95,66 @@ __global__ __launch_bounds__(256) void conv32_kernel(const T* __restrict__ in,
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  f32x4_t acc[2][4];
+  f32x4_t acc[RPW][2][4];
 #pragma unroll
-  for (int m = 0; m < 2; ++m)
+  for (int q = 0; q < RPW; ++q)
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < 2; ++m)
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int dy = t / 3, dx = t - (t / 3) * 3;
-    frag8<T> a0, a1;
-    hs_load_frag(a0, wp + ((t * 2 + 0) * 64 + lane) * 8);
-    hs_load_frag(a1, wp + ((t * 2 + 1) * 64 + lane) * 8);
+      for (int n = 0; n < 4; ++n) acc[q][m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  // input row RPW w + d (d = 0..RPW+1) feeds output row q with tap dy = d - q
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      const int lx = n * 16 + r + dx, ly = wave + dy;
-      frag8<T> bf;
-      lds_frag(bf, lds + (ly * CL_W + lx) * 32, lx, g);
-      acc[0][n] = hs_mma(a0, bf, acc[0][n]);
-      acc[1][n] = hs_mma(a1, bf, acc[1][n]);
-    }
-  }
-  const int gy = y0 + wave;
-  if (gy >= H) return;
+  for (int d = 0; d < RPW + 2; ++d) {
 #pragma unroll
-  for (int n = 0; n < 4; ++n) {
-    const int gx = x0 + n * 16 + r;
-    if (gx >= W) continue;
-    const size_t o = (img + (size_t)gy * W + gx) * 32;
+    for (int dx = 0; dx < 3; ++dx) {
+      frag8<T> a[RPW][2];
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const int co = 16 * m + 4 * g;
-      float v[4];
+      for (int q = 0; q < RPW; ++q) {
+        const int dy = d - q;
+        if (dy < 0 || dy > 2) continue;
+        const int t = dy * 3 + dx;
+        hs_load_frag(a[q][0], wp + ((t * 2 + 0) * 64 + lane) * 8);
+        hs_load_frag(a[q][1], wp + ((t * 2 + 1) * 64 + lane) * 8);
+      }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        v[i] = acc[m][n][i];
-        if (MODE == 0) {
-          v[i] = fmaxf(v[i] + bias[co + i], 0.0f);
-        } else {
-          v[i] = hs_to_f(mask[o + co + i]) > 0.0f ? v[i] : 0.0f;
+      for (int n = 0; n < 4; ++n) {
+        const int lx = n * 16 + r + dx, ly = RPW * wave + d;
+        frag8<T> bf;
+        lds_frag(bf, lds + (ly * CL_W + lx) * 32, lx, g);
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+          const int dy = d - q;
+          if (dy < 0 || dy > 2) continue;
+          acc[q][0][n] = hs_mma(a[q][0], bf, acc[q][0][n]);
+          acc[q][1][n] = hs_mma(a[q][1], bf, acc[q][1][n]);
         }
       }
-      hs_store4(out + o + co, v[0], v[1], v[2], v[3]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RPW; ++q) {
+    const int gy = y0 + RPW * wave + q;
+    if (gy >= H) break;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const int gx = x0 + n * 16 + r;
+      if (gx >= W) continue;
+      const size_t o = (img + (size_t)gy * W + gx) * 32;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int co = 16 * m + 4 * g;
+        float vv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          vv[i] = acc[q][m][n][i];
+          if (MODE == 0) {
+            vv[i] = fmaxf(vv[i] + bias[co + i], 0.0f);
+          } else {
+            vv[i] = hs_to_f(mask[o + co + i]) > 0.0f ? vv[i] : 0.0f;
+          }
+        }
+        hs_store4(out + o + co, vv[0], vv[1], vv[2], vv[3]);
+      }
     }
   }
 }
@@ -784,7 +814,8 @@ hipError_t launch_conv_first(const float* contone, const uint64_t* seeds, const 
 
 hipError_t launch_conv32(const void* in, const void* wpack, const float* bias, const void* mask,
                          void* out, int B, int H, int W, int precision, int mode, hipStream_t s) {
-  const dim3 grid((W + CT_W - 1) / CT_W, (H + CT_H - 1) / CT_H, B);
+  const int ct_h = precision == HS_BF16 ? conv_rows<__bf16>::CT_H : conv_rows<float>::CT_H;
+  const dim3 grid((W + CT_W - 1) / CT_W, (H + ct_h - 1) / ct_h, B);
   if (precision == HS_BF16) {
     if (mode == 0)
       conv32_kernel<__bf16, 0><<<grid, 256, 0, s>>>((const __bf16*)in, (const __bf16*)wpack, bias,

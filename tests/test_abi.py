@@ -239,3 +239,22 @@ def test_levels_argument_errors(lib):
         assert lib.halftone_infer_levels(*a) == hb.HS_EINVAL
     a = list(args); a[13] = need - 1
     assert lib.halftone_infer_levels(*a) == hb.HS_EWORKSPACE
+
+
+def test_recompute_workspace_and_errors(lib):
+    full = hb.default_train_params()
+    rec = hb.default_train_params(recompute=1)
+    for prec, px in ((hb.HS_BF16, 64), (hb.HS_FP32, 128)):
+        n0 = lib.halftone_train_workspace_size_params(32, 256, 256, 64, 64, 64, prec,
+                                                      ctypes.byref(full))
+        n1 = lib.halftone_train_workspace_size_params(32, 256, 256, 64, 64, 64, prec,
+                                                      ctypes.byref(rec))
+        assert n0 == lib.halftone_train_workspace_size(32, 256, 256, 64, 64, 64, prec)
+        # three NHWC activation maps of the larger batch fewer
+        assert n0 - n1 >= 3 * 32 * 256 * 256 * px
+    bad = hb.default_train_params(recompute=2)
+    p = _fake()
+    n = 1 << 30
+    assert lib.policy_train_step(p, p, p, p, p, 1, 32, 32, None, None, 0, 0, 0, 0, 10,
+                                 ctypes.byref(bad), hb.HS_BF16, p, None, None, p, n,
+                                 None) == hb.HS_EINVAL

@@ -213,3 +213,28 @@ def test_short_training_improves_reward():
     first = np.mean(rewards[:5])
     last = np.mean(rewards[-5:])
     assert last > first, (first, last)
+
+
+@pytest.mark.parametrize("prec", [hb.HS_BF16, hb.HS_FP32])
+def test_recompute_gives_the_same_step(prec):
+    """Activation recomputation rebuilds every layer input with the same
+    kernels on the same input: actions, gradient, metrics and the updated
+    weights equal those of the step that keeps all activations, bit for bit."""
+    B, H, W = 2, 48, 80
+    seeds = [70, 71]
+    w = synth.he_weights(11, head_std=0.3)
+    c = synth.contone_batch(seeds, H, W)
+    cg = synth.gray_batch(2, 32, 64)
+    out = []
+    for rec in (0, 1):
+        tp = hb.default_train_params(recompute=rec)
+        st = hb.TrainState(to_dev(w), B, H, W, 2, 32, 64, precision=prec, tp=tp)
+        acts = torch.empty((B, H, W), dtype=torch.uint8, device=device())
+        grad = torch.empty(hb.HS_PARAM_COUNT, dtype=torch.float32, device=device())
+        met = hb.policy_train_step(st, to_dev(c), seeds_t(seeds), to_dev(cg), seeds_t([3, 4]),
+                                   5, 100, actions_out=acts, grad_out=grad).clone()
+        out.append((acts, grad, met, st.weights.clone(), st.ws.numel()))
+    (a0, g0, m0, w0, n0), (a1, g1, m1, w1, n1) = out
+    assert torch.equal(a0, a1) and torch.equal(g0, g1) and torch.equal(m0, m1)
+    assert torch.equal(w0, w1)
+    assert n1 < n0
