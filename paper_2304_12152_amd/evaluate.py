@@ -20,9 +20,15 @@ averaged power and the anisotropy per ring. Reported per method and gray:
               |x| falls in the decades [0, 1e-4), [1e-4, 1e-3), ...,
               [10, inf) -- a bimodal policy keeps almost all of them in the
               top decades -- and recheck / fp32, the fractions the BF16
-              path recomputed with split-BF16 and in FP32.
+              path recomputed with split-BF16 and in FP32; with levels > 2
+              also near_level, the share of v (L - 1) within 0.1 of an
+              integer.
 With K periodograms averaged, an isotropic spectrum has anisotropy about
 1 / K, so -10 log10(K) dB is the floor the figures are read against.
+With --levels L > 2 the policy is the multitoning variant (Sec. VII): its
+output is the level index k, the image k / (L - 1) is scored, and its
+power is taken in units of that image (the level indices' spectrum divided
+by (L - 1)^2); Floyd-Steinberg stays the binary reference.
 
 Command line:
     python -m paper_2304_12152_amd.evaluate --weights weights.npy
@@ -40,11 +46,12 @@ GRAYS = (15, 80, 100, 127)
 LOGIT_DECADES = (1e-4, 1e-3, 1e-2, 1e-1, 1.0, 10.0)
 
 
-def _summary(bits, c, g, P, hb):
+def _summary(bits, c, g, P, hb, levels=2):
     B = c.shape[0]
-    loss = hb.halftone_loss(bits, c)[:3 * B].view(B, 3).double()
+    loss = hb.halftone_loss(bits, c, prm=hb.default_loss_params(levels=levels))
+    loss = loss[:3 * B].view(B, 3).double()
     r, a = hb.halftone_spectrum(bits, P)
-    r = r.double().cpu().numpy()
+    r = r.double().cpu().numpy() / float((levels - 1) ** 2)
     a = a.double().cpu().numpy()
     var = g * (1.0 - g)
     rings = np.arange(1, P // 2 + 1)
@@ -56,7 +63,7 @@ def _summary(bits, c, g, P, hb):
     fp = math.sqrt(min(g, 1.0 - g)) * P
     low = float((ac * counts)[np.arange(1, len(r)) < fp].sum() / max((ac * counts).sum(), 1e-30))
     return {
-        "fill": float(bits.double().mean()),
+        "fill": float(bits.double().mean()) / (levels - 1),
         "hvs_mse": float(loss[:, 0].mean()),
         "rapsd_db": [round(float(v), 3) for v in rdb],
         "anis_db": [round(float(v), 3) for v in adb],
@@ -78,7 +85,7 @@ def _ring_counts(P):
 
 
 def bluenoise(weights, grays=GRAYS, B=8, H=512, W=512, P=64, precision=None, with_fs=True,
-              seed=1000):
+              seed=1000, levels=2):
     """Spectral summary per gray level (dict keyed by the gray out of 255)."""
     import torch
     from . import binding as hb
@@ -91,13 +98,23 @@ def bluenoise(weights, grays=GRAYS, B=8, H=512, W=512, P=64, precision=None, wit
         g = gi / 255.0
         c = torch.full((B, H, W), g, dtype=torch.float32, device=dev)
         s = torch.arange(seed + B * gi, seed + B * gi + B, dtype=torch.int64, device=dev)
-        bits, x, st = hb.halftone_infer(w, c, s, precision=prec, logits=True, stats=True)
-        rec = {"policy": _summary(bits, c, g, P, hb)}
+        if levels > 2:
+            bits, x, st = hb.halftone_infer_pages(w, c.reshape(-1), s, [(H, W)] * B,
+                                                  precision=prec, logits=True, stats=True,
+                                                  levels=levels)
+            bits, x = bits.view(B, H, W), x.view(B, H, W)
+        else:
+            bits, x, st = hb.halftone_infer(w, c, s, precision=prec, logits=True, stats=True)
+        rec = {"policy": _summary(bits, c, g, P, hb, levels)}
         n = float(B * H * W)
         edges = torch.tensor(LOGIT_DECADES, dtype=torch.float32, device=dev)
         cnt = torch.bucketize(x.abs().flatten(), edges, right=True).bincount(
             minlength=len(LOGIT_DECADES) + 1)
         rec["policy"]["logit_hist"] = [round(float(v) / n, 6) for v in cnt.cpu()]
+        if levels > 2:
+            # the paper's multitone histogram: outputs gather at the levels
+            t = torch.sigmoid(x.double()) * (levels - 1)
+            rec["policy"]["near_level"] = float(((t - t.round()).abs() < 0.1).double().mean())
         st = st.cpu().numpy()
         rec["policy"]["recheck"] = float(st[0]) / n
         rec["policy"]["fp32"] = float(st[2]) / n
@@ -115,10 +132,12 @@ def main(argv=None):
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--P", type=int, default=64, choices=(32, 64))
     ap.add_argument("--no-fs", action="store_true")
+    ap.add_argument("--levels", type=int, default=2, help="2 = halftone, 3..8 = multitone")
     ap.add_argument("--out", help="write the JSON here as well")
     a = ap.parse_args(argv)
     w = np.load(a.weights) if a.weights else synth.he_weights(42)
-    res = bluenoise(w, B=a.batch, H=a.size, W=a.size, P=a.P, with_fs=not a.no_fs)
+    res = bluenoise(w, B=a.batch, H=a.size, W=a.size, P=a.P, with_fs=not a.no_fs,
+                    levels=a.levels)
     for gi in GRAYS:
         for m, r in res[str(gi)].items():
             am = r["anis_mean_db"]

@@ -175,3 +175,45 @@ def test_train_step_multilevel_matches_oracle(orc, L):
     want = orc.multitone_actions(v, seeds, L, step)
     assert np.array_equal(a[clear], want[clear])
     assert len(np.unique(a)) >= 3
+
+
+def test_c5_pages_four_levels_full_size_sampled(orc):
+    """The 48-page batch (about 0.5 Gpx) in one 4-level call with the He
+    weights, whose logits crowd the lowest threshold logit(1/6) (7.5% of the
+    pixels go through the recheck stages); sampled pixels of every page
+    against the oracle evaluated one receptive field at a time."""
+    shapes = synth.page_sizes(3_000_000)
+    seeds = [3_000_000 + i for i in range(len(shapes))]
+    dev = device()
+    _say("multitone C5 pages", sum(h * w for h, w in shapes))
+    flat = torch.cat([synth.contone_torch(s, h, w, dev).reshape(-1)
+                      for s, (h, w) in zip(seeds, shapes)])
+    w = synth.he_weights(42)
+    out, lg, st = hb.halftone_infer_pages(to_dev(w), flat, seeds_t(seeds), shapes,
+                                          precision=hb.HS_BF16, recheck_tau=0.055, logits=True,
+                                          stats=True, levels=4)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert st[0] > 0.05 * flat.numel() and 0 < st[2] <= st[0]
+    thr = np.log((2 * np.arange(3) + 1.0) / (5 - 2 * np.arange(3)))
+    rng = np.random.default_rng(6)
+    wd = w.astype(np.float64)
+    off = 0
+    for (h, ww), s in zip(shapes, seeds):
+        pts = [(0, 0), (h - 1, ww - 1), (h // 2, ww // 2)]
+        pts += [tuple(int(v) for v in p) for p in rng.integers(0, [h, ww], size=(5, 2))]
+        for (y, x) in pts:
+            y0, y1, x0, x1 = max(0, y - 6), min(h, y + 7), max(0, x - 6), min(ww, x + 7)
+            rows = [flat[off + yy * ww + x0: off + yy * ww + x1] for yy in range(y0, y1)]
+            cimg = torch.stack(rows).cpu().numpy()
+            zc = np.array([[orc.normal(s, yy * ww + xx, 1, 0) for xx in range(x0, x1)]
+                           for yy in range(y0, y1)])
+            ref = orc.policy_forward_window(wd, cimg.astype(np.float64), zc, y - y0,
+                                            y - y0 + 1, x - x0, x - x0 + 1)[0:1, 0:1]
+            o = off + y * ww + x
+            if _level_mask(orc, ref, 4)[0, 0]:
+                assert int(out[o]) == int(orc.multitone_levels(ref, 4)[0, 0]), ((h, ww), y, x)
+            lo = float(lg[o])
+            near = np.min(np.abs(lo - thr)) < 0.055
+            assert abs(lo - ref[0, 0]) < (5e-4 if near else 0.055), ((h, ww), y, x)
+        off += h * ww
