@@ -9,13 +9,18 @@ The JSON line also carries:
   roofline     -- the fused BF16 kernel's algorithmic FLOP per launch over its
                   average duration (HIP events around that kernel, live);
   cpu_baseline -- the CPU oracle on a bounded sample of the same workload;
+  cpu_error_diffusion -- Floyd-Steinberg on the host over the same batch,
+                  one thread and one image per thread;
   fp32         -- the FP32 path on the same batch (speedup stated);
   train        -- policy_train_step steps/s on 32 x 256 x 256 crops plus 64
                   constant-gray 64 x 64 images (BF16 activations), with the
-                  conv FLOP rate against the BF16 matrix peak;
+                  conv FLOP rate against the BF16 matrix peak, and the same
+                  with activation recomputation;
+  loss         -- halftone_loss_backward on 16 x 256 x 256 crops, its rate
+                  against the FP32 vector peak;
   pages        -- the uneven batch: 48 pages of 600..4960 x 800..7016 in one
                   halftone_infer_pages call (BF16 + recheck), Mpx/s and the
-                  fused launch's FLOP rate.
+                  fused launch's FLOP rate, and the same pages with 4 levels.
 """
 import argparse
 import hashlib
@@ -31,6 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "halftone Mpixels/s (BF16 vs FP32 CNN, oracle-matched bits); train steps/s"
 FLOP_PER_PX = 75456          # 2 x (2*32*9 + 4*32*32*9 + 32*9) multiply-adds per pixel
 PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak (published)
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (published)
 KERNEL_SRC = os.path.join(ROOT, "paper_2304_12152_amd", "csrc", "infer.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_infer_bf16_8x1024x1024_traffic.txt")
 
@@ -71,6 +77,67 @@ def cpu_baseline(c_img, seed, w):
             "kind": "oracle",
             "sample": "oracle (C, FP64, 1 thread): Philox noise + 6x32 policy forward + "
                       "threshold on the 512x512 top-left crop of workload image 0; %.1f s" % dt}
+
+
+def cpu_error_diffusion(hb, c):
+    """Floyd-Steinberg on the host (the library's serial fallback) over the
+    8 x 1024 x 1024 batch: one thread, then one image per thread on the
+    host's cores (the scan is serial within an image)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    hb.halftone_error_diffusion_host(c)
+    d1 = time.perf_counter() - t0
+    n = min(len(c), len(os.sched_getaffinity(0)))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        list(ex.map(lambda i: hb.halftone_error_diffusion_host(c[i]), range(len(c))))
+    dn = time.perf_counter() - t0
+    npx = int(np.prod(c.shape))
+    return {"value": round(npx / d1 / 1e6, 2), "unit": "Mpx/s", "cores": 1,
+            "kind": "floyd_steinberg_host",
+            "sample": "the whole 8 x 1024 x 1024 batch, FP64 error, raster order",
+            "parallel": {"value": round(npx / dn / 1e6, 2), "cores": n,
+                         "sample": "one image per thread"}}
+
+
+# Algorithmic FLOP per pixel of the loss and its gradient (HVS and SSIM window
+# statistics, the toggle update of the MSE and CSSIM terms over the 121
+# window centres, the anisotropy DFT and its adjoint): about 3.5 kFLOP
+LOSS_FLOP_PER_PX = 3500
+
+
+def bench_loss(hb, synth, torch, dev, steps):
+    """Loss and gradient on 16 x 256 x 256 crops (seeds 100..115): the
+    probabilities of the He-initialised policy, actions drawn from them, and
+    the anisotropy term on the 32 x 32 patches of the same probabilities."""
+    B, H, W = 16, 256, 256
+    seeds = list(range(100, 116))
+    wt = torch.tensor(synth.he_weights(42), device=dev)
+    c = torch.tensor(synth.contone_batch(seeds, H, W), device=dev)
+    st = torch.tensor(seeds, dtype=torch.int64, device=dev)
+    probs, _ = hb.halftone_policy_forward(wt, c, st, 0, precision=hb.HS_FP32)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    acts = (torch.rand(probs.shape, generator=gen, device=dev) < probs).to(torch.uint8)
+
+    def run():
+        return hb.halftone_loss_backward(acts, c, probs=probs, probs_gray=probs,
+                                         grad_space=hb.HS_WRT_LOGIT)
+
+    for _ in range(5):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    tf = LOSS_FLOP_PER_PX * B * H * W / dt / 1e12
+    log("loss + gradient: %.3f ms" % (dt * 1e3))
+    return {"ms_per_call": round(dt * 1e3, 4), "tflops": round(tf, 2),
+            "valu_frac": round(tf / PEAK_FP32_TFLOPS, 4),
+            "config": "16 x 256x256 crops, LE gradient + anisotropy gradient, FP32"}
 
 
 def bench_pages(hb, synth, torch, dev, wt, steps, tau):
@@ -314,6 +381,8 @@ def main():
                                        "workspace_gb_without": round(state.ws.numel() / 1e9, 3)}
         del state_r
         log("train with recomputation: %.2f steps/s" % sps_r)
+    if not args.no_train:
+        extra["loss"] = bench_loss(hb, synth, torch, dev, 20)
     if not args.no_pages:
         extra["pages"] = bench_pages(hb, synth, torch, dev, wt, args.page_steps, args.tau)
     out = {
@@ -330,6 +399,8 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(c[0], seeds[0], w)
+        log("cpu error diffusion")
+        out["cpu_error_diffusion"] = cpu_error_diffusion(hb, c)
     out.update(extra)
     print(json.dumps(out), flush=True)
 
