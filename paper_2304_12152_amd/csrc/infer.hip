@@ -140,11 +140,14 @@ HS_DEV uint32_t relu_bf16x2(float lo, float hi) {
 // ReLU + BF16 of one finished 16-pixel run in the ring channel order; zero
 // where the pixel lies outside the image (the next layer's zero padding)
 HS_DEV bf16x8_t relu_bf16(const f32x4_t (&acc)[2], bool in) {
+  // branch-free: the pairs are packed for every lane and masked (a select
+  // per pair instead of a divergent branch around each)
+  const uint32_t keep = 0u - (uint32_t)in;
   uint32_t u[4];
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
-    u[2 * m] = in ? relu_bf16x2(acc[m][0], acc[m][1]) : 0u;
-    u[2 * m + 1] = in ? relu_bf16x2(acc[m][2], acc[m][3]) : 0u;
+    u[2 * m] = relu_bf16x2(acc[m][0], acc[m][1]) & keep;
+    u[2 * m + 1] = relu_bf16x2(acc[m][2], acc[m][3]) & keep;
   }
   bf16x8_t v;
   __builtin_memcpy(&v, u, 16);
