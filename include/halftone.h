@@ -344,6 +344,14 @@ int halftone_spectrum(const uint8_t* bits, int B, int H, int W, int P, float* ra
  * --------------------------------------------------------------------- */
 int halftone_error_diffusion_host(const float* contone_host, int B, int H, int W,
                                   uint8_t* bits_host);
+/* The same with L output levels k / (L-1), the serial fallback beside the
+ * multitoning variant (Sec. VII): each pixel takes the level nearest to
+ * v = c + diffused error (a tie going up, clamped to 0..L-1) and diffuses
+ * v - k / (L-1) with the same weights; levels = 2 gives the bits of
+ * halftone_error_diffusion_host. levels_host [B][H][W] level indices out;
+ * HS_EINVAL for levels outside 2..HS_MAX_LEVELS. */
+int halftone_error_diffusion_levels_host(const float* contone_host, int B, int H, int W,
+                                         int levels, uint8_t* levels_host);
 
 #ifdef __cplusplus
 }

@@ -1013,3 +1013,31 @@ void or_floyd_steinberg(const double* c, int B, int H, int W, uint8_t* h) {
   }
   free(v);
 }
+
+/* Floyd-Steinberg with L output levels k / (L-1), the error diffusion that
+ * stands beside the multitoning variant (Sec. VII) as its serial fallback:
+ * v = c + diffused error, k = the level nearest to v (a tie going up, clamped
+ * to 0..L-1), error v - k / (L-1) pushed with the same weights and borders
+ * as or_floyd_steinberg, which is the case L = 2. */
+void or_floyd_steinberg_levels(const double* c, int B, int H, int W, int L, uint8_t* k) {
+  double* v = (double*)malloc(sizeof(double) * (size_t)H * W);
+  for (int b = 0; b < B; ++b) {
+    memcpy(v, c + (size_t)b * H * W, sizeof(double) * (size_t)H * W);
+    for (int y = 0; y < H; ++y)
+      for (int x = 0; x < W; ++x) {
+        double val = v[(size_t)y * W + x];
+        int lev = (int)floor(val * (L - 1) + 0.5);
+        if (lev < 0) lev = 0;
+        if (lev > L - 1) lev = L - 1;
+        double q = val - (double)lev / (L - 1);
+        k[(size_t)b * H * W + (size_t)y * W + x] = (uint8_t)lev;
+        if (x + 1 < W) v[(size_t)y * W + x + 1] += q * 7.0 / 16.0;
+        if (y + 1 < H) {
+          if (x > 0) v[(size_t)(y + 1) * W + x - 1] += q * 3.0 / 16.0;
+          v[(size_t)(y + 1) * W + x] += q * 5.0 / 16.0;
+          if (x + 1 < W) v[(size_t)(y + 1) * W + x + 1] += q * 1.0 / 16.0;
+        }
+      }
+  }
+  free(v);
+}

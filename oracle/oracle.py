@@ -90,6 +90,7 @@ def lib():
                                      c_int, c_int, c_int, c_long, c_long, D, D, c_int, U8, U8, D,
                                      D]),
             "or_floyd_steinberg": (None, [D, c_int, c_int, c_int, U8]),
+            "or_floyd_steinberg_levels": (None, [D, c_int, c_int, c_int, c_int, U8]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -403,6 +404,15 @@ def floyd_steinberg(c):
     h, hp = _u8(np.zeros((B, H, W)))
     lib().or_floyd_steinberg(cp, B, H, W, hp)
     return h
+
+
+def floyd_steinberg_levels(c, L):
+    """Level indices of L-level Floyd-Steinberg error diffusion."""
+    B, H, W = _bhw(c)
+    c, cp = _d(np.reshape(c, (B, H, W)))
+    k, kp = _u8(np.zeros((B, H, W)))
+    lib().or_floyd_steinberg_levels(cp, B, H, W, L, kp)
+    return k
 
 
 def sigmoid(x):

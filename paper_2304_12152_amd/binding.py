@@ -72,6 +72,7 @@ _SIGS = {
                               ctypes.c_int64, ctypes.POINTER(HsTrainParams), I, P, P, P, P, SZ,
                               P]),
     "halftone_error_diffusion_host": (I, [P, I, I, I, P]),
+    "halftone_error_diffusion_levels_host": (I, [P, I, I, I, I, P]),
     "halftone_spectrum_rings": (I, [I]),
     "halftone_spectrum_workspace_size": (SZ, [I, I, I, I]),
     "halftone_spectrum": (I, [P, I, I, I, I, P, P, P, SZ, P]),
@@ -330,3 +331,14 @@ def halftone_error_diffusion_host(contone_host):
     bits = torch.empty((B, H, W), dtype=torch.uint8)
     _check(lib().halftone_error_diffusion_host(_ptr(c), B, H, W, _ptr(bits)))
     return bits
+
+
+def halftone_error_diffusion_levels_host(contone_host, levels):
+    """L-level Floyd-Steinberg on the host: float32 [B,H,W] -> uint8 level indices."""
+    c = torch.as_tensor(contone_host, dtype=torch.float32).contiguous()
+    if c.dim() == 2:
+        c = c[None]
+    B, H, W = c.shape
+    out = torch.empty((B, H, W), dtype=torch.uint8)
+    _check(lib().halftone_error_diffusion_levels_host(_ptr(c), B, H, W, int(levels), _ptr(out)))
+    return out

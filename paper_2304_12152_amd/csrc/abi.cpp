@@ -922,4 +922,36 @@ int halftone_error_diffusion_host(const float* contone_host, int B, int H, int W
   return HS_OK;
 }
 
+int halftone_error_diffusion_levels_host(const float* contone_host, int B, int H, int W,
+                                         int levels, uint8_t* levels_host) {
+  if (!contone_host || !levels_host) return fail(HS_EINVAL, "error diffusion: null pointer");
+  if (!shape_ok(B, H, W)) return fail(HS_ESHAPE, "error diffusion: bad shape");
+  if (levels < 2 || levels > HS_MAX_LEVELS)
+    return fail(HS_EINVAL, "error diffusion: levels %d (2..%d)", levels, HS_MAX_LEVELS);
+  const double step = 1.0 / (levels - 1);
+  std::vector<double> cur(W + 2), nxt(W + 2);
+  for (int b = 0; b < B; ++b) {
+    std::fill(cur.begin(), cur.end(), 0.0);
+    std::fill(nxt.begin(), nxt.end(), 0.0);
+    const float* c = contone_host + (size_t)b * H * W;
+    uint8_t* k = levels_host + (size_t)b * H * W;
+    for (int y = 0; y < H; ++y) {
+      for (int x = 0; x < W; ++x) {
+        const double v = (double)c[(size_t)y * W + x] + cur[x + 1];
+        int lev = (int)floor(v * (levels - 1) + 0.5);
+        lev = lev < 0 ? 0 : (lev > levels - 1 ? levels - 1 : lev);
+        const double q = v - lev * step;
+        k[(size_t)y * W + x] = (uint8_t)lev;
+        if (x + 1 < W) cur[x + 2] += q * (7.0 / 16.0);
+        if (x > 0) nxt[x] += q * (3.0 / 16.0);
+        nxt[x + 1] += q * (5.0 / 16.0);
+        if (x + 1 < W) nxt[x + 2] += q * (1.0 / 16.0);
+      }
+      std::swap(cur, nxt);
+      std::fill(nxt.begin(), nxt.end(), 0.0);
+    }
+  }
+  return HS_OK;
+}
+
 }  // extern "C"

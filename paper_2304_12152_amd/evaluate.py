@@ -28,7 +28,7 @@ With K periodograms averaged, an isotropic spectrum has anisotropy about
 With --levels L > 2 the policy is the multitoning variant (Sec. VII): its
 output is the level index k, the image k / (L - 1) is scored, and its
 power is taken in units of that image (the level indices' spectrum divided
-by (L - 1)^2); Floyd-Steinberg stays the binary reference.
+by (L - 1)^2); the reference is Floyd-Steinberg with the same L levels.
 
 Command line:
     python -m paper_2304_12152_amd.evaluate --weights weights.npy
@@ -119,8 +119,10 @@ def bluenoise(weights, grays=GRAYS, B=8, H=512, W=512, P=64, precision=None, wit
         rec["policy"]["recheck"] = float(st[0]) / n
         rec["policy"]["fp32"] = float(st[2]) / n
         if with_fs:
-            fs = hb.halftone_error_diffusion_host(np.full((B, H, W), g, dtype=np.float32))
-            rec["fs"] = _summary(fs.to(dev), c, g, P, hb)
+            flat = np.full((B, H, W), g, dtype=np.float32)
+            fs = (hb.halftone_error_diffusion_levels_host(flat, levels) if levels > 2
+                  else hb.halftone_error_diffusion_host(flat))
+            rec["fs"] = _summary(fs.to(dev), c, g, P, hb, levels)
         out[str(gi)] = rec
     return out
 

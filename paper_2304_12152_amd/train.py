@@ -122,7 +122,7 @@ def judge(weights, contones, seeds, precision=None, with_fs=True, levels=2):
 
     contones: float32 [N, H, W] (host); seeds: uint64 [N] noise keys. With
     levels > 2 the policy's output is its multitone (nearest-level) image
-    and Floyd-Steinberg stays the binary reference."""
+    and the reference is Floyd-Steinberg with the same levels."""
     import torch
     from . import binding as hb
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -148,8 +148,13 @@ def judge(weights, contones, seeds, precision=None, with_fs=True, levels=2):
     out["policy_cssim"] = float(loss[:, 1].mean())
     out["policy_fill"] = float(fill)
     if with_fs:
-        fs = hb.halftone_error_diffusion_host(np.asarray(contones)).to(dev)
-        lf = hb.halftone_loss(fs, c)[:3 * N].view(N, 3).double()
+        if levels > 2:
+            fs = hb.halftone_error_diffusion_levels_host(np.asarray(contones), levels).to(dev)
+            lf = hb.halftone_loss(fs, c, prm=hb.default_loss_params(levels=levels))
+        else:
+            fs = hb.halftone_error_diffusion_host(np.asarray(contones)).to(dev)
+            lf = hb.halftone_loss(fs, c)
+        lf = lf[:3 * N].view(N, 3).double()
         out["fs_hvs_mse"] = float(lf[:, 0].mean())
         out["fs_cssim"] = float(lf[:, 1].mean())
     out["contone_mean"] = float(c.double().mean())

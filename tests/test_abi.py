@@ -258,3 +258,15 @@ def test_recompute_workspace_and_errors(lib):
     assert lib.policy_train_step(p, p, p, p, p, 1, 32, 32, None, None, 0, 0, 0, 0, 10,
                                  ctypes.byref(bad), hb.HS_BF16, p, None, None, p, n,
                                  None) == hb.HS_EINVAL
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 8])
+def test_host_error_diffusion_levels_matches_oracle(orc, lib, L):
+    from paper_2304_12152_amd import synth
+    c = synth.contone_batch([6, 7], 41, 50)
+    got = hb.halftone_error_diffusion_levels_host(c, L).numpy()
+    assert np.array_equal(got, orc.floyd_steinberg_levels(c.astype(np.float64), L))
+    if L == 2:
+        assert np.array_equal(got, hb.halftone_error_diffusion_host(c).numpy())
+    with pytest.raises(hb.HalftoneError):
+        hb.halftone_error_diffusion_levels_host(c, 9)

@@ -135,3 +135,34 @@ def test_train_step_matches_autograd_and_adam(orc, noise_kind):
     met = out["metrics"]
     assert abs(met["lr"] - lr) < 1e-18
     assert abs(met["fill"] - h.mean()) < 1e-15
+
+
+def test_fs_levels_two_is_binary_fs(orc):
+    c = synth.contone_batch([33, 34], 40, 56).astype(np.float64)
+    assert np.array_equal(orc.floyd_steinberg_levels(c, 2), orc.floyd_steinberg(c))
+
+
+def test_fs_levels_exact_levels_carry_no_error(orc):
+    # a contone that sits on a level everywhere is reproduced exactly
+    for L, k in ((3, 1), (4, 2), (8, 5)):
+        c = np.full((1, 9, 13), k / (L - 1.0))
+        assert np.all(orc.floyd_steinberg_levels(c, L) == k)
+
+
+def test_fs_levels_hand_worked(orc):
+    # L = 3 (levels 0, 1/2, 1) on [[.3, .9], [.6, .2]] worked by hand:
+    # (0,0) .3 -> 1/2, error -.2; (0,1) .9 - .0875 = .8125 -> 1, error
+    # -.1875; (1,0) .6 - .0625 - .03516 = .50234 -> 1/2, error .00234;
+    # (1,1) .2 - .0125 - .05859 + .00103 = .12993 -> 0
+    k = orc.floyd_steinberg_levels(np.array([[[0.3, 0.9], [0.6, 0.2]]]), 3)[0]
+    assert k.tolist() == [[1, 2], [1, 0]]
+
+
+@pytest.mark.parametrize("L", [3, 4])
+def test_fs_levels_tone_preservation(orc, L):
+    c = synth.contone_batch([35, 36], 64, 64).astype(np.float64)
+    k = orc.floyd_steinberg_levels(c, L)
+    for b in range(2):
+        # the error left at the right column and bottom row is below one
+        # level step per pixel there
+        assert abs(k[b].mean() / (L - 1) - c[b].mean()) <= (64 + 64) / (64 * 64) / (L - 1)
