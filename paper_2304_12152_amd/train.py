@@ -186,6 +186,8 @@ def main(argv=None):
     ap.add_argument("--judge-every", type=int, default=0,
                     help="steps between held-out evaluations of the policy during training")
     ap.add_argument("--out", default=None, help="write the trained weights (.npy)")
+    ap.add_argument("--init", default=None,
+                    help="start from these weights (.npy); with --steps 0 this only judges them")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -214,8 +216,9 @@ def main(argv=None):
     kw["estimator"] = hb.HS_EST_COMA if args.estimator == "coma" else hb.HS_EST_LE
     kw["levels"] = args.levels
     tp = hb.default_train_params(**kw)
+    init = np.load(args.init).astype(np.float32) if args.init else None
     tr = Trainer(pool, args.steps, batch=args.batch, run_seed=args.run_seed,
-                 weight_seed=args.weight_seed, precision=prec, tp=tp)
+                 weight_seed=args.weight_seed, precision=prec, tp=tp, weights=init)
     w0 = tr.weights.clone()
     before = judge(w0, held, hseeds, levels=args.levels)
     log("untrained: " + json.dumps(before))
@@ -247,7 +250,7 @@ def main(argv=None):
             log("judge at step %d: policy HVS-MSE %.6g (FS %.6g) fill %.4f"
                 % (i + 1, j["policy_hvs_mse"], before["fs_hvs_mse"], j["policy_fill"]))
     torch.cuda.synchronize()
-    train_s = time.perf_counter() - t1
+    train_s = max(time.perf_counter() - t1, 1e-9)
     after = judge(tr.weights, held, hseeds, levels=args.levels)
     log("trained: " + json.dumps(after))
     gafter = judge(tr.weights, gheld, gseeds, levels=args.levels)
