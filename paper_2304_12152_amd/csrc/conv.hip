@@ -171,11 +171,18 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict
                                                          T* __restrict__ out,
                                                          float* __restrict__ zout,
                                                          float* __restrict__ cout) {
-  __shared__ float sc[18 * 18], sz[18 * 18], sw[32 * 2 * 9 + 32];
+  // weights as [tap][co][channel c, z], so one 16-byte LDS read brings the
+  // four weights of two output channels (the same for every lane)
+  __shared__ __attribute__((aligned(16))) float swt[9 * 32 * 2];
+  __shared__ float sc[18 * 18], sz[18 * 18], sb[32];
   const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16;
   const size_t img = (size_t)b * H * W;
   const uint64_t seed = seeds[b];
-  for (int i = threadIdx.x; i < 32 * 2 * 9 + 32; i += 256) sw[i] = w[HS_W1 + i];
+  for (int i = threadIdx.x; i < 32 * 2 * 9; i += 256) {
+    const int co = i / 18, ch = (i / 9) % 2, t = i % 9;  // source W1[co][ch][t]
+    swt[(t * 32 + co) * 2 + ch] = w[HS_W1 + i];
+  }
+  if (threadIdx.x < 32) sb[threadIdx.x] = w[HS_B1 + threadIdx.x];
   for (int i = threadIdx.x; i < 18 * 18; i += 256) {
     const int ly = i / 18, lx = i - ly * 18, gy = y0 + ly - 1, gx = x0 + lx - 1;
     float cv = 0.0f, zv = 0.0f;
@@ -194,14 +201,17 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict
   if (cout) cout[img + (size_t)gy * W + gx] = sc[(ty + 1) * 18 + tx + 1];
   float acc[32];
 #pragma unroll
-  for (int co = 0; co < 32; ++co) acc[co] = sw[HS_B1 + co];
+  for (int co = 0; co < 32; ++co) acc[co] = sb[co];
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
     const int dy = t / 3, dx = t - (t / 3) * 3;
     const float c = sc[(ty + dy) * 18 + tx + dx], z = sz[(ty + dy) * 18 + tx + dx];
 #pragma unroll
-    for (int co = 0; co < 32; ++co)
-      acc[co] = fmaf(sw[(co * 2 + 1) * 9 + t], z, fmaf(sw[(co * 2 + 0) * 9 + t], c, acc[co]));
+    for (int co = 0; co < 32; co += 2) {
+      const f32x4_t q = *(const f32x4_t*)(swt + (t * 32 + co) * 2);
+      acc[co] = fmaf(q[1], z, fmaf(q[0], c, acc[co]));
+      acc[co + 1] = fmaf(q[3], z, fmaf(q[2], c, acc[co + 1]));
+    }
   }
   T* o = out + (img + (size_t)gy * W + gx) * 32;
 #pragma unroll
