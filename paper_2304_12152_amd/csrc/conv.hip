@@ -312,10 +312,12 @@ __global__ __launch_bounds__(256) void dgrad_last_kernel(const float* __restrict
                                                          const float* __restrict__ w, int H,
                                                          int W, float* __restrict__ g6out,
                                                          T* __restrict__ g5) {
-  __shared__ float sg[18 * 18], sw[32 * 9];
+  // weights as [tap][ci]: one 16-byte LDS read brings four channels' weights
+  __shared__ __attribute__((aligned(16))) float sw[9 * 32];
+  __shared__ float sg[18 * 18];
   const int b = blockIdx.z, y0 = blockIdx.y * 16, x0 = blockIdx.x * 16;
   const size_t img = (size_t)b * H * W;
-  for (int i = threadIdx.x; i < 32 * 9; i += 256) sw[i] = w[HS_W6 + i];
+  for (int i = threadIdx.x; i < 32 * 9; i += 256) sw[(i % 9) * 32 + i / 9] = w[HS_W6 + i];
   for (int i = threadIdx.x; i < 18 * 18; i += 256) {
     const int ly = i / 18, lx = i - ly * 18, gy = y0 + ly - 1, gx = x0 + lx - 1;
     float v = 0.0f;
@@ -339,7 +341,11 @@ __global__ __launch_bounds__(256) void dgrad_last_kernel(const float* __restrict
     const int dy = t / 3, dx = t - (t / 3) * 3;
     const float gv = sg[(ty + 2 - dy) * 18 + tx + 2 - dx];
 #pragma unroll
-    for (int ci = 0; ci < 32; ++ci) acc[ci] = fmaf(sw[ci * 9 + t], gv, acc[ci]);
+    for (int ci = 0; ci < 32; ci += 4) {
+      const f32x4_t q = *(const f32x4_t*)(sw + t * 32 + ci);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[ci + k] = fmaf(q[k], gv, acc[ci + k]);
+    }
   }
   const T* m = a5 + o * 32;
   T* dst = g5 + o * 32;
@@ -623,29 +629,55 @@ __global__ __launch_bounds__(256) void wgrad_first_kernel(const float* __restric
   float ac[9], az[9], accb = 0.0f;
 #pragma unroll
   for (int t = 0; t < 9; ++t) ac[t] = az[t] = 0.0f;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  // staging of a tile: 256 pixels x 8 groups of 4 channels of g1 (8 per
+  // thread) and the 18 x 18 c and z values (up to 2 per thread); the next
+  // tile's loads are issued before this tile's arithmetic
+  float vg[8][4], vc[2], vz[2];
+  auto load = [&](int tile) {
     const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
     const int y0 = (rem / tiles_x) * 16, x0 = (rem % tiles_x) * 16;
     const size_t img = (size_t)b * H * W;
-    __syncthreads();
-    for (int i = threadIdx.x; i < 256 * 8; i += 256) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = (int)threadIdx.x + 256 * k;
       const int p = i >> 3, q = (i & 7) * 4, gy = y0 + (p >> 4), gx = x0 + (p & 15);
-      float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) vg[k][e] = 0.0f;
       if (gy < H && gx < W) {
         const T* src = g1 + (img + (size_t)gy * W + gx) * 32 + q;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = hs_to_f(src[k]);
+        for (int e = 0; e < 4; ++e) vg[k][e] = hs_to_f(src[e]);
       }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) sg[p * 33 + q + k] = v[k];
     }
-    for (int i = threadIdx.x; i < 18 * 18; i += 256) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int i = (int)threadIdx.x + 256 * k;
       const int ly = i / 18, lx = i - ly * 18, gy = y0 + ly - 1, gx = x0 + lx - 1;
-      const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-      sc[i] = in ? contone[img + (size_t)gy * W + gx] : 0.0f;
-      sz[i] = in ? z[img + (size_t)gy * W + gx] : 0.0f;
+      const bool in = i < 18 * 18 && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      vc[k] = in ? contone[img + (size_t)gy * W + gx] : 0.0f;
+      vz[k] = in ? z[img + (size_t)gy * W + gx] : 0.0f;
+    }
+  };
+  if ((int)blockIdx.x < ntiles) load(blockIdx.x);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = (int)threadIdx.x + 256 * k;
+      const int p = i >> 3, q = (i & 7) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sg[p * 33 + q + e] = vg[k][e];
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int i = (int)threadIdx.x + 256 * k;
+      if (i < 18 * 18) {
+        sc[i] = vc[k];
+        sz[i] = vz[k];
+      }
     }
     __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
 #pragma unroll
     for (int rr = 0; rr < 2; ++rr) {
       const int py = 2 * pg + rr;
@@ -717,28 +749,46 @@ __global__ __launch_bounds__(256) void wgrad_last_kernel(const T* __restrict__ a
   float acc[9], accb = 0.0f;
 #pragma unroll
   for (int t = 0; t < 9; ++t) acc[t] = 0.0f;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  // staging of a tile: 18 x 18 positions x 8 groups of 4 channels, NIT per
+  // thread, plus one g6 value; the next tile's loads are issued before this
+  // tile's arithmetic
+  constexpr int NA = 18 * 18 * 8, NIT = (NA + 255) / 256;
+  float v[NIT][4], gv6 = 0.0f;
+  auto load = [&](int tile) {
     const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
     const int y0 = (rem / tiles_x) * 16, x0 = (rem % tiles_x) * 16;
     const size_t img = (size_t)b * H * W;
-    __syncthreads();
-    for (int i = threadIdx.x; i < 18 * 18 * 8; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int i = (int)threadIdx.x + 256 * k;
       const int p = i >> 3, q = (i & 7) * 4;
       const int ly = p / 18, lx = p - ly * 18, gy = y0 + ly - 1, gx = x0 + lx - 1;
-      float v[4] = {0.f, 0.f, 0.f, 0.f};
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[k][e] = 0.0f;
+      if (i < NA && gy >= 0 && gy < H && gx >= 0 && gx < W) {
         const T* src = a5 + (img + (size_t)gy * W + gx) * 32 + q;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = hs_to_f(src[k]);
+        for (int e = 0; e < 4; ++e) v[k][e] = hs_to_f(src[e]);
       }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) sa[p * LP + q + k] = v[k];
     }
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) {
-      const int gy = y0 + (i >> 4), gx = x0 + (i & 15);
-      sg[i] = (gy < H && gx < W) ? g6[img + (size_t)gy * W + gx] : 0.0f;
-    }
+    const int gy = y0 + ((int)threadIdx.x >> 4), gx = x0 + ((int)threadIdx.x & 15);
+    gv6 = (gy < H && gx < W) ? g6[img + (size_t)gy * W + gx] : 0.0f;
+  };
+  if ((int)blockIdx.x < ntiles) load(blockIdx.x);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int i = (int)threadIdx.x + 256 * k;
+      const int p = i >> 3, q = (i & 7) * 4;
+      if (i < NA) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sa[p * LP + q + e] = v[k][e];
+      }
+    }
+    sg[threadIdx.x] = gv6;
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
 #pragma unroll
     for (int rr = 0; rr < 2; ++rr) {
       const int py = 2 * pg + rr;

@@ -49,14 +49,16 @@ __global__ __launch_bounds__(256) void count_ones_kernel(const uint8_t* __restri
 
 // metrics = {mean MSE, mean CSSIM, mean R, L_AS, lr, |grad|_2, fill, 0}; fill
 // is the mean of h = action / (levels - 1)
-__global__ __launch_bounds__(256) void metrics_kernel(const float* __restrict__ loss_out, int B,
+// one workgroup of 1024 threads: the gradient norm is a single pass of 37
+// loads per thread, summed per wave and then over the 16 waves in order
+__global__ __launch_bounds__(1024) void metrics_kernel(const float* __restrict__ loss_out, int B,
                                                       const float* __restrict__ grad, int n,
                                                       const unsigned long long* __restrict__ ones,
                                                       size_t nact, int levels, float lr,
                                                       float* __restrict__ metrics) {
-  __shared__ float red[4];
+  __shared__ float red[16];
   float s = 0.0f;
-  for (int i = threadIdx.x; i < n; i += 256) s = fmaf(grad[i], grad[i], s);
+  for (int i = threadIdx.x; i < n; i += 1024) s = fmaf(grad[i], grad[i], s);
   s = hs_wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -72,7 +74,9 @@ __global__ __launch_bounds__(256) void metrics_kernel(const float* __restrict__ 
   metrics[2] = r / B;
   metrics[3] = loss_out[3 * B];
   metrics[4] = lr;
-  metrics[5] = sqrtf(((red[0] + red[1]) + red[2]) + red[3]);
+  float g2 = 0.0f;
+  for (int k = 0; k < 16; ++k) g2 += red[k];
+  metrics[5] = sqrtf(g2);
   metrics[6] = (float)((double)*ones / ((double)nact * (levels - 1)));
   metrics[7] = 0.0f;
 }
@@ -98,7 +102,7 @@ hipError_t launch_train_metrics(const float* loss_out, int B, const float* grad,
   if (blocks < 1) blocks = 1;
   if (blocks > 1024) blocks = 1024;
   count_ones_kernel<<<(unsigned)blocks, 256, 0, s>>>(actions, nact, counter);
-  metrics_kernel<<<1, 256, 0, s>>>(loss_out, B, grad, n, counter, nact, levels, lr, metrics);
+  metrics_kernel<<<1, 1024, 0, s>>>(loss_out, B, grad, n, counter, nact, levels, lr, metrics);
   return hipGetLastError();
 }
 
