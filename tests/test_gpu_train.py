@@ -215,8 +215,8 @@ def test_short_training_improves_reward():
     assert last > first, (first, last)
 
 
-@pytest.mark.parametrize("prec", [hb.HS_BF16, hb.HS_FP32])
-def test_recompute_gives_the_same_step(prec):
+@pytest.mark.parametrize("prec,levels", [(hb.HS_BF16, 2), (hb.HS_FP32, 2), (hb.HS_BF16, 4)])
+def test_recompute_gives_the_same_step(prec, levels):
     """Activation recomputation rebuilds every layer input with the same
     kernels on the same input: actions, gradient, metrics and the updated
     weights equal those of the step that keeps all activations, bit for bit."""
@@ -227,7 +227,7 @@ def test_recompute_gives_the_same_step(prec):
     cg = synth.gray_batch(2, 32, 64)
     out = []
     for rec in (0, 1):
-        tp = hb.default_train_params(recompute=rec)
+        tp = hb.default_train_params(recompute=rec, levels=levels)
         st = hb.TrainState(to_dev(w), B, H, W, 2, 32, 64, precision=prec, tp=tp)
         acts = torch.empty((B, H, W), dtype=torch.uint8, device=device())
         grad = torch.empty(hb.HS_PARAM_COUNT, dtype=torch.float32, device=device())
