@@ -211,6 +211,12 @@ def calibrate(hb, synth, torch, dev):
            "pixels": int(err.numel())}
     for tau in (0.02, 0.03, 0.04, 0.05, 0.06, 0.08):
         res["frac_below_%.2f" % tau] = float((l16.abs() < tau).float().mean())
+    _, lh = hb.halftone_infer(wt, c, st, 0, hb.HS_FP16, 0.0, logits=True)
+    eh = (lh - l32).abs()
+    res["fp16_max_err"] = float(eh.max())
+    res["fp16_rms_err"] = float(eh.pow(2).mean().sqrt())
+    for tau in (0.004, 0.005, 0.006, 0.0075, 0.01):
+        res["fp16_frac_below_%.4f" % tau] = float((lh.abs() < tau).float().mean())
     # split-BF16 stage on every pixel of a 2 x 256 x 256 batch
     c2 = c[:2, :256, :256].contiguous()
     _, a32 = hb.halftone_infer(wt, c2, st[:2], 0, hb.HS_FP32, logits=True)
@@ -320,6 +326,36 @@ def main():
     stats = stats.cpu().tolist()
     extra = {"recheck": {"tau": args.tau, "rechecked": stats[0], "flipped": stats[1],
                          "fp32_recomputed": stats[2], "fraction": round(stats[0] / npx, 6)}}
+    # the same path with an FP16 fused pass (three more mantissa bits at the
+    # same matrix-core rate, so an 8 times narrower recheck band)
+    tau16 = hb.RECHECK_TAU[hb.HS_FP16]
+
+    def step16():
+        return hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_FP16, tau16, workspace=ws)
+
+    for _ in range(10):
+        step16()
+    torch.cuda.synchronize()
+    hb.halftone_profile_start()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step16()
+    torch.cuda.synchronize()
+    dt16 = time.perf_counter() - t0
+    kern16_ms, launches16 = hb.halftone_profile_stop()
+    k16 = kern16_ms / 1e3 / max(launches16, 1)
+    bits_h, st16 = hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_FP16, tau16,
+                                     stats=True, workspace=ws)
+    st16 = st16.cpu().tolist()
+    v16 = npx * args.steps / dt16 / 1e6
+    extra["fp16"] = {"value": round(v16, 1), "unit": "Mpx/s",
+                     "ms_per_step": round(dt16 * 1e3 / args.steps, 4),
+                     "fused_kernel_ms": round(k16 * 1e3, 4),
+                     "fused_mfma_frac": round(FLOP_PER_PX * npx / k16 / 1e12 / PEAK_BF16_TFLOPS, 4),
+                     "tau": tau16, "rechecked": st16[0], "flipped": st16[1],
+                     "fp32_recomputed": st16[2], "overflow_rerun": st16[3],
+                     "fraction": round(st16[0] / npx, 6)}
+    log("fp16: %.3f ms/step, %.1f Mpx/s" % (dt16 * 1e3 / args.steps, v16))
     if not args.no_fp32:
         ws32 = torch.empty(hb.lib().halftone_infer_workspace_size(B, H, W, hb.HS_FP32),
                            dtype=torch.uint8, device=dev)
@@ -334,6 +370,7 @@ def main():
         v32 = npx * n32 / (time.perf_counter() - t1) / 1e6
         off = l32.abs() > 4.1e-4
         mism = int(((bits16 != b32) & off).sum().item())
+        extra["fp16"]["bits_differing_off_margin"] = int(((bits_h != b32) & off).sum().item())
         extra["fp32"] = {"value": round(v32, 1), "unit": "Mpx/s",
                          "speedup_bf16_vs_fp32": round(value / v32, 2),
                          "bits_differing_off_margin": mism}

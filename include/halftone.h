@@ -46,6 +46,7 @@ extern "C" {
 
 #define HS_FP32 0 /* FP32 arithmetic throughout                           */
 #define HS_BF16 1 /* BF16 MFMA with FP32 accumulation                      */
+#define HS_FP16 2 /* FP16 MFMA with FP32 accumulation (inference only)     */
 
 #define HS_NOISE_GAUSS 0   /* z ~ N(0,1) (Sec. III, "State")               */
 #define HS_NOISE_UNIFORM 1 /* z ~ U(0,1), the variant of Sec. VI-D         */
@@ -135,10 +136,17 @@ int64_t halftone_param_count(void);
  *          to [5e-4, 1e-2] is recomputed once more in FP32 and decided from that
  *          value (recheck_tau >= 0; it must exceed the largest BF16 logit
  *          error for the bits to equal FP32's off-margin).
+ *          HS_FP16: the same with FP16 in place of BF16 in the fused pass
+ *          (unit roundoff 2^-11 instead of 2^-8, so recheck_tau can be
+ *          about 8 times smaller); FP16 holds at most 65504, and if any
+ *          activation of the pass overflows, the pass is run again in BF16
+ *          with 8 * recheck_tau, decided on the device (no host
+ *          synchronisation), and stats[3] reads 1.
  * bits     [B][H][W] uint8 out.
  * logits_or_null [B][H][W] FP32 out: the logit each bit was decided from.
  * stats_or_null  int32[4] out: {pixels rechecked (|x_bf16| < recheck_tau),
- *          bits changed by the rechecks, pixels recomputed in FP32, 0};
+ *          bits changed by the rechecks, pixels recomputed in FP32,
+ *          1 if an HS_FP16 pass overflowed and was run again in BF16};
  *          zeros for HS_FP32.
  * Shapes: B >= 1, H >= 1, W >= 1, B*H*W < 2^31.
  * --------------------------------------------------------------------- */
@@ -150,7 +158,7 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
 
 /* ---------------------------------------------------------------------
  * Inference over pages of different sizes (the TEST procedure of
- * Algorithm 1 on an uneven batch), with HS_BF16 in ONE persistent launch
+ * Algorithm 1 on an uneven batch), with HS_BF16 or HS_FP16 in ONE persistent launch
  * of the fused kernel whose workgroups split all pages' strips evenly,
  * followed by the same two recheck stages as halftone_infer; with HS_FP32
  * page by page.
@@ -180,7 +188,7 @@ int halftone_infer_pages(const float* weights, const float* contone, const uint6
  * halftone_infer_pages, with
  * levels   2..HS_MAX_LEVELS (HS_EINVAL otherwise);
  * levels_out the level index k in 0..L-1 per pixel (image value k/(L-1)).
- * With HS_BF16 the recheck band is |x - nearest threshold| < recheck_tau
+ * With HS_BF16 or HS_FP16 the recheck band is |x - nearest threshold| < recheck_tau
  * (the split stage: < tau2), so every level equals the FP32 one wherever v
  * is farther than the BF16 error from the midpoints; stats as for
  * halftone_infer ("bits changed" counts changed levels). Workspace from

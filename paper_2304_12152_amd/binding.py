@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhalftone.so")
 
 HS_OK, HS_EINVAL, HS_ESHAPE, HS_EUNSUPPORTED, HS_EWORKSPACE, HS_EHIP = 0, -1, -2, -3, -4, -5
-HS_FP32, HS_BF16 = 0, 1
+HS_FP32, HS_BF16, HS_FP16 = 0, 1, 2
 HS_NOISE_GAUSS, HS_NOISE_UNIFORM = 0, 1
 HS_WRT_PROB, HS_WRT_LOGIT = 0, 1
 HS_EST_LE, HS_EST_COMA = 0, 1
@@ -138,10 +138,21 @@ def default_train_params(**kw):
     return p
 
 
+# recheck band per precision: about 1.3 times the largest logit error of the
+# fused pass measured on the C2 batch (BF16 0.042, FP16 0.0056)
+RECHECK_TAU = {HS_FP32: 0.0, HS_BF16: 0.055, HS_FP16: 0.0075}
+
+
+def _tau(precision, recheck_tau):
+    return RECHECK_TAU.get(precision, 0.0) if recheck_tau is None else recheck_tau
+
+
 def halftone_infer(weights, contone, seeds, noise_kind=HS_NOISE_GAUSS, precision=HS_BF16,
-                   recheck_tau=0.055, logits=False, stats=False, workspace=None):
+                   recheck_tau=None, logits=False, stats=False, workspace=None):
     """bits [B,H,W] uint8 (and optionally logits, and stats =
-    (rechecked, flipped, recomputed in FP32, 0))."""
+    (rechecked, flipped, recomputed in FP32, FP16 overflow re-run)).
+    recheck_tau None: the band of RECHECK_TAU for the precision."""
+    recheck_tau = _tau(precision, recheck_tau)
     B, H, W = contone.shape
     dev = contone.device
     _dev(weights, torch.float32), _dev(contone, torch.float32), _dev(seeds, torch.int64)
@@ -168,13 +179,14 @@ def page_shapes_array(shapes):
 
 
 def halftone_infer_pages(weights, contone, seeds, shapes, noise_kind=HS_NOISE_GAUSS,
-                         precision=HS_BF16, recheck_tau=0.055, logits=False, stats=False,
+                         precision=HS_BF16, recheck_tau=None, logits=False, stats=False,
                          workspace=None, levels=None):
     """Pages of different sizes in one call. contone: flat FP32 device tensor
     of the pages concatenated (page p at offset sum of the earlier H*W);
     shapes: (H, W) per page; returns flat bits (and logits, stats). With
     `levels` (2..HS_MAX_LEVELS) the multitone call halftone_infer_levels:
     level indices instead of bits."""
+    recheck_tau = _tau(precision, recheck_tau)
     sh = page_shapes_array(shapes)
     n = sh.shape[0]
     N = int((sh[:, 0].astype("int64") * sh[:, 1]).sum())

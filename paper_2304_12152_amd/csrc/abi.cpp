@@ -342,11 +342,12 @@ const char* halftone_last_error(void) { return g_err.c_str(); }
 int64_t halftone_param_count(void) { return HS_PARAM_COUNT; }
 
 // ------------------------------------------------------------- inference --
-// Workspace of the BF16 path (sizes in bytes) for pages of the given shapes:
-// packed fragments, the split and FP32 weight copies, the page table, the
-// segmented recheck list and its counts, the FP32-stage list, counters.
+// Workspace of the 16-bit paths (sizes in bytes) for pages of the given
+// shapes: packed BF16 and FP16 fragments, the split and FP32 weight copies,
+// the page table, the segmented recheck list and its counts, the FP32-stage
+// list, counters.
 struct Bf16Ws {
-  char *pack, *split;
+  char *pack, *pack16, *split;
   Page* pages;
   uint64_t *seglist, *list2;
   int *seg_count, *cnt;
@@ -355,6 +356,7 @@ static size_t bf16_ws(const int* shapes, int npages, size_t N, Bf16Ws* out, void
   Carve cv(base);
   Bf16Ws w;
   w.pack = cv.take<char>(fused_frag_bytes());
+  w.pack16 = cv.take<char>(fused_frag_bytes());
   w.split = cv.take<char>(split_frag_bytes() + fp32_pack_bytes());
   w.pages = cv.take<Page>((size_t)npages * sizeof(Page));
   const size_t ne = fused_list_entries(shapes, npages, num_cus());
@@ -387,22 +389,26 @@ static std::vector<int> uniform_shapes(int B, int H, int W) {
 
 size_t halftone_infer_workspace_size(int B, int H, int W, int precision) {
   if (!shape_ok(B, H, W)) return 0;
-  if (precision == HS_BF16) {
+  if (precision != HS_FP32) {
     const std::vector<int> sh = uniform_shapes(B, H, W);
     return bf16_ws(sh.data(), B, (size_t)B * H * W, nullptr, nullptr);
   }
   return fp32_ws(B, H, W, nullptr, nullptr, nullptr);
 }
 
-// The BF16 path over a page table (one persistent fused launch for all pages):
-//   stage 1: fused BF16 pass, pixels with |x| < tau listed
+// The 16-bit path over a page table (one persistent fused launch for all pages):
+//   stage 1: fused BF16 (or FP16) pass, pixels with |x| < tau listed
+//   stage 1b (FP16 only): if an activation overflowed FP16, the fused BF16
+//            pass again, with 8 tau (BF16 rounds 8 times coarser); a launch
+//            that returns at once otherwise, so no host synchronisation
 //   stage 2: split-BF16 receptive-field recompute, |x| < tau2 listed again
 //   stage 3: FP32 receptive-field recompute
 // The page table is built on the device (uniform batch) or from pages_host.
 static int infer_bf16(const float* weights, const float* contone, const uint64_t* seeds,
                       const int* shapes, int npages, size_t N, const Page* pages_host,
-                      int noise_kind, float recheck_tau, const Levels& lv, uint8_t* bits,
-                      float* logits, int32_t* stats_or_null, void* workspace, hipStream_t s) {
+                      int noise_kind, float recheck_tau, const Levels& lv, bool fp16,
+                      uint8_t* bits, float* logits, int32_t* stats_or_null, void* workspace,
+                      hipStream_t s) {
   Bf16Ws w;
   bf16_ws(shapes, npages, N, &w, workspace);
   int32_t* stats = stats_or_null ? stats_or_null : (int32_t*)(w.cnt + 8);
@@ -414,15 +420,21 @@ static int infer_bf16(const float* weights, const float* contone, const uint64_t
   char* whi = w.split;
   char* wlo = whi + split_frag_bytes() / 2;
   char* wt = whi + split_frag_bytes();
-  HS_TRY(launch_fused_pack(weights, w.pack, s));
+  HS_TRY(launch_fused_pack(weights, w.pack, fp16 ? w.pack16 : nullptr, s));
   HS_TRY(launch_split_pack(weights, whi, wlo, wt, s));
   int nseg = 0;
   long long seg_cap = 0;
+  int* ovf = stats + 3;  // zeroed above
   prof_begin(s);
   HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
                             recheck_tau, lv, bits, logits, w.seglist, w.seg_count, &nseg,
-                            &seg_cap, w.pack, num_cus(), s));
+                            &seg_cap, fp16 ? w.pack16 : w.pack, fp16, ovf, nullptr, num_cus(),
+                            s));
   prof_end(s);
+  if (fp16)
+    HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
+                              8.0f * recheck_tau, lv, bits, logits, w.seglist, w.seg_count,
+                              &nseg, &seg_cap, w.pack, false, nullptr, ovf, num_cus(), s));
   HS_TRY(launch_recheck_split(weights, contone, seeds, w.pages, noise_kind, w.seglist,
                               w.seg_count, nseg, seg_cap, whi, wlo, tau2, lv, w.list2,
                               w.cnt + 1, bits, logits, stats, num_cus(), s));
@@ -464,7 +476,7 @@ static int check_infer_args(const float* weights, const float* contone, const ui
                             int precision, float recheck_tau, const char* who) {
   if (!weights || !contone || !seeds || !bits || !workspace)
     return fail(HS_EINVAL, "%s: null pointer", who);
-  if (precision != HS_FP32 && precision != HS_BF16)
+  if (precision != HS_FP32 && precision != HS_BF16 && precision != HS_FP16)
     return fail(HS_EUNSUPPORTED, "%s: precision %d", who, precision);
   if (noise_kind != HS_NOISE_GAUSS && noise_kind != HS_NOISE_UNIFORM)
     return fail(HS_EINVAL, "%s: noise kind %d", who, noise_kind);
@@ -484,11 +496,11 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
     return fail(HS_EWORKSPACE, "halftone_infer: workspace too small");
   if ((rc = check_device())) return rc;
   hipStream_t s = (hipStream_t)stream;
-  if (precision == HS_BF16) {
+  if (precision != HS_FP32) {
     const std::vector<int> sh = uniform_shapes(B, H, W);
     return infer_bf16(weights, contone, seeds, sh.data(), B, (size_t)B * H * W, nullptr,
-                      noise_kind, recheck_tau, make_levels(2), bits, logits_or_null,
-                      stats_or_null, workspace, s);
+                      noise_kind, recheck_tau, make_levels(2), precision == HS_FP16, bits,
+                      logits_or_null, stats_or_null, workspace, s);
   }
   if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
   return infer_fp32(weights, contone, seeds, B, H, W, noise_kind, make_levels(2), bits,
@@ -512,7 +524,7 @@ size_t halftone_infer_pages_workspace_size(int npages, const int32_t* shapes_hos
                                            int precision) {
   size_t N = 0;
   if (!pages_ok(npages, shapes_host, &N)) return 0;
-  if (precision == HS_BF16) return bf16_ws(shapes_host, npages, N, nullptr, nullptr);
+  if (precision != HS_FP32) return bf16_ws(shapes_host, npages, N, nullptr, nullptr);
   size_t m = 0;  // the FP32 path runs page by page
   for (int p = 0; p < npages; ++p) {
     const size_t b = fp32_ws(1, shapes_host[2 * p], shapes_host[2 * p + 1], nullptr, nullptr,
@@ -540,7 +552,7 @@ static int infer_pages(const float* weights, const float* contone, const uint64_
   if ((rc = check_device())) return rc;
   hipStream_t s = (hipStream_t)stream;
   const Levels lv = make_levels(levels);
-  if (precision == HS_BF16) {
+  if (precision != HS_FP32) {
     std::vector<Page> pages(npages);
     long long off = 0, vstart = 0;
     for (int p = 0; p < npages; ++p) {
@@ -555,7 +567,8 @@ static int infer_pages(const float* weights, const float* contone, const uint64_
       vstart += (long long)fused_strips(W) * (H + fused_fill());
     }
     return infer_bf16(weights, contone, seeds, shapes_host, npages, N, pages.data(), noise_kind,
-                      recheck_tau, lv, out, logits_or_null, stats_or_null, workspace, s);
+                      recheck_tau, lv, precision == HS_FP16, out, logits_or_null, stats_or_null,
+                      workspace, s);
   }
   if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
   long long off = 0;

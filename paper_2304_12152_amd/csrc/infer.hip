@@ -1,7 +1,11 @@
 // infer.hip -- the TEST procedure of Algorithm 1 on gfx950: the fused BF16
-// pass of the policy network over whole images, with each pixel's logit
-// thresholded at 0 (p = 0.5) and the near-threshold pixels listed for the
-// recheck stages (recheck.hip).
+// (or FP16) pass of the policy network over whole images, with each pixel's
+// logit thresholded at 0 (p = 0.5) and the near-threshold pixels listed for
+// the recheck stages (recheck.hip). FP16 has 11 significant bits to BF16's 8
+// at the same matrix-core rate, so its logit error and recheck band are about
+// 8 times smaller; its range ends at 65504, so the FP16 pass records whether
+// any activation overflowed, and a BF16 launch that does nothing otherwise
+// then redoes the pass.
 #include "hs_common.h"
 #include "hs_internal.h"
 
@@ -79,7 +83,9 @@ HS_DEV int ring_off(int col, int g) { return (col * 4 + (g ^ ((col >> 1) & 3))) 
 
 HS_DEV int ring_channel(int g, int e) { return hs_ring_channel(g, e); }
 
-__global__ void pack_fused_kernel(const float* __restrict__ w, __bf16* __restrict__ out) {
+// out: BF16 fragments; out16 (may be null): the same fragments in FP16
+__global__ void pack_fused_kernel(const float* __restrict__ w, __bf16* __restrict__ out,
+                                  _Float16* __restrict__ out16) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < FRAG_TOTAL * 8;
        i += gridDim.x * blockDim.x) {
     const int f = i >> 3, e = i & 7;
@@ -98,13 +104,37 @@ __global__ void pack_fused_kernel(const float* __restrict__ w, __bf16* __restric
       if (r < 9) v = w[HS_W6 + ring_channel(g, e) * 9 + r];
     }
     out[i] = (__bf16)v;
+    if (out16) out16[i] = (_Float16)v;
   }
 }
+
+// The 16-bit element type of the fused pass: BF16, or FP16 (three more
+// mantissa bits at the same matrix-core rate, a range of 65504).
+template <typename E>
+struct Elem;
+template <>
+struct Elem<__bf16> {
+  using v8 = bf16x8_t;
+  using v2 = bf16x2_t;
+  static constexpr bool kRangeCheck = false;  // FP32's exponent range
+  static HS_DEV f32x4_t mma(v8 a, v8 b, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Elem<_Float16> {
+  using v8 = f16x8_t;
+  using v2 = f16x2_t;
+  static constexpr bool kRangeCheck = true;  // a finite FP32 value can round to inf
+  static HS_DEV f32x4_t mma(v8 a, v8 b, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
 
 struct FusedArgs {
   const float* contone;
   const uint64_t* seeds;
-  const bf16x8_t* frags;
+  const void* frags;  // 16-bit fragments of the element type
   const float* w;
   const hs::Page* pages;
   int npages, kind;
@@ -116,6 +146,8 @@ struct FusedArgs {
   uint64_t* list;     // per output wave a segment of seg_cap entries
   int* seg_count;     // entries written per segment
   long long seg_cap;
+  int* ovf;           // FP16: set to 1 when an activation left the FP16 range
+  const int* guard;   // when set: run only if *guard != 0 (the BF16 re-run)
 };
 
 template <int V>
@@ -123,12 +155,14 @@ struct StepIndex {
   static constexpr int value = V;
 };
 
-// two floats -> packed BF16 pair (round to nearest even), then ReLU on the
-// packed bits: a BF16 with its sign bit set is a negative int16, so a 16-bit
-// integer max with 0 is the ReLU (and equals ReLU before rounding)
-HS_DEV uint32_t relu_bf16x2(float lo, float hi) {
+// two floats -> packed 16-bit pair (round to nearest even), then ReLU on the
+// packed bits: a BF16 or FP16 value with its sign bit set is a negative
+// int16, so a 16-bit integer max with 0 is the ReLU (and equals ReLU before
+// rounding)
+template <typename E>
+HS_DEV uint32_t relu_x2(float lo, float hi) {
   const f32x2_t v = {lo, hi};
-  const bf16x2_t h = __builtin_convertvector(v, bf16x2_t);
+  const typename Elem<E>::v2 h = __builtin_convertvector(v, typename Elem<E>::v2);
   i16x2_t q;
   __builtin_memcpy(&q, &h, 4);
   q = __builtin_elementwise_max(q, (i16x2_t){0, 0});
@@ -137,19 +171,31 @@ HS_DEV uint32_t relu_bf16x2(float lo, float hi) {
   return u;
 }
 
-// ReLU + BF16 of one finished 16-pixel run in the ring channel order; zero
-// where the pixel lies outside the image (the next layer's zero padding)
-HS_DEV bf16x8_t relu_bf16(const f32x4_t (&acc)[2], bool in) {
+// ReLU + conversion of one finished 16-pixel run in the ring channel order;
+// zero where the pixel lies outside the image (the next layer's zero
+// padding). FP16: ovf keeps the running maximum of the packed results as
+// int16 pairs; a non-negative FP16 at or above 0x7C00 is inf or NaN, so a
+// maximum that reaches it means an activation overflowed.
+template <typename E>
+HS_DEV typename Elem<E>::v8 relu_pack(const f32x4_t (&acc)[2], bool in, i16x2_t& ovf) {
   // branch-free: the pairs are packed for every lane and masked (a select
   // per pair instead of a divergent branch around each)
   const uint32_t keep = 0u - (uint32_t)in;
   uint32_t u[4];
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
-    u[2 * m] = relu_bf16x2(acc[m][0], acc[m][1]) & keep;
-    u[2 * m + 1] = relu_bf16x2(acc[m][2], acc[m][3]) & keep;
+    u[2 * m] = relu_x2<E>(acc[m][0], acc[m][1]) & keep;
+    u[2 * m + 1] = relu_x2<E>(acc[m][2], acc[m][3]) & keep;
   }
-  bf16x8_t v;
+  if constexpr (Elem<E>::kRangeCheck) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      i16x2_t q;
+      __builtin_memcpy(&q, &u[j], 4);
+      ovf = __builtin_elementwise_max(ovf, q);
+    }
+  }
+  typename Elem<E>::v8 v;
   __builtin_memcpy(&v, u, 16);
   return v;
 }
@@ -161,15 +207,20 @@ HS_DEV bf16x8_t relu_bf16(const f32x4_t (&acc)[2], bool in) {
 // MULTI: the output is the level of the logit among a.lv's thresholds
 // (multitoning), and the recheck band is around the nearest threshold;
 // otherwise the bit [x >= 0] with the band around 0.
-template <int NW, bool MULTI>
+// E: the 16-bit element type of activations and weights (BF16 or FP16).
+template <int NW, bool MULTI, typename E>
 __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a) {
+  using V8 = typename Elem<E>::v8;
+  using V2 = typename Elem<E>::v2;
   constexpr int RPW = 8 / NW, NT = 64 * 4 * NW, HPW = 2 / NW;  // runs, threads, 64-px halves per wave
-  __shared__ __attribute__((aligned(16))) __bf16 ring[4 * 2 * ROWE];   // layers 1..4
+  // the re-run launch exits at once unless the pass before it overflowed
+  if (a.guard && __builtin_amdgcn_readfirstlane(*a.guard) == 0) return;
+  __shared__ __attribute__((aligned(16))) E ring[4 * 2 * ROWE];   // layers 1..4
   // input rows as per-column records [(c, z) of columns j, j+1, j+2, 0],
-  // each (c, z) a BF16 pair: one record is a layer-1 operand row
+  // each (c, z) a 16-bit pair: one record is a layer-1 operand row
   __shared__ __attribute__((aligned(16))) uint32_t inring[4 * RWID * 4];
   __shared__ __attribute__((aligned(16))) float tring[2 * RWID * 12];  // T, 12 floats per column
-  __shared__ bf16x8_t cfrag[3 * 64];  // layer-1 A operands (m = 0, 1), layer-6 tap matrix
+  __shared__ V8 cfrag[3 * 64];  // layer-1 A operands (m = 0, 1), layer-6 tap matrix
   __shared__ __attribute__((aligned(16))) float cbias[5 * 32];  // biases of layers 1..5
   __shared__ float osum[3][FW];  // the output stage's running sums, per strip column
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, r = lane & 15;
@@ -183,14 +234,15 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
   // weights of the owned layer stay in registers (A operands, [dy][dx][m]);
   // the biases and the role operands (layer 1's two A operands, the layer-6
   // tap matrix) are read from LDS where they are used
-  bf16x8_t wA[3][3][2];
+  const V8* frags = (const V8*)a.frags;
+  V8 wA[3][3][2];
 #pragma unroll
   for (int t = 0; t < 9; ++t)
 #pragma unroll
     for (int m = 0; m < 2; ++m)
-      wA[t / 3][t % 3][m] = a.frags[FRAG_L32 + (((k - 2) * 9 + t) * 2 + m) * 64 + lane];
+      wA[t / 3][t % 3][m] = frags[FRAG_L32 + (((k - 2) * 9 + t) * 2 + m) * 64 + lane];
   for (int i = tid; i < 3 * 64; i += NT)
-    cfrag[i] = a.frags[i < 128 ? FRAG_L1 + i : FRAG_T + (i - 128)];
+    cfrag[i] = frags[i < 128 ? FRAG_L1 + i : FRAG_T + (i - 128)];
   for (int i = tid; i < 5 * 32; i += NT) cbias[i] = a.w[i < 32 ? HS_B1 + i : hs_bk(2 + (i - 32) / 32) + (i & 31)];
   const float b6 = a.w[HS_B6];
   // this lane's element offset in a ring row: chunk g, first column of its
@@ -203,6 +255,7 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
   for (int j = 0; j < 3; ++j)
 #pragma unroll
     for (int n = 0; n < RPW; ++n) S[j][n][0] = S[j][n][1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  i16x2_t ovf = {0, 0};  // running maximum of the packed activations (FP16)
   int nflag[HPW];
 #pragma unroll
   for (int h = 0; h < HPW; ++h) nflag[h] = 0;
@@ -323,24 +376,24 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
       if (k < 5) {
         const int rs = A + t + 1 - 3 * k;
         const bool row_in = rs >= 0 && rs < H;
-        __bf16* dst = ring + ((size_t)(k - 1) * 2 + cur) * ROWE + woff;
+        E* dst = ring + ((size_t)(k - 1) * 2 + cur) * ROWE + woff;
 #pragma unroll
         for (int n = 0; n < RPW; ++n) {
           const int x = X + col0 + 16 * n + lr;
           const bool in = row_in && (cols_inside || (x >= 0 && x < W));
-          *(bf16x8_t*)(dst + n * RUNE) = relu_bf16(S[J][n], in);
+          *(V8*)(dst + n * RUNE) = relu_pack<E>(S[J][n], in, ovf);
         }
       } else {  // layer 5: the nine layer-6 taps of row rs into the T ring
         const int rs = A + t - 14;
         const bool row_in = rs >= 0 && rs < H;
         float* trow = tring + (size_t)cur * RWID * 12;
-        const bf16x8_t w6 = cfrag[128 + ln];
+        const V8 w6 = cfrag[128 + ln];
 #pragma unroll
         for (int n = 0; n < RPW; ++n) {
           const int c = col0 + 16 * n + lr, x = X + c;
           const bool in = row_in && (cols_inside || (x >= 0 && x < W));
-          const f32x4_t tv = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              w6, relu_bf16(S[J][n], in), f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+          const f32x4_t tv =
+              Elem<E>::mma(w6, relu_pack<E>(S[J][n], in, ovf), f32x4_t{0.f, 0.f, 0.f, 0.f});
           if (lg < 3) *(f32x4_t*)(trow + (c + 1) * 12 + 4 * lg) = tv;
         }
       }
@@ -354,18 +407,18 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
         }
       }
       // ---- one input row q (written by layer k-1 in the previous step)
-      const __bf16* src = ring + ((size_t)(k - 2) * 2 + prev) * ROWE;
+      const E* src = ring + ((size_t)(k - 2) * 2 + prev) * ROWE;
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
-        const __bf16* srcd = src + ring_off(col0 + lr + dx, lg);
+        const E* srcd = src + ring_off(col0 + lr + dx, lg);
 #pragma unroll
         for (int n = 0; n < RPW; ++n) {
-          const bf16x8_t bf = *(const bf16x8_t*)(srcd + n * RUNE);
+          const V8 bf = *(const V8*)(srcd + n * RUNE);
 #pragma unroll
           for (int m = 0; m < 2; ++m) {
-            S[J][n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wA[0][dx][m], bf, S[J][n][m], 0, 0, 0);
-            S[M1][n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wA[1][dx][m], bf, S[M1][n][m], 0, 0, 0);
-            S[M2][n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wA[2][dx][m], bf, S[M2][n][m], 0, 0, 0);
+            S[J][n][m] = Elem<E>::mma(wA[0][dx][m], bf, S[J][n][m]);
+            S[M1][n][m] = Elem<E>::mma(wA[1][dx][m], bf, S[M1][n][m]);
+            S[M2][n][m] = Elem<E>::mma(wA[2][dx][m], bf, S[M2][n][m]);
           }
         }
       }
@@ -379,20 +432,20 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
         // lane group g reads kernel row dy = g (group 3 meets zero weights)
         const int dyl = lg < 3 ? lg : 2;
         const uint4* rec = (const uint4*)inring + ((t + 1 + dyl) & 3) * RWID + col0 + lr;
-        __bf16* dst = ring + (size_t)cur * ROWE + woff;
-        const bf16x8_t w10 = cfrag[ln], w11 = cfrag[64 + ln];
+        E* dst = ring + (size_t)cur * ROWE + woff;
+        const V8 w10 = cfrag[ln], w11 = cfrag[64 + ln];
         const f32x4_t b10 = *(const f32x4_t*)(cbias + 4 * lg), b11 = *(const f32x4_t*)(cbias + 16 + 4 * lg);
 #pragma unroll
         for (int n = 0; n < RPW; ++n) {
           const int c0 = col0 + 16 * n + lr;  // column of tap dx = 0
           const uint4 u = rec[16 * n];
-          bf16x8_t bf;
+          V8 bf;
           __builtin_memcpy(&bf, &u, 16);
           f32x4_t l1[2];
-          l1[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w10, bf, b10, 0, 0, 0);
-          l1[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w11, bf, b11, 0, 0, 0);
+          l1[0] = Elem<E>::mma(w10, bf, b10);
+          l1[1] = Elem<E>::mma(w11, bf, b11);
           const int x = X + c0;
-          *(bf16x8_t*)(dst + n * RUNE) = relu_bf16(l1, row_in && x >= 0 && x < W);
+          *(V8*)(dst + n * RUNE) = relu_pack<E>(l1, row_in && x >= 0 && x < W, ovf);
         }
       }
       // ---- input stage (waves NW..2NW-1): row A+t into slot t % 4
@@ -405,7 +458,7 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
           const float cval = cin[h];
           float zval = 0.f;
           if (xin_ok && ri >= 0 && ri < H) zval = hs_noise(seed, (uint64_t)ri * W + xin, 0u, a.kind);
-          const bf16x2_t cz = __builtin_convertvector((f32x2_t){cval, zval}, bf16x2_t);
+          const V2 cz = __builtin_convertvector((f32x2_t){cval, zval}, V2);
           uint32_t u;
           __builtin_memcpy(&u, &cz, 4);
           // column j = Lx + 1 is element e of the record of column j - e
@@ -422,6 +475,10 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
       step(t + 1, StepIndex<1>{});
       step(t + 2, StepIndex<2>{});
     }
+  }
+  if constexpr (Elem<E>::kRangeCheck) {
+    // a packed half at or above 0x7C00 is inf or NaN; no wave reads the flag
+    if (__ballot(ovf[0] >= 0x7C00 || ovf[1] >= 0x7C00) && lane == 0 && a.ovf) *a.ovf = 1;
   }
   // recheck list: the output stage's 64-pixel halves each own a segment
   if (role == 2 && lane == 0 && a.seg_count) {
@@ -462,8 +519,8 @@ namespace hs {
 
 size_t fused_frag_bytes() { return (size_t)FRAG_TOTAL * 16; }
 
-hipError_t launch_fused_pack(const float* w, void* frags, hipStream_t s) {
-  pack_fused_kernel<<<38, 256, 0, s>>>(w, (__bf16*)frags);
+hipError_t launch_fused_pack(const float* w, void* frags, void* frags16, hipStream_t s) {
+  pack_fused_kernel<<<38, 256, 0, s>>>(w, (__bf16*)frags, (_Float16*)frags16);
   return hipGetLastError();
 }
 
@@ -521,11 +578,14 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
                               const Page* pages, const int* shapes_host, int npages, int kind,
                               float tau, const Levels& lv, uint8_t* bits, float* logits,
                               uint64_t* list, int* seg_count, int* nseg, long long* seg_cap,
-                              const void* frags, int num_cus, hipStream_t s) {
+                              const void* frags, bool fp16, int* ovf, const int* guard,
+                              int num_cus, hipStream_t s) {
   FusedArgs a;
   a.contone = contone;
   a.seeds = seeds;
-  a.frags = (const bf16x8_t*)frags;
+  a.frags = frags;
+  a.ovf = ovf;
+  a.guard = guard;
   a.w = w;
   a.pages = pages;
   a.npages = npages;
@@ -542,10 +602,15 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
   a.seg_cap = rows * 64;
   *nseg = 2 * grid;
   *seg_cap = a.seg_cap;
-  if (lv.n == 1 && lv.thr[0] == 0.0f)
-    fused_infer_kernel<FUSED_NW, false><<<grid, 64 * 4 * FUSED_NW, 0, s>>>(a);
-  else
-    fused_infer_kernel<FUSED_NW, true><<<grid, 64 * 4 * FUSED_NW, 0, s>>>(a);
+  const bool binary = lv.n == 1 && lv.thr[0] == 0.0f;
+  const dim3 block(64 * 4 * FUSED_NW);
+  if (fp16) {
+    if (binary) fused_infer_kernel<FUSED_NW, false, _Float16><<<grid, block, 0, s>>>(a);
+    else fused_infer_kernel<FUSED_NW, true, _Float16><<<grid, block, 0, s>>>(a);
+  } else {
+    if (binary) fused_infer_kernel<FUSED_NW, false, __bf16><<<grid, block, 0, s>>>(a);
+    else fused_infer_kernel<FUSED_NW, true, __bf16><<<grid, block, 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 

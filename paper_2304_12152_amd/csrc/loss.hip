@@ -286,18 +286,41 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
   grad[oa] = gv;
 }
 
-// Ring of frequency (u, v) of a P x P periodogram: the rho with
-// (2 rho - 1)^2 <= 4 (ub^2 + vb^2) < (2 rho + 1)^2, ub = min(u, P - u).
-HS_DEV int ring_of(int u, int v) {
+constexpr int NRING = 24;
+
+// Ring of frequency (u, v) of a 32 x 32 periodogram: the rho with
+// (2 rho - 1)^2 <= 4 (ub^2 + vb^2) < (2 rho + 1)^2, ub = min(u, 32 - u).
+constexpr int ring_of(int u, int v) {
   const int ub = u < 32 - u ? u : 32 - u, vb = v < 32 - v ? v : 32 - v;
   const int q4 = 4 * (ub * ub + vb * vb);
-  int rho = (int)sqrtf((float)(ub * ub + vb * vb));
+  int rho = 0;
   while ((2 * rho + 1) * (2 * rho + 1) <= q4) ++rho;
-  while (rho > 0 && (2 * rho - 1) * (2 * rho - 1) > q4) --rho;
   return rho;
 }
 
-constexpr int NRING = 24;
+// The frequencies grouped by ring (row-major order inside a ring) and the
+// ring of each frequency; the same for every patch, so built at compile time.
+struct RingTable {
+  unsigned short idx[1024];
+  unsigned short start[NRING + 1];
+  unsigned char ring[1024];
+};
+
+constexpr RingTable make_ring_table() {
+  RingTable t{};
+  for (int i = 0; i < 1024; ++i) t.ring[i] = (unsigned char)ring_of(i >> 5, i & 31);
+  int n = 0;
+  for (int r = 0; r < NRING; ++r) {
+    t.start[r] = (unsigned short)n;
+    for (int i = 0; i < 1024; ++i)
+      if (t.ring[i] == r) t.idx[n++] = (unsigned short)i;
+  }
+  t.start[NRING] = (unsigned short)n;
+  return t;
+}
+
+__constant__ RingTable kRings = make_ring_table();
+static_assert(make_ring_table().start[NRING] == 1024, "every frequency lies in a ring");
 
 __global__ __launch_bounds__(256) void as_kernel(const float* __restrict__ pg, int Bg, int Hg,
                                                  int Wg, float scale, int logit_space,
@@ -309,7 +332,6 @@ __global__ __launch_bounds__(256) void as_kernel(const float* __restrict__ pg, i
   __shared__ float ph[32 * 32];
   __shared__ float cs[32], sn[32];
   __shared__ float ring_part[NRING][8];
-  __shared__ int ring_npart[NRING][8];
   __shared__ float ring_mean[NRING];
   __shared__ float red[4];
   const int py = Hg / 32, px = Wg / 32;
@@ -360,29 +382,20 @@ __global__ __launch_bounds__(256) void as_kernel(const float* __restrict__ pg, i
   if (t < NRING * 8) {
     const int r = t >> 3, sub = t & 7;
     float s = 0.f;
-    int cnt = 0;
-    for (int i = sub; i < 1024; i += 8)
-      if (ring_of(i >> 5, i & 31) == r) {
-        s += ph[i];
-        ++cnt;
-      }
+    const int e = kRings.start[r + 1];
+    for (int j = kRings.start[r] + sub; j < e; j += 8) s += ph[kRings.idx[j]];
     ring_part[r][sub] = s;
-    ring_npart[r][sub] = cnt;
   }
   __syncthreads();
   if (t < NRING) {
     float s = 0.f;
-    int cnt = 0;
-    for (int k = 0; k < 8; ++k) {
-      s += ring_part[t][k];
-      cnt += ring_npart[t][k];
-    }
-    ring_mean[t] = s / (float)cnt;
+    for (int k = 0; k < 8; ++k) s += ring_part[t][k];
+    ring_mean[t] = s / (float)(kRings.start[t + 1] - kRings.start[t]);
   }
   __syncthreads();
   float lsum = 0.f;
   for (int i = t; i < 1024; i += 256) {
-    const float d = ph[i] - ring_mean[ring_of(i >> 5, i & 31)];
+    const float d = ph[i] - ring_mean[kRings.ring[i]];
     lsum = fmaf(d, d, lsum);
     ph[i] = 2.0f * d;  // dL/dPhat
   }

@@ -87,6 +87,15 @@ def _fake(n=64):
     return ctypes.c_void_p(ctypes.addressof(ctypes.create_string_buffer(n)))
 
 
+def test_fp16_inference_takes_the_bf16_workspace(lib):
+    """HS_FP16 runs the same stages as HS_BF16 (plus a BF16 re-run that
+    exits at once unless the FP16 pass overflowed), in the same workspace."""
+    for B, H, W in [(1, 8, 8), (8, 1024, 1024)]:
+        assert lib.halftone_infer_workspace_size(B, H, W, hb.HS_FP16) == \
+            lib.halftone_infer_workspace_size(B, H, W, hb.HS_BF16)
+    assert hb.RECHECK_TAU[hb.HS_FP16] < hb.RECHECK_TAU[hb.HS_BF16] / 4
+
+
 def test_infer_argument_errors(lib):
     p = _fake()
     ws = lib.halftone_infer_workspace_size(1, 8, 8, hb.HS_FP32)
@@ -172,6 +181,8 @@ def test_train_argument_errors(lib):
     a = list(base); a[0] = None
     assert lib.policy_train_step(*a) == hb.HS_EINVAL
     a = list(base); a[16] = 9
+    assert lib.policy_train_step(*a) == hb.HS_EUNSUPPORTED
+    a = list(base); a[16] = hb.HS_FP16  # inference only
     assert lib.policy_train_step(*a) == hb.HS_EUNSUPPORTED
     a = list(base); a[13] = -1
     assert lib.policy_train_step(*a) == hb.HS_EINVAL

@@ -1,0 +1,146 @@
+"""GPU parity of the FP16 inference pass (precision HS_FP16) against the
+oracle: FP16 carries three more mantissa bits than BF16 at the same matrix
+core rate, so its recheck band is about 8 times narrower; the bits must
+still equal the oracle's wherever |p - 0.5| > 1e-4. An activation beyond
+FP16's range sends the whole pass through BF16 again, on the device."""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import inputs, parity_mask, seeds_t, to_dev
+from paper_2304_12152_amd import binding as hb
+
+pytestmark = pytest.mark.gpu
+
+TAU16 = hb.RECHECK_TAU[hb.HS_FP16]
+SHAPES = [(1, 1, 1), (1, 3, 200), (1, 37, 45), (2, 64, 130), (1, 256, 256)]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_logits(orc, w, c, seeds):
+    B, H, W = c.shape
+    z = orc.noise_map(seeds, H, W, kind=0, stream=1, step=0)
+    return orc.policy_forward(w.astype(np.float64), c.astype(np.float64), z)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fp16_with_recheck_matches_oracle(orc, shape):
+    B, H, W = shape
+    seeds = list(range(21, 21 + B))
+    _say("infer fp16", shape)
+    w, c = inputs(seeds, H, W)
+    ref = _oracle_logits(orc, w, c, seeds)
+    bits, lg, st = hb.halftone_infer(to_dev(w), to_dev(c), seeds_t(seeds), 0, hb.HS_FP16,
+                                     logits=True, stats=True)
+    bits, lg, st = bits.cpu().numpy(), lg.cpu().numpy(), st.cpu().numpy()
+    m = parity_mask(orc, ref)
+    assert np.array_equal(bits[m], (ref >= 0)[m].astype(np.uint8))
+    near = np.abs(lg) < TAU16
+    assert np.abs(lg[near] - ref[near]).max(initial=0.0) <= 5e-4
+    nearer = np.abs(lg) < 5e-4  # tau2 = clamp(tau / 64, 5e-4, 1e-2)
+    assert np.abs(lg[nearer] - ref[nearer]).max(initial=0.0) <= 2e-5 * max(1.0, np.abs(ref).max())
+    assert np.abs(lg - ref).max() < TAU16
+    assert st[0] >= near.sum() and 0 <= st[1] <= st[0] and 0 <= st[2] <= st[0]
+    assert st[3] == 0
+
+
+def test_fp16_c2_error_and_bits():
+    """8 x 1024 x 1024: the raw FP16 logits (recheck_tau = 0, nothing
+    listed) stay within tau / 1.25 of the FP32 path's, and with the default
+    band the bits equal FP32's wherever |x_fp32| > 4.1e-4."""
+    B, H, W = 8, 1024, 1024
+    seeds = list(range(101, 109))
+    _say("infer fp16 C2")
+    w, c = inputs(seeds, H, W)
+    wt, ct, st = to_dev(w), to_dev(c), seeds_t(seeds)
+    b32, l32 = hb.halftone_infer(wt, ct, st, 0, hb.HS_FP32, logits=True)
+    _, raw = hb.halftone_infer(wt, ct, st, 0, hb.HS_FP16, 0.0, logits=True)
+    _, rawb = hb.halftone_infer(wt, ct, st, 0, hb.HS_BF16, 0.0, logits=True)
+    err16 = float((raw - l32).abs().max())
+    err_bf = float((rawb - l32).abs().max())
+    _say("max |logit error|: fp16 %.5f bf16 %.5f" % (err16, err_bf))
+    assert err16 < TAU16 / 1.25 and err16 < err_bf / 4
+    b16, stats = hb.halftone_infer(wt, ct, st, 0, hb.HS_FP16, stats=True)
+    b32, l32, b16 = b32.cpu().numpy(), l32.cpu().numpy(), b16.cpu().numpy()
+    m = np.abs(l32) > 4.1e-4
+    assert np.array_equal(b16[m], b32[m])
+    stats = stats.cpu().numpy()
+    _say("fp16 stats", stats.tolist())
+    assert stats[3] == 0 and stats[0] > 0
+
+
+def _scaled(w, s):
+    """Layer 1 (weights and bias) times s, layer 2's weights divided by s:
+    ReLU commutes with a positive scale, so the network is the same, but the
+    layer-1 activations grow by s."""
+    w = w.copy()
+    n1 = 32 * 2 * 9
+    w[:n1 + 32] *= s
+    w[n1 + 32:n1 + 32 + 32 * 32 * 9] /= s
+    return w
+
+
+def test_fp16_overflow_reruns_in_bf16(orc):
+    """With layer-1 activations scaled by 2^16 the FP16 pass overflows; the
+    call then decides every pixel from the BF16 pass with an 8 times wider
+    band. Power-of-two scaling is exact in BF16 and FP32, so the result
+    equals the unscaled network's BF16 result bit for bit."""
+    B, H, W = 2, 40, 150
+    seeds = [41, 42]
+    _say("infer fp16 overflow re-run")
+    w, c = inputs(seeds, H, W)
+    ws = _scaled(w, 2.0 ** 16)
+    assert hb.HS_PARAM_COUNT == w.size
+    ct, st = to_dev(c), seeds_t(seeds)
+    bits, lg, stats = hb.halftone_infer(to_dev(ws), ct, st, 0, hb.HS_FP16, logits=True,
+                                        stats=True)
+    ref_bits, ref_lg, ref_stats = hb.halftone_infer(to_dev(w), ct, st, 0, hb.HS_BF16,
+                                                    8 * TAU16, logits=True, stats=True)
+    stats, ref_stats = stats.cpu().numpy(), ref_stats.cpu().numpy()
+    assert stats[3] == 1 and ref_stats[3] == 0
+    assert np.array_equal(stats[:3], ref_stats[:3])
+    assert np.array_equal(bits.cpu().numpy(), ref_bits.cpu().numpy())
+    assert np.array_equal(lg.cpu().numpy(), ref_lg.cpu().numpy())
+    ref = _oracle_logits(orc, w, c, seeds)
+    m = parity_mask(orc, ref)
+    assert np.array_equal(bits.cpu().numpy()[m], (ref >= 0)[m].astype(np.uint8))
+    # the same weights without the scale stay in range
+    _, st2 = hb.halftone_infer(to_dev(w), ct, st, 0, hb.HS_FP16, stats=True)
+    assert st2.cpu().numpy()[3] == 0
+
+
+def test_fp16_pages_and_levels(orc):
+    """Uneven pages in one launch, binary and with 4 levels."""
+    pages = [(37, 200), (130, 129), (5, 300)]
+    seeds = [51, 52, 53]
+    _say("infer fp16 pages")
+    w = inputs([0], 1, 1)[0]
+    from paper_2304_12152_amd import synth
+    cs = [synth.contone_batch([s], h, ww)[0] for s, (h, ww) in zip(seeds, pages)]
+    flat = np.concatenate([x.ravel() for x in cs]).astype(np.float32)
+    for levels in (None, 4):
+        out, lg = hb.halftone_infer_pages(to_dev(w), to_dev(flat), seeds_t(seeds), pages,
+                                          precision=hb.HS_FP16, logits=True, levels=levels)
+        ref32, lg32 = hb.halftone_infer_pages(to_dev(w), to_dev(flat), seeds_t(seeds), pages,
+                                              precision=hb.HS_FP32, logits=True, levels=levels)
+        out, lg, ref32, lg32 = (t.cpu().numpy() for t in (out, lg, ref32, lg32))
+        L = 2 if levels is None else levels
+        thr = np.log((2 * np.arange(L - 1) + 1) / (2 * L - 3 - 2 * np.arange(L - 1)))
+        dist = np.min(np.abs(lg32[:, None] - thr[None, :]), axis=1)
+        m = dist > 4.1e-4
+        assert np.array_equal(out[m], ref32[m]), levels
+        assert np.abs(lg - lg32).max() < TAU16
+    # the binary pages against the oracle, page by page
+    off = 0
+    for s, (h, ww), x in zip(seeds, pages, cs):
+        ref = _oracle_logits(orc, w, x[None], [s])[0]
+        o = hb.halftone_infer_pages(to_dev(w), to_dev(flat), seeds_t(seeds), pages,
+                                    precision=hb.HS_FP16).cpu().numpy()[off:off + h * ww]
+        m = parity_mask(orc, ref).ravel()
+        assert np.array_equal(o[m], (ref.ravel() >= 0)[m].astype(np.uint8))
+        off += h * ww
