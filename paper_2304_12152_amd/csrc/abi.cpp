@@ -420,21 +420,32 @@ static int infer_bf16(const float* weights, const float* contone, const uint64_t
   char* whi = w.split;
   char* wlo = whi + split_frag_bytes() / 2;
   char* wt = whi + split_frag_bytes();
-  HS_TRY(launch_fused_pack(weights, w.pack, fp16 ? w.pack16 : nullptr, s));
+  int* needs_all = w.cnt + 24;  // FP16: layers 1..4 not cleared by their bounds
+  HS_TRY(launch_fused_pack(weights, w.pack, fp16 ? w.pack16 : nullptr, needs_all, s));
   HS_TRY(launch_split_pack(weights, whi, wlo, wt, s));
   int nseg = 0;
   long long seg_cap = 0;
   int* ovf = stats + 3;  // zeroed above
   prof_begin(s);
-  HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
-                            recheck_tau, lv, bits, logits, w.seglist, w.seg_count, &nseg,
-                            &seg_cap, fp16 ? w.pack16 : w.pack, fp16, ovf, nullptr, num_cus(),
-                            s));
+  if (!fp16) {
+    HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
+                              recheck_tau, lv, bits, logits, w.seglist, w.seg_count, &nseg,
+                              &seg_cap, w.pack, FUSED_BF16, nullptr, nullptr, 0, num_cus(), s));
+  } else {
+    // the device picks the FP16 form: of the two launches, the one whose
+    // gate does not match needs_all returns at once
+    for (int form : {FUSED_FP16_L5, FUSED_FP16_ALL})
+      HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
+                                recheck_tau, lv, bits, logits, w.seglist, w.seg_count, &nseg,
+                                &seg_cap, w.pack16, form, ovf, needs_all,
+                                form == FUSED_FP16_ALL, num_cus(), s));
+  }
   prof_end(s);
   if (fp16)
     HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
                               8.0f * recheck_tau, lv, bits, logits, w.seglist, w.seg_count,
-                              &nseg, &seg_cap, w.pack, false, nullptr, ovf, num_cus(), s));
+                              &nseg, &seg_cap, w.pack, FUSED_BF16, nullptr, ovf, 1, num_cus(),
+                              s));
   HS_TRY(launch_recheck_split(weights, contone, seeds, w.pages, noise_kind, w.seglist,
                               w.seg_count, nseg, seg_cap, whi, wlo, tau2, lv, w.list2,
                               w.cnt + 1, bits, logits, stats, num_cus(), s));

@@ -111,13 +111,16 @@ hipError_t launch_conv_last(const void* in, const float* w, int B, int H, int W,
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 size_t fused_frag_bytes();
 // BF16 fragments into frags and, when frags16 is not null, the same in FP16
-hipError_t launch_fused_pack(const float* w, void* frags, void* frags16, hipStream_t s);
+// and *needs_all: 1 unless a priori bounds keep FP16 layers 1..4 in range
+hipError_t launch_fused_pack(const float* w, void* frags, void* frags16, int* needs_all,
+                             hipStream_t s);
 // persistent fused inference over pages (one launch for all of them;
 // shapes_host = [npages][H, W] as in the device page table); the recheck
 // list is segmented (two segments per workgroup, counts in seg_count; list
-// may be null). fp16: FP16 fragments and activations, *ovf set to 1 when an
-// activation overflows FP16; guard (may be null): the launch does nothing
-// unless *guard != 0
+// may be null). form FUSED_BF16, or FP16 fragments and activations with
+// *ovf set to 1 when a tested value overflows FP16: FUSED_FP16_L5 tests
+// layer 5 and the contone range, FUSED_FP16_ALL every layer. guard (may be
+// null): the launch does nothing unless (*guard != 0) == guard_nonzero
 int fused_strips(int W);
 int fused_fill();
 hipError_t launch_uniform_pages(Page* pages, int B, int H, int W, hipStream_t s);
@@ -127,8 +130,9 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
                               const Page* pages, const int* shapes_host, int npages, int kind,
                               float tau, const Levels& lv, uint8_t* bits, float* logits,
                               uint64_t* list, int* seg_count, int* nseg, long long* seg_cap,
-                              const void* frags, bool fp16, int* ovf, const int* guard,
-                              int num_cus, hipStream_t s);
+                              const void* frags, int form, int* ovf, const int* guard,
+                              int guard_nonzero, int num_cus, hipStream_t s);
+enum { FUSED_BF16 = 0, FUSED_FP16_L5 = 1, FUSED_FP16_ALL = 2 };
 // recheck.hip: re-evaluation of listed pixels over their receptive field
 // (wt: layers 2..5 transposed for the FP32 stage, fp32_pack_bytes())
 hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,

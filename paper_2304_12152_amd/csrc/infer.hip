@@ -83,9 +83,23 @@ HS_DEV int ring_off(int col, int g) { return (col * 4 + (g ^ ((col >> 1) & 3))) 
 
 HS_DEV int ring_channel(int g, int e) { return hs_ring_channel(g, e); }
 
-// out: BF16 fragments; out16 (may be null): the same fragments in FP16
+// Activation bound below which FP16 carries a layer safely: the FP16 pass
+// rounds weights and activations (relative 2^-11 each, at most ten roundings
+// up to layer 5) and accumulates in FP32, all within 1% of the bound; 65504
+// is FP16's largest finite value.
+constexpr float FP16_SAFE = 60000.0f;
+// The Gaussian noise takes u1 >= 2^-24 in the Box-Muller transform, so
+// |z| <= sqrt(48 ln 2) = 5.77; the uniform noise lies in [0, 1).
+constexpr float NOISE_MAX = 5.8f;
+
+// out: BF16 fragments; out16 (may be null): the same fragments in FP16, and
+// then *needs_all = 1 unless a priori bounds keep layers 1..4 inside FP16's
+// range. With contones in [0, 1] (which the FP16 pass verifies) every
+// layer's inputs are non-negative after the ReLU, so output channel co is at
+// most the sum over its inputs of max(w, 0) times the input's bound, plus the
+// bias (layer 1 takes |w| for the noise channel).
 __global__ void pack_fused_kernel(const float* __restrict__ w, __bf16* __restrict__ out,
-                                  _Float16* __restrict__ out16) {
+                                  _Float16* __restrict__ out16, int* __restrict__ needs_all) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < FRAG_TOTAL * 8;
        i += gridDim.x * blockDim.x) {
     const int f = i >> 3, e = i & 7;
@@ -106,6 +120,34 @@ __global__ void pack_fused_kernel(const float* __restrict__ w, __bf16* __restric
     out[i] = (__bf16)v;
     if (out16) out16[i] = (_Float16)v;
   }
+  if (!out16 || blockIdx.x != 0) return;  // block-uniform: the barriers below are safe
+  // thread t: output channel co = t / 8, input channels ci = 4 (t % 8) .. +3
+  __shared__ float bound[32], part[256];
+  const int t = threadIdx.x, co = t >> 3, q = t & 7;
+  bool over = false;
+  for (int k = 1; k <= 4; ++k) {
+    const int cin = k == 1 ? 2 : 32;
+    const float* wk = w + (k == 1 ? HS_W1 : hs_wk(k));
+    float sum = 0.0f;
+    for (int ci = 4 * q; ci < 4 * q + 4 && ci < cin; ++ci) {
+      float sp = 0.0f;  // over the taps
+      for (int tp = 0; tp < 9; ++tp) {
+        const float wv = wk[(co * cin + ci) * 9 + tp];
+        sp += (k == 1 && ci == 1) ? fabsf(wv) : fmaxf(wv, 0.0f);
+      }
+      sum += sp * (k == 1 ? (ci == 0 ? 1.0f : NOISE_MAX) : bound[ci]);
+    }
+    part[t] = sum;
+    __syncthreads();
+    if (t < 32) {
+      float b = w[(k == 1 ? HS_B1 : hs_bk(k)) + t];
+      for (int j = 0; j < 8; ++j) b += part[8 * t + j];
+      bound[t] = fmaxf(b, 0.0f);
+    }
+    __syncthreads();
+    for (int c = 0; c < 32; ++c) over = over || !(bound[c] < FP16_SAFE);
+  }
+  if (t == 0) *needs_all = over ? 1 : 0;
 }
 
 // The 16-bit element type of the fused pass: BF16, or FP16 (three more
@@ -116,7 +158,6 @@ template <>
 struct Elem<__bf16> {
   using v8 = bf16x8_t;
   using v2 = bf16x2_t;
-  static constexpr bool kRangeCheck = false;  // FP32's exponent range
   static HS_DEV f32x4_t mma(v8 a, v8 b, f32x4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
@@ -125,7 +166,6 @@ template <>
 struct Elem<_Float16> {
   using v8 = f16x8_t;
   using v2 = f16x2_t;
-  static constexpr bool kRangeCheck = true;  // a finite FP32 value can round to inf
   static HS_DEV f32x4_t mma(v8 a, v8 b, f32x4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
@@ -147,8 +187,13 @@ struct FusedArgs {
   int* seg_count;     // entries written per segment
   long long seg_cap;
   int* ovf;           // FP16: set to 1 when an activation left the FP16 range
-  const int* guard;   // when set: run only if *guard != 0 (the BF16 re-run)
+  const int* guard;   // when set: run only if (*guard != 0) == guard_nonzero
+  int guard_nonzero;
 };
+
+// Overflow tests of an FP16 pass: none (BF16), layer 5 only plus the range
+// of the contones (when the a priori bounds clear layers 1..4), or every layer.
+enum Check { CHECK_NONE = 0, CHECK_L5 = 1, CHECK_ALL = 2 };
 
 template <int V>
 struct StepIndex {
@@ -173,11 +218,11 @@ HS_DEV uint32_t relu_x2(float lo, float hi) {
 
 // ReLU + conversion of one finished 16-pixel run in the ring channel order;
 // zero where the pixel lies outside the image (the next layer's zero
-// padding). FP16: ovf keeps the running maximum of the packed results as
-// int16 pairs; a non-negative FP16 at or above 0x7C00 is inf or NaN, so a
-// maximum that reaches it means an activation overflowed.
-template <typename E>
-HS_DEV typename Elem<E>::v8 relu_pack(const f32x4_t (&acc)[2], bool in, i16x2_t& ovf) {
+// padding). CHECK: ovf keeps the running maximum of the packed results as
+// unsigned 16-bit pairs; a non-negative FP16 at or above 0x7C00 is inf or
+// NaN, so a maximum that reaches it means an activation overflowed.
+template <typename E, bool CHECK>
+HS_DEV typename Elem<E>::v8 relu_pack(const f32x4_t (&acc)[2], bool in, u16x2_t& ovf) {
   // branch-free: the pairs are packed for every lane and masked (a select
   // per pair instead of a divergent branch around each)
   const uint32_t keep = 0u - (uint32_t)in;
@@ -187,10 +232,10 @@ HS_DEV typename Elem<E>::v8 relu_pack(const f32x4_t (&acc)[2], bool in, i16x2_t&
     u[2 * m] = relu_x2<E>(acc[m][0], acc[m][1]) & keep;
     u[2 * m + 1] = relu_x2<E>(acc[m][2], acc[m][3]) & keep;
   }
-  if constexpr (Elem<E>::kRangeCheck) {
+  if constexpr (CHECK) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      i16x2_t q;
+      u16x2_t q;
       __builtin_memcpy(&q, &u[j], 4);
       ovf = __builtin_elementwise_max(ovf, q);
     }
@@ -207,14 +252,17 @@ HS_DEV typename Elem<E>::v8 relu_pack(const f32x4_t (&acc)[2], bool in, i16x2_t&
 // MULTI: the output is the level of the logit among a.lv's thresholds
 // (multitoning), and the recheck band is around the nearest threshold;
 // otherwise the bit [x >= 0] with the band around 0.
-// E: the 16-bit element type of activations and weights (BF16 or FP16).
-template <int NW, bool MULTI, typename E>
+// E: the 16-bit element type of activations and weights (BF16 or FP16);
+// CHK: the overflow tests (CHECK_NONE for BF16).
+template <int NW, bool MULTI, typename E, int CHK>
 __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a) {
   using V8 = typename Elem<E>::v8;
   using V2 = typename Elem<E>::v2;
   constexpr int RPW = 8 / NW, NT = 64 * 4 * NW, HPW = 2 / NW;  // runs, threads, 64-px halves per wave
-  // the re-run launch exits at once unless the pass before it overflowed
-  if (a.guard && __builtin_amdgcn_readfirstlane(*a.guard) == 0) return;
+  // a gated launch exits at once unless its condition holds (the BF16 re-run
+  // after an FP16 overflow, the FP16 form the layer bounds select)
+  if (a.guard && ((__builtin_amdgcn_readfirstlane(*a.guard) != 0) != (a.guard_nonzero != 0)))
+    return;
   __shared__ __attribute__((aligned(16))) E ring[4 * 2 * ROWE];   // layers 1..4
   // input rows as per-column records [(c, z) of columns j, j+1, j+2, 0],
   // each (c, z) a 16-bit pair: one record is a layer-1 operand row
@@ -255,7 +303,8 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
   for (int j = 0; j < 3; ++j)
 #pragma unroll
     for (int n = 0; n < RPW; ++n) S[j][n][0] = S[j][n][1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  i16x2_t ovf = {0, 0};  // running maximum of the packed activations (FP16)
+  u16x2_t ovf = {0, 0};  // running maximum of the tested FP16 values
+
   int nflag[HPW];
 #pragma unroll
   for (int h = 0; h < HPW; ++h) nflag[h] = 0;
@@ -377,25 +426,31 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
         const int rs = A + t + 1 - 3 * k;
         const bool row_in = rs >= 0 && rs < H;
         E* dst = ring + ((size_t)(k - 1) * 2 + cur) * ROWE + woff;
+        auto store = [&]() {
 #pragma unroll
-        for (int n = 0; n < RPW; ++n) {
-          const int x = X + col0 + 16 * n + lr;
-          const bool in = row_in && (cols_inside || (x >= 0 && x < W));
-          *(V8*)(dst + n * RUNE) = relu_pack<E>(S[J][n], in, ovf);
-        }
+          for (int n = 0; n < RPW; ++n) {
+            const int x = X + col0 + 16 * n + lr;
+            const bool in = row_in && (cols_inside || (x >= 0 && x < W));
+            *(V8*)(dst + n * RUNE) = relu_pack<E, CHK == CHECK_ALL>(S[J][n], in, ovf);
+          }
+        };
+        store();
       } else {  // layer 5: the nine layer-6 taps of row rs into the T ring
         const int rs = A + t - 14;
         const bool row_in = rs >= 0 && rs < H;
         float* trow = tring + (size_t)cur * RWID * 12;
         const V8 w6 = cfrag[128 + ln];
+        auto taps = [&]() {
 #pragma unroll
-        for (int n = 0; n < RPW; ++n) {
-          const int c = col0 + 16 * n + lr, x = X + c;
-          const bool in = row_in && (cols_inside || (x >= 0 && x < W));
-          const f32x4_t tv =
-              Elem<E>::mma(w6, relu_pack<E>(S[J][n], in, ovf), f32x4_t{0.f, 0.f, 0.f, 0.f});
-          if (lg < 3) *(f32x4_t*)(trow + (c + 1) * 12 + 4 * lg) = tv;
-        }
+          for (int n = 0; n < RPW; ++n) {
+            const int c = col0 + 16 * n + lr, x = X + c;
+            const bool in = row_in && (cols_inside || (x >= 0 && x < W));
+            const f32x4_t tv = Elem<E>::mma(
+                w6, relu_pack<E, CHK != CHECK_NONE>(S[J][n], in, ovf), f32x4_t{0.f, 0.f, 0.f, 0.f});
+            if (lg < 3) *(f32x4_t*)(trow + (c + 1) * 12 + 4 * lg) = tv;
+          }
+        };
+        taps();
       }
       {
         const f32x4_t bk0 = *(const f32x4_t*)(cbias + 32 * (k - 1) + 4 * lg);
@@ -435,18 +490,22 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
         E* dst = ring + (size_t)cur * ROWE + woff;
         const V8 w10 = cfrag[ln], w11 = cfrag[64 + ln];
         const f32x4_t b10 = *(const f32x4_t*)(cbias + 4 * lg), b11 = *(const f32x4_t*)(cbias + 16 + 4 * lg);
+        auto layer1 = [&]() {
 #pragma unroll
-        for (int n = 0; n < RPW; ++n) {
-          const int c0 = col0 + 16 * n + lr;  // column of tap dx = 0
-          const uint4 u = rec[16 * n];
-          V8 bf;
-          __builtin_memcpy(&bf, &u, 16);
-          f32x4_t l1[2];
-          l1[0] = Elem<E>::mma(w10, bf, b10);
-          l1[1] = Elem<E>::mma(w11, bf, b11);
-          const int x = X + c0;
-          *(V8*)(dst + n * RUNE) = relu_pack<E>(l1, row_in && x >= 0 && x < W, ovf);
-        }
+          for (int n = 0; n < RPW; ++n) {
+            const int c0 = col0 + 16 * n + lr;  // column of tap dx = 0
+            const uint4 u = rec[16 * n];
+            V8 bf;
+            __builtin_memcpy(&bf, &u, 16);
+            f32x4_t l1[2];
+            l1[0] = Elem<E>::mma(w10, bf, b10);
+            l1[1] = Elem<E>::mma(w11, bf, b11);
+            const int x = X + c0;
+            *(V8*)(dst + n * RUNE) =
+                relu_pack<E, CHK == CHECK_ALL>(l1, row_in && x >= 0 && x < W, ovf);
+          }
+        };
+        layer1();
       }
       // ---- input stage (waves NW..2NW-1): row A+t into slot t % 4
       if (role == 1) {
@@ -456,11 +515,21 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
           const int Lx = 64 * (HPW * part + h) + ln, xin = X + Lx;
           const bool xin_ok = xin >= 0 && xin < W;
           const float cval = cin[h];
+
           float zval = 0.f;
           if (xin_ok && ri >= 0 && ri < H) zval = hs_noise(seed, (uint64_t)ri * W + xin, 0u, a.kind);
           const V2 cz = __builtin_convertvector((f32x2_t){cval, zval}, V2);
           uint32_t u;
           __builtin_memcpy(&u, &cz, 4);
+          if constexpr (CHK == CHECK_L5) {
+            // the contone range the layer bounds assume: c in [0, 1], i.e. FP16
+            // bits at most 0x3C00 (negative c sets bit 15); adding 0x3FFF with
+            // saturation reaches 0x7C00 exactly when c lies outside
+            const uint32_t hi = u << 16;  // c into the upper half, 0 below
+            u16x2_t cv;
+            __builtin_memcpy(&cv, &hi, 4);
+            ovf = __builtin_elementwise_max(ovf, __builtin_elementwise_add_sat(cv, (u16x2_t){0, 0x3FFF}));
+          }
           // column j = Lx + 1 is element e of the record of column j - e
           uint32_t* rrow = inring + (t & 3) * RWID * 4;
           rrow[(Lx + 1) * 4] = u;
@@ -476,9 +545,10 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
       step(t + 2, StepIndex<2>{});
     }
   }
-  if constexpr (Elem<E>::kRangeCheck) {
+  if constexpr (CHK != CHECK_NONE) {
     // a packed half at or above 0x7C00 is inf or NaN; no wave reads the flag
-    if (__ballot(ovf[0] >= 0x7C00 || ovf[1] >= 0x7C00) && lane == 0 && a.ovf) *a.ovf = 1;
+    const bool bad = ovf[0] >= 0x7C00 || ovf[1] >= 0x7C00;
+    if (__ballot(bad) && lane == 0 && a.ovf) *a.ovf = 1;
   }
   // recheck list: the output stage's 64-pixel halves each own a segment
   if (role == 2 && lane == 0 && a.seg_count) {
@@ -519,8 +589,9 @@ namespace hs {
 
 size_t fused_frag_bytes() { return (size_t)FRAG_TOTAL * 16; }
 
-hipError_t launch_fused_pack(const float* w, void* frags, void* frags16, hipStream_t s) {
-  pack_fused_kernel<<<38, 256, 0, s>>>(w, (__bf16*)frags, (_Float16*)frags16);
+hipError_t launch_fused_pack(const float* w, void* frags, void* frags16, int* needs_all,
+                             hipStream_t s) {
+  pack_fused_kernel<<<38, 256, 0, s>>>(w, (__bf16*)frags, (_Float16*)frags16, needs_all);
   return hipGetLastError();
 }
 
@@ -578,14 +649,15 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
                               const Page* pages, const int* shapes_host, int npages, int kind,
                               float tau, const Levels& lv, uint8_t* bits, float* logits,
                               uint64_t* list, int* seg_count, int* nseg, long long* seg_cap,
-                              const void* frags, bool fp16, int* ovf, const int* guard,
-                              int num_cus, hipStream_t s) {
+                              const void* frags, int form, int* ovf, const int* guard,
+                              int guard_nonzero, int num_cus, hipStream_t s) {
   FusedArgs a;
   a.contone = contone;
   a.seeds = seeds;
   a.frags = frags;
   a.ovf = ovf;
   a.guard = guard;
+  a.guard_nonzero = guard_nonzero;
   a.w = w;
   a.pages = pages;
   a.npages = npages;
@@ -604,12 +676,16 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
   *seg_cap = a.seg_cap;
   const bool binary = lv.n == 1 && lv.thr[0] == 0.0f;
   const dim3 block(64 * 4 * FUSED_NW);
-  if (fp16) {
-    if (binary) fused_infer_kernel<FUSED_NW, false, _Float16><<<grid, block, 0, s>>>(a);
-    else fused_infer_kernel<FUSED_NW, true, _Float16><<<grid, block, 0, s>>>(a);
+  constexpr int N = FUSED_NW;
+  if (form == FUSED_FP16_L5) {
+    if (binary) fused_infer_kernel<N, false, _Float16, CHECK_L5><<<grid, block, 0, s>>>(a);
+    else fused_infer_kernel<N, true, _Float16, CHECK_L5><<<grid, block, 0, s>>>(a);
+  } else if (form == FUSED_FP16_ALL) {
+    if (binary) fused_infer_kernel<N, false, _Float16, CHECK_ALL><<<grid, block, 0, s>>>(a);
+    else fused_infer_kernel<N, true, _Float16, CHECK_ALL><<<grid, block, 0, s>>>(a);
   } else {
-    if (binary) fused_infer_kernel<FUSED_NW, false, __bf16><<<grid, block, 0, s>>>(a);
-    else fused_infer_kernel<FUSED_NW, true, __bf16><<<grid, block, 0, s>>>(a);
+    if (binary) fused_infer_kernel<N, false, __bf16, CHECK_NONE><<<grid, block, 0, s>>>(a);
+    else fused_infer_kernel<N, true, __bf16, CHECK_NONE><<<grid, block, 0, s>>>(a);
   }
   return hipGetLastError();
 }

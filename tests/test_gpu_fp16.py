@@ -114,6 +114,45 @@ def test_fp16_overflow_reruns_in_bf16(orc):
     assert st2.cpu().numpy()[3] == 0
 
 
+def test_fp16_form_that_tests_every_layer(orc):
+    """Layer 1 scaled by 2^12 (layer 2 by 2^-12): its a priori bound passes
+    FP16's range, so the form that tests every layer runs; its activations
+    (at most a few times 2^12) still fit, so it decides, to the oracle."""
+    B, H, W = 1, 64, 130
+    seeds = [61]
+    _say("infer fp16, every layer tested")
+    w, c = inputs(seeds, H, W)
+    ws = _scaled(w, 2.0 ** 12)
+    ref = _oracle_logits(orc, ws, c, seeds)
+    bits, lg, st = hb.halftone_infer(to_dev(ws), to_dev(c), seeds_t(seeds), 0, hb.HS_FP16,
+                                     logits=True, stats=True)
+    bits, lg, st = bits.cpu().numpy(), lg.cpu().numpy(), st.cpu().numpy()
+    assert st[3] == 0
+    m = parity_mask(orc, ref)
+    assert np.array_equal(bits[m], (ref >= 0)[m].astype(np.uint8))
+    assert np.abs(lg - ref).max() < TAU16
+
+
+def test_fp16_contone_outside_the_unit_range_reruns_in_bf16():
+    """The layer bounds assume contones in [0, 1]; a page with values
+    outside is decided by the BF16 pass, bit for bit as a BF16 call with
+    the 8 times wider band."""
+    B, H, W = 2, 50, 90
+    seeds = [71, 72]
+    _say("infer fp16, contone outside [0, 1]")
+    w, c = inputs(seeds, H, W)
+    for bad in (1.25, -0.5):
+        cb = c.copy()
+        cb[1, 20, 33] = bad
+        ct, st = to_dev(cb), seeds_t(seeds)
+        bits, lg, stats = hb.halftone_infer(to_dev(w), ct, st, 0, hb.HS_FP16, logits=True,
+                                            stats=True)
+        rb, rl = hb.halftone_infer(to_dev(w), ct, st, 0, hb.HS_BF16, 8 * TAU16, logits=True)
+        assert stats.cpu().numpy()[3] == 1, bad
+        assert np.array_equal(bits.cpu().numpy(), rb.cpu().numpy())
+        assert np.array_equal(lg.cpu().numpy(), rl.cpu().numpy())
+
+
 def test_fp16_pages_and_levels(orc):
     """Uneven pages in one launch, binary and with 4 levels."""
     pages = [(37, 200), (130, 129), (5, 300)]
