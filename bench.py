@@ -155,24 +155,31 @@ def bench_pages(hb, synth, torch, dev, wt, steps, tau):
         len(shapes), sh.ctypes.data_as(hb.ctypes.c_void_p), hb.HS_BF16), dtype=torch.uint8,
         device=dev)
 
-    def run(stats=False, levels=None):
-        return hb.halftone_infer_pages(wt, flat, st, shapes, precision=hb.HS_BF16,
-                                       recheck_tau=tau, stats=stats, workspace=ws,
-                                       levels=levels)
+    def run(stats=False, levels=None, prec=hb.HS_BF16):
+        return hb.halftone_infer_pages(wt, flat, st, shapes, precision=prec,
+                                       recheck_tau=tau if prec == hb.HS_BF16 else None,
+                                       stats=stats, workspace=ws, levels=levels)
 
-    def timed(levels):
-        run(levels=levels)
+    def timed(levels, prec=hb.HS_BF16):
+        run(levels=levels, prec=prec)
         torch.cuda.synchronize()
         hb.halftone_profile_start()
         t0 = time.perf_counter()
         for _ in range(steps):
-            run(levels=levels)
+            run(levels=levels, prec=prec)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         kern_ms, launches = hb.halftone_profile_stop()
         kern_s = kern_ms / 1e3 / max(launches, 1)
-        _, stats = run(stats=True, levels=levels)
+        _, stats = run(stats=True, levels=levels, prec=prec)
         return dt, kern_s, stats.cpu().tolist()
+
+    def line(dt, kern_s, stats):
+        return {"value": round(npx / dt / 1e6, 1), "unit": "Mpx/s",
+                "ms_per_call": round(dt * 1e3, 3), "fused_kernel_ms": round(kern_s * 1e3, 3),
+                "fused_mfma_frac": round(FLOP_PER_PX * npx / kern_s / 1e12 / PEAK_BF16_TFLOPS, 4),
+                "rechecked": stats[0], "fp32_recomputed": stats[2],
+                "recheck_fraction": round(stats[0] / npx, 6)}
 
     dt, kern_s, stats = timed(None)
     ach = FLOP_PER_PX * npx / kern_s / 1e12
@@ -180,6 +187,10 @@ def bench_pages(hb, synth, torch, dev, wt, steps, tau):
     # the 4-level multitoning variant (Sec. VII) on the same pages
     mdt, mkern_s, mstats = timed(4)
     log("pages, 4 levels: %.3f ms, %.1f Mpx/s" % (mdt * 1e3, npx / mdt / 1e6))
+    # both with the FP16 fused pass
+    h = line(*timed(None, hb.HS_FP16))
+    h["multitone4"] = line(*timed(4, hb.HS_FP16))
+    log("pages, fp16: %.1f Mpx/s; 4 levels %.1f Mpx/s" % (h["value"], h["multitone4"]["value"]))
     return {"value": round(npx / dt / 1e6, 1), "unit": "Mpx/s", "pages": len(shapes),
             "mpx": round(npx / 1e6, 2), "ms_per_call": round(dt * 1e3, 3),
             "fused_kernel_ms": round(kern_s * 1e3, 3), "fused_tflops": round(ach, 1),
@@ -192,7 +203,8 @@ def bench_pages(hb, synth, torch, dev, wt, steps, tau):
                            "fused_mfma_frac": round(FLOP_PER_PX * npx / mkern_s / 1e12 /
                                                     PEAK_BF16_TFLOPS, 4),
                            "rechecked": mstats[0], "fp32_recomputed": mstats[2],
-                           "recheck_fraction": round(mstats[0] / npx, 6)}}
+                           "recheck_fraction": round(mstats[0] / npx, 6)},
+            "fp16": h}
 
 
 def calibrate(hb, synth, torch, dev):
@@ -333,7 +345,9 @@ def main():
     def step16():
         return hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_FP16, tau16, workspace=ws)
 
-    for _ in range(10):
+    # the clock drops in the host synchronisations of the stats call above
+    # and takes some tens of calls to recover, as at the start
+    for _ in range(args.warmup):
         step16()
     torch.cuda.synchronize()
     hb.halftone_profile_start()
