@@ -133,7 +133,7 @@ int64_t halftone_param_count(void);
  *          with split-BF16 products (hi*hi + lo*hi + hi*lo, FP32
  *          accumulation, about 2^-8 of the BF16 error), and every pixel
  *          whose recomputed |x| is still below tau2 = recheck_tau/64 clamped
- *          to [5e-4, 1e-2] is recomputed once more in FP32 and decided from that
+ *          to [1.5e-4, 1e-2] is recomputed once more in FP32 and decided from that
  *          value (recheck_tau >= 0; it must exceed the largest BF16 logit
  *          error for the bits to equal FP32's off-margin).
  *          HS_FP16: the same with FP16 in place of BF16 in the fused pass

@@ -426,31 +426,25 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
         const int rs = A + t + 1 - 3 * k;
         const bool row_in = rs >= 0 && rs < H;
         E* dst = ring + ((size_t)(k - 1) * 2 + cur) * ROWE + woff;
-        auto store = [&]() {
 #pragma unroll
-          for (int n = 0; n < RPW; ++n) {
-            const int x = X + col0 + 16 * n + lr;
-            const bool in = row_in && (cols_inside || (x >= 0 && x < W));
-            *(V8*)(dst + n * RUNE) = relu_pack<E, CHK == CHECK_ALL>(S[J][n], in, ovf);
-          }
-        };
-        store();
+        for (int n = 0; n < RPW; ++n) {
+          const int x = X + col0 + 16 * n + lr;
+          const bool in = row_in && (cols_inside || (x >= 0 && x < W));
+          *(V8*)(dst + n * RUNE) = relu_pack<E, CHK == CHECK_ALL>(S[J][n], in, ovf);
+        }
       } else {  // layer 5: the nine layer-6 taps of row rs into the T ring
         const int rs = A + t - 14;
         const bool row_in = rs >= 0 && rs < H;
         float* trow = tring + (size_t)cur * RWID * 12;
         const V8 w6 = cfrag[128 + ln];
-        auto taps = [&]() {
 #pragma unroll
-          for (int n = 0; n < RPW; ++n) {
-            const int c = col0 + 16 * n + lr, x = X + c;
-            const bool in = row_in && (cols_inside || (x >= 0 && x < W));
-            const f32x4_t tv = Elem<E>::mma(
-                w6, relu_pack<E, CHK != CHECK_NONE>(S[J][n], in, ovf), f32x4_t{0.f, 0.f, 0.f, 0.f});
-            if (lg < 3) *(f32x4_t*)(trow + (c + 1) * 12 + 4 * lg) = tv;
-          }
-        };
-        taps();
+        for (int n = 0; n < RPW; ++n) {
+          const int c = col0 + 16 * n + lr, x = X + c;
+          const bool in = row_in && (cols_inside || (x >= 0 && x < W));
+          const f32x4_t tv = Elem<E>::mma(
+              w6, relu_pack<E, CHK != CHECK_NONE>(S[J][n], in, ovf), f32x4_t{0.f, 0.f, 0.f, 0.f});
+          if (lg < 3) *(f32x4_t*)(trow + (c + 1) * 12 + 4 * lg) = tv;
+        }
       }
       {
         const f32x4_t bk0 = *(const f32x4_t*)(cbias + 32 * (k - 1) + 4 * lg);
@@ -505,7 +499,26 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
                 relu_pack<E, CHK == CHECK_ALL>(l1, row_in && x >= 0 && x < W, ovf);
           }
         };
-        layer1();
+        // the same loop, spelled inline for the multitone forms and as a lambda
+        // for the binary ones: with these spellings neither form's step loop
+        // spills registers (each spelling spills in the other form)
+        if constexpr (MULTI) {
+#pragma unroll
+          for (int n = 0; n < RPW; ++n) {
+            const int c0 = col0 + 16 * n + lr;  // column of tap dx = 0
+            const uint4 u = rec[16 * n];
+            V8 bf;
+            __builtin_memcpy(&bf, &u, 16);
+            f32x4_t l1[2];
+            l1[0] = Elem<E>::mma(w10, bf, b10);
+            l1[1] = Elem<E>::mma(w11, bf, b11);
+            const int x = X + c0;
+            *(V8*)(dst + n * RUNE) =
+                relu_pack<E, CHK == CHECK_ALL>(l1, row_in && x >= 0 && x < W, ovf);
+          }
+        } else {
+          layer1();
+        }
       }
       // ---- input stage (waves NW..2NW-1): row A+t into slot t % 4
       if (role == 1) {

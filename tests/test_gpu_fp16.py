@@ -42,7 +42,7 @@ def test_fp16_with_recheck_matches_oracle(orc, shape):
     assert np.array_equal(bits[m], (ref >= 0)[m].astype(np.uint8))
     near = np.abs(lg) < TAU16
     assert np.abs(lg[near] - ref[near]).max(initial=0.0) <= 5e-4
-    nearer = np.abs(lg) < 5e-4  # tau2 = clamp(tau / 64, 5e-4, 1e-2)
+    nearer = np.abs(lg) < 1.5e-4  # tau2 = clamp(tau / 64, 1.5e-4, 1e-2)
     assert np.abs(lg[nearer] - ref[nearer]).max(initial=0.0) <= 2e-5 * max(1.0, np.abs(ref).max())
     assert np.abs(lg - ref).max() < TAU16
     assert st[0] >= near.sum() and 0 <= st[1] <= st[0] and 0 <= st[2] <= st[0]
@@ -89,7 +89,9 @@ def test_fp16_overflow_reruns_in_bf16(orc):
     """With layer-1 activations scaled by 2^16 the FP16 pass overflows; the
     call then decides every pixel from the BF16 pass with an 8 times wider
     band. Power-of-two scaling is exact in BF16 and FP32, so the result
-    equals the unscaled network's BF16 result bit for bit."""
+    equals the unscaled network's BF16 result bit for bit, except that the
+    split stage keeps the FP16 call's tau2 (clamp(tau / 64, 1.5e-4, 1e-2)),
+    so pixels between the two tau2 are decided by different stages."""
     B, H, W = 2, 40, 150
     seeds = [41, 42]
     _say("infer fp16 overflow re-run")
@@ -103,9 +105,12 @@ def test_fp16_overflow_reruns_in_bf16(orc):
                                                     8 * TAU16, logits=True, stats=True)
     stats, ref_stats = stats.cpu().numpy(), ref_stats.cpu().numpy()
     assert stats[3] == 1 and ref_stats[3] == 0
-    assert np.array_equal(stats[:3], ref_stats[:3])
-    assert np.array_equal(bits.cpu().numpy(), ref_bits.cpu().numpy())
-    assert np.array_equal(lg.cpu().numpy(), ref_lg.cpu().numpy())
+    assert stats[0] == ref_stats[0]  # the same BF16 list (band 8 tau)
+    lg, ref_lg = lg.cpu().numpy(), ref_lg.cpu().numpy()
+    same = np.abs(ref_lg) >= max(8 * TAU16 / 64, 1.5e-4)  # the larger tau2
+    assert np.array_equal(bits.cpu().numpy()[same], ref_bits.cpu().numpy()[same])
+    assert np.array_equal(lg[same], ref_lg[same])
+    assert np.abs(lg - ref_lg).max() <= 5e-4
     ref = _oracle_logits(orc, w, c, seeds)
     m = parity_mask(orc, ref)
     assert np.array_equal(bits.cpu().numpy()[m], (ref >= 0)[m].astype(np.uint8))
@@ -136,7 +141,7 @@ def test_fp16_form_that_tests_every_layer(orc):
 def test_fp16_contone_outside_the_unit_range_reruns_in_bf16():
     """The layer bounds assume contones in [0, 1]; a page with values
     outside is decided by the BF16 pass, bit for bit as a BF16 call with
-    the 8 times wider band."""
+    the 8 times wider band wherever both calls' split stages decide."""
     B, H, W = 2, 50, 90
     seeds = [71, 72]
     _say("infer fp16, contone outside [0, 1]")
@@ -149,8 +154,11 @@ def test_fp16_contone_outside_the_unit_range_reruns_in_bf16():
                                             stats=True)
         rb, rl = hb.halftone_infer(to_dev(w), ct, st, 0, hb.HS_BF16, 8 * TAU16, logits=True)
         assert stats.cpu().numpy()[3] == 1, bad
-        assert np.array_equal(bits.cpu().numpy(), rb.cpu().numpy())
-        assert np.array_equal(lg.cpu().numpy(), rl.cpu().numpy())
+        lg, rl = lg.cpu().numpy(), rl.cpu().numpy()
+        same = np.abs(rl) >= max(8 * TAU16 / 64, 1.5e-4)  # split-stage decisions in both
+        assert np.array_equal(bits.cpu().numpy()[same], rb.cpu().numpy()[same])
+        assert np.array_equal(lg[same], rl[same])
+        assert np.abs(lg - rl).max() <= 5e-4
 
 
 def test_fp16_pages_and_levels(orc):
