@@ -412,10 +412,10 @@ static int infer_bf16(const float* weights, const float* contone, const uint64_t
   Bf16Ws w;
   bf16_ws(shapes, npages, N, &w, workspace);
   int32_t* stats = stats_or_null ? stats_or_null : (int32_t*)(w.cnt + 8);
-  HS_TRY(launch_zero_ints(w.cnt, 16, s));
-  if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
+  // counters cleared and the uniform page table written by the packing launch
+  PackPrologue pro{w.cnt, 16, stats_or_null, stats_or_null ? 4 : 0,
+                   pages_host ? nullptr : w.pages, npages, shapes[0], shapes[1]};
   if (pages_host) HS_TRY(launch_put_pages(w.pages, pages_host, npages, s));
-  else HS_TRY(launch_uniform_pages(w.pages, npages, shapes[0], shapes[1], s));
   // the split stage decides |x| >= tau2: its measured error (at most 5.9e-5)
   // stays under half the floor, and the floor under the 4e-4 margin
   const float tau2 = fminf(fmaxf(recheck_tau / 64.0f, 1.5e-4f), 1e-2f);
@@ -423,7 +423,7 @@ static int infer_bf16(const float* weights, const float* contone, const uint64_t
   char* wlo = whi + split_frag_bytes() / 2;
   char* wt = whi + split_frag_bytes();
   int* needs_all = w.cnt + 24;  // FP16: layers 1..4 not cleared by their bounds
-  HS_TRY(launch_fused_pack(weights, w.pack, fp16 ? w.pack16 : nullptr, needs_all, s));
+  HS_TRY(launch_fused_pack(weights, w.pack, fp16 ? w.pack16 : nullptr, needs_all, pro, s));
   HS_TRY(launch_split_pack(weights, whi, wlo, wt, s));
   int nseg = 0;
   long long seg_cap = 0;

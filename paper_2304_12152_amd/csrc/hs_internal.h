@@ -110,10 +110,21 @@ hipError_t launch_conv_last(const void* in, const float* w, int B, int H, int W,
 // infer.hip: the fused BF16 pass
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 size_t fused_frag_bytes();
+// Set-up folded into the fragment packing launch: zero0[0..n0) and
+// zero1[0..n1) cleared (null / 0 to skip), and when pages is set the page
+// table of a uniform batch of B images of H x W.
+struct PackPrologue {
+  int* zero0;
+  int n0;
+  int* zero1;
+  int n1;
+  Page* pages;
+  int B, H, W;
+};
 // BF16 fragments into frags and, when frags16 is not null, the same in FP16
 // and *needs_all: 1 unless a priori bounds keep FP16 layers 1..4 in range
 hipError_t launch_fused_pack(const float* w, void* frags, void* frags16, int* needs_all,
-                             hipStream_t s);
+                             const PackPrologue& pro, hipStream_t s);
 // persistent fused inference over pages (one launch for all of them;
 // shapes_host = [npages][H, W] as in the device page table); the recheck
 // list is segmented (two segments per workgroup, counts in seg_count; list

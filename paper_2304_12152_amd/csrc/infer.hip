@@ -92,6 +92,21 @@ constexpr float FP16_SAFE = 60000.0f;
 // |z| <= sqrt(48 ln 2) = 5.77; the uniform noise lies in [0, 1).
 constexpr float NOISE_MAX = 5.8f;
 
+// Page of a uniform batch: image b of B images of H x W.
+HS_DEV hs::Page uniform_page(int b, int H, int W) {
+  const int nstrip = (W + FS - 1) / FS;
+  hs::Page p;
+  p.off = (long long)b * H * W;
+  p.vstart = (long long)b * nstrip * (H + FILL);
+  p.H = H;
+  p.W = W;
+  p.nstrip = nstrip;
+  p.pad = 0;
+  return p;
+}
+
+// The call's other set-up in the same launch: counters to clear and, for a
+// uniform batch, the page table (one kernel instead of three).
 // out: BF16 fragments; out16 (may be null): the same fragments in FP16, and
 // then *needs_all = 1 unless a priori bounds keep layers 1..4 inside FP16's
 // range. With contones in [0, 1] (which the FP16 pass verifies) every
@@ -99,7 +114,13 @@ constexpr float NOISE_MAX = 5.8f;
 // most the sum over its inputs of max(w, 0) times the input's bound, plus the
 // bias (layer 1 takes |w| for the noise channel).
 __global__ void pack_fused_kernel(const float* __restrict__ w, __bf16* __restrict__ out,
-                                  _Float16* __restrict__ out16, int* __restrict__ needs_all) {
+                                  _Float16* __restrict__ out16, int* __restrict__ needs_all,
+                                  const hs::PackPrologue pro) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < pro.n0) pro.zero0[gid] = 0;
+  if (gid < pro.n1) pro.zero1[gid] = 0;
+  if (pro.pages)
+    for (int b = gid; b < pro.B; b += gridDim.x * blockDim.x) pro.pages[b] = uniform_page(b, pro.H, pro.W);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < FRAG_TOTAL * 8;
        i += gridDim.x * blockDim.x) {
     const int f = i >> 3, e = i & 7;
@@ -584,16 +605,7 @@ __global__ void put_pages_kernel(hs::Page* pages, PageChunk c) {
 // Pages of a uniform batch: B images of H x W.
 __global__ void uniform_pages_kernel(hs::Page* pages, int B, int H, int W) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  const int nstrip = (W + FS - 1) / FS;
-  hs::Page p;
-  p.off = (long long)b * H * W;
-  p.vstart = (long long)b * nstrip * (H + FILL);
-  p.H = H;
-  p.W = W;
-  p.nstrip = nstrip;
-  p.pad = 0;
-  pages[b] = p;
+  if (b < B) pages[b] = uniform_page(b, H, W);
 }
 
 }  // namespace
@@ -603,8 +615,8 @@ namespace hs {
 size_t fused_frag_bytes() { return (size_t)FRAG_TOTAL * 16; }
 
 hipError_t launch_fused_pack(const float* w, void* frags, void* frags16, int* needs_all,
-                             hipStream_t s) {
-  pack_fused_kernel<<<38, 256, 0, s>>>(w, (__bf16*)frags, (_Float16*)frags16, needs_all);
+                             const PackPrologue& pro, hipStream_t s) {
+  pack_fused_kernel<<<38, 256, 0, s>>>(w, (__bf16*)frags, (_Float16*)frags16, needs_all, pro);
   return hipGetLastError();
 }
 

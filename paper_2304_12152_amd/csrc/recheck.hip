@@ -66,19 +66,18 @@ static_assert(win_runs(1) == 8 && win_runs(2) == 6 && win_runs(3) == 4 && win_ru
                   win_runs(5) == 1,
               "wave roles assume these run counts");
 
-__global__ void pack_split_kernel(const float* __restrict__ w, __bf16* __restrict__ hi,
-                                  __bf16* __restrict__ lo) {
-  // layers 2..5 in the ring channel order: [layer][tap][m][lane][8]
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 4 * 9 * 2 * 64 * 8;
-       i += gridDim.x * blockDim.x) {
-    const int e = i & 7, l = (i >> 3) & 63, m = (i >> 9) & 1, t = (i >> 10) % 9,
-              layer = (i >> 10) / 9;
-    const int g = l >> 4, r = l & 15;
-    const float v = w[hs_wk(layer + 2) + ((16 * m + r) * 32 + hs_ring_channel(g, e)) * 9 + t];
-    const __bf16 h = (__bf16)v;
-    hi[i] = h;
-    lo[i] = (__bf16)(v - (float)h);
-  }
+// element i of the split fragments: layers 2..5 in the ring channel order,
+// [layer][tap][m][lane][8]
+constexpr int SPLIT_ELEMS = 4 * 9 * 2 * 64 * 8;
+HS_DEV void pack_split_elem(const float* __restrict__ w, __bf16* __restrict__ hi,
+                            __bf16* __restrict__ lo, int i) {
+  const int e = i & 7, l = (i >> 3) & 63, m = (i >> 9) & 1, t = (i >> 10) % 9,
+            layer = (i >> 10) / 9;
+  const int g = l >> 4, r = l & 15;
+  const float v = w[hs_wk(layer + 2) + ((16 * m + r) * 32 + hs_ring_channel(g, e)) * 9 + t];
+  const __bf16 h = (__bf16)v;
+  hi[i] = h;
+  lo[i] = (__bf16)(v - (float)h);
 }
 
 struct SplitArgs {
@@ -503,14 +502,21 @@ constexpr int F32_THREADS = 256;
 constexpr int F32_LAYER = 9 * 32 * 32;                // weights of one 32 -> 32 layer
 constexpr int F32_VPT = F32_LAYER / 4 / F32_THREADS;  // 16-byte vectors per thread per layer
 
-// layers 2..5 as [layer][tap][ci][co] FP32, so a thread's four output
-// channels are one 16-byte read
-__global__ void pack_fp32_kernel(const float* __restrict__ w, float* __restrict__ out) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 4 * F32_LAYER;
+// element i of layers 2..5 as [layer][tap][ci][co] FP32, so a thread's four
+// output channels are one 16-byte read
+HS_DEV void pack_fp32_elem(const float* __restrict__ w, float* __restrict__ out, int i) {
+  const int layer = i / F32_LAYER, rem = i - layer * F32_LAYER;
+  const int t = rem / 1024, ci = (rem >> 5) & 31, co = rem & 31;
+  out[i] = w[hs_wk(layer + 2) + (co * 32 + ci) * 9 + t];
+}
+
+// both weight copies of the recheck stages in one launch
+__global__ void pack_recheck_kernel(const float* __restrict__ w, __bf16* __restrict__ hi,
+                                    __bf16* __restrict__ lo, float* __restrict__ wt) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < SPLIT_ELEMS + 4 * F32_LAYER;
        i += gridDim.x * blockDim.x) {
-    const int layer = i / F32_LAYER, rem = i - layer * F32_LAYER;
-    const int t = rem / 1024, ci = (rem >> 5) & 31, co = rem & 31;
-    out[i] = w[hs_wk(layer + 2) + (co * 32 + ci) * 9 + t];
+    if (i < SPLIT_ELEMS) pack_split_elem(w, hi, lo, i);
+    else pack_fp32_elem(w, wt, i - SPLIT_ELEMS);
   }
 }
 
@@ -666,8 +672,7 @@ size_t split_frag_bytes() { return 2 * (size_t)(4 * 9 * 2 * 64 * 8) * sizeof(__b
 size_t fp32_pack_bytes() { return (size_t)4 * F32_LAYER * sizeof(float); }
 
 hipError_t launch_split_pack(const float* w, void* whi, void* wlo, void* wt, hipStream_t s) {
-  pack_split_kernel<<<36, 256, 0, s>>>(w, (__bf16*)whi, (__bf16*)wlo);
-  pack_fp32_kernel<<<36, 256, 0, s>>>(w, (float*)wt);
+  pack_recheck_kernel<<<72, 256, 0, s>>>(w, (__bf16*)whi, (__bf16*)wlo, (float*)wt);
   return hipGetLastError();
 }
 
