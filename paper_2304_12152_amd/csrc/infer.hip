@@ -3,9 +3,10 @@
 // logit thresholded at 0 (p = 0.5) and the near-threshold pixels listed for
 // the recheck stages (recheck.hip). FP16 has 11 significant bits to BF16's 8
 // at the same matrix-core rate, so its logit error and recheck band are about
-// 8 times smaller; its range ends at 65504, so the FP16 pass records whether
-// any activation overflowed, and a BF16 launch that does nothing otherwise
-// then redoes the pass.
+// 8 times smaller; its range ends at 65504, so the FP16 pass tests the
+// activations it stores (only layer 5's and the contone range when a priori
+// bounds clear layers 1..4) and records an overflow, and a BF16 launch that
+// does nothing otherwise then redoes the pass.
 #include "hs_common.h"
 #include "hs_internal.h"
 
