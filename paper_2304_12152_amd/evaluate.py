@@ -16,7 +16,9 @@ averaged power and the anisotropy per ring. Reported per method and gray:
   anis_mean_db the mean of anis_db over those rings;
   low_power   the share of the AC power in rings below the principal
               frequency sqrt(min(g, 1 - g)) (in cycles per pixel, times P);
-  policy only: logit_hist, the fraction of pixels whose logit magnitude
+  policy only: recheck_tau, the recheck band measured for the weights on two
+              of the gray's pages (`calibrate.recheck_tau`); logit_hist,
+              the fraction of pixels whose logit magnitude
               |x| falls in the decades [0, 1e-4), [1e-4, 1e-3), ...,
               [10, inf) -- a bimodal policy keeps almost all of them in the
               top decades -- and recheck / fp32, the fractions the BF16
@@ -40,6 +42,7 @@ import sys
 
 import numpy as np
 
+from . import calibrate
 from . import synth
 
 GRAYS = (15, 80, 100, 127)
@@ -98,13 +101,17 @@ def bluenoise(weights, grays=GRAYS, B=8, H=512, W=512, P=64, precision=None, wit
         g = gi / 255.0
         c = torch.full((B, H, W), g, dtype=torch.float32, device=dev)
         s = torch.arange(seed + B * gi, seed + B * gi + B, dtype=torch.int64, device=dev)
+        # the recheck band for these weights, measured on two of the pages
+        tau = (calibrate.recheck_tau(w, prec, c[:2], s[:2].tolist())
+               if prec != hb.HS_FP32 else 0.0)
         if levels > 2:
             bits, x, st = hb.halftone_infer_pages(w, c.reshape(-1), s, [(H, W)] * B,
-                                                  precision=prec, logits=True, stats=True,
-                                                  levels=levels)
+                                                  precision=prec, recheck_tau=tau, logits=True,
+                                                  stats=True, levels=levels)
             bits, x = bits.view(B, H, W), x.view(B, H, W)
         else:
-            bits, x, st = hb.halftone_infer(w, c, s, precision=prec, logits=True, stats=True)
+            bits, x, st = hb.halftone_infer(w, c, s, precision=prec, recheck_tau=tau, logits=True,
+                                            stats=True)
         rec = {"policy": _summary(bits, c, g, P, hb, levels)}
         n = float(B * H * W)
         edges = torch.tensor(LOGIT_DECADES, dtype=torch.float32, device=dev)
@@ -116,6 +123,7 @@ def bluenoise(weights, grays=GRAYS, B=8, H=512, W=512, P=64, precision=None, wit
             t = torch.sigmoid(x.double()) * (levels - 1)
             rec["policy"]["near_level"] = float(((t - t.round()).abs() < 0.1).double().mean())
         st = st.cpu().numpy()
+        rec["policy"]["recheck_tau"] = tau
         rec["policy"]["recheck"] = float(st[0]) / n
         rec["policy"]["fp32"] = float(st[2]) / n
         if with_fs:
