@@ -135,7 +135,10 @@ int64_t halftone_param_count(void);
  *          whose recomputed |x| is still below tau2 = recheck_tau/64 clamped
  *          to [1.5e-4, 1e-2] is recomputed once more in FP32 and decided from that
  *          value (recheck_tau >= 0; it must exceed the largest BF16 logit
- *          error for the bits to equal FP32's off-margin).
+ *          error for the bits to equal FP32's off-margin). That error
+ *          depends on the weights (0.042 for a He-initialised policy, 4.5
+ *          for a trained one on the same images): measure it by comparing
+ *          the logits of a call with recheck_tau = 0 against HS_FP32's.
  *          HS_FP16: the same with FP16 in place of BF16 in the fused pass
  *          (unit roundoff 2^-11 instead of 2^-8, so recheck_tau can be
  *          about 8 times smaller); FP16 holds at most 65504, and if any
