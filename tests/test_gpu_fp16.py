@@ -191,3 +191,31 @@ def test_fp16_pages_and_levels(orc):
         m = parity_mask(orc, ref).ravel()
         assert np.array_equal(o[m], (ref.ravel() >= 0)[m].astype(np.uint8))
         off += h * ww
+
+
+def test_fp16_overflow_reruns_in_bf16_with_levels(orc):
+    """The same re-run for the multitoning call (4 levels): the FP16 pass of
+    the 2^16-scaled network overflows, and the levels equal a BF16 call's on
+    the unscaled network wherever both calls' split stages decide."""
+    pages = [(40, 150), (33, 70)]
+    seeds = [81, 82]
+    _say("infer fp16 overflow re-run, 4 levels")
+    w = inputs([0], 1, 1)[0]
+    from paper_2304_12152_amd import synth
+    flat = np.concatenate([synth.contone_batch([s], h, ww)[0].ravel()
+                           for s, (h, ww) in zip(seeds, pages)]).astype(np.float32)
+    ft, st = to_dev(flat), seeds_t(seeds)
+    out, lg, stats = hb.halftone_infer_pages(to_dev(_scaled(w, 2.0 ** 16)), ft, st, pages,
+                                             precision=hb.HS_FP16, logits=True, stats=True,
+                                             levels=4)
+    ref, rl, rst = hb.halftone_infer_pages(to_dev(w), ft, st, pages, precision=hb.HS_BF16,
+                                           recheck_tau=8 * TAU16, logits=True, stats=True,
+                                           levels=4)
+    stats, rst = stats.cpu().numpy(), rst.cpu().numpy()
+    assert stats[3] == 1 and rst[3] == 0 and stats[0] == rst[0]
+    lg, rl = lg.cpu().numpy(), rl.cpu().numpy()
+    thr = np.log(np.array([1.0, 3.0, 5.0]) / np.array([5.0, 3.0, 1.0]))
+    dist = np.min(np.abs(rl[:, None] - thr[None, :]), axis=1)
+    same = dist >= max(8 * TAU16 / 64, 1.5e-4)
+    assert np.array_equal(out.cpu().numpy()[same], ref.cpu().numpy()[same])
+    assert np.array_equal(lg[same], rl[same])
