@@ -3,7 +3,9 @@ halftones (Sec. IV, Eqs. psd, rapsd, anis; the paper's spectral figure
 shows the grays 15, 80, 100 and 127 of 255).
 
 For every gray g a batch of B constant pages of H x W is halftoned by the
-policy (Alg. 1 TEST, `halftone_infer`) and by Floyd-Steinberg error
+policy (Alg. 1 TEST, `halftone_infer`, in the cheapest exact-bit precision
+that `calibrate.plan` finds for the weights, with the band measured per
+gray) and by Floyd-Steinberg error
 diffusion; `halftone_spectrum` estimates the power spectrum as the mean
 periodogram of all P x P patches of the batch and reduces it to the radially
 averaged power and the anisotropy per ring. Reported per method and gray:
@@ -94,8 +96,10 @@ def bluenoise(weights, grays=GRAYS, B=8, H=512, W=512, P=64, precision=None, wit
     from . import binding as hb
     dev = torch.device("cuda", torch.cuda.current_device())
     w = torch.as_tensor(np.asarray(weights, dtype=np.float32)).to(dev)
-    prec = hb.HS_BF16 if precision is None else precision
-    out = {"P": P, "periodograms": B * (H // P) * (W // P), "pages": [B, H, W]}
+    # default: the cheapest exact-bit precision for these weights
+    prec = calibrate.plan(w)["precision"] if precision is None else precision
+    out = {"P": P, "periodograms": B * (H // P) * (W // P), "pages": [B, H, W],
+           "precision": {hb.HS_FP32: "fp32", hb.HS_BF16: "bf16", hb.HS_FP16: "fp16"}[prec]}
     out["floor_db"] = -10.0 * math.log10(out["periodograms"])
     for gi in grays:
         g = gi / 255.0

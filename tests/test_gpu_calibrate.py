@@ -56,3 +56,17 @@ def test_calibration_argument_errors():
     with pytest.raises(ValueError):
         calibrate.recheck_tau(to_dev(w), hb.HS_BF16,
                               contone=torch.zeros((1, 8, 8), device=device()))
+
+
+def test_plan_prices_the_options():
+    """For the He policy both 16-bit passes list well under the ~4% at which
+    the FP32 path would be cheaper; FP16 lists fewer and wins."""
+    _say("calibration plan")
+    w, _ = inputs([0], 1, 1)
+    p = calibrate.plan(to_dev(w))
+    o = p["options"]
+    assert set(o) == {hb.HS_FP32, hb.HS_BF16, hb.HS_FP16}
+    assert 0.0 < o[hb.HS_FP16]["listed"] < o[hb.HS_BF16]["listed"] < 0.02
+    assert p["precision"] == hb.HS_FP16
+    assert p["recheck_tau"] == o[hb.HS_FP16]["recheck_tau"] >= hb.RECHECK_TAU[hb.HS_FP16]
+    assert o[hb.HS_FP32]["ns_per_px"] > o[hb.HS_BF16]["ns_per_px"]
