@@ -184,7 +184,7 @@ def bench_pages(hb, synth, torch, dev, wt, steps, tau):
     dt, kern_s, stats = timed(None)
     ach = FLOP_PER_PX * npx / kern_s / 1e12
     log("pages: %.3f ms, %.1f Mpx/s" % (dt * 1e3, npx / dt / 1e6))
-    # the 4-level multitoning variant (Sec. VII) on the same pages
+    # the 4-level multitoning variant (Sec. VI-E) on the same pages
     mdt, mkern_s, mstats = timed(4)
     log("pages, 4 levels: %.3f ms, %.1f Mpx/s" % (mdt * 1e3, npx / mdt / 1e6))
     # both with the FP16 fused pass

@@ -69,8 +69,8 @@ extern "C" {
  * al. 2004 for L = 1), anisotropy patches of 32x32, the Local Expectation
  * estimator, 2 output levels (binary halftoning).
  *
- * levels > 2 selects the multitoning prototype of Sec. VII (Eq.
- * multitone): the network keeps its one sigmoid output v, the L levels are
+ * levels > 2 selects the multitoning prototype of Sec. VI-E (its
+ * unnumbered rounding equation): the network keeps its one sigmoid output v, the L levels are
  * k / (L-1), and agent a's two actions are the levels k_f and k_f + 1 around
  * v_a (k_f = min(floor(v_a (L-1)), L-2)), the upper one drawn with
  * probability v_a (L-1) - k_f. Actions are then level indices k (one byte,
@@ -184,7 +184,7 @@ int halftone_infer_pages(const float* weights, const float* contone, const uint6
                          void* stream);
 
 /* ---------------------------------------------------------------------
- * Multitoning inference (Sec. VII, the TEST phase with L output levels):
+ * Multitoning inference (Sec. VI-E, the TEST phase with L output levels):
  * the level nearest to v = sigmoid(x), a tie going up, i.e. the number of
  * thresholds logit((j + 1/2)/(L-1)), j = 0..L-2, that the logit x reaches
  * (levels = 2 is halftone_infer_pages exactly). Arguments as for
@@ -356,7 +356,7 @@ int halftone_spectrum(const uint8_t* bits, int B, int H, int W, int P, float* ra
 int halftone_error_diffusion_host(const float* contone_host, int B, int H, int W,
                                   uint8_t* bits_host);
 /* The same with L output levels k / (L-1), the serial fallback beside the
- * multitoning variant (Sec. VII): each pixel takes the level nearest to
+ * multitoning variant (Sec. VI-E): each pixel takes the level nearest to
  * v = c + diffused error (a tie going up, clamped to 0..L-1) and diffuses
  * v - k / (L-1) with the same weights; levels = 2 gives the bits of
  * halftone_error_diffusion_host. levels_host [B][H][W] level indices out;

@@ -20,6 +20,7 @@
  *     W[cout][cin][3][3] followed by bias[cout].
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -115,6 +116,56 @@ void or_bernoulli(const double* p, const uint64_t* seeds, int B, int H, int W,
 }
 
 /* ------------------------------------------------------------------------
+ * Optional threads, for speed only. or_set_threads(n) lets the channel loops
+ * of the conv stack (forward: output channels; backward: output channels for
+ * the weight gradient, input channels for the input gradient) run on n POSIX
+ * threads. Each thread owns whole output elements and adds their terms in the
+ * order of the serial loop, so every result is bit-identical for any n. The
+ * default is one thread.
+ * ---------------------------------------------------------------------- */
+static int g_threads = 1;
+
+void or_set_threads(int n) { g_threads = n < 1 ? 1 : (n > 256 ? 256 : n); }
+int or_get_threads(void) { return g_threads; }
+
+typedef void (*range_fn)(int lo, int hi, void* ctx);
+typedef struct { range_fn fn; void* ctx; int lo, hi; } range_job;
+
+static void* run_range(void* p) {
+  range_job* j = (range_job*)p;
+  j->fn(j->lo, j->hi, j->ctx);
+  return NULL;
+}
+
+/* fn over [0, n) split into contiguous ranges, one per thread; a range whose
+ * thread cannot be started runs on the calling thread */
+static void parallel_ranges(int n, range_fn fn, void* ctx) {
+  int T = g_threads < n ? g_threads : n;
+  if (T <= 1) {
+    fn(0, n, ctx);
+    return;
+  }
+  pthread_t* tid = (pthread_t*)malloc(sizeof(pthread_t) * T);
+  range_job* job = (range_job*)malloc(sizeof(range_job) * T);
+  int* started = (int*)calloc(T, sizeof(int));
+  for (int t = 0; t < T; ++t) {
+    job[t].fn = fn;
+    job[t].ctx = ctx;
+    job[t].lo = (int)((long)n * t / T);
+    job[t].hi = (int)((long)n * (t + 1) / T);
+    if (t > 0) started[t] = pthread_create(&tid[t], NULL, run_range, &job[t]) == 0;
+  }
+  fn(job[0].lo, job[0].hi, ctx);
+  for (int t = 1; t < T; ++t) {
+    if (started[t]) pthread_join(tid[t], NULL);
+    else fn(job[t].lo, job[t].hi, ctx);
+  }
+  free(tid);
+  free(job);
+  free(started);
+}
+
+/* ------------------------------------------------------------------------
  * Policy network (Sec. VI-A "Details of Our Method"; Sec. III "Agents"):
  * a fully convolutional stack of 3x3 convolutions, stride 1, zero 'same'
  * padding, with bias, ReLU after every layer but the last, and a pixel-wise
@@ -144,6 +195,45 @@ static region grow(region r, int m, int H, int W) {
   return g;
 }
 
+/* One conv layer of the stack, output channels [o0, o1): out[o](y, x) =
+ * b[o] + sum_{i, dy, dx} W[o][i][dy][dx] s_i(y + dy - 1, x + dx - 1), zero
+ * outside the image, then the ReLU (all layers but the last). `prev` holds
+ * the input on region prev_r (ph x pw), `cur` the output on region r. */
+typedef struct {
+  const double *Wk, *bk, *prev;
+  double* cur;
+  int ci_n, relu, H, W;
+  region r, prev_r;
+  int ph, pw;
+} conv_layer;
+
+static void conv_channels(int o0, int o1, void* ctx) {
+  const conv_layer* c = (const conv_layer*)ctx;
+  const double* Wk = c->Wk;
+  const double* bk = c->bk;
+  const double* prev = c->prev;
+  double* cur = c->cur;
+  const int ci_n = c->ci_n, H = c->H, W = c->W, ph = c->ph, pw = c->pw;
+  const region r = c->r, prev_r = c->prev_r;
+  const int rh = r.y1 - r.y0, rw = r.x1 - r.x0;
+  for (int o = o0; o < o1; ++o)
+    for (int y = 0; y < rh; ++y)
+      for (int x = 0; x < rw; ++x) {
+        double acc = bk[o];
+        int gy = r.y0 + y, gx = r.x0 + x;
+        for (int i = 0; i < ci_n; ++i)
+          for (int dy = 0; dy < 3; ++dy)
+            for (int dx = 0; dx < 3; ++dx) {
+              int sy = gy + dy - 1, sx = gx + dx - 1;
+              if (sy < 0 || sy >= H || sx < 0 || sx >= W) continue;
+              double s = prev[((size_t)i * ph + (sy - prev_r.y0)) * pw + (sx - prev_r.x0)];
+              acc += Wk[(((size_t)o * ci_n + i) * 3 + dy) * 3 + dx] * s;
+            }
+        if (c->relu && acc < 0.0) acc = 0.0; /* ReLU */
+        cur[((size_t)o * rh + y) * rw + x] = acc;
+      }
+}
+
 /* One image. Layer k (1..L) is evaluated on the output region grown by
  * (L - k) pixels and clipped to the image, so every value a later layer reads
  * inside the image has been computed; reads outside the image are the zero
@@ -169,23 +259,8 @@ static void forward_one(const double* w, const int* ch, int L,
     const double* Wk = w + layer_offset(ch, k - 1);
     const double* bk = Wk + (long)co_n * ci_n * 9;
     double* cur = (double*)malloc(sizeof(double) * (size_t)co_n * rh * rw);
-    for (int o = 0; o < co_n; ++o)
-      for (int y = 0; y < rh; ++y)
-        for (int x = 0; x < rw; ++x) {
-          double acc = bk[o];
-          int gy = r.y0 + y, gx = r.x0 + x;
-          for (int i = 0; i < ci_n; ++i)
-            for (int dy = 0; dy < 3; ++dy)
-              for (int dx = 0; dx < 3; ++dx) {
-                int sy = gy + dy - 1, sx = gx + dx - 1;
-                if (sy < 0 || sy >= H || sx < 0 || sx >= W) continue;
-                double s = prev[((size_t)i * ph + (sy - prev_r.y0)) * pw +
-                                (sx - prev_r.x0)];
-                acc += Wk[(((size_t)o * ci_n + i) * 3 + dy) * 3 + dx] * s;
-              }
-          if (k < L && acc < 0.0) acc = 0.0; /* ReLU */
-          cur[((size_t)o * rh + y) * rw + x] = acc;
-        }
+    conv_layer lay = {Wk, bk, prev, cur, ci_n, k < L, H, W, r, prev_r, ph, pw};
+    parallel_ranges(co_n, conv_channels, &lay);
     if (keep) memcpy(keep[k - 1], cur, sizeof(double) * (size_t)co_n * rh * rw);
     free(prev);
     prev = cur;
@@ -224,6 +299,67 @@ void or_threshold(const double* logits, long n, uint8_t* bits) {
   for (long i = 0; i < n; ++i) bits[i] = logits[i] >= 0.0 ? 1 : 0;
 }
 
+/* Gradients of one conv layer y = b + W * s given g = dLoss/dy (C x H x W):
+ *   dLoss/dW[o][i][dy][dx] += sum_{y,x} g[o](y, x) s_i(y + dy - 1, x + dx - 1),
+ *   dLoss/db[o]            += sum_{y,x} g[o](y, x),
+ *   dLoss/ds_i(sy, sx)     += sum_{o, dy, dx} g[o](sy - dy + 1, sx - dx + 1) W[o][i][dy][dx],
+ * terms outside the image dropped. Both sums visit their terms in the order
+ * (o, y, x, dy, dx) of one loop over the output, so splitting the first over
+ * o and the second over i changes no rounding. */
+typedef struct {
+  const double *Wk, *in, *g;
+  double *gW, *gb, *gin;
+  int ci_n, co_n, H, W;
+} conv_grad;
+
+static void conv_grad_weights(int o0, int o1, void* ctx) {
+  const conv_grad* c = (const conv_grad*)ctx;
+  const double* in = c->in;
+  const double* g = c->g;
+  double* gW = c->gW;
+  double* gb = c->gb;
+  const int H = c->H, W = c->W, ci_n = c->ci_n;
+  const size_t HW = (size_t)H * W;
+  for (int o = o0; o < o1; ++o)
+    for (int y = 0; y < H; ++y)
+      for (int x = 0; x < W; ++x) {
+        double go = g[(size_t)o * HW + (size_t)y * W + x];
+        if (go == 0.0) continue;
+        gb[o] += go;
+        for (int i = 0; i < ci_n; ++i)
+          for (int dy = 0; dy < 3; ++dy)
+            for (int dx = 0; dx < 3; ++dx) {
+              int sy = y + dy - 1, sx = x + dx - 1;
+              if (sy < 0 || sy >= H || sx < 0 || sx >= W) continue;
+              gW[(((size_t)o * ci_n + i) * 3 + dy) * 3 + dx] +=
+                  go * in[(size_t)i * HW + (size_t)sy * W + sx];
+            }
+      }
+}
+
+static void conv_grad_input(int i0, int i1, void* ctx) {
+  const conv_grad* c = (const conv_grad*)ctx;
+  const double* Wk = c->Wk;
+  const double* g = c->g;
+  double* gin = c->gin;
+  const int H = c->H, W = c->W, ci_n = c->ci_n, co_n = c->co_n;
+  const size_t HW = (size_t)H * W;
+  for (int i = i0; i < i1; ++i)
+    for (int o = 0; o < co_n; ++o)
+      for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+          double go = g[(size_t)o * HW + (size_t)y * W + x];
+          if (go == 0.0) continue;
+          for (int dy = 0; dy < 3; ++dy)
+            for (int dx = 0; dx < 3; ++dx) {
+              int sy = y + dy - 1, sx = x + dx - 1;
+              if (sy < 0 || sy >= H || sx < 0 || sx >= W) continue;
+              gin[(size_t)i * HW + (size_t)sy * W + sx] +=
+                  go * Wk[(((size_t)o * ci_n + i) * 3 + dy) * 3 + dx];
+            }
+        }
+}
+
 /* Backward pass of the conv stack (the chain rule through Sec. VI-A's
  * network): given g = dLoss/dlogit for every pixel, accumulate dLoss/dtheta
  * into grad_w (same layout as w; the caller zeroes it) and, if requested,
@@ -256,23 +392,9 @@ void or_policy_backward(const double* w, const int* ch, int L, const double* c,
       double* gb = gW + (long)co_n * ci_n * 9;
       const double* in = k >= 2 ? keep[k - 2] : s0;
       double* gin = (double*)calloc((size_t)ci_n * HW, sizeof(double));
-      for (int o = 0; o < co_n; ++o)
-        for (int y = 0; y < H; ++y)
-          for (int x = 0; x < W; ++x) {
-            double go = g[(size_t)o * HW + (size_t)y * W + x];
-            if (go == 0.0) continue;
-            gb[o] += go;
-            for (int i = 0; i < ci_n; ++i)
-              for (int dy = 0; dy < 3; ++dy)
-                for (int dx = 0; dx < 3; ++dx) {
-                  int sy = y + dy - 1, sx = x + dx - 1;
-                  if (sy < 0 || sy >= H || sx < 0 || sx >= W) continue;
-                  size_t si = (size_t)i * HW + (size_t)sy * W + sx;
-                  size_t wi = (((size_t)o * ci_n + i) * 3 + dy) * 3 + dx;
-                  gW[wi] += go * in[si];
-                  gin[si] += go * Wk[wi];
-                }
-          }
+      conv_grad cg = {Wk, in, g, gW, gb, gin, ci_n, co_n, H, W};
+      parallel_ranges(co_n, conv_grad_weights, &cg);
+      parallel_ranges(ci_n, conv_grad_input, &cg);
       if (k >= 2) {
         /* through the ReLU of layer k-1: zero where its output is 0 */
         for (size_t i = 0; i < (size_t)ci_n * HW; ++i)
@@ -520,12 +642,12 @@ void or_le_delta_local(const double* h, const double* c, int B, int H, int W,
 }
 
 /* ------------------------------------------------------------------------
- * Multitoning (Sec. VII, the deep multitoning prototype). There are L ink
+ * Multitoning (Sec. VI-E, the deep multitoning prototype). There are L ink
  * levels l_k = k Delta, k = 0..L-1, Delta = 1/(L-1). The network keeps its
  * single sigmoid output v_a, and agent a chooses between the two levels
  * around v_a: the upper one with probability (v_a - floor(v_a)) / Delta and
- * the lower one otherwise (Eq. multitone). So every agent still has two
- * actions, and E[h_a] = v_a.
+ * the lower one otherwise (the unnumbered rounding equation of Sec. VI-E).
+ * So every agent still has two actions, and E[h_a] = v_a.
  * Readings where the paper is silent:
  *   - the pair around v is (k_f, k_f + 1) with k_f = min(floor(v / Delta),
  *     L - 2), so v = 1 picks level L-1 with probability one;
@@ -1015,7 +1137,7 @@ void or_floyd_steinberg(const double* c, int B, int H, int W, uint8_t* h) {
 }
 
 /* Floyd-Steinberg with L output levels k / (L-1), the error diffusion that
- * stands beside the multitoning variant (Sec. VII) as its serial fallback:
+ * stands beside the multitoning variant (Sec. VI-E) as its serial fallback:
  * v = c + diffused error, k = the level nearest to v (a tie going up, clamped
  * to 0..L-1), error v - k / (L-1) pushed with the same weights and borders
  * as or_floyd_steinberg, which is the case L = 2. */

@@ -37,7 +37,8 @@ def build(force=False):
     """Compile the oracle with plain gcc -O2 (no fast-math, no intrinsics)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-pthread", "-o", tmp,
+                               SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -58,6 +59,8 @@ def lib():
         c_int, c_long, c_double, c_u32, c_u64 = (ctypes.c_int, ctypes.c_long, ctypes.c_double,
                                                   ctypes.c_uint32, ctypes.c_uint64)
         sig = {
+            "or_set_threads": (None, [c_int]),
+            "or_get_threads": (c_int, []),
             "or_philox4x32_10": (None, [U32, U32, U32]),
             "or_uniform": (c_double, [c_u64, c_u64, c_u32, c_u32]),
             "or_normal": (c_double, [c_u64, c_u64, c_u32, c_u32]),
@@ -98,6 +101,29 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads for the conv stack's channel loops (results are bit-identical
+    for any count); returns the previous count."""
+    prev = lib().or_get_threads()
+    lib().or_set_threads(int(n))
+    return prev
+
+
+class threads:
+    """Context manager: run the oracle on n threads inside the block."""
+
+    def __init__(self, n):
+        self.n = n
+
+    def __enter__(self):
+        self.prev = set_threads(self.n)
+        return self
+
+    def __exit__(self, *exc):
+        set_threads(self.prev)
+        return False
 
 
 def _d(a):
@@ -265,7 +291,7 @@ def le_grad_probs(h, c, prm=None):
 
 
 def multitone_actions(v, seeds, L, step=0):
-    """Level indices k_a in {k_f, k_f + 1} around v_a (Sec. VII, Eq. multitone)."""
+    """Level indices k_a in {k_f, k_f + 1} around v_a (Sec. VI-E, its unnumbered rounding equation)."""
     B, H, W = _bhw(v)
     v, vp = _d(np.reshape(v, (B, H, W)))
     s, sp = _u64(seeds)

@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict
 // with multitone levels (lv.n > 1) the level of x among lv's thresholds.
 // MODE 1: p = sigmoid(x), action = [u < p] with u from stream 0 at `step`;
 // with L = lv.n + 1 > 2 levels the index kf + [u < q] of the stochastic
-// rounding between the levels around p (Sec. VII, Eq. multitone):
+// rounding between the levels around p (Sec. VI-E, its unnumbered rounding equation):
 // kf = min(floor(p (L-1)), L-2), q = p (L-1) - kf.
 // ---------------------------------------------------------------------------
 constexpr int LP = 33;  // padded pixel stride (floats) of the staged tile

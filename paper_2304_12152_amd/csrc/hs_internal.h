@@ -40,7 +40,7 @@ inline __host__ __device__ int entry_page(uint64_t e) { return (int)((e >> 31) &
 inline __host__ __device__ int entry_bit(uint64_t e) { return (int)(e >> 63); }
 constexpr int WGRAD_BLOCKS = 512;  // rows of weight-gradient partial sums
 
-// Output levels of the test phase (Sec. VII multitoning; binary = 2 levels):
+// Output levels of the test phase (Sec. VI-E multitoning; binary = 2 levels):
 // level = #{j : x >= thr[j]} over the logit midpoints
 // thr[j] = logit((j + 1/2) / (L - 1)), j = 0..L-2; binary: thr = {0}.
 constexpr int MAX_LEVELS = 8;

@@ -16,7 +16,7 @@
 // of products expanded in those increments, so no two O(1) values are
 // subtracted. dR_a = delta (R(toggled) - R(h)); dL_MARL/dp_a = -dR_a / B.
 //
-// Multitoning (Sec. VII, Eq. multitone; L levels spaced s = 1/(L-1)): an
+// Multitoning (Sec. VI-E, its unnumbered rounding equation; L levels spaced s = 1/(L-1)): an
 // action byte is a level index k, h = k s. Agent a's two actions are the
 // levels kf, kf + 1 around its output v_a (kf = min(floor(v (L-1)), L-2)),
 // and its toggle moves h_a by delta = +s (from kf) or -s (from kf + 1). Then

@@ -10,7 +10,7 @@
 //                in FP32. Pixels with |x| >= tau2 are decided here, the
 //                rest listed again.
 //   FP32 stage   the pixels listed by the split stage, in plain FP32.
-// With multitone levels (Sec. VII) the same holds with |x| replaced by the
+// With multitone levels (Sec. VI-E) the same holds with |x| replaced by the
 // distance to the nearest level threshold; the output is the level.
 #include "hs_common.h"
 #include "hs_internal.h"

@@ -29,7 +29,7 @@ averaged power and the anisotropy per ring. Reported per method and gray:
               integer.
 With K periodograms averaged, an isotropic spectrum has anisotropy about
 1 / K, so -10 log10(K) dB is the floor the figures are read against.
-With --levels L > 2 the policy is the multitoning variant (Sec. VII): its
+With --levels L > 2 the policy is the multitoning variant (Sec. VI-E): its
 output is the level index k, the image k / (L - 1) is scored, and its
 power is taken in units of that image (the level indices' spectrum divided
 by (L - 1)^2); the reference is Floyd-Steinberg with the same L levels.

@@ -4,7 +4,7 @@ Every training iteration is one `policy_train_step` call: forward of the
 batch and of the constant-gray side batch, Bernoulli actions, the Local
 Expectation gradient of the reward (Sec. III-B/C), the anisotropy gradient
 (Eq. as), backward through the conv stack and Adam with the cosine schedule
-(Sec. IV-A) -- all in the library's kernels. This module only feeds it
+(Sec. VI-A) -- all in the library's kernels. This module only feeds it
 batches and seeds.
 
 Training data: a pool of synthetic contones (the seeded generator of
@@ -182,7 +182,7 @@ def main(argv=None):
     ap.add_argument("--estimator", choices=["le", "coma"], default="le",
                     help="policy-gradient estimator: Local Expectation (Eq. le) or COMA (Eq. coma)")
     ap.add_argument("--levels", type=int, default=2,
-                    help="output levels: 2 = binary halftoning, 3..8 = multitoning (Sec. VII)")
+                    help="output levels: 2 = binary halftoning, 3..8 = multitoning (Sec. VI-E)")
     ap.add_argument("--judge-every", type=int, default=0,
                     help="steps between held-out evaluations of the policy during training")
     ap.add_argument("--out", default=None, help="write the trained weights (.npy)")

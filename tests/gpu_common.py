@@ -35,3 +35,10 @@ def inputs(seeds, H, W, wseed=42):
     w = synth.he_weights(wseed)
     c = synth.contone_batch(seeds, H, W)
     return w, c
+
+
+def oracle_threads():
+    """Threads for the oracle's conv loops in the large parity cases (the
+    results are bit-identical for any count): the host's cores, at most 16."""
+    import os
+    return max(1, min(16, os.cpu_count() or 1))

@@ -1,4 +1,4 @@
-"""GPU parity of the multitoning prototype (Sec. VII, Eq. multitone) against
+"""GPU parity of the multitoning prototype (Sec. VI-E, its unnumbered rounding equation) against
 the oracle: the nearest-level test phase (FP32 and BF16 with the recheck
 around every level threshold), the multi-level reward and Local Expectation
 gradient, and one TRAIN iteration with stochastic rounding between levels."""

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import device, seeds_t, to_dev
+from gpu_common import device, oracle_threads, seeds_t, to_dev
 from paper_2304_12152_amd import autograd as hag
 from paper_2304_12152_amd import binding as hb
 from paper_2304_12152_amd import synth
@@ -178,6 +178,92 @@ def test_train_step_bf16_gradient(orc):
                        np.array(seeds, np.uint64), cg.astype(np.float64),
                        np.array([5, 6], np.uint64), 0, 10, actions=acts.cpu().numpy())
     assert _cos(grad.cpu().numpy(), o["grad"]) > 0.999
+
+
+# flat-gradient ranges of the six layers (weights then bias)
+_LAYERS = [(0, 608), (608, 9856), (9856, 19104), (19104, 28352), (28352, 37600),
+           (37600, 37889)]
+
+
+def _tap_errors(g, ref, k):
+    """Normwise error of each of the nine taps of 32->32 layer k (2..5)."""
+    lo = 608 + (k - 2) * 9248
+    gk = g[lo:lo + 9216].reshape(32, 32, 9)
+    rk = ref[lo:lo + 9216].reshape(32, 32, 9)
+    return np.array([_rel(gk[:, :, t], rk[:, :, t]) for t in range(9)])
+
+
+def _multi_tile_case(orc, precision, seed0):
+    """One TRAIN iteration on 8 x 256 x 256 crops plus 8 constant grays of
+    64 x 64 against the oracle's, given the GPU's actions. The weight-gradient
+    kernels run 512 blocks that stride over tiles: 4,096 tiles of 2 x 64
+    pixels (8 per block) for the 32->32 layers and 2,048 of 16 x 16 (4 per
+    block) for the first and last layers, so every block goes through its
+    tile loop, with the next tile's loads in flight, several times."""
+    B, H, W = 8, 256, 256
+    seeds = list(range(seed0, seed0 + B))
+    w = synth.he_weights(5, head_std=0.01)
+    c = synth.contone_batch(seeds, H, W)
+    cg = synth.gray_batch(8, 64, 64)
+    gseeds = list(range(seed0 + 100, seed0 + 108))
+    state = hb.TrainState(to_dev(w), B, H, W, 8, 64, 64, precision=precision)
+    acts = torch.empty((B, H, W), dtype=torch.uint8, device=device())
+    grad = torch.empty(hb.HS_PARAM_COUNT, dtype=torch.float32, device=device())
+    hb.policy_train_step(state, to_dev(c), seeds_t(seeds), to_dev(cg), seeds_t(gseeds), 2, 100,
+                         actions_out=acts, grad_out=grad)
+    wd = w.astype(np.float64)
+    with orc.threads(oracle_threads()):
+        o = orc.train_step(wd, np.zeros_like(wd), np.zeros_like(wd), c.astype(np.float64),
+                           np.array(seeds, np.uint64), cg.astype(np.float64),
+                           np.array(gseeds, np.uint64), 2, 100, actions=acts.cpu().numpy())
+    return grad.cpu().numpy(), o["grad"]
+
+
+def test_train_step_multi_tile_fp32_matches_oracle(orc):
+    g, ref = _multi_tile_case(orc, hb.HS_FP32, 300)
+    print("FP32 multi-tile step: rel", _rel(g, ref),
+          "per layer", [round(float(_rel(g[a:b], ref[a:b])), 8) for a, b in _LAYERS], flush=True)
+    assert _rel(g, ref) < 1e-5
+    for a, b in _LAYERS:
+        assert _rel(g[a:b], ref[a:b]) < 1e-5
+
+
+def test_train_step_multi_tile_bf16_matches_oracle(orc):
+    g, ref = _multi_tile_case(orc, hb.HS_BF16, 400)
+    cos = _cos(g, ref)
+    per_layer = [float(_rel(g[a:b], ref[a:b])) for a, b in _LAYERS]
+    print("BF16 multi-tile step: cosine", cos, "per layer", np.round(per_layer, 4), flush=True)
+    assert cos >= 0.999
+    # BF16 rounding spreads its error evenly over the taps of a layer; a tap
+    # read from the wrong row, column or tile, or scaled wrongly, stands out
+    for k in range(2, 6):
+        e = _tap_errors(g, ref, k)
+        print("layer", k, "per-tap error", np.round(e, 4), flush=True)
+        assert e.max() <= 3.0 * np.median(e) + 1e-3, (k, e)
+
+
+def test_policy_backward_bf16_matches_fp32_at_c4(orc):
+    """The conv-stack backward on the full training batch (32 x 256 x 256) in
+    BF16 against the FP32 kernels (which the multi-tile case above checks
+    against the oracle) for the same dL/dp."""
+    B, H, W = 32, 256, 256
+    seeds = list(range(500, 500 + B))
+    w = to_dev(synth.he_weights(5, head_std=0.01))
+    c = to_dev(synth.contone_batch(seeds, H, W))
+    gprob = to_dev(np.random.default_rng(3).normal(size=(B, H, W)).astype(np.float32))
+    out = {}
+    for prec in (hb.HS_FP32, hb.HS_BF16):
+        probs, ws = hb.halftone_policy_forward(w, c, seeds_t(seeds), 0, precision=prec)
+        out[prec] = hb.halftone_policy_backward(w, gprob, probs, ws, prec).cpu().numpy()
+        del ws
+    g32, g16 = out[hb.HS_FP32], out[hb.HS_BF16]
+    cos = _cos(g16, g32)
+    print("C4 backward BF16 vs FP32: cosine", cos, "per layer",
+          np.round([float(_rel(g16[a:b], g32[a:b])) for a, b in _LAYERS], 4), flush=True)
+    assert cos >= 0.999
+    for k in range(2, 6):
+        e = _tap_errors(g16, g32, k)
+        assert e.max() <= 3.0 * np.median(e) + 1e-3, (k, e)
 
 
 def test_train_step_is_deterministic():

@@ -1,4 +1,4 @@
-"""Pins of the oracle's multitoning prototype (Sec. VII, Eq. multitone):
+"""Pins of the oracle's multitoning prototype (Sec. VI-E, its unnumbered rounding equation):
 L = 2 is the binary method, the local toggle equals brute force, the
 actions are the unbiased stochastic rounding between adjacent levels, the
 test phase rounds to the nearest level, and the estimator is the exact

@@ -147,3 +147,24 @@ def test_backward_finite_differences(orc):
         wm = w.copy(); wm[i] -= eps
         fd = (loss(wp) - loss(wm)) / (2 * eps)
         assert abs(fd - gw[i]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_threads_leave_every_bit_unchanged(orc):
+    # the channel loops split over threads add each element's terms in the
+    # serial order: the forward, the weight gradient and the input gradient
+    # are bit-identical for any thread count
+    B, H, W = 2, 21, 34
+    rng = np.random.default_rng(12)
+    w = rng.normal(scale=0.3, size=orc.param_count())
+    c = rng.uniform(size=(B, H, W))
+    z = rng.normal(size=(B, H, W))
+    g = rng.normal(size=(B, H, W))
+    ref = None
+    for n in (1, 3, 7, 32):
+        with orc.threads(n):
+            out = (orc.policy_forward(w, c, z),) + tuple(orc.policy_backward(w, c, z, g))
+        if ref is None:
+            ref = out
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b)
+    assert orc.set_threads(1) == 1
