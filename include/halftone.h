@@ -43,6 +43,17 @@ extern "C" {
 #define HS_EUNSUPPORTED (-3) /* precision or device not supported          */
 #define HS_EWORKSPACE (-4)   /* workspace smaller than *_workspace_size    */
 #define HS_EHIP (-5)         /* a HIP call or kernel launch failed          */
+#define HS_ENONFINITE (-6)   /* an input holds NaN or +-inf (checked only
+                                when HS_CHECK_FINITE is requested)        */
+
+/* Optional input check, OR-ed into the `noise_kind` argument of the
+ * inference calls, into hs_loss_params.flags, or into the flags of
+ * halftone_policy_pack: before any other launch the call counts the NaN and
+ * infinite values of its floating-point inputs on the device, waits for the
+ * count (so the call synchronises its stream) and returns HS_ENONFINITE if
+ * there is one. Without it non-finite inputs give unspecified outputs, but
+ * nothing is written out of bounds. */
+#define HS_CHECK_FINITE 0x100
 
 #define HS_FP32 0 /* FP32 arithmetic throughout                           */
 #define HS_BF16 1 /* BF16 MFMA with FP32 accumulation                      */
@@ -89,6 +100,7 @@ typedef struct hs_loss_params {
   int as_patch;  /* only 32 is supported */
   int estimator; /* HS_EST_LE or HS_EST_COMA */
   int levels;    /* 2 (binary) .. HS_MAX_LEVELS (multitoning) */
+  int flags;     /* 0 or HS_CHECK_FINITE (contone and probabilities) */
 } hs_loss_params;
 
 /* Optimiser and sampling parameters of one TRAIN iteration (Algorithm 1).
@@ -132,10 +144,12 @@ int64_t halftone_param_count(void);
  *          |x| < recheck_tau is recomputed over its 13x13 receptive field
  *          with split-BF16 products (hi*hi + lo*hi + hi*lo, FP32
  *          accumulation, about 2^-8 of the BF16 error), and every pixel
- *          whose recomputed |x| is still below tau2 = recheck_tau/64 clamped
- *          to [1.5e-4, 1e-2] is recomputed once more in FP32 and decided from that
+ *          whose recomputed |x| is still below tau2 = max(recheck_tau/64,
+ *          1.5e-4) is recomputed once more in FP32 and decided from that
  *          value (recheck_tau >= 0; it must exceed the largest BF16 logit
- *          error for the bits to equal FP32's off-margin). That error
+ *          error for the bits to equal FP32's off-margin, and tau2 the
+ *          split stage's, about 2^-8 of it; halftone_policy_infer takes
+ *          tau2 explicitly). That error
  *          depends on the weights (0.042 for a He-initialised policy, 4.5
  *          for a trained one on the same images): measure it by comparing
  *          the logits of a call with recheck_tau = 0 against HS_FP32's.
@@ -145,6 +159,8 @@ int64_t halftone_param_count(void);
  *          activation of the pass overflows, the pass is run again in BF16
  *          with 8 * recheck_tau, decided on the device (no host
  *          synchronisation), and stats[3] reads 1.
+ * noise_kind HS_NOISE_GAUSS or HS_NOISE_UNIFORM, optionally OR-ed with
+ *          HS_CHECK_FINITE (the contone is then checked first).
  * bits     [B][H][W] uint8 out.
  * logits_or_null [B][H][W] FP32 out: the logit each bit was decided from.
  * stats_or_null  int32[4] out: {pixels rechecked (|x_bf16| < recheck_tau),
@@ -204,6 +220,51 @@ int halftone_infer_levels(const float* weights, const float* contone, const uint
                           size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
+ * A packed inference policy (the network of the TEST procedure, Algorithm
+ * 1): a copy of the FP32 weights together with every derived copy the
+ * inference calls use -- the BF16 and FP16 MFMA fragments of the fused
+ * pass, its FP16 layer bounds, the split hi/lo BF16 and transposed FP32
+ * copies of the recheck stages, and the FP32 per-layer fragments -- made
+ * once per weight update instead of on every call.
+ *
+ * halftone_policy_bytes: device memory one packed policy needs.
+ * halftone_policy_pack: packs `weights` (device FP32 [HS_PARAM_COUNT])
+ *          into `mem` (device memory of at least halftone_policy_bytes(),
+ *          256-byte aligned, owned by the caller and left untouched by it
+ *          while the policy is used) and fills the host struct *policy.
+ *          The copy is taken on `stream`: later changes to `weights` do
+ *          not affect the policy until it is packed again. flags: 0 or
+ *          HS_CHECK_FINITE (then the weights are checked and the call
+ *          waits for the stream).
+ * halftone_policy_infer: halftone_infer_levels (levels = 2: the bits of
+ *          halftone_infer_pages) with the policy's packed copies, so the
+ *          call launches no packing kernel. Arguments and results as for
+ *          halftone_infer_levels, plus recheck_tau2: the split stage's
+ *          band (pixels whose split-precision |x| is below it go to the
+ *          FP32 stage; it must exceed the split stage's largest logit
+ *          error for the weights), or -1 for the default rule of
+ *          halftone_infer. recheck_tau2 = 0 with a large recheck_tau
+ *          returns the split stage's logits for every listed pixel, which
+ *          is how that error is measured. Workspace from
+ *          halftone_infer_pages_workspace_size. Calls on the same policy
+ *          may overlap (the policy is only read); the work must be
+ *          enqueued after the pack on a stream ordered after `stream`.
+ * --------------------------------------------------------------------- */
+typedef struct hs_policy {
+  void* mem;    /* the caller's device memory holding the packed copies */
+  size_t bytes; /* its size */
+  int packed;   /* 1 once halftone_policy_pack has succeeded */
+} hs_policy;
+size_t halftone_policy_bytes(void);
+int halftone_policy_pack(hs_policy* policy, const float* weights, void* mem, size_t bytes,
+                         int flags, void* stream);
+int halftone_policy_infer(const hs_policy* policy, const float* contone, const uint64_t* seeds,
+                          int npages, const int32_t* shapes_host, int levels, int noise_kind,
+                          int precision, float recheck_tau, float recheck_tau2, uint8_t* out,
+                          float* logits_or_null, int32_t* stats_or_null, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
  * Training-mode policy forward and its backward (the conv stack of
  * Sec. VI-A with its chain rule), for torch.autograd wrappers.
  *
@@ -233,9 +294,12 @@ int halftone_policy_backward(const float* weights, const float* grad_probs, cons
  * probs_gray_or_null [Bg][Hg][Wg] FP32: pi(h=1) of the constant-gray side
  *          batch; L_AS is computed over its non-overlapping 32x32 patches
  *          (remainders dropped). Pass NULL (and Bg = 0) to skip L_AS.
- * out      FP32, 3*B + 1 values: per image {MSE(HVS(h), HVS(c)), mean
+ * out      FP32, 3*B + 2 values: per image {MSE(HVS(h), HVS(c)), mean
  *          CSSIM, R = -MSE + w_s*CSSIM}, then L_AS (mean over patches; 0 if
- *          no patch). MSE and CSSIM are means over the valid region
+ *          no patch), then the total training loss of the batch,
+ *          -mean_b R_b + w_a * L_AS (the value whose gradient the
+ *          estimators of halftone_loss_backward stand in for, Sec. III-B
+ *          and Sec. IV). MSE and CSSIM are means over the valid region
  *          [m, H-m) x [m, W-m), m = max(hvs_radius, ssim_radius).
  * Shapes: H, W >= 2m+1.
  * --------------------------------------------------------------------- */
@@ -292,7 +356,9 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
  * precision HS_FP32 or HS_BF16 (BF16 activations and MFMA, FP32 master
  *          weights, FP32 gradients accumulated in FP32).
  * metrics  FP32[8] out: mean MSE, mean CSSIM, mean R, L_AS, lr, |grad|_2,
- *          fill (the mean of h: the fraction of ones for binary actions), 0.
+ *          fill (the mean of h: the fraction of ones for binary actions),
+ *          the total loss -mean R + w_a L_AS.
+ * tp->loss.flags & HS_CHECK_FINITE checks the contones (and gray levels).
  * actions_out_or_null [B][H][W] uint8: the sampled actions.
  * grad_out_or_null [HS_PARAM_COUNT] FP32: the total gradient before Adam.
  * --------------------------------------------------------------------- */

@@ -5,8 +5,9 @@ backward (input gradients and weight gradients in HIP).
 HalftoneLoss: the training loss whose gradient is the Local Expectation
 estimator for the main batch (dL_MARL/dp = -dR/B) plus w_a times the
 anisotropy-suppressing loss for the gray batch. Its forward value is the
-scalar -mean(R) + w_a L_AS (the reported surrogate); its backward is the
-estimator, not the derivative of that value with respect to p.
+scalar -mean(R) + w_a L_AS that the library returns (the reported
+surrogate); its backward is the estimator, not the derivative of that value
+with respect to p.
 """
 import torch
 
@@ -38,8 +39,7 @@ class HalftoneLoss(torch.autograd.Function):
         B = contone.shape[0]
         ctx.save_for_backward(probs, actions, contone, probs_gray)
         ctx.prm = prm
-        R = out[2:3 * B:3]
-        return -R.mean() + prm.w_a * out[3 * B]
+        return out[3 * B + 1]
 
     @staticmethod
     def backward(ctx, g):

@@ -13,6 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhalftone.so")
 
 HS_OK, HS_EINVAL, HS_ESHAPE, HS_EUNSUPPORTED, HS_EWORKSPACE, HS_EHIP = 0, -1, -2, -3, -4, -5
+HS_ENONFINITE = -6
+HS_CHECK_FINITE = 0x100
 HS_FP32, HS_BF16, HS_FP16 = 0, 1, 2
 HS_NOISE_GAUSS, HS_NOISE_UNIFORM = 0, 1
 HS_WRT_PROB, HS_WRT_LOGIT = 0, 1
@@ -26,13 +28,17 @@ class HsLossParams(ctypes.Structure):
                 ("hvs_radius", ctypes.c_int), ("ssim_sigma", ctypes.c_float),
                 ("ssim_radius", ctypes.c_int), ("k", ctypes.c_float), ("c1", ctypes.c_float),
                 ("c2", ctypes.c_float), ("as_patch", ctypes.c_int), ("estimator", ctypes.c_int),
-                ("levels", ctypes.c_int)]
+                ("levels", ctypes.c_int), ("flags", ctypes.c_int)]
 
 
 class HsTrainParams(ctypes.Structure):
     _fields_ = [("loss", HsLossParams), ("lr_max", ctypes.c_float), ("lr_min", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("noise_kind", ctypes.c_int), ("recompute", ctypes.c_int)]
+
+
+class HsPolicy(ctypes.Structure):
+    _fields_ = [("mem", ctypes.c_void_p), ("bytes", ctypes.c_size_t), ("packed", ctypes.c_int)]
 
 
 class HalftoneError(RuntimeError):
@@ -58,6 +64,10 @@ _SIGS = {
     "halftone_infer_pages_workspace_size": (SZ, [I, P, I]),
     "halftone_infer_pages": (I, [P, P, P, I, P, I, I, F, P, P, P, P, SZ, P]),
     "halftone_infer_levels": (I, [P, P, P, I, P, I, I, I, F, P, P, P, P, SZ, P]),
+    "halftone_policy_bytes": (SZ, []),
+    "halftone_policy_pack": (I, [ctypes.POINTER(HsPolicy), P, P, SZ, I, P]),
+    "halftone_policy_infer": (I, [ctypes.POINTER(HsPolicy), P, P, I, P, I, I, I, F, F, P, P, P, P,
+                                  SZ, P]),
     "halftone_policy_workspace_size": (SZ, [I, I, I, I]),
     "halftone_policy_forward": (I, [P, P, P, I, I, I, I, ctypes.c_uint32, I, P, P, SZ, P]),
     "halftone_policy_backward": (I, [P, P, P, I, I, I, I, P, P, SZ, P]),
@@ -218,6 +228,54 @@ def halftone_infer_pages(weights, contone, seeds, shapes, noise_kind=HS_NOISE_GA
     return out[0] if len(out) == 1 else tuple(out)
 
 
+class Policy:
+    """A packed inference policy (halftone_policy_pack): the weights and all
+    their derived copies in one device buffer owned by this object."""
+
+    def __init__(self, weights, check_finite=False):
+        _dev(weights, torch.float32)
+        n = lib().halftone_policy_bytes()
+        self.mem = torch.empty(n, dtype=torch.uint8, device=weights.device)
+        self.handle = HsPolicy()
+        _check(lib().halftone_policy_pack(ctypes.byref(self.handle), _ptr(weights), _ptr(self.mem),
+                                          n, HS_CHECK_FINITE if check_finite else 0, _stream()))
+
+
+def halftone_policy_infer(policy, contone, seeds, shapes=None, noise_kind=HS_NOISE_GAUSS,
+                          precision=HS_BF16, recheck_tau=None, recheck_tau2=-1.0, logits=False,
+                          stats=False, workspace=None, levels=2):
+    """halftone_policy_infer on a packed Policy. contone: [B,H,W] (a uniform
+    batch) or the flat concatenation of pages with `shapes`; the outputs
+    have the contone's shape."""
+    recheck_tau = _tau(precision, recheck_tau)
+    if shapes is None:
+        B, H, W = contone.shape
+        shapes = [(H, W)] * B
+    sh = page_shapes_array(shapes)
+    n = sh.shape[0]
+    dev = contone.device
+    _dev(contone, torch.float32), _dev(seeds, torch.int64)
+    assert seeds.numel() == n
+    out = torch.empty(contone.shape, dtype=torch.uint8, device=dev)
+    lg = torch.empty(contone.shape, dtype=torch.float32, device=dev) if logits else None
+    st = torch.zeros(4, dtype=torch.int32, device=dev) if stats else None
+    shp = sh.ctypes.data_as(ctypes.c_void_p)
+    need = lib().halftone_infer_pages_workspace_size(n, shp, precision)
+    if need == 0:
+        raise HalftoneError(HS_ESHAPE, "bad page shapes")
+    ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
+    _check(lib().halftone_policy_infer(ctypes.byref(policy.handle), _ptr(contone), _ptr(seeds), n,
+                                       shp, int(levels), noise_kind, precision, recheck_tau,
+                                       recheck_tau2, _ptr(out), _ptr(lg), _ptr(st), _ptr(ws),
+                                       ws.numel(), _stream()))
+    res = [out]
+    if logits:
+        res.append(lg)
+    if stats:
+        res.append(st)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
 def halftone_policy_forward(weights, contone, seeds, step=0, noise_kind=HS_NOISE_GAUSS,
                             precision=HS_FP32, workspace=None):
     """probs [B,H,W] and the workspace holding the saved activations."""
@@ -242,11 +300,12 @@ def halftone_policy_backward(weights, grad_probs, probs, workspace, precision=HS
 
 
 def halftone_loss(actions, contone, probs_gray=None, prm=None):
-    """Tensor [3B+1]: per image (MSE, CSSIM, R), then L_AS."""
+    """Tensor [3B+2]: per image (MSE, CSSIM, R), then L_AS, then the total
+    loss -mean(R) + w_a L_AS."""
     prm = prm or default_loss_params()
     B, H, W = contone.shape
     Bg, Hg, Wg = probs_gray.shape if probs_gray is not None else (0, 0, 0)
-    out = torch.empty(3 * B + 1, dtype=torch.float32, device=contone.device)
+    out = torch.empty(3 * B + 2, dtype=torch.float32, device=contone.device)
     need = lib().halftone_loss_workspace_size(B, H, W, Bg, Hg, Wg, ctypes.byref(prm))
     ws = _ws(need, contone.device)
     _check(lib().halftone_loss(_ptr(actions), _ptr(contone), B, H, W, _ptr(probs_gray), Bg, Hg,

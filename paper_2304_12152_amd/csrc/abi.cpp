@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <initializer_list>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -82,6 +83,29 @@ int check_params(const hs_loss_params* p) {
     return fail(HS_EINVAL, "levels %d (2..%d)", p->levels, HS_MAX_LEVELS);
   if (p->levels > 2 && p->estimator != HS_EST_LE)
     return fail(HS_EUNSUPPORTED, "multitone levels need the Local Expectation estimator");
+  if (p->flags & ~HS_CHECK_FINITE) return fail(HS_EINVAL, "loss flags 0x%x", p->flags);
+  return HS_OK;
+}
+
+// HS_CHECK_FINITE: count the NaN / infinite values of the given inputs on
+// the device (counter: one device int of the call's workspace), wait for the
+// count and fail with HS_ENONFINITE if there is any.
+struct FloatSpan {
+  const float* p;
+  size_t n;
+};
+int check_finite(std::initializer_list<FloatSpan> spans, int* counter, hipStream_t s,
+                 const char* who) {
+  if (launch_zero_ints(counter, 1, s) != hipSuccess)
+    return fail(HS_EHIP, "%s: clearing the finite-check counter failed", who);
+  for (const FloatSpan& sp : spans)
+    if (sp.p && launch_count_nonfinite(sp.p, sp.n, counter, s) != hipSuccess)
+      return fail(HS_EHIP, "%s: finite check launch failed", who);
+  int bad = 0;
+  if (hipMemcpyAsync(&bad, counter, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(HS_EHIP, "%s: reading the finite-check counter failed", who);
+  if (bad) return fail(HS_ENONFINITE, "%s: %d non-finite input values", who, bad);
   return HS_OK;
 }
 
@@ -120,6 +144,7 @@ PolicyWs carve_policy(Carve& cv, size_t N, int prec, bool recompute = false) {
 
 struct LossWs {
   float *maps, *tiles, *patches;
+  int* flag;  // the finite check's counter
   int ntiles;
 };
 LossWs carve_loss(Carve& cv, int B, int H, int W, int Bg, int Hg, int Wg, int m, bool maps) {
@@ -130,6 +155,7 @@ LossWs carve_loss(Carve& cv, int B, int H, int W, int Bg, int Hg, int Wg, int m,
   w.tiles = cv.take<float>((size_t)B * w.ntiles * 2 * 4);
   const size_t np = (size_t)Bg * (Hg / 32) * (Wg / 32);
   w.patches = cv.take<float>((np > 0 ? np : 1) * 4);
+  w.flag = cv.take<int>(64);
   return w;
 }
 
@@ -299,6 +325,7 @@ void halftone_default_loss_params(hs_loss_params* p) {
   p->as_patch = 32;
   p->estimator = HS_EST_LE;
   p->levels = 2;
+  p->flags = 0;
 }
 
 void halftone_default_train_params(hs_train_params* p) {
@@ -313,7 +340,7 @@ void halftone_default_train_params(hs_train_params* p) {
   p->recompute = 0;
 }
 
-int halftone_version(void) { return 100; }
+int halftone_version(void) { return 200; }
 
 int halftone_profile_start(void) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
@@ -342,6 +369,29 @@ const char* halftone_last_error(void) { return g_err.c_str(); }
 int64_t halftone_param_count(void) { return HS_PARAM_COUNT; }
 
 // ------------------------------------------------------------- inference --
+// The packed copies of one weight set: the FP32 weights, the fused pass's
+// BF16 and FP16 fragments, its FP16 layer bounds flag, the split hi/lo and
+// transposed FP32 copies of the recheck stages, and the FP32 per-layer
+// fragments. They live in a packed policy's memory, or in the workspace of a
+// call that packs for itself.
+struct Packed {
+  float* w;
+  char *frags, *frags16, *split, *pack32;
+  int* needs_all;
+};
+static size_t policy_layout(void* base, Packed* out) {
+  Carve cv(base);
+  Packed p;
+  p.w = cv.take<float>((size_t)NPARAM * 4);
+  p.frags = cv.take<char>(fused_frag_bytes());
+  p.frags16 = cv.take<char>(fused_frag_bytes());
+  p.split = cv.take<char>(split_frag_bytes() + fp32_pack_bytes());
+  p.pack32 = cv.take<char>(pack_bytes(HS_FP32));
+  p.needs_all = cv.take<int>(64 * sizeof(int));
+  if (out) *out = p;
+  return cv.off;
+}
+
 // Workspace of the 16-bit paths (sizes in bytes) for pages of the given
 // shapes: packed BF16 and FP16 fragments, the split and FP32 weight copies,
 // the page table, the segmented recheck list and its counts, the FP32-stage
@@ -367,6 +417,10 @@ static size_t bf16_ws(const int* shapes, int npages, size_t N, Bf16Ws* out, void
   if (out) *out = w;
   return cv.off;
 }
+// counters of the 16-bit workspace: [0, 16) cleared by the prologue, [8, 12)
+// the statistics when the caller passes none, 24 the FP16 bounds flag of a
+// self-packing call, 40 the finite check's counter
+constexpr int CNT_FINITE = 40;
 
 // Workspace of the FP32 path for one batch of B images of H x W.
 static size_t fp32_ws(int B, int H, int W, InferWs* out, int** cnt, void* base) {
@@ -396,6 +450,14 @@ size_t halftone_infer_workspace_size(int B, int H, int W, int precision) {
   return fp32_ws(B, H, W, nullptr, nullptr, nullptr);
 }
 
+// The split stage decides |x| >= tau2 and must err by less than tau2: the
+// default is tau / 64 (the split products carry about 2^-8 of the 16-bit
+// error, so this keeps the factor 1.3..1.5 of tau over the 16-bit error
+// about 16 times over the split error whatever the weights), and at least
+// 1.5e-4, which is under the 4e-4 margin and 2.8 times the largest split
+// error measured for the He policy.
+static float default_tau2(float tau) { return fmaxf(tau / 64.0f, 1.5e-4f); }
+
 // The 16-bit path over a page table (one persistent fused launch for all pages):
 //   stage 1: fused BF16 (or FP16) pass, pixels with |x| < tau listed
 //   stage 1b (FP16 only): if an activation overflowed FP16, the fused BF16
@@ -404,27 +466,41 @@ size_t halftone_infer_workspace_size(int B, int H, int W, int precision) {
 //   stage 2: split-BF16 receptive-field recompute, |x| < tau2 listed again
 //   stage 3: FP32 receptive-field recompute
 // The page table is built on the device (uniform batch) or from pages_host.
-static int infer_bf16(const float* weights, const float* contone, const uint64_t* seeds,
-                      const int* shapes, int npages, size_t N, const Page* pages_host,
-                      int noise_kind, float recheck_tau, const Levels& lv, bool fp16,
-                      uint8_t* bits, float* logits, int32_t* stats_or_null, void* workspace,
-                      hipStream_t s) {
+// pp: the weights packed beforehand (a packed policy), or null to pack them
+// into the workspace in this call.
+static int infer_bf16(const float* weights, const Packed* pp, const float* contone,
+                      const uint64_t* seeds, const int* shapes, int npages, size_t N,
+                      const Page* pages_host, int noise_kind, float recheck_tau, float tau2,
+                      const Levels& lv, bool fp16, uint8_t* bits, float* logits,
+                      int32_t* stats_or_null, void* workspace, hipStream_t s) {
   Bf16Ws w;
   bf16_ws(shapes, npages, N, &w, workspace);
   int32_t* stats = stats_or_null ? stats_or_null : (int32_t*)(w.cnt + 8);
-  // counters cleared and the uniform page table written by the packing launch
+  // counters cleared and the uniform page table written by the first launch
   PackPrologue pro{w.cnt, 16, stats_or_null, stats_or_null ? 4 : 0,
                    pages_host ? nullptr : w.pages, npages, shapes[0], shapes[1]};
   if (pages_host) HS_TRY(launch_put_pages(w.pages, pages_host, npages, s));
-  // the split stage decides |x| >= tau2: its measured error (at most 5.9e-5)
-  // stays under half the floor, and the floor under the 4e-4 margin
-  const float tau2 = fminf(fmaxf(recheck_tau / 64.0f, 1.5e-4f), 1e-2f);
-  char* whi = w.split;
+  char* whi;
+  const int* needs_all;  // FP16: layers 1..4 not cleared by their bounds
+  const char *frags, *frags16;
+  if (pp) {
+    weights = pp->w;
+    whi = pp->split;
+    needs_all = pp->needs_all;
+    frags = pp->frags;
+    frags16 = pp->frags16;
+    HS_TRY(launch_prologue(pro, s));
+  } else {
+    whi = w.split;
+    needs_all = w.cnt + 24;
+    frags = w.pack;
+    frags16 = w.pack16;
+    HS_TRY(launch_fused_pack(weights, w.pack, fp16 ? w.pack16 : nullptr, w.cnt + 24, pro, s));
+    HS_TRY(launch_split_pack(weights, w.split, w.split + split_frag_bytes() / 2,
+                             w.split + split_frag_bytes(), s));
+  }
   char* wlo = whi + split_frag_bytes() / 2;
   char* wt = whi + split_frag_bytes();
-  int* needs_all = w.cnt + 24;  // FP16: layers 1..4 not cleared by their bounds
-  HS_TRY(launch_fused_pack(weights, w.pack, fp16 ? w.pack16 : nullptr, needs_all, pro, s));
-  HS_TRY(launch_split_pack(weights, whi, wlo, wt, s));
   int nseg = 0;
   long long seg_cap = 0;
   int* ovf = stats + 3;  // zeroed above
@@ -432,21 +508,21 @@ static int infer_bf16(const float* weights, const float* contone, const uint64_t
   if (!fp16) {
     HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
                               recheck_tau, lv, bits, logits, w.seglist, w.seg_count, &nseg,
-                              &seg_cap, w.pack, FUSED_BF16, nullptr, nullptr, 0, num_cus(), s));
+                              &seg_cap, frags, FUSED_BF16, nullptr, nullptr, 0, num_cus(), s));
   } else {
     // the device picks the FP16 form: of the two launches, the one whose
     // gate does not match needs_all returns at once
     for (int form : {FUSED_FP16_L5, FUSED_FP16_ALL})
       HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
                                 recheck_tau, lv, bits, logits, w.seglist, w.seg_count, &nseg,
-                                &seg_cap, w.pack16, form, ovf, needs_all,
+                                &seg_cap, frags16, form, ovf, needs_all,
                                 form == FUSED_FP16_ALL, num_cus(), s));
   }
   prof_end(s);
   if (fp16)
     HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
                               8.0f * recheck_tau, lv, bits, logits, w.seglist, w.seg_count,
-                              &nseg, &seg_cap, w.pack, FUSED_BF16, nullptr, ovf, 1, num_cus(),
+                              &nseg, &seg_cap, frags, FUSED_BF16, nullptr, ovf, 1, num_cus(),
                               s));
   HS_TRY(launch_recheck_split(weights, contone, seeds, w.pages, noise_kind, w.seglist,
                               w.seg_count, nseg, seg_cap, whi, wlo, tau2, lv, w.list2,
@@ -456,24 +532,30 @@ static int infer_bf16(const float* weights, const float* contone, const uint64_t
   return HS_OK;
 }
 
-// The FP32 path (per-layer kernels) on one uniform batch.
-static int infer_fp32(const float* weights, const float* contone, const uint64_t* seeds, int B,
-                      int H, int W, int noise_kind, const Levels& lv, uint8_t* bits, float* logits,
-                      void* workspace, hipStream_t s) {
+// The FP32 path (per-layer kernels) on one uniform batch; pack32: the FP32
+// fragments packed beforehand, or null to pack them into the workspace.
+static int infer_fp32(const float* weights, const char* pack32, const float* contone,
+                      const uint64_t* seeds, int B, int H, int W, int noise_kind,
+                      const Levels& lv, uint8_t* bits, float* logits, void* workspace,
+                      hipStream_t s) {
   InferWs iw;
   int* cnt;
   fp32_ws(B, H, W, &iw, &cnt, workspace);
   const size_t per_layer = (size_t)PACK32_PER_LAYER * 4;
   HS_TRY(launch_zero_ints(cnt, 16, s));
-  HS_TRY(launch_pack32(weights, iw.pack, HS_FP32, 0, s));
+  const char* pack = pack32;
+  if (!pack) {
+    HS_TRY(launch_pack32(weights, iw.pack, HS_FP32, 0, s));
+    pack = (const char*)iw.pack;
+  }
   HS_TRY(launch_conv_first(contone, seeds, weights, B, H, W, noise_kind, 0u, HS_FP32, iw.a0,
                            nullptr, nullptr, s));
   void* src = iw.a0;
   void* dst = iw.a1;
   for (int k = 2; k <= 5; ++k) {
     if (k == 2) prof_begin(s);
-    HS_TRY(launch_conv32(src, (const char*)iw.pack + (k - 2) * per_layer, weights + hs_bk(k),
-                         nullptr, dst, B, H, W, HS_FP32, 0, s));
+    HS_TRY(launch_conv32(src, pack + (k - 2) * per_layer, weights + hs_bk(k), nullptr, dst, B, H,
+                         W, HS_FP32, 0, s));
     if (k == 5) prof_end(s);
     void* t = src;
     src = dst;
@@ -491,7 +573,8 @@ static int check_infer_args(const float* weights, const float* contone, const ui
     return fail(HS_EINVAL, "%s: null pointer", who);
   if (precision != HS_FP32 && precision != HS_BF16 && precision != HS_FP16)
     return fail(HS_EUNSUPPORTED, "%s: precision %d", who, precision);
-  if (noise_kind != HS_NOISE_GAUSS && noise_kind != HS_NOISE_UNIFORM)
+  const int kind = noise_kind & ~HS_CHECK_FINITE;
+  if (kind != HS_NOISE_GAUSS && kind != HS_NOISE_UNIFORM)
     return fail(HS_EINVAL, "%s: noise kind %d", who, noise_kind);
   if (!(recheck_tau >= 0.0f)) return fail(HS_EINVAL, "%s: recheck_tau < 0", who);
   return HS_OK;
@@ -509,14 +592,26 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
     return fail(HS_EWORKSPACE, "halftone_infer: workspace too small");
   if ((rc = check_device())) return rc;
   hipStream_t s = (hipStream_t)stream;
+  const int kind = noise_kind & ~HS_CHECK_FINITE;
+  const size_t N = (size_t)B * H * W;
   if (precision != HS_FP32) {
     const std::vector<int> sh = uniform_shapes(B, H, W);
-    return infer_bf16(weights, contone, seeds, sh.data(), B, (size_t)B * H * W, nullptr,
-                      noise_kind, recheck_tau, make_levels(2), precision == HS_FP16, bits,
-                      logits_or_null, stats_or_null, workspace, s);
+    if (noise_kind & HS_CHECK_FINITE) {
+      Bf16Ws w;
+      bf16_ws(sh.data(), B, N, &w, workspace);
+      if ((rc = check_finite({{contone, N}}, w.cnt + CNT_FINITE, s, "halftone_infer"))) return rc;
+    }
+    return infer_bf16(weights, nullptr, contone, seeds, sh.data(), B, N, nullptr, kind,
+                      recheck_tau, default_tau2(recheck_tau), make_levels(2),
+                      precision == HS_FP16, bits, logits_or_null, stats_or_null, workspace, s);
+  }
+  if (noise_kind & HS_CHECK_FINITE) {
+    int* cnt;
+    fp32_ws(B, H, W, nullptr, &cnt, workspace);
+    if ((rc = check_finite({{contone, N}}, cnt + CNT_FINITE, s, "halftone_infer"))) return rc;
   }
   if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
-  return infer_fp32(weights, contone, seeds, B, H, W, noise_kind, make_levels(2), bits,
+  return infer_fp32(weights, nullptr, contone, seeds, B, H, W, kind, make_levels(2), bits,
                     logits_or_null, workspace, s);
 }
 
@@ -547,11 +642,12 @@ size_t halftone_infer_pages_workspace_size(int npages, const int32_t* shapes_hos
   return m;
 }
 
-static int infer_pages(const float* weights, const float* contone, const uint64_t* seeds,
-                       int npages, const int32_t* shapes_host, int levels, int noise_kind,
-                       int precision, float recheck_tau, uint8_t* out, float* logits_or_null,
-                       int32_t* stats_or_null, void* workspace, size_t workspace_bytes,
-                       void* stream, const char* who) {
+// pp: packed weights (a packed policy) or null; tau2 < 0: the default rule.
+static int infer_pages(const float* weights, const Packed* pp, const float* contone,
+                       const uint64_t* seeds, int npages, const int32_t* shapes_host, int levels,
+                       int noise_kind, int precision, float recheck_tau, float tau2, uint8_t* out,
+                       float* logits_or_null, int32_t* stats_or_null, void* workspace,
+                       size_t workspace_bytes, void* stream, const char* who) {
   int rc = check_infer_args(weights, contone, seeds, out, workspace, noise_kind, precision,
                             recheck_tau, who);
   if (rc) return rc;
@@ -565,30 +661,50 @@ static int infer_pages(const float* weights, const float* contone, const uint64_
   if ((rc = check_device())) return rc;
   hipStream_t s = (hipStream_t)stream;
   const Levels lv = make_levels(levels);
+  const int kind = noise_kind & ~HS_CHECK_FINITE;
   if (precision != HS_FP32) {
-    std::vector<Page> pages(npages);
-    long long off = 0, vstart = 0;
-    for (int p = 0; p < npages; ++p) {
-      const int H = shapes_host[2 * p], W = shapes_host[2 * p + 1];
-      pages[p].off = off;
-      pages[p].vstart = vstart;
-      pages[p].H = H;
-      pages[p].W = W;
-      pages[p].nstrip = fused_strips(W);
-      pages[p].pad = 0;
-      off += (long long)H * W;
-      vstart += (long long)fused_strips(W) * (H + fused_fill());
+    if (noise_kind & HS_CHECK_FINITE) {
+      Bf16Ws w;
+      bf16_ws(shapes_host, npages, N, &w, workspace);
+      if ((rc = check_finite({{contone, N}}, w.cnt + CNT_FINITE, s, who))) return rc;
     }
-    return infer_bf16(weights, contone, seeds, shapes_host, npages, N, pages.data(), noise_kind,
-                      recheck_tau, lv, precision == HS_FP16, out, logits_or_null, stats_or_null,
-                      workspace, s);
+    bool uniform = true;
+    for (int p = 1; p < npages; ++p)
+      uniform = uniform && shapes_host[2 * p] == shapes_host[0] &&
+                shapes_host[2 * p + 1] == shapes_host[1];
+    std::vector<Page> pages;
+    if (!uniform) {  // a uniform batch's table is written on the device
+      pages.resize(npages);
+      long long off = 0, vstart = 0;
+      for (int p = 0; p < npages; ++p) {
+        const int H = shapes_host[2 * p], W = shapes_host[2 * p + 1];
+        pages[p].off = off;
+        pages[p].vstart = vstart;
+        pages[p].H = H;
+        pages[p].W = W;
+        pages[p].nstrip = fused_strips(W);
+        pages[p].pad = 0;
+        off += (long long)H * W;
+        vstart += (long long)fused_strips(W) * (H + fused_fill());
+      }
+    }
+    return infer_bf16(weights, pp, contone, seeds, shapes_host, npages, N,
+                      uniform ? nullptr : pages.data(), kind, recheck_tau,
+                      tau2 < 0.0f ? default_tau2(recheck_tau) : tau2, lv, precision == HS_FP16,
+                      out, logits_or_null, stats_or_null, workspace, s);
+  }
+  if (noise_kind & HS_CHECK_FINITE) {
+    int* cnt;
+    fp32_ws(1, shapes_host[0], shapes_host[1], nullptr, &cnt, workspace);
+    if ((rc = check_finite({{contone, N}}, cnt + CNT_FINITE, s, who))) return rc;
   }
   if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
+  if (pp) weights = pp->w;
   long long off = 0;
   for (int p = 0; p < npages; ++p) {
     const int H = shapes_host[2 * p], W = shapes_host[2 * p + 1];
-    rc = infer_fp32(weights, contone + off, seeds + p, 1, H, W, noise_kind, lv, out + off,
-                    logits_or_null ? logits_or_null + off : nullptr, workspace, s);
+    rc = infer_fp32(weights, pp ? pp->pack32 : nullptr, contone + off, seeds + p, 1, H, W, kind,
+                    lv, out + off, logits_or_null ? logits_or_null + off : nullptr, workspace, s);
     if (rc) return rc;
     off += (long long)H * W;
   }
@@ -600,9 +716,9 @@ int halftone_infer_pages(const float* weights, const float* contone, const uint6
                          float recheck_tau, uint8_t* bits, float* logits_or_null,
                          int32_t* stats_or_null, void* workspace, size_t workspace_bytes,
                          void* stream) {
-  return infer_pages(weights, contone, seeds, npages, shapes_host, 2, noise_kind, precision,
-                     recheck_tau, bits, logits_or_null, stats_or_null, workspace,
-                     workspace_bytes, stream, "halftone_infer_pages");
+  return infer_pages(weights, nullptr, contone, seeds, npages, shapes_host, 2, noise_kind,
+                     precision, recheck_tau, -1.0f, bits, logits_or_null, stats_or_null,
+                     workspace, workspace_bytes, stream, "halftone_infer_pages");
 }
 
 int halftone_infer_levels(const float* weights, const float* contone, const uint64_t* seeds,
@@ -610,9 +726,57 @@ int halftone_infer_levels(const float* weights, const float* contone, const uint
                           int precision, float recheck_tau, uint8_t* levels_out,
                           float* logits_or_null, int32_t* stats_or_null, void* workspace,
                           size_t workspace_bytes, void* stream) {
-  return infer_pages(weights, contone, seeds, npages, shapes_host, levels, noise_kind, precision,
-                     recheck_tau, levels_out, logits_or_null, stats_or_null, workspace,
-                     workspace_bytes, stream, "halftone_infer_levels");
+  return infer_pages(weights, nullptr, contone, seeds, npages, shapes_host, levels, noise_kind,
+                     precision, recheck_tau, -1.0f, levels_out, logits_or_null, stats_or_null,
+                     workspace, workspace_bytes, stream, "halftone_infer_levels");
+}
+
+// ------------------------------------------------------ packed policies --
+size_t halftone_policy_bytes(void) { return policy_layout(nullptr, nullptr); }
+
+int halftone_policy_pack(hs_policy* policy, const float* weights, void* mem, size_t bytes,
+                         int flags, void* stream) {
+  if (!policy || !weights || !mem) return fail(HS_EINVAL, "halftone_policy_pack: null pointer");
+  if (flags & ~HS_CHECK_FINITE) return fail(HS_EINVAL, "halftone_policy_pack: flags 0x%x", flags);
+  if ((uintptr_t)mem & 255) return fail(HS_EINVAL, "halftone_policy_pack: mem not 256-byte aligned");
+  if (bytes < halftone_policy_bytes())
+    return fail(HS_EWORKSPACE, "halftone_policy_pack: %zu bytes, %zu needed", bytes,
+                halftone_policy_bytes());
+  int rc = check_device();
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  policy->packed = 0;
+  Packed pk;
+  policy_layout(mem, &pk);
+  if ((flags & HS_CHECK_FINITE) &&
+      (rc = check_finite({{weights, (size_t)NPARAM}}, pk.needs_all + 8, s, "halftone_policy_pack")))
+    return rc;
+  HS_TRY(hipMemcpyAsync(pk.w, weights, (size_t)NPARAM * 4, hipMemcpyDeviceToDevice, s));
+  const PackPrologue none{nullptr, 0, nullptr, 0, nullptr, 0, 0, 0};
+  HS_TRY(launch_fused_pack(pk.w, pk.frags, pk.frags16, pk.needs_all, none, s));
+  HS_TRY(launch_split_pack(pk.w, pk.split, pk.split + split_frag_bytes() / 2,
+                           pk.split + split_frag_bytes(), s));
+  HS_TRY(launch_pack32(pk.w, pk.pack32, HS_FP32, 0, s));
+  policy->mem = mem;
+  policy->bytes = bytes;
+  policy->packed = 1;
+  return HS_OK;
+}
+
+int halftone_policy_infer(const hs_policy* policy, const float* contone, const uint64_t* seeds,
+                          int npages, const int32_t* shapes_host, int levels, int noise_kind,
+                          int precision, float recheck_tau, float recheck_tau2, uint8_t* out,
+                          float* logits_or_null, int32_t* stats_or_null, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+  if (!policy || !policy->packed || !policy->mem)
+    return fail(HS_EINVAL, "halftone_policy_infer: policy not packed");
+  if (!(recheck_tau2 >= 0.0f) && recheck_tau2 != -1.0f)
+    return fail(HS_EINVAL, "halftone_policy_infer: recheck_tau2 must be >= 0 or -1");
+  Packed pk;
+  policy_layout(policy->mem, &pk);
+  return infer_pages(pk.w, &pk, contone, seeds, npages, shapes_host, levels, noise_kind,
+                     precision, recheck_tau, recheck_tau2, out, logits_or_null, stats_or_null,
+                     workspace, workspace_bytes, stream, "halftone_policy_infer");
 }
 
 // ------------------------------------------------------- policy fwd / bwd --
@@ -706,6 +870,10 @@ int halftone_loss(const uint8_t* actions, const float* contone, int B, int H, in
   const int m = margin(prm);
   Carve cv(workspace);
   LossWs lw = carve_loss(cv, B, H, W, Bg, Hg, Wg, m, true);
+  if ((prm->flags & HS_CHECK_FINITE) &&
+      (rc = check_finite({{contone, (size_t)B * H * W}, {probs_gray_or_null, (size_t)Bg * Hg * Wg}},
+                         lw.flag, s, "halftone_loss")))
+    return rc;
   LossDev win;
   make_windows(*prm, &win);
   HS_TRY(launch_loss_stats(actions, contone, B, H, W, *prm, win, nullptr, lw.tiles, lw.ntiles, s));
@@ -714,6 +882,7 @@ int halftone_loss(const uint8_t* actions, const float* contone, int B, int H, in
     HS_TRY(launch_as(probs_gray_or_null, Bg, Hg, Wg, 1.0f, 0, lw.patches, nullptr, s));
   HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, prm->w_s,
                             (long)(H - 2 * m) * (W - 2 * m), out, s));
+  HS_TRY(launch_loss_total(B, prm->w_a, out, s));
   return HS_OK;
 }
 
@@ -745,6 +914,12 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
   const int m = margin(prm);
   Carve cv(workspace);
   LossWs lw = carve_loss(cv, B, H, W, Bg, Hg, Wg, m, true);
+  if ((prm->flags & HS_CHECK_FINITE) &&
+      (rc = check_finite({{contone, (size_t)B * H * W},
+                          {probs_or_null, probs_or_null ? (size_t)B * H * W : 0},
+                          {probs_gray_or_null, (size_t)Bg * Hg * Wg}},
+                         lw.flag, s, "halftone_loss_backward")))
+    return rc;
   LossDev win;
   make_windows(*prm, &win);
   HS_TRY(launch_loss_stats(actions, contone, B, H, W, *prm, win, lw.maps, lw.tiles, lw.ntiles, s));
@@ -777,7 +952,7 @@ static size_t train_ws(int B, int H, int W, int Bg, int Hg, int Wg, int prec, bo
   float* gp = cv.take<float>(N * 4);
   float* gg = cv.take<float>((Ng ? Ng : 1) * 4);
   float* g = cv.take<float>((size_t)NPARAM * 4);
-  float* lo = cv.take<float>((size_t)(3 * B + 1) * 4);
+  float* lo = cv.take<float>((size_t)(3 * B + 2) * 4);
   if (pw) *pw = p;
   if (lw) *lw = l;
   if (probs) *probs = pr;
@@ -842,6 +1017,10 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
            &probs_g, &act, &gradp, &gradg, &grad, &loss_out);
   lw.ntiles = ((H - 2 * m + 15) / 16) * ((W - 2 * m + 15) / 16);
   const hs_loss_params& lp = tp->loss;
+  if ((lp.flags & HS_CHECK_FINITE) &&
+      (rc = check_finite({{contones, (size_t)B * H * W}, {gray, (size_t)Bg * Hg * Wg}}, lw.flag,
+                         s, "policy_train_step")))
+    return rc;
   const int kind = tp->noise_kind;
   const uint32_t st = (uint32_t)step;
   // batch: forward, actions, policy gradient (logit space), backward
@@ -877,7 +1056,7 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   if (grad_out_or_null)
     HS_TRY(hipMemcpyAsync(grad_out_or_null, grad, (size_t)NPARAM * 4, hipMemcpyDeviceToDevice, s));
   HS_TRY(launch_train_metrics(loss_out, B, grad, NPARAM, act, (size_t)B * H * W, lp.levels,
-                              (float)lr, metrics, pw.counter, s));
+                              (float)lr, lp.w_a, metrics, pw.counter, s));
   HS_TRY(launch_adam(weights, adam_m, adam_v, grad, NPARAM, (float)lr, tp->beta1, tp->beta2,
                      tp->eps, (float)c1, (float)c2, s));
   if (actions_out_or_null)

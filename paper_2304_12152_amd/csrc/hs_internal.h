@@ -109,6 +109,8 @@ hipError_t launch_conv_last(const void* in, const float* w, int B, int H, int W,
                             const Levels& lv, hipStream_t s);
 // infer.hip: the fused BF16 pass
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
+// *count (zeroed beforehand) += the NaN and infinite values of x[0, n)
+hipError_t launch_count_nonfinite(const float* x, size_t n, int* count, hipStream_t s);
 size_t fused_frag_bytes();
 // Set-up folded into the fragment packing launch: zero0[0..n0) and
 // zero1[0..n1) cleared (null / 0 to skip), and when pages is set the page
@@ -125,6 +127,8 @@ struct PackPrologue {
 // and *needs_all: 1 unless a priori bounds keep FP16 layers 1..4 in range
 hipError_t launch_fused_pack(const float* w, void* frags, void* frags16, int* needs_all,
                              const PackPrologue& pro, hipStream_t s);
+// the prologue alone (weights packed beforehand)
+hipError_t launch_prologue(const PackPrologue& pro, hipStream_t s);
 // persistent fused inference over pages (one launch for all of them;
 // shapes_host = [npages][H, W] as in the device page table); the recheck
 // list is segmented (two segments per workgroup, counts in seg_count; list
@@ -190,6 +194,8 @@ hipError_t launch_loss_stats(const uint8_t* h, const float* c, int B, int H, int
 hipError_t launch_loss_reduce(const float* tile_partials, int B, int ntiles_per_img,
                               const float* as_partials, int npatch, float w_s, long M, float* out,
                               hipStream_t s);
+// out[3B + 1] = -mean_b out[3b + 2] + w_a out[3B] (after launch_loss_reduce)
+hipError_t launch_loss_total(int B, float w_a, float* out, hipStream_t s);
 // per-pixel policy gradient from the toggle differences dR (Local Expectation
 // or COMA, p.estimator); probs may be null only for LE in probability space
 hipError_t launch_le_grad(const uint8_t* h, const float* c, const float* probs, int logit_space,
@@ -204,7 +210,8 @@ hipError_t launch_adam(float* w, float* m, float* v, const float* g, int n, floa
                        float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_train_metrics(const float* loss_out, int B, const float* grad, int n,
                                 const uint8_t* actions, size_t nact, int levels, float lr,
-                                float* metrics, unsigned long long* counter, hipStream_t s);
+                                float w_a, float* metrics, unsigned long long* counter,
+                                hipStream_t s);
 
 // spectrum.hip
 int spectrum_rings(int P);

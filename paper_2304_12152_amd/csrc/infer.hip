@@ -17,12 +17,31 @@ __global__ void zero_ints_kernel(int* p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// *count (zeroed before) += number of NaN / infinite values in x[0, n):
+// exponent bits all ones. One atomic per wave that found any.
+__global__ void count_nonfinite_kernel(const float* __restrict__ x, size_t n, int* count) {
+  int bad = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    bad += ((__float_as_uint(x[i]) & 0x7F800000u) == 0x7F800000u) ? 1 : 0;
+  for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o);
+  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(count, bad);
+}
+
 }  // namespace
 
 namespace hs {
 
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
   zero_ints_kernel<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const float* x, size_t n, int* count, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  count_nonfinite_kernel<<<(unsigned)blocks, 256, 0, s>>>(x, n, count);
   return hipGetLastError();
 }
 
@@ -170,6 +189,16 @@ __global__ void pack_fused_kernel(const float* __restrict__ w, __bf16* __restric
     for (int c = 0; c < 32; ++c) over = over || !(bound[c] < FP16_SAFE);
   }
   if (t == 0) *needs_all = over ? 1 : 0;
+}
+
+// The set-up of a call whose weights are already packed: the counters and
+// the uniform page table of the pack prologue, without the packing.
+__global__ void prologue_kernel(const hs::PackPrologue pro) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < pro.n0) pro.zero0[gid] = 0;
+  if (gid < pro.n1) pro.zero1[gid] = 0;
+  if (pro.pages)
+    for (int b = gid; b < pro.B; b += gridDim.x * blockDim.x) pro.pages[b] = uniform_page(b, pro.H, pro.W);
 }
 
 // The 16-bit element type of the fused pass: BF16, or FP16 (three more
@@ -618,6 +647,11 @@ size_t fused_frag_bytes() { return (size_t)FRAG_TOTAL * 16; }
 hipError_t launch_fused_pack(const float* w, void* frags, void* frags16, int* needs_all,
                              const PackPrologue& pro, hipStream_t s) {
   pack_fused_kernel<<<38, 256, 0, s>>>(w, (__bf16*)frags, (_Float16*)frags16, needs_all, pro);
+  return hipGetLastError();
+}
+
+hipError_t launch_prologue(const PackPrologue& pro, hipStream_t s) {
+  prologue_kernel<<<1, 256, 0, s>>>(pro);
   return hipGetLastError();
 }
 

@@ -172,6 +172,15 @@ __global__ void loss_reduce_kernel(const float* __restrict__ partials, int B, in
   }
 }
 
+// The total training loss of the batch, -mean_b R_b + w_a L_AS, after the
+// per-image rewards and L_AS are in out (images summed in order).
+__global__ void loss_total_kernel(int B, float w_a, float* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  float r = 0.0f;
+  for (int b = 0; b < B; ++b) r += out[3 * b + 2];
+  out[3 * B + 1] = -r / (float)B + w_a * out[3 * B];
+}
+
 // MULTI: multitone levels (q.levels > 2), with the var_h map; otherwise the
 // binary form, whose var_h is mu_h (1 - mu_h)
 template <bool MULTI>
@@ -500,6 +509,11 @@ hipError_t launch_loss_reduce(const float* tile_partials, int B, int ntiles_per_
                               hipStream_t s) {
   loss_reduce_kernel<<<B + 1, 256, 0, s>>>(tile_partials, B, ntiles_per_img, as_partials, npatch,
                                            w_s, (float)(1.0 / (double)M), out);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_total(int B, float w_a, float* out, hipStream_t s) {
+  loss_total_kernel<<<1, 64, 0, s>>>(B, w_a, out);
   return hipGetLastError();
 }
 

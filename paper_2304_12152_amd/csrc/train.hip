@@ -55,7 +55,7 @@ __global__ __launch_bounds__(1024) void metrics_kernel(const float* __restrict__
                                                       const float* __restrict__ grad, int n,
                                                       const unsigned long long* __restrict__ ones,
                                                       size_t nact, int levels, float lr,
-                                                      float* __restrict__ metrics) {
+                                                      float w_a, float* __restrict__ metrics) {
   __shared__ float red[16];
   float s = 0.0f;
   for (int i = threadIdx.x; i < n; i += 1024) s = fmaf(grad[i], grad[i], s);
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(1024) void metrics_kernel(const float* __restrict__
   for (int k = 0; k < 16; ++k) g2 += red[k];
   metrics[5] = sqrtf(g2);
   metrics[6] = (float)((double)*ones / ((double)nact * (levels - 1)));
-  metrics[7] = 0.0f;
+  metrics[7] = -metrics[2] + w_a * metrics[3];
 }
 
 __global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
@@ -96,13 +96,15 @@ hipError_t launch_adam(float* w, float* m, float* v, const float* g, int n, floa
 
 hipError_t launch_train_metrics(const float* loss_out, int B, const float* grad, int n,
                                 const uint8_t* actions, size_t nact, int levels, float lr,
-                                float* metrics, unsigned long long* counter, hipStream_t s) {
+                                float w_a, float* metrics, unsigned long long* counter,
+                                hipStream_t s) {
   zero_u64_kernel<<<1, 1, 0, s>>>(counter);
   size_t blocks = (nact / 16 + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 1024) blocks = 1024;
   count_ones_kernel<<<(unsigned)blocks, 256, 0, s>>>(actions, nact, counter);
-  metrics_kernel<<<1, 1024, 0, s>>>(loss_out, B, grad, n, counter, nact, levels, lr, metrics);
+  metrics_kernel<<<1, 1024, 0, s>>>(loss_out, B, grad, n, counter, nact, levels, lr, w_a,
+                                    metrics);
   return hipGetLastError();
 }
 

@@ -281,3 +281,52 @@ def test_host_error_diffusion_levels_matches_oracle(orc, lib, L):
         assert np.array_equal(got, hb.halftone_error_diffusion_host(c).numpy())
     with pytest.raises(hb.HalftoneError):
         hb.halftone_error_diffusion_levels_host(c, 9)
+
+
+def test_policy_handle_argument_errors(lib):
+    p = _fake()
+    n = lib.halftone_policy_bytes()
+    # the FP32 weight copy, the BF16 and FP16 fragments, the split and FP32
+    # recheck copies and the FP32 per-layer fragments
+    assert n >= 37889 * 4 + 2 * 4800 * 16 + 2 * 36864 * 2 + 4 * 9216 * 4 + 4 * 9216 * 4
+    pol = hb.HsPolicy()
+    # before any device work: null pointers, bad flags, misaligned or short memory
+    assert lib.halftone_policy_pack(None, p, p, n, 0, None) == hb.HS_EINVAL
+    assert lib.halftone_policy_pack(ctypes.byref(pol), None, p, n, 0, None) == hb.HS_EINVAL
+    assert lib.halftone_policy_pack(ctypes.byref(pol), p, p, n, 0x2, None) == hb.HS_EINVAL
+    assert lib.halftone_policy_pack(ctypes.byref(pol), p, ctypes.c_void_p(4096 + 8), n, 0,
+                                    None) == hb.HS_EINVAL
+    assert lib.halftone_policy_pack(ctypes.byref(pol), p, ctypes.c_void_p(4096), n - 1, 0,
+                                    None) == hb.HS_EWORKSPACE
+    assert pol.packed == 0
+    sh = hb.page_shapes_array([(8, 8)])
+    shp = sh.ctypes.data_as(ctypes.c_void_p)
+    ws = lib.halftone_infer_pages_workspace_size(1, shp, hb.HS_BF16)
+    args = [ctypes.byref(pol), p, p, 1, shp, 2, 0, hb.HS_BF16, 0.05, -1.0, p, None, None, p, ws,
+            None]
+    assert lib.halftone_policy_infer(*args) == hb.HS_EINVAL  # not packed
+    assert b"not packed" in lib.halftone_last_error()
+    a = list(args); a[0] = None
+    assert lib.halftone_policy_infer(*a) == hb.HS_EINVAL
+    pol.packed, pol.mem, pol.bytes = 1, 4096, n  # a packed-looking handle: argument checks only
+    a = list(args); a[9] = -0.5
+    assert lib.halftone_policy_infer(*a) == hb.HS_EINVAL
+    a = list(args); a[5] = 9
+    assert lib.halftone_policy_infer(*a) == hb.HS_EINVAL
+    a = list(args); a[14] = ws - 1
+    assert lib.halftone_policy_infer(*a) == hb.HS_EWORKSPACE
+    a = list(args); a[1] = None
+    assert lib.halftone_policy_infer(*a) == hb.HS_EINVAL
+
+
+def test_finite_check_flag_is_validated(lib):
+    p = _fake()
+    ws = lib.halftone_infer_workspace_size(1, 8, 8, hb.HS_FP32)
+    args = [p, p, p, 1, 8, 8, 0, hb.HS_FP32, 0.05, p, None, None, p, ws, None]
+    a = list(args); a[6] = hb.HS_CHECK_FINITE | 0x2  # unknown noise kind under the flag
+    assert lib.halftone_infer(*a) == hb.HS_EINVAL
+    prm = hb.default_loss_params(flags=0x4)  # unknown loss flag
+    lws = lib.halftone_loss_workspace_size(1, 16, 16, 0, 0, 0, ctypes.byref(prm))
+    assert lib.halftone_loss(p, p, 1, 16, 16, None, 0, 0, 0, ctypes.byref(prm), p, p, lws,
+                             None) == hb.HS_EINVAL
+    assert hb.default_loss_params().flags == 0

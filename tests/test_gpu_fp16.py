@@ -42,7 +42,7 @@ def test_fp16_with_recheck_matches_oracle(orc, shape):
     assert np.array_equal(bits[m], (ref >= 0)[m].astype(np.uint8))
     near = np.abs(lg) < TAU16
     assert np.abs(lg[near] - ref[near]).max(initial=0.0) <= 5e-4
-    nearer = np.abs(lg) < 1.5e-4  # tau2 = clamp(tau / 64, 1.5e-4, 1e-2)
+    nearer = np.abs(lg) < 1.5e-4  # tau2 = max(tau / 64, 1.5e-4)
     assert np.abs(lg[nearer] - ref[nearer]).max(initial=0.0) <= 2e-5 * max(1.0, np.abs(ref).max())
     assert np.abs(lg - ref).max() < TAU16
     assert st[0] >= near.sum() and 0 <= st[1] <= st[0] and 0 <= st[2] <= st[0]
@@ -90,7 +90,7 @@ def test_fp16_overflow_reruns_in_bf16(orc):
     call then decides every pixel from the BF16 pass with an 8 times wider
     band. Power-of-two scaling is exact in BF16 and FP32, so the result
     equals the unscaled network's BF16 result bit for bit, except that the
-    split stage keeps the FP16 call's tau2 (clamp(tau / 64, 1.5e-4, 1e-2)),
+    split stage keeps the FP16 call's tau2 (max(tau / 64, 1.5e-4)),
     so pixels between the two tau2 are decided by different stages."""
     B, H, W = 2, 40, 150
     seeds = [41, 42]

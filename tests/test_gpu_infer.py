@@ -62,7 +62,7 @@ def test_bf16_with_recheck_matches_oracle(orc, shape):
     # within tau2 of the threshold, the FP32 one; the others a BF16 logit
     near = np.abs(lg) < tau
     assert np.abs(lg[near] - ref[near]).max(initial=0.0) <= 5e-4
-    tau2 = min(max(tau / 64, 5e-4), 1e-2)
+    tau2 = max(tau / 64, 1.5e-4)
     nearer = np.abs(lg) < tau2
     assert np.abs(lg[nearer] - ref[nearer]).max(initial=0.0) <= 2e-5 * max(1.0, np.abs(ref).max())
     assert np.abs(lg - ref).max() < tau
@@ -74,23 +74,34 @@ def test_split_stage_on_every_pixel(orc, shape):
     """recheck_tau above every |x|: every pixel goes through the split-BF16
     cone pipeline (thousands of two-cone batches per launch, cones at every
     border); each logit it returns must be within the split error of the
-    oracle's, and those it hands to the FP32 stage within FP32 rounding."""
+    oracle's, and those it hands to the FP32 stage (an explicit tau2 of a
+    packed policy) within FP32 rounding."""
     B, H, W = shape
     seeds = list(range(31, 31 + B))
     _say("infer split stage on every pixel", shape)
     w, c = inputs(seeds, H, W)
     ref = _oracle_logits(orc, w, c, seeds, 0)
-    tau = 1e9
-    bits, lg, st = hb.halftone_infer(to_dev(w), to_dev(c), seeds_t(seeds), 0, hb.HS_BF16, tau,
-                                     logits=True, stats=True)
+    tau, tau2 = 1e9, 1e-2
+    pol = hb.Policy(to_dev(w))
+    bits, lg, st = hb.halftone_policy_infer(pol, to_dev(c), seeds_t(seeds), precision=hb.HS_BF16,
+                                            recheck_tau=tau, recheck_tau2=tau2, logits=True,
+                                            stats=True)
     bits, lg, st = bits.cpu().numpy(), lg.cpu().numpy(), st.cpu().numpy()
     assert st[0] == B * H * W
     assert np.abs(lg - ref).max() <= 5e-4
-    tau2 = 1e-2
     nearer = np.abs(lg) < tau2
     assert np.abs(lg[nearer] - ref[nearer]).max(initial=0.0) <= 2e-5 * max(1.0, np.abs(ref).max())
     assert abs(int(st[2]) - int(nearer.sum())) <= 2
     m = parity_mask(orc, ref)
+    assert np.array_equal(bits[m], (ref >= 0)[m].astype(np.uint8))
+    # the default band rule tau2 = max(tau / 64, 1.5e-4) sends every pixel on
+    # to the FP32 stage at this tau
+    bits, lg, st = hb.halftone_infer(to_dev(w), to_dev(c), seeds_t(seeds), 0, hb.HS_BF16, tau,
+                                     logits=True, stats=True)
+    st = st.cpu().numpy()
+    assert st[0] == st[2] == B * H * W
+    assert np.abs(lg.cpu().numpy() - ref).max() <= 2e-5 * max(1.0, np.abs(ref).max())
+    bits = bits.cpu().numpy()
     assert np.array_equal(bits[m], (ref >= 0)[m].astype(np.uint8))
 
 
@@ -132,7 +143,7 @@ def test_c2_full_size_sampled(orc):
     near = np.abs(l16) < 0.055
     assert int(stats[0]) >= int(near.sum()) > 0
     assert np.abs(l16[near] - l32[near]).max() <= 5e-4
-    nearer = np.abs(l16) < min(max(0.055 / 64, 5e-4), 1e-2)
+    nearer = np.abs(l16) < max(0.055 / 64, 1.5e-4)
     assert np.abs(l16[nearer] - l32[nearer]).max() <= 1e-4
 
 

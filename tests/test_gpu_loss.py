@@ -29,6 +29,9 @@ def test_loss_matches_oracle(orc, shape):
     ref = orc.reward(h.astype(np.float64), c.astype(np.float64))
     np.testing.assert_allclose(out[:3 * B].reshape(B, 3), ref, rtol=1e-5, atol=1e-8)
     assert out[3 * B] == 0.0
+    # the library's total loss, -mean R (no gray batch)
+    total = -ref[:, 2].mean()
+    assert abs(out[3 * B + 1] - total) <= 1e-5 * abs(total) + 1e-8
 
 
 def test_loss_with_gray_batch(orc):
@@ -39,6 +42,14 @@ def test_loss_with_gray_batch(orc):
     out = hb.halftone_loss(to_dev(h), to_dev(c), to_dev(pg)).cpu().numpy()
     L, _ = orc.as_loss(pg.astype(np.float64), grad=False)
     assert abs(out[3 * B] - L) <= 1e-5 * abs(L)
+    # total loss of the batch: -mean_b R_b + w_a L_AS (Sec. III-B with Sec. IV)
+    ref = orc.reward(h.astype(np.float64), c.astype(np.float64))
+    total = -ref[:, 2].mean() + 0.002 * L
+    assert abs(out[3 * B + 1] - total) <= 1e-5 * abs(total)
+    big = hb.default_loss_params(w_a=0.5)
+    out2 = hb.halftone_loss(to_dev(h), to_dev(c), to_dev(pg), prm=big).cpu().numpy()
+    total2 = -ref[:, 2].mean() + 0.5 * L
+    assert abs(out2[3 * B + 1] - total2) <= 1e-5 * abs(total2)
 
 
 @pytest.mark.parametrize("prm", [dict(), dict(w_s=1.0), dict(hvs_radius=3, ssim_radius=2,

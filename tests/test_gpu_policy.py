@@ -1,0 +1,165 @@
+"""GPU tests of the packed-policy handle and of the optional finite-input
+check (the boundary of Algorithm 1's TEST call with weights packed once).
+
+A packed policy must give exactly the outputs of the self-packing calls
+(bits, logits and statistics, every precision, uniform batches, uneven pages
+and multitone levels), must hold a copy of the weights taken at packing
+time, and its split-stage band must be settable, which exposes the split
+stage's own logit error. HS_CHECK_FINITE must turn NaN or infinite inputs
+into HS_ENONFINITE before any other work."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import inputs, parity_mask, seeds_t, to_dev
+from paper_2304_12152_amd import binding as hb
+from paper_2304_12152_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("prec", [hb.HS_FP32, hb.HS_BF16, hb.HS_FP16])
+def test_packed_policy_equals_self_packing_call(prec):
+    B, H, W = 3, 70, 131
+    seeds = [41, 42, 43]
+    _say("policy uniform", prec)
+    w, c = inputs(seeds, H, W)
+    wt, ct, st = to_dev(w), to_dev(c), seeds_t(seeds)
+    pol = hb.Policy(wt)
+    ref = hb.halftone_infer(wt, ct, st, precision=prec, logits=True, stats=True)
+    got = hb.halftone_policy_infer(pol, ct, st, precision=prec, logits=True, stats=True)
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [hb.HS_FP32, hb.HS_BF16, hb.HS_FP16])
+@pytest.mark.parametrize("levels", [2, 4])
+def test_packed_policy_pages_and_levels(prec, levels):
+    shapes = [(37, 45), (90, 260), (1, 1), (128, 64)]
+    seeds = [51, 52, 53, 54]
+    _say("policy pages", prec, levels)
+    w = synth.he_weights(42)
+    c = np.concatenate([synth.contone(s, h, ww).ravel() for s, (h, ww) in zip(seeds, shapes)])
+    wt, ct, st = to_dev(w), to_dev(c), seeds_t(seeds)
+    pol = hb.Policy(wt)
+    ref = hb.halftone_infer_pages(wt, ct, st, shapes, precision=prec, logits=True, stats=True,
+                                  levels=levels)
+    got = hb.halftone_policy_infer(pol, ct, st, shapes, precision=prec, logits=True, stats=True,
+                                   levels=levels)
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+
+
+def test_packed_policy_keeps_its_copy_of_the_weights(orc):
+    B, H, W = 2, 48, 64
+    seeds = [61, 62]
+    w, c = inputs(seeds, H, W)
+    wt, ct, st = to_dev(w), to_dev(c), seeds_t(seeds)
+    pol = hb.Policy(wt)
+    before = hb.halftone_policy_infer(pol, ct, st, logits=True)[1]
+    wt.mul_(-1.0)  # the caller's weights change after packing
+    after = hb.halftone_policy_infer(pol, ct, st, logits=True)[1]
+    assert torch.equal(before, after)
+    pol2 = hb.Policy(wt)  # packed again: the new weights
+    neg = hb.halftone_policy_infer(pol2, ct, st, logits=True)[1]
+    ref = hb.halftone_infer(wt, ct, st, logits=True)[1]
+    assert torch.equal(neg, ref)
+    # and the bits of the packed call still match the oracle off the margin
+    z = orc.noise_map(seeds, H, W, kind=0, stream=1, step=0)
+    ref64 = orc.policy_forward(w.astype(np.float64), c.astype(np.float64), z)
+    bits = hb.halftone_policy_infer(pol, ct, st).cpu().numpy()
+    m = parity_mask(orc, ref64)
+    assert np.array_equal(bits[m], (ref64 >= 0)[m].astype(np.uint8))
+
+
+def test_split_stage_band_exposes_its_error():
+    # tau huge lists every pixel; tau2 = 0 sends none to the FP32 stage, so
+    # the logits are the split stage's own: their error against the FP32
+    # path is the split error (about 2^-8 of BF16's for the He policy)
+    B, H, W = 2, 96, 120
+    seeds = [71, 72]
+    w, c = inputs(seeds, H, W)
+    wt, ct, st = to_dev(w), to_dev(c), seeds_t(seeds)
+    pol = hb.Policy(wt)
+    _, l32 = hb.halftone_infer(wt, ct, st, precision=hb.HS_FP32, logits=True)
+    _, lsp, stt = hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_BF16, recheck_tau=1e30,
+                                           recheck_tau2=0.0, logits=True, stats=True)
+    stt = stt.cpu().numpy()
+    assert stt[0] == B * H * W and stt[2] == 0
+    err = (lsp - l32).abs().max().item()
+    _, l16 = hb.halftone_infer(wt, ct, st, precision=hb.HS_BF16, recheck_tau=0.0, logits=True)
+    e16 = (l16 - l32).abs().max().item()
+    _say("split error", err, "bf16 error", e16)
+    assert 0.0 < err < e16 / 50
+    # with an explicit tau2 above that error the bits equal the FP32 path's
+    # wherever the two FP32 summation orders cannot disagree
+    bits = hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_BF16, recheck_tau=1e30,
+                                    recheck_tau2=4 * err)
+    b32 = hb.halftone_infer(wt, ct, st, precision=hb.HS_FP32)
+    off = l32.abs() > 1e-4
+    assert torch.equal(bits[off], b32[off])
+
+
+def test_finite_check_rejects_nan_and_inf(orc):
+    B, H, W = 1, 40, 40
+    w, c = inputs([81], H, W)
+    wt, st = to_dev(w), seeds_t([81])
+    bad = c.copy()
+    bad[0, 5, 7] = np.nan
+    ct = to_dev(bad)
+    for prec in (hb.HS_FP32, hb.HS_BF16):
+        with pytest.raises(hb.HalftoneError) as e:
+            hb.halftone_infer(wt, ct, st, noise_kind=hb.HS_CHECK_FINITE, precision=prec)
+        assert e.value.code == hb.HS_ENONFINITE
+        # without the flag the call runs (outputs unspecified near the NaN)
+        hb.halftone_infer(wt, ct, st, precision=prec)
+    good = to_dev(c)
+    bits = hb.halftone_infer(wt, good, st, noise_kind=hb.HS_CHECK_FINITE)
+    assert torch.equal(bits, hb.halftone_infer(wt, good, st))
+    # weights with an infinity: the pack refuses them under the flag
+    wbad = w.copy()
+    wbad[1000] = np.inf
+    with pytest.raises(hb.HalftoneError) as e:
+        hb.Policy(to_dev(wbad), check_finite=True)
+    assert e.value.code == hb.HS_ENONFINITE
+    pol = hb.Policy(wt, check_finite=True)
+    with pytest.raises(hb.HalftoneError) as e:
+        hb.halftone_policy_infer(pol, ct, st, noise_kind=hb.HS_CHECK_FINITE)
+    assert e.value.code == hb.HS_ENONFINITE
+    # the loss calls check contone and probabilities
+    h = to_dev((c > 0.5).astype(np.uint8))
+    prm = hb.default_loss_params(flags=hb.HS_CHECK_FINITE)
+    with pytest.raises(hb.HalftoneError) as e:
+        hb.halftone_loss(h, ct, prm=prm)
+    assert e.value.code == hb.HS_ENONFINITE
+    p = np.full(c.shape, 0.5, dtype=np.float32)
+    p[0, 0, 0] = -np.inf
+    with pytest.raises(hb.HalftoneError) as e:
+        hb.halftone_loss_backward(h, good, to_dev(p), prm=prm, grad_space=hb.HS_WRT_LOGIT)
+    assert e.value.code == hb.HS_ENONFINITE
+    out = hb.halftone_loss(h, good, prm=prm)
+    assert torch.equal(out, hb.halftone_loss(h, good))
+    # and the train step checks its contones
+    state = hb.TrainState(wt, B, H, W, 0, 0, 0, precision=hb.HS_FP32,
+                          tp=hb.default_train_params(flags=hb.HS_CHECK_FINITE))
+    with pytest.raises(hb.HalftoneError) as e:
+        hb.policy_train_step(state, ct, st, None, None, 0, 10)
+    assert e.value.code == hb.HS_ENONFINITE
+
+
+def test_train_metrics_carry_the_total_loss():
+    B, H, W = 2, 48, 48
+    w, c = inputs([91, 92], H, W)
+    gray = np.stack([np.full((64, 64), g, np.float32) for g in (0.3, 0.7)])
+    state = hb.TrainState(to_dev(w), B, H, W, 2, 64, 64, precision=hb.HS_BF16)
+    m = hb.policy_train_step(state, to_dev(c), seeds_t([91, 92]), to_dev(gray), seeds_t([5, 6]),
+                             0, 10).cpu().numpy()
+    assert m[3] > 0.0
+    assert abs(m[7] - (-m[2] + 0.002 * m[3])) <= 1e-6 * max(1.0, abs(m[7]))
