@@ -176,6 +176,29 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
                    size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
+ * halftone_infer for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same call without the workspace argument. Its
+ * workspace is a static device array of HS_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * that the library holds on each GPU it runs on until the process ends;
+ * the call allocates nothing and, without HS_CHECK_FINITE, does not
+ * synchronise.
+ *
+ * Arguments, results and errors as for halftone_infer, plus HS_EWORKSPACE
+ * when halftone_infer_workspace_size(B, H, W, precision) exceeds the
+ * scratch: about 3.6 Mpx for HS_BF16 and HS_FP16 (e.g. 3 x 1024 x 1024),
+ * about 250 kpx for HS_FP32 (256 B per pixel). Every call on one GPU uses
+ * that GPU's one array (its counters are cleared by each call), so calls
+ * that overlap on one GPU -- on different streams or from different host
+ * threads -- race and must be serialised by the caller.
+ * --------------------------------------------------------------------- */
+#define HS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int halftone_infer_noalloc(const float* weights, const float* contone, const uint64_t* seeds,
+                           int B, int H, int W, int noise_kind, int precision, float recheck_tau,
+                           uint8_t* bits, float* logits_or_null, int32_t* stats_or_null,
+                           void* stream);
+
+/* ---------------------------------------------------------------------
  * Inference over pages of different sizes (the TEST procedure of
  * Algorithm 1 on an uneven batch), with HS_BF16 or HS_FP16 in ONE persistent launch
  * of the fused kernel whose workgroups split all pages' strips evenly,

@@ -61,6 +61,7 @@ _SIGS = {
     "halftone_param_count": (ctypes.c_int64, []),
     "halftone_infer_workspace_size": (SZ, [I, I, I, I]),
     "halftone_infer": (I, [P, P, P, I, I, I, I, I, F, P, P, P, P, SZ, P]),
+    "halftone_infer_noalloc": (I, [P, P, P, I, I, I, I, I, F, P, P, P, P]),
     "halftone_infer_pages_workspace_size": (SZ, [I, P, I]),
     "halftone_infer_pages": (I, [P, P, P, I, P, I, I, F, P, P, P, P, SZ, P]),
     "halftone_infer_levels": (I, [P, P, P, I, P, I, I, I, F, P, P, P, P, SZ, P]),
@@ -174,6 +175,28 @@ def halftone_infer(weights, contone, seeds, noise_kind=HS_NOISE_GAUSS, precision
     _check(lib().halftone_infer(_ptr(weights), _ptr(contone), _ptr(seeds), B, H, W, noise_kind,
                                 precision, recheck_tau, _ptr(bits), _ptr(lg), _ptr(st), _ptr(ws),
                                 ws.numel(), _stream()))
+    out = [bits]
+    if logits:
+        out.append(lg)
+    if stats:
+        out.append(st)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def halftone_infer_noalloc(weights, contone, seeds, noise_kind=HS_NOISE_GAUSS, precision=HS_BF16,
+                           recheck_tau=None, logits=False, stats=False):
+    """halftone_infer without a workspace (the library's static scratch):
+    bits [B,H,W] uint8, and optionally logits and stats."""
+    recheck_tau = _tau(precision, recheck_tau)
+    B, H, W = contone.shape
+    dev = contone.device
+    _dev(weights, torch.float32), _dev(contone, torch.float32), _dev(seeds, torch.int64)
+    bits = torch.empty((B, H, W), dtype=torch.uint8, device=dev)
+    lg = torch.empty((B, H, W), dtype=torch.float32, device=dev) if logits else None
+    st = torch.zeros(4, dtype=torch.int32, device=dev) if stats else None
+    _check(lib().halftone_infer_noalloc(_ptr(weights), _ptr(contone), _ptr(seeds), B, H, W,
+                                        noise_kind, precision, recheck_tau, _ptr(bits), _ptr(lg),
+                                        _ptr(st), _stream()))
     out = [bits]
     if logits:
         out.append(lg)

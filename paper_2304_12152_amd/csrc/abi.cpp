@@ -615,6 +615,56 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
                     logits_or_null, workspace, s);
 }
 
+// ------------------------------------------------ inference, no allocation --
+// The workspace of halftone_infer_noalloc: one array per device, kept until
+// the process ends. In host code `scratch` names a host-side stand-in, so
+// its device address is looked up once per device (hipGetSymbolAddress with
+// that device current) and only that address is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[HS_NOALLOC_SCRATCH_BYTES];
+
+static int scratch_address(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> addr;  // per device; null until looked up
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(HS_EHIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(HS_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return HS_OK;
+}
+
+int halftone_infer_noalloc(const float* weights, const float* contone, const uint64_t* seeds,
+                           int B, int H, int W, int noise_kind, int precision, float recheck_tau,
+                           uint8_t* bits, float* logits_or_null, int32_t* stats_or_null,
+                           void* stream) {
+  // the same checks as halftone_infer, before the scratch is looked up
+  const int dummy = 0;
+  int rc = check_infer_args(weights, contone, seeds, bits, &dummy, noise_kind, precision,
+                            recheck_tau, "halftone_infer_noalloc");
+  if (rc) return rc;
+  if (!shape_ok(B, H, W))
+    return fail(HS_ESHAPE, "halftone_infer_noalloc: bad shape %d x %d x %d", B, H, W);
+  const size_t need = halftone_infer_workspace_size(B, H, W, precision);
+  if (need > (size_t)HS_NOALLOC_SCRATCH_BYTES)
+    return fail(HS_EWORKSPACE,
+                "halftone_infer_noalloc: %d x %d x %d needs %zu bytes of workspace, more than "
+                "the %zu-byte static scratch",
+                B, H, W, need, (size_t)HS_NOALLOC_SCRATCH_BYTES);
+  if ((rc = check_device())) return rc;
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  return halftone_infer(weights, contone, seeds, B, H, W, noise_kind, precision, recheck_tau, bits,
+                        logits_or_null, stats_or_null, ws, (size_t)HS_NOALLOC_SCRATCH_BYTES,
+                        stream);
+}
+
 // Page shapes: every page at least 1 x 1 and the total under 2^31 pixels.
 static bool pages_ok(int npages, const int32_t* shapes, size_t* N) {
   if (npages < 1 || !shapes) return false;
