@@ -63,20 +63,44 @@ def log(*a):
 
 
 def cpu_baseline(c_img, seed, w):
-    """The oracle (plain C, FP64, one thread) on the 512 x 512 top-left crop of
-    workload image 0: noise map, policy forward, threshold."""
+    """The oracle (plain C, FP64) timed on the host: noise map, policy forward
+    and threshold, the median of 3 runs, on all of the host's cores (its conv
+    channel loops split over threads; the results are the same bits for any
+    count) over the whole of workload image 0 (1024 x 1024), and on one
+    thread over its 256 x 256 top-left crop."""
     import numpy as np
+    import platform
     import oracle.oracle as orc
-    crop = c_img[:512, :512].astype(np.float64)[None]
-    t0 = time.perf_counter()
-    z = orc.noise_map([seed], 512, 512, kind=0, stream=1, step=0)
-    x = orc.policy_forward(w.astype(np.float64), crop, z)
-    orc.threshold(x)
-    dt = time.perf_counter() - t0
-    return {"value": round(512 * 512 / dt / 1e6, 5), "unit": "Mpx/s", "cores": 1,
+    ncores = max(1, min(16, len(os.sched_getaffinity(0))))
+    w64 = w.astype(np.float64)
+
+    def run(img):
+        h, wd = img.shape
+        t0 = time.perf_counter()
+        z = orc.noise_map([seed], h, wd, kind=0, stream=1, step=0)
+        orc.threshold(orc.policy_forward(w64, img.astype(np.float64)[None], z))
+        return time.perf_counter() - t0
+
+    with orc.threads(ncores):
+        tn = sorted(run(c_img) for _ in range(3))[1]
+    with orc.threads(1):
+        t1 = sorted(run(c_img[:256, :256]) for _ in range(3))[1]
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    npx = c_img.size
+    return {"value": round(npx / tn / 1e6, 5), "unit": "Mpx/s", "cores": ncores,
             "kind": "oracle",
-            "sample": "oracle (C, FP64, 1 thread): Philox noise + 6x32 policy forward + "
-                      "threshold on the 512x512 top-left crop of workload image 0; %.1f s" % dt}
+            "sample": "oracle (C, FP64): Philox noise + 6x32 policy forward + threshold on "
+                      "workload image 0 (1024x1024), %d threads, median of 3 runs: %.2f s; "
+                      "host CPU %s" % (ncores, tn, model),
+            "single_thread": {"value": round(256 * 256 / t1 / 1e6, 5), "cores": 1,
+                              "sample": "the 256x256 top-left crop, median of 3: %.2f s" % t1}}
 
 
 def cpu_error_diffusion(hb, c):
@@ -178,7 +202,7 @@ def bench_pages(hb, synth, torch, dev, wt, steps, tau):
         return {"value": round(npx / dt / 1e6, 1), "unit": "Mpx/s",
                 "ms_per_call": round(dt * 1e3, 3), "fused_kernel_ms": round(kern_s * 1e3, 3),
                 "fused_mfma_frac": round(FLOP_PER_PX * npx / kern_s / 1e12 / PEAK_BF16_TFLOPS, 4),
-                "rechecked": stats[0], "fp32_recomputed": stats[2],
+                "rechecked": stats[0], "split_recomputed": stats[4], "fp32_recomputed": stats[2],
                 "recheck_fraction": round(stats[0] / npx, 6)}
 
     dt, kern_s, stats = timed(None)
@@ -195,14 +219,15 @@ def bench_pages(hb, synth, torch, dev, wt, steps, tau):
             "mpx": round(npx / 1e6, 2), "ms_per_call": round(dt * 1e3, 3),
             "fused_kernel_ms": round(kern_s * 1e3, 3), "fused_tflops": round(ach, 1),
             "fused_mfma_frac": round(ach / PEAK_BF16_TFLOPS, 4),
-            "rechecked": stats[0], "fp32_recomputed": stats[2],
+            "rechecked": stats[0], "split_recomputed": stats[4], "fp32_recomputed": stats[2],
             "recheck_fraction": round(stats[0] / npx, 6),
             "multitone4": {"value": round(npx / mdt / 1e6, 1), "unit": "Mpx/s",
                            "ms_per_call": round(mdt * 1e3, 3),
                            "fused_kernel_ms": round(mkern_s * 1e3, 3),
                            "fused_mfma_frac": round(FLOP_PER_PX * npx / mkern_s / 1e12 /
                                                     PEAK_BF16_TFLOPS, 4),
-                           "rechecked": mstats[0], "fp32_recomputed": mstats[2],
+                           "rechecked": mstats[0], "split_recomputed": mstats[4],
+                           "fp32_recomputed": mstats[2],
                            "recheck_fraction": round(mstats[0] / npx, 6)},
             "fp16": h}
 
@@ -229,15 +254,19 @@ def calibrate(hb, synth, torch, dev):
     res["fp16_rms_err"] = float(eh.pow(2).mean().sqrt())
     for tau in (0.004, 0.005, 0.006, 0.0075, 0.01):
         res["fp16_frac_below_%.4f" % tau] = float((lh.abs() < tau).float().mean())
-    # split-BF16 stage on every pixel of a 2 x 256 x 256 batch
-    c2 = c[:2, :256, :256].contiguous()
+    # the FP16 cone stage and the split stage, each deciding every pixel of a
+    # 2 x 512 x 512 batch (a packed policy with explicit bands)
+    c2 = c[:2, :512, :512].contiguous()
+    pol = hb.Policy(wt)
     _, a32 = hb.halftone_infer(wt, c2, st[:2], 0, hb.HS_FP32, logits=True)
-    _, a2, s2 = hb.halftone_infer(wt, c2, st[:2], 0, hb.HS_BF16, 1e9, logits=True, stats=True)
-    m = a2.abs() >= 1e-2  # decided by the split stage (tau2 is capped at 1e-2)
-    e2 = (a2 - a32).abs()[m]
-    res["split_max_err"] = float(e2.max())
-    res["split_rms_err"] = float(e2.pow(2).mean().sqrt())
-    res["split_stats"] = s2.cpu().tolist()
+    for name, t16 in (("fp16_cone", 1e-30), ("split", 0.0)):
+        _, a2, s2 = hb.halftone_policy_infer(pol, c2, st[:2], precision=hb.HS_BF16,
+                                             recheck_tau=1e30, recheck_tau16=t16,
+                                             recheck_tau2=0.0, logits=True, stats=True)
+        e2 = (a2 - a32).abs()
+        res[name + "_max_err"] = float(e2.max())
+        res[name + "_rms_err"] = float(e2.pow(2).mean().sqrt())
+        res[name + "_stats"] = s2.cpu().tolist()
     print(json.dumps(res), flush=True)
 
 
@@ -299,10 +328,13 @@ def main():
     npx = B * H * W
     ws = torch.empty(hb.lib().halftone_infer_workspace_size(B, H, W, hb.HS_BF16),
                      dtype=torch.uint8, device=dev)
+    # the weights are packed once (as a server does when it loads them); a
+    # step is one inference call over the batch with the packed policy
+    pol = hb.Policy(wt)
 
     def step():
-        return hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_BF16, args.tau,
-                                 workspace=ws)
+        return hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_BF16, recheck_tau=args.tau,
+                                        workspace=ws)
 
     if args.probe == "infer":
         step()
@@ -332,18 +364,39 @@ def main():
                 "traffic": traffic, "kernel": "fused_infer_kernel (BF16, 8x1024x1024)",
                 "kernel_ms": round(avg_kernel_s * 1e3, 4)}
 
+    # the same calls packing the weights in every call (halftone_infer)
+    def step_repack():
+        return hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_BF16, args.tau,
+                                 workspace=ws)
+
+    for _ in range(10):
+        step_repack()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_repack()
+    torch.cuda.synchronize()
+    v_repack = npx * args.steps / (time.perf_counter() - t0) / 1e6
+    log("bf16, weights packed in every call: %.1f Mpx/s" % v_repack)
+
     # recheck statistics and agreement with the FP32 path on the same batch
-    bits16, lg16, stats = hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_BF16, args.tau,
-                                            logits=True, stats=True, workspace=ws)
+    bits16, lg16, stats = hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_BF16,
+                                                   recheck_tau=args.tau, logits=True, stats=True,
+                                                   workspace=ws)
     stats = stats.cpu().tolist()
     extra = {"recheck": {"tau": args.tau, "rechecked": stats[0], "flipped": stats[1],
-                         "fp32_recomputed": stats[2], "fraction": round(stats[0] / npx, 6)}}
+                         "fp16_cone_decided": stats[0] - stats[4],
+                         "split_recomputed": stats[4], "fp32_recomputed": stats[2],
+                         "fraction": round(stats[0] / npx, 6)},
+             "repack_each_call": {"value": round(v_repack, 1), "unit": "Mpx/s",
+                                  "call": "halftone_infer (weights packed inside every call)"}}
     # the same path with an FP16 fused pass (three more mantissa bits at the
     # same matrix-core rate, so an 8 times narrower recheck band)
     tau16 = hb.RECHECK_TAU[hb.HS_FP16]
 
     def step16():
-        return hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_FP16, tau16, workspace=ws)
+        return hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_FP16, recheck_tau=tau16,
+                                        workspace=ws)
 
     # the clock drops in the host synchronisations of the stats call above
     # and takes some tens of calls to recover, as at the start
@@ -358,8 +411,8 @@ def main():
     dt16 = time.perf_counter() - t0
     kern16_ms, launches16 = hb.halftone_profile_stop()
     k16 = kern16_ms / 1e3 / max(launches16, 1)
-    bits_h, st16 = hb.halftone_infer(wt, ct, st, hb.HS_NOISE_GAUSS, hb.HS_FP16, tau16,
-                                     stats=True, workspace=ws)
+    bits_h, st16 = hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_FP16, recheck_tau=tau16,
+                                            stats=True, workspace=ws)
     st16 = st16.cpu().tolist()
     v16 = npx * args.steps / dt16 / 1e6
     extra["fp16"] = {"value": round(v16, 1), "unit": "Mpx/s",
@@ -367,7 +420,8 @@ def main():
                      "fused_kernel_ms": round(k16 * 1e3, 4),
                      "fused_mfma_frac": round(FLOP_PER_PX * npx / k16 / 1e12 / PEAK_BF16_TFLOPS, 4),
                      "tau": tau16, "rechecked": st16[0], "flipped": st16[1],
-                     "fp32_recomputed": st16[2], "overflow_rerun": st16[3],
+                     "split_recomputed": st16[4], "fp32_recomputed": st16[2],
+                     "overflow_rerun": st16[3],
                      "fraction": round(st16[0] / npx, 6)}
     log("fp16: %.3f ms/step, %.1f Mpx/s" % (dt16 * 1e3 / args.steps, v16))
     if not args.no_fp32:
@@ -442,8 +496,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": "inference: 8 x 1024x1024 synthetic contones (seeds 11..18), "
-                               "6x32 policy, He-init weights (seed 42), BF16 MFMA + FP32 "
-                               "recheck", "batch": B, "height": H, "width": W,
+                               "6x32 policy, He-init weights (seed 42) packed once, BF16 MFMA "
+                               "+ FP16/split/FP32 recheck", "batch": B, "height": H, "width": W,
                    "recheck_tau": args.tau},
         "roofline": roofline,
     }

@@ -144,18 +144,20 @@ int64_t halftone_param_count(void);
  *          |x| < recheck_tau is recomputed over its 13x13 receptive field
  *          with split-BF16 products (hi*hi + lo*hi + hi*lo, FP32
  *          accumulation, about 2^-8 of the BF16 error), and every pixel
- *          whose recomputed |x| is still below tau2 = max(recheck_tau/64,
- *          1.5e-4) is recomputed once more in FP32 and decided from that
- *          value (recheck_tau >= 0; it must exceed the largest BF16 logit
- *          error for the bits to equal FP32's off-margin, and tau2 the
- *          split stage's, about 2^-8 of it; halftone_policy_infer takes
- *          tau2 explicitly). That error
+ *          whose split |x| is still below tau2 = max(recheck_tau/64,
+ *          1.5e-4) once more in FP32, decided from that value
+ *          (recheck_tau >= 0; it must exceed the largest BF16 logit error
+ *          for the bits to equal FP32's off-margin, and tau2 the split
+ *          stage's). halftone_policy_infer takes tau2 explicitly and can
+ *          put an FP16 cone stage (FP16 products, about 1/8 of the BF16
+ *          error) with its own band tau16 in front of the split stage.
+ *          The BF16 error
  *          depends on the weights (0.042 for a He-initialised policy, 4.5
  *          for a trained one on the same images): measure it by comparing
  *          the logits of a call with recheck_tau = 0 against HS_FP32's.
- *          HS_FP16: the same with FP16 in place of BF16 in the fused pass
- *          (unit roundoff 2^-11 instead of 2^-8, so recheck_tau can be
- *          about 8 times smaller); FP16 holds at most 65504, and if any
+ *          HS_FP16: the same with FP16 in place of BF16 in the fused pass,
+ *          so recheck_tau can be about 8 times smaller (and there is no
+ *          FP16 cone stage); FP16 holds at most 65504, and if any
  *          activation of the pass overflows, the pass is run again in BF16
  *          with 8 * recheck_tau, decided on the device (no host
  *          synchronisation), and stats[3] reads 1.
@@ -163,10 +165,11 @@ int64_t halftone_param_count(void);
  *          HS_CHECK_FINITE (the contone is then checked first).
  * bits     [B][H][W] uint8 out.
  * logits_or_null [B][H][W] FP32 out: the logit each bit was decided from.
- * stats_or_null  int32[4] out: {pixels rechecked (|x_bf16| < recheck_tau),
+ * stats_or_null  int32[8] out: {pixels rechecked (|x_bf16| < recheck_tau),
  *          bits changed by the rechecks, pixels recomputed in FP32,
- *          1 if an HS_FP16 pass overflowed and was run again in BF16};
- *          zeros for HS_FP32.
+ *          1 if an HS_FP16 pass overflowed and was run again in BF16,
+ *          pixels recomputed by the split stage, 0, 0, 0}; zeros for
+ *          HS_FP32.
  * Shapes: B >= 1, H >= 1, W >= 1, B*H*W < 2^31.
  * --------------------------------------------------------------------- */
 size_t halftone_infer_workspace_size(int B, int H, int W, int precision);
@@ -262,13 +265,18 @@ int halftone_infer_levels(const float* weights, const float* contone, const uint
  * halftone_policy_infer: halftone_infer_levels (levels = 2: the bits of
  *          halftone_infer_pages) with the policy's packed copies, so the
  *          call launches no packing kernel. Arguments and results as for
- *          halftone_infer_levels, plus recheck_tau2: the split stage's
- *          band (pixels whose split-precision |x| is below it go to the
- *          FP32 stage; it must exceed the split stage's largest logit
- *          error for the weights), or -1 for the default rule of
- *          halftone_infer. recheck_tau2 = 0 with a large recheck_tau
- *          returns the split stage's logits for every listed pixel, which
- *          is how that error is measured. Workspace from
+ *          halftone_infer_levels, plus the bands of the cone stages, each
+ *          >= 0 or -1 for the default rule of halftone_infer:
+ *          recheck_tau16 the FP16 stage's after an HS_BF16 pass (pixels
+ *          whose FP16 |x| is below it go on to the split stage; it must
+ *          exceed the FP16 stage's largest logit error for the weights; 0
+ *          skips the stage) and recheck_tau2 the split stage's (pixels
+ *          below it go to the FP32 stage; it must exceed the split
+ *          stage's largest error). A large recheck_tau with
+ *          recheck_tau16 = 0 and recheck_tau2 = 0 returns the split
+ *          stage's logits for every pixel, and with recheck_tau2 = 0 and a
+ *          huge recheck_tau16 all pass the FP16 stage undecided: that is
+ *          how the errors are measured. Workspace from
  *          halftone_infer_pages_workspace_size. Calls on the same policy
  *          may overlap (the policy is only read); the work must be
  *          enqueued after the pack on a stream ordered after `stream`.
@@ -283,9 +291,10 @@ int halftone_policy_pack(hs_policy* policy, const float* weights, void* mem, siz
                          int flags, void* stream);
 int halftone_policy_infer(const hs_policy* policy, const float* contone, const uint64_t* seeds,
                           int npages, const int32_t* shapes_host, int levels, int noise_kind,
-                          int precision, float recheck_tau, float recheck_tau2, uint8_t* out,
-                          float* logits_or_null, int32_t* stats_or_null, void* workspace,
-                          size_t workspace_bytes, void* stream);
+                          int precision, float recheck_tau, float recheck_tau16,
+                          float recheck_tau2, uint8_t* out, float* logits_or_null,
+                          int32_t* stats_or_null, void* workspace, size_t workspace_bytes,
+                          void* stream);
 
 /* ---------------------------------------------------------------------
  * Training-mode policy forward and its backward (the conv stack of

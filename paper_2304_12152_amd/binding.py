@@ -67,8 +67,8 @@ _SIGS = {
     "halftone_infer_levels": (I, [P, P, P, I, P, I, I, I, F, P, P, P, P, SZ, P]),
     "halftone_policy_bytes": (SZ, []),
     "halftone_policy_pack": (I, [ctypes.POINTER(HsPolicy), P, P, SZ, I, P]),
-    "halftone_policy_infer": (I, [ctypes.POINTER(HsPolicy), P, P, I, P, I, I, I, F, F, P, P, P, P,
-                                  SZ, P]),
+    "halftone_policy_infer": (I, [ctypes.POINTER(HsPolicy), P, P, I, P, I, I, I, F, F, F, P, P, P,
+                                  P, SZ, P]),
     "halftone_policy_workspace_size": (SZ, [I, I, I, I]),
     "halftone_policy_forward": (I, [P, P, P, I, I, I, I, ctypes.c_uint32, I, P, P, SZ, P]),
     "halftone_policy_backward": (I, [P, P, P, I, I, I, I, P, P, SZ, P]),
@@ -161,7 +161,8 @@ def _tau(precision, recheck_tau):
 def halftone_infer(weights, contone, seeds, noise_kind=HS_NOISE_GAUSS, precision=HS_BF16,
                    recheck_tau=None, logits=False, stats=False, workspace=None):
     """bits [B,H,W] uint8 (and optionally logits, and stats =
-    (rechecked, flipped, recomputed in FP32, FP16 overflow re-run)).
+    (rechecked, flipped, recomputed in FP32, FP16 overflow re-run,
+    recomputed by the split stage, 0, 0, 0)).
     recheck_tau None: the band of RECHECK_TAU for the precision."""
     recheck_tau = _tau(precision, recheck_tau)
     B, H, W = contone.shape
@@ -169,7 +170,7 @@ def halftone_infer(weights, contone, seeds, noise_kind=HS_NOISE_GAUSS, precision
     _dev(weights, torch.float32), _dev(contone, torch.float32), _dev(seeds, torch.int64)
     bits = torch.empty((B, H, W), dtype=torch.uint8, device=dev)
     lg = torch.empty((B, H, W), dtype=torch.float32, device=dev) if logits else None
-    st = torch.zeros(4, dtype=torch.int32, device=dev) if stats else None
+    st = torch.zeros(8, dtype=torch.int32, device=dev) if stats else None
     need = lib().halftone_infer_workspace_size(B, H, W, precision)
     ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
     _check(lib().halftone_infer(_ptr(weights), _ptr(contone), _ptr(seeds), B, H, W, noise_kind,
@@ -193,7 +194,7 @@ def halftone_infer_noalloc(weights, contone, seeds, noise_kind=HS_NOISE_GAUSS, p
     _dev(weights, torch.float32), _dev(contone, torch.float32), _dev(seeds, torch.int64)
     bits = torch.empty((B, H, W), dtype=torch.uint8, device=dev)
     lg = torch.empty((B, H, W), dtype=torch.float32, device=dev) if logits else None
-    st = torch.zeros(4, dtype=torch.int32, device=dev) if stats else None
+    st = torch.zeros(8, dtype=torch.int32, device=dev) if stats else None
     _check(lib().halftone_infer_noalloc(_ptr(weights), _ptr(contone), _ptr(seeds), B, H, W,
                                         noise_kind, precision, recheck_tau, _ptr(bits), _ptr(lg),
                                         _ptr(st), _stream()))
@@ -228,7 +229,7 @@ def halftone_infer_pages(weights, contone, seeds, shapes, noise_kind=HS_NOISE_GA
     assert contone.numel() == N and seeds.numel() == n, (contone.numel(), N, seeds.numel(), n)
     bits = torch.empty(N, dtype=torch.uint8, device=dev)
     lg = torch.empty(N, dtype=torch.float32, device=dev) if logits else None
-    st = torch.zeros(4, dtype=torch.int32, device=dev) if stats else None
+    st = torch.zeros(8, dtype=torch.int32, device=dev) if stats else None
     shp = sh.ctypes.data_as(ctypes.c_void_p)
     need = lib().halftone_infer_pages_workspace_size(n, shp, precision)
     if need == 0:
@@ -265,11 +266,12 @@ class Policy:
 
 
 def halftone_policy_infer(policy, contone, seeds, shapes=None, noise_kind=HS_NOISE_GAUSS,
-                          precision=HS_BF16, recheck_tau=None, recheck_tau2=-1.0, logits=False,
-                          stats=False, workspace=None, levels=2):
+                          precision=HS_BF16, recheck_tau=None, recheck_tau16=-1.0,
+                          recheck_tau2=-1.0, logits=False, stats=False, workspace=None, levels=2):
     """halftone_policy_infer on a packed Policy. contone: [B,H,W] (a uniform
     batch) or the flat concatenation of pages with `shapes`; the outputs
-    have the contone's shape."""
+    have the contone's shape. The cone stages' bands recheck_tau16 and
+    recheck_tau2: -1 for the default rules."""
     recheck_tau = _tau(precision, recheck_tau)
     if shapes is None:
         B, H, W = contone.shape
@@ -281,7 +283,7 @@ def halftone_policy_infer(policy, contone, seeds, shapes=None, noise_kind=HS_NOI
     assert seeds.numel() == n
     out = torch.empty(contone.shape, dtype=torch.uint8, device=dev)
     lg = torch.empty(contone.shape, dtype=torch.float32, device=dev) if logits else None
-    st = torch.zeros(4, dtype=torch.int32, device=dev) if stats else None
+    st = torch.zeros(8, dtype=torch.int32, device=dev) if stats else None
     shp = sh.ctypes.data_as(ctypes.c_void_p)
     need = lib().halftone_infer_pages_workspace_size(n, shp, precision)
     if need == 0:
@@ -289,7 +291,8 @@ def halftone_policy_infer(policy, contone, seeds, shapes=None, noise_kind=HS_NOI
     ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, dev)
     _check(lib().halftone_policy_infer(ctypes.byref(policy.handle), _ptr(contone), _ptr(seeds), n,
                                        shp, int(levels), noise_kind, precision, recheck_tau,
-                                       recheck_tau2, _ptr(out), _ptr(lg), _ptr(st), _ptr(ws),
+                                       recheck_tau16, recheck_tau2, _ptr(out), _ptr(lg), _ptr(st),
+                                       _ptr(ws),
                                        ws.numel(), _stream()))
     res = [out]
     if logits:

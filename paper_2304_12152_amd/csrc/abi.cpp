@@ -369,6 +369,21 @@ const char* halftone_last_error(void) { return g_err.c_str(); }
 int64_t halftone_param_count(void) { return HS_PARAM_COUNT; }
 
 // ------------------------------------------------------------- inference --
+// The cone stages' weight copies in one region: split hi | lo, FP32
+// transposed, FP16.
+static size_t cone_region_bytes() {
+  return split_frag_bytes() + fp32_pack_bytes() + half_frag_bytes();
+}
+static ConeWeights cone_weights(char* region, int* wflag) {
+  ConeWeights cw;
+  cw.whi = region;
+  cw.wlo = region + split_frag_bytes() / 2;
+  cw.wt = region + split_frag_bytes();
+  cw.w16 = region + split_frag_bytes() + fp32_pack_bytes();
+  cw.wflag = wflag;
+  return cw;
+}
+
 // The packed copies of one weight set: the FP32 weights, the fused pass's
 // BF16 and FP16 fragments, its FP16 layer bounds flag, the split hi/lo and
 // transposed FP32 copies of the recheck stages, and the FP32 per-layer
@@ -385,7 +400,7 @@ static size_t policy_layout(void* base, Packed* out) {
   p.w = cv.take<float>((size_t)NPARAM * 4);
   p.frags = cv.take<char>(fused_frag_bytes());
   p.frags16 = cv.take<char>(fused_frag_bytes());
-  p.split = cv.take<char>(split_frag_bytes() + fp32_pack_bytes());
+  p.split = cv.take<char>(cone_region_bytes());
   p.pack32 = cv.take<char>(pack_bytes(HS_FP32));
   p.needs_all = cv.take<int>(64 * sizeof(int));
   if (out) *out = p;
@@ -407,7 +422,7 @@ static size_t bf16_ws(const int* shapes, int npages, size_t N, Bf16Ws* out, void
   Bf16Ws w;
   w.pack = cv.take<char>(fused_frag_bytes());
   w.pack16 = cv.take<char>(fused_frag_bytes());
-  w.split = cv.take<char>(split_frag_bytes() + fp32_pack_bytes());
+  w.split = cv.take<char>(cone_region_bytes());
   w.pages = cv.take<Page>((size_t)npages * sizeof(Page));
   const size_t ne = fused_list_entries(shapes, npages, num_cus());
   w.seglist = cv.take<uint64_t>(ne * sizeof(uint64_t));
@@ -417,10 +432,13 @@ static size_t bf16_ws(const int* shapes, int npages, size_t N, Bf16Ws* out, void
   if (out) *out = w;
   return cv.off;
 }
-// counters of the 16-bit workspace: [0, 16) cleared by the prologue, [8, 12)
-// the statistics when the caller passes none, 24 the FP16 bounds flag of a
-// self-packing call, 40 the finite check's counter
+// counters of the 16-bit workspace: [0, 24) cleared by the prologue (1 and 2
+// the lengths of the lists between the cone stages, 3 the FP16 weight flag
+// of a self-packing call, [16, 24) the statistics when the caller passes
+// none), 24 the FP16 bounds flag of a self-packing call, 40 the finite
+// check's counter
 constexpr int CNT_FINITE = 40;
+constexpr int NSTATS = 8;  // entries of the statistics array
 
 // Workspace of the FP32 path for one batch of B images of H x W.
 static size_t fp32_ws(int B, int H, int W, InferWs* out, int** cnt, void* base) {
@@ -457,6 +475,12 @@ size_t halftone_infer_workspace_size(int B, int H, int W, int precision) {
 // 1.5e-4, which is under the 4e-4 margin and 2.8 times the largest split
 // error measured for the He policy.
 static float default_tau2(float tau) { return fmaxf(tau / 64.0f, 1.5e-4f); }
+// The FP16 cone stage after a BF16 pass decides |x| >= tau16 (FP16 rounds 8
+// times finer than BF16, so a quarter of the BF16 band would leave it twice
+// its share of the error). Per listed pixel it costs about as much as the
+// split stage it would spare, so by default it is off; a packed policy's
+// call can set its band.
+static float default_tau16(float) { return 0.0f; }
 
 // The 16-bit path over a page table (one persistent fused launch for all pages):
 //   stage 1: fused BF16 (or FP16) pass, pixels with |x| < tau listed
@@ -470,37 +494,34 @@ static float default_tau2(float tau) { return fmaxf(tau / 64.0f, 1.5e-4f); }
 // into the workspace in this call.
 static int infer_bf16(const float* weights, const Packed* pp, const float* contone,
                       const uint64_t* seeds, const int* shapes, int npages, size_t N,
-                      const Page* pages_host, int noise_kind, float recheck_tau, float tau2,
-                      const Levels& lv, bool fp16, uint8_t* bits, float* logits,
+                      const Page* pages_host, int noise_kind, float recheck_tau, float tau16,
+                      float tau2, const Levels& lv, bool fp16, uint8_t* bits, float* logits,
                       int32_t* stats_or_null, void* workspace, hipStream_t s) {
   Bf16Ws w;
   bf16_ws(shapes, npages, N, &w, workspace);
-  int32_t* stats = stats_or_null ? stats_or_null : (int32_t*)(w.cnt + 8);
+  int32_t* stats = stats_or_null ? stats_or_null : (int32_t*)(w.cnt + 16);
   // counters cleared and the uniform page table written by the first launch
-  PackPrologue pro{w.cnt, 16, stats_or_null, stats_or_null ? 4 : 0,
+  PackPrologue pro{w.cnt, 24, stats_or_null, stats_or_null ? NSTATS : 0,
                    pages_host ? nullptr : w.pages, npages, shapes[0], shapes[1]};
   if (pages_host) HS_TRY(launch_put_pages(w.pages, pages_host, npages, s));
-  char* whi;
+  ConeWeights cw;
   const int* needs_all;  // FP16: layers 1..4 not cleared by their bounds
   const char *frags, *frags16;
   if (pp) {
     weights = pp->w;
-    whi = pp->split;
+    cw = cone_weights(pp->split, pp->needs_all + 16);
     needs_all = pp->needs_all;
     frags = pp->frags;
     frags16 = pp->frags16;
     HS_TRY(launch_prologue(pro, s));
   } else {
-    whi = w.split;
+    cw = cone_weights(w.split, w.cnt + 3);  // the flag cleared by the pack's prologue
     needs_all = w.cnt + 24;
     frags = w.pack;
     frags16 = w.pack16;
     HS_TRY(launch_fused_pack(weights, w.pack, fp16 ? w.pack16 : nullptr, w.cnt + 24, pro, s));
-    HS_TRY(launch_split_pack(weights, w.split, w.split + split_frag_bytes() / 2,
-                             w.split + split_frag_bytes(), s));
+    HS_TRY(launch_split_pack(weights, cw, s));
   }
-  char* wlo = whi + split_frag_bytes() / 2;
-  char* wt = whi + split_frag_bytes();
   int nseg = 0;
   long long seg_cap = 0;
   int* ovf = stats + 3;  // zeroed above
@@ -524,11 +545,26 @@ static int infer_bf16(const float* weights, const Packed* pp, const float* conto
                               8.0f * recheck_tau, lv, bits, logits, w.seglist, w.seg_count,
                               &nseg, &seg_cap, frags, FUSED_BF16, nullptr, ovf, 1, num_cus(),
                               s));
-  HS_TRY(launch_recheck_split(weights, contone, seeds, w.pages, noise_kind, w.seglist,
-                              w.seg_count, nseg, seg_cap, whi, wlo, tau2, lv, w.list2,
-                              w.cnt + 1, bits, logits, stats, num_cus(), s));
+  if (!fp16 && tau16 > 0.0f) {
+    // FP16 cones over the fused pass's list (into list2), split cones over
+    // theirs (into the fused list's memory, which is free by then), FP32
+    HS_TRY(launch_recheck_cones(true, weights, contone, seeds, w.pages, noise_kind, w.seglist,
+                                w.seg_count, nseg, seg_cap, cw, tau16, lv, w.list2, w.cnt + 1,
+                                bits, logits, stats, 0, num_cus(), s));
+    HS_TRY(launch_recheck_cones(false, weights, contone, seeds, w.pages, noise_kind, w.list2,
+                                w.cnt + 1, 1, (long long)N, cw, tau2, lv, w.seglist, w.cnt + 2,
+                                bits, logits, stats, 4, num_cus(), s));
+    HS_TRY(launch_recheck_fp32(weights, contone, seeds, w.pages, noise_kind, w.seglist,
+                               w.cnt + 2, cw.wt, lv, bits, logits, stats, 2, num_cus(), s));
+    return HS_OK;
+  }
+  // after an FP16 pass (or with tau16 = 0): split cones over the fused
+  // pass's list, then FP32
+  HS_TRY(launch_recheck_cones(false, weights, contone, seeds, w.pages, noise_kind, w.seglist,
+                              w.seg_count, nseg, seg_cap, cw, tau2, lv, w.list2, w.cnt + 1, bits,
+                              logits, stats, 0, num_cus(), s));
   HS_TRY(launch_recheck_fp32(weights, contone, seeds, w.pages, noise_kind, w.list2, w.cnt + 1,
-                             wt, lv, bits, logits, stats, 2, num_cus(), s));
+                             cw.wt, lv, bits, logits, stats, 2, num_cus(), s));
   return HS_OK;
 }
 
@@ -602,15 +638,16 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
       if ((rc = check_finite({{contone, N}}, w.cnt + CNT_FINITE, s, "halftone_infer"))) return rc;
     }
     return infer_bf16(weights, nullptr, contone, seeds, sh.data(), B, N, nullptr, kind,
-                      recheck_tau, default_tau2(recheck_tau), make_levels(2),
-                      precision == HS_FP16, bits, logits_or_null, stats_or_null, workspace, s);
+                      recheck_tau, default_tau16(recheck_tau), default_tau2(recheck_tau),
+                      make_levels(2), precision == HS_FP16, bits, logits_or_null, stats_or_null,
+                      workspace, s);
   }
   if (noise_kind & HS_CHECK_FINITE) {
     int* cnt;
     fp32_ws(B, H, W, nullptr, &cnt, workspace);
     if ((rc = check_finite({{contone, N}}, cnt + CNT_FINITE, s, "halftone_infer"))) return rc;
   }
-  if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
+  if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, NSTATS, s));
   return infer_fp32(weights, nullptr, contone, seeds, B, H, W, kind, make_levels(2), bits,
                     logits_or_null, workspace, s);
 }
@@ -692,10 +729,12 @@ size_t halftone_infer_pages_workspace_size(int npages, const int32_t* shapes_hos
   return m;
 }
 
-// pp: packed weights (a packed policy) or null; tau2 < 0: the default rule.
+// pp: packed weights (a packed policy) or null; tau16, tau2 < 0: the default
+// rules.
 static int infer_pages(const float* weights, const Packed* pp, const float* contone,
                        const uint64_t* seeds, int npages, const int32_t* shapes_host, int levels,
-                       int noise_kind, int precision, float recheck_tau, float tau2, uint8_t* out,
+                       int noise_kind, int precision, float recheck_tau, float tau16, float tau2,
+                       uint8_t* out,
                        float* logits_or_null, int32_t* stats_or_null, void* workspace,
                        size_t workspace_bytes, void* stream, const char* who) {
   int rc = check_infer_args(weights, contone, seeds, out, workspace, noise_kind, precision,
@@ -740,6 +779,7 @@ static int infer_pages(const float* weights, const Packed* pp, const float* cont
     }
     return infer_bf16(weights, pp, contone, seeds, shapes_host, npages, N,
                       uniform ? nullptr : pages.data(), kind, recheck_tau,
+                      tau16 < 0.0f ? default_tau16(recheck_tau) : tau16,
                       tau2 < 0.0f ? default_tau2(recheck_tau) : tau2, lv, precision == HS_FP16,
                       out, logits_or_null, stats_or_null, workspace, s);
   }
@@ -748,7 +788,7 @@ static int infer_pages(const float* weights, const Packed* pp, const float* cont
     fp32_ws(1, shapes_host[0], shapes_host[1], nullptr, &cnt, workspace);
     if ((rc = check_finite({{contone, N}}, cnt + CNT_FINITE, s, who))) return rc;
   }
-  if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, 4, s));
+  if (stats_or_null) HS_TRY(launch_zero_ints(stats_or_null, NSTATS, s));
   if (pp) weights = pp->w;
   long long off = 0;
   for (int p = 0; p < npages; ++p) {
@@ -767,7 +807,7 @@ int halftone_infer_pages(const float* weights, const float* contone, const uint6
                          int32_t* stats_or_null, void* workspace, size_t workspace_bytes,
                          void* stream) {
   return infer_pages(weights, nullptr, contone, seeds, npages, shapes_host, 2, noise_kind,
-                     precision, recheck_tau, -1.0f, bits, logits_or_null, stats_or_null,
+                     precision, recheck_tau, -1.0f, -1.0f, bits, logits_or_null, stats_or_null,
                      workspace, workspace_bytes, stream, "halftone_infer_pages");
 }
 
@@ -777,8 +817,8 @@ int halftone_infer_levels(const float* weights, const float* contone, const uint
                           float* logits_or_null, int32_t* stats_or_null, void* workspace,
                           size_t workspace_bytes, void* stream) {
   return infer_pages(weights, nullptr, contone, seeds, npages, shapes_host, levels, noise_kind,
-                     precision, recheck_tau, -1.0f, levels_out, logits_or_null, stats_or_null,
-                     workspace, workspace_bytes, stream, "halftone_infer_levels");
+                     precision, recheck_tau, -1.0f, -1.0f, levels_out, logits_or_null,
+                     stats_or_null, workspace, workspace_bytes, stream, "halftone_infer_levels");
 }
 
 // ------------------------------------------------------ packed policies --
@@ -803,9 +843,9 @@ int halftone_policy_pack(hs_policy* policy, const float* weights, void* mem, siz
     return rc;
   HS_TRY(hipMemcpyAsync(pk.w, weights, (size_t)NPARAM * 4, hipMemcpyDeviceToDevice, s));
   const PackPrologue none{nullptr, 0, nullptr, 0, nullptr, 0, 0, 0};
+  HS_TRY(launch_zero_ints(pk.needs_all, 64, s));
   HS_TRY(launch_fused_pack(pk.w, pk.frags, pk.frags16, pk.needs_all, none, s));
-  HS_TRY(launch_split_pack(pk.w, pk.split, pk.split + split_frag_bytes() / 2,
-                           pk.split + split_frag_bytes(), s));
+  HS_TRY(launch_split_pack(pk.w, cone_weights(pk.split, pk.needs_all + 16), s));
   HS_TRY(launch_pack32(pk.w, pk.pack32, HS_FP32, 0, s));
   policy->mem = mem;
   policy->bytes = bytes;
@@ -815,18 +855,21 @@ int halftone_policy_pack(hs_policy* policy, const float* weights, void* mem, siz
 
 int halftone_policy_infer(const hs_policy* policy, const float* contone, const uint64_t* seeds,
                           int npages, const int32_t* shapes_host, int levels, int noise_kind,
-                          int precision, float recheck_tau, float recheck_tau2, uint8_t* out,
-                          float* logits_or_null, int32_t* stats_or_null, void* workspace,
-                          size_t workspace_bytes, void* stream) {
+                          int precision, float recheck_tau, float recheck_tau16,
+                          float recheck_tau2, uint8_t* out, float* logits_or_null,
+                          int32_t* stats_or_null, void* workspace, size_t workspace_bytes,
+                          void* stream) {
   if (!policy || !policy->packed || !policy->mem)
     return fail(HS_EINVAL, "halftone_policy_infer: policy not packed");
   if (!(recheck_tau2 >= 0.0f) && recheck_tau2 != -1.0f)
     return fail(HS_EINVAL, "halftone_policy_infer: recheck_tau2 must be >= 0 or -1");
+  if (!(recheck_tau16 >= 0.0f) && recheck_tau16 != -1.0f)
+    return fail(HS_EINVAL, "halftone_policy_infer: recheck_tau16 must be >= 0 or -1");
   Packed pk;
   policy_layout(policy->mem, &pk);
   return infer_pages(pk.w, &pk, contone, seeds, npages, shapes_host, levels, noise_kind,
-                     precision, recheck_tau, recheck_tau2, out, logits_or_null, stats_or_null,
-                     workspace, workspace_bytes, stream, "halftone_policy_infer");
+                     precision, recheck_tau, recheck_tau16, recheck_tau2, out, logits_or_null,
+                     stats_or_null, workspace, workspace_bytes, stream, "halftone_policy_infer");
 }
 
 // ------------------------------------------------------- policy fwd / bwd --

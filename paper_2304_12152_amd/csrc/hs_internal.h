@@ -156,14 +156,27 @@ hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint6
                                float* logits, int32_t* stats, int count_slot, int num_cus,
                                hipStream_t s);
 size_t split_frag_bytes();
+size_t half_frag_bytes();
 size_t fp32_pack_bytes();
-hipError_t launch_split_pack(const float* w, void* whi, void* wlo, void* wt, hipStream_t s);
-hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
-                                const Page* pages, int kind, const uint64_t* seglist,
-                                const int* seg_count, int nseg, long long seg_cap,
-                                const void* whi, const void* wlo, float tau2, const Levels& lv,
-                                uint64_t* list2, int* count2, uint8_t* bits, float* logits,
-                                int32_t* stats, int num_cus, hipStream_t s);
+// the weight copies of the cone stages: split hi / lo (BF16), FP16, FP32
+// transposed, and a flag set when a weight of layers 1..5 overflows FP16
+struct ConeWeights {
+  void *whi, *wlo, *w16, *wt;
+  int* wflag;
+};
+// wflag must be zero before the launch
+hipError_t launch_split_pack(const float* w, const ConeWeights& cw, hipStream_t s);
+// one cone stage over a segmented list: the FP16 form (half) or the split
+// form; pixels at least `band` from the nearest threshold are decided, the
+// others appended to list_out (count_out); stats[total_slot] = the number
+// of input entries
+hipError_t launch_recheck_cones(bool half, const float* w, const float* contone,
+                                const uint64_t* seeds, const Page* pages, int kind,
+                                const uint64_t* seglist, const int* seg_count, int nseg,
+                                long long seg_cap, const ConeWeights& cw, float band,
+                                const Levels& lv, uint64_t* list_out, int* count_out,
+                                uint8_t* bits, float* logits, int32_t* stats, int total_slot,
+                                int num_cus, hipStream_t s);
 // g6 = grad (if probs == null) or grad * p (1 - p); writes g6 and the
 // masked input gradient of layer 6.
 hipError_t launch_dgrad_last(const float* grad, const float* probs, const void* a5,

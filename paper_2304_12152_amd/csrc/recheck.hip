@@ -4,11 +4,13 @@
 // A listed pixel is recomputed over its 13 x 13 receptive field only: layer
 // k is evaluated on the (13 - 2k) x (13 - 2k) window centred on the pixel
 // (its "cone"), with every activation outside the image forced to zero (the
-// zero 'same' padding of each layer). Two stages:
-//   split stage  every pixel the fused pass listed (|x_bf16| < tau); layers
-//                1..5 with split-BF16 products on the matrix cores, layer 6
-//                in FP32. Pixels with |x| >= tau2 are decided here, the
-//                rest listed again.
+// zero 'same' padding of each layer). Up to three stages:
+//   FP16 stage   (after a BF16 pass) every pixel the fused pass listed
+//                (|x_bf16| < tau); layers 1..5 with FP16 products on the
+//                matrix cores, layer 6 in FP32. Pixels with |x| >= tau16 are
+//                decided here, the rest listed again.
+//   split stage  the pixels still listed; the same with split-BF16
+//                products, decided at |x| >= tau2.
 //   FP32 stage   the pixels listed by the split stage, in plain FP32.
 // With multitone levels (Sec. VI-E) the same holds with |x| replaced by the
 // distance to the nearest level threshold; the output is the level.
@@ -18,18 +20,29 @@
 namespace {
 
 // ===========================================================================
-// Split stage. Every FP32 value v is carried as hi + lo with hi = bf16(v)
-// and lo = bf16(v - hi); a product is taken as hi*hi' + lo*hi' + hi*lo'
-// (lo*lo', ~2^-16 relative, is dropped), each of the three in its own FP32
-// accumulator. The result's error is ~2^-8 of the BF16 pass's.
+// Cone stages. A listed pixel's receptive field is recomputed in one of two
+// precisions by the same pipelined kernel:
+//   split (HALF = false): every FP32 value v is carried as hi + lo with
+//     hi = bf16(v) and lo = bf16(v - hi); a product is taken as
+//     hi*hi' + lo*hi' + hi*lo' (lo*lo', ~2^-16 relative, is dropped), each of
+//     the three in its own FP32 accumulator. The result's error is ~2^-8 of
+//     the BF16 pass's.
+//   FP16 (HALF = true): weights and activations of layers 1..5 rounded to
+//     FP16 (11 significant bits to BF16's 8), one product per operand pair,
+//     FP32 accumulation, layer 5's output and layer 6 in FP32: about 1/8 of
+//     the BF16 pass's error for a third of the split stage's matrix work.
+//     FP16 holds at most 65504: a cone in which any stored activation (or
+//     the contone, or a weight) would round to infinity is not decided here
+//     but passed on to the split stage.
+// Each stage decides the pixels whose recomputed logit is at least its band
+// from the nearest threshold and lists the rest for the next stage.
 //
 // The kernel is a pipeline over the listed pixels, one cone per step. Each
-// wave owns one layer (its hi weight fragments stay in registers for the
-// whole kernel, the lo fragments of all four layers sit in LDS) and up to two
-// of that layer's 16-position runs, which it computes together (twelve
-// independent MFMA chains, the next tap's operands loaded while a tap's
-// MFMAs run). In step t the stage of
-// layer k works on cone t - k:
+// wave owns one layer (its A fragments stay in registers for the whole
+// kernel; in the split form the lo fragments of all four layers sit in LDS)
+// and up to two of that layer's 16-position runs, which it computes together
+// (independent MFMA chains, the next tap's operands loaded while a tap's
+// MFMAs run). In step t the stage of layer k works on cone t - k:
 //   stage 0    the (c, z) state of the 13 x 13 window (z drawn from Philox
 //              exactly as the fused pass drew it)
 //   stage 1-5  layers 1..5 (layer 5's output kept in FP32)
@@ -39,21 +52,41 @@ namespace {
 // orders all of it. The barrier orders LDS only: the global loads issued for
 // a later step (list entries, window values) stay in flight across it.
 //
-// Waves (w and w+4 share a SIMD), balanced by their measured step times:
+// Waves (w and w+4 share a SIMD), balanced by their measured step times in
+// the split form:
 //   w0, w1, w2  layer 2, runs 0-1 / 2-3 / 4-5; layer 1, run 0 / 1 / 2
 //   w3          layer 3, runs 0-1; staging of window positions 0-63; layer 6
 //   w4          layer 3, runs 2-3
 //   w5          layer 4, runs 0-1
 //   w6          layer 5, run 0; layer 1, runs 3-5
 //   w7          layer 1, runs 6-7; staging of positions 64-168; the cone list
-// (a layer-1 run is 6 MFMAs; a layer-2..5 run 54)
+// (a layer-1 run is 2 products of 16x16x32; a layer-2..5 run 18)
 // ===========================================================================
 constexpr int SPLIT_MAXSEG = 1024;    // list segments the stage accepts
-constexpr int CREC = 128;             // bytes per staged position: 4 groups x (hi, lo) x 16 B
 constexpr int NSTAGE = 7;             // staging, layers 1..5, layer 6
 constexpr int SPLIT_THREADS = 512;
+constexpr float F16_INF_AT = 65520.0f;  // smallest value that rounds to FP16 infinity
 
-HS_DEV int crec_slot(int p, int c) { return c ^ (p & 7); }  // bank-spreading swizzle
+// the element type of a form: operand fragments, record size (bytes per
+// staged position: 4 lane groups x (hi, lo) x 16 B, or 4 x 16 B) and the
+// record's chunk swizzle (spreads a run's reads over the banks)
+template <bool HALF> struct ConeForm;
+template <> struct ConeForm<false> {
+  using op = bf16x8_t;
+  static constexpr int REC = 128;
+  static HS_DEV int slot(int p, int c) { return c ^ (p & 7); }
+  static HS_DEV f32x4_t mma(op a, op b, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct ConeForm<true> {
+  using op = f16x8_t;
+  static constexpr int REC = 64;
+  static HS_DEV int slot(int p, int c) { return c ^ (p & 3); }
+  static HS_DEV f32x4_t mma(op a, op b, f32x4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
 
 // cone record: pixel (-1: none), row, column, bit of the fused pass, page,
 // page height and width, seed (two words)
@@ -66,18 +99,14 @@ static_assert(win_runs(1) == 8 && win_runs(2) == 6 && win_runs(3) == 4 && win_ru
                   win_runs(5) == 1,
               "wave roles assume these run counts");
 
-// element i of the split fragments: layers 2..5 in the ring channel order,
+// element i of the cone fragments: layers 2..5 in the ring channel order,
 // [layer][tap][m][lane][8]
 constexpr int SPLIT_ELEMS = 4 * 9 * 2 * 64 * 8;
-HS_DEV void pack_split_elem(const float* __restrict__ w, __bf16* __restrict__ hi,
-                            __bf16* __restrict__ lo, int i) {
+HS_DEV float cone_weight(const float* __restrict__ w, int i) {
   const int e = i & 7, l = (i >> 3) & 63, m = (i >> 9) & 1, t = (i >> 10) % 9,
             layer = (i >> 10) / 9;
   const int g = l >> 4, r = l & 15;
-  const float v = w[hs_wk(layer + 2) + ((16 * m + r) * 32 + hs_ring_channel(g, e)) * 9 + t];
-  const __bf16 h = (__bf16)v;
-  hi[i] = h;
-  lo[i] = (__bf16)(v - (float)h);
+  return w[hs_wk(layer + 2) + ((16 * m + r) * 32 + hs_ring_channel(g, e)) * 9 + t];
 }
 
 struct SplitArgs {
@@ -89,53 +118,76 @@ struct SplitArgs {
   const uint64_t* seglist;
   const int* seg_count;
   long long seg_cap;
-  const bf16x8_t* whi;
-  const bf16x8_t* wlo;
-  float tau2;
-  hs::Levels lv;  // output thresholds (binary: {0})
+  const void* whi;        // hi (split) or FP16 fragments of layers 2..5
+  const bf16x8_t* wlo;    // lo fragments (split form)
+  const int* wflag;       // FP16 form: nonzero if a weight of layers 1..5 overflows FP16
+  float tau2;             // the band of this stage
+  hs::Levels lv;          // output thresholds (binary: {0})
   uint64_t* list2;
   int* count2;
   uint8_t* bits;
   float* logits;
   int32_t* stats;
+  int total_slot;         // stats entry that receives this stage's input count
 };
 
+template <bool HALF>
 struct SplitSmem {
+  static constexpr int REC = ConeForm<HALF>::REC;
   __attribute__((aligned(16))) float s0[2][169 * 2];  // (c, z) of the 13 x 13 window
-  __attribute__((aligned(16))) char b1[2][121 * CREC];  // layer outputs, split BF16
-  __attribute__((aligned(16))) char b2[2][81 * CREC];
-  __attribute__((aligned(16))) char b3[2][49 * CREC];
-  __attribute__((aligned(16))) char b4[2][25 * CREC];
+  __attribute__((aligned(16))) char b1[2][121 * REC];  // layer outputs
+  __attribute__((aligned(16))) char b2[2][81 * REC];
+  __attribute__((aligned(16))) char b3[2][49 * REC];
+  __attribute__((aligned(16))) char b4[2][25 * REC];
   float l5[2][9 * 32];                                   // layer 5 in FP32
-  bf16x8_t wlo[4][9][2][64];                             // layers 2..5, lo parts
-  bf16x8_t w1[2][2][64];                                 // layer 1: [hi, lo][m][lane]
+  bf16x8_t wlo[HALF ? 1 : 4][9][2][HALF ? 1 : 64];       // layers 2..5, lo parts (split)
+  typename ConeForm<HALF>::op w1[2][2][64];              // layer 1: [hi, lo][m][lane]
   float w6[288];                                         // layer 6, [channel][tap]
   __attribute__((aligned(16))) float b1v[32];           // layer 1 bias
   int spre[SPLIT_MAXSEG + 1];                            // exclusive prefix of the segment counts
   int cinfo[16][CI_N];  // per cone, the CI_* fields
+  int covf[16];         // per cone: an FP16 activation overflowed
 };
 
-HS_DEV void split_store(char* rec_base, int p, int g, const float (&v)[2][4]) {
-  bf16x8_t vh, vl;
+// one position's 32 channels (lane group g's 8 of them) into a record
+template <bool HALF>
+HS_DEV void cone_store(char* rec_base, int p, int g, const float (&v)[2][4], bool& ovf) {
+  using F = ConeForm<HALF>;
+  char* rec = rec_base + p * F::REC;
+  if constexpr (HALF) {
+    f16x8_t vh;
 #pragma unroll
-  for (int m = 0; m < 2; ++m)
+    for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const __bf16 h = (__bf16)v[m][i];
-      vh[4 * m + i] = h;
-      vl[4 * m + i] = (__bf16)(v[m][i] - (float)h);
-    }
-  char* rec = rec_base + p * CREC;
-  *(bf16x8_t*)(rec + crec_slot(p, 2 * g) * 16) = vh;
-  *(bf16x8_t*)(rec + crec_slot(p, 2 * g + 1) * 16) = vl;
+      for (int i = 0; i < 4; ++i) {
+        vh[4 * m + i] = (_Float16)v[m][i];
+        ovf = ovf || v[m][i] >= F16_INF_AT;  // ReLU'd: never negative or NaN
+      }
+    *(f16x8_t*)(rec + F::slot(p, g) * 16) = vh;
+  } else {
+    bf16x8_t vh, vl;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const __bf16 h = (__bf16)v[m][i];
+        vh[4 * m + i] = h;
+        vl[4 * m + i] = (__bf16)(v[m][i] - (float)h);
+      }
+    *(bf16x8_t*)(rec + F::slot(p, 2 * g) * 16) = vh;
+    *(bf16x8_t*)(rec + F::slot(p, 2 * g + 1) * 16) = vl;
+  }
 }
 
 // Layer K (2..5) on runs run0 .. run0 + NR - 1 of one cone (ci); src / dst
-// are the cone's input and output slots.
-template <int K, int NR>
-HS_DEV void split_layer(const bf16x8_t (&wh)[9][2], const bf16x8_t (*wl)[2][64],
-                        const f32x4_t (&bias)[2], const char* src, char* dst, float* dst5,
-                        const int* ci, int run0, int lane) {
+// are the cone's input and output slots; returns whether a stored value
+// overflowed FP16 (FP16 form).
+template <bool HALF, int K, int NR>
+HS_DEV bool cone_layer(const typename ConeForm<HALF>::op (&wh)[9][2], const bf16x8_t* wl,
+                       const f32x4_t (&bias)[2], const char* src, char* dst, float* dst5,
+                       const int* ci, int run0, int lane) {
+  using F = ConeForm<HALF>;
+  using op = typename F::op;
   constexpr int EO = win_edge(K), EI = EO + 2, NP = EO * EO;
   const int H = ci[CI_H], W = ci[CI_W];
   const int g = lane >> 4, r = lane & 15;
@@ -159,17 +211,24 @@ HS_DEV void split_layer(const bf16x8_t (&wh)[9][2], const bf16x8_t (*wl)[2][64],
   // the operands of tap t + 1 are loaded while tap t's MFMAs run; the
   // scheduling barrier at the end of each tap keeps the compiler from
   // hoisting every tap's loads to the top (which would exhaust the registers)
-  bf16x8_t bh[2][NR], bl[2][NR], wlo[2][2];
+  op bh[2][NR], bl[2][NR];
+  bf16x8_t wlo[2][2];
   auto load_tap = [&](int t, int s) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
       const int q = q0[j] + (t / 3) * EI + t % 3;
-      const char* rec = src + q * CREC;
-      bh[s][j] = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g) * 16);
-      bl[s][j] = *(const bf16x8_t*)(rec + crec_slot(q, 2 * g + 1) * 16);
+      const char* rec = src + q * F::REC;
+      if constexpr (HALF) {
+        bh[s][j] = *(const op*)(rec + F::slot(q, g) * 16);
+      } else {
+        bh[s][j] = *(const op*)(rec + F::slot(q, 2 * g) * 16);
+        bl[s][j] = *(const op*)(rec + F::slot(q, 2 * g + 1) * 16);
+      }
     }
-    wlo[s][0] = wl[t][0][ln];
-    wlo[s][1] = wl[t][1][ln];
+    if constexpr (!HALF) {
+      wlo[s][0] = wl[(t * 2 + 0) * 64 + ln];
+      wlo[s][1] = wl[(t * 2 + 1) * 64 + ln];
+    }
   };
   load_tap(0, 0);
 #pragma unroll
@@ -180,13 +239,16 @@ HS_DEV void split_layer(const bf16x8_t (&wh)[9][2], const bf16x8_t (*wl)[2][64],
     for (int j = 0; j < NR; ++j)
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
-        a0[j][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[t][m], bh[s][j], a0[j][m], 0, 0, 0);
-        a1[j][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo[s][m], bh[s][j], a1[j][m], 0, 0, 0);
-        a2[j][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh[t][m], bl[s][j], a2[j][m], 0, 0, 0);
+        a0[j][m] = F::mma(wh[t][m], bh[s][j], a0[j][m]);
+        if constexpr (!HALF) {
+          a1[j][m] = F::mma(wlo[s][m], bh[s][j], a1[j][m]);
+          a2[j][m] = F::mma(wh[t][m], bl[s][j], a2[j][m]);
+        }
       }
     __builtin_amdgcn_sched_barrier(0);
   }
   const bool cone = ci[CI_O] >= 0;
+  bool ovf = false;
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
     if (p[j] < 0) continue;
@@ -196,12 +258,12 @@ HS_DEV void split_layer(const bf16x8_t (&wh)[9][2], const bf16x8_t (*wl)[2][64],
     float v[2][4];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const f32x4_t s = a0[j][m] + (a1[j][m] + a2[j][m]);
+      const f32x4_t s = HALF ? a0[j][m] : a0[j][m] + (a1[j][m] + a2[j][m]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) v[m][i] = in_img ? fmaxf(s[i] + bias[m][i], 0.f) : 0.f;
     }
     if (K < 5) {
-      split_store(dst, p[j], g, v);
+      cone_store<HALF>(dst, p[j], g, v, ovf);
     } else {
       float* d = dst5 + p[j] * 32;
 #pragma unroll
@@ -210,27 +272,33 @@ HS_DEV void split_layer(const bf16x8_t (&wh)[9][2], const bf16x8_t (*wl)[2][64],
         for (int i = 0; i < 4; ++i) d[16 * m + 4 * g + i] = v[m][i];
     }
   }
+  return ovf;
 }
 
+template <bool HALF>
 __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitArgs a) {
-  __shared__ SplitSmem sm;
+  using F = ConeForm<HALF>;
+  using op = typename F::op;
+  __shared__ SplitSmem<HALF> sm;
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, r = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // ---- wave roles (see the table above); wave 7 owns no layer
   const int K = wave < 3 ? 2 : wave < 5 ? 3 : wave == 5 ? 4 : wave == 6 ? 5 : 0;
   const int run0 = (wave < 3) ? 2 * wave : (wave == 4) ? 2 : 0;
   const bool stager = wave == 3 || wave == 7;
-  // the owned layer's hi A operands and biases, for the whole kernel; the
-  // lo A operands of all four layers in LDS
-  bf16x8_t wh[9][2];
+  // the owned layer's A operands (hi or FP16) and biases, for the whole
+  // kernel; the lo A operands of all four layers in LDS
+  op wh[9][2];
   f32x4_t bias[2];
-  for (int i = tid; i < 4 * 9 * 2 * 64; i += SPLIT_THREADS) (&sm.wlo[0][0][0][0])[i] = a.wlo[i];
+  if constexpr (!HALF)
+    for (int i = tid; i < 4 * 9 * 2 * 64; i += SPLIT_THREADS) (&sm.wlo[0][0][0][0])[i] = a.wlo[i];
   {
     const int kk = K ? K : 2;
+    const op* whi = (const op*)a.whi;
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
-      for (int m = 0; m < 2; ++m) wh[t][m] = a.whi[(((kk - 2) * 9 + t) * 2 + m) * 64 + lane];
+      for (int m = 0; m < 2; ++m) wh[t][m] = whi[(((kk - 2) * 9 + t) * 2 + m) * 64 + lane];
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -240,14 +308,19 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
   // kernel row, slot e = (dx = e / 2, channel e % 2); zero in the padding slots
   if (wave < 2) {
     const int m = wave;
-    bf16x8_t vh, vl;
+    op vh, vl;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const float v =
           (g < 3 && e < 6) ? a.w[HS_W1 + ((16 * m + r) * 2 + (e & 1)) * 9 + g * 3 + (e >> 1)] : 0.0f;
-      const __bf16 h = (__bf16)v;
-      vh[e] = h;
-      vl[e] = (__bf16)(v - (float)h);
+      if constexpr (HALF) {
+        vh[e] = (_Float16)v;
+        vl[e] = (_Float16)0.0f;
+      } else {
+        const __bf16 h = (__bf16)v;
+        vh[e] = h;
+        vl[e] = (__bf16)(v - (float)h);
+      }
     }
     sm.w1[0][m][lane] = vh;
     sm.w1[1][m][lane] = vl;
@@ -282,8 +355,13 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
   const int cb0 = (int)((long long)blockIdx.x * total / gridDim.x);
   const int cb1 = (int)((long long)(blockIdx.x + 1) * total / gridDim.x);
   const int nloc = cb1 - cb0;
-  if (blockIdx.x == 0 && tid == 0) a.stats[0] = total;
+  if (blockIdx.x == 0 && tid == 0) {
+    a.stats[a.total_slot] = total;
+    if (!HALF) a.stats[4] = total;  // the pixels the split stage recomputes
+  }
   if (nloc <= 0) return;  // uniform over the block
+  // FP16 form: weights outside FP16's range send every cone on
+  const bool wbad = HALF && *a.wflag != 0;
 
   // Cone i's record goes to cinfo[i % 16] (wave 7, lane 0). Its list entry
   // is loaded one step before it is decoded, and its window values one step
@@ -301,6 +379,7 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
   };
   auto put_cone = [&](int i, uint64_t u) {
     int* d = sm.cinfo[i & 15];
+    sm.covf[i & 15] = 0;
     if (i >= nloc) {
       d[CI_O] = -1;
       d[CI_Y] = d[CI_X] = d[CI_BIT] = d[CI_PG] = d[CI_SLO] = d[CI_SHI] = 0;
@@ -393,10 +472,11 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
       const int* ci = sm.cinfo[i & 15];
       const bool cone = ci[CI_O] >= 0;
       const int H = ci[CI_H], W = ci[CI_W];
-      const bf16x8_t ah0 = sm.w1[0][0][lane], al0 = sm.w1[1][0][lane];
-      const bf16x8_t ah1 = sm.w1[0][1][lane], al1 = sm.w1[1][1][lane];
+      const op ah0 = sm.w1[0][0][lane], al0 = sm.w1[1][0][lane];
+      const op ah1 = sm.w1[0][1][lane], al1 = sm.w1[1][1][lane];
       const f32x4_t bb0 = *(const f32x4_t*)&sm.b1v[4 * g];
       const f32x4_t bb1 = *(const f32x4_t*)&sm.b1v[16 + 4 * g];
+      bool ovf = false;
       for (int run = l1run0; run < l1run0 + l1runs; ++run) {
         const int P = run * 16 + r;
         const int p = P < 121 ? P : 0;
@@ -405,20 +485,28 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
         const f32x2_t* sp = (const f32x2_t*)&sm.s0[sl][((pi + (g < 3 ? g : 2)) * 13 + pj) * 2];
         const f32x2_t v0 = sp[0], v1 = sp[1], v2 = sp[2];
         const float vv[8] = {v0[0], v0[1], v1[0], v1[1], v2[0], v2[1], 0.f, 0.f};
-        bf16x8_t bh, bl;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const __bf16 h = (__bf16)vv[e];
-          bh[e] = h;
-          bl[e] = (__bf16)(vv[e] - (float)h);
-        }
         const f32x4_t z4 = {0.f, 0.f, 0.f, 0.f};
-        const f32x4_t s0v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, z4, 0, 0, 0) +
-                            (__builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, z4, 0, 0, 0) +
-                             __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, z4, 0, 0, 0));
-        const f32x4_t s1v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, z4, 0, 0, 0) +
-                            (__builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, z4, 0, 0, 0) +
-                             __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, z4, 0, 0, 0));
+        f32x4_t s0v, s1v;
+        if constexpr (HALF) {
+          f16x8_t bh;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            bh[e] = (_Float16)vv[e];
+            ovf = ovf || !(fabsf(vv[e]) < F16_INF_AT);  // also NaN
+          }
+          s0v = F::mma(ah0, bh, z4);
+          s1v = F::mma(ah1, bh, z4);
+        } else {
+          bf16x8_t bh, bl;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const __bf16 h = (__bf16)vv[e];
+            bh[e] = h;
+            bl[e] = (__bf16)(vv[e] - (float)h);
+          }
+          s0v = F::mma(ah0, bh, z4) + (F::mma(al0, bh, z4) + F::mma(ah0, bl, z4));
+          s1v = F::mma(ah1, bh, z4) + (F::mma(al1, bh, z4) + F::mma(ah1, bl, z4));
+        }
         const int gy = ci[CI_Y] - 5 + pi, gx = ci[CI_X] - 5 + pj;
         const bool in_img = cone && gy >= 0 && gy < H && gx >= 0 && gx < W;
         float v[2][4];
@@ -427,8 +515,9 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
           v[0][ii] = in_img ? fmaxf(s0v[ii] + bb0[ii], 0.f) : 0.f;
           v[1][ii] = in_img ? fmaxf(s1v[ii] + bb1[ii], 0.f) : 0.f;
         }
-        if (P < 121) split_store(sm.b1[sl], p, g, v);
+        if (P < 121) cone_store<HALF>(sm.b1[sl], p, g, v, ovf);
       }
+      if (HALF && ovf) sm.covf[i & 15] = 1;
     }
     // ---- stages 2..5: the owned layer on cone t - K
     if (K) {
@@ -436,20 +525,28 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
       if (i >= 0 && i < nloc) {
         const int sl = i & 1;
         const int* ci = sm.cinfo[i & 15];
+        const bf16x8_t* wl = &sm.wlo[0][0][0][0];
+        constexpr int LS = HALF ? 0 : 9 * 2 * 64;  // lo fragments per layer
+        bool ovf;
         switch (K) {
           case 2:
-            split_layer<2, 2>(wh, sm.wlo[0], bias, sm.b1[sl], sm.b2[sl], nullptr, ci, run0, lane);
+            ovf = cone_layer<HALF, 2, 2>(wh, wl, bias, sm.b1[sl], sm.b2[sl], nullptr, ci, run0,
+                                         lane);
             break;
           case 3:
-            split_layer<3, 2>(wh, sm.wlo[1], bias, sm.b2[sl], sm.b3[sl], nullptr, ci, run0, lane);
+            ovf = cone_layer<HALF, 3, 2>(wh, wl + LS, bias, sm.b2[sl], sm.b3[sl], nullptr, ci,
+                                         run0, lane);
             break;
           case 4:
-            split_layer<4, 2>(wh, sm.wlo[2], bias, sm.b3[sl], sm.b4[sl], nullptr, ci, run0, lane);
+            ovf = cone_layer<HALF, 4, 2>(wh, wl + 2 * LS, bias, sm.b3[sl], sm.b4[sl], nullptr, ci,
+                                         run0, lane);
             break;
           default:
-            split_layer<5, 1>(wh, sm.wlo[3], bias, sm.b4[sl], nullptr, sm.l5[sl], ci, run0, lane);
+            ovf = cone_layer<HALF, 5, 1>(wh, wl + 3 * LS, bias, sm.b4[sl], nullptr, sm.l5[sl], ci,
+                                         run0, lane);
             break;
         }
+        if (HALF && ovf) sm.covf[i & 15] = 1;
       }
     }
     // ---- stage 6 (wave 3): layer 6 in FP32 and the decision
@@ -471,7 +568,8 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
           float dist;
           int side;
           const int nb = hs::level_of(a.lv, xl, &dist, &side);
-          if (dist >= a.tau2) {
+          const bool trusted = !HALF || (!wbad && sm.covf[i & 15] == 0);
+          if (trusted && dist >= a.tau2) {
             // the level decided before: the side of the same nearest threshold
             const int old = hs::nearest_threshold(a.lv, xl) + ci[CI_BIT];
             if (old != nb) atomicAdd(&a.stats[1], 1);
@@ -510,14 +608,28 @@ HS_DEV void pack_fp32_elem(const float* __restrict__ w, float* __restrict__ out,
   out[i] = w[hs_wk(layer + 2) + (co * 32 + ci) * 9 + t];
 }
 
-// both weight copies of the recheck stages in one launch
+// the weight copies of the recheck stages in one launch: split hi and lo,
+// FP16, FP32 transposed; *wflag (zeroed before) set if a weight of layers
+// 1..5 rounds to infinity in FP16
 __global__ void pack_recheck_kernel(const float* __restrict__ w, __bf16* __restrict__ hi,
-                                    __bf16* __restrict__ lo, float* __restrict__ wt) {
+                                    __bf16* __restrict__ lo, _Float16* __restrict__ h16,
+                                    float* __restrict__ wt, int* __restrict__ wflag) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < SPLIT_ELEMS + 4 * F32_LAYER;
        i += gridDim.x * blockDim.x) {
-    if (i < SPLIT_ELEMS) pack_split_elem(w, hi, lo, i);
-    else pack_fp32_elem(w, wt, i - SPLIT_ELEMS);
+    if (i < SPLIT_ELEMS) {
+      const float v = cone_weight(w, i);
+      const __bf16 h = (__bf16)v;
+      hi[i] = h;
+      lo[i] = (__bf16)(v - (float)h);
+      h16[i] = (_Float16)v;
+    } else {
+      pack_fp32_elem(w, wt, i - SPLIT_ELEMS);
+    }
   }
+  bool bad = false;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < HS_W6; i += gridDim.x * blockDim.x)
+    bad = bad || !(fabsf(w[i]) < F16_INF_AT);
+  if (bad) atomicOr(wflag, 1);
 }
 
 template <int K>
@@ -668,20 +780,23 @@ namespace hs {
 
 // bytes of the hi and the lo copy together (each 4 layers x 9 taps x 2 row
 // tiles x 64 lanes x 8 BF16 values)
-size_t split_frag_bytes() { return 2 * (size_t)(4 * 9 * 2 * 64 * 8) * sizeof(__bf16); }
+size_t split_frag_bytes() { return 2 * (size_t)SPLIT_ELEMS * sizeof(__bf16); }
+size_t half_frag_bytes() { return (size_t)SPLIT_ELEMS * sizeof(_Float16); }
 size_t fp32_pack_bytes() { return (size_t)4 * F32_LAYER * sizeof(float); }
 
-hipError_t launch_split_pack(const float* w, void* whi, void* wlo, void* wt, hipStream_t s) {
-  pack_recheck_kernel<<<72, 256, 0, s>>>(w, (__bf16*)whi, (__bf16*)wlo, (float*)wt);
+hipError_t launch_split_pack(const float* w, const ConeWeights& cw, hipStream_t s) {
+  pack_recheck_kernel<<<72, 256, 0, s>>>(w, (__bf16*)cw.whi, (__bf16*)cw.wlo, (_Float16*)cw.w16,
+                                         (float*)cw.wt, cw.wflag);
   return hipGetLastError();
 }
 
-hipError_t launch_recheck_split(const float* w, const float* contone, const uint64_t* seeds,
-                                const Page* pages, int kind, const uint64_t* seglist,
-                                const int* seg_count, int nseg, long long seg_cap,
-                                const void* whi, const void* wlo, float tau2, const Levels& lv,
-                                uint64_t* list2, int* count2, uint8_t* bits, float* logits,
-                                int32_t* stats, int num_cus, hipStream_t s) {
+hipError_t launch_recheck_cones(bool half, const float* w, const float* contone,
+                                const uint64_t* seeds, const Page* pages, int kind,
+                                const uint64_t* seglist, const int* seg_count, int nseg,
+                                long long seg_cap, const ConeWeights& cw, float band,
+                                const Levels& lv, uint64_t* list_out, int* count_out,
+                                uint8_t* bits, float* logits, int32_t* stats, int total_slot,
+                                int num_cus, hipStream_t s) {
   if (nseg < 1 || nseg > SPLIT_MAXSEG) return hipErrorInvalidValue;
   SplitArgs a;
   a.w = w;
@@ -693,16 +808,19 @@ hipError_t launch_recheck_split(const float* w, const float* contone, const uint
   a.seglist = seglist;
   a.seg_count = seg_count;
   a.seg_cap = seg_cap;
-  a.whi = (const bf16x8_t*)whi;
-  a.wlo = (const bf16x8_t*)wlo;
-  a.tau2 = tau2;
+  a.whi = half ? cw.w16 : cw.whi;
+  a.wlo = (const bf16x8_t*)cw.wlo;
+  a.wflag = cw.wflag;
+  a.tau2 = band;
   a.lv = lv;
-  a.list2 = list2;
-  a.count2 = count2;
+  a.list2 = list_out;
+  a.count2 = count_out;
   a.bits = bits;
   a.logits = logits;
   a.stats = stats;
-  recheck_split_kernel<<<num_cus, SPLIT_THREADS, 0, s>>>(a);
+  a.total_slot = total_slot;
+  if (half) recheck_split_kernel<true><<<num_cus, SPLIT_THREADS, 0, s>>>(a);
+  else recheck_split_kernel<false><<<num_cus, SPLIT_THREADS, 0, s>>>(a);
   return hipGetLastError();
 }
 

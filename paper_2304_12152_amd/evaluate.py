@@ -3,9 +3,9 @@ halftones (Sec. IV, Eqs. psd, rapsd, anis; the paper's spectral figure
 shows the grays 15, 80, 100 and 127 of 255).
 
 For every gray g a batch of B constant pages of H x W is halftoned by the
-policy (Alg. 1 TEST, `halftone_infer`, in the cheapest exact-bit precision
-that `calibrate.plan` finds for the weights, with the band measured per
-gray) and by Floyd-Steinberg error
+policy (Alg. 1 TEST, a packed policy's `halftone_policy_infer`, in the
+cheapest exact-bit precision that `calibrate.plan` finds for the weights,
+with the recheck bands measured per gray) and by Floyd-Steinberg error
 diffusion; `halftone_spectrum` estimates the power spectrum as the mean
 periodogram of all P x P patches of the batch and reduces it to the radially
 averaged power and the anisotropy per ring. Reported per method and gray:
@@ -18,13 +18,14 @@ averaged power and the anisotropy per ring. Reported per method and gray:
   anis_mean_db the mean of anis_db over those rings;
   low_power   the share of the AC power in rings below the principal
               frequency sqrt(min(g, 1 - g)) (in cycles per pixel, times P);
-  policy only: recheck_tau, the recheck band measured for the weights on two
-              of the gray's pages (`calibrate.recheck_tau`); logit_hist,
+  policy only: bands, the recheck bands measured for the weights on two
+              of the gray's pages (`calibrate.bands`); logit_hist,
               the fraction of pixels whose logit magnitude
               |x| falls in the decades [0, 1e-4), [1e-4, 1e-3), ...,
               [10, inf) -- a bimodal policy keeps almost all of them in the
-              top decades -- and recheck / fp32, the fractions the BF16
-              path recomputed with split-BF16 and in FP32; with levels > 2
+              top decades -- and recheck / split / fp32, the fractions the
+              16-bit path listed, recomputed with split-BF16 and in FP32;
+              with levels > 2
               also near_level, the share of v (L - 1) within 0.1 of an
               integer.
 With K periodograms averaged, an isotropic spectrum has anisotropy about
@@ -97,7 +98,8 @@ def bluenoise(weights, grays=GRAYS, B=8, H=512, W=512, P=64, precision=None, wit
     dev = torch.device("cuda", torch.cuda.current_device())
     w = torch.as_tensor(np.asarray(weights, dtype=np.float32)).to(dev)
     # default: the cheapest exact-bit precision for these weights
-    prec = calibrate.plan(w)["precision"] if precision is None else precision
+    prec = calibrate.plan(w, levels=levels)["precision"] if precision is None else precision
+    pol = hb.Policy(w)
     out = {"P": P, "periodograms": B * (H // P) * (W // P), "pages": [B, H, W],
            "precision": {hb.HS_FP32: "fp32", hb.HS_BF16: "bf16", hb.HS_FP16: "fp16"}[prec]}
     out["floor_db"] = -10.0 * math.log10(out["periodograms"])
@@ -105,17 +107,14 @@ def bluenoise(weights, grays=GRAYS, B=8, H=512, W=512, P=64, precision=None, wit
         g = gi / 255.0
         c = torch.full((B, H, W), g, dtype=torch.float32, device=dev)
         s = torch.arange(seed + B * gi, seed + B * gi + B, dtype=torch.int64, device=dev)
-        # the recheck band for these weights, measured on two of the pages
-        tau = (calibrate.recheck_tau(w, prec, c[:2], s[:2].tolist())
-               if prec != hb.HS_FP32 else 0.0)
-        if levels > 2:
-            bits, x, st = hb.halftone_infer_pages(w, c.reshape(-1), s, [(H, W)] * B,
-                                                  precision=prec, recheck_tau=tau, logits=True,
-                                                  stats=True, levels=levels)
-            bits, x = bits.view(B, H, W), x.view(B, H, W)
+        # the recheck bands for these weights, measured on two of the pages
+        if prec != hb.HS_FP32:
+            b = calibrate.bands(w, prec, c[:2], s[:2].tolist(), levels=levels)
         else:
-            bits, x, st = hb.halftone_infer(w, c, s, precision=prec, recheck_tau=tau, logits=True,
-                                            stats=True)
+            b = {"tau": 0.0, "tau16": -1.0, "tau2": -1.0}
+        bits, x, st = hb.halftone_policy_infer(pol, c, s, precision=prec, recheck_tau=b["tau"],
+                                               recheck_tau16=b["tau16"], recheck_tau2=b["tau2"],
+                                               logits=True, stats=True, levels=levels)
         rec = {"policy": _summary(bits, c, g, P, hb, levels)}
         n = float(B * H * W)
         edges = torch.tensor(LOGIT_DECADES, dtype=torch.float32, device=dev)
@@ -127,8 +126,9 @@ def bluenoise(weights, grays=GRAYS, B=8, H=512, W=512, P=64, precision=None, wit
             t = torch.sigmoid(x.double()) * (levels - 1)
             rec["policy"]["near_level"] = float(((t - t.round()).abs() < 0.1).double().mean())
         st = st.cpu().numpy()
-        rec["policy"]["recheck_tau"] = tau
+        rec["policy"]["bands"] = {k: v for k, v in b.items() if k != "errors"}
         rec["policy"]["recheck"] = float(st[0]) / n
+        rec["policy"]["split"] = float(st[4]) / n
         rec["policy"]["fp32"] = float(st[2]) / n
         if with_fs:
             flat = np.full((B, H, W), g, dtype=np.float32)

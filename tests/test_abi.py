@@ -302,8 +302,8 @@ def test_policy_handle_argument_errors(lib):
     sh = hb.page_shapes_array([(8, 8)])
     shp = sh.ctypes.data_as(ctypes.c_void_p)
     ws = lib.halftone_infer_pages_workspace_size(1, shp, hb.HS_BF16)
-    args = [ctypes.byref(pol), p, p, 1, shp, 2, 0, hb.HS_BF16, 0.05, -1.0, p, None, None, p, ws,
-            None]
+    args = [ctypes.byref(pol), p, p, 1, shp, 2, 0, hb.HS_BF16, 0.05, -1.0, -1.0, p, None, None, p,
+            ws, None]
     assert lib.halftone_policy_infer(*args) == hb.HS_EINVAL  # not packed
     assert b"not packed" in lib.halftone_last_error()
     a = list(args); a[0] = None
@@ -311,9 +311,11 @@ def test_policy_handle_argument_errors(lib):
     pol.packed, pol.mem, pol.bytes = 1, 4096, n  # a packed-looking handle: argument checks only
     a = list(args); a[9] = -0.5
     assert lib.halftone_policy_infer(*a) == hb.HS_EINVAL
+    a = list(args); a[10] = float("nan")
+    assert lib.halftone_policy_infer(*a) == hb.HS_EINVAL
     a = list(args); a[5] = 9
     assert lib.halftone_policy_infer(*a) == hb.HS_EINVAL
-    a = list(args); a[14] = ws - 1
+    a = list(args); a[15] = ws - 1
     assert lib.halftone_policy_infer(*a) == hb.HS_EWORKSPACE
     a = list(args); a[1] = None
     assert lib.halftone_policy_infer(*a) == hb.HS_EINVAL

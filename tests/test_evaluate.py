@@ -28,6 +28,6 @@ def test_bluenoise_summary_on_the_gpu():
     assert abs(rec["fs"]["fill"] - 80 / 255) < 0.01
     assert len(rec["policy"]["rapsd_db"]) == 16 and len(rec["fs"]["anis_db"]) == 16
     assert res["precision"] == "fp16"  # the planner's choice for the He policy
-    assert rec["policy"]["recheck_tau"] >= hb.RECHECK_TAU[hb.HS_FP16]
+    assert rec["policy"]["bands"]["tau"] >= hb.RECHECK_TAU[hb.HS_FP16]
     assert 0.0 <= rec["policy"]["fill"] <= 1.0
     assert abs(sum(rec["policy"]["logit_hist"]) - 1.0) < 1e-5

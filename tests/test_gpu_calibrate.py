@@ -68,5 +68,10 @@ def test_plan_prices_the_options():
     assert set(o) == {hb.HS_FP32, hb.HS_BF16, hb.HS_FP16}
     assert 0.0 < o[hb.HS_FP16]["listed"] < o[hb.HS_BF16]["listed"] < 0.02
     assert p["precision"] == hb.HS_FP16
-    assert p["recheck_tau"] == o[hb.HS_FP16]["recheck_tau"] >= hb.RECHECK_TAU[hb.HS_FP16]
+    assert p["bands"]["tau"] == o[hb.HS_FP16]["bands"]["tau"] >= hb.RECHECK_TAU[hb.HS_FP16]
     assert o[hb.HS_FP32]["ns_per_px"] > o[hb.HS_BF16]["ns_per_px"]
+    # the BF16 bands: the FP16 cone stage's between the pass's and the split's
+    bb = o[hb.HS_BF16]["bands"]
+    assert bb["tau"] > bb["tau16"] > bb["tau2"] >= 1.5e-4
+    e = bb["errors"]
+    assert e["pass"] > e["cone16"] > e["split"] > 0.0 and not e["overflow"]

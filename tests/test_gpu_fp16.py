@@ -101,8 +101,11 @@ def test_fp16_overflow_reruns_in_bf16(orc):
     ct, st = to_dev(c), seeds_t(seeds)
     bits, lg, stats = hb.halftone_infer(to_dev(ws), ct, st, 0, hb.HS_FP16, logits=True,
                                         stats=True)
-    ref_bits, ref_lg, ref_stats = hb.halftone_infer(to_dev(w), ct, st, 0, hb.HS_BF16,
-                                                    8 * TAU16, logits=True, stats=True)
+    # the reference: a BF16 call with the 8 times wider band and, as after
+    # an FP16 pass, without the FP16 cone stage (tau16 = 0)
+    ref_bits, ref_lg, ref_stats = hb.halftone_policy_infer(
+        hb.Policy(to_dev(w)), ct, st, precision=hb.HS_BF16, recheck_tau=8 * TAU16,
+        recheck_tau16=0.0, logits=True, stats=True)
     stats, ref_stats = stats.cpu().numpy(), ref_stats.cpu().numpy()
     assert stats[3] == 1 and ref_stats[3] == 0
     assert stats[0] == ref_stats[0]  # the same BF16 list (band 8 tau)
@@ -152,7 +155,8 @@ def test_fp16_contone_outside_the_unit_range_reruns_in_bf16():
         ct, st = to_dev(cb), seeds_t(seeds)
         bits, lg, stats = hb.halftone_infer(to_dev(w), ct, st, 0, hb.HS_FP16, logits=True,
                                             stats=True)
-        rb, rl = hb.halftone_infer(to_dev(w), ct, st, 0, hb.HS_BF16, 8 * TAU16, logits=True)
+        rb, rl = hb.halftone_policy_infer(hb.Policy(to_dev(w)), ct, st, precision=hb.HS_BF16,
+                                          recheck_tau=8 * TAU16, recheck_tau16=0.0, logits=True)
         assert stats.cpu().numpy()[3] == 1, bad
         lg, rl = lg.cpu().numpy(), rl.cpu().numpy()
         same = np.abs(rl) >= max(8 * TAU16 / 64, 1.5e-4)  # split-stage decisions in both
@@ -208,9 +212,9 @@ def test_fp16_overflow_reruns_in_bf16_with_levels(orc):
     out, lg, stats = hb.halftone_infer_pages(to_dev(_scaled(w, 2.0 ** 16)), ft, st, pages,
                                              precision=hb.HS_FP16, logits=True, stats=True,
                                              levels=4)
-    ref, rl, rst = hb.halftone_infer_pages(to_dev(w), ft, st, pages, precision=hb.HS_BF16,
-                                           recheck_tau=8 * TAU16, logits=True, stats=True,
-                                           levels=4)
+    ref, rl, rst = hb.halftone_policy_infer(hb.Policy(to_dev(w)), ft, st, pages,
+                                            precision=hb.HS_BF16, recheck_tau=8 * TAU16,
+                                            recheck_tau16=0.0, logits=True, stats=True, levels=4)
     stats, rst = stats.cpu().numpy(), rst.cpu().numpy()
     assert stats[3] == 1 and rst[3] == 0 and stats[0] == rst[0]
     lg, rl = lg.cpu().numpy(), rl.cpu().numpy()

@@ -90,7 +90,8 @@ def test_split_stage_band_exposes_its_error():
     pol = hb.Policy(wt)
     _, l32 = hb.halftone_infer(wt, ct, st, precision=hb.HS_FP32, logits=True)
     _, lsp, stt = hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_BF16, recheck_tau=1e30,
-                                           recheck_tau2=0.0, logits=True, stats=True)
+                                           recheck_tau16=0.0, recheck_tau2=0.0, logits=True,
+                                           stats=True)
     stt = stt.cpu().numpy()
     assert stt[0] == B * H * W and stt[2] == 0
     err = (lsp - l32).abs().max().item()
@@ -101,7 +102,7 @@ def test_split_stage_band_exposes_its_error():
     # with an explicit tau2 above that error the bits equal the FP32 path's
     # wherever the two FP32 summation orders cannot disagree
     bits = hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_BF16, recheck_tau=1e30,
-                                    recheck_tau2=4 * err)
+                                    recheck_tau16=0.0, recheck_tau2=4 * err)
     b32 = hb.halftone_infer(wt, ct, st, precision=hb.HS_FP32)
     off = l32.abs() > 1e-4
     assert torch.equal(bits[off], b32[off])
