@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict
     if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
       const uint64_t a = (uint64_t)gy * W + gx;
       cv = contone[img + a];
-      zv = hs_noise(seed, a, step, kind);
+      zv = hs_noise<true>(seed, a, step, kind);
     }
     sc[i] = cv;
     sz[i] = zv;

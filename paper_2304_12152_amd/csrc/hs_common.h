@@ -25,6 +25,12 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 // Weyl constants between rounds. Integer-only, so every implementation of
 // the published definition gives the same bits.
 // ---------------------------------------------------------------------------
+// WIDE takes each 32 x 32 -> 64-bit product in one multiply
+// (v_mad_u64_u32) instead of separate low and high halves: fewer
+// quarter-rate instructions, but one more 64-bit temporary, so kernels at
+// the edge of their register budget use the narrow form. Both give the same
+// bits.
+template <bool WIDE = false>
 HS_DEV uint4 hs_philox(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
@@ -32,16 +38,28 @@ HS_DEV uint4 hs_philox(uint4 c, uint32_t k0, uint32_t k1) {
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    uint32_t lo0, hi0, lo1, hi1;
+    if constexpr (WIDE) {
+      const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+      lo0 = (uint32_t)p0;
+      hi0 = (uint32_t)(p0 >> 32);
+      lo1 = (uint32_t)p1;
+      hi1 = (uint32_t)(p1 >> 32);
+    } else {
+      lo0 = 0xD2511F53u * c.x;
+      hi0 = __umulhi(0xD2511F53u, c.x);
+      lo1 = 0xCD9E8D57u * c.z;
+      hi1 = __umulhi(0xCD9E8D57u, c.z);
+    }
     c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
   }
   return c;
 }
 
+template <bool WIDE = false>
 HS_DEV uint4 hs_draw(uint64_t seed, uint64_t a, uint32_t stream, uint32_t step) {
-  return hs_philox(make_uint4((uint32_t)a, (uint32_t)(a >> 32), stream, step), (uint32_t)seed,
-                   (uint32_t)(seed >> 32));
+  return hs_philox<WIDE>(make_uint4((uint32_t)a, (uint32_t)(a >> 32), stream, step),
+                         (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
 // u in [0,1) with 24 random bits (exact in FP32).
@@ -49,8 +67,9 @@ HS_DEV float hs_u24(uint32_t w) { return (float)(w >> 8) * (1.0f / 16777216.0f);
 
 // Noise map value of pixel a (stream 1): Gaussian by Box-Muller on words 0
 // and 1 (u1 in (0,1], so the log is finite), or the uniform variant.
+template <bool WIDE = false>
 HS_DEV float hs_noise(uint64_t seed, uint64_t a, uint32_t step, int kind) {
-  const uint4 w = hs_draw(seed, a, 1u, step);
+  const uint4 w = hs_draw<WIDE>(seed, a, 1u, step);
   if (kind == 1) return hs_u24(w.x);
   const float u1 = (float)((w.x >> 8) + 1u) * (1.0f / 16777216.0f);
   const float u2 = hs_u24(w.y);
@@ -59,7 +78,7 @@ HS_DEV float hs_noise(uint64_t seed, uint64_t a, uint32_t step, int kind) {
 
 // Action draw of pixel a (stream 0): h = [u < p].
 HS_DEV float hs_action_u(uint64_t seed, uint64_t a, uint32_t step) {
-  return hs_u24(hs_draw(seed, a, 0u, step).x);
+  return hs_u24(hs_draw<true>(seed, a, 0u, step).x);
 }
 
 // ---------------------------------------------------------------------------

@@ -580,8 +580,13 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
           const bool xin_ok = xin >= 0 && xin < W;
           const float cval = cin[h];
 
+          // the 64-bit-product Philox only where it does not cost spills:
+          // the binary FP16 form that tests layer 5 (the BF16 forms went
+          // from 1 to 30 spilled registers with it)
+          constexpr bool WIDE = CHK == CHECK_L5 && !MULTI;
           float zval = 0.f;
-          if (xin_ok && ri >= 0 && ri < H) zval = hs_noise(seed, (uint64_t)ri * W + xin, 0u, a.kind);
+          if (xin_ok && ri >= 0 && ri < H)
+            zval = hs_noise<WIDE>(seed, (uint64_t)ri * W + xin, 0u, a.kind);
           const V2 cz = __builtin_convertvector((f32x2_t){cval, zval}, V2);
           uint32_t u;
           __builtin_memcpy(&u, &cz, 4);

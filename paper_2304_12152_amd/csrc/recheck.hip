@@ -52,15 +52,23 @@ namespace {
 // orders all of it. The barrier orders LDS only: the global loads issued for
 // a later step (list entries, window values) stay in flight across it.
 //
-// Waves (w and w+4 share a SIMD), balanced by their measured step times in
-// the split form:
+// Waves (w and w+4 share a SIMD), split form (balanced by measured step
+// times):
 //   w0, w1, w2  layer 2, runs 0-1 / 2-3 / 4-5; layer 1, run 0 / 1 / 2
 //   w3          layer 3, runs 0-1; staging of window positions 0-63; layer 6
 //   w4          layer 3, runs 2-3
 //   w5          layer 4, runs 0-1
 //   w6          layer 5, run 0; layer 1, runs 3-5
 //   w7          layer 1, runs 6-7; staging of positions 64-168; the cone list
-// (a layer-1 run is 2 products of 16x16x32; a layer-2..5 run 18)
+// FP16 form (a third of the matrix work, so the staging is spread out):
+//   w0, w1, w2  as above
+//   w3          layer 3, runs 0-1; staging of positions 0-63; layer 6
+//   w4          layer 3, runs 2-3; layer 1, runs 3-4; staging of 128-168
+//   w5          layer 4, runs 0-1; layer 1, runs 5-6
+//   w6          layer 5, run 0; layer 1, run 7; staging of 64-127
+//   w7          the cone list
+// (a layer-1 run is 2 products of 16x16x32 per precision term, a
+// layer-2..5 run 18)
 // ===========================================================================
 constexpr int SPLIT_MAXSEG = 1024;    // list segments the stage accepts
 constexpr int NSTAGE = 7;             // staging, layers 1..5, layer 6
@@ -208,11 +216,14 @@ HS_DEV bool cone_layer(const typename ConeForm<HALF>::op (&wh)[9][2], const bf16
 #pragma unroll
     for (int m = 0; m < 2; ++m) a0[j][m] = a1[j][m] = a2[j][m] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   }
-  // the operands of tap t + 1 are loaded while tap t's MFMAs run; the
-  // scheduling barrier at the end of each tap keeps the compiler from
-  // hoisting every tap's loads to the top (which would exhaust the registers)
-  op bh[2][NR], bl[2][NR];
-  bf16x8_t wlo[2][2];
+  // the operands of tap t + PD are loaded while tap t's MFMAs run (PD = 2
+  // in the FP16 form, whose 4 MFMAs per tap are too short to cover one load
+  // latency; 1 in the split form, with 12); the scheduling barrier at the
+  // end of each tap keeps the compiler from hoisting every tap's loads to
+  // the top (which would exhaust the registers)
+  constexpr int PD = HALF ? 2 : 1, NS = PD + 1;
+  op bh[NS][NR], bl[NS][NR];
+  bf16x8_t wlo[NS][2];
   auto load_tap = [&](int t, int s) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
@@ -230,11 +241,12 @@ HS_DEV bool cone_layer(const typename ConeForm<HALF>::op (&wh)[9][2], const bf16
       wlo[s][1] = wl[(t * 2 + 1) * 64 + ln];
     }
   };
-  load_tap(0, 0);
+#pragma unroll
+  for (int t = 0; t < PD; ++t) load_tap(t, t);
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
-    const int s = t & 1;
-    if (t < 8) load_tap(t + 1, s ^ 1);
+    const int s = t % NS;
+    if (t + PD < 9) load_tap(t + PD, (t + PD) % NS);
 #pragma unroll
     for (int j = 0; j < NR; ++j)
 #pragma unroll
@@ -285,7 +297,6 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
   // ---- wave roles (see the table above); wave 7 owns no layer
   const int K = wave < 3 ? 2 : wave < 5 ? 3 : wave == 5 ? 4 : wave == 6 ? 5 : 0;
   const int run0 = (wave < 3) ? 2 * wave : (wave == 4) ? 2 : 0;
-  const bool stager = wave == 3 || wave == 7;
   // the owned layer's A operands (hi or FP16) and biases, for the whole
   // kernel; the lo A operands of all four layers in LDS
   op wh[9][2];
@@ -363,19 +374,26 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
   // FP16 form: weights outside FP16's range send every cone on
   const bool wbad = HALF && *a.wflag != 0;
 
-  // Cone i's record goes to cinfo[i % 16] (wave 7, lane 0). Its list entry
-  // is loaded one step before it is decoded, and its window values one step
-  // before they are staged, so no wave waits on global memory inside a step
-  // (except for the page record, which is loaded when the page changes).
-  // The segment of entry e is the last with spre <= e; entries are taken in
-  // order, so the segment pointer only moves forward.
-  int seg = 0, cpage = -1;
+  // Cone i's record goes to cinfo[i % 16] (wave 7, lane 0), three steps
+  // before cone i is staged. Wave 7 loads the list entries 64 at a time (one
+  // per lane, 64 cones before they are decoded) and hands them to lane 0
+  // with readlane, so no step waits on a list load; the page record is
+  // loaded when the page changes. The segment of entry e is the last with
+  // spre <= e.
+  int cpage = -1;
   hs::Page cp = {};
   uint64_t cseed = 0;
-  auto load_entry = [&](int i) -> uint64_t {
+  auto load_batch = [&](int j) -> uint64_t {  // entry of cone 64 j + lane
+    const int i = 64 * j + lane;
+    if (i >= nloc) return 0;
     const int e = cb0 + i;
-    while (seg + 1 < a.nseg && sm.spre[seg + 1] <= e) ++seg;
-    return a.seglist[(size_t)seg * a.seg_cap + (e - sm.spre[seg])];
+    int lo = 0, hi = a.nseg - 1;  // spre[lo] <= e < spre[hi + 1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sm.spre[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    return a.seglist[(size_t)lo * a.seg_cap + (e - sm.spre[lo])];
   };
   auto put_cone = [&](int i, uint64_t u) {
     int* d = sm.cinfo[i & 15];
@@ -404,33 +422,50 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
     d[CI_SLO] = (int)(uint32_t)cseed;
     d[CI_SHI] = (int)(uint32_t)(cseed >> 32);
   };
-  // staging: window position j = lane (wave 3), 64 + lane + 64 k (wave 7);
-  // the contone values and the image seed are loaded a step ahead
+  uint64_t ebuf0 = 0, ebuf1 = 0;  // entries of batches 2j and 2j + 1
+  auto decode = [&](int i) {      // wave 7: cone i's record; refills the batch of i - 64
+    const uint64_t b = ((i >> 6) & 1) ? ebuf1 : ebuf0;
+    const uint32_t ulo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, i & 63);
+    const uint32_t uhi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), i & 63);
+    if (lane == 0) put_cone(i, (uint64_t)ulo | ((uint64_t)uhi << 32));
+    if ((i & 63) == 63 && i + 65 < nloc) {  // batch i >> 6 is used up: load i >> 6 + 2
+      if ((i >> 6) & 1) ebuf1 = load_batch((i >> 6) + 2);
+      else ebuf0 = load_batch((i >> 6) + 2);
+    }
+  };
+  // staging: window positions j = 64 s + lane for the wave's slots s. The
+  // split form stages on waves 3 (slot 0) and 7 (slots 1, 2); the FP16 form,
+  // whose layer waves have slack, on waves 3, 6 and 4 (one slot each). The
+  // contone values are loaded a step ahead, always from a valid address
+  // (the same loads every step, no branch), and masked where they are used
+  // (a select on the loaded value would wait for it at once).
   constexpr int NSTG = 2;
-  auto stage_pos = [&](int k) { return wave == 3 ? (k == 0 ? lane : 999) : 64 + lane + 64 * k; };
+  const int slot0 = HALF ? (wave == 3 ? 0 : wave == 6 ? 1 : wave == 4 ? 2 : -1)
+                         : (wave == 3 ? 0 : wave == 7 ? 1 : -1);
+  const int nslot = slot0 < 0 ? 0 : (!HALF && wave == 7) ? 2 : 1;
+  const bool stager = nslot > 0;
+  auto stage_pos = [&](int k) { return k < nslot ? 64 * (slot0 + k) + lane : 999; };
   float pcv[NSTG];
   auto prefetch_window = [&](int i) {
     const int* ci = sm.cinfo[i & 15];
-    const int H = ci[CI_H], W = ci[CI_W];
+    const int H = ci[CI_H], W = ci[CI_W], o = ci[CI_O];
 #pragma unroll
     for (int k = 0; k < NSTG; ++k) {
       const int j = stage_pos(k);
-      pcv[k] = 0.f;
-      if (j < 169 && i < nloc && ci[CI_O] >= 0) {
-        const int dy = j / 13 - 6, dx = j % 13 - 6;
-        const int gy = ci[CI_Y] + dy, gx = ci[CI_X] + dx;
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) pcv[k] = a.contone[ci[CI_O] + dy * W + dx];
-      }
+      const int dy = j / 13 - 6, dx = j % 13 - 6;
+      const int gy = ci[CI_Y] + dy, gx = ci[CI_X] + dx;
+      const bool ok = j < 169 && i < nloc && o >= 0 && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      pcv[k] = a.contone[ok ? o + dy * W + dx : 0];
     }
   };
   for (int i = tid; i < 288; i += SPLIT_THREADS) sm.w6[i] = a.w[HS_W6 + i];
   const float b6 = a.w[HS_B6];
-  // prologue: cones 0..2 decoded, cone 3's entry in flight, cone 0's window
-  // values in flight
-  uint64_t pend_u = 0;
-  if (wave == 7 && lane == 0) {
-    for (int i = 0; i < 3; ++i) put_cone(i, i < nloc ? load_entry(i) : 0u);
-    if (3 < nloc) pend_u = load_entry(3);
+  // prologue: the first two batches of entries, cones 0..2 decoded, the
+  // window values of cone 0 in flight
+  if (wave == 7) {
+    ebuf0 = load_batch(0);
+    ebuf1 = load_batch(1);
+    for (int i = 0; i < 3; ++i) decode(i);
   }
   __syncthreads();
   if (stager) prefetch_window(0);
@@ -448,25 +483,27 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void recheck_split_kernel(SplitAr
           const int j = stage_pos(k);
           if (j < 169) {
             const int gy = ci[CI_Y] - 6 + j / 13, gx = ci[CI_X] - 6 + j % 13;
+            const bool in = ci[CI_O] >= 0 && gy >= 0 && gy < H && gx >= 0 && gx < W;
             float zv = 0.f;
-            if (ci[CI_O] >= 0 && gy >= 0 && gy < H && gx >= 0 && gx < W)
-              zv = hs_noise(sd, (uint64_t)gy * W + gx, 0u, a.kind);
-            sm.s0[t & 1][j * 2] = pcv[k];
+            if (in) zv = hs_noise<true>(sd, (uint64_t)gy * W + gx, 0u, a.kind);
+            sm.s0[t & 1][j * 2] = in ? pcv[k] : 0.f;
             sm.s0[t & 1][j * 2 + 1] = zv;
           }
         }
       }
       prefetch_window(t + 1);
     }
-    // ---- cone t + 3 decoded, cone t + 4's entry loaded
-    if (wave == 7 && lane == 0) {
-      put_cone(t + 3, pend_u);
-      if (t + 4 < nloc) pend_u = load_entry(t + 4);
-    }
-    // ---- stage 1: layer 1 of cone t - 1, one run at a time (waves 0-2 one
-    // run each, wave 6 three, wave 7 two)
-    const int l1run0 = wave < 3 ? wave : wave == 6 ? 3 : 6;
-    const int l1runs = wave < 3 ? 1 : wave == 6 ? 3 : wave == 7 ? 2 : 0;
+    // ---- cone t + 3 decoded
+    if (wave == 7) decode(t + 3);
+    // ---- stage 1: layer 1 of cone t - 1, one run at a time (split: waves
+    // 0-2 one run each, wave 6 three, wave 7 two; FP16: waves 0-2 one each,
+    // waves 4 and 5 two, wave 6 one)
+    const int l1run0 = wave < 3 ? wave
+                       : HALF ? (wave == 4 ? 3 : wave == 5 ? 5 : wave == 6 ? 7 : 0)
+                              : (wave == 6 ? 3 : 6);
+    const int l1runs = wave < 3 ? 1
+                       : HALF ? (wave == 4 || wave == 5 ? 2 : wave == 6 ? 1 : 0)
+                              : (wave == 6 ? 3 : wave == 7 ? 2 : 0);
     if (l1runs && t >= 1 && t - 1 < nloc) {
       const int i = t - 1, sl = i & 1;
       const int* ci = sm.cinfo[i & 15];
@@ -714,7 +751,7 @@ __global__ __launch_bounds__(F32_THREADS, 2) void recheck_fp32_kernel(
       if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
         const uint64_t a = (uint64_t)gy * W + gx;
         cv = contone[img + a];
-        zv = hs_noise(seed, a, 0u, kind);
+        zv = hs_noise<true>(seed, a, 0u, kind);
       }
       s0[i * 2] = cv;
       s0[i * 2 + 1] = zv;
