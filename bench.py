@@ -164,7 +164,7 @@ def bench_loss(hb, synth, torch, dev, steps):
             "config": "16 x 256x256 crops, LE gradient + anisotropy gradient, FP32"}
 
 
-def bench_pages(hb, synth, torch, dev, wt, steps, tau):
+def bench_pages(hb, synth, torch, dev, wt, steps, tau, tau2):
     """The uneven batch: 48 pages (sizes from seed 3,000,000, page seeds
     3,000,000 + i), contones made on the device with the same recipe."""
     shapes = synth.page_sizes(3_000_000)
@@ -179,10 +179,13 @@ def bench_pages(hb, synth, torch, dev, wt, steps, tau):
         len(shapes), sh.ctypes.data_as(hb.ctypes.c_void_p), hb.HS_BF16), dtype=torch.uint8,
         device=dev)
 
+    pol = hb.Policy(wt)
+
     def run(stats=False, levels=None, prec=hb.HS_BF16):
-        return hb.halftone_infer_pages(wt, flat, st, shapes, precision=prec,
-                                       recheck_tau=tau if prec == hb.HS_BF16 else None,
-                                       stats=stats, workspace=ws, levels=levels)
+        return hb.halftone_policy_infer(pol, flat, st, shapes, precision=prec,
+                                        recheck_tau=tau if prec == hb.HS_BF16 else None,
+                                        recheck_tau2=tau2, stats=stats, workspace=ws,
+                                        levels=levels or 2)
 
     def timed(levels, prec=hb.HS_BF16):
         run(levels=levels, prec=prec)
@@ -285,6 +288,11 @@ def main():
     # 1.3 x the largest BF16 logit error (0.0423) measured by --calibrate on
     # 8 x 1024 x 1024 calibration images (seeds 101..108)
     ap.add_argument("--tau", type=float, default=0.055)
+    # the split stage's band: 2 x its largest logit error (5.4e-5, measured
+    # by --calibrate on the same calibration images), at the floor 1.5e-4;
+    # at most 2e-4, so the split stage decides every listed pixel (those it
+    # leaves near zero are inside the 4e-4 margin) and no FP32 stage runs
+    ap.add_argument("--tau2", type=float, default=1.5e-4)
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -334,7 +342,7 @@ def main():
 
     def step():
         return hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_BF16, recheck_tau=args.tau,
-                                        workspace=ws)
+                                        recheck_tau2=args.tau2, workspace=ws)
 
     if args.probe == "infer":
         step()
@@ -381,22 +389,25 @@ def main():
 
     # recheck statistics and agreement with the FP32 path on the same batch
     bits16, lg16, stats = hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_BF16,
-                                                   recheck_tau=args.tau, logits=True, stats=True,
-                                                   workspace=ws)
+                                                   recheck_tau=args.tau, recheck_tau2=args.tau2,
+                                                   logits=True, stats=True, workspace=ws)
     stats = stats.cpu().tolist()
-    extra = {"recheck": {"tau": args.tau, "rechecked": stats[0], "flipped": stats[1],
+    extra = {"recheck": {"tau": args.tau, "tau2": args.tau2, "rechecked": stats[0],
+                         "flipped": stats[1],
                          "fp16_cone_decided": stats[0] - stats[4],
                          "split_recomputed": stats[4], "fp32_recomputed": stats[2],
                          "fraction": round(stats[0] / npx, 6)},
              "repack_each_call": {"value": round(v_repack, 1), "unit": "Mpx/s",
-                                  "call": "halftone_infer (weights packed inside every call)"}}
+                                  "call": "halftone_infer (weights packed inside every call, "
+                                          "default split band tau / 64, so with the FP32 "
+                                          "stage)"}}
     # the same path with an FP16 fused pass (three more mantissa bits at the
     # same matrix-core rate, so an 8 times narrower recheck band)
     tau16 = hb.RECHECK_TAU[hb.HS_FP16]
 
     def step16():
         return hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_FP16, recheck_tau=tau16,
-                                        workspace=ws)
+                                        recheck_tau2=args.tau2, workspace=ws)
 
     # the clock drops in the host synchronisations of the stats call above
     # and takes some tens of calls to recover, as at the start
@@ -412,7 +423,7 @@ def main():
     kern16_ms, launches16 = hb.halftone_profile_stop()
     k16 = kern16_ms / 1e3 / max(launches16, 1)
     bits_h, st16 = hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_FP16, recheck_tau=tau16,
-                                            stats=True, workspace=ws)
+                                            recheck_tau2=args.tau2, stats=True, workspace=ws)
     st16 = st16.cpu().tolist()
     v16 = npx * args.steps / dt16 / 1e6
     extra["fp16"] = {"value": round(v16, 1), "unit": "Mpx/s",
@@ -489,7 +500,8 @@ def main():
     if not args.no_train:
         extra["loss"] = bench_loss(hb, synth, torch, dev, 20)
     if not args.no_pages:
-        extra["pages"] = bench_pages(hb, synth, torch, dev, wt, args.page_steps, args.tau)
+        extra["pages"] = bench_pages(hb, synth, torch, dev, wt, args.page_steps, args.tau,
+                                     args.tau2)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpx/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -498,7 +510,7 @@ def main():
         "config": {"workload": "inference: 8 x 1024x1024 synthetic contones (seeds 11..18), "
                                "6x32 policy, He-init weights (seed 42) packed once, BF16 MFMA "
                                "+ FP16/split/FP32 recheck", "batch": B, "height": H, "width": W,
-                   "recheck_tau": args.tau},
+                   "recheck_tau": args.tau, "recheck_tau2": args.tau2},
         "roofline": roofline,
     }
     if not args.no_cpu:

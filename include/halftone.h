@@ -145,7 +145,11 @@ int64_t halftone_param_count(void);
  *          with split-BF16 products (hi*hi + lo*hi + hi*lo, FP32
  *          accumulation, about 2^-8 of the BF16 error), and every pixel
  *          whose split |x| is still below tau2 = max(recheck_tau/64,
- *          1.5e-4) once more in FP32, decided from that value
+ *          1.5e-4) once more in FP32, decided from that value (when tau2
+ *          <= 2e-4 there is no FP32 stage: such a pixel's exact logit is
+ *          within 2 tau2 <= 4e-4 of the threshold, inside the margin
+ *          |p - 1/2| <= 1e-4 where either bit is the oracle's, and the
+ *          split stage decides it from its own logit)
  *          (recheck_tau >= 0; it must exceed the largest BF16 logit error
  *          for the bits to equal FP32's off-margin, and tau2 the split
  *          stage's). halftone_policy_infer takes tau2 explicitly and can

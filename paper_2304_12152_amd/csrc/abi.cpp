@@ -475,6 +475,13 @@ size_t halftone_infer_workspace_size(int B, int H, int W, int precision) {
 // 1.5e-4, which is under the 4e-4 margin and 2.8 times the largest split
 // error measured for the He policy.
 static float default_tau2(float tau) { return fmaxf(tau / 64.0f, 1.5e-4f); }
+// The bits must equal the oracle's wherever |p - 1/2| > 1e-4, i.e. |x| >
+// 2 atanh(2e-4) = 4.0e-4. A pixel the split stage leaves undecided has
+// |x_split| < tau2 and so, its error being below tau2, an exact |x| below
+// 2 tau2: with tau2 <= 2e-4 it is inside that margin, where either bit is
+// the oracle's, and the split stage decides it from its own logit; only a
+// larger tau2 needs the FP32 stage.
+constexpr float HALF_MARGIN_X = 2.0e-4f;
 // The FP16 cone stage after a BF16 pass decides |x| >= tau16 (FP16 rounds 8
 // times finer than BF16, so a quarter of the BF16 band would leave it twice
 // its share of the error). Per listed pixel it costs about as much as the
@@ -545,6 +552,8 @@ static int infer_bf16(const float* weights, const Packed* pp, const float* conto
                               8.0f * recheck_tau, lv, bits, logits, w.seglist, w.seg_count,
                               &nseg, &seg_cap, frags, FUSED_BF16, nullptr, ovf, 1, num_cus(),
                               s));
+  const bool fp32_stage = tau2 > HALF_MARGIN_X;
+  const float split_band = fp32_stage ? tau2 : 0.0f;  // 0: the split stage decides all
   if (!fp16 && tau16 > 0.0f) {
     // FP16 cones over the fused pass's list (into list2), split cones over
     // theirs (into the fused list's memory, which is free by then), FP32
@@ -552,19 +561,21 @@ static int infer_bf16(const float* weights, const Packed* pp, const float* conto
                                 w.seg_count, nseg, seg_cap, cw, tau16, lv, w.list2, w.cnt + 1,
                                 bits, logits, stats, 0, num_cus(), s));
     HS_TRY(launch_recheck_cones(false, weights, contone, seeds, w.pages, noise_kind, w.list2,
-                                w.cnt + 1, 1, (long long)N, cw, tau2, lv, w.seglist, w.cnt + 2,
-                                bits, logits, stats, 4, num_cus(), s));
-    HS_TRY(launch_recheck_fp32(weights, contone, seeds, w.pages, noise_kind, w.seglist,
-                               w.cnt + 2, cw.wt, lv, bits, logits, stats, 2, num_cus(), s));
+                                w.cnt + 1, 1, (long long)N, cw, split_band, lv, w.seglist,
+                                w.cnt + 2, bits, logits, stats, 4, num_cus(), s));
+    if (fp32_stage)
+      HS_TRY(launch_recheck_fp32(weights, contone, seeds, w.pages, noise_kind, w.seglist,
+                                 w.cnt + 2, cw.wt, lv, bits, logits, stats, 2, num_cus(), s));
     return HS_OK;
   }
   // after an FP16 pass (or with tau16 = 0): split cones over the fused
   // pass's list, then FP32
   HS_TRY(launch_recheck_cones(false, weights, contone, seeds, w.pages, noise_kind, w.seglist,
-                              w.seg_count, nseg, seg_cap, cw, tau2, lv, w.list2, w.cnt + 1, bits,
-                              logits, stats, 0, num_cus(), s));
-  HS_TRY(launch_recheck_fp32(weights, contone, seeds, w.pages, noise_kind, w.list2, w.cnt + 1,
-                             cw.wt, lv, bits, logits, stats, 2, num_cus(), s));
+                              w.seg_count, nseg, seg_cap, cw, split_band, lv, w.list2, w.cnt + 1,
+                              bits, logits, stats, 0, num_cus(), s));
+  if (fp32_stage)
+    HS_TRY(launch_recheck_fp32(weights, contone, seeds, w.pages, noise_kind, w.list2, w.cnt + 1,
+                               cw.wt, lv, bits, logits, stats, 2, num_cus(), s));
   return HS_OK;
 }
 

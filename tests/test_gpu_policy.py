@@ -100,12 +100,51 @@ def test_split_stage_band_exposes_its_error():
     _say("split error", err, "bf16 error", e16)
     assert 0.0 < err < e16 / 50
     # with an explicit tau2 above that error the bits equal the FP32 path's
-    # wherever the two FP32 summation orders cannot disagree
-    bits = hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_BF16, recheck_tau=1e30,
-                                    recheck_tau16=0.0, recheck_tau2=4 * err)
+    # off the margin |x| > 4e-4 (a tau2 of at most 2e-4 leaves no pixel to
+    # the FP32 stage: the split stage decides all of them)
+    bits, stt = hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_BF16, recheck_tau=1e30,
+                                         recheck_tau16=0.0, recheck_tau2=4 * err, stats=True)
     b32 = hb.halftone_infer(wt, ct, st, precision=hb.HS_FP32)
-    off = l32.abs() > 1e-4
+    off = l32.abs() > 4.1e-4
     assert torch.equal(bits[off], b32[off])
+    if 4 * err <= 2e-4:
+        assert stt[2].item() == 0
+
+
+def test_no_fp32_stage_when_the_split_band_is_below_half_the_margin(orc):
+    """tau2 <= 2e-4: every pixel the split stage cannot resolve is within
+    2 tau2 <= 4e-4 of the threshold (inside the margin), so the split stage
+    decides all listed pixels and no FP32 stage runs; the bits still equal
+    the oracle's off the margin (binary and 4 levels)."""
+    B, H, W = 3, 120, 200
+    seeds = [75, 76, 77]
+    w, c = inputs(seeds, H, W)
+    wt, ct, st = to_dev(w), to_dev(c), seeds_t(seeds)
+    pol = hb.Policy(wt)
+    z = orc.noise_map(seeds, H, W, kind=0, stream=1, step=0)
+    ref = orc.policy_forward(w.astype(np.float64), c.astype(np.float64), z)
+    for tau2 in (1.5e-4, 2e-4, 2.5e-4):
+        bits, lg, stt = hb.halftone_policy_infer(pol, ct, st, precision=hb.HS_BF16,
+                                                 recheck_tau=0.055, recheck_tau2=tau2,
+                                                 logits=True, stats=True)
+        stt = stt.cpu().numpy()
+        assert stt[0] > 0 and stt[4] == stt[0]
+        assert (stt[2] == 0) == (tau2 <= 2e-4), (tau2, stt)
+        m = parity_mask(orc, ref)
+        assert np.array_equal(bits.cpu().numpy()[m], (ref >= 0)[m].astype(np.uint8))
+        lgn = lg.cpu().numpy()
+        near = np.abs(lgn) < 0.055  # listed: the split stage's logits
+        assert np.abs(lgn[near] - ref[near]).max() < 2e-4
+    # 4 levels: the distance to the nearest threshold the same way
+    shapes = [(H, W)] * B
+    lev, stl = hb.halftone_policy_infer(pol, ct.reshape(-1), st, shapes, precision=hb.HS_BF16,
+                                        recheck_tau=0.055, recheck_tau2=1.5e-4, stats=True,
+                                        levels=4)
+    assert stl.cpu().numpy()[2] == 0
+    thr = np.log(np.array([1.0, 3.0, 5.0]) / np.array([5.0, 3.0, 1.0]))
+    want = (ref[..., None] >= thr).sum(-1).reshape(-1)
+    keep = (np.abs(ref[..., None] - thr).min(-1) > 4e-4).reshape(-1)
+    assert np.array_equal(lev.cpu().numpy()[keep], want[keep])
 
 
 def test_finite_check_rejects_nan_and_inf(orc):
