@@ -276,10 +276,11 @@ def calibrate(hb, synth, torch, dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--calibrate", action="store_true")
-    ap.add_argument("--probe", choices=["infer", "copy"], default=None,
+    ap.add_argument("--probe", choices=["infer", "copy", "train"], default=None,
                     help="a minimal run for hardware-counter passes: one inference call "
-                         "on the workload, or a plain 512 MiB device copy (the reference "
-                         "for scaling the memory-traffic counters)")
+                         "on the workload, a plain 512 MiB device copy (the reference "
+                         "for scaling the memory-traffic counters), or two training steps "
+                         "on the training batch (32 x 256 x 256 + 64 gray 64 x 64)")
     ap.add_argument("--gpus", type=int, default=1)
     # the GPU reaches its sustained clock after some tens of milliseconds of
     # load: 50 warm-up calls (about 55 ms on the inference workload) come first
@@ -324,6 +325,19 @@ def main():
             bcopy.copy_(a)
         torch.cuda.synchronize()
         log("copied 3 x 512 MiB")
+        return
+    if args.probe == "train":
+        Bt, Ht, Wt, Bg = 32, 256, 256, 64
+        tw = torch.tensor(synth.he_weights(42, head_std=0.01), device=dev)
+        state = hb.TrainState(tw, Bt, Ht, Wt, Bg, 64, 64, precision=hb.HS_BF16)
+        tc = torch.tensor(synth.contone_batch(range(1000000, 1000032), Ht, Wt), device=dev)
+        ts = torch.tensor(list(range(1000000, 1000032)), dtype=torch.int64, device=dev)
+        gray = torch.tensor(synth.gray_batch(64, 64, 64), device=dev)
+        gs = torch.tensor(list(range(5000, 5064)), dtype=torch.int64, device=dev)
+        for i in range(2):
+            hb.policy_train_step(state, tc, ts, gray, gs, i, 1000)
+        torch.cuda.synchronize()
+        log("two training steps")
         return
     B, H, W = 8, 1024, 1024
     seeds = list(range(11, 19))
