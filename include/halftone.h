@@ -58,6 +58,8 @@ extern "C" {
 #define HS_FP32 0 /* FP32 arithmetic throughout                           */
 #define HS_BF16 1 /* BF16 MFMA with FP32 accumulation                      */
 #define HS_FP16 2 /* FP16 MFMA with FP32 accumulation (inference only)     */
+#define HS_FP8 3  /* FP8 (E4M3) MFMA for the 32->32 layers, FP32
+                     accumulation (packed policies with FP8 scales only)   */
 
 #define HS_NOISE_GAUSS 0   /* z ~ N(0,1) (Sec. III, "State")               */
 #define HS_NOISE_UNIFORM 1 /* z ~ U(0,1), the variant of Sec. VI-D         */
@@ -289,6 +291,8 @@ typedef struct hs_policy {
   void* mem;    /* the caller's device memory holding the packed copies */
   size_t bytes; /* its size */
   int packed;   /* 1 once halftone_policy_pack has succeeded */
+  int fp8;      /* 1 once halftone_policy_set_fp8 has succeeded (a new
+                   pack clears it) */
 } hs_policy;
 size_t halftone_policy_bytes(void);
 int halftone_policy_pack(hs_policy* policy, const float* weights, void* mem, size_t bytes,
@@ -299,6 +303,40 @@ int halftone_policy_infer(const hs_policy* policy, const float* contone, const u
                           float recheck_tau2, uint8_t* out, float* logits_or_null,
                           int32_t* stats_or_null, void* workspace, size_t workspace_bytes,
                           void* stream);
+
+/* ---------------------------------------------------------------------
+ * The FP8 pass of a packed policy: the TEST procedure of Algorithm 1 with
+ * the four 32->32 convolutions of the policy network (Sec. VI-A; 97.7% of
+ * its multiply-adds) on the FP8 E4M3 matrix cores. The paper reports FP32
+ * runtimes only (Sec. VI-C); this precision is the library's own, and the
+ * recheck stages keep the bits those of FP32 off the margin.
+ *
+ * halftone_layer_max: the FP32 forward of `weights` (noise and shapes as
+ *          in halftone_infer with HS_FP32); layer_max [5] FP32 DEVICE out:
+ *          the largest activation (after the ReLU) of layers 1..5 over the
+ *          batch. Workspace halftone_infer_workspace_size(B, H, W,
+ *          HS_FP32). For calibration on images other than those to be
+ *          halftoned.
+ * halftone_policy_set_fp8: the FP8 copy of a packed policy from
+ *          act_max_host [4] (HOST FP32, finite, >= 0): calibrated maxima
+ *          of layers 1..4's activations. Layer k's activations are stored
+ *          as E4M3 codes of a / s_k, s_k the smallest power of two with
+ *          4 act_max[k] <= 448 s_k; each output channel of layers 2..5 has
+ *          its own power-of-two weight scale (largest |w| at most 448
+ *          times it). Layers 1 and 6 stay BF16. Enqueued on `stream`;
+ *          packing the policy again clears it. Errors: HS_EINVAL (policy
+ *          not packed, a bad maximum).
+ * halftone_policy_infer with precision HS_FP8: the fused pass in FP8, then
+ *          the split and FP32 stages as after HS_FP16 (recheck_tau16 is
+ *          ignored). recheck_tau must exceed the FP8 pass's largest logit
+ *          error, measured like the BF16 one. If an activation exceeds 448
+ *          s_k (saturation), the pass is run again in BF16 with
+ *          recheck_tau / 8, decided on the device, and stats[3] reads 1.
+ * --------------------------------------------------------------------- */
+int halftone_layer_max(const float* weights, const float* contone, const uint64_t* seeds, int B,
+                       int H, int W, int noise_kind, float* layer_max, void* workspace,
+                       size_t workspace_bytes, void* stream);
+int halftone_policy_set_fp8(hs_policy* policy, const float* act_max_host, void* stream);
 
 /* ---------------------------------------------------------------------
  * Training-mode policy forward and its backward (the conv stack of

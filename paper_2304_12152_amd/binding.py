@@ -7,6 +7,8 @@ library is not built, or the device is not a gfx950, calls fail loudly.
 import ctypes
 import os
 
+import numpy as np
+
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -15,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libhalftone.so")
 HS_OK, HS_EINVAL, HS_ESHAPE, HS_EUNSUPPORTED, HS_EWORKSPACE, HS_EHIP = 0, -1, -2, -3, -4, -5
 HS_ENONFINITE = -6
 HS_CHECK_FINITE = 0x100
-HS_FP32, HS_BF16, HS_FP16 = 0, 1, 2
+HS_FP32, HS_BF16, HS_FP16, HS_FP8 = 0, 1, 2, 3
 HS_NOISE_GAUSS, HS_NOISE_UNIFORM = 0, 1
 HS_WRT_PROB, HS_WRT_LOGIT = 0, 1
 HS_EST_LE, HS_EST_COMA = 0, 1
@@ -38,7 +40,8 @@ class HsTrainParams(ctypes.Structure):
 
 
 class HsPolicy(ctypes.Structure):
-    _fields_ = [("mem", ctypes.c_void_p), ("bytes", ctypes.c_size_t), ("packed", ctypes.c_int)]
+    _fields_ = [("mem", ctypes.c_void_p), ("bytes", ctypes.c_size_t), ("packed", ctypes.c_int),
+                ("fp8", ctypes.c_int)]
 
 
 class HalftoneError(RuntimeError):
@@ -69,6 +72,8 @@ _SIGS = {
     "halftone_policy_pack": (I, [ctypes.POINTER(HsPolicy), P, P, SZ, I, P]),
     "halftone_policy_infer": (I, [ctypes.POINTER(HsPolicy), P, P, I, P, I, I, I, F, F, F, P, P, P,
                                   P, SZ, P]),
+    "halftone_layer_max": (I, [P, P, P, I, I, I, I, P, P, SZ, P]),
+    "halftone_policy_set_fp8": (I, [ctypes.POINTER(HsPolicy), P, P]),
     "halftone_policy_workspace_size": (SZ, [I, I, I, I]),
     "halftone_policy_forward": (I, [P, P, P, I, I, I, I, ctypes.c_uint32, I, P, P, SZ, P]),
     "halftone_policy_backward": (I, [P, P, P, I, I, I, I, P, P, SZ, P]),
@@ -208,7 +213,6 @@ def halftone_infer_noalloc(weights, contone, seeds, noise_kind=HS_NOISE_GAUSS, p
 
 def page_shapes_array(shapes):
     """int32 [npages][2] host array of (H, W) pairs."""
-    import numpy as np
     return np.ascontiguousarray(np.asarray(shapes, dtype=np.int32).reshape(-1, 2))
 
 
@@ -263,6 +267,31 @@ class Policy:
         self.handle = HsPolicy()
         _check(lib().halftone_policy_pack(ctypes.byref(self.handle), _ptr(weights), _ptr(self.mem),
                                           n, HS_CHECK_FINITE if check_finite else 0, _stream()))
+        self.act_max = None
+
+    def set_fp8(self, act_max):
+        """halftone_policy_set_fp8: the FP8 copy from the calibrated maxima
+        of layers 1..4's activations (4 floats, e.g. the first four of
+        halftone_layer_max on calibration images)."""
+        a = np.ascontiguousarray(np.asarray(act_max, dtype=np.float32)[:4])
+        assert a.shape == (4,)
+        _check(lib().halftone_policy_set_fp8(ctypes.byref(self.handle),
+                                             a.ctypes.data_as(ctypes.c_void_p), _stream()))
+        self.act_max = a.copy()
+        return self
+
+
+def halftone_layer_max(weights, contone, seeds, noise_kind=HS_NOISE_GAUSS, workspace=None):
+    """The largest activation of layers 1..5 of the FP32 forward over the
+    batch contone [B,H,W]: a float32 tensor of 5 on the device."""
+    _dev(weights, torch.float32), _dev(contone, torch.float32), _dev(seeds, torch.int64)
+    B, H, W = contone.shape
+    out = torch.empty(5, dtype=torch.float32, device=contone.device)
+    need = lib().halftone_infer_workspace_size(B, H, W, HS_FP32)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _ws(need, contone.device)
+    _check(lib().halftone_layer_max(_ptr(weights), _ptr(contone), _ptr(seeds), B, H, W, noise_kind,
+                                    _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
 
 
 def halftone_policy_infer(policy, contone, seeds, shapes=None, noise_kind=HS_NOISE_GAUSS,
@@ -271,7 +300,10 @@ def halftone_policy_infer(policy, contone, seeds, shapes=None, noise_kind=HS_NOI
     """halftone_policy_infer on a packed Policy. contone: [B,H,W] (a uniform
     batch) or the flat concatenation of pages with `shapes`; the outputs
     have the contone's shape. The cone stages' bands recheck_tau16 and
-    recheck_tau2: -1 for the default rules."""
+    recheck_tau2: -1 for the default rules. HS_FP8 needs policy.set_fp8 and
+    an explicit recheck_tau (calibrate.bands)."""
+    if precision == HS_FP8 and recheck_tau is None:
+        raise ValueError("HS_FP8 has no default band: pass recheck_tau (calibrate.bands)")
     recheck_tau = _tau(precision, recheck_tau)
     if shapes is None:
         B, H, W = contone.shape

@@ -27,13 +27,20 @@ recipe of `synth.contone`.
 
 `plan` also prices the options: with a band wide enough to list a few
 percent of the pixels, the FP32 path becomes the cheaper exact one.
+
+The FP8 pass (HS_FP8) also needs activation scales: `fp8_policy` measures
+the largest activation of layers 1..4 in the FP32 forward on the
+calibration batch (`halftone_layer_max`) and makes a packed policy's FP8
+copy from them; `bands(weights, hb.HS_FP8)` does so when it is given no
+such policy and returns it under "policy", since the band holds for those
+scales only.
 """
 import numpy as np
 
 from . import binding as hb
 from . import synth
 
-MARGIN = {hb.HS_BF16: 1.3, hb.HS_FP16: 1.5}
+MARGIN = {hb.HS_BF16: 1.3, hb.HS_FP16: 1.5, hb.HS_FP8: 1.5}
 CONE_MARGIN = 2.0     # the cone stages' bands over their largest measured error
 TAU2_FLOOR = 1.5e-4   # the split stage's band is never below this (the library's floor)
 
@@ -77,24 +84,41 @@ def _distance(x, levels):
     return (x.reshape(-1, 1) - thr).abs().min(dim=1).values.reshape(x.shape)
 
 
-def stage_errors(weights, precision, contone, seeds, levels=2):
+def fp8_policy(weights, contone=None, seeds=None, policy=None):
+    """A packed Policy of `weights` (or `policy`, packed from them) with its
+    FP8 copy, scaled for the largest activations of layers 1..4 in the FP32
+    forward over the calibration batch (default: 2 synthetic 512 x 512
+    contones, seeds 101 and 102)."""
+    contone, st = _batch(weights, contone, seeds, "fp8_policy")
+    mx = hb.halftone_layer_max(weights, contone, st).cpu().numpy()
+    pol = hb.Policy(weights) if policy is None else policy
+    return pol.set_fp8(mx[:4])
+
+
+def stage_errors(weights, precision, contone, seeds, levels=2, policy=None):
     """Largest |x - x_32| of each stage over the batch (device tensors:
     weights FP32, contone [B, H, W] FP32, seeds int64): "pass" the fused
-    16-bit pass (the BF16 re-run if an FP16 pass overflowed, then
-    "overflow" is True), "cone16" the FP16 cone stage (BF16 only; cones it
-    passes on for overflow are not counted) and "split" the split stage."""
+    pass (the BF16 re-run if an FP16 pass overflowed or an FP8 pass
+    saturated, then "overflow" is True), "cone16" the FP16 cone stage (BF16
+    only; cones it passes on for overflow are not counted) and "split" the
+    split stage. HS_FP8 runs on `policy`, which must have its FP8 copy."""
     flat, shapes = _pages(contone, levels)
     _, l32 = hb.halftone_infer_pages(weights, flat, seeds, shapes, precision=hb.HS_FP32,
                                      logits=True, levels=levels)
-    _, l16, st = hb.halftone_infer_pages(weights, flat, seeds, shapes, precision=precision,
-                                         recheck_tau=0.0, logits=True, stats=True,
-                                         levels=levels)
+    pol = hb.Policy(weights) if policy is None else policy
+    if precision == hb.HS_FP8:
+        _, l16, st = hb.halftone_policy_infer(pol, flat, seeds, shapes, precision=precision,
+                                              recheck_tau=0.0, logits=True, stats=True,
+                                              levels=levels)
+    else:
+        _, l16, st = hb.halftone_infer_pages(weights, flat, seeds, shapes, precision=precision,
+                                             recheck_tau=0.0, logits=True, stats=True,
+                                             levels=levels)
     out = {"overflow": int(st[3]) != 0}
     if out["overflow"]:
         _, l16 = hb.halftone_infer_pages(weights, flat, seeds, shapes, precision=hb.HS_BF16,
                                          recheck_tau=0.0, logits=True, levels=levels)
     out["pass"] = float((l16 - l32).abs().max())
-    pol = hb.Policy(weights)
     # every pixel listed; one stage decides all of them (tau2 = 0: none go
     # on to FP32; tau16 = 1e-30: the FP16 stage decides all but overflowed
     # cones and exact zeros, which the split stage decides)
@@ -120,22 +144,34 @@ def max_logit_error(weights, precision, contone, seeds):
     return float((l16 - l32).abs().max())
 
 
-def bands(weights, precision=hb.HS_BF16, contone=None, seeds=None, margin=None, levels=2):
+def bands(weights, precision=hb.HS_BF16, contone=None, seeds=None, margin=None, levels=2,
+          policy=None):
     """The three bands for `weights` (a device tensor) from the stage errors
     on the calibration batch (default: 2 synthetic 512 x 512 contones, seeds
     101 and 102): {"tau", "tau16", "tau2", "errors"}; tau16 is 0 (no FP16
-    cone stage) for an FP16 pass."""
+    cone stage) after an FP16 or FP8 pass. HS_FP8: on `policy` if it has
+    its FP8 copy, else on one made by fp8_policy from the calibration batch
+    (returned under "policy"); tau is at least 8 times the BF16 default,
+    so that the BF16 re-run after a saturation (tau / 8) keeps that band."""
     if precision not in MARGIN:
-        raise ValueError("bands: precision must be HS_BF16 or HS_FP16")
+        raise ValueError("bands: precision must be HS_BF16, HS_FP16 or HS_FP8")
     contone, st = _batch(weights, contone, seeds, "bands")
-    e = stage_errors(weights, precision, contone, st, levels)
+    if precision == hb.HS_FP8 and (policy is None or policy.act_max is None):
+        policy = fp8_policy(weights, contone, st.tolist(), policy)
+    e = stage_errors(weights, precision, contone, st, levels, policy)
     m = MARGIN[precision] if margin is None else margin
-    tau = max(m * e["pass"], hb.RECHECK_TAU[precision])
-    if e["overflow"]:
-        tau = max(tau, 8.0 * hb.RECHECK_TAU[precision])
+    if precision == hb.HS_FP8:
+        tau = max(m * e["pass"], 8.0 * hb.RECHECK_TAU[hb.HS_BF16])
+    else:
+        tau = max(m * e["pass"], hb.RECHECK_TAU[precision])
+        if e["overflow"]:
+            tau = max(tau, 8.0 * hb.RECHECK_TAU[precision])
     tau2 = max(CONE_MARGIN * e["split"], TAU2_FLOOR)
     tau16 = max(CONE_MARGIN * e["cone16"], 2.0 * tau2) if "cone16" in e else 0.0
-    return {"tau": tau, "tau16": tau16, "tau2": tau2, "errors": e}
+    out = {"tau": tau, "tau16": tau16, "tau2": tau2, "errors": e}
+    if precision == hb.HS_FP8:
+        out["policy"] = policy
+    return out
 
 
 def recheck_tau(weights, precision=hb.HS_BF16, contone=None, seeds=None, margin=None):
@@ -143,8 +179,8 @@ def recheck_tau(weights, precision=hb.HS_BF16, contone=None, seeds=None, margin=
     logit error of the fused pass on the calibration batch (default: 2
     synthetic 512 x 512 contones, seeds 101 and 102), at least
     RECHECK_TAU[precision]."""
-    if precision not in MARGIN:
-        raise ValueError("recheck_tau: precision must be HS_BF16 or HS_FP16")
+    if precision not in (hb.HS_BF16, hb.HS_FP16):
+        raise ValueError("recheck_tau: precision must be HS_BF16 or HS_FP16 (bands for HS_FP8)")
     contone, st = _batch(weights, contone, seeds, "recheck_tau")
     err = max_logit_error(weights, precision, contone, st)
     m = MARGIN[precision] if margin is None else margin

@@ -6,9 +6,12 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <initializer_list>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "hs_internal.h"
@@ -391,7 +394,7 @@ static ConeWeights cone_weights(char* region, int* wflag) {
 // call that packs for itself.
 struct Packed {
   float* w;
-  char *frags, *frags16, *split, *pack32;
+  char *frags, *frags16, *split, *pack32, *frags8;
   int* needs_all;
 };
 static size_t policy_layout(void* base, Packed* out) {
@@ -403,6 +406,7 @@ static size_t policy_layout(void* base, Packed* out) {
   p.split = cv.take<char>(cone_region_bytes());
   p.pack32 = cv.take<char>(pack_bytes(HS_FP32));
   p.needs_all = cv.take<int>(64 * sizeof(int));
+  p.frags8 = cv.take<char>(fp8_block_bytes());
   if (out) *out = p;
   return cv.off;
 }
@@ -489,11 +493,17 @@ constexpr float HALF_MARGIN_X = 2.0e-4f;
 // call can set its band.
 static float default_tau16(float) { return 0.0f; }
 
+// The fused pass's arithmetic.
+enum Pass { PASS_BF16, PASS_FP16, PASS_FP8 };
+
 // The 16-bit path over a page table (one persistent fused launch for all pages):
-//   stage 1: fused BF16 (or FP16) pass, pixels with |x| < tau listed
-//   stage 1b (FP16 only): if an activation overflowed FP16, the fused BF16
-//            pass again, with 8 tau (BF16 rounds 8 times coarser); a launch
-//            that returns at once otherwise, so no host synchronisation
+//   stage 1: fused BF16 (or FP16, or FP8) pass, pixels with |x| < tau listed
+//   stage 1b (FP16 and FP8): if an activation overflowed FP16 or saturated
+//            FP8, the fused BF16 pass again, with 8 tau after FP16 (BF16
+//            rounds 8 times coarser) and tau / 8 after FP8 (E4M3 keeps 4
+//            significant bits to BF16's 8, and its measured logit error is
+//            12 to 16 times BF16's); a launch that returns at once
+//            otherwise, so no host synchronisation
 //   stage 2: split-BF16 receptive-field recompute, |x| < tau2 listed again
 //   stage 3: FP32 receptive-field recompute
 // The page table is built on the device (uniform batch) or from pages_host.
@@ -502,8 +512,9 @@ static float default_tau16(float) { return 0.0f; }
 static int infer_bf16(const float* weights, const Packed* pp, const float* contone,
                       const uint64_t* seeds, const int* shapes, int npages, size_t N,
                       const Page* pages_host, int noise_kind, float recheck_tau, float tau16,
-                      float tau2, const Levels& lv, bool fp16, uint8_t* bits, float* logits,
+                      float tau2, const Levels& lv, Pass pass, uint8_t* bits, float* logits,
                       int32_t* stats_or_null, void* workspace, hipStream_t s) {
+  const bool fp16 = pass == PASS_FP16;
   Bf16Ws w;
   bf16_ws(shapes, npages, N, &w, workspace);
   int32_t* stats = stats_or_null ? stats_or_null : (int32_t*)(w.cnt + 16);
@@ -533,28 +544,34 @@ static int infer_bf16(const float* weights, const Packed* pp, const float* conto
   long long seg_cap = 0;
   int* ovf = stats + 3;  // zeroed above
   prof_begin(s);
-  if (!fp16) {
+  if (pass == PASS_FP8) {
     HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
                               recheck_tau, lv, bits, logits, w.seglist, w.seg_count, &nseg,
-                              &seg_cap, frags, FUSED_BF16, nullptr, nullptr, 0, num_cus(), s));
+                              &seg_cap, frags, pp->frags8, FUSED_FP8, ovf, nullptr, 0, num_cus(),
+                              s));
+  } else if (!fp16) {
+    HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
+                              recheck_tau, lv, bits, logits, w.seglist, w.seg_count, &nseg,
+                              &seg_cap, frags, nullptr, FUSED_BF16, nullptr, nullptr, 0,
+                              num_cus(), s));
   } else {
     // the device picks the FP16 form: of the two launches, the one whose
     // gate does not match needs_all returns at once
     for (int form : {FUSED_FP16_L5, FUSED_FP16_ALL})
       HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
                                 recheck_tau, lv, bits, logits, w.seglist, w.seg_count, &nseg,
-                                &seg_cap, frags16, form, ovf, needs_all,
+                                &seg_cap, frags16, nullptr, form, ovf, needs_all,
                                 form == FUSED_FP16_ALL, num_cus(), s));
   }
   prof_end(s);
-  if (fp16)
+  if (pass != PASS_BF16)
     HS_TRY(launch_fused_infer(weights, contone, seeds, w.pages, shapes, npages, noise_kind,
-                              8.0f * recheck_tau, lv, bits, logits, w.seglist, w.seg_count,
-                              &nseg, &seg_cap, frags, FUSED_BF16, nullptr, ovf, 1, num_cus(),
-                              s));
+                              fp16 ? 8.0f * recheck_tau : 0.125f * recheck_tau, lv, bits, logits,
+                              w.seglist, w.seg_count, &nseg, &seg_cap, frags, nullptr,
+                              FUSED_BF16, nullptr, ovf, 1, num_cus(), s));
   const bool fp32_stage = tau2 > HALF_MARGIN_X;
   const float split_band = fp32_stage ? tau2 : 0.0f;  // 0: the split stage decides all
-  if (!fp16 && tau16 > 0.0f) {
+  if (pass == PASS_BF16 && tau16 > 0.0f) {
     // FP16 cones over the fused pass's list (into list2), split cones over
     // theirs (into the fused list's memory, which is free by then), FP32
     HS_TRY(launch_recheck_cones(true, weights, contone, seeds, w.pages, noise_kind, w.seglist,
@@ -568,7 +585,7 @@ static int infer_bf16(const float* weights, const Packed* pp, const float* conto
                                  w.cnt + 2, cw.wt, lv, bits, logits, stats, 2, num_cus(), s));
     return HS_OK;
   }
-  // after an FP16 pass (or with tau16 = 0): split cones over the fused
+  // after an FP16 or FP8 pass (or with tau16 = 0): split cones over the fused
   // pass's list, then FP32
   HS_TRY(launch_recheck_cones(false, weights, contone, seeds, w.pages, noise_kind, w.seglist,
                               w.seg_count, nseg, seg_cap, cw, split_band, lv, w.list2, w.cnt + 1,
@@ -615,10 +632,15 @@ static int infer_fp32(const float* weights, const char* pack32, const float* con
 
 static int check_infer_args(const float* weights, const float* contone, const uint64_t* seeds,
                             const uint8_t* bits, const void* workspace, int noise_kind,
-                            int precision, float recheck_tau, const char* who) {
+                            int precision, float recheck_tau, const char* who,
+                            bool fp8_ok = false) {
   if (!weights || !contone || !seeds || !bits || !workspace)
     return fail(HS_EINVAL, "%s: null pointer", who);
-  if (precision != HS_FP32 && precision != HS_BF16 && precision != HS_FP16)
+  if (precision == HS_FP8 && !fp8_ok)
+    return fail(HS_EUNSUPPORTED, "%s: HS_FP8 needs a packed policy with FP8 scales "
+                "(halftone_policy_set_fp8)", who);
+  if (precision != HS_FP32 && precision != HS_BF16 && precision != HS_FP16 &&
+      precision != HS_FP8)
     return fail(HS_EUNSUPPORTED, "%s: precision %d", who, precision);
   const int kind = noise_kind & ~HS_CHECK_FINITE;
   if (kind != HS_NOISE_GAUSS && kind != HS_NOISE_UNIFORM)
@@ -650,8 +672,8 @@ int halftone_infer(const float* weights, const float* contone, const uint64_t* s
     }
     return infer_bf16(weights, nullptr, contone, seeds, sh.data(), B, N, nullptr, kind,
                       recheck_tau, default_tau16(recheck_tau), default_tau2(recheck_tau),
-                      make_levels(2), precision == HS_FP16, bits, logits_or_null, stats_or_null,
-                      workspace, s);
+                      make_levels(2), precision == HS_FP16 ? PASS_FP16 : PASS_BF16, bits,
+                      logits_or_null, stats_or_null, workspace, s);
   }
   if (noise_kind & HS_CHECK_FINITE) {
     int* cnt;
@@ -747,9 +769,10 @@ static int infer_pages(const float* weights, const Packed* pp, const float* cont
                        int noise_kind, int precision, float recheck_tau, float tau16, float tau2,
                        uint8_t* out,
                        float* logits_or_null, int32_t* stats_or_null, void* workspace,
-                       size_t workspace_bytes, void* stream, const char* who) {
+                       size_t workspace_bytes, void* stream, const char* who,
+                       bool fp8_ok = false) {
   int rc = check_infer_args(weights, contone, seeds, out, workspace, noise_kind, precision,
-                            recheck_tau, who);
+                            recheck_tau, who, fp8_ok);
   if (rc) return rc;
   if (levels < 2 || levels > HS_MAX_LEVELS)
     return fail(HS_EINVAL, "%s: levels %d (2..%d)", who, levels, HS_MAX_LEVELS);
@@ -791,7 +814,9 @@ static int infer_pages(const float* weights, const Packed* pp, const float* cont
     return infer_bf16(weights, pp, contone, seeds, shapes_host, npages, N,
                       uniform ? nullptr : pages.data(), kind, recheck_tau,
                       tau16 < 0.0f ? default_tau16(recheck_tau) : tau16,
-                      tau2 < 0.0f ? default_tau2(recheck_tau) : tau2, lv, precision == HS_FP16,
+                      tau2 < 0.0f ? default_tau2(recheck_tau) : tau2, lv,
+                      precision == HS_FP16 ? PASS_FP16
+                                           : (precision == HS_FP8 ? PASS_FP8 : PASS_BF16),
                       out, logits_or_null, stats_or_null, workspace, s);
   }
   if (noise_kind & HS_CHECK_FINITE) {
@@ -861,6 +886,78 @@ int halftone_policy_pack(hs_policy* policy, const float* weights, void* mem, siz
   policy->mem = mem;
   policy->bytes = bytes;
   policy->packed = 1;
+  policy->fp8 = 0;
+  return HS_OK;
+}
+
+// Activation scales of the FP8 pass: s_k = 2^e, the smallest power of two
+// with FP8_HEADROOM * act_max[k] <= 448 s_k, so an image may reach 4 times
+// the calibration maximum before the pass saturates (it then runs again in
+// BF16). Values below 2^-6 s_k lose precision as E4M3 subnormals, but their
+// absolute error (at most 2^-10 s_k, under 1e-4 of the maximum) stays far
+// below that of the largest values.
+constexpr float FP8_HEADROOM = 4.0f;
+
+int halftone_policy_set_fp8(hs_policy* policy, const float* act_max_host, void* stream) {
+  if (!policy || !policy->packed || !policy->mem)
+    return fail(HS_EINVAL, "halftone_policy_set_fp8: policy not packed");
+  if (!act_max_host) return fail(HS_EINVAL, "halftone_policy_set_fp8: null act_max");
+  int ex[4];
+  for (int k = 0; k < 4; ++k) {
+    const float m = act_max_host[k];
+    if (!(m >= 0.0f) || !std::isfinite(m) || m > 1e15f)
+      return fail(HS_EINVAL, "halftone_policy_set_fp8: act_max[%d] = %g", k, (double)m);
+    int e = 0;
+    if (m > 0.0f) {
+      const double need = (double)FP8_HEADROOM * m / 448.0;
+      e = (int)std::ceil(std::log2(need));
+      while (std::ldexp(448.0, e - 1) >= FP8_HEADROOM * (double)m) --e;
+      while (std::ldexp(448.0, e) < FP8_HEADROOM * (double)m) ++e;
+      e = std::max(-60, std::min(60, e));
+    }
+    ex[k] = e;
+  }
+  int rc = check_device();
+  if (rc) return rc;
+  Packed pk;
+  policy_layout(policy->mem, &pk);
+  policy->fp8 = 0;
+  HS_TRY(launch_fp8_pack(pk.w, pk.frags8, ex, (hipStream_t)stream));
+  policy->fp8 = 1;
+  return HS_OK;
+}
+
+int halftone_layer_max(const float* weights, const float* contone, const uint64_t* seeds, int B,
+                       int H, int W, int noise_kind, float* layer_max, void* workspace,
+                       size_t workspace_bytes, void* stream) {
+  if (!weights || !contone || !seeds || !layer_max || !workspace)
+    return fail(HS_EINVAL, "halftone_layer_max: null pointer");
+  if (noise_kind != HS_NOISE_GAUSS && noise_kind != HS_NOISE_UNIFORM)
+    return fail(HS_EINVAL, "halftone_layer_max: noise kind %d", noise_kind);
+  if (!shape_ok(B, H, W))
+    return fail(HS_ESHAPE, "halftone_layer_max: bad shape %d x %d x %d", B, H, W);
+  if (workspace_bytes < halftone_infer_workspace_size(B, H, W, HS_FP32))
+    return fail(HS_EWORKSPACE, "halftone_layer_max: workspace too small");
+  int rc = check_device();
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  InferWs iw;
+  fp32_ws(B, H, W, &iw, nullptr, workspace);
+  const size_t n = (size_t)B * H * W * 32;
+  const size_t per_layer = (size_t)PACK32_PER_LAYER * 4;
+  HS_TRY(launch_zero_ints((int*)layer_max, 5, s));
+  HS_TRY(launch_pack32(weights, iw.pack, HS_FP32, 0, s));
+  HS_TRY(launch_conv_first(contone, seeds, weights, B, H, W, noise_kind, 0u, HS_FP32, iw.a0,
+                           nullptr, nullptr, s));
+  HS_TRY(launch_layer_max((const float*)iw.a0, n, layer_max, s));
+  void* src = iw.a0;
+  void* dst = iw.a1;
+  for (int k = 2; k <= 5; ++k) {
+    HS_TRY(launch_conv32(src, (const char*)iw.pack + (k - 2) * per_layer, weights + hs_bk(k),
+                         nullptr, dst, B, H, W, HS_FP32, 0, s));
+    HS_TRY(launch_layer_max((const float*)dst, n, layer_max + (k - 1), s));
+    std::swap(src, dst);
+  }
   return HS_OK;
 }
 
@@ -880,7 +977,8 @@ int halftone_policy_infer(const hs_policy* policy, const float* contone, const u
   policy_layout(policy->mem, &pk);
   return infer_pages(pk.w, &pk, contone, seeds, npages, shapes_host, levels, noise_kind,
                      precision, recheck_tau, recheck_tau16, recheck_tau2, out, logits_or_null,
-                     stats_or_null, workspace, workspace_bytes, stream, "halftone_policy_infer");
+                     stats_or_null, workspace, workspace_bytes, stream, "halftone_policy_infer",
+                     policy->fp8 == 1);
 }
 
 // ------------------------------------------------------- policy fwd / bwd --

@@ -18,6 +18,7 @@ typedef __attribute__((__vector_size__(2 * sizeof(unsigned short)))) unsigned sh
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8_t;
 typedef __attribute__((__vector_size__(2 * sizeof(_Float16)))) _Float16 f16x2_t;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+typedef __attribute__((__vector_size__(8 * sizeof(int)))) int i32x8_t;
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of a multiply-and-swap

@@ -145,9 +145,18 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
                               const Page* pages, const int* shapes_host, int npages, int kind,
                               float tau, const Levels& lv, uint8_t* bits, float* logits,
                               uint64_t* list, int* seg_count, int* nseg, long long* seg_cap,
-                              const void* frags, int form, int* ovf, const int* guard,
-                              int guard_nonzero, int num_cus, hipStream_t s);
-enum { FUSED_BF16 = 0, FUSED_FP16_L5 = 1, FUSED_FP16_ALL = 2 };
+                              const void* frags, const void* frags8, int form, int* ovf,
+                              const int* guard, int guard_nonzero, int num_cus, hipStream_t s);
+// FUSED_FP8: layers 2..5 in FP8 from frags8 (the FP8 block), layers 1 and 6
+// in BF16 (layer 6 from frags), *ovf set to 1 when an activation saturated
+enum { FUSED_BF16 = 0, FUSED_FP16_L5 = 1, FUSED_FP16_ALL = 2, FUSED_FP8 = 3 };
+// the FP8 block: FP8 fragments of layers 2..5 with per-output-channel
+// power-of-two scales, layer 1 in BF16, the row scales and biases for the
+// activation scales 2^act_exp[0..3] of layers 1..4
+size_t fp8_block_bytes();
+hipError_t launch_fp8_pack(const float* w, void* blk, const int* act_exp, hipStream_t s);
+// *out = max(*out, x[0, n)) for non-negative floats, n a multiple of 4
+hipError_t launch_layer_max(const float* x, size_t n, float* out, hipStream_t s);
 // recheck.hip: re-evaluation of listed pixels over their receptive field
 // (wt: layers 2..5 transposed for the FP32 stage, fp32_pack_bytes())
 hipError_t launch_recheck_fp32(const float* w, const float* contone, const uint64_t* seeds,

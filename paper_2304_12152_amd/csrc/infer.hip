@@ -103,6 +103,63 @@ HS_DEV int ring_off(int col, int g) { return (col * 4 + (g ^ ((col >> 1) & 3))) 
 
 HS_DEV int ring_channel(int g, int e) { return hs_ring_channel(g, e); }
 
+// ---- the FP8 form: layers 2..5 on the 16x16x128 FP8 (E4M3) matrix-core
+// instruction, whose K of 128 takes the three taps dx of one kernel row
+// (32 channels each; the fourth K slice meets zero weights). Layers 1..4
+// store their activations as E4M3 codes q = a / s_k with a per-layer power
+// of two s_k; the weights of layers 2..5 are codes W / sw with a power of
+// two sw per output channel, and the instruction's per-row E8M0 scale
+// applies sw * s_(k-1) / s_k, so the accumulator holds q_k (a_5 for layer
+// 5, which feeds the BF16 layer-6 taps). Layer 1 stays BF16 (weights and
+// bias divided by s_1).
+//
+// An FP8 ring row is RWID 32-byte records, a record being the column's 32
+// channels in ring order (8-byte piece q = the producing lane group); the
+// two 16-byte halves are swapped in columns with bit 3 set, so that the
+// 8-byte stores of a 32-lane half-wave (16 columns) and the 16-byte loads
+// of 8 consecutive columns fall in distinct LDS banks.
+constexpr int ROWB8 = RWID * 32;  // bytes per FP8 ring row
+constexpr int RUNB8 = 16 * 32;    // bytes per 16-column run
+HS_DEV int ring8_off(int col, int q) {
+  return col * 32 + ((((q >> 1) ^ (col >> 3)) & 1) << 4) + ((q & 1) << 3);
+}
+HS_DEV int ring8_half(int col, int h) { return col * 32 + (((h ^ (col >> 3)) & 1) << 4); }
+// the largest finite E4M3 value; the conversion gives NaN above 464
+constexpr float FP8_MAX = 448.0f;
+// the FP8 block of a packed policy (byte offsets)
+constexpr int F8_L32 = 0;                      // layers 2..5: [layer][dy][m][lane] x 32 B
+constexpr int F8_L1 = 4 * 3 * 2 * 64 * 32;     // layer 1, BF16: [m][lane] x 16 B
+constexpr int F8_SCALE = F8_L1 + 2 * 64 * 16;  // int32 [layer][lane]: byte m = row 16m + lane%16
+constexpr int F8_BIAS = F8_SCALE + 4 * 64 * 4;  // float [5][32]: b_k / s_k (s_5 = 1)
+constexpr int F8_TOTAL = F8_BIAS + 5 * 32 * 4;
+
+template <int M>  // M: the byte of the scale word that holds this m-tile's row scale
+HS_DEV f32x4_t mma8(const i32x8_t& a, const i32x8_t& b, f32x4_t c, int sc) {
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, M, sc, 0, 127);
+}
+
+// ReLU, saturation test and E4M3 conversion (round to nearest even) of one
+// finished 16-pixel run: the lane's eight channels, ring order, as 8 bytes,
+// zero where the pixel is padding. amax keeps the largest value before the
+// clamp; one above 448 means the pass saturated.
+HS_DEV uint2 relu_pack8(const f32x4_t (&acc)[2], bool in, float& amax) {
+  float v[8];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[4 * m + i] = acc[m][i];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) amax = fmaxf(amax, fmaxf(v[2 * j], v[2 * j + 1]));
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = __builtin_amdgcn_fmed3f(v[j], 0.0f, FP8_MAX);
+  uint32_t lo = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+  lo = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], (int)lo, true);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], 0, false);
+  hi = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], (int)hi, true);
+  const uint32_t keep = 0u - (uint32_t)in;
+  return make_uint2(lo & keep, hi & keep);
+}
+
 // Activation bound below which FP16 carries a layer safely: the FP16 pass
 // rounds weights and activations (relative 2^-11 each, at most ten roundings
 // up to layer 5) and accumulates in FP32, all within 1% of the bound; 65504
@@ -201,6 +258,99 @@ __global__ void prologue_kernel(const hs::PackPrologue pro) {
     for (int b = gid; b < pro.B; b += gridDim.x * blockDim.x) pro.pages[b] = uniform_page(b, pro.H, pro.W);
 }
 
+// Exponents (base 2) of the FP8 form's activation scales s_1..s_4.
+struct Fp8Exp {
+  int e[4];
+};
+
+// the smallest e in [-60, 60] with mx <= 448 * 2^e (0 for mx = 0)
+HS_DEV int fp8_exp(float mx) {
+  if (!(mx > 0.0f)) return 0;
+  int e = 0;
+  frexpf(mx / FP8_MAX, &e);
+  while (e > -60 && ldexpf(FP8_MAX, e - 1) >= mx) --e;
+  while (e < 60 && ldexpf(FP8_MAX, e) < mx) ++e;
+  return e;
+}
+
+// The FP8 block from the FP32 weights, one workgroup of 256 threads: each
+// output channel of layers 2..5 gets the power-of-two weight scale that
+// brings its largest |w| to at most 448, and each row's E8M0 scale combines
+// it with the activation scales around the layer.
+__global__ __launch_bounds__(256) void pack_fp8_kernel(const float* __restrict__ w,
+                                                       uint8_t* __restrict__ blk, Fp8Exp ex) {
+  __shared__ int ew[4][32];  // [layer 2..5][output channel]
+  const int t = threadIdx.x;
+  if (t < 128) {
+    const int L = t >> 5, co = t & 31;
+    const float* wk = w + hs_wk(L + 2) + co * 32 * 9;
+    float mx = 0.0f;
+    for (int i = 0; i < 32 * 9; ++i) mx = fmaxf(mx, fabsf(wk[i]));
+    ew[L][co] = fp8_exp(mx);
+  }
+  __syncthreads();
+  auto es = [&](int k) { return k >= 5 ? 0 : ex.e[k - 1]; };  // exponent of s_k
+  // layers 2..5, one 32-bit word (4 codes) per thread and iteration: word
+  // i & 7 of the 32-byte slice of lane (i >> 3) & 63 of fragment i >> 9 =
+  // ((layer * 3 + dy) * 2 + m); lane (g, r): row 16m + r, tap dx = g
+  for (int i = t; i < F8_L1 / 4; i += 256) {
+    const int lane = (i >> 3) & 63, f = i >> 9;
+    const int m = f & 1, dy = (f >> 1) % 3, L = (f >> 1) / 3;
+    const int g = lane >> 4, co = 16 * m + (lane & 15);
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (g < 3) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = 4 * (i & 7) + b;  // byte of the slice = ring position
+        const int ci = ring_channel(j >> 3, j & 7);
+        v[b] = ldexpf(w[hs_wk(L + 2) + (co * 32 + ci) * 9 + dy * 3 + g], -ew[L][co]);
+      }
+    }
+    uint32_t u = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+    u = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], (int)u, true);
+    ((uint32_t*)(blk + F8_L32))[i] = u;
+  }
+  // layer 1 in BF16 as in the 16-bit fragments, divided by s_1
+  __bf16* l1 = (__bf16*)(blk + F8_L1);
+  for (int i = t; i < 128 * 8; i += 256) {
+    const int f = i >> 3, e = i & 7, m = f >> 6, l = f & 63, g = l >> 4;
+    const int co = 16 * m + (l & 15);
+    float v = 0.0f;
+    if (g < 3 && e < 6) v = ldexpf(w[HS_W1 + (co * 2 + (e & 1)) * 9 + g * 3 + (e >> 1)], -es(1));
+    l1[i] = (__bf16)v;
+  }
+  {  // scale words: thread t = layer * 64 + lane
+    const int L = t >> 6, r = t & 15, k = L + 2;
+    uint32_t word = 0x7F7F0000u;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int e = min(max(127 + ew[L][16 * m + r] + es(k - 1) - es(k), 1), 254);
+      word |= (uint32_t)e << (8 * m);
+    }
+    ((uint32_t*)(blk + F8_SCALE))[t] = word;
+  }
+  float* bias = (float*)(blk + F8_BIAS);
+  for (int i = t; i < 5 * 32; i += 256) {
+    const int k = 1 + i / 32, c = i & 31;
+    bias[i] = ldexpf(w[(k == 1 ? HS_B1 : hs_bk(k)) + c], -es(k));
+  }
+}
+
+// *out = max(*out, x[0, n)) for non-negative x, n a multiple of 4 (*out
+// zeroed before): such floats order like their bit patterns as unsigned
+// integers. One atomic per wave.
+__global__ void layer_max_kernel(const float4* __restrict__ x, size_t n4, unsigned* out) {
+  float m = 0.0f;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const float4 v = x[i];
+    m = fmaxf(m, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(out, __float_as_uint(m));
+}
+
 // The 16-bit element type of the fused pass: BF16, or FP16 (three more
 // mantissa bits at the same matrix-core rate, a range of 65504).
 template <typename E>
@@ -226,6 +376,7 @@ struct FusedArgs {
   const float* contone;
   const uint64_t* seeds;
   const void* frags;  // 16-bit fragments of the element type
+  const uint8_t* frags8;  // the FP8 form's block (FP8 form only)
   const float* w;
   const hs::Page* pages;
   int npages, kind;
@@ -237,7 +388,8 @@ struct FusedArgs {
   uint64_t* list;     // per output wave a segment of seg_cap entries
   int* seg_count;     // entries written per segment
   long long seg_cap;
-  int* ovf;           // FP16: set to 1 when an activation left the FP16 range
+  int* ovf;           // FP16: set to 1 when an activation left the FP16 range;
+                      // FP8: when one saturated
   const int* guard;   // when set: run only if (*guard != 0) == guard_nonzero
   int guard_nonzero;
 };
@@ -304,9 +456,11 @@ HS_DEV typename Elem<E>::v8 relu_pack(const f32x4_t (&acc)[2], bool in, u16x2_t&
 // (multitoning), and the recheck band is around the nearest threshold;
 // otherwise the bit [x >= 0] with the band around 0.
 // E: the 16-bit element type of activations and weights (BF16 or FP16);
-// CHK: the overflow tests (CHECK_NONE for BF16).
-template <int NW, bool MULTI, typename E, int CHK>
+// CHK: the overflow tests (CHECK_NONE for BF16). F8: the FP8 form (E is
+// then BF16, the type of layer 1 and of the layer-6 taps).
+template <int NW, bool MULTI, typename E, int CHK, bool F8 = false>
 __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a) {
+  static_assert(!F8 || (CHK == CHECK_NONE && sizeof(E) == 2), "the FP8 form runs BF16 layers 1, 6");
   using V8 = typename Elem<E>::v8;
   using V2 = typename Elem<E>::v2;
   constexpr int RPW = 8 / NW, NT = 64 * 4 * NW, HPW = 2 / NW;  // runs, threads, 64-px halves per wave
@@ -335,14 +489,32 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
   // tap matrix) are read from LDS where they are used
   const V8* frags = (const V8*)a.frags;
   V8 wA[3][3][2];
+  i32x8_t w8[3][2];  // FP8 form: [dy][m], K = the taps dx of kernel row dy
+  int sc8 = 0;       // FP8 form: E8M0 row scales of the owned layer, byte m
+  if constexpr (F8) {
+    const i32x8_t* f8 = (const i32x8_t*)(a.frags8 + F8_L32);
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
+    for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
-      wA[t / 3][t % 3][m] = frags[FRAG_L32 + (((k - 2) * 9 + t) * 2 + m) * 64 + lane];
-  for (int i = tid; i < 3 * 64; i += NT)
-    cfrag[i] = frags[i < 128 ? FRAG_L1 + i : FRAG_T + (i - 128)];
-  for (int i = tid; i < 5 * 32; i += NT) cbias[i] = a.w[i < 32 ? HS_B1 + i : hs_bk(2 + (i - 32) / 32) + (i & 31)];
+      for (int m = 0; m < 2; ++m) w8[dy][m] = f8[(((k - 2) * 3 + dy) * 2 + m) * 64 + lane];
+    sc8 = ((const int*)(a.frags8 + F8_SCALE))[(k - 2) * 64 + lane];
+    const V8* l1 = (const V8*)(a.frags8 + F8_L1);
+    const float* b8 = (const float*)(a.frags8 + F8_BIAS);
+    for (int i = tid; i < 3 * 64; i += NT) cfrag[i] = i < 128 ? l1[i] : frags[FRAG_T + (i - 128)];
+    for (int i = tid; i < 5 * 32; i += NT) cbias[i] = b8[i];
+  } else {
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+        wA[t / 3][t % 3][m] = frags[FRAG_L32 + (((k - 2) * 9 + t) * 2 + m) * 64 + lane];
+    for (int i = tid; i < 3 * 64; i += NT)
+      cfrag[i] = frags[i < 128 ? FRAG_L1 + i : FRAG_T + (i - 128)];
+    for (int i = tid; i < 5 * 32; i += NT)
+      cbias[i] = a.w[i < 32 ? HS_B1 + i : hs_bk(2 + (i - 32) / 32) + (i & 31)];
+  }
+  uint8_t* const ring8 = (uint8_t*)ring;  // the FP8 form's rings (ROWB8 bytes a row)
+  float amax8 = 0.0f;                     // FP8: the largest value before a clamp
   const float b6 = a.w[HS_B6];
   // this lane's element offset in a ring row: chunk g, first column of its
   // runs (tap dx and run n are added as immediates)
@@ -476,12 +648,22 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
       if (k < 5) {
         const int rs = A + t + 1 - 3 * k;
         const bool row_in = rs >= 0 && rs < H;
-        E* dst = ring + ((size_t)(k - 1) * 2 + cur) * ROWE + woff;
+        if constexpr (F8) {
+          uint8_t* dst8 = ring8 + ((k - 1) * 2 + cur) * ROWB8 + ring8_off(col0 + lr + 1, lg);
 #pragma unroll
-        for (int n = 0; n < RPW; ++n) {
-          const int x = X + col0 + 16 * n + lr;
-          const bool in = row_in && (cols_inside || (x >= 0 && x < W));
-          *(V8*)(dst + n * RUNE) = relu_pack<E, CHK == CHECK_ALL>(S[J][n], in, ovf);
+          for (int n = 0; n < RPW; ++n) {
+            const int x = X + col0 + 16 * n + lr;
+            const bool in = row_in && (cols_inside || (x >= 0 && x < W));
+            *(uint2*)(dst8 + n * RUNB8) = relu_pack8(S[J][n], in, amax8);
+          }
+        } else {
+          E* dst = ring + ((size_t)(k - 1) * 2 + cur) * ROWE + woff;
+#pragma unroll
+          for (int n = 0; n < RPW; ++n) {
+            const int x = X + col0 + 16 * n + lr;
+            const bool in = row_in && (cols_inside || (x >= 0 && x < W));
+            *(V8*)(dst + n * RUNE) = relu_pack<E, CHK == CHECK_ALL>(S[J][n], in, ovf);
+          }
         }
       } else {  // layer 5: the nine layer-6 taps of row rs into the T ring
         const int rs = A + t - 14;
@@ -507,6 +689,29 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
         }
       }
       // ---- one input row q (written by layer k-1 in the previous step)
+      if constexpr (F8) {
+        // lane group g reads the record of tap dx = g (group 3 meets zero
+        // weights and reads tap 2's); half 1 of a record sits 16 bytes after
+        // or before half 0
+        const uint8_t* src8 = ring8 + ((k - 2) * 2 + prev) * ROWB8;
+        const int cr = col0 + lr + (lg < 3 ? lg : 2);
+        const uint8_t* p0 = src8 + ring8_half(cr, 0);
+        const uint8_t* p1 = src8 + ring8_half(cr, 1);
+#pragma unroll
+        for (int n = 0; n < RPW; ++n) {
+          const uint4 h0 = *(const uint4*)(p0 + n * RUNB8);
+          const uint4 h1 = *(const uint4*)(p1 + n * RUNB8);
+          i32x8_t bf;
+          __builtin_memcpy(&bf, &h0, 16);
+          __builtin_memcpy((char*)&bf + 16, &h1, 16);
+          S[J][n][0] = mma8<0>(w8[0][0], bf, S[J][n][0], sc8);
+          S[M1][n][0] = mma8<0>(w8[1][0], bf, S[M1][n][0], sc8);
+          S[M2][n][0] = mma8<0>(w8[2][0], bf, S[M2][n][0], sc8);
+          S[J][n][1] = mma8<1>(w8[0][1], bf, S[J][n][1], sc8);
+          S[M1][n][1] = mma8<1>(w8[1][1], bf, S[M1][n][1], sc8);
+          S[M2][n][1] = mma8<1>(w8[2][1], bf, S[M2][n][1], sc8);
+        }
+      } else {
       const E* src = ring + ((size_t)(k - 2) * 2 + prev) * ROWE;
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
@@ -521,6 +726,7 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
             S[M2][n][m] = Elem<E>::mma(wA[2][dx][m], bf, S[M2][n][m]);
           }
         }
+      }
       }
       // ---- layer 1 (waves 0..NW-1), after their MFMAs: the wave sharing the
       // SIMD runs the output stage before its own, so the two stages overlap
@@ -553,7 +759,21 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
         // the same loop, spelled inline for the multitone forms and as a lambda
         // for the binary ones: with these spellings neither form's step loop
         // spills registers (each spelling spills in the other form)
-        if constexpr (MULTI) {
+        if constexpr (F8) {
+          uint8_t* dst8 = ring8 + cur * ROWB8 + ring8_off(col0 + lr + 1, lg);
+#pragma unroll
+          for (int n = 0; n < RPW; ++n) {
+            const int c0 = col0 + 16 * n + lr;  // column of tap dx = 0
+            const uint4 u = rec[16 * n];
+            V8 bf;
+            __builtin_memcpy(&bf, &u, 16);
+            f32x4_t l1[2];
+            l1[0] = Elem<E>::mma(w10, bf, b10);
+            l1[1] = Elem<E>::mma(w11, bf, b11);
+            const int x = X + c0;
+            *(uint2*)(dst8 + n * RUNB8) = relu_pack8(l1, row_in && x >= 0 && x < W, amax8);
+          }
+        } else if constexpr (MULTI) {
 #pragma unroll
           for (int n = 0; n < RPW; ++n) {
             const int c0 = col0 + 16 * n + lr;  // column of tap dx = 0
@@ -619,6 +839,9 @@ __global__ __launch_bounds__(64 * 4 * NW, 1) void fused_infer_kernel(FusedArgs a
     const bool bad = ovf[0] >= 0x7C00 || ovf[1] >= 0x7C00;
     if (__ballot(bad) && lane == 0 && a.ovf) *a.ovf = 1;
   }
+  if constexpr (F8) {
+    if (__ballot(amax8 > FP8_MAX) && lane == 0 && a.ovf) *a.ovf = 1;
+  }
   // recheck list: the output stage's 64-pixel halves each own a segment
   if (role == 2 && lane == 0 && a.seg_count) {
 #pragma unroll
@@ -648,6 +871,23 @@ __global__ void uniform_pages_kernel(hs::Page* pages, int B, int H, int W) {
 namespace hs {
 
 size_t fused_frag_bytes() { return (size_t)FRAG_TOTAL * 16; }
+size_t fp8_block_bytes() { return (size_t)F8_TOTAL; }
+
+hipError_t launch_fp8_pack(const float* w, void* blk, const int* act_exp, hipStream_t s) {
+  Fp8Exp ex;
+  for (int k = 0; k < 4; ++k) ex.e[k] = act_exp[k];
+  pack_fp8_kernel<<<1, 256, 0, s>>>(w, (uint8_t*)blk, ex);
+  return hipGetLastError();
+}
+
+hipError_t launch_layer_max(const float* x, size_t n, float* out, hipStream_t s) {
+  const size_t n4 = n / 4;
+  size_t blocks = (n4 + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  layer_max_kernel<<<(unsigned)blocks, 256, 0, s>>>((const float4*)x, n4, (unsigned*)out);
+  return hipGetLastError();
+}
 
 hipError_t launch_fused_pack(const float* w, void* frags, void* frags16, int* needs_all,
                              const PackPrologue& pro, hipStream_t s) {
@@ -714,12 +954,13 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
                               const Page* pages, const int* shapes_host, int npages, int kind,
                               float tau, const Levels& lv, uint8_t* bits, float* logits,
                               uint64_t* list, int* seg_count, int* nseg, long long* seg_cap,
-                              const void* frags, int form, int* ovf, const int* guard,
-                              int guard_nonzero, int num_cus, hipStream_t s) {
+                              const void* frags, const void* frags8, int form, int* ovf,
+                              const int* guard, int guard_nonzero, int num_cus, hipStream_t s) {
   FusedArgs a;
   a.contone = contone;
   a.seeds = seeds;
   a.frags = frags;
+  a.frags8 = (const uint8_t*)frags8;
   a.ovf = ovf;
   a.guard = guard;
   a.guard_nonzero = guard_nonzero;
@@ -742,7 +983,10 @@ hipError_t launch_fused_infer(const float* w, const float* contone, const uint64
   const bool binary = lv.n == 1 && lv.thr[0] == 0.0f;
   const dim3 block(64 * 4 * FUSED_NW);
   constexpr int N = FUSED_NW;
-  if (form == FUSED_FP16_L5) {
+  if (form == FUSED_FP8) {
+    if (binary) fused_infer_kernel<N, false, __bf16, CHECK_NONE, true><<<grid, block, 0, s>>>(a);
+    else fused_infer_kernel<N, true, __bf16, CHECK_NONE, true><<<grid, block, 0, s>>>(a);
+  } else if (form == FUSED_FP16_L5) {
     if (binary) fused_infer_kernel<N, false, _Float16, CHECK_L5><<<grid, block, 0, s>>>(a);
     else fused_infer_kernel<N, true, _Float16, CHECK_L5><<<grid, block, 0, s>>>(a);
   } else if (form == FUSED_FP16_ALL) {

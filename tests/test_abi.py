@@ -332,3 +332,44 @@ def test_finite_check_flag_is_validated(lib):
     assert lib.halftone_loss(p, p, 1, 16, 16, None, 0, 0, 0, ctypes.byref(prm), p, p, lws,
                              None) == hb.HS_EINVAL
     assert hb.default_loss_params().flags == 0
+
+
+def test_fp8_argument_errors(lib):
+    """HS_FP8: refused without a packed policy's FP8 copy; set_fp8 and
+    layer_max reject bad arguments before any device work."""
+    p = _fake()
+    n = lib.halftone_policy_bytes()
+    ws = lib.halftone_infer_workspace_size(1, 8, 8, hb.HS_FP8)
+    assert ws == lib.halftone_infer_workspace_size(1, 8, 8, hb.HS_BF16)
+    args = [p, p, p, 1, 8, 8, 0, hb.HS_FP8, 0.5, p, None, None, p, ws, None]
+    assert lib.halftone_infer(*args) == hb.HS_EUNSUPPORTED
+    assert b"halftone_policy_set_fp8" in lib.halftone_last_error()
+    pol = hb.HsPolicy()
+    amax = np.ones(4, dtype=np.float32)
+    ap = amax.ctypes.data_as(ctypes.c_void_p)
+    assert lib.halftone_policy_set_fp8(None, ap, None) == hb.HS_EINVAL
+    assert lib.halftone_policy_set_fp8(ctypes.byref(pol), ap, None) == hb.HS_EINVAL  # not packed
+    pol.packed, pol.mem, pol.bytes = 1, 4096, n
+    assert lib.halftone_policy_set_fp8(ctypes.byref(pol), None, None) == hb.HS_EINVAL
+    for bad in (-1.0, float("inf"), float("nan")):
+        a = amax.copy(); a[2] = bad
+        assert lib.halftone_policy_set_fp8(ctypes.byref(pol), a.ctypes.data_as(ctypes.c_void_p),
+                                           None) == hb.HS_EINVAL
+    assert pol.fp8 == 0
+    sh = hb.page_shapes_array([(8, 8)])
+    shp = sh.ctypes.data_as(ctypes.c_void_p)
+    pws = lib.halftone_infer_pages_workspace_size(1, shp, hb.HS_FP8)
+    pargs = [ctypes.byref(pol), p, p, 1, shp, 2, 0, hb.HS_FP8, 0.5, -1.0, -1.0, p, None, None, p,
+             pws, None]
+    assert lib.halftone_policy_infer(*pargs) == hb.HS_EUNSUPPORTED  # no FP8 copy
+    fws = lib.halftone_infer_workspace_size(1, 8, 8, hb.HS_FP32)
+    largs = [p, p, p, 1, 8, 8, 0, p, p, fws, None]
+    for i in (0, 1, 2, 7, 8):
+        a = list(largs); a[i] = None
+        assert lib.halftone_layer_max(*a) == hb.HS_EINVAL
+    a = list(largs); a[6] = 5
+    assert lib.halftone_layer_max(*a) == hb.HS_EINVAL
+    a = list(largs); a[4] = 0
+    assert lib.halftone_layer_max(*a) == hb.HS_ESHAPE
+    a = list(largs); a[9] = fws - 1
+    assert lib.halftone_layer_max(*a) == hb.HS_EWORKSPACE
