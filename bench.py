@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "halftone Mpixels/s (BF16 vs FP32 CNN, oracle-matched bits); train steps/s"
 FLOP_PER_PX = 75456          # 2 x (2*32*9 + 4*32*32*9 + 32*9) multiply-adds per pixel
 PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak (published)
+PEAK_FP8_TFLOPS = 5000.0     # MI355X dense FP8 matrix peak (published)
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (published)
 KERNEL_SRC = os.path.join(ROOT, "paper_2304_12152_amd", "csrc", "infer.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_infer_bf16_8x1024x1024_traffic.txt")
@@ -164,7 +165,7 @@ def bench_loss(hb, synth, torch, dev, steps):
             "config": "16 x 256x256 crops, LE gradient + anisotropy gradient, FP32"}
 
 
-def bench_pages(hb, synth, torch, dev, wt, steps, tau, tau2):
+def bench_pages(hb, synth, torch, dev, wt, steps, tau, tau2, pol8=None, tau8=None):
     """The uneven batch: 48 pages (sizes from seed 3,000,000, page seeds
     3,000,000 + i), contones made on the device with the same recipe."""
     shapes = synth.page_sizes(3_000_000)
@@ -182,6 +183,10 @@ def bench_pages(hb, synth, torch, dev, wt, steps, tau, tau2):
     pol = hb.Policy(wt)
 
     def run(stats=False, levels=None, prec=hb.HS_BF16):
+        if prec == hb.HS_FP8:
+            return hb.halftone_policy_infer(pol8, flat, st, shapes, precision=prec,
+                                            recheck_tau=tau8, recheck_tau2=tau2, stats=stats,
+                                            workspace=ws, levels=levels or 2)
         return hb.halftone_policy_infer(pol, flat, st, shapes, precision=prec,
                                         recheck_tau=tau if prec == hb.HS_BF16 else None,
                                         recheck_tau2=tau2, stats=stats, workspace=ws,
@@ -218,6 +223,16 @@ def bench_pages(hb, synth, torch, dev, wt, steps, tau, tau2):
     h = line(*timed(None, hb.HS_FP16))
     h["multitone4"] = line(*timed(4, hb.HS_FP16))
     log("pages, fp16: %.1f Mpx/s; 4 levels %.1f Mpx/s" % (h["value"], h["multitone4"]["value"]))
+    f8 = None
+    if pol8 is not None:
+        # the FP8 fused pass (binary): its recheck list is about 25 times the
+        # BF16 one, so one timed call
+        f8 = line(*timed(None, hb.HS_FP8)) if steps else None
+        if f8 is not None:
+            f8["fused_frac_of_fp8_peak"] = round(FLOP_PER_PX * npx / (f8["fused_kernel_ms"] / 1e3)
+                                                 / 1e12 / PEAK_FP8_TFLOPS, 4)
+            f8["tau"] = tau8
+            log("pages, fp8: %.1f Mpx/s (fused %.3f ms)" % (f8["value"], f8["fused_kernel_ms"]))
     return {"value": round(npx / dt / 1e6, 1), "unit": "Mpx/s", "pages": len(shapes),
             "mpx": round(npx / 1e6, 2), "ms_per_call": round(dt * 1e3, 3),
             "fused_kernel_ms": round(kern_s * 1e3, 3), "fused_tflops": round(ach, 1),
@@ -232,7 +247,19 @@ def bench_pages(hb, synth, torch, dev, wt, steps, tau, tau2):
                            "rechecked": mstats[0], "split_recomputed": mstats[4],
                            "fp32_recomputed": mstats[2],
                            "recheck_fraction": round(mstats[0] / npx, 6)},
-            "fp16": h}
+            "fp16": h, "fp8": f8}
+
+
+def fp8_policy(hb, wt, dev):
+    """The packed policy with its FP8 copy, scaled for the activation maxima
+    of the FP32 forward on two 1024 x 1024 calibration contones (seeds 101
+    and 102, disjoint from the benchmark's)."""
+    import torch
+    from paper_2304_12152_amd import calibrate as cal
+    from paper_2304_12152_amd import synth
+    seeds = [101, 102]
+    c = torch.tensor(synth.contone_batch(seeds, 1024, 1024), device=dev)
+    return cal.fp8_policy(wt, c, seeds)
 
 
 def calibrate(hb, synth, torch, dev):
@@ -257,6 +284,19 @@ def calibrate(hb, synth, torch, dev):
     res["fp16_rms_err"] = float(eh.pow(2).mean().sqrt())
     for tau in (0.004, 0.005, 0.006, 0.0075, 0.01):
         res["fp16_frac_below_%.4f" % tau] = float((lh.abs() < tau).float().mean())
+    # the FP8 pass with the bench's activation scales (fp8_policy on seeds
+    # 101 and 102), its error on all eight calibration images
+    pol8 = fp8_policy(hb, wt, dev)
+    _, l8, s8 = hb.halftone_policy_infer(pol8, c, st, precision=hb.HS_FP8, recheck_tau=0.0,
+                                         logits=True, stats=True)
+    e8 = (l8 - l32).abs()
+    res["fp8_act_max"] = pol8.act_max.tolist()
+    res["fp8_saturated"] = int(s8[3])
+    res["fp8_max_err"] = float(e8.max())
+    res["fp8_rms_err"] = float(e8.pow(2).mean().sqrt())
+    for tau in (0.4, 0.5, 0.6, 0.7, 0.8):
+        res["fp8_frac_below_%.2f" % tau] = float((l8.abs() < tau).float().mean())
+    del l8, e8
     # the FP16 cone stage and the split stage, each deciding every pixel of a
     # 2 x 512 x 512 batch (a packed policy with explicit bands)
     c2 = c[:2, :512, :512].contiguous()
@@ -294,6 +334,11 @@ def main():
     # at most 2e-4, so the split stage decides every listed pixel (those it
     # leaves near zero are inside the 4e-4 margin) and no FP32 stage runs
     ap.add_argument("--tau2", type=float, default=1.5e-4)
+    # the FP8 pass's band: 1.5 x its largest logit error (0.524) measured by
+    # --calibrate on the calibration images (seeds 101..108), with the
+    # activation scales of fp8_policy
+    ap.add_argument("--tau8", type=float, default=0.79)
+    ap.add_argument("--no-fp8", action="store_true")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -449,6 +494,45 @@ def main():
                      "overflow_rerun": st16[3],
                      "fraction": round(st16[0] / npx, 6)}
     log("fp16: %.3f ms/step, %.1f Mpx/s" % (dt16 * 1e3 / args.steps, v16))
+    pol8 = None
+    if not args.no_fp8:
+        # the FP8 fused pass (layers 2..5 on the FP8 matrix cores), scaled on
+        # calibration images, with the same split stage behind it
+        pol8 = fp8_policy(hb, wt, dev)
+
+        def step8():
+            return hb.halftone_policy_infer(pol8, ct, st, precision=hb.HS_FP8,
+                                            recheck_tau=args.tau8, recheck_tau2=args.tau2,
+                                            workspace=ws)
+
+        n8 = max(5, args.steps // 5)
+        for _ in range(n8):
+            step8()
+        torch.cuda.synchronize()
+        hb.halftone_profile_start()
+        t0 = time.perf_counter()
+        for _ in range(n8):
+            step8()
+        torch.cuda.synchronize()
+        dt8 = (time.perf_counter() - t0) / n8
+        kern8_ms, launches8 = hb.halftone_profile_stop()
+        k8 = kern8_ms / 1e3 / max(launches8, 1)
+        bits_8, st8 = hb.halftone_policy_infer(pol8, ct, st, precision=hb.HS_FP8,
+                                               recheck_tau=args.tau8, recheck_tau2=args.tau2,
+                                               stats=True, workspace=ws)
+        st8 = st8.cpu().tolist()
+        a8 = FLOP_PER_PX * npx / k8 / 1e12
+        extra["fp8"] = {"value": round(npx / dt8 / 1e6, 1), "unit": "Mpx/s",
+                        "ms_per_step": round(dt8 * 1e3, 4), "steps": n8,
+                        "fused_kernel_ms": round(k8 * 1e3, 4), "fused_tflops": round(a8, 1),
+                        "fused_frac_of_fp8_peak": round(a8 / PEAK_FP8_TFLOPS, 4),
+                        "fused_vs_bf16_fused": round(avg_kernel_s / k8, 3),
+                        "tau": args.tau8, "act_max": [round(float(x), 4) for x in pol8.act_max],
+                        "rechecked": st8[0], "flipped": st8[1], "split_recomputed": st8[4],
+                        "fp32_recomputed": st8[2], "saturated_rerun": st8[3],
+                        "fraction": round(st8[0] / npx, 6)}
+        log("fp8: %.3f ms/step, %.1f Mpx/s, fused %.3f ms, %d listed"
+            % (dt8 * 1e3, npx / dt8 / 1e6, k8 * 1e3, st8[0]))
     if not args.no_fp32:
         ws32 = torch.empty(hb.lib().halftone_infer_workspace_size(B, H, W, hb.HS_FP32),
                            dtype=torch.uint8, device=dev)
@@ -464,6 +548,13 @@ def main():
         off = l32.abs() > 4.1e-4
         mism = int(((bits16 != b32) & off).sum().item())
         extra["fp16"]["bits_differing_off_margin"] = int(((bits_h != b32) & off).sum().item())
+        if pol8 is not None:
+            extra["fp8"]["bits_differing_off_margin"] = int(((bits_8 != b32) & off).sum().item())
+            _, l8 = hb.halftone_policy_infer(pol8, ct, st, precision=hb.HS_FP8, recheck_tau=0.0,
+                                             logits=True, workspace=ws)
+            extra["fp8"]["max_logit_error"] = round(float((l8 - l32).abs().max()), 4)
+            extra["fp8"]["rms_logit_error"] = round(float((l8 - l32).pow(2).mean().sqrt()), 5)
+            del l8
         extra["fp32"] = {"value": round(v32, 1), "unit": "Mpx/s",
                          "speedup_bf16_vs_fp32": round(value / v32, 2),
                          "bits_differing_off_margin": mism}
@@ -515,7 +606,7 @@ def main():
         extra["loss"] = bench_loss(hb, synth, torch, dev, 20)
     if not args.no_pages:
         extra["pages"] = bench_pages(hb, synth, torch, dev, wt, args.page_steps, args.tau,
-                                     args.tau2)
+                                     args.tau2, pol8, args.tau8)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpx/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
