@@ -430,6 +430,12 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
                 "traffic": traffic, "kernel": "fused_infer_kernel (BF16, 8x1024x1024)",
                 "kernel_ms": round(avg_kernel_s * 1e3, 4)}
+    # the whole path (fused pass and recheck stages) against the same
+    # roofline: the batch's 75,456 FLOP per pixel at the BF16 peak
+    whole = FLOP_PER_PX * npx / (ms_per_step / 1e3) / 1e12
+    extra_whole = {"tflops": round(whole, 1), "frac": round(whole / PEAK_BF16_TFLOPS, 4),
+                   "roofline_mpx_s": round(PEAK_BF16_TFLOPS * 1e12 / FLOP_PER_PX / 1e6, 1),
+                   "outside_fused_kernel_ms": round(ms_per_step - avg_kernel_s * 1e3, 4)}
 
     # the same calls packing the weights in every call (halftone_infer)
     def step_repack():
@@ -456,6 +462,7 @@ def main():
                          "fp16_cone_decided": stats[0] - stats[4],
                          "split_recomputed": stats[4], "fp32_recomputed": stats[2],
                          "fraction": round(stats[0] / npx, 6)},
+             "whole_path_roofline": extra_whole,
              "repack_each_call": {"value": round(v_repack, 1), "unit": "Mpx/s",
                                   "call": "halftone_infer (weights packed inside every call, "
                                           "default split band tau / 64, so with the FP32 "

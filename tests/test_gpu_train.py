@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 import torch
 
+import bf16_emulation
 from gpu_common import device, oracle_threads, seeds_t, to_dev
 from paper_2304_12152_amd import autograd as hag
 from paper_2304_12152_amd import binding as hb
@@ -55,14 +56,21 @@ def test_policy_backward_bf16(orc):
     ref, _ = orc.policy_backward(w.astype(np.float64), c.astype(np.float64), z,
                                  gprob * p * (1 - p))
     # BF16 rounding of the forward activations and weights alone moves this
-    # gradient to cosine 0.9967 (layer-1 normwise error 0.115) in a CPU
-    # emulation of the same rounding points; gradient rounding adds ~3e-6.
-    # Bound: cosine > 0.99 overall and < 0.3 normwise error per layer.
+    # gradient to cosine 0.9977 (layer-1 normwise error 0.11) against the
+    # exact one: the CPU emulation of the same rounding points
+    # (bf16_emulation, pinned to the oracle in test_bf16_bound.py). So the
+    # GPU gradient is held to the emulated one, tightly, and to the exact
+    # one as loosely as the rounding requires.
     g = gw.cpu().numpy()
-    assert _cos(g, ref) > 0.99
-    for lo, hi in [(0, 608), (608, 9856), (9856, 19104), (19104, 28352), (28352, 37600),
-                   (37600, 37889)]:
-        assert _rel(g[lo:hi], ref[lo:hi]) < 0.3
+    em, _ = bf16_emulation.weight_gradient(w, c, z, gprob, bf16=True)
+    cos_g, cos_em = _cos(g, ref), _cos(em, ref)
+    per = [_rel(g[lo:hi], em[lo:hi]) for lo, hi in bf16_emulation.layer_slices()]
+    print("BF16 backward: cosine to exact %.5f (emulated %.5f), to emulated %.6f, per layer %s"
+          % (cos_g, cos_em, _cos(g, em), np.round(per, 4)), flush=True)
+    assert abs(cos_g - cos_em) < 2e-3 and cos_g > 0.99
+    # measured: cosine 0.99999 to the emulation, 0.3-0.6% per layer
+    assert _cos(g, em) > 0.9999
+    assert max(per) < 0.02
     # every tap of the four 32 -> 32 weight gradients on its own (a tap taken
     # from the wrong column or row would be off by O(1))
     for k in range(4):
@@ -72,6 +80,9 @@ def test_policy_backward_bf16(orc):
         errs = [_rel(gw_k[:, :, t], rw_k[:, :, t]) for t in range(9)]
         print("layer", k + 2, "per-tap relative error", np.round(errs, 4), flush=True)
         assert max(errs) < 0.3, (k, errs)
+        emk = em[lo:lo + 9216].reshape(32, 32, 9)
+        errs_em = [_rel(gw_k[:, :, t], emk[:, :, t]) for t in range(9)]
+        assert max(errs_em) < 0.05, (k, errs_em)
 
 
 def test_autograd_wrappers(orc):
