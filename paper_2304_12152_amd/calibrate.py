@@ -45,12 +45,13 @@ CONE_MARGIN = 2.0     # the cone stages' bands over their largest measured error
 TAU2_FLOOR = 1.5e-4   # the split stage's band is never below this (the library's floor)
 
 # Costs per pixel measured on one MI355X for 8 x 1024 x 1024 (ns): the fused
-# 16-bit pass (BF16 0.57 ms, FP16 0.59 ms per batch), one listed pixel in the
-# FP16 cone stage and in the split stage, and the FP32 per-layer path.
-COST_FUSED_NS = {hb.HS_BF16: 0.068, hb.HS_FP16: 0.070}
+# 16-bit pass (BF16 0.565 ms, FP16 0.570 ms per batch), one listed pixel in
+# the FP16 cone stage and in the split stage (0.332 ms for 25,094), and the
+# FP32 per-layer path (1,389 Mpx/s).
+COST_FUSED_NS = {hb.HS_BF16: 0.067, hb.HS_FP16: 0.068}
 COST_CONE16_NS = 6.0
-COST_SPLIT_NS = 15.3
-COST_FP32_NS = 0.722
+COST_SPLIT_NS = 13.2
+COST_FP32_NS = 0.720
 
 
 def _batch(weights, contone, seeds, who):
