@@ -218,6 +218,8 @@ hipError_t recompute_act(const float* w, const FwdInput& in, int j, int B, int H
   return hipSuccess;
 }
 
+int num_cus();  // compute units of the current device (below)
+
 // Backward of the stack given dL/dprobs (probs != null) or dL/dlogit
 // (probs == null); accumulates into the weight-gradient partial rows.
 // With pw.recompute, `in` must be the forward's input (act(4) is still in
@@ -239,12 +241,19 @@ hipError_t run_backward(const float* w, const float* grad, const float* probs, i
   for (int k = 5; k >= 2; --k) {
     if (pw.recompute && (e = recompute_act(w, *in, k - 2, B, H, W, prec, pw, s)) != hipSuccess)
       return e;
-    if ((e = launch_wgrad32(pw.act(k - 2), g, k, B, H, W, prec, pw.partials, accumulate, s)) !=
-        hipSuccess)
-      return e;
-    if ((e = launch_conv32(g, (const char*)pw.packT + (k - 2) * per_layer, nullptr,
-                           pw.act(k - 2), other, B, H, W, prec, 1, s)) != hipSuccess)
-      return e;
+    if (prec == HS_BF16) {
+      // input and weight gradients in one pass over g and a
+      if ((e = launch_bwd32(pw.act(k - 2), g, (const char*)pw.packT + (k - 2) * per_layer, other,
+                            k, B, H, W, pw.partials, accumulate, num_cus(), s)) != hipSuccess)
+        return e;
+    } else {
+      if ((e = launch_wgrad32(pw.act(k - 2), g, k, B, H, W, prec, pw.partials, accumulate, s)) !=
+          hipSuccess)
+        return e;
+      if ((e = launch_conv32(g, (const char*)pw.packT + (k - 2) * per_layer, nullptr,
+                             pw.act(k - 2), other, B, H, W, prec, 1, s)) != hipSuccess)
+        return e;
+    }
     void* t = g;
     g = other;
     other = t;

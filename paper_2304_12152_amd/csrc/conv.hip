@@ -451,33 +451,6 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(const T* __restrict__ a_in
   }
 }
 
-// ---------------------------------------------------------------------------
-// Weight gradient of a 32->32 layer on the BF16 matrix cores (FP32
-// accumulation). K is the pixel dimension: a lane's 8 K-values are 8
-// consecutive pixels of one row. The output gradient is staged transposed,
-// gT[co][px]; the input tile once, transposed, aS[ci][row][col] =
-// a[y0-1+row][x0-1+col][ci] for col = 0..67. The K-slice of tap dx starts
-// dx columns into an aligned 8-column group, so it is built from two
-// aligned 16-byte LDS reads: the first one (dx = 0), a 2-byte funnel shift
-// across the pair (dx = 1) or dwords 1..4 of the pair (dx = 2). Tile =
-// 2 x 64 pixels; wave w owns the (co tile, ci tile) = (w >> 1, w & 1) block
-// of all nine taps; the bias gradient is one more MFMA against a ones
-// operand.
-// Staging: "a" operations (4 consecutive columns x 8 channels of one row)
-// number (WB_H + 2) x 17 x 4 = 272, "g" operations WB_H x 16 x 4 = 128;
-// thread i owns operations i and i + 256 of the 400. All of a tile's global
-// loads are issued together into registers, and the next tile's loads are
-// in flight while the current tile's MFMAs run.
-// ---------------------------------------------------------------------------
-constexpr int WB_H = 2, WB_W = 64, WB_PX = WB_H * WB_W;
-constexpr int WB_GS = WB_PX + 8;                // gT channel stride (17 x 16 B: odd)
-constexpr int WB_AC = WB_W + 4;                 // staged input columns (68)
-constexpr int WB_RS = WB_W + 8;                 // aS row stride (72)
-constexpr int WB_CS = (WB_H + 2) * WB_RS + 8;   // aS channel stride (37 x 16 B: odd)
-constexpr int WB_AOPS = (WB_H + 2) * (WB_AC / 4) * 4;  // 272
-constexpr int WB_GOPS = WB_H * (WB_W / 4) * 4;          // 128
-static_assert(WB_AOPS + WB_GOPS <= 512 && WB_AOPS >= 256, "wgrad staging split");
-
 // 8 consecutive bf16 starting `dx` elements into the 16 loaded ones
 HS_DEV bf16x8_t shift_frag(const bf16x8_t lo, const bf16x8_t hi, int dx) {
   uint32_t d[8], o[4];
@@ -497,56 +470,125 @@ HS_DEV bf16x8_t shift_frag(const bf16x8_t lo, const bf16x8_t hi, int dx) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void wgrad32_bf16_kernel(const __bf16* __restrict__ a_in,
-                                                           const __bf16* __restrict__ g_out,
-                                                           int B, int H, int W, int layer,
-                                                           float* __restrict__ partials,
-                                                           int accumulate) {
-  __shared__ __attribute__((aligned(16))) __bf16 gT[32 * WB_GS];
-  __shared__ __attribute__((aligned(16))) __bf16 aS[32 * WB_CS];
-  const int tiles_x = (W + WB_W - 1) / WB_W, tiles_y = (H + WB_H - 1) / WB_H;
+// ---------------------------------------------------------------------------
+// Backward of a 32->32 layer in BF16 in one pass over the pixels: the input
+// gradient (the conv of g with the transposed, flipped weights, times the
+// ReLU mask [a > 0]) and the weight and bias gradients (sums over pixels of
+// g[px][co] a[px + tap][ci] and of g[px][co]). A block of 8 waves strides
+// over 8 x 64 pixel tiles; each tile of g and of a, with its one-pixel halo,
+// is read from HBM once and staged in LDS three ways:
+//   gP[row][col][chunk]  g pixel-major with the chunk swizzle of conv32
+//                        (10 x 66 pixels): the input gradient's B operands;
+//   gT[co][px]           g's 8 x 64 interior transposed: the weight
+//                        gradient's A operands (K = 8 consecutive pixels);
+//   aT[ci][row][col]     a transposed (10 rows x 68 columns): the weight
+//                        gradient's B operands (the K-slice of tap dx cut out
+//                        of two aligned 16-byte reads) and the ReLU mask.
+// Wave w computes row w of the input gradient (both channel tiles, four
+// 16-pixel runs) and the weight-gradient block (co tile, ci tile) = ((w >>
+// 1) & 1, w & 1) over tile rows 4 (w >> 2) .. 4 (w >> 2) + 3; the two row
+// halves are added in a fixed order at the end, so each block's row of
+// partial sums is deterministic. It computes what conv32_kernel (MODE 1)
+// and wgrad32_kernel compute in FP32, reading g and a once: a separate
+// input-gradient pass and weight-gradient pass read them three times (the
+// conv's tile, its mask, and the weight gradient's own staging with a
+// halo twice its tile's height), about twice the bytes.
+// Staging operations: "g" = 4 consecutive columns x 8 channels of one row
+// of g (rows -1..8, columns 0..63), "h" = one 16-byte chunk of g's halo
+// columns -1 and 64, "a" = 4 columns x 8 channels of a (rows -1..8, columns
+// -1..66); thread i owns operations i, i + 512 and i + 1024 of the 1,400.
+// All of a tile's global loads are issued together into registers, and the
+// next tile's loads are in flight while the current tile's MFMAs run.
+// ---------------------------------------------------------------------------
+constexpr int FB_H = 8, FB_W = 64, FB_PX = FB_H * FB_W;
+constexpr int FB_LH = FB_H + 2, FB_LW = FB_W + 2;  // gP: 10 x 66 pixels
+constexpr int FB_GS = FB_PX + 8;                   // gT channel stride (65 x 16 B: odd)
+constexpr int FB_AC = FB_W + 4;                    // aT staged columns (68)
+constexpr int FB_RS = FB_W + 8;                    // aT row stride (72)
+constexpr int FB_CS = FB_LH * FB_RS + 8;           // aT channel stride (91 x 16 B: odd)
+constexpr int FB_GOPS = FB_LH * (FB_W / 4) * 4;    // 640
+constexpr int FB_HOPS = FB_LH * 2 * 4;             // 80
+constexpr int FB_AOPS = FB_LH * (FB_AC / 4) * 4;   // 680
+constexpr int FB_OPS = FB_GOPS + FB_HOPS + FB_AOPS;
+constexpr int FB_NT = 512, FB_NOP = (FB_OPS + FB_NT - 1) / FB_NT;
+static_assert(FB_NOP == 3, "bwd32 staging split");
+static_assert(4 * 64 * 40 * 4 <= FB_LH * FB_LW * 32 * 2, "bwd32 combine scratch fits in gP");
+
+__global__ __launch_bounds__(FB_NT, 1) void bwd32_bf16_kernel(
+    const __bf16* __restrict__ a_in, const __bf16* __restrict__ g_out,
+    const __bf16* __restrict__ wpT, __bf16* __restrict__ g_in, int B, int H, int W, int layer,
+    float* __restrict__ partials, int accumulate) {
+  __shared__ __attribute__((aligned(16))) __bf16 gP[FB_LH * FB_LW * 32];
+  __shared__ __attribute__((aligned(16))) __bf16 gT[32 * FB_GS];
+  __shared__ __attribute__((aligned(16))) __bf16 aT[32 * FB_CS];
+  // the input gradient's weight fragments [tap][row tile][lane], in LDS so
+  // that the tile loop issues no global load besides the next tile's
+  // prefetch (a wait on the vector memory counter for a weight load would
+  // also wait for the prefetch)
+  __shared__ bf16x8_t wS[9 * 2 * 64];
+  const int tiles_x = (W + FB_W - 1) / FB_W, tiles_y = (H + FB_H - 1) / FB_H;
   const int ntiles = B * tiles_x * tiles_y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  const int mt = wave >> 1, nt = wave & 1;
-  f32x4_t acc[9], accb = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
+  const int mt = (wave >> 1) & 1, nt = wave & 1, kh = wave >> 2;
+  for (int i = tid; i < 9 * 2 * 64; i += FB_NT) wS[i] = *(const bf16x8_t*)(wpT + i * 8);
+  f32x4_t accw[9], accb = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int t = 0; t < 9; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < 9; ++t) accw[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   bf16x8_t ones;
 #pragma unroll
   for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
-  // operation k of this thread: kind (0 none, 1 a, 2 g), source row and
-  // first column relative to (y0, x0), channel group, LDS destination;
-  // identical for every tile
-  int o_kind[2], o_row[2], o_col[2], o_c8[2], o_dst[2];
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    int q = (int)threadIdx.x + 256 * k;
-    o_kind[k] = q < WB_AOPS ? 1 : (q < WB_AOPS + WB_GOPS ? 2 : 0);
-    const bool is_g = o_kind[k] == 2;
-    if (is_g) q -= WB_AOPS;
-    const int c8 = q & 3;
-    q >>= 2;
-    const int ngrp = is_g ? WB_W / 4 : WB_AC / 4;
-    const int j4 = (q % ngrp) * 4, row = q / ngrp;
-    o_row[k] = is_g ? row : row - 1;
-    o_col[k] = is_g ? j4 : j4 - 1;
-    o_c8[k] = c8;
-    o_dst[k] = is_g ? (8 * c8) * WB_GS + row * WB_W + j4 : (8 * c8) * WB_CS + row * WB_RS + j4;
-  }
-  bf16x8_t v[2][4];
+  // staging operation k of this thread, the same for every tile: kind (0
+  // none, 1 g, 2 a, 3 halo chunk of g), source row and first column
+  // relative to (y0, x0), channel group. Decoded where it is used from a
+  // thread number the compiler cannot hoist (a volatile copy), which keeps
+  // twelve registers free across the tile loop.
+  struct Op {
+    int kind, row, col, c8;
+  };
+  auto op = [&](int k) {
+    int q;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(q) : "v"(tid));
+    q += FB_NT * k;
+    Op o{0, 0, 0, 0};
+    if (q < FB_GOPS) {
+      o.kind = 1;
+      o.c8 = q & 3;
+      q >>= 2;
+      o.col = 4 * (q % (FB_W / 4));
+      o.row = q / (FB_W / 4) - 1;
+    } else if (q < FB_GOPS + FB_HOPS) {
+      q -= FB_GOPS;
+      o.kind = 3;
+      o.c8 = q & 3;
+      q >>= 2;
+      o.col = (q & 1) ? FB_W : -1;
+      o.row = (q >> 1) - 1;
+    } else if (q < FB_OPS) {
+      q -= FB_GOPS + FB_HOPS;
+      o.kind = 2;
+      o.c8 = q & 3;
+      q >>= 2;
+      o.col = 4 * (q % (FB_AC / 4)) - 1;
+      o.row = q / (FB_AC / 4) - 1;
+    }
+    return o;
+  };
+  bf16x8_t v[FB_NOP][4];
   auto load = [&](int tile) {
     const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
-    const int y0 = (rem / tiles_x) * WB_H, x0 = (rem % tiles_x) * WB_W;
+    const int y0 = (rem / tiles_x) * FB_H, x0 = (rem % tiles_x) * FB_W;
     const size_t img = (size_t)b * H * W;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const __bf16* src = o_kind[k] == 2 ? g_out : a_in;
-      const int gy = y0 + o_row[k];
+    for (int k = 0; k < FB_NOP; ++k) {
+      const Op o = op(k);
+      const __bf16* src = o.kind == 2 ? a_in : g_out;
+      const int gy = y0 + o.row;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int gx = x0 + o_col[k] + u;
-        if (o_kind[k] != 0 && gy >= 0 && gy < H && gx >= 0 && gx < W)
-          v[k][u] = *(const bf16x8_t*)(src + (img + (size_t)gy * W + gx) * 32 + 8 * o_c8[k]);
+        const int gx = x0 + o.col + u;
+        const bool used = o.kind != 0 && (u == 0 || o.kind != 3);
+        if (used && gy >= 0 && gy < H && gx >= 0 && gx < W)
+          v[k][u] = *(const bf16x8_t*)(src + (img + (size_t)gy * W + gx) * 32 + 8 * o.c8);
         else
 #pragma unroll
           for (int e = 0; e < 8; ++e) v[k][u][e] = (__bf16)0.0f;
@@ -555,55 +597,157 @@ __global__ __launch_bounds__(256) void wgrad32_bf16_kernel(const __bf16* __restr
   };
   auto store = [&]() {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      if (o_kind[k] == 0) continue;
-      __bf16* base = (o_kind[k] == 2 ? gT : aS) + o_dst[k];
-      const int cs = o_kind[k] == 2 ? WB_GS : WB_CS;
+    for (int k = 0; k < FB_NOP; ++k) {
+      const Op o = op(k);
+      const int row = o.row + 1, c8 = o.c8;
+      if (o.kind == 1 || o.kind == 3) {
+        const int nu = o.kind == 1 ? 4 : 1;
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
-        *(bf16x4_t*)(base + e * cs) = bf16x4_t{v[k][0][e], v[k][1][e], v[k][2][e], v[k][3][e]};
+        for (int u = 0; u < 4; ++u) {
+          if (u >= nu) break;
+          const int lx = o.col + u + 1;
+          *(bf16x8_t*)(gP + (row * FB_LW + lx) * 32 + hs_swz<__bf16>(lx, c8) * 8) = v[k][u];
+        }
+        if (o.kind == 1 && row >= 1 && row <= FB_H) {
+          __bf16* base = gT + (8 * c8) * FB_GS + (row - 1) * FB_W + o.col;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            *(bf16x4_t*)(base + e * FB_GS) =
+                bf16x4_t{v[k][0][e], v[k][1][e], v[k][2][e], v[k][3][e]};
+        }
+      } else if (o.kind == 2) {
+        __bf16* base = aT + (8 * c8) * FB_CS + row * FB_RS + (o.col + 1);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          *(bf16x4_t*)(base + e * FB_CS) = bf16x4_t{v[k][0][e], v[k][1][e], v[k][2][e], v[k][3][e]};
+      }
     }
   };
   if ((int)blockIdx.x < ntiles) load(blockIdx.x);
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    __syncthreads();  // the previous tile's MFMAs have read the LDS tiles
+    const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
+    const int y0 = (rem / tiles_x) * FB_H, x0 = (rem % tiles_x) * FB_W;
+    const size_t img = (size_t)b * H * W;
+    __syncthreads();  // the previous tile's operands have been read
     store();
     __syncthreads();
     if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
+    // ---- input gradient, row `wave` of the tile: input row wave + d of gP
+    // (tap dy = d), both 16-channel tiles, four 16-pixel runs. The weight
+    // fragments are read from LDS where they are used; the lane number comes
+    // from a volatile statement so that the compiler does not hoist all
+    // eighteen out of the tile loop (72 registers it does not have)
+    int ln;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+    f32x4_t acc[2][4];
 #pragma unroll
-    for (int kc = 0; kc < WB_PX / 32; ++kc) {
-      const int py = kc / (WB_W / 32), pc = (kc % (WB_W / 32)) * 32 + 8 * g;
-      const bf16x8_t af = *(const bf16x8_t*)(gT + (16 * mt + r) * WB_GS + py * WB_W + pc);
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int t = d * 3 + dx;
+        frag8<__bf16> w0, w1;
+        w0.v = wS[(t * 2 + 0) * 64 + ln];
+        w1.v = wS[(t * 2 + 1) * 64 + ln];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          const int lx = n * 16 + r + dx;
+          frag8<__bf16> bf;
+          lds_frag(bf, gP + ((wave + d) * FB_LW + lx) * 32, lx, g);
+          acc[0][n] = hs_mma(w0, bf, acc[0][n]);
+          acc[1][n] = hs_mma(w1, bf, acc[1][n]);
+        }
+      }
+    }
+    // ---- weight gradient: K = 32 pixels of one tile row per MFMA
+#pragma unroll
+    for (int kc = 0; kc < 8; ++kc) {
+      const int py = 4 * kh + (kc >> 1), pc = (kc & 1) * 32 + 8 * g;
+      const bf16x8_t af = *(const bf16x8_t*)(gT + (16 * mt + r) * FB_GS + py * FB_W + pc);
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
-        const __bf16* rowp = aS + (16 * nt + r) * WB_CS + (py + dy) * WB_RS + pc;
+        const __bf16* rowp = aT + (16 * nt + r) * FB_CS + (py + dy) * FB_RS + pc;
         const bf16x8_t lo = *(const bf16x8_t*)rowp;
         const bf16x8_t hi = *(const bf16x8_t*)(rowp + 8);
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx)
-          acc[dy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, shift_frag(lo, hi, dx),
-                                                                      acc[dy * 3 + dx], 0, 0, 0);
+          accw[dy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              af, shift_frag(lo, hi, dx), accw[dy * 3 + dx], 0, 0, 0);
       }
       if (nt == 0) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, ones, accb, 0, 0, 0);
     }
+    // ---- input gradient out, times the ReLU mask of a (from aT)
+    const int gy = y0 + wave;
+    if (gy < H) {
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const int gx = x0 + n * 16 + r;
+        if (gx >= W) continue;
+        const size_t o = (img + (size_t)gy * W + gx) * 32;
+        const __bf16* mk = aT + (wave + 1) * FB_RS + (n * 16 + r + 1);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const int co = 16 * m + 4 * g;
+          float vv[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            vv[i] = (float)mk[(co + i) * FB_CS] > 0.0f ? acc[m][n][i] : 0.0f;
+          hs_store4(g_in + o + co, vv[0], vv[1], vv[2], vv[3]);
+        }
+      }
+    }
   }
-  // acc[t][i] = dW[co = 16 mt + 4 g + i][ci = 16 nt + r][t]
-  float* row = partials + (size_t)blockIdx.x * hs::NPARAM + hs_wk(layer);
+  // ---- the two row halves of each weight-gradient block, in a fixed order
+  __syncthreads();
+  float* scratch = (float*)gP;
+  if (kh == 1) {
+    float* sp = scratch + ((wave - 4) * 64 + lane) * 40;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sp[4 * t + i] = accw[t][i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sp[36 + i] = accb[i];
+  }
+  __syncthreads();
+  if (kh == 1) return;
+  {
+    const float* sp = scratch + (wave * 64 + lane) * 40;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) accw[t][i] += sp[4 * t + i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) accb[i] += sp[36 + i];
+  }
+  // accw[t][i] = dW[co = 16 mt + 4 g + i][ci = 16 nt + r][t]
+  float* prow = partials + (size_t)blockIdx.x * hs::NPARAM + hs_wk(layer);
 #pragma unroll
   for (int t = 0; t < 9; ++t)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int co = 16 * mt + 4 * g + i, ci = 16 * nt + r;
-      float* d = row + (co * 32 + ci) * 9 + t;
-      *d = accumulate ? *d + acc[t][i] : acc[t][i];
+      float* dd = prow + (co * 32 + ci) * 9 + t;
+      *dd = accumulate ? *dd + accw[t][i] : accw[t][i];
     }
   if (nt == 0 && r == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      float* d = row + 32 * 32 * 9 + 16 * mt + 4 * g + i;
-      *d = accumulate ? *d + accb[i] : accb[i];
+      float* dd = prow + 32 * 32 * 9 + 16 * mt + 4 * g + i;
+      *dd = accumulate ? *dd + accb[i] : accb[i];
     }
   }
+  // a grid of fewer than WGRAD_BLOCKS blocks: the layer's rows no block owns
+  // are cleared when this call starts the sum (accumulating calls add
+  // nothing to them)
+  if (!accumulate)
+    for (int rr = blockIdx.x + gridDim.x; rr < hs::WGRAD_BLOCKS; rr += gridDim.x) {
+      float* zr = partials + (size_t)rr * hs::NPARAM + hs_wk(layer);
+      for (int i = tid; i < 32 * 32 * 9 + 32; i += 4 * 64) zr[i] = 0.0f;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -877,13 +1021,10 @@ hipError_t launch_conv32(const void* in, const void* wpack, const float* bias, c
   const int ct_h = precision == HS_BF16 ? conv_rows<__bf16>::CT_H : conv_rows<float>::CT_H;
   const dim3 grid((W + CT_W - 1) / CT_W, (H + ct_h - 1) / ct_h, B);
   if (precision == HS_BF16) {
-    if (mode == 0)
-      conv32_kernel<__bf16, 0><<<grid, 256, 0, s>>>((const __bf16*)in, (const __bf16*)wpack, bias,
-                                                    nullptr, (__bf16*)out, H, W);
-    else
-      conv32_kernel<__bf16, 1><<<grid, 256, 0, s>>>((const __bf16*)in, (const __bf16*)wpack,
-                                                    nullptr, (const __bf16*)mask, (__bf16*)out, H,
-                                                    W);
+    // the input gradient of a BF16 layer comes from the fused backward
+    if (mode != 0) return hipErrorInvalidValue;
+    conv32_kernel<__bf16, 0><<<grid, 256, 0, s>>>((const __bf16*)in, (const __bf16*)wpack, bias,
+                                                  nullptr, (__bf16*)out, H, W);
   } else {
     if (mode == 0)
       conv32_kernel<float, 0><<<grid, 256, 0, s>>>((const float*)in, (const float*)wpack, bias,
@@ -945,12 +1086,21 @@ hipError_t launch_wgrad_first(const float* contone, const float* z, const void* 
 
 hipError_t launch_wgrad32(const void* a_in, const void* g_out, int layer, int B, int H, int W,
                           int precision, float* partials, int accumulate, hipStream_t s) {
-  if (precision == HS_BF16)
-    wgrad32_bf16_kernel<<<WGRAD_BLOCKS, 256, 0, s>>>((const __bf16*)a_in, (const __bf16*)g_out, B,
+  // BF16 layers take the fused backward (launch_bwd32)
+  if (precision == HS_BF16) return hipErrorInvalidValue;
+  wgrad32_kernel<float><<<WGRAD_BLOCKS, 256, 0, s>>>((const float*)a_in, (const float*)g_out, B,
                                                      H, W, layer, partials, accumulate);
-  else
-    wgrad32_kernel<float><<<WGRAD_BLOCKS, 256, 0, s>>>((const float*)a_in, (const float*)g_out, B,
-                                                       H, W, layer, partials, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd32(const void* a_in, const void* g_out, const void* wpackT, void* g_in,
+                        int layer, int B, int H, int W, float* partials, int accumulate,
+                        int num_cus, hipStream_t s) {
+  // one block per CU (its LDS allows no second), all resident at once
+  const int grid = num_cus < WGRAD_BLOCKS ? (num_cus > 0 ? num_cus : 1) : WGRAD_BLOCKS;
+  bwd32_bf16_kernel<<<grid, FB_NT, 0, s>>>((const __bf16*)a_in, (const __bf16*)g_out,
+                                                   (const __bf16*)wpackT, (__bf16*)g_in, B, H, W,
+                                                   layer, partials, accumulate);
   return hipGetLastError();
 }
 

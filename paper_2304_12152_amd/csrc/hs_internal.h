@@ -194,6 +194,11 @@ hipError_t launch_dgrad_last(const float* grad, const float* probs, const void* 
 hipError_t launch_wgrad_first(const float* contone, const float* z, const void* g1, int B, int H,
                               int W, int precision, float* partials, int accumulate,
                               hipStream_t s);
+// BF16 only: the input gradient g_in of a 32->32 layer (through the ReLU
+// mask of a_in) and its weight-gradient partial rows in one pass
+hipError_t launch_bwd32(const void* a_in, const void* g_out, const void* wpackT, void* g_in,
+                        int layer, int B, int H, int W, float* partials, int accumulate,
+                        int num_cus, hipStream_t s);
 hipError_t launch_wgrad32(const void* a_in, const void* g_out, int layer, int B, int H, int W,
                           int precision, float* partials, int accumulate, hipStream_t s);
 hipError_t launch_wgrad_last(const void* a5, const float* g6, int B, int H, int W, int precision,
