@@ -128,7 +128,10 @@ struct PolicyWs {
   bool recompute;
   void* act(int j) const { return buf[recompute ? j % 2 : j]; }
 };
-PolicyWs carve_policy(Carve& cv, size_t N, int prec, bool recompute = false) {
+// partials: the rows of weight-gradient partial sums to use, or null to
+// carve WGRAD_BLOCKS x rows of them
+PolicyWs carve_policy(Carve& cv, size_t N, int prec, bool recompute = false,
+                      float* partials = nullptr, int rows = WGRAD_BLOCKS) {
   PolicyWs w;
   w.recompute = recompute;
   w.packF = cv.take<char>(pack_bytes(prec));
@@ -139,7 +142,7 @@ PolicyWs carve_policy(Carve& cv, size_t N, int prec, bool recompute = false) {
   w.z = cv.take<float>(N * 4);
   w.c = cv.take<float>(N * 4);
   w.g6 = cv.take<float>(N * 4);
-  w.partials = cv.take<float>((size_t)WGRAD_BLOCKS * NPARAM * 4);
+  w.partials = partials ? partials : cv.take<float>((size_t)rows * NPARAM * 4);
   w.rtmp = cv.take<float>((size_t)REDUCE_GROUPS * NPARAM * 4);
   w.counter = cv.take<unsigned long long>(64);
   return w;
@@ -1147,14 +1150,48 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
 }
 
 // ------------------------------------------------------------ train step --
+// The second stream of a device (default priority, non-blocking) and the two
+// events that fork the gray side batch onto it and join it back; created on
+// first use, kept until the process ends. The mutex keeps each caller's
+// record / wait / launch sequence on them whole.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::mutex mu;
+};
+static int side_stream(SideStream** out) {
+  static std::mutex mu;
+  static std::vector<SideStream*> per_dev;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(HS_EHIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)per_dev.size() <= dev) per_dev.resize(dev + 1, nullptr);
+  if (!per_dev[dev]) {
+    SideStream* ss = new SideStream;
+    if (hipStreamCreateWithFlags(&ss->s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ss->join, hipEventDisableTiming) != hipSuccess) {
+      delete ss;
+      return fail(HS_EHIP, "policy_train_step: creating the side stream failed");
+    }
+    per_dev[dev] = ss;
+  }
+  *out = per_dev[dev];
+  return HS_OK;
+}
+
+// The batch and the gray side batch have workspaces of their own, so that
+// the side batch runs on a second stream beside the batch; the side batch's
+// weight-gradient partial sums are the second WGRAD_BLOCKS rows.
 static size_t train_ws(int B, int H, int W, int Bg, int Hg, int Wg, int prec, bool recompute,
-                       void* base, PolicyWs* pw, LossWs* lw, float** probs, float** probs_g,
-                       uint8_t** act, float** gradp, float** gradg, float** grad,
-                       float** loss_out) {
+                       void* base, PolicyWs* pw, PolicyWs* pwg, LossWs* lw, float** probs,
+                       float** probs_g, uint8_t** act, float** gradp, float** gradg,
+                       float** grad, float** loss_out) {
   Carve cv(base);
   const size_t N = (size_t)B * H * W, Ng = (size_t)Bg * Hg * Wg;
-  const size_t Nmax = N > Ng ? N : Ng;
-  PolicyWs p = carve_policy(cv, Nmax, prec, recompute);
+  PolicyWs p = carve_policy(cv, N, prec, recompute, nullptr, Ng ? 2 * WGRAD_BLOCKS : WGRAD_BLOCKS);
+  PolicyWs q{};
+  if (Ng) q = carve_policy(cv, Ng, prec, recompute, p.partials + (size_t)WGRAD_BLOCKS * NPARAM);
   // sized for the smallest margin (most tiles); the caller sets the real count
   LossWs l = carve_loss(cv, B, H, W, Bg, Hg, Wg, 1, true);
   float* pr = cv.take<float>(N * 4);
@@ -1165,6 +1202,7 @@ static size_t train_ws(int B, int H, int W, int Bg, int Hg, int Wg, int prec, bo
   float* g = cv.take<float>((size_t)NPARAM * 4);
   float* lo = cv.take<float>((size_t)(3 * B + 2) * 4);
   if (pw) *pw = p;
+  if (pwg) *pwg = q;
   if (lw) *lw = l;
   if (probs) *probs = pr;
   if (probs_g) *probs_g = pg;
@@ -1182,7 +1220,7 @@ size_t halftone_train_workspace_size_params(int B, int H, int W, int Bg, int Hg,
   if (Bg > 0 && !shape_ok(Bg, Hg, Wg)) return 0;
   if (Bg == 0) Hg = Wg = 0;
   return train_ws(B, H, W, Bg, Hg, Wg, precision, tp && tp->recompute, nullptr, nullptr, nullptr,
-                  nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+                  nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
 size_t halftone_train_workspace_size(int B, int H, int W, int Bg, int Hg, int Wg,
@@ -1220,11 +1258,11 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
     return fail(HS_EWORKSPACE, "policy_train_step: workspace too small");
   if ((rc = check_device())) return rc;
   hipStream_t s = (hipStream_t)stream;
-  PolicyWs pw;
+  PolicyWs pw, pwg;
   LossWs lw;
   float *probs, *probs_g, *gradp, *gradg, *grad, *loss_out;
   uint8_t* act;
-  train_ws(B, H, W, Bg, Hg, Wg, precision, tp->recompute != 0, workspace, &pw, &lw, &probs,
+  train_ws(B, H, W, Bg, Hg, Wg, precision, tp->recompute != 0, workspace, &pw, &pwg, &lw, &probs,
            &probs_g, &act, &gradp, &gradg, &grad, &loss_out);
   lw.ntiles = ((H - 2 * m + 15) / 16) * ((W - 2 * m + 15) / 16);
   const hs_loss_params& lp = tp->loss;
@@ -1234,27 +1272,42 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
     return rc;
   const int kind = tp->noise_kind;
   const uint32_t st = (uint32_t)step;
-  // batch: forward, actions, policy gradient (logit space), backward
-  HS_TRY(run_forward_train(weights, contones, seeds, B, H, W, kind, st, precision, pw, probs, act,
-                           lp.levels, s));
   LossDev win;
   make_windows(lp, &win);
+  // batch: forward and actions
+  HS_TRY(run_forward_train(weights, contones, seeds, B, H, W, kind, st, precision, pw, probs, act,
+                           lp.levels, s));
+  // the constant-gray side batch (forward, anisotropy gradient, backward
+  // into its own partial rows) on a second stream, beside the batch's loss
+  // kernels, which are bound by the vector ALUs and leave room for its small
+  // launches; it starts after the batch's forward, and the batch waits for
+  // it before the partial sums are added
+  const int npatch = Bg * (Hg / 32) * (Wg / 32);
+  SideStream* side = nullptr;
+  std::unique_lock<std::mutex> side_lock;
+  if (Bg > 0) {
+    if ((rc = side_stream(&side))) return rc;
+    side_lock = std::unique_lock<std::mutex>(side->mu);
+    HS_TRY(hipEventRecord(side->fork, s));
+    HS_TRY(hipStreamWaitEvent(side->s, side->fork, 0));
+    hipStream_t s2 = side->s;
+    HS_TRY(run_forward_train(weights, gray, gray_seeds, Bg, Hg, Wg, kind, st, precision, pwg,
+                             probs_g, nullptr, lp.levels, s2));
+    HS_TRY(launch_fill(gradg, (size_t)Bg * Hg * Wg, 0.0f, s2));
+    if (npatch > 0)
+      HS_TRY(launch_as(probs_g, Bg, Hg, Wg, lp.w_a / (float)npatch, 1, lw.patches, gradg, s2));
+    const FwdInput gin{gray, gray_seeds, kind, st};
+    HS_TRY(run_backward(weights, gradg, nullptr, Bg, Hg, Wg, precision, pwg, 0, s2, &gin));
+    HS_TRY(hipEventRecord(side->join, s2));
+  }
+  // batch: policy gradient (logit space) and backward
   HS_TRY(launch_loss_stats(act, contones, B, H, W, lp, win, lw.maps, lw.tiles, lw.ntiles, s));
   HS_TRY(launch_le_grad(act, contones, probs, 1, B, H, W, lp, win, lw.maps, gradp, s));
   const FwdInput fin{contones, seeds, kind, st};
   HS_TRY(run_backward(weights, gradp, nullptr, B, H, W, precision, pw, 0, s, &fin));
-  // constant-gray side batch: forward, anisotropy gradient, backward
-  const int npatch = Bg * (Hg / 32) * (Wg / 32);
-  if (Bg > 0) {
-    HS_TRY(run_forward_train(weights, gray, gray_seeds, Bg, Hg, Wg, kind, st, precision, pw,
-                             probs_g, nullptr, lp.levels, s));
-    HS_TRY(launch_fill(gradg, (size_t)Bg * Hg * Wg, 0.0f, s));
-    if (npatch > 0)
-      HS_TRY(launch_as(probs_g, Bg, Hg, Wg, lp.w_a / (float)npatch, 1, lw.patches, gradg, s));
-    const FwdInput gin{gray, gray_seeds, kind, st};
-    HS_TRY(run_backward(weights, gradg, nullptr, Bg, Hg, Wg, precision, pw, 1, s, &gin));
-  }
-  HS_TRY(launch_reduce_partials(pw.partials, WGRAD_BLOCKS, pw.rtmp, grad, s));
+  if (Bg > 0) HS_TRY(hipStreamWaitEvent(s, side->join, 0));
+  HS_TRY(launch_reduce_partials(pw.partials, Bg > 0 ? 2 * WGRAD_BLOCKS : WGRAD_BLOCKS, pw.rtmp,
+                                grad, s));
   HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, lp.w_s,
                             (long)(H - 2 * m) * (W - 2 * m), loss_out, s));
   // Adam with the cosine learning rate of this step, bias corrections at t = step + 1
