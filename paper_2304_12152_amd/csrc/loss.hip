@@ -137,6 +137,153 @@ __global__ __launch_bounds__(256) void loss_stats_kernel(const uint8_t* __restri
   }
 }
 
+// The same statistics for compile-time window radii RH (HVS) and RS (SSIM),
+// register-blocked: a thread computes four horizontally adjacent outputs,
+// reading each staged row segment (4 + 2R values of h and of c) once per
+// kernel row for all four instead of once per tap and output, and holding
+// the row's weights in registers. The taps of every output are summed in
+// the same order and with the same operations as in loss_stats_kernel
+// (rows, then columns); the per-tile sums are added in another order. A
+// block covers 16 x 64 outputs, i.e. four of the 16 x 16 tiles whose
+// partial sums loss_reduce_kernel adds.
+constexpr int LB_TY = 16, LB_TX = 64;
+
+template <int RH, int RS>
+__global__ __launch_bounds__(256) void loss_stats_rb_kernel(const uint8_t* __restrict__ h,
+                                                            const float* __restrict__ c, int H,
+                                                            int W, LossConst q,
+                                                            const hs::LossDev win,
+                                                            float* __restrict__ maps,
+                                                            float* __restrict__ partials,
+                                                            int ntiles_per_img) {
+  constexpr int R = RH > RS ? RH : RS, SY = LB_TY + 2 * R, SX = LB_TX + 2 * R, NS = 4 + 2 * R;
+  __shared__ float sh[SY * SX], sc[SY * SX];
+  __shared__ float sG[(2 * RH + 1) * (2 * RH + 1)], sw[(2 * RS + 1) * (2 * RS + 1)];
+  __shared__ float red[2][256];
+  const int b = blockIdx.z;
+  const int vy0 = R + blockIdx.y * LB_TY, vx0 = R + blockIdx.x * LB_TX;
+  const size_t img = (size_t)b * H * W;
+  // the windows' rows of 2 r + 1 taps, stored densely (win holds 15 x 15)
+  for (int i = threadIdx.x; i < (2 * RH + 1) * (2 * RH + 1); i += 256)
+    sG[i] = win.G[(i / (2 * RH + 1)) * (2 * RH + 1) + i % (2 * RH + 1)];
+  for (int i = threadIdx.x; i < (2 * RS + 1) * (2 * RS + 1); i += 256)
+    sw[i] = win.w[(i / (2 * RS + 1)) * (2 * RS + 1) + i % (2 * RS + 1)];
+  for (int i = threadIdx.x; i < SY * SX; i += 256) {
+    const int ly = i / SX, lx = i - ly * SX, gy = vy0 - R + ly, gx = vx0 - R + lx;
+    const bool in = gy < H && gx < W;  // gy, gx >= 0 because vy0, vx0 >= R
+    sh[i] = in ? (float)h[img + (size_t)gy * W + gx] * q.hstep : 0.0f;
+    sc[i] = in ? c[img + (size_t)gy * W + gx] : 0.0f;
+  }
+  __syncthreads();
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const int jy = vy0 + ty, jx0 = vx0 + 4 * tx;
+  // row segment of kernel row i: staged columns 4 tx .. 4 tx + 2R + 3
+  const float* hr0 = sh + ty * SX + 4 * tx;
+  const float* cr0 = sc + ty * SX + 4 * tx;
+  float e[4] = {0.f, 0.f, 0.f, 0.f}, mh[4] = {0.f, 0.f, 0.f, 0.f}, mc[4] = {0.f, 0.f, 0.f, 0.f};
+  // kernel rows one at a time (unrolled, the loads of all rows would be
+  // hoisted and spill)
+#pragma unroll 1
+  for (int i = 0; i < 2 * R + 1; ++i) {
+    float hv[NS], cv[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      hv[j] = hr0[i * SX + j];
+      cv[j] = cr0[i * SX + j];
+    }
+    if (i >= R - RH && i <= R + RH) {
+      const int gi = i - (R - RH);
+#pragma unroll
+      for (int j = 0; j < 2 * RH + 1; ++j) {
+        const float g = sG[gi * (2 * RH + 1) + j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int p = k + j + (R - RH);
+          e[k] = fmaf(g, hv[p] - cv[p], e[k]);
+        }
+      }
+    }
+    if (i >= R - RS && i <= R + RS) {
+      const int wi = i - (R - RS);
+#pragma unroll
+      for (int j = 0; j < 2 * RS + 1; ++j) {
+        const float wv = sw[wi * (2 * RS + 1) + j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int p = k + j + (R - RS);
+          mh[k] = fmaf(wv, hv[p], mh[k]);
+          mc[k] = fmaf(wv, cv[p], mc[k]);
+        }
+      }
+    }
+  }
+  float vh[4] = {0.f, 0.f, 0.f, 0.f}, vc[4] = {0.f, 0.f, 0.f, 0.f}, cov[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int i = R - RS; i <= R + RS; ++i) {
+    const int wi = i - (R - RS);
+    float hv[NS], cv[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      hv[j] = hr0[i * SX + j];
+      cv[j] = cr0[i * SX + j];
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * RS + 1; ++j) {
+      const float wv = sw[wi * (2 * RS + 1) + j];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int p = k + j + (R - RS);
+        const float dh = hv[p] - mh[k], dc = cv[p] - mc[k];
+        vh[k] = fmaf(wv * dh, dh, vh[k]);
+        vc[k] = fmaf(wv * dc, dc, vc[k]);
+        cov[k] = fmaf(wv * dh, dc, cov[k]);
+      }
+    }
+  }
+  float e2 = 0.0f, cs = 0.0f;
+  const size_t n = (size_t)gridDim.z * H * W;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int jx = jx0 + k;
+    if (jy < H - R && jx < W - R) {
+      const float ssim = ((2.0f * mh[k] * mc[k] + q.c1) * (2.0f * cov[k] + q.c2)) /
+                         ((mh[k] * mh[k] + mc[k] * mc[k] + q.c1) * (vh[k] + vc[k] + q.c2));
+      const float sig = q.k * sqrtf(vc[k]);
+      e2 += e[k] * e[k];
+      cs += sig * ssim + (1.0f - sig);
+      if (maps) {
+        const size_t o = img + (size_t)jy * W + jx;
+        maps[o] = e[k];
+        maps[n + o] = mh[k];
+        maps[2 * n + o] = mc[k];
+        maps[3 * n + o] = vc[k];
+        maps[4 * n + o] = cov[k];
+        if (q.levels > 2) maps[5 * n + o] = vh[k];
+      }
+    }
+  }
+  red[0][threadIdx.x] = e2;
+  red[1][threadIdx.x] = cs;
+  __syncthreads();
+  // the four 16 x 16 tiles: thread t < 4 adds tile t's 64 threads in order
+  const int tiles_x = (W - 2 * R + 15) / 16;
+  if (threadIdx.x < 4) {
+    const int tcol = blockIdx.x * 4 + threadIdx.x;
+    if (tcol < tiles_x) {
+      float a = 0.0f, d = 0.0f;
+      for (int r = 0; r < 16; ++r)
+        for (int u = 0; u < 4; ++u) {
+          const int t = r * 16 + 4 * threadIdx.x + u;
+          a += red[0][t];
+          d += red[1][t];
+        }
+      float* dp = partials + ((size_t)b * ntiles_per_img + blockIdx.y * tiles_x + tcol) * 2;
+      dp[0] = a;
+      dp[1] = d;
+    }
+  }
+}
+
 __global__ void loss_reduce_kernel(const float* __restrict__ partials, int B, int ntiles,
                                    const float* __restrict__ as_partials, int npatch, float w_s,
                                    float invM, float* __restrict__ out) {
@@ -498,6 +645,12 @@ hipError_t launch_loss_stats(const uint8_t* h, const float* c, int B, int H, int
                              float* tile_partials, int ntiles_per_img, hipStream_t s) {
   const LossConst q = make_const(p);
   const int vh = H - 2 * q.m, vw = W - 2 * q.m;
+  if (q.rh == 5 && q.rs == 5) {  // the default windows
+    const dim3 grid((vw + LB_TX - 1) / LB_TX, (vh + LB_TY - 1) / LB_TY, B);
+    loss_stats_rb_kernel<5, 5><<<grid, 256, 0, s>>>(h, c, H, W, q, win, maps, tile_partials,
+                                                    ntiles_per_img);
+    return hipGetLastError();
+  }
   const dim3 grid((vw + LT - 1) / LT, (vh + LT - 1) / LT, B);
   loss_stats_kernel<<<grid, 256, 0, s>>>(h, c, H, W, q, win, maps, tile_partials,
                                          ntiles_per_img);
