@@ -442,6 +442,135 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
   grad[oa] = gv;
 }
 
+// The binary form of le_grad_kernel for compile-time window radii RH and RS,
+// register-blocked: a thread computes the gradient of four horizontally
+// adjacent pixels. It walks each kernel row's segment of 4 + 2R window
+// centres once, computing a centre's own terms (A, B, C, D and their
+// products) once for the up to four pixels whose windows hold it, and adds
+// every pixel's terms in the same order as le_grad_kernel. A centre outside
+// the valid region has zero maps and zero sigma_c, so its SSIM term adds
+// exactly zero; its HVS term is masked. A block covers 16 x 64 pixels.
+template <int RH, int RS>
+__global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restrict__ h,
+                                                         const float* __restrict__ c,
+                                                         const float* __restrict__ probs,
+                                                         int logit_space, int B, int H, int W,
+                                                         LossConst q, const hs::LossDev win,
+                                                         const float* __restrict__ maps,
+                                                         float invM, float* __restrict__ grad) {
+  constexpr int R = RH > RS ? RH : RS, SY = LB_TY + 2 * R, SX = LB_TX + 2 * R;
+  constexpr int NH = 2 * RH + 1, NSW = 2 * RS + 1;
+  __shared__ float se[SY * SX], smh[SY * SX], smc[SY * SX], svc[SY * SX], scv[SY * SX],
+      ssg[SY * SX];
+  __shared__ float sG[NH * NH], sw[NSW * NSW];
+  const int b = blockIdx.z;
+  const int ay0 = blockIdx.y * LB_TY, ax0 = blockIdx.x * LB_TX;
+  const size_t img = (size_t)b * H * W, n = (size_t)B * H * W;
+  for (int i = threadIdx.x; i < NH * NH; i += 256) sG[i] = win.G[i];
+  for (int i = threadIdx.x; i < NSW * NSW; i += 256) sw[i] = win.w[i];
+  for (int i = threadIdx.x; i < SY * SX; i += 256) {
+    const int ly = i / SX, lx = i - ly * SX, gy = ay0 - R + ly, gx = ax0 - R + lx;
+    const bool in = gy >= q.m && gy < H - q.m && gx >= q.m && gx < W - q.m;
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f;
+    if (in) {
+      const size_t o = img + (size_t)gy * W + gx;
+      v0 = maps[o];
+      v1 = maps[n + o];
+      v2 = maps[2 * n + o];
+      v3 = maps[3 * n + o];
+      v4 = maps[4 * n + o];
+    }
+    se[i] = v0;
+    smh[i] = v1;
+    smc[i] = v2;
+    svc[i] = v3;
+    scv[i] = v4;
+    ssg[i] = q.k * sqrtf(v3);
+  }
+  __syncthreads();
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const int ay = ay0 + ty, axb = ax0 + 4 * tx;
+  if (ay >= H || axb >= W) return;
+  float delta[4], ca[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const bool ok = axb + k < W;
+    const size_t oa = img + (size_t)ay * W + (ok ? axb + k : axb);
+    delta[k] = h[oa] ? -1.0f : 1.0f;
+    ca[k] = c[oa];
+  }
+  // staged row of centre row ay + i: ty + R + i; centre segment of the four
+  // pixels: staged columns 4 tx .. 4 tx + 2R + 3 (global ax0 - R + column)
+  float dmse[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int i = -RH; i <= RH; ++i) {
+    const int jy = ay + i;
+    if (jy < q.m || jy >= H - q.m) continue;
+    const int rowo = (ty + R + i) * SX + 4 * tx + (R - RH);
+#pragma unroll
+    for (int jc = 0; jc < 2 * RH + 4; ++jc) {
+      const int gx = axb - RH + jc;
+      const float vm = (gx >= q.m && gx < W - q.m) ? 1.0f : 0.0f;
+      const float sev = se[rowo + jc];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int jt = jc - k;  // tap j = jt - RH
+        if (jt < 0 || jt > 2 * RH) continue;
+        const float dG = delta[k] * sG[(RH - i) * NH + (2 * RH - jt)] * vm;
+        dmse[k] = fmaf(2.0f * dG, sev, fmaf(dG, dG, dmse[k]));
+      }
+    }
+  }
+  float dcs[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int i = -RS; i <= RS; ++i) {
+    const int jy = ay + i;
+    if (jy < q.m || jy >= H - q.m) continue;
+    const int rowo = (ty + R + i) * SX + 4 * tx + (R - RS);
+#pragma unroll
+    for (int jc = 0; jc < 2 * RS + 4; ++jc) {
+      const int p = rowo + jc;
+      const float mh = smh[p], mc = smc[p], sg = ssg[p];
+      const float A = 2.0f * mh * mc + q.c1;
+      const float Bc = 2.0f * scv[p] + q.c2;
+      const float C = mh * mh + mc * mc + q.c1;
+      const float D = mh * (1.0f - mh) + svc[p] + q.c2;
+      const float CD = C * D, ABc = A * Bc, twomh = 2.0f * mh, omtmh = 1.0f - 2.0f * mh;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int jt = jc - k;
+        if (jt < 0 || jt > 2 * RS) continue;
+        const float wa = sw[(RS - i) * NSW + (2 * RS - jt)];
+        const float dw = delta[k] * wa;
+        const float dA = 2.0f * dw * mc;
+        const float dB = 2.0f * dw * (ca[k] - mc);
+        const float dC = dw * (twomh + dw);
+        const float dD = dw * (omtmh - dw);
+        const float num = CD * (A * dB + Bc * dA + dA * dB) - ABc * (C * dD + D * dC + dC * dD);
+        const float den = (C + dC) * (D + dD) * CD;
+        dcs[k] = fmaf(sg, num * __builtin_amdgcn_rcpf(den), dcs[k]);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (axb + k >= W) break;
+    const size_t oa = img + (size_t)ay * W + axb + k;
+    const float sgn = delta[k] > 0.0f ? 1.0f : -1.0f;
+    const float dR = sgn * (-dmse[k] * invM + q.w_s * dcs[k] * invM);
+    float gv = -dR / (float)B;
+    if (q.est == HS_EST_COMA) {
+      const float pa = probs[oa];
+      const bool one = h[oa] != 0;
+      if (logit_space) gv *= one ? (1.0f - pa) * (1.0f - pa) : pa * pa;
+      else gv *= one ? (1.0f - pa) / pa : pa / (1.0f - pa);
+    } else if (logit_space) {
+      gv *= probs[oa] * (1.0f - probs[oa]);
+    }
+    grad[oa] = gv;
+  }
+}
+
 constexpr int NRING = 24;
 
 // Ring of frequency (u, v) of a 32 x 32 periodogram: the rho with
@@ -675,6 +804,12 @@ hipError_t launch_le_grad(const uint8_t* h, const float* c, const float* probs, 
                           const float* maps, float* grad, hipStream_t s) {
   const LossConst q = make_const(p);
   const long M = (long)(H - 2 * q.m) * (W - 2 * q.m);
+  if (q.levels == 2 && q.rh == 5 && q.rs == 5) {  // binary, the default windows
+    const dim3 grid((W + LB_TX - 1) / LB_TX, (H + LB_TY - 1) / LB_TY, B);
+    le_grad_rb_kernel<5, 5><<<grid, 256, 0, s>>>(h, c, probs, logit_space, B, H, W, q, win, maps,
+                                                 (float)(1.0 / (double)M), grad);
+    return hipGetLastError();
+  }
   const dim3 grid((W + LT - 1) / LT, (H + LT - 1) / LT, B);
   auto kern = q.levels > 2 ? le_grad_kernel<true> : le_grad_kernel<false>;
   kern<<<grid, 256, 0, s>>>(h, c, probs, logit_space, B, H, W, q, win, maps,
