@@ -1038,7 +1038,9 @@ int halftone_policy_backward(const float* weights, const float* grad_probs, cons
   Carve cv(workspace);
   PolicyWs pw = carve_policy(cv, (size_t)B * H * W, precision);
   HS_TRY(run_backward(weights, grad_probs, probs, B, H, W, precision, pw, 0, s));
-  HS_TRY(launch_reduce_partials(pw.partials, WGRAD_BLOCKS, pw.rtmp, grad_weights, s));
+  HS_TRY(launch_reduce_partials(pw.partials, WGRAD_BLOCKS,
+                                precision == HS_BF16 ? bwd32_grid(num_cus()) : WGRAD_BLOCKS,
+                                pw.rtmp, grad_weights, s));
   return HS_OK;
 }
 
@@ -1306,8 +1308,9 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   const FwdInput fin{contones, seeds, kind, st};
   HS_TRY(run_backward(weights, gradp, nullptr, B, H, W, precision, pw, 0, s, &fin));
   if (Bg > 0) HS_TRY(hipStreamWaitEvent(s, side->join, 0));
-  HS_TRY(launch_reduce_partials(pw.partials, Bg > 0 ? 2 * WGRAD_BLOCKS : WGRAD_BLOCKS, pw.rtmp,
-                                grad, s));
+  HS_TRY(launch_reduce_partials(pw.partials, Bg > 0 ? 2 * WGRAD_BLOCKS : WGRAD_BLOCKS,
+                                precision == HS_BF16 ? bwd32_grid(num_cus()) : WGRAD_BLOCKS,
+                                pw.rtmp, grad, s));
   HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, lp.w_s,
                             (long)(H - 2 * m) * (W - 2 * m), loss_out, s));
   // Adam with the cosine learning rate of this step, bias corrections at t = step + 1

@@ -740,14 +740,9 @@ __global__ __launch_bounds__(FB_NT, 1) void bwd32_bf16_kernel(
       *dd = accumulate ? *dd + accb[i] : accb[i];
     }
   }
-  // a grid of fewer than WGRAD_BLOCKS blocks: the layer's rows no block owns
-  // are cleared when this call starts the sum (accumulating calls add
-  // nothing to them)
-  if (!accumulate)
-    for (int rr = blockIdx.x + gridDim.x; rr < hs::WGRAD_BLOCKS; rr += gridDim.x) {
-      float* zr = partials + (size_t)rr * hs::NPARAM + hs_wk(layer);
-      for (int i = tid; i < 32 * 32 * 9 + 32; i += 4 * 64) zr[i] = 0.0f;
-    }
+  // with fewer than WGRAD_BLOCKS blocks the layer's other rows are left
+  // alone: the reduction reads only the first gridDim.x rows of the 32->32
+  // layers (launch_reduce_partials, rows32)
 }
 
 // ---------------------------------------------------------------------------
@@ -972,12 +967,17 @@ __global__ __launch_bounds__(256) void wgrad_last_kernel(const T* __restrict__ a
 
 // Two-level fixed-order sum of the partial rows: group gi sums rows
 // gi, gi + G, gi + 2G, ... into tmp[gi]; then the G group sums in order.
-__global__ void reduce_partials_kernel(const float* __restrict__ partials, int rows,
+// rows: a multiple of WGRAD_BLOCKS (one set of rows per batch); the 32->32
+// layers' parameters have partial sums only in the first rows32 rows of each
+// set (their weight-gradient kernel's grid), the other rows are skipped
+__global__ void reduce_partials_kernel(const float* __restrict__ partials, int rows, int rows32,
                                        float* __restrict__ tmp) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x, gi = blockIdx.y;
   if (p >= hs::NPARAM) return;
+  const bool l32 = p >= hs_wk(2) && p < hs_bk(5) + 32;
   float s = 0.0f;
-  for (int r = gi; r < rows; r += hs::REDUCE_GROUPS) s += partials[(size_t)r * hs::NPARAM + p];
+  for (int r = gi; r < rows; r += hs::REDUCE_GROUPS)
+    if (!l32 || r % hs::WGRAD_BLOCKS < rows32) s += partials[(size_t)r * hs::NPARAM + p];
   tmp[(size_t)gi * hs::NPARAM + p] = s;
 }
 
@@ -1097,7 +1097,7 @@ hipError_t launch_bwd32(const void* a_in, const void* g_out, const void* wpackT,
                         int layer, int B, int H, int W, float* partials, int accumulate,
                         int num_cus, hipStream_t s) {
   // one block per CU (its LDS allows no second), all resident at once
-  const int grid = num_cus < WGRAD_BLOCKS ? (num_cus > 0 ? num_cus : 1) : WGRAD_BLOCKS;
+  const int grid = bwd32_grid(num_cus);
   bwd32_bf16_kernel<<<grid, FB_NT, 0, s>>>((const __bf16*)a_in, (const __bf16*)g_out,
                                                    (const __bf16*)wpackT, (__bf16*)g_in, B, H, W,
                                                    layer, partials, accumulate);
@@ -1115,10 +1115,14 @@ hipError_t launch_wgrad_last(const void* a5, const float* g6, int B, int H, int 
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_partials(const float* partials, int rows, float* tmp, float* grad,
-                                  hipStream_t s) {
-  reduce_partials_kernel<<<dim3((NPARAM + 255) / 256, REDUCE_GROUPS), 256, 0, s>>>(partials, rows,
-                                                                                  tmp);
+int bwd32_grid(int num_cus) {
+  return num_cus < WGRAD_BLOCKS ? (num_cus > 0 ? num_cus : 1) : WGRAD_BLOCKS;
+}
+
+hipError_t launch_reduce_partials(const float* partials, int rows, int rows32, float* tmp,
+                                  float* grad, hipStream_t s) {
+  reduce_partials_kernel<<<dim3((NPARAM + 255) / 256, REDUCE_GROUPS), 256, 0, s>>>(
+      partials, rows, rows32, tmp);
   reduce_groups_kernel<<<(NPARAM + 255) / 256, 256, 0, s>>>(tmp, grad);
   return hipGetLastError();
 }

@@ -206,8 +206,10 @@ hipError_t launch_wgrad_last(const void* a5, const float* g6, int B, int H, int 
 // sums `rows` rows of NPARAM partial sums in a fixed order; `tmp` holds
 // REDUCE_GROUPS * NPARAM floats
 constexpr int REDUCE_GROUPS = 16;
-hipError_t launch_reduce_partials(const float* partials, int rows, float* tmp, float* grad,
-                                  hipStream_t s);
+// the grid (and partial rows) of launch_bwd32 on a device with num_cus CUs
+int bwd32_grid(int num_cus);
+hipError_t launch_reduce_partials(const float* partials, int rows, int rows32, float* tmp,
+                                  float* grad, hipStream_t s);
 
 // loss.hip
 struct LossDev {  // the two normalised windows, passed to kernels by value
