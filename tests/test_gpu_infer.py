@@ -141,6 +141,26 @@ def test_c2_full_size_sampled(orc):
                 assert b32[b, y, x] == (ref >= 0) and b16[b, y, x] == (ref >= 0)
     m = np.abs(l32) > 4.1e-4
     assert np.array_equal(b16[m], b32[m])
+    # the oracle over one 48 x 48 window per image, and on the 200 listed
+    # pixels per image nearest the threshold (the ones the recheck stages
+    # decide), one receptive field each
+    z = orc.noise_map(seeds, H, W, kind=0, stream=1, step=0)
+    l16n = l16.cpu().numpy()
+    checked = 0
+    for b in range(B):
+        y0, x0 = int(rng.integers(0, H - 48)), int(rng.integers(0, W - 48))
+        ref = orc.policy_forward_window(wd, c[b].astype(np.float64), z[b], y0, y0 + 48, x0, x0 + 48)
+        mw = parity_mask(orc, ref)
+        assert np.array_equal(b16[b, y0:y0 + 48, x0:x0 + 48][mw], (ref >= 0)[mw].astype(np.uint8))
+        listed = np.argwhere(np.abs(l16n[b]) < 0.055)
+        order = np.argsort(np.abs(l32[b][listed[:, 0], listed[:, 1]]))[:200]
+        for (y, x) in listed[order]:
+            r = window_logit(orc, wd, c[b], seeds[b], int(y), int(x))
+            if abs(orc.sigmoid(r) - 0.5) > P_MARGIN:
+                assert b16[b, y, x] == (r >= 0), (b, y, x, r)
+                checked += 1
+    _say("C2: listed pixels checked against the oracle off the margin:", checked)
+    assert checked > 8 * 100
     # every rechecked logit is the FP16 cone stage's or, nearer the
     # threshold, the split stage's or the FP32 stage's; each agrees with the
     # FP32 path to its error
