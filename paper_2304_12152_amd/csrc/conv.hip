@@ -302,6 +302,83 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T* __restrict__ in
 }
 
 // ---------------------------------------------------------------------------
+// Layer 6 and the head of the training forward (MODE 1 of conv_last_kernel)
+// on BF16 activations, on the matrix cores: one MFMA pair per 16-pixel run
+// of the tile and its halo gives the nine taps' 32-channel sums
+// T[tap][pixel] = sum_ci W6[ci][tap] a5[pixel][ci] (the FP32 weights split
+// into BF16 hi + lo parts, about 16 significant bits; a5 is BF16 already),
+// and each output adds its neighbours' taps, x = b6 + sum_t T[t][pixel +
+// tap t], in tap order. A block covers 16 x 64 outputs (four per thread),
+// with T of the 18 x 66 positions in LDS.
+// ---------------------------------------------------------------------------
+constexpr int CLM_TY = 16, CLM_TX = 64, CLM_RY = CLM_TY + 2, CLM_RX = CLM_TX + 2;
+constexpr int CLM_RUNS = (CLM_RX + 15) / 16;  // 16-pixel runs per halo row
+constexpr int CLM_TS = 12;                    // floats per position (taps 0..8, 3 unused)
+
+__global__ __launch_bounds__(256) void conv_last_mfma_kernel(const __bf16* __restrict__ in,
+                                                             const float* __restrict__ w, int H,
+                                                             int W,
+                                                             const uint64_t* __restrict__ seeds,
+                                                             uint32_t step,
+                                                             uint8_t* __restrict__ bits,
+                                                             float* __restrict__ probs,
+                                                             const hs::Levels lv) {
+  __shared__ __attribute__((aligned(16))) float sT[CLM_RY * CLM_RX * CLM_TS];
+  const int b = blockIdx.z, y0 = blockIdx.y * CLM_TY, x0 = blockIdx.x * CLM_TX;
+  const size_t img = (size_t)b * H * W;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  // A operands: row r = tap r (rows 9..15 zero), K = channels 8g .. 8g + 7
+  bf16x8_t whi, wlo;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float v = r < 9 ? w[HS_W6 + (8 * g + e) * 9 + r] : 0.0f;
+    const __bf16 hi = (__bf16)v;
+    whi[e] = hi;
+    wlo[e] = (__bf16)(v - (float)hi);
+  }
+  for (int run = wave; run < CLM_RY * CLM_RUNS; run += 4) {
+    const int ry = run / CLM_RUNS, rc = (run - ry * CLM_RUNS) * 16;
+    const int gy = y0 + ry - 1, gx = x0 + rc + r - 1;
+    bf16x8_t a;
+    if (rc + r < CLM_RX && gy >= 0 && gy < H && gx >= 0 && gx < W)
+      a = *(const bf16x8_t*)(in + (img + (size_t)gy * W + gx) * 32 + 8 * g);
+    else
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a[e] = (__bf16)0.0f;
+    f32x4_t t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi, a, f32x4_t{0.f, 0.f, 0.f, 0.f},
+                                                         0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo, a, t, 0, 0, 0);
+    // lane (g, r) holds taps 4g .. 4g + 3 of position (ry, rc + r)
+    if (g < 3 && rc + r < CLM_RX) *(f32x4_t*)(sT + (ry * CLM_RX + rc + r) * CLM_TS + 4 * g) = t;
+  }
+  __syncthreads();
+  const float b6 = w[HS_B6];
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15, gy = y0 + ty;
+  if (gy >= H) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int cx = 4 * tx + k, gx = x0 + cx;
+    if (gx >= W) break;
+    float x = b6;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) x += sT[((ty + t / 3) * CLM_RX + cx + t % 3) * CLM_TS + t];
+    const size_t o = img + (size_t)gy * W + gx;
+    const float p = hs_sigmoid(x);
+    probs[o] = p;
+    if (bits) {
+      const float u = hs_action_u(seeds[b], (uint64_t)gy * W + gx, step);
+      if (lv.n == 1) {
+        bits[o] = u < p ? 1 : 0;
+      } else {
+        const float tl = p * (float)lv.n;
+        const int kf = min((int)floorf(tl), lv.n - 1);
+        bits[o] = (uint8_t)(kf + (u < tl - (float)kf ? 1 : 0));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Backward through the head and layer 6: g6 = dL/dlogit, and
 // g5[y][x][ci] = [a5 > 0] * sum_t W6[ci][t] g6[y - dy + 1][x - dx + 1].
 // ---------------------------------------------------------------------------
@@ -1046,8 +1123,8 @@ hipError_t launch_conv_last(const void* in, const float* w, int B, int H, int W,
       conv_last_kernel<__bf16, 0><<<grid, 256, 0, s>>>((const __bf16*)in, w, H, W, seeds, step,
                                                        bits, logits, probs, tau, list, count, lv);
     else
-      conv_last_kernel<__bf16, 1><<<grid, 256, 0, s>>>((const __bf16*)in, w, H, W, seeds, step,
-                                                       bits, logits, probs, tau, list, count, lv);
+      conv_last_mfma_kernel<<<dim3((W + CLM_TX - 1) / CLM_TX, (H + CLM_TY - 1) / CLM_TY, B), 256,
+                              0, s>>>((const __bf16*)in, w, H, W, seeds, step, bits, probs, lv);
   } else {
     if (mode == 0)
       conv_last_kernel<float, 0><<<grid, 256, 0, s>>>((const float*)in, w, H, W, seeds, step,
