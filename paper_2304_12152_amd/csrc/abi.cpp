@@ -232,11 +232,8 @@ hipError_t run_backward(const float* w, const float* grad, const float* probs, i
                         const FwdInput* in = nullptr) {
   hipError_t e;
   if ((e = launch_pack32(w, pw.packT, prec, 1, s)) != hipSuccess) return e;
-  if ((e = launch_dgrad_last(grad, probs, pw.act(4), w, B, H, W, prec, pw.g6, pw.gA, s)) !=
-      hipSuccess)
-    return e;
-  if ((e = launch_wgrad_last(pw.act(4), pw.g6, B, H, W, prec, pw.partials, accumulate, s)) !=
-      hipSuccess)
+  if ((e = launch_bwd_last(grad, probs, pw.act(4), w, B, H, W, prec, pw.g6, pw.gA, pw.partials,
+                           accumulate, s)) != hipSuccess)
     return e;
   const size_t per_layer = (size_t)PACK32_PER_LAYER * (prec == HS_BF16 ? 2 : 4);
   void* g = pw.gA;  // gradient at the pre-activation of layer k

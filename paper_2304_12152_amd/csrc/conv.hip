@@ -1042,6 +1042,135 @@ __global__ __launch_bounds__(256) void wgrad_last_kernel(const T* __restrict__ a
   }
 }
 
+// ---------------------------------------------------------------------------
+// Backward through the head and layer 6 in one pass (BF16 activations).
+// With G_t(q) = g6[q_y - dy + 1][q_x - dx + 1] for tap t = (dy, dx) (zero
+// outside the image), the input gradient
+//   g5[q][ci] = [a5[q][ci] > 0] sum_t W6[ci][t] G_t(q)
+// and the weight gradient, re-indexed by q = px + tap t,
+//   dW6[ci][t] = sum_px g6[px] a5[px + tap t][ci] = sum_q a5[q][ci] G_t(q)
+// take the same nine values of g6 around q and a5 at q only, so a5 is read
+// once and with no halo. A block takes 8 x 32 tiles in turn: the tile's g6
+// with a one-pixel halo is formed in LDS from dL/dp and p, and thread
+// (c4, seg) owns channels 4 c4 .. 4 c4 + 3 of the 8-pixel row segment seg,
+// with those channels' 36 weights and 36 weight-gradient sums in
+// registers, sliding the 3 x 3 window of g6 along the segment. The next
+// tile's loads are issued before this tile's arithmetic; the 32 segments'
+// sums are added in a fixed order at the end.
+// ---------------------------------------------------------------------------
+constexpr int BL_TY = 8, BL_TX = 32, BL_SEG = 8;               // tile rows, columns; segment
+constexpr int BL_GX = BL_TX + 2, BL_GN = (BL_TY + 2) * BL_GX;  // staged g6 with its halo
+constexpr int BL_GPT = (BL_GN + 255) / 256;                    // staged values per thread
+
+__global__ __launch_bounds__(256) void bwd_last_bf16_kernel(
+    const float* __restrict__ grad, const float* __restrict__ probs,
+    const __bf16* __restrict__ a5, const float* __restrict__ w, int B, int H, int W,
+    __bf16* __restrict__ g5, float* __restrict__ partials, int accumulate) {
+  __shared__ float sg[BL_GN];
+  __shared__ float sred[32][289];
+  const int tiles_x = (W + BL_TX - 1) / BL_TX, tiles_y = (H + BL_TY - 1) / BL_TY;
+  const int ntiles = B * tiles_x * tiles_y;
+  const int c4 = threadIdx.x & 7, seg = threadIdx.x >> 3;
+  const int ly = seg >> 2, lx0 = (seg & 3) * BL_SEG;
+  float wr[4][9], acc[4][9], accb = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      wr[k][t] = w[HS_W6 + (4 * c4 + k) * 9 + t];
+      acc[k][t] = 0.0f;
+    }
+  bf16x4_t av[BL_SEG];
+  float gq[BL_GPT], pq[BL_GPT];
+  auto load = [&](int tile) {
+    const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
+    const int y0 = (rem / tiles_x) * BL_TY, x0 = (rem % tiles_x) * BL_TX;
+    const size_t img = (size_t)b * H * W;
+#pragma unroll
+    for (int j = 0; j < BL_GPT; ++j) {
+      const int i = (int)threadIdx.x + 256 * j;
+      const int sy = i / BL_GX, sx = i - sy * BL_GX, gy = y0 + sy - 1, gx = x0 + sx - 1;
+      gq[j] = 0.0f;
+      pq[j] = 0.0f;
+      if (i < BL_GN && gy >= 0 && gy < H && gx >= 0 && gx < W) {
+        const size_t o = img + (size_t)gy * W + gx;
+        gq[j] = grad[o];
+        if (probs) pq[j] = probs[o];
+      }
+    }
+    const int gy = y0 + ly;
+#pragma unroll
+    for (int e = 0; e < BL_SEG; ++e) {
+      const int gx = x0 + lx0 + e;
+      av[e] = bf16x4_t{(__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f};
+      if (gy < H && gx < W)
+        av[e] = *(const bf16x4_t*)(a5 + (img + (size_t)gy * W + gx) * 32 + 4 * c4);
+    }
+  };
+  if ((int)blockIdx.x < ntiles) load(blockIdx.x);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
+    const int y0 = (rem / tiles_x) * BL_TY, x0 = (rem % tiles_x) * BL_TX;
+    const size_t img = (size_t)b * H * W;
+    __syncthreads();  // the previous tile's reads of sg are done
+#pragma unroll
+    for (int j = 0; j < BL_GPT; ++j) {
+      const int i = (int)threadIdx.x + 256 * j;
+      if (i < BL_GN) sg[i] = probs ? gq[j] * (pq[j] * (1.0f - pq[j])) : gq[j];
+    }
+    bf16x4_t cur[BL_SEG];
+#pragma unroll
+    for (int e = 0; e < BL_SEG; ++e) cur[e] = av[e];
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
+    // window columns lx .. lx + 2 of staged rows ly .. ly + 2; G_t = win[2 - dy][2 - dx]
+    float win[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) win[r][c + 1] = sg[(ly + r) * BL_GX + lx0 + c];
+    const int gy = y0 + ly;
+#pragma unroll
+    for (int e = 0; e < BL_SEG; ++e) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        win[r][0] = win[r][1];
+        win[r][1] = win[r][2];
+        win[r][2] = sg[(ly + r) * BL_GX + lx0 + e + 2];
+      }
+      float a[4], o[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a[k] = (float)cur[e][k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float x = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) x = fmaf(wr[k][t], win[2 - t / 3][2 - t % 3], x);
+        o[k] = a[k] > 0.0f ? x : 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[k][t] = fmaf(a[k], win[2 - t / 3][2 - t % 3], acc[k][t]);
+      }
+      accb += win[1][1];
+      const int gx = x0 + lx0 + e;
+      if (gy < H && gx < W)
+        hs_store4(g5 + (img + (size_t)gy * W + gx) * 32 + 4 * c4, o[0], o[1], o[2], o[3]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) sred[seg][(4 * c4 + k) * 9 + t] = acc[k][t];
+  if (c4 == 0) sred[seg][288] = accb;
+  __syncthreads();
+  for (int prm = threadIdx.x; prm <= 288; prm += blockDim.x) {
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) s += sred[k][prm];
+    float* d = partials + (size_t)blockIdx.x * hs::NPARAM + HS_W6 + prm;
+    *d = accumulate ? *d + s : s;
+  }
+}
+
 // Two-level fixed-order sum of the partial rows: group gi sums rows
 // gi, gi + G, gi + 2G, ... into tmp[gi]; then the G group sums in order.
 // rows: a multiple of WGRAD_BLOCKS (one set of rows per batch); the 32->32
@@ -1147,6 +1276,19 @@ hipError_t launch_dgrad_last(const float* grad, const float* probs, const void* 
     dgrad_last_kernel<float><<<grid, 256, 0, s>>>(grad, probs, (const float*)a5, w, H, W, g6,
                                                   (float*)g5);
   return hipGetLastError();
+}
+
+hipError_t launch_bwd_last(const float* grad, const float* probs, const void* a5, const float* w,
+                           int B, int H, int W, int precision, float* g6, void* g5,
+                           float* partials, int accumulate, hipStream_t s) {
+  if (precision == HS_BF16) {
+    bwd_last_bf16_kernel<<<WGRAD_BLOCKS, 256, 0, s>>>(grad, probs, (const __bf16*)a5, w, B, H, W,
+                                                      (__bf16*)g5, partials, accumulate);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_dgrad_last(grad, probs, a5, w, B, H, W, precision, g6, g5, s);
+  if (e != hipSuccess) return e;
+  return launch_wgrad_last(a5, g6, B, H, W, precision, partials, accumulate, s);
 }
 
 hipError_t launch_wgrad_first(const float* contone, const float* z, const void* g1, int B, int H,

@@ -191,6 +191,12 @@ hipError_t launch_recheck_cones(bool half, const float* w, const float* contone,
 hipError_t launch_dgrad_last(const float* grad, const float* probs, const void* a5,
                              const float* w, int B, int H, int W, int precision, float* g6,
                              void* g5, hipStream_t s);
+// The head's and layer 6's backward: the input gradient g5 as
+// launch_dgrad_last and the weight-gradient partial rows as
+// launch_wgrad_last (BF16: one pass that writes no g6; FP32: those two)
+hipError_t launch_bwd_last(const float* grad, const float* probs, const void* a5, const float* w,
+                           int B, int H, int W, int precision, float* g6, void* g5,
+                           float* partials, int accumulate, hipStream_t s);
 hipError_t launch_wgrad_first(const float* contone, const float* z, const void* g1, int B, int H,
                               int W, int precision, float* partials, int accumulate,
                               hipStream_t s);
