@@ -823,6 +823,161 @@ __global__ __launch_bounds__(FB_NT, 1) void bwd32_bf16_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Weight gradient of layer 1 (2 -> 32) on BF16 activations, on the matrix
+// cores: dW1[co][n] = sum_px g1[px][co] u_n(px), where column n = 9 ci + t
+// (n < 18) takes u_n(px) = in_ci[px + tap t] (ci 0 the contone, 1 the noise)
+// and column 18 takes u = 1 (the bias gradient). One MFMA sums over 32
+// pixels of a tile row. g1's pixel-major 16-byte fragments become
+// channel-major ones through an MFMA with a unit matrix (every output is a
+// single product by 1, so exact); the contone and noise values are split
+// into BF16 hi + lo parts (about 16 significant bits), staged in LDS as
+// one dword per value and position. A block takes 8 x 32 tiles in turn, wave
+// w rows 2w and 2w + 1, and loads the next tile during this one's work;
+// the four waves' sums are added in a fixed order at the end.
+// ---------------------------------------------------------------------------
+constexpr int WF_TY = 8, WF_TX = 32;
+constexpr int WF_SX = WF_TX + 2, WF_SN = (WF_TY + 2) * WF_SX;  // staged window with its halo
+constexpr int WF_SPT = (WF_SN + 255) / 256;                   // staged positions per thread
+
+__device__ __forceinline__ uint32_t split_bf16(float v) {
+  const __bf16 hi = (__bf16)v, lo = (__bf16)(v - (float)hi);
+  return (uint32_t)__builtin_bit_cast(unsigned short, hi) |
+         ((uint32_t)__builtin_bit_cast(unsigned short, lo) << 16);
+}
+
+__global__ __launch_bounds__(256) void wgrad_first_bf16_kernel(
+    const float* __restrict__ contone, const float* __restrict__ z,
+    const __bf16* __restrict__ g1, int B, int H, int W, float* __restrict__ partials,
+    int accumulate) {
+  __shared__ uint32_t sin[2][WF_SN];
+  __shared__ float sred[4][32 * 19];
+  const int tiles_x = (W + WF_TX - 1) / WF_TX, tiles_y = (H + WF_TY - 1) / WF_TY;
+  const int ntiles = B * tiles_x * tiles_y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  // unit B operands: channel tile c, lane (g, r) holds [8 g + j == 16 c + r]
+  bf16x8_t unit[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) unit[c][j] = (__bf16)(8 * g + j == 16 * c + r ? 1.0f : 0.0f);
+  // this lane's columns: n = r in column tile 0, n = 16 + r in tile 1
+  // (16, 17: the noise's taps 7, 8; 18: the bias; beyond: zero)
+  const int n1 = 16 + r;
+  const int ci0 = r / 9, t0 = r % 9, ci1 = n1 < 18 ? 1 : 0, t1 = n1 < 18 ? n1 - 9 : 0;
+  const int base0 = ci0 * WF_SN + (t0 / 3) * WF_SX + t0 % 3;
+  const int base1 = ci1 * WF_SN + (t1 / 3) * WF_SX + t1 % 3;
+  const uint32_t fixed1 = n1 == 18 ? (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)1.0f)
+                                   : 0u;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) acc[c][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  bf16x8_t gv[2][2];
+  float cv[WF_SPT], zv[WF_SPT];
+  auto load = [&](int tile) {
+    const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
+    const int y0 = (rem / tiles_x) * WF_TY, x0 = (rem % tiles_x) * WF_TX;
+    const size_t img = (size_t)b * H * W;
+#pragma unroll
+    for (int j = 0; j < WF_SPT; ++j) {
+      const int i = (int)threadIdx.x + 256 * j;
+      const int sy = i / WF_SX, sx = i - sy * WF_SX, gy = y0 + sy - 1, gx = x0 + sx - 1;
+      const bool in = i < WF_SN && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      cv[j] = in ? contone[img + (size_t)gy * W + gx] : 0.0f;
+      zv[j] = in ? z[img + (size_t)gy * W + gx] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int gy = y0 + 2 * wave + i, gx = x0 + 16 * h + r;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) gv[i][h][e] = (__bf16)0.0f;
+        if (gy < H && gx < W)
+          gv[i][h] = *(const bf16x8_t*)(g1 + (img + (size_t)gy * W + gx) * 32 + 8 * g);
+      }
+  };
+  if ((int)blockIdx.x < ntiles) load(blockIdx.x);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();  // the previous tile's reads of sin are done
+#pragma unroll
+    for (int j = 0; j < WF_SPT; ++j) {
+      const int i = (int)threadIdx.x + 256 * j;
+      if (i < WF_SN) {
+        sin[0][i] = split_bf16(cv[j]);
+        sin[1][i] = split_bf16(zv[j]);
+      }
+    }
+    bf16x8_t cur[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) cur[i][h] = gv[i][h];
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
+    const uint32_t* s0 = &sin[0][0];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      // K slot j of lane group g is pixel 4 g + j (j < 4) or 16 + 4 g + j - 4
+      bf16x8_t a[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const f32x4_t t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              cur[i][h], unit[c], f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) a[c][4 * h + e] = (__bf16)t[e];
+        }
+      }
+      const int row = (2 * wave + i) * WF_SX + 4 * g;
+      uint32_t d0[8], d1[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int p = row + (j < 4 ? j : 12 + j);
+        d0[j] = s0[base0 + p];
+        d1[j] = n1 < 18 ? s0[base1 + p] : fixed1;
+      }
+      bf16x8_t bh[2], bl[2];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        bh[0][j] = __builtin_bit_cast(__bf16, (unsigned short)(d0[j] & 0xffffu));
+        bl[0][j] = __builtin_bit_cast(__bf16, (unsigned short)(d0[j] >> 16));
+        bh[1][j] = __builtin_bit_cast(__bf16, (unsigned short)(d1[j] & 0xffffu));
+        bl[1][j] = __builtin_bit_cast(__bf16, (unsigned short)(d1[j] >> 16));
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+          acc[c][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], bh[nt], acc[c][nt], 0, 0, 0);
+          acc[c][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], bl[nt], acc[c][nt], 0, 0, 0);
+        }
+    }
+  }
+  // lane (g, r) of (c, nt) holds output channels 16 c + 4 g + e, column 16 nt + r
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int n = 16 * nt + r;
+      if (n <= 18)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sred[wave][(16 * c + 4 * g + e) * 19 + n] = acc[c][nt][e];
+    }
+  __syncthreads();
+  // W1[co][ci][t] at co * 18 + ci * 9 + t, then the biases at 576 + co
+  float* rowp = partials + (size_t)blockIdx.x * hs::NPARAM + HS_W1;
+  for (int q = threadIdx.x; q < 32 * 19; q += 256) {
+    const int co = q / 19, n = q - co * 19;
+    const float s = ((sred[0][q] + sred[1][q]) + sred[2][q]) + sred[3][q];
+    const int prm = n < 18 ? co * 18 + n : 576 + co;
+    rowp[prm] = accumulate ? rowp[prm] + s : s;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient of the first layer (2 -> 32) on the vector ALUs.
 // Tile = 16 x 16 pixels; thread i < 608 owns parameter i of layer 1.
 // ---------------------------------------------------------------------------
@@ -1295,8 +1450,8 @@ hipError_t launch_wgrad_first(const float* contone, const float* z, const void* 
                               int W, int precision, float* partials, int accumulate,
                               hipStream_t s) {
   if (precision == HS_BF16)
-    wgrad_first_kernel<__bf16><<<WGRAD_BLOCKS, 256, 0, s>>>(contone, z, (const __bf16*)g1, B, H,
-                                                            W, partials, accumulate);
+    wgrad_first_bf16_kernel<<<WGRAD_BLOCKS, 256, 0, s>>>(contone, z, (const __bf16*)g1, B, H, W,
+                                                         partials, accumulate);
   else
     wgrad_first_kernel<float><<<WGRAD_BLOCKS, 256, 0, s>>>(contone, z, (const float*)g1, B, H, W,
                                                            partials, accumulate);
