@@ -1280,7 +1280,9 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   // into its own partial rows) on a second stream, beside the batch's loss
   // kernels, which are bound by the vector ALUs and leave room for its small
   // launches; it starts after the batch's forward, and the batch waits for
-  // it before the partial sums are added
+  // it before the partial sums are added. The batch's loss kernels are
+  // launched first, so that its stream is not left idle while the host
+  // issues the side batch's many small launches.
   const int npatch = Bg * (Hg / 32) * (Wg / 32);
   SideStream* side = nullptr;
   std::unique_lock<std::mutex> side_lock;
@@ -1288,6 +1290,11 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
     if ((rc = side_stream(&side))) return rc;
     side_lock = std::unique_lock<std::mutex>(side->mu);
     HS_TRY(hipEventRecord(side->fork, s));
+  }
+  // batch: policy gradient (logit space)
+  HS_TRY(launch_loss_stats(act, contones, B, H, W, lp, win, lw.maps, lw.tiles, lw.ntiles, s));
+  HS_TRY(launch_le_grad(act, contones, probs, 1, B, H, W, lp, win, lw.maps, gradp, s));
+  if (Bg > 0) {
     HS_TRY(hipStreamWaitEvent(side->s, side->fork, 0));
     hipStream_t s2 = side->s;
     HS_TRY(run_forward_train(weights, gray, gray_seeds, Bg, Hg, Wg, kind, st, precision, pwg,
@@ -1299,9 +1306,7 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
     HS_TRY(run_backward(weights, gradg, nullptr, Bg, Hg, Wg, precision, pwg, 0, s2, &gin));
     HS_TRY(hipEventRecord(side->join, s2));
   }
-  // batch: policy gradient (logit space) and backward
-  HS_TRY(launch_loss_stats(act, contones, B, H, W, lp, win, lw.maps, lw.tiles, lw.ntiles, s));
-  HS_TRY(launch_le_grad(act, contones, probs, 1, B, H, W, lp, win, lw.maps, gradp, s));
+  // batch: backward
   const FwdInput fin{contones, seeds, kind, st};
   HS_TRY(run_backward(weights, gradp, nullptr, B, H, W, precision, pw, 0, s, &fin));
   if (Bg > 0) HS_TRY(hipStreamWaitEvent(s, side->join, 0));

@@ -314,6 +314,7 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T* __restrict__ in
 constexpr int CLM_TY = 16, CLM_TX = 64, CLM_RY = CLM_TY + 2, CLM_RX = CLM_TX + 2;
 constexpr int CLM_RUNS = (CLM_RX + 15) / 16;  // 16-pixel runs per halo row
 constexpr int CLM_TS = 12;                    // floats per position (taps 0..8, 3 unused)
+constexpr int CLM_WRUNS = (CLM_RY * CLM_RUNS + 3) / 4;  // runs per wave
 
 __global__ __launch_bounds__(256) void conv_last_mfma_kernel(const __bf16* __restrict__ in,
                                                              const float* __restrict__ w, int H,
@@ -336,20 +337,26 @@ __global__ __launch_bounds__(256) void conv_last_mfma_kernel(const __bf16* __res
     whi[e] = hi;
     wlo[e] = (__bf16)(v - (float)hi);
   }
-  for (int run = wave; run < CLM_RY * CLM_RUNS; run += 4) {
-    const int ry = run / CLM_RUNS, rc = (run - ry * CLM_RUNS) * 16;
-    const int gy = y0 + ry - 1, gx = x0 + rc + r - 1;
-    bf16x8_t a;
-    if (rc + r < CLM_RX && gy >= 0 && gy < H && gx >= 0 && gx < W)
-      a = *(const bf16x8_t*)(in + (img + (size_t)gy * W + gx) * 32 + 8 * g);
-    else
+  // all of a wave's runs are loaded before the first MFMA
+  bf16x8_t a[CLM_WRUNS];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) a[e] = (__bf16)0.0f;
-    f32x4_t t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi, a, f32x4_t{0.f, 0.f, 0.f, 0.f},
+  for (int k = 0; k < CLM_WRUNS; ++k) {
+    const int run = wave + 4 * k, ry = run / CLM_RUNS, rc = (run - ry * CLM_RUNS) * 16;
+    const int gy = y0 + ry - 1, gx = x0 + rc + r - 1;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) a[k][e] = (__bf16)0.0f;
+    if (run < CLM_RY * CLM_RUNS && rc + r < CLM_RX && gy >= 0 && gy < H && gx >= 0 && gx < W)
+      a[k] = *(const bf16x8_t*)(in + (img + (size_t)gy * W + gx) * 32 + 8 * g);
+  }
+#pragma unroll
+  for (int k = 0; k < CLM_WRUNS; ++k) {
+    const int run = wave + 4 * k, ry = run / CLM_RUNS, rc = (run - ry * CLM_RUNS) * 16;
+    f32x4_t t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(whi, a[k], f32x4_t{0.f, 0.f, 0.f, 0.f},
                                                          0, 0, 0);
-    t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo, a, t, 0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo, a[k], t, 0, 0, 0);
     // lane (g, r) holds taps 4g .. 4g + 3 of position (ry, rc + r)
-    if (g < 3 && rc + r < CLM_RX) *(f32x4_t*)(sT + (ry * CLM_RX + rc + r) * CLM_TS + 4 * g) = t;
+    if (run < CLM_RY * CLM_RUNS && g < 3 && rc + r < CLM_RX)
+      *(f32x4_t*)(sT + (ry * CLM_RX + rc + r) * CLM_TS + 4 * g) = t;
   }
   __syncthreads();
   const float b6 = w[HS_B6];
@@ -1336,9 +1343,24 @@ __global__ void reduce_partials_kernel(const float* __restrict__ partials, int r
   const int p = blockIdx.x * blockDim.x + threadIdx.x, gi = blockIdx.y;
   if (p >= hs::NPARAM) return;
   const bool l32 = p >= hs_wk(2) && p < hs_bk(5) + 32;
+  constexpr int G = hs::REDUCE_GROUPS;
+  const float* col = partials + p;
   float s = 0.0f;
-  for (int r = gi; r < rows; r += hs::REDUCE_GROUPS)
-    if (!l32 || r % hs::WGRAD_BLOCKS < rows32) s += partials[(size_t)r * hs::NPARAM + p];
+  // rows gi, gi + G, ... of each set in increasing order, four loads in flight
+  for (int set = 0; set < rows; set += hs::WGRAD_BLOCKS) {
+    const int end = set + (l32 ? rows32 : hs::WGRAD_BLOCKS);
+    int r = set + gi;
+    for (; r + 3 * G < end; r += 4 * G) {
+      const float a = col[(size_t)r * hs::NPARAM], b = col[(size_t)(r + G) * hs::NPARAM];
+      const float c = col[(size_t)(r + 2 * G) * hs::NPARAM];
+      const float d = col[(size_t)(r + 3 * G) * hs::NPARAM];
+      s += a;
+      s += b;
+      s += c;
+      s += d;
+    }
+    for (; r < end; r += G) s += col[(size_t)r * hs::NPARAM];
+  }
   tmp[(size_t)gi * hs::NPARAM + p] = s;
 }
 
@@ -1495,6 +1517,8 @@ int bwd32_grid(int num_cus) {
 
 hipError_t launch_reduce_partials(const float* partials, int rows, int rows32, float* tmp,
                                   float* grad, hipStream_t s) {
+  if (rows <= 0 || rows % WGRAD_BLOCKS != 0 || rows32 <= 0 || rows32 > WGRAD_BLOCKS)
+    return hipErrorInvalidValue;
   reduce_partials_kernel<<<dim3((NPARAM + 255) / 256, REDUCE_GROUPS), 256, 0, s>>>(
       partials, rows, rows32, tmp);
   reduce_groups_kernel<<<(NPARAM + 255) / 256, 256, 0, s>>>(tmp, grad);
