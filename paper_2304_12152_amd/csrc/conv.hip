@@ -160,6 +160,133 @@ __global__ __launch_bounds__(256) void conv32_kernel(const T* __restrict__ in,
 }
 
 // ---------------------------------------------------------------------------
+// The forward 32 -> 32 layer on BF16 activations as a persistent kernel: the
+// tiles, fragments and MFMA order of conv32_kernel (each output sums its taps
+// t = 0..8 in order, bias first), with the layer's 18 weight fragments and
+// the lane's biases held in registers for the whole kernel and the next
+// tile's loads issued before this tile's matrix work, so that the loads of
+// one tile overlap the MFMAs of the previous one. Staging is arranged to cost
+// few vector instructions: thread (column sc, chunk c) loads column sc of
+// the tile's ten staged rows (threads < 80 also one of the two extra
+// columns) from clamped, always valid addresses, and positions outside the
+// image are zeroed when the registers are stored to LDS; the row checks
+// are uniform over the block. Two blocks per CU.
+// ---------------------------------------------------------------------------
+constexpr int CF_BLOCKS = 512;  // 2 per CU on 256 CUs
+
+__global__ __launch_bounds__(256, 2) void conv32_fwd_bf16_kernel(
+    const __bf16* __restrict__ in, const __bf16* __restrict__ wp, const float* __restrict__ bias,
+    __bf16* __restrict__ out, int B, int H, int W) {
+  constexpr int RPW = conv_rows<__bf16>::RPW, CT_H = conv_rows<__bf16>::CT_H;
+  constexpr int CL_H = conv_rows<__bf16>::CL_H;
+  constexpr int NEX = CL_H * 2 * 4;  // chunks of the two extra columns
+  static_assert(CT_W == 64 && CL_W == 66 && NEX <= 256, "staging assumes 64 + 2 columns");
+  __shared__ __attribute__((aligned(16))) __bf16 lds[CL_H * CL_W * 32];
+  const int tiles_x = (W + CT_W - 1) / CT_W, tiles_y = (H + CT_H - 1) / CT_H;
+  const int ntiles = B * tiles_x * tiles_y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  frag8<__bf16> wf[9][2];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) hs_load_frag(wf[t][m], wp + ((t * 2 + m) * 64 + lane) * 8);
+  float bv[2][4];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bv[m][i] = bias[16 * m + 4 * g + i];
+  // staging geometry (element offsets in LDS of staged row 0)
+  const int c = threadIdx.x & 3, sc = threadIdx.x >> 2;
+  const int st_off = sc * 32 + hs_swz<__bf16>(sc, c) * 8;
+  const bool has_ex = (int)threadIdx.x < NEX;
+  const int ex_ly = (int)threadIdx.x >> 3, ex_lx = CT_W + (((int)threadIdx.x >> 2) & 1);
+  const int ex_off = (ex_ly * CL_W + ex_lx) * 32 + hs_swz<__bf16>(ex_lx, c) * 8;
+  // B-fragment offsets of this lane for dx = 0, 1, 2 (the swizzle depends on
+  // the column's bits 1..2, which the run offset n * 16 leaves alone)
+  int boff[3];
+#pragma unroll
+  for (int dx = 0; dx < 3; ++dx) boff[dx] = (r + dx) * 32 + hs_swz<__bf16>(r + dx, g) * 8;
+  uint4 v[CL_H], vx;
+  auto load = [&](int tile) {
+    const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
+    const int y0 = (rem / tiles_x) * CT_H, x0 = (rem % tiles_x) * CT_W;
+    const __bf16* base = in + (size_t)b * H * W * 32 + c * 8;
+    const int gxc = min(max(x0 + sc - 1, 0), W - 1);
+#pragma unroll
+    for (int ly = 0; ly < CL_H; ++ly) {
+      const int gyc = min(max(y0 + ly - 1, 0), H - 1);
+      v[ly] = *(const uint4*)(base + ((size_t)gyc * W + gxc) * 32);
+    }
+    const int eyc = min(max(y0 + ex_ly - 1, 0), H - 1), exc = min(x0 + ex_lx - 1, W - 1);
+    vx = *(const uint4*)(base + ((size_t)eyc * W + exc) * 32);
+  };
+  if ((int)blockIdx.x < ntiles) load(blockIdx.x);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
+    const int y0 = (rem / tiles_x) * CT_H, x0 = (rem % tiles_x) * CT_W;
+    __syncthreads();  // the previous tile's LDS reads are done
+    {
+      const int gx = x0 + sc - 1;
+      const bool xin = gx >= 0 && gx < W;
+#pragma unroll
+      for (int ly = 0; ly < CL_H; ++ly) {
+        const int gy = y0 + ly - 1;
+        const bool in_img = xin && gy >= 0 && gy < H;
+        const uint32_t k = in_img ? ~0u : 0u;
+        *(uint4*)(lds + st_off + ly * CL_W * 32) =
+            make_uint4(v[ly].x & k, v[ly].y & k, v[ly].z & k, v[ly].w & k);
+      }
+      const int ey = y0 + ex_ly - 1, ex = x0 + ex_lx - 1;
+      const uint32_t k = (ey >= 0 && ey < H && ex < W) ? ~0u : 0u;
+      if (has_ex) *(uint4*)(lds + ex_off) = make_uint4(vx.x & k, vx.y & k, vx.z & k, vx.w & k);
+    }
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
+    f32x4_t acc[RPW][2][4];
+#pragma unroll
+    for (int q = 0; q < RPW; ++q)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[q][m][n] = f32x4_t{bv[m][0], bv[m][1], bv[m][2], bv[m][3]};
+#pragma unroll
+    for (int d = 0; d < RPW + 2; ++d) {
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          frag8<__bf16> bf;
+          bf.v = *(const bf16x8_t*)(lds + boff[dx] + ((RPW * wave + d) * CL_W + n * 16) * 32);
+#pragma unroll
+          for (int q = 0; q < RPW; ++q) {
+            const int dy = d - q;
+            if (dy < 0 || dy > 2) continue;
+            acc[q][0][n] = hs_mma(wf[dy * 3 + dx][0], bf, acc[q][0][n]);
+            acc[q][1][n] = hs_mma(wf[dy * 3 + dx][1], bf, acc[q][1][n]);
+          }
+        }
+      }
+    }
+    const bool full_x = x0 + CT_W <= W;
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {
+      const int gy = y0 + RPW * wave + q;
+      if (gy >= H) break;
+      __bf16* rowp = out + (((size_t)b * H + gy) * W + x0 + r) * 32 + 4 * g;
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        if (!full_x && x0 + n * 16 + r >= W) continue;
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+          hs_store4(rowp + n * 16 * 32 + 16 * m, fmaxf(acc[q][m][n][0], 0.0f),
+                    fmaxf(acc[q][m][n][1], 0.0f), fmaxf(acc[q][m][n][2], 0.0f),
+                    fmaxf(acc[q][m][n][3], 0.0f));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // First layer 2 -> 32 on the state s = (c, z); z from Philox stream 1.
 // 16 x 16 pixel tile per block, one pixel per thread, 32 outputs each.
 // ---------------------------------------------------------------------------
@@ -218,6 +345,99 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float* __restrict
   for (int co = 0; co < 32; co += 4)
     hs_store4(o + co, fmaxf(acc[co], 0.f), fmaxf(acc[co + 1], 0.f), fmaxf(acc[co + 2], 0.f),
               fmaxf(acc[co + 3], 0.f));
+}
+
+// ---------------------------------------------------------------------------
+// First layer 2 -> 32 of the training forward on BF16 activations, on the
+// FP32 matrix cores: a1[px][co] = relu(sum_k W[co][k] U[k][px]), where column
+// k = 9 ci + t (k < 18) takes U = s_ci[px + tap t] (s_0 the contone, s_1 the
+// noise z of Philox stream 1), column 18 takes U = 1 against the bias and
+// column 19 is zero: five K-steps of four. The products are FP32 as in the
+// per-pixel form, so the BF16 rounding of a1 sees the same values up to
+// FP32 summation order. The weight rows are permuted so that lane (g, r) of
+// the two results holds channels 8 g .. 8 g + 7 of pixel r: one 16-byte
+// store. A block computes 16 x 64 pixels from the state of its 18 x 66
+// window, staged in LDS.
+// ---------------------------------------------------------------------------
+constexpr int CFM_TY = 16, CFM_TX = 64, CFM_SX = CFM_TX + 2, CFM_SN = (CFM_TY + 2) * CFM_SX;
+constexpr int CFM_RUNS = CFM_TY * CFM_TX / 16 / 4;  // 16-pixel runs per wave
+
+__global__ __launch_bounds__(256) void conv_first_mfma_kernel(
+    const float* __restrict__ contone, const uint64_t* __restrict__ seeds,
+    const float* __restrict__ w, int H, int W, int kind, uint32_t step,
+    __bf16* __restrict__ out, float* __restrict__ zout, float* __restrict__ cout) {
+  __shared__ float sst[2 * CFM_SN + 2];  // contone, noise; then the constants 1 and 0
+  const int b = blockIdx.z, y0 = blockIdx.y * CFM_TY, x0 = blockIdx.x * CFM_TX;
+  const size_t img = (size_t)b * H * W;
+  const uint64_t seed = seeds[b];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  // K-step q: lane (g, r) holds A[r][k] and B[k][r] with k = 4 q + g; row r of
+  // tile c is channel 8 (r / 4) + 4 c + r % 4
+  float wa[2][5];
+  int off[5], stp[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const int k = 4 * q + g, ci = k / 9, t = k - 9 * ci;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int co = 8 * (r >> 2) + 4 * c + (r & 3);
+      wa[c][q] = k < 18 ? w[HS_W1 + co * 18 + k] : k == 18 ? w[HS_B1 + co] : 0.0f;
+    }
+    off[q] = k < 18 ? ci * CFM_SN + (t / 3) * CFM_SX + t % 3 : k == 18 ? 2 * CFM_SN : 2 * CFM_SN + 1;
+    stp[q] = k < 18 ? 1 : 0;
+  }
+  for (int i = threadIdx.x; i < CFM_SN; i += 256) {
+    const int sy = i / CFM_SX, sx = i - sy * CFM_SX, gy = y0 + sy - 1, gx = x0 + sx - 1;
+    float cv = 0.0f, zv = 0.0f;
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+      const uint64_t a = (uint64_t)gy * W + gx;
+      cv = contone[img + a];
+      zv = hs_noise<true>(seed, a, step, kind);
+      if (sy >= 1 && sy <= CFM_TY && sx >= 1 && sx <= CFM_TX) {
+        if (zout) zout[img + a] = zv;
+        if (cout) cout[img + a] = cv;
+      }
+    }
+    sst[i] = cv;
+    sst[CFM_SN + i] = zv;
+  }
+  if (threadIdx.x == 0) {
+    sst[2 * CFM_SN] = 1.0f;
+    sst[2 * CFM_SN + 1] = 0.0f;
+  }
+  __syncthreads();
+#pragma unroll 2
+  for (int n = 0; n < CFM_RUNS; ++n) {
+    const int run = wave + 4 * n, ly = run >> 2, lx = (run & 3) * 16 + r;
+    const int pos = ly * CFM_SX + lx;
+    float u[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) u[q] = sst[off[q] + pos * stp[q]];
+    f32x4_t acc[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      acc[c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[c][q], u[q], acc[c], 0, 0, 0);
+    }
+    const int gy = y0 + ly, gx = x0 + lx;
+    if (gy < H && gx < W) {
+      bf16x8_t o;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        o[e] = (__bf16)fmaxf(acc[0][e], 0.0f);
+        o[4 + e] = (__bf16)fmaxf(acc[1][e], 0.0f);
+      }
+      *(bf16x8_t*)(out + (img + (size_t)gy * W + gx) * 32 + 8 * g) = o;
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t split_bf16(float v) {
+  const __bf16 hi = (__bf16)v, lo = (__bf16)(v - (float)hi);
+  return (uint32_t)__builtin_bit_cast(unsigned short, hi) |
+         ((uint32_t)__builtin_bit_cast(unsigned short, lo) << 16);
 }
 
 // ---------------------------------------------------------------------------
@@ -846,12 +1066,6 @@ constexpr int WF_TY = 8, WF_TX = 32;
 constexpr int WF_SX = WF_TX + 2, WF_SN = (WF_TY + 2) * WF_SX;  // staged window with its halo
 constexpr int WF_SPT = (WF_SN + 255) / 256;                   // staged positions per thread
 
-__device__ __forceinline__ uint32_t split_bf16(float v) {
-  const __bf16 hi = (__bf16)v, lo = (__bf16)(v - (float)hi);
-  return (uint32_t)__builtin_bit_cast(unsigned short, hi) |
-         ((uint32_t)__builtin_bit_cast(unsigned short, lo) << 16);
-}
-
 __global__ __launch_bounds__(256) void wgrad_first_bf16_kernel(
     const float* __restrict__ contone, const float* __restrict__ z,
     const __bf16* __restrict__ g1, int B, int H, int W, float* __restrict__ partials,
@@ -1391,8 +1605,9 @@ hipError_t launch_conv_first(const float* contone, const uint64_t* seeds, const 
                              int H, int W, int kind, uint32_t step, int precision, void* out,
                              float* zout, float* cout, hipStream_t s) {
   if (precision == HS_BF16)
-    conv_first_kernel<__bf16><<<tiles16(B, H, W), 256, 0, s>>>(contone, seeds, w, H, W, kind,
-                                                               step, (__bf16*)out, zout, cout);
+    conv_first_mfma_kernel<<<dim3((W + CFM_TX - 1) / CFM_TX, (H + CFM_TY - 1) / CFM_TY, B), 256,
+                             0, s>>>(contone, seeds, w, H, W, kind, step, (__bf16*)out, zout,
+                                     cout);
   else
     conv_first_kernel<float><<<tiles16(B, H, W), 256, 0, s>>>(contone, seeds, w, H, W, kind,
                                                               step, (float*)out, zout, cout);
@@ -1406,8 +1621,9 @@ hipError_t launch_conv32(const void* in, const void* wpack, const float* bias, c
   if (precision == HS_BF16) {
     // the input gradient of a BF16 layer comes from the fused backward
     if (mode != 0) return hipErrorInvalidValue;
-    conv32_kernel<__bf16, 0><<<grid, 256, 0, s>>>((const __bf16*)in, (const __bf16*)wpack, bias,
-                                                  nullptr, (__bf16*)out, H, W);
+    const int ntiles = (int)(grid.x * grid.y * grid.z);
+    conv32_fwd_bf16_kernel<<<ntiles < CF_BLOCKS ? ntiles : CF_BLOCKS, 256, 0, s>>>(
+        (const __bf16*)in, (const __bf16*)wpack, bias, (__bf16*)out, B, H, W);
   } else {
     if (mode == 0)
       conv32_kernel<float, 0><<<grid, 256, 0, s>>>((const float*)in, (const float*)wpack, bias,
