@@ -843,40 +843,43 @@ __global__ __launch_bounds__(FB_NT, 1) void bwd32_bf16_kernel(
   for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
   // staging operation k of this thread, the same for every tile: kind (0
   // none, 1 g, 2 a, 3 halo chunk of g), source row and first column
-  // relative to (y0, x0), channel group. Decoded where it is used from a
-  // thread number the compiler cannot hoist (a volatile copy), which keeps
-  // twelve registers free across the tile loop.
+  // relative to (y0, x0), channel group. Thread t: operation 0 is g at row
+  // t / 64 - 1, columns 4 ((t / 4) % 16) + 0..3, channel group t % 4;
+  // operation 1 is a at the same row and channel group, columns one to the
+  // left; operation 2 covers the rest (g and a at rows 7 and 8, a's last
+  // column group, g's halo chunks). Decoded where it is used from a thread
+  // number the compiler cannot hoist (a volatile copy), which keeps registers
+  // free across the tile loop.
   struct Op {
     int kind, row, col, c8;
   };
   auto op = [&](int k) {
     int q;
     asm volatile("v_mov_b32 %0, %1" : "=v"(q) : "v"(tid));
-    q += FB_NT * k;
-    Op o{0, 0, 0, 0};
-    if (q < FB_GOPS) {
-      o.kind = 1;
-      o.c8 = q & 3;
-      q >>= 2;
-      o.col = 4 * (q % (FB_W / 4));
-      o.row = q / (FB_W / 4) - 1;
-    } else if (q < FB_GOPS + FB_HOPS) {
-      q -= FB_GOPS;
-      o.kind = 3;
-      o.c8 = q & 3;
-      q >>= 2;
-      o.col = (q & 1) ? FB_W : -1;
-      o.row = (q >> 1) - 1;
-    } else if (q < FB_OPS) {
-      q -= FB_GOPS + FB_HOPS;
+    Op o{0, 0, 0, q & 3};
+    const int cg = (q >> 2) & 15;
+    if (k < 2) {
+      o.kind = k + 1;
+      o.row = (q >> 6) - 1;
+      o.col = 4 * cg - k;
+    } else if (q < 256) {
+      o.kind = q < 128 ? 1 : 2;
+      o.row = 7 + ((q >> 6) & 1);
+      o.col = 4 * cg - (q < 128 ? 0 : 1);
+    } else if (q < 296) {
       o.kind = 2;
-      o.c8 = q & 3;
-      q >>= 2;
-      o.col = 4 * (q % (FB_AC / 4)) - 1;
-      o.row = q / (FB_AC / 4) - 1;
+      o.row = ((q - 256) >> 2) - 1;
+      o.col = FB_AC - 5;
+    } else if (q < 376) {
+      q -= 296;
+      o.kind = 3;
+      o.col = ((q >> 2) & 1) ? FB_W : -1;
+      o.row = (q >> 3) - 1;
     }
     return o;
   };
+  // loads from clamped (always valid) addresses; positions outside the image
+  // are zeroed when the registers are stored to LDS
   bf16x8_t v[FB_NOP][4];
   auto load = [&](int tile) {
     const int b = tile / (tiles_x * tiles_y), rem = tile - b * tiles_x * tiles_y;
@@ -885,45 +888,53 @@ __global__ __launch_bounds__(FB_NT, 1) void bwd32_bf16_kernel(
 #pragma unroll
     for (int k = 0; k < FB_NOP; ++k) {
       const Op o = op(k);
-      const __bf16* src = o.kind == 2 ? a_in : g_out;
-      const int gy = y0 + o.row;
+      if (o.kind == 0) continue;
+      const __bf16* src = (o.kind == 2 ? a_in : g_out) + img * 32 + 8 * o.c8;
+      const int gyc = min(max(y0 + o.row, 0), H - 1);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int gx = x0 + o.col + u;
-        const bool used = o.kind != 0 && (u == 0 || o.kind != 3);
-        if (used && gy >= 0 && gy < H && gx >= 0 && gx < W)
-          v[k][u] = *(const bf16x8_t*)(src + (img + (size_t)gy * W + gx) * 32 + 8 * o.c8);
-        else
-#pragma unroll
-          for (int e = 0; e < 8; ++e) v[k][u][e] = (__bf16)0.0f;
+        const int gxc = min(max(x0 + o.col + u, 0), W - 1);
+        v[k][u] = *(const bf16x8_t*)(src + ((size_t)gyc * W + gxc) * 32);
       }
     }
   };
-  auto store = [&]() {
+  auto store = [&](int y0, int x0, auto masked) {
+    bf16x8_t zero;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) zero[e] = (__bf16)0.0f;
 #pragma unroll
     for (int k = 0; k < FB_NOP; ++k) {
       const Op o = op(k);
       const int row = o.row + 1, c8 = o.c8;
+      bf16x8_t w4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        w4[u] = v[k][u];
+        if (decltype(masked)::value) {
+          const bool ok = (unsigned)(y0 + o.row) < (unsigned)H &&
+                          (unsigned)(x0 + o.col + u) < (unsigned)W;
+          w4[u] = ok ? w4[u] : zero;
+        }
+      }
       if (o.kind == 1 || o.kind == 3) {
         const int nu = o.kind == 1 ? 4 : 1;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           if (u >= nu) break;
           const int lx = o.col + u + 1;
-          *(bf16x8_t*)(gP + (row * FB_LW + lx) * 32 + hs_swz<__bf16>(lx, c8) * 8) = v[k][u];
+          *(bf16x8_t*)(gP + (row * FB_LW + lx) * 32 + hs_swz<__bf16>(lx, c8) * 8) = w4[u];
         }
         if (o.kind == 1 && row >= 1 && row <= FB_H) {
           __bf16* base = gT + (8 * c8) * FB_GS + (row - 1) * FB_W + o.col;
 #pragma unroll
           for (int e = 0; e < 8; ++e)
-            *(bf16x4_t*)(base + e * FB_GS) =
-                bf16x4_t{v[k][0][e], v[k][1][e], v[k][2][e], v[k][3][e]};
+            *(bf16x4_t*)(base + e * FB_GS) = bf16x4_t{w4[0][e], w4[1][e], w4[2][e], w4[3][e]};
         }
       } else if (o.kind == 2) {
         __bf16* base = aT + (8 * c8) * FB_CS + row * FB_RS + (o.col + 1);
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-          *(bf16x4_t*)(base + e * FB_CS) = bf16x4_t{v[k][0][e], v[k][1][e], v[k][2][e], v[k][3][e]};
+          *(bf16x4_t*)(base + e * FB_CS) = bf16x4_t{w4[0][e], w4[1][e], w4[2][e], w4[3][e]};
       }
     }
   };
@@ -933,7 +944,11 @@ __global__ __launch_bounds__(FB_NT, 1) void bwd32_bf16_kernel(
     const int y0 = (rem / tiles_x) * FB_H, x0 = (rem % tiles_x) * FB_W;
     const size_t img = (size_t)b * H * W;
     __syncthreads();  // the previous tile's operands have been read
-    store();
+    // a tile whose staged window lies inside the image needs no zeroing
+    if (y0 >= 1 && y0 + FB_H + 1 <= H && x0 >= 1 && x0 + FB_AC - 1 <= W)
+      store(y0, x0, std::false_type{});
+    else
+      store(y0, x0, std::true_type{});
     __syncthreads();
     if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
     // ---- input gradient, row `wave` of the tile: input row wave + d of gP
