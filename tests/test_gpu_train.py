@@ -206,11 +206,14 @@ def _tap_errors(g, ref, k):
 
 def _multi_tile_case(orc, precision, seed0):
     """One TRAIN iteration on 8 x 256 x 256 crops plus 8 constant grays of
-    64 x 64 against the oracle's, given the GPU's actions. The weight-gradient
-    kernels run 512 blocks that stride over tiles: 4,096 tiles of 2 x 64
-    pixels (8 per block) for the 32->32 layers and 2,048 of 16 x 16 (4 per
-    block) for the first and last layers, so every block goes through its
-    tile loop, with the next tile's loads in flight, several times."""
+    64 x 64 against the oracle's, given the GPU's actions. The persistent
+    kernels stride over tiles with the next tile's loads in flight, and every
+    block goes through that loop more than once: in FP32 the weight
+    gradients' 512 blocks (4,096 tiles of 2 x 64 pixels for the 32->32
+    layers, 2,048 of 16 x 16 for the first and last layers); in BF16 the
+    forward 32->32 layer (1,024 tiles of 8 x 64 over 512 blocks), the fused
+    32->32 backward (1,024 over 256 blocks), and the head's backward and the
+    first layer's weight gradient (2,048 tiles of 8 x 32 over 512 blocks)."""
     B, H, W = 8, 256, 256
     seeds = list(range(seed0, seed0 + B))
     w = synth.he_weights(5, head_std=0.01)
