@@ -143,7 +143,7 @@ PolicyWs carve_policy(Carve& cv, size_t N, int prec, bool recompute = false,
   w.c = cv.take<float>(N * 4);
   w.g6 = cv.take<float>(N * 4);
   w.partials = partials ? partials : cv.take<float>((size_t)rows * NPARAM * 4);
-  w.rtmp = cv.take<float>((size_t)REDUCE_GROUPS * NPARAM * 4);
+  w.rtmp = cv.take<float>(((size_t)REDUCE_GROUPS * NPARAM + REDUCE_BLOCKS) * 4);
   w.counter = cv.take<unsigned long long>(64);
   return w;
 }
@@ -1155,7 +1155,7 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
 // record / wait / launch sequence on them whole.
 struct SideStream {
   hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, stats = nullptr;
   std::mutex mu;
 };
 static int side_stream(SideStream** out) {
@@ -1169,7 +1169,8 @@ static int side_stream(SideStream** out) {
     SideStream* ss = new SideStream;
     if (hipStreamCreateWithFlags(&ss->s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ss->join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ss->join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ss->stats, hipEventDisableTiming) != hipSuccess) {
       delete ss;
       return fail(HS_EHIP, "policy_train_step: creating the side stream failed");
     }
@@ -1293,15 +1294,24 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   }
   // batch: policy gradient (logit space)
   HS_TRY(launch_loss_stats(act, contones, B, H, W, lp, win, lw.maps, lw.tiles, lw.ntiles, s));
+  if (Bg > 0) HS_TRY(hipEventRecord(side->stats, s));
   HS_TRY(launch_le_grad(act, contones, probs, 1, B, H, W, lp, win, lw.maps, gradp, s));
+  const long M = (long)(H - 2 * m) * (W - 2 * m);
+  const size_t nact = (size_t)B * H * W;
   if (Bg > 0) {
+    // the second stream also takes the reported metrics' action count and
+    // the loss sums (after the batch's statistics), off the batch's path
     HS_TRY(hipStreamWaitEvent(side->s, side->fork, 0));
     hipStream_t s2 = side->s;
+    HS_TRY(launch_count_actions(act, nact, pw.counter, s2));
     HS_TRY(run_forward_train(weights, gray, gray_seeds, Bg, Hg, Wg, kind, st, precision, pwg,
                              probs_g, nullptr, lp.levels, s2));
     HS_TRY(launch_fill(gradg, (size_t)Bg * Hg * Wg, 0.0f, s2));
     if (npatch > 0)
       HS_TRY(launch_as(probs_g, Bg, Hg, Wg, lp.w_a / (float)npatch, 1, lw.patches, gradg, s2));
+    HS_TRY(hipStreamWaitEvent(s2, side->stats, 0));
+    HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, lp.w_s, M, loss_out,
+                              s2));
     const FwdInput gin{gray, gray_seeds, kind, st};
     HS_TRY(run_backward(weights, gradg, nullptr, Bg, Hg, Wg, precision, pwg, 0, s2, &gin));
     HS_TRY(hipEventRecord(side->join, s2));
@@ -1313,8 +1323,11 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   HS_TRY(launch_reduce_partials(pw.partials, Bg > 0 ? 2 * WGRAD_BLOCKS : WGRAD_BLOCKS,
                                 precision == HS_BF16 ? bwd32_grid(num_cus()) : WGRAD_BLOCKS,
                                 pw.rtmp, grad, s));
-  HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, lp.w_s,
-                            (long)(H - 2 * m) * (W - 2 * m), loss_out, s));
+  if (Bg == 0) {
+    HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, lp.w_s, M, loss_out,
+                              s));
+    HS_TRY(launch_count_actions(act, nact, pw.counter, s));
+  }
   // Adam with the cosine learning rate of this step, bias corrections at t = step + 1
   const double T = (double)total_steps;
   const double lr = T > 0 ? tp->lr_min + 0.5 * ((double)tp->lr_max - tp->lr_min) *
@@ -1324,8 +1337,8 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   const double c2 = 1.0 - pow((double)tp->beta2, (double)(step + 1));
   if (grad_out_or_null)
     HS_TRY(hipMemcpyAsync(grad_out_or_null, grad, (size_t)NPARAM * 4, hipMemcpyDeviceToDevice, s));
-  HS_TRY(launch_train_metrics(loss_out, B, grad, NPARAM, act, (size_t)B * H * W, lp.levels,
-                              (float)lr, lp.w_a, metrics, pw.counter, s));
+  HS_TRY(launch_train_metrics(loss_out, B, pw.rtmp + (size_t)REDUCE_GROUPS * NPARAM,
+                              pw.counter, nact, lp.levels, (float)lr, lp.w_a, metrics, s));
   HS_TRY(launch_adam(weights, adam_m, adam_v, grad, NPARAM, (float)lr, tp->beta1, tp->beta2,
                      tp->eps, (float)c1, (float)c2, s));
   if (actions_out_or_null)

@@ -1593,12 +1593,23 @@ __global__ void reduce_partials_kernel(const float* __restrict__ partials, int r
   tmp[(size_t)gi * hs::NPARAM + p] = s;
 }
 
-__global__ void reduce_groups_kernel(const float* __restrict__ tmp, float* __restrict__ grad) {
+// also the block's sum of grad^2 into gsq[blockIdx.x] (waves in order)
+__global__ __launch_bounds__(256) void reduce_groups_kernel(const float* __restrict__ tmp,
+                                                            float* __restrict__ grad,
+                                                            float* __restrict__ gsq) {
+  __shared__ float part[4];
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= hs::NPARAM) return;
   float s = 0.0f;
-  for (int gi = 0; gi < hs::REDUCE_GROUPS; ++gi) s += tmp[(size_t)gi * hs::NPARAM + p];
-  grad[p] = s;
+  if (p < hs::NPARAM) {
+    for (int gi = 0; gi < hs::REDUCE_GROUPS; ++gi) s += tmp[(size_t)gi * hs::NPARAM + p];
+    grad[p] = s;
+  }
+  float q = s * s;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) gsq[blockIdx.x] = ((part[0] + part[1]) + part[2]) + part[3];
 }
 
 inline dim3 tiles16(int B, int H, int W) { return dim3((W + 15) / 16, (H + 15) / 16, B); }
@@ -1752,7 +1763,8 @@ hipError_t launch_reduce_partials(const float* partials, int rows, int rows32, f
     return hipErrorInvalidValue;
   reduce_partials_kernel<<<dim3((NPARAM + 255) / 256, REDUCE_GROUPS), 256, 0, s>>>(
       partials, rows, rows32, tmp);
-  reduce_groups_kernel<<<(NPARAM + 255) / 256, 256, 0, s>>>(tmp, grad);
+  reduce_groups_kernel<<<REDUCE_BLOCKS, 256, 0, s>>>(tmp, grad,
+                                                     tmp + (size_t)REDUCE_GROUPS * NPARAM);
   return hipGetLastError();
 }
 

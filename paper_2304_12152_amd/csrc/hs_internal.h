@@ -210,8 +210,10 @@ hipError_t launch_wgrad32(const void* a_in, const void* g_out, int layer, int B,
 hipError_t launch_wgrad_last(const void* a5, const float* g6, int B, int H, int W, int precision,
                              float* partials, int accumulate, hipStream_t s);
 // sums `rows` rows of NPARAM partial sums in a fixed order; `tmp` holds
-// REDUCE_GROUPS * NPARAM floats
+// REDUCE_GROUPS * NPARAM + REDUCE_BLOCKS floats, the last REDUCE_BLOCKS of
+// which receive partial sums of grad^2 (launch_train_metrics' gsq)
 constexpr int REDUCE_GROUPS = 16;
+constexpr int REDUCE_BLOCKS = (NPARAM + 255) / 256;
 // the grid (and partial rows) of launch_bwd32 on a device with num_cus CUs
 int bwd32_grid(int num_cus);
 hipError_t launch_reduce_partials(const float* partials, int rows, int rows32, float* tmp,
@@ -243,10 +245,15 @@ hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
 // train.hip
 hipError_t launch_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1,
                        float b2, float eps, float c1, float c2, hipStream_t s);
-hipError_t launch_train_metrics(const float* loss_out, int B, const float* grad, int n,
-                                const uint8_t* actions, size_t nact, int levels, float lr,
-                                float w_a, float* metrics, unsigned long long* counter,
-                                hipStream_t s);
+// the number of actions' ones (levels: the sum of the level indices) into
+// *counter
+hipError_t launch_count_actions(const uint8_t* actions, size_t nact,
+                                unsigned long long* counter, hipStream_t s);
+// metrics[8] from the loss sums, the REDUCE_BLOCKS partial sums of grad^2
+// (gsq) and the action count (after launch_count_actions)
+hipError_t launch_train_metrics(const float* loss_out, int B, const float* gsq,
+                                const unsigned long long* counter, size_t nact, int levels,
+                                float lr, float w_a, float* metrics, hipStream_t s);
 
 // spectrum.hip
 int spectrum_rings(int P);

@@ -51,14 +51,13 @@ __global__ __launch_bounds__(256) void count_ones_kernel(const uint8_t* __restri
 // is the mean of h = action / (levels - 1)
 // one workgroup of 1024 threads: the gradient norm is a single pass of 37
 // loads per thread, summed per wave and then over the 16 waves in order
-__global__ __launch_bounds__(1024) void metrics_kernel(const float* __restrict__ loss_out, int B,
-                                                      const float* __restrict__ grad, int n,
-                                                      const unsigned long long* __restrict__ ones,
-                                                      size_t nact, int levels, float lr,
-                                                      float w_a, float* __restrict__ metrics) {
-  __shared__ float red[16];
-  float s = 0.0f;
-  for (int i = threadIdx.x; i < n; i += 1024) s = fmaf(grad[i], grad[i], s);
+__global__ __launch_bounds__(256) void metrics_kernel(const float* __restrict__ loss_out, int B,
+                                                     const float* __restrict__ gsq,
+                                                     const unsigned long long* __restrict__ ones,
+                                                     size_t nact, int levels, float lr,
+                                                     float w_a, float* __restrict__ metrics) {
+  __shared__ float red[4];
+  float s = threadIdx.x < hs::REDUCE_BLOCKS ? gsq[threadIdx.x] : 0.0f;
   s = hs_wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -75,7 +74,7 @@ __global__ __launch_bounds__(1024) void metrics_kernel(const float* __restrict__
   metrics[3] = loss_out[3 * B];
   metrics[4] = lr;
   float g2 = 0.0f;
-  for (int k = 0; k < 16; ++k) g2 += red[k];
+  for (int k = 0; k < 4; ++k) g2 += red[k];
   metrics[5] = sqrtf(g2);
   metrics[6] = (float)((double)*ones / ((double)nact * (levels - 1)));
   metrics[7] = -metrics[2] + w_a * metrics[3];
@@ -94,17 +93,21 @@ hipError_t launch_adam(float* w, float* m, float* v, const float* g, int n, floa
   return hipGetLastError();
 }
 
-hipError_t launch_train_metrics(const float* loss_out, int B, const float* grad, int n,
-                                const uint8_t* actions, size_t nact, int levels, float lr,
-                                float w_a, float* metrics, unsigned long long* counter,
-                                hipStream_t s) {
+hipError_t launch_count_actions(const uint8_t* actions, size_t nact,
+                                unsigned long long* counter, hipStream_t s) {
   zero_u64_kernel<<<1, 1, 0, s>>>(counter);
   size_t blocks = (nact / 16 + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 1024) blocks = 1024;
   count_ones_kernel<<<(unsigned)blocks, 256, 0, s>>>(actions, nact, counter);
-  metrics_kernel<<<1, 1024, 0, s>>>(loss_out, B, grad, n, counter, nact, levels, lr, w_a,
-                                    metrics);
+  return hipGetLastError();
+}
+
+hipError_t launch_train_metrics(const float* loss_out, int B, const float* gsq,
+                                const unsigned long long* counter, size_t nact, int levels,
+                                float lr, float w_a, float* metrics, hipStream_t s) {
+  static_assert(REDUCE_BLOCKS <= 256, "one block sums the partial sums of grad^2");
+  metrics_kernel<<<1, 256, 0, s>>>(loss_out, B, gsq, counter, nact, levels, lr, w_a, metrics);
   return hipGetLastError();
 }
 
