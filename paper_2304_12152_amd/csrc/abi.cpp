@@ -1274,17 +1274,6 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   const uint32_t st = (uint32_t)step;
   LossDev win;
   make_windows(lp, &win);
-  // batch: forward and actions
-  HS_TRY(run_forward_train(weights, contones, seeds, B, H, W, kind, st, precision, pw, probs, act,
-                           lp.levels, s));
-  // the constant-gray side batch (forward, anisotropy gradient, backward
-  // into its own partial rows) on a second stream, beside the batch's loss
-  // kernels, which are bound by the vector ALUs and leave room for its small
-  // launches; it starts after the batch's forward, and the batch waits for
-  // it before the partial sums are added. The batch's loss kernels are
-  // launched first, so that its stream is not left idle while the host
-  // issues the side batch's many small launches.
-  const int npatch = Bg * (Hg / 32) * (Wg / 32);
   SideStream* side = nullptr;
   std::unique_lock<std::mutex> side_lock;
   if (Bg > 0) {
@@ -1292,6 +1281,16 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
     side_lock = std::unique_lock<std::mutex>(side->mu);
     HS_TRY(hipEventRecord(side->fork, s));
   }
+  // batch: forward and actions
+  HS_TRY(run_forward_train(weights, contones, seeds, B, H, W, kind, st, precision, pw, probs, act,
+                           lp.levels, s));
+  // the constant-gray side batch (forward, anisotropy gradient, backward
+  // into its own partial rows) on a second stream, forked before the
+  // batch's forward and beside it and the batch's loss kernels; the batch
+  // waits for it before the partial sums are added. The batch's forward and
+  // loss kernels are launched first, so that its stream is not left idle
+  // while the host issues the side batch's many small launches.
+  const int npatch = Bg * (Hg / 32) * (Wg / 32);
   // batch: policy gradient (logit space)
   HS_TRY(launch_loss_stats(act, contones, B, H, W, lp, win, lw.maps, lw.tiles, lw.ntiles, s));
   if (Bg > 0) HS_TRY(hipEventRecord(side->stats, s));
@@ -1300,16 +1299,17 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   const size_t nact = (size_t)B * H * W;
   if (Bg > 0) {
     // the second stream also takes the reported metrics' action count and
-    // the loss sums (after the batch's statistics), off the batch's path
+    // the loss sums (both after the batch's loss statistics), off the
+    // batch's path
     HS_TRY(hipStreamWaitEvent(side->s, side->fork, 0));
     hipStream_t s2 = side->s;
-    HS_TRY(launch_count_actions(act, nact, pw.counter, s2));
     HS_TRY(run_forward_train(weights, gray, gray_seeds, Bg, Hg, Wg, kind, st, precision, pwg,
                              probs_g, nullptr, lp.levels, s2));
     HS_TRY(launch_fill(gradg, (size_t)Bg * Hg * Wg, 0.0f, s2));
     if (npatch > 0)
       HS_TRY(launch_as(probs_g, Bg, Hg, Wg, lp.w_a / (float)npatch, 1, lw.patches, gradg, s2));
     HS_TRY(hipStreamWaitEvent(s2, side->stats, 0));
+    HS_TRY(launch_count_actions(act, nact, pw.counter, s2));
     HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, lp.w_s, M, loss_out,
                               s2));
     const FwdInput gin{gray, gray_seeds, kind, st};
