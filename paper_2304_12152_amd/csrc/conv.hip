@@ -533,7 +533,7 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T* __restrict__ in
 // ---------------------------------------------------------------------------
 constexpr int CLM_TY = 16, CLM_TX = 64, CLM_RY = CLM_TY + 2, CLM_RX = CLM_TX + 2;
 constexpr int CLM_RUNS = (CLM_RX + 15) / 16;  // 16-pixel runs per halo row
-constexpr int CLM_TS = 12;                    // floats per position (taps 0..8, 3 unused)
+constexpr int CLM_NP = CLM_RY * CLM_RX;      // positions of the tile and its halo
 constexpr int CLM_WRUNS = (CLM_RY * CLM_RUNS + 3) / 4;  // runs per wave
 
 __global__ __launch_bounds__(256) void conv_last_mfma_kernel(const __bf16* __restrict__ in,
@@ -544,7 +544,10 @@ __global__ __launch_bounds__(256) void conv_last_mfma_kernel(const __bf16* __res
                                                              uint8_t* __restrict__ bits,
                                                              float* __restrict__ probs,
                                                              const hs::Levels lv) {
-  __shared__ __attribute__((aligned(16))) float sT[CLM_RY * CLM_RX * CLM_TS];
+  // T tap-major, [tap][position]: a wave's stores of one tap are 16
+  // consecutive positions, and the 16 lanes of a row read positions 4 apart,
+  // both free of bank conflicts
+  __shared__ float sT[9 * CLM_NP];
   const int b = blockIdx.z, y0 = blockIdx.y * CLM_TY, x0 = blockIdx.x * CLM_TX;
   const size_t img = (size_t)b * H * W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
@@ -576,7 +579,9 @@ __global__ __launch_bounds__(256) void conv_last_mfma_kernel(const __bf16* __res
     t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wlo, a[k], t, 0, 0, 0);
     // lane (g, r) holds taps 4g .. 4g + 3 of position (ry, rc + r)
     if (run < CLM_RY * CLM_RUNS && g < 3 && rc + r < CLM_RX)
-      *(f32x4_t*)(sT + (ry * CLM_RX + rc + r) * CLM_TS + 4 * g) = t;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (4 * g + e < 9) sT[(4 * g + e) * CLM_NP + ry * CLM_RX + rc + r] = t[e];
   }
   __syncthreads();
   const float b6 = w[HS_B6];
@@ -588,7 +593,7 @@ __global__ __launch_bounds__(256) void conv_last_mfma_kernel(const __bf16* __res
     if (gx >= W) break;
     float x = b6;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) x += sT[((ty + t / 3) * CLM_RX + cx + t % 3) * CLM_TS + t];
+    for (int t = 0; t < 9; ++t) x += sT[t * CLM_NP + (ty + t / 3) * CLM_RX + cx + t % 3];
     const size_t o = img + (size_t)gy * W + gx;
     const float p = hs_sigmoid(x);
     probs[o] = p;
