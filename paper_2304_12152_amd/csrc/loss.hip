@@ -443,73 +443,52 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
 }
 
 // The binary form of le_grad_kernel for compile-time window radii RH and RS,
-// with each window centre's SSIM terms prepared once per block. For binary
-// h the toggle's increments are all multiples of dw = delta w_{a-j} (dA =
-// 2 dw mu_c, dB = 2 dw t with t = c_a - mu_c, dC = dw (2 mu_h + dw), dD =
-// dw (1 - 2 mu_h - dw)), so the term sigma_c (SSIM' - SSIM) of centre j,
-//   sigma_c [C D (A dB + B dA + dA dB) - A B (C dD + D dC + dC dD)]
-//           / [(C + dC)(D + dD) C D],
-// is N(dw, t) / ((C + dC)(D + dD)) with the polynomial
-//   N = dw (c1 + dw (c2 + dw (c3 + dw c4))), c1 = a1 t + b1, c2 = a2 t + b2,
-// whose coefficients (sigma_c and 1 / (C D) folded in) depend on the centre
-// only:
-//   a1 = 2 s A, b1 = 2 s B mu_c - r (C (1 - 2 mu_h) + 2 D mu_h),
-//   a2 = 4 s mu_c, b2 = -r (D - C + 2 mu_h (1 - 2 mu_h)),
-//   c3 = -r (1 - 4 mu_h), c4 = r,   with s = sigma_c, r = s A B / (C D).
-// The staging pass turns the maps of the block's window into one record per
-// centre (the HVS error and those coefficients, 48 bytes); a thread then
-// computes four horizontally adjacent pixels, each (pixel, centre) pair in
-// about fourteen vector instructions and one reciprocal, the centres in the
-// order of le_grad_kernel. A centre outside the valid region has a zero
-// record (and C = c1, D = c2), so its SSIM term adds exactly zero; its HVS
-// term is masked. A block covers 16 x 32 pixels.
-constexpr int LP_TY = 16, LP_TX = 32, LP_NT = LP_TY * LP_TX / 4;
-
+// register-blocked: a thread computes the gradient of four horizontally
+// adjacent pixels. It walks each kernel row's segment of 4 + 2R window
+// centres once, computing a centre's own terms (A, B, C, D and their
+// products) once for the up to four pixels whose windows hold it, and adds
+// every pixel's terms in the same order as le_grad_kernel. A centre outside
+// the valid region has zero maps and zero sigma_c, so its SSIM term adds
+// exactly zero; its HVS term is masked. A block covers 16 x 64 pixels.
 template <int RH, int RS>
-__global__ __launch_bounds__(LP_NT) void le_grad_poly_kernel(const uint8_t* __restrict__ h,
-                                                             const float* __restrict__ c,
-                                                             const float* __restrict__ probs,
-                                                             int logit_space, int B, int H, int W,
-                                                             LossConst q, const hs::LossDev win,
-                                                             const float* __restrict__ maps,
-                                                             float invM,
-                                                             float* __restrict__ grad) {
-  constexpr int R = RH > RS ? RH : RS, SY = LP_TY + 2 * R, SX = LP_TX + 2 * R;
+__global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restrict__ h,
+                                                         const float* __restrict__ c,
+                                                         const float* __restrict__ probs,
+                                                         int logit_space, int B, int H, int W,
+                                                         LossConst q, const hs::LossDev win,
+                                                         const float* __restrict__ maps,
+                                                         float invM, float* __restrict__ grad) {
+  constexpr int R = RH > RS ? RH : RS, SY = LB_TY + 2 * R, SX = LB_TX + 2 * R;
   constexpr int NH = 2 * RH + 1, NSW = 2 * RS + 1;
-  // record of a centre: {a1, b1, a2, b2}, {c3, c4, C, D}, {2 mu_h, 1 - 2 mu_h, mu_c, e}
-  __shared__ f32x4_t rec[SY * SX][3];
+  __shared__ float se[SY * SX], smh[SY * SX], smc[SY * SX], svc[SY * SX], scv[SY * SX],
+      ssg[SY * SX];
   __shared__ float sG[NH * NH], sw[NSW * NSW];
   const int b = blockIdx.z;
-  const int ay0 = blockIdx.y * LP_TY, ax0 = blockIdx.x * LP_TX;
+  const int ay0 = blockIdx.y * LB_TY, ax0 = blockIdx.x * LB_TX;
   const size_t img = (size_t)b * H * W, n = (size_t)B * H * W;
-  for (int i = threadIdx.x; i < NH * NH; i += LP_NT) sG[i] = win.G[i];
-  for (int i = threadIdx.x; i < NSW * NSW; i += LP_NT) sw[i] = win.w[i];
-  for (int i = threadIdx.x; i < SY * SX; i += LP_NT) {
+  for (int i = threadIdx.x; i < NH * NH; i += 256) sG[i] = win.G[i];
+  for (int i = threadIdx.x; i < NSW * NSW; i += 256) sw[i] = win.w[i];
+  for (int i = threadIdx.x; i < SY * SX; i += 256) {
     const int ly = i / SX, lx = i - ly * SX, gy = ay0 - R + ly, gx = ax0 - R + lx;
     const bool in = gy >= q.m && gy < H - q.m && gx >= q.m && gx < W - q.m;
-    f32x4_t r0 = {0.f, 0.f, 0.f, 0.f}, r1 = {0.f, 0.f, q.c1, q.c2}, r2 = {0.f, 1.f, 0.f, 0.f};
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f;
     if (in) {
       const size_t o = img + (size_t)gy * W + gx;
-      const float e = maps[o], mh = maps[n + o], mc = maps[2 * n + o], vc = maps[3 * n + o],
-                  cv = maps[4 * n + o];
-      const float sg = q.k * sqrtf(vc);
-      const float A = 2.0f * mh * mc + q.c1;
-      const float Bc = 2.0f * cv + q.c2;
-      const float C = mh * mh + mc * mc + q.c1;
-      const float D = mh * (1.0f - mh) + vc + q.c2;
-      const float tm = 2.0f * mh, om = 1.0f - tm;
-      const float rr = sg * (A * Bc) / (C * D);
-      r0 = f32x4_t{2.0f * sg * A, 2.0f * sg * Bc * mc - rr * (C * om + D * tm), 4.0f * sg * mc,
-                   -rr * (D - C + tm * om)};
-      r1 = f32x4_t{-rr * (om - tm), rr, C, D};
-      r2 = f32x4_t{tm, om, mc, e};
+      v0 = maps[o];
+      v1 = maps[n + o];
+      v2 = maps[2 * n + o];
+      v3 = maps[3 * n + o];
+      v4 = maps[4 * n + o];
     }
-    rec[i][0] = r0;
-    rec[i][1] = r1;
-    rec[i][2] = r2;
+    se[i] = v0;
+    smh[i] = v1;
+    smc[i] = v2;
+    svc[i] = v3;
+    scv[i] = v4;
+    ssg[i] = q.k * sqrtf(v3);
   }
   __syncthreads();
-  const int ty = threadIdx.x / (LP_TX / 4), tx = threadIdx.x % (LP_TX / 4);
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   const int ay = ay0 + ty, axb = ax0 + 4 * tx;
   if (ay >= H || axb >= W) return;
   float delta[4], ca[4];
@@ -520,43 +499,56 @@ __global__ __launch_bounds__(LP_NT) void le_grad_poly_kernel(const uint8_t* __re
     delta[k] = h[oa] ? -1.0f : 1.0f;
     ca[k] = c[oa];
   }
-  float dmse[4] = {0.f, 0.f, 0.f, 0.f}, dcs[4] = {0.f, 0.f, 0.f, 0.f};
-  // staged row of centre row ay + i: ty + R + i; the four pixels' centres:
-  // staged columns 4 tx .. 4 tx + 2R + 3 (global ax0 - R + column)
+  // staged row of centre row ay + i: ty + R + i; centre segment of the four
+  // pixels: staged columns 4 tx .. 4 tx + 2R + 3 (global ax0 - R + column)
+  float dmse[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
-  for (int i = -R; i <= R; ++i) {
+  for (int i = -RH; i <= RH; ++i) {
     const int jy = ay + i;
     if (jy < q.m || jy >= H - q.m) continue;
-    const int rowo = (ty + R + i) * SX + 4 * tx;
+    const int rowo = (ty + R + i) * SX + 4 * tx + (R - RH);
 #pragma unroll
-    for (int jc = 0; jc < 2 * R + 4; ++jc) {
-      const f32x4_t r0 = rec[rowo + jc][0], r1 = rec[rowo + jc][1], r2 = rec[rowo + jc][2];
-      const int gx = axb - R + jc;
-      if (i >= -RH && i <= RH) {
-        const float vm = (gx >= q.m && gx < W - q.m) ? 1.0f : 0.0f;
+    for (int jc = 0; jc < 2 * RH + 4; ++jc) {
+      const int gx = axb - RH + jc;
+      const float vm = (gx >= q.m && gx < W - q.m) ? 1.0f : 0.0f;
+      const float sev = se[rowo + jc];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int jt = jc - k - (R - RH);  // tap j = jt - RH
-          if (jt < 0 || jt > 2 * RH) continue;
-          const float dG = delta[k] * sG[(RH - i) * NH + (2 * RH - jt)] * vm;
-          dmse[k] = fmaf(2.0f * dG, r2[3], fmaf(dG, dG, dmse[k]));
-        }
+      for (int k = 0; k < 4; ++k) {
+        const int jt = jc - k;  // tap j = jt - RH
+        if (jt < 0 || jt > 2 * RH) continue;
+        const float dG = delta[k] * sG[(RH - i) * NH + (2 * RH - jt)] * vm;
+        dmse[k] = fmaf(2.0f * dG, sev, fmaf(dG, dG, dmse[k]));
       }
-      if (i >= -RS && i <= RS) {
+    }
+  }
+  float dcs[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int i = -RS; i <= RS; ++i) {
+    const int jy = ay + i;
+    if (jy < q.m || jy >= H - q.m) continue;
+    const int rowo = (ty + R + i) * SX + 4 * tx + (R - RS);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int jt = jc - k - (R - RS);
-          if (jt < 0 || jt > 2 * RS) continue;
-          const float dw = delta[k] * sw[(RS - i) * NSW + (2 * RS - jt)];
-          const float t = ca[k] - r2[2];
-          const float c1 = fmaf(r0[0], t, r0[1]), c2 = fmaf(r0[2], t, r0[3]);
-          float p = fmaf(dw, r1[1], r1[0]);
-          p = fmaf(dw, p, c2);
-          p = fmaf(dw, p, c1);
-          const float den = fmaf(dw, r2[0] + dw, r1[2]) * fmaf(dw, r2[1] - dw, r1[3]);
-          // hardware reciprocal (1 ulp) instead of the IEEE division sequence
-          dcs[k] = fmaf(p * dw, __builtin_amdgcn_rcpf(den), dcs[k]);
-        }
+    for (int jc = 0; jc < 2 * RS + 4; ++jc) {
+      const int p = rowo + jc;
+      const float mh = smh[p], mc = smc[p], sg = ssg[p];
+      const float A = 2.0f * mh * mc + q.c1;
+      const float Bc = 2.0f * scv[p] + q.c2;
+      const float C = mh * mh + mc * mc + q.c1;
+      const float D = mh * (1.0f - mh) + svc[p] + q.c2;
+      const float CD = C * D, ABc = A * Bc, twomh = 2.0f * mh, omtmh = 1.0f - 2.0f * mh;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int jt = jc - k;
+        if (jt < 0 || jt > 2 * RS) continue;
+        const float wa = sw[(RS - i) * NSW + (2 * RS - jt)];
+        const float dw = delta[k] * wa;
+        const float dA = 2.0f * dw * mc;
+        const float dB = 2.0f * dw * (ca[k] - mc);
+        const float dC = dw * (twomh + dw);
+        const float dD = dw * (omtmh - dw);
+        const float num = CD * (A * dB + Bc * dA + dA * dB) - ABc * (C * dD + D * dC + dC * dD);
+        const float den = (C + dC) * (D + dD) * CD;
+        dcs[k] = fmaf(sg, num * __builtin_amdgcn_rcpf(den), dcs[k]);
       }
     }
   }
@@ -813,9 +805,9 @@ hipError_t launch_le_grad(const uint8_t* h, const float* c, const float* probs, 
   const LossConst q = make_const(p);
   const long M = (long)(H - 2 * q.m) * (W - 2 * q.m);
   if (q.levels == 2 && q.rh == 5 && q.rs == 5) {  // binary, the default windows
-    const dim3 grid((W + LP_TX - 1) / LP_TX, (H + LP_TY - 1) / LP_TY, B);
-    le_grad_poly_kernel<5, 5><<<grid, LP_NT, 0, s>>>(h, c, probs, logit_space, B, H, W, q, win,
-                                                     maps, (float)(1.0 / (double)M), grad);
+    const dim3 grid((W + LB_TX - 1) / LB_TX, (H + LB_TY - 1) / LB_TY, B);
+    le_grad_rb_kernel<5, 5><<<grid, 256, 0, s>>>(h, c, probs, logit_space, B, H, W, q, win, maps,
+                                                 (float)(1.0 / (double)M), grad);
     return hipGetLastError();
   }
   const dim3 grid((W + LT - 1) / LT, (H + LT - 1) / LT, B);
