@@ -23,6 +23,7 @@ The JSON line also carries:
                   fused launch's FLOP rate, and the same pages with 4 levels.
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -146,9 +147,14 @@ def bench_loss(hb, synth, torch, dev, steps):
     gen.manual_seed(7)
     acts = (torch.rand(probs.shape, generator=gen, device=dev) < probs).to(torch.uint8)
 
+    # outputs and workspace allocated once, as a training loop holds them
+    out = (torch.empty_like(probs), torch.empty_like(probs))
+    ws = torch.empty(hb.lib().halftone_loss_workspace_size(
+        B, H, W, B, H, W, ctypes.byref(hb.default_loss_params())), dtype=torch.uint8, device=dev)
+
     def run():
         return hb.halftone_loss_backward(acts, c, probs=probs, probs_gray=probs,
-                                         grad_space=hb.HS_WRT_LOGIT)
+                                         grad_space=hb.HS_WRT_LOGIT, workspace=ws, out=out)
 
     for _ in range(5):
         run()

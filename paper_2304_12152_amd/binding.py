@@ -373,16 +373,27 @@ def halftone_loss(actions, contone, probs_gray=None, prm=None):
 
 
 def halftone_loss_backward(actions, contone, probs=None, probs_gray=None, prm=None,
-                           grad_space=HS_WRT_PROB):
-    """(grad_probs, grad_probs_gray or None)."""
+                           grad_space=HS_WRT_PROB, workspace=None, out=None):
+    """(grad_probs, grad_probs_gray or None). out: a (grad_probs,
+    grad_probs_gray) pair to write into instead of new tensors; workspace: a
+    uint8 device tensor reused when large enough."""
     prm = prm or default_loss_params()
     B, H, W = contone.shape
     Bg, Hg, Wg = probs_gray.shape if probs_gray is not None else (0, 0, 0)
-    gp = torch.empty((B, H, W), dtype=torch.float32, device=contone.device)
-    gg = torch.empty((Bg, Hg, Wg), dtype=torch.float32, device=contone.device) \
-        if probs_gray is not None else None
+    if out is not None:
+        gp, gg = out
+        _dev(gp, torch.float32)
+        assert tuple(gp.shape) == (B, H, W)
+        if probs_gray is not None:
+            _dev(gg, torch.float32)
+            assert tuple(gg.shape) == (Bg, Hg, Wg)
+    else:
+        gp = torch.empty((B, H, W), dtype=torch.float32, device=contone.device)
+        gg = torch.empty((Bg, Hg, Wg), dtype=torch.float32, device=contone.device) \
+            if probs_gray is not None else None
     need = lib().halftone_loss_workspace_size(B, H, W, Bg, Hg, Wg, ctypes.byref(prm))
-    ws = _ws(need, contone.device)
+    ws = workspace if workspace is not None and workspace.numel() >= need else \
+        _ws(need, contone.device)
     _check(lib().halftone_loss_backward(_ptr(actions), _ptr(contone), _ptr(probs), B, H, W,
                                         _ptr(probs_gray), Bg, Hg, Wg, ctypes.byref(prm),
                                         grad_space, _ptr(gp), _ptr(gg), _ptr(ws), ws.numel(),
