@@ -1,6 +1,8 @@
 """GPU parity of halftone_loss / halftone_loss_backward against the oracle:
 reward terms and L_AS to 1e-5 relative, Local Expectation and anisotropy
 gradients to 1e-4 of their largest entry."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -134,3 +136,24 @@ def test_coma_needs_probs():
     lp = hb.default_loss_params(estimator=hb.HS_EST_COMA)
     with pytest.raises(hb.HalftoneError):
         hb.halftone_loss_backward(to_dev(h), to_dev(c), None, prm=lp)
+
+
+def test_loss_backward_into_caller_buffers():
+    """The binding's caller-provided outputs and workspace (as a training
+    loop holds them) give the same gradients as fresh allocations, twice in
+    a row on the same buffers."""
+    B, H, W = 2, 40, 56
+    c, p, h = _case([41, 42], H, W)
+    ct, pt, ht = to_dev(c), to_dev(p), to_dev(h)
+    ref = hb.halftone_loss_backward(ht, ct, probs=pt, probs_gray=pt, grad_space=hb.HS_WRT_LOGIT)
+    out = (torch.full_like(pt, float("nan")), torch.full_like(pt, float("nan")))
+    need = hb.lib().halftone_loss_workspace_size(B, H, W, B, H, W,
+                                                  ctypes.byref(hb.default_loss_params()))
+    ws = torch.empty(need, dtype=torch.uint8, device=ct.device)
+    for _ in range(2):
+        got = hb.halftone_loss_backward(ht, ct, probs=pt, probs_gray=pt,
+                                        grad_space=hb.HS_WRT_LOGIT, workspace=ws, out=out)
+        assert got[0].data_ptr() == out[0].data_ptr() and got[1].data_ptr() == out[1].data_ptr()
+        assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+    with pytest.raises(AssertionError):
+        hb.halftone_loss_backward(ht, ct, probs=pt, probs_gray=pt, out=(out[0][:1], out[1]))
