@@ -223,6 +223,7 @@ hipError_t launch_reduce_partials(const float* partials, int rows, int rows32, f
 struct LossDev {  // the two normalised windows, passed to kernels by value
   float G[15 * 15];
   float w[15 * 15];
+  float g1[15], w1[15];  // their normalised 1-D factors (G = g1 g1^T, w = w1 w1^T)
 };
 void make_windows(const hs_loss_params& p, LossDev* host_out);
 hipError_t launch_loss_stats(const uint8_t* h, const float* c, int B, int H, int W,

@@ -138,14 +138,17 @@ __global__ __launch_bounds__(256) void loss_stats_kernel(const uint8_t* __restri
 }
 
 // The same statistics for compile-time window radii RH (HVS) and RS (SSIM),
-// register-blocked: a thread computes four horizontally adjacent outputs,
-// reading each staged row segment (4 + 2R values of h and of c) once per
-// kernel row for all four instead of once per tap and output, and holding
-// the row's weights in registers. The taps of every output are summed in
-// the same order and with the same operations as in loss_stats_kernel
-// (rows, then columns); the per-tile sums are added in another order. A
-// block covers 16 x 64 outputs, i.e. four of the 16 x 16 tiles whose
-// partial sums loss_reduce_kernel adds.
+// register-blocked: a thread computes four horizontally adjacent outputs.
+// The first pass (e = G * (h - c), mu_h = w * h, mu_c = w * c) uses the
+// separability of the Gaussian windows (G = g g^T, w = w1 w1^T): row sums
+// over the taps j of every staged row into LDS, then column sums over the
+// taps i, 4 (2r + 1) operations per output instead of 2 (2r + 1)^2. The
+// second pass (the centred second moments, which do not separate) reads
+// each staged row segment (4 + 2R values of h and of c) once per kernel row
+// for all four outputs, with the same taps in the same order as in
+// loss_stats_kernel; the per-tile sums are added in another order. A block
+// covers 16 x 64 outputs, i.e. four of the 16 x 16 tiles whose partial sums
+// loss_reduce_kernel adds.
 constexpr int LB_TY = 16, LB_TX = 64;
 
 template <int RH, int RS>
@@ -158,14 +161,15 @@ __global__ __launch_bounds__(256) void loss_stats_rb_kernel(const uint8_t* __res
                                                             int ntiles_per_img) {
   constexpr int R = RH > RS ? RH : RS, SY = LB_TY + 2 * R, SX = LB_TX + 2 * R, NS = 4 + 2 * R;
   __shared__ float sh[SY * SX], sc[SY * SX];
-  __shared__ float sG[(2 * RH + 1) * (2 * RH + 1)], sw[(2 * RS + 1) * (2 * RS + 1)];
+  __shared__ float sw[(2 * RS + 1) * (2 * RS + 1)];
   __shared__ float red[2][256];
+  // the first pass's row sums: e, mu_h, mu_c of every staged row at the
+  // tile's output columns (the windows are separable Gaussians)
+  __shared__ __attribute__((aligned(16))) float rE[SY * LB_TX], rH[SY * LB_TX], rC[SY * LB_TX];
   const int b = blockIdx.z;
   const int vy0 = R + blockIdx.y * LB_TY, vx0 = R + blockIdx.x * LB_TX;
   const size_t img = (size_t)b * H * W;
-  // the windows' rows of 2 r + 1 taps, stored densely (win holds 15 x 15)
-  for (int i = threadIdx.x; i < (2 * RH + 1) * (2 * RH + 1); i += 256)
-    sG[i] = win.G[(i / (2 * RH + 1)) * (2 * RH + 1) + i % (2 * RH + 1)];
+  // the SSIM window's rows of 2 r + 1 taps, stored densely (win holds 15 x 15)
   for (int i = threadIdx.x; i < (2 * RS + 1) * (2 * RS + 1); i += 256)
     sw[i] = win.w[(i / (2 * RS + 1)) * (2 * RS + 1) + i % (2 * RS + 1)];
   for (int i = threadIdx.x; i < SY * SX; i += 256) {
@@ -175,46 +179,63 @@ __global__ __launch_bounds__(256) void loss_stats_rb_kernel(const uint8_t* __res
     sc[i] = in ? c[img + (size_t)gy * W + gx] : 0.0f;
   }
   __syncthreads();
+  // ---- first pass, separable: row sums over the taps j (item = a staged
+  // row and four output columns), then column sums over the taps i
+  for (int it = threadIdx.x; it < SY * (LB_TX / 4); it += 256) {
+    const int ly = it / (LB_TX / 4), x4 = 4 * (it % (LB_TX / 4));
+    float hv[NS], cv[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      hv[j] = sh[ly * SX + x4 + j];
+      cv[j] = sc[ly * SX + x4 + j];
+    }
+    f32x4_t re = {0.f, 0.f, 0.f, 0.f}, rh = {0.f, 0.f, 0.f, 0.f}, rc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 2 * RH + 1; ++j) {
+      const float g = win.g1[j];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int p = k + j + (R - RH);
+        re[k] = fmaf(g, hv[p] - cv[p], re[k]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * RS + 1; ++j) {
+      const float wv = win.w1[j];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int p = k + j + (R - RS);
+        rh[k] = fmaf(wv, hv[p], rh[k]);
+        rc[k] = fmaf(wv, cv[p], rc[k]);
+      }
+    }
+    *(f32x4_t*)(rE + ly * LB_TX + x4) = re;
+    *(f32x4_t*)(rH + ly * LB_TX + x4) = rh;
+    *(f32x4_t*)(rC + ly * LB_TX + x4) = rc;
+  }
+  __syncthreads();
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   const int jy = vy0 + ty, jx0 = vx0 + 4 * tx;
   // row segment of kernel row i: staged columns 4 tx .. 4 tx + 2R + 3
   const float* hr0 = sh + ty * SX + 4 * tx;
   const float* cr0 = sc + ty * SX + 4 * tx;
   float e[4] = {0.f, 0.f, 0.f, 0.f}, mh[4] = {0.f, 0.f, 0.f, 0.f}, mc[4] = {0.f, 0.f, 0.f, 0.f};
-  // kernel rows one at a time (unrolled, the loads of all rows would be
-  // hoisted and spill)
-#pragma unroll 1
-  for (int i = 0; i < 2 * R + 1; ++i) {
-    float hv[NS], cv[NS];
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      hv[j] = hr0[i * SX + j];
-      cv[j] = cr0[i * SX + j];
-    }
-    if (i >= R - RH && i <= R + RH) {
-      const int gi = i - (R - RH);
+  for (int i = 0; i < 2 * RH + 1; ++i) {
+    const f32x4_t v = *(const f32x4_t*)(rE + (ty + i + (R - RH)) * LB_TX + 4 * tx);
+    const float g = win.g1[i];
 #pragma unroll
-      for (int j = 0; j < 2 * RH + 1; ++j) {
-        const float g = sG[gi * (2 * RH + 1) + j];
+    for (int k = 0; k < 4; ++k) e[k] = fmaf(g, v[k], e[k]);
+  }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int p = k + j + (R - RH);
-          e[k] = fmaf(g, hv[p] - cv[p], e[k]);
-        }
-      }
-    }
-    if (i >= R - RS && i <= R + RS) {
-      const int wi = i - (R - RS);
+  for (int i = 0; i < 2 * RS + 1; ++i) {
+    const f32x4_t vh4 = *(const f32x4_t*)(rH + (ty + i + (R - RS)) * LB_TX + 4 * tx);
+    const f32x4_t vc4 = *(const f32x4_t*)(rC + (ty + i + (R - RS)) * LB_TX + 4 * tx);
+    const float wv = win.w1[i];
 #pragma unroll
-      for (int j = 0; j < 2 * RS + 1; ++j) {
-        const float wv = sw[wi * (2 * RS + 1) + j];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int p = k + j + (R - RS);
-          mh[k] = fmaf(wv, hv[p], mh[k]);
-          mc[k] = fmaf(wv, cv[p], mc[k]);
-        }
-      }
+    for (int k = 0; k < 4; ++k) {
+      mh[k] = fmaf(wv, vh4[k], mh[k]);
+      mc[k] = fmaf(wv, vc4[k], mc[k]);
     }
   }
   float vh[4] = {0.f, 0.f, 0.f, 0.f}, vc[4] = {0.f, 0.f, 0.f, 0.f}, cov[4] = {0.f, 0.f, 0.f, 0.f};
@@ -752,6 +773,15 @@ void make_windows(const hs_loss_params& p, LossDev* out) {
   };
   gauss(p.hvs_sigma, p.hvs_radius, out->G);
   gauss(p.ssim_sigma, p.ssim_radius, out->w);
+  // the 1-D factors: exp(-(i^2 + j^2) / 2 s^2) / Z = f_i f_j with f_i =
+  // exp(-i^2 / 2 s^2) / sqrt(Z), sqrt(Z) the 1-D sum
+  auto gauss1 = [](double sigma, int r, float* dst) {
+    double tmp[15], sum = 0.0;
+    for (int i = -r; i <= r; ++i) sum += (tmp[i + r] = exp(-(double)(i * i) / (2.0 * sigma * sigma)));
+    for (int i = 0; i < 15; ++i) dst[i] = i < 2 * r + 1 ? (float)(tmp[i] / sum) : 0.0f;
+  };
+  gauss1(p.hvs_sigma, p.hvs_radius, out->g1);
+  gauss1(p.ssim_sigma, p.ssim_radius, out->w1);
 }
 
 static LossConst make_const(const hs_loss_params& p) {
