@@ -465,12 +465,16 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
 
 // The binary form of le_grad_kernel for compile-time window radii RH and RS,
 // register-blocked: a thread computes the gradient of four horizontally
-// adjacent pixels. It walks each kernel row's segment of 4 + 2R window
-// centres once, computing a centre's own terms (A, B, C, D and their
-// products) once for the up to four pixels whose windows hold it, and adds
-// every pixel's terms in the same order as le_grad_kernel. A centre outside
-// the valid region has zero maps and zero sigma_c, so its SSIM term adds
-// exactly zero; its HVS term is masked. A block covers 16 x 64 pixels.
+// adjacent pixels. The HVS part, sum over valid centres j of 2 delta
+// G_{a-j} e_j + G_{a-j}^2, is 2 delta (G * e)_a plus the sum of G^2 over
+// the valid centres, both separable (G = g g^T, and the valid region is a
+// rectangle): row sums of e into LDS, then column sums. For the SSIM part
+// it walks each kernel row's segment of 4 + 2R window centres once,
+// computing a centre's own terms (A, B, C, D and their products) once for
+// the up to four pixels whose windows hold it, and adds every pixel's terms
+// in the same order as le_grad_kernel. A centre outside the valid region
+// has zero maps and zero sigma_c, so its SSIM term adds exactly zero. A
+// block covers 16 x 64 pixels.
 template <int RH, int RS>
 __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restrict__ h,
                                                          const float* __restrict__ c,
@@ -480,14 +484,14 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
                                                          const float* __restrict__ maps,
                                                          float invM, float* __restrict__ grad) {
   constexpr int R = RH > RS ? RH : RS, SY = LB_TY + 2 * R, SX = LB_TX + 2 * R;
-  constexpr int NH = 2 * RH + 1, NSW = 2 * RS + 1;
+  constexpr int NSW = 2 * RS + 1;
   __shared__ float se[SY * SX], smh[SY * SX], smc[SY * SX], svc[SY * SX], scv[SY * SX],
       ssg[SY * SX];
-  __shared__ float sG[NH * NH], sw[NSW * NSW];
+  __shared__ float sw[NSW * NSW];
+  __shared__ __attribute__((aligned(16))) float rS[SY * LB_TX];  // row sums of g * e
   const int b = blockIdx.z;
   const int ay0 = blockIdx.y * LB_TY, ax0 = blockIdx.x * LB_TX;
   const size_t img = (size_t)b * H * W, n = (size_t)B * H * W;
-  for (int i = threadIdx.x; i < NH * NH; i += 256) sG[i] = win.G[i];
   for (int i = threadIdx.x; i < NSW * NSW; i += 256) sw[i] = win.w[i];
   for (int i = threadIdx.x; i < SY * SX; i += 256) {
     const int ly = i / SX, lx = i - ly * SX, gy = ay0 - R + ly, gx = ax0 - R + lx;
@@ -509,6 +513,21 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
     ssg[i] = q.k * sqrtf(v3);
   }
   __syncthreads();
+  // row sums of g * e at the tile's pixel columns (item: a staged row and
+  // four columns)
+  for (int it = threadIdx.x; it < SY * (LB_TX / 4); it += 256) {
+    const int ly = it / (LB_TX / 4), x4 = 4 * (it % (LB_TX / 4));
+    f32x4_t rs = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 2 * RH + 4; ++t) {
+      const float ev = se[ly * SX + x4 + (R - RH) + t];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (t - k >= 0 && t - k <= 2 * RH) rs[k] = fmaf(win.g1[t - k], ev, rs[k]);
+    }
+    *(f32x4_t*)(rS + ly * LB_TX + x4) = rs;
+  }
+  __syncthreads();
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   const int ay = ay0 + ty, axb = ax0 + 4 * tx;
   if (ay >= H || axb >= W) return;
@@ -520,26 +539,30 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
     delta[k] = h[oa] ? -1.0f : 1.0f;
     ca[k] = c[oa];
   }
-  // staged row of centre row ay + i: ty + R + i; centre segment of the four
-  // pixels: staged columns 4 tx .. 4 tx + 2R + 3 (global ax0 - R + column)
-  float dmse[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-  for (int i = -RH; i <= RH; ++i) {
-    const int jy = ay + i;
-    if (jy < q.m || jy >= H - q.m) continue;
-    const int rowo = (ty + R + i) * SX + 4 * tx + (R - RH);
+  // HVS: 2 delta (G * e)_a + sum of G^2 over the valid centres (the product
+  // of the valid rows' and the valid columns' sums of g^2)
+  float dmse[4];
+  {
+    f32x4_t ge = {0.f, 0.f, 0.f, 0.f};
+    float rowg2 = 0.0f;
 #pragma unroll
-    for (int jc = 0; jc < 2 * RH + 4; ++jc) {
-      const int gx = axb - RH + jc;
-      const float vm = (gx >= q.m && gx < W - q.m) ? 1.0f : 0.0f;
-      const float sev = se[rowo + jc];
+    for (int i = 0; i <= 2 * RH; ++i) {
+      const f32x4_t v = *(const f32x4_t*)(rS + (ty + (R - RH) + i) * LB_TX + 4 * tx);
+      const float g = win.g1[i];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int jt = jc - k;  // tap j = jt - RH
-        if (jt < 0 || jt > 2 * RH) continue;
-        const float dG = delta[k] * sG[(RH - i) * NH + (2 * RH - jt)] * vm;
-        dmse[k] = fmaf(2.0f * dG, sev, fmaf(dG, dG, dmse[k]));
+      for (int k = 0; k < 4; ++k) ge[k] = fmaf(g, v[k], ge[k]);
+      const int jy = ay - RH + i;
+      if (jy >= q.m && jy < H - q.m) rowg2 = fmaf(g, g, rowg2);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float colg2 = 0.0f;
+#pragma unroll
+      for (int j = 0; j <= 2 * RH; ++j) {
+        const int jx = axb + k - RH + j;
+        if (jx >= q.m && jx < W - q.m) colg2 = fmaf(win.g1[j], win.g1[j], colg2);
       }
+      dmse[k] = fmaf(2.0f * delta[k], ge[k], rowg2 * colg2);
     }
   }
   float dcs[4] = {0.f, 0.f, 0.f, 0.f};
