@@ -176,13 +176,15 @@ InferWs carve_infer(Carve& cv, size_t N, int prec) {
   return w;
 }
 
-// Forward of the stack on one batch: pack -> first -> four 32->32 -> last.
-// mode 0: inference bits/logits; mode 1: probs (+ actions) keeping activations.
+// Forward of the stack on one batch: pack -> first -> four 32->32 -> last,
+// keeping the activations, with probs (+ actions) out. pack = false: the
+// caller has already packed w into pw.packF on this stream.
 hipError_t run_forward_train(const float* w, const float* contone, const uint64_t* seeds, int B,
                              int H, int W, int kind, uint32_t step, int prec, const PolicyWs& pw,
-                             float* probs, uint8_t* actions, int levels, hipStream_t s) {
+                             float* probs, uint8_t* actions, int levels, hipStream_t s,
+                             bool pack = true) {
   hipError_t e;
-  if ((e = launch_pack32(w, pw.packF, prec, 0, s)) != hipSuccess) return e;
+  if (pack && (e = launch_pack32(w, pw.packF, prec, 0, s)) != hipSuccess) return e;
   if ((e = launch_conv_first(contone, seeds, w, B, H, W, kind, step, prec, pw.act(0), pw.z, pw.c,
                              s)) != hipSuccess)
     return e;
@@ -229,9 +231,9 @@ int num_cus();  // compute units of the current device (below)
 // its buffer from the forward; the others are rebuilt layer by layer).
 hipError_t run_backward(const float* w, const float* grad, const float* probs, int B, int H,
                         int W, int prec, const PolicyWs& pw, int accumulate, hipStream_t s,
-                        const FwdInput* in = nullptr) {
+                        const FwdInput* in = nullptr, bool pack = true) {
   hipError_t e;
-  if ((e = launch_pack32(w, pw.packT, prec, 1, s)) != hipSuccess) return e;
+  if (pack && (e = launch_pack32(w, pw.packT, prec, 1, s)) != hipSuccess) return e;
   if ((e = launch_bwd_last(grad, probs, pw.act(4), w, B, H, W, prec, pw.g6, pw.gA, pw.partials,
                            accumulate, s)) != hipSuccess)
     return e;
@@ -1274,6 +1276,10 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   const uint32_t st = (uint32_t)step;
   LossDev win;
   make_windows(lp, &win);
+  // the layers' packed weights, forward and transposed, once for both batches
+  HS_TRY(launch_pack32_both(weights, pw.packF, pw.packT, precision, s));
+  pwg.packF = pw.packF;
+  pwg.packT = pw.packT;
   SideStream* side = nullptr;
   std::unique_lock<std::mutex> side_lock;
   if (Bg > 0) {
@@ -1283,7 +1289,7 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   }
   // batch: forward and actions
   HS_TRY(run_forward_train(weights, contones, seeds, B, H, W, kind, st, precision, pw, probs, act,
-                           lp.levels, s));
+                           lp.levels, s, false));
   // the constant-gray side batch (forward, anisotropy gradient, backward
   // into its own partial rows) on a second stream, forked before the
   // batch's forward and beside it and the batch's loss kernels; the batch
@@ -1304,7 +1310,7 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
     HS_TRY(hipStreamWaitEvent(side->s, side->fork, 0));
     hipStream_t s2 = side->s;
     HS_TRY(run_forward_train(weights, gray, gray_seeds, Bg, Hg, Wg, kind, st, precision, pwg,
-                             probs_g, nullptr, lp.levels, s2));
+                             probs_g, nullptr, lp.levels, s2, false));
     HS_TRY(launch_fill(gradg, (size_t)Bg * Hg * Wg, 0.0f, s2));
     if (npatch > 0)
       HS_TRY(launch_as(probs_g, Bg, Hg, Wg, lp.w_a / (float)npatch, 1, lw.patches, gradg, s2));
@@ -1313,12 +1319,12 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
     HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, lp.w_s, M, loss_out,
                               s2));
     const FwdInput gin{gray, gray_seeds, kind, st};
-    HS_TRY(run_backward(weights, gradg, nullptr, Bg, Hg, Wg, precision, pwg, 0, s2, &gin));
+    HS_TRY(run_backward(weights, gradg, nullptr, Bg, Hg, Wg, precision, pwg, 0, s2, &gin, false));
     HS_TRY(hipEventRecord(side->join, s2));
   }
   // batch: backward
   const FwdInput fin{contones, seeds, kind, st};
-  HS_TRY(run_backward(weights, gradp, nullptr, B, H, W, precision, pw, 0, s, &fin));
+  HS_TRY(run_backward(weights, gradp, nullptr, B, H, W, precision, pw, 0, s, &fin, false));
   if (Bg > 0) HS_TRY(hipStreamWaitEvent(s, side->join, 0));
   HS_TRY(launch_reduce_partials(pw.partials, Bg > 0 ? 2 * WGRAD_BLOCKS : WGRAD_BLOCKS,
                                 precision == HS_BF16 ? bwd32_grid(num_cus()) : WGRAD_BLOCKS,

@@ -21,9 +21,13 @@ namespace {
 // forward:    element (t, m, l, j) = W[16m + l%16][8(l/16) + j][t]
 // transposed: element (t, m, l, j) = W[8(l/16) + j][16m + l%16][8 - t]
 // ---------------------------------------------------------------------------
+// blockIdx.y + y0 = 4 x (transposed) + layer, layer 0..3 being conv layer 2..5;
+// the forward copy goes to outF, the transposed one to outT.
 template <typename T>
-__global__ void pack32_kernel(const float* __restrict__ w, T* __restrict__ out, int transposed) {
-  const int layer = blockIdx.y;  // 0..3 is conv layer 2..5
+__global__ void pack32_kernel(const float* __restrict__ w, T* __restrict__ outF,
+                              T* __restrict__ outT, int y0) {
+  const int y = blockIdx.y + y0, layer = y & 3, transposed = y >> 2;
+  T* __restrict__ out = transposed ? outT : outF;
   const float* Wk = w + hs_wk(layer + 2);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < hs::PACK32_PER_LAYER;
        i += gridDim.x * blockDim.x) {
@@ -1625,10 +1629,20 @@ namespace hs {
 
 hipError_t launch_pack32(const float* w, void* out, int precision, int transposed,
                          hipStream_t s) {
+  const int y0 = transposed ? 4 : 0;
   if (precision == HS_BF16)
-    pack32_kernel<__bf16><<<dim3(36, 4), 256, 0, s>>>(w, (__bf16*)out, transposed);
+    pack32_kernel<__bf16><<<dim3(36, 4), 256, 0, s>>>(w, (__bf16*)out, (__bf16*)out, y0);
   else
-    pack32_kernel<float><<<dim3(36, 4), 256, 0, s>>>(w, (float*)out, transposed);
+    pack32_kernel<float><<<dim3(36, 4), 256, 0, s>>>(w, (float*)out, (float*)out, y0);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack32_both(const float* w, void* outF, void* outT, int precision,
+                              hipStream_t s) {
+  if (precision == HS_BF16)
+    pack32_kernel<__bf16><<<dim3(36, 8), 256, 0, s>>>(w, (__bf16*)outF, (__bf16*)outT, 0);
+  else
+    pack32_kernel<float><<<dim3(36, 8), 256, 0, s>>>(w, (float*)outF, (float*)outT, 0);
   return hipGetLastError();
 }
 

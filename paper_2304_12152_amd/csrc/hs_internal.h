@@ -96,6 +96,9 @@ inline size_t pack_bytes(int precision) {
 
 // conv.hip
 hipError_t launch_pack32(const float* w, void* out, int precision, int transposed, hipStream_t s);
+// Both copies (forward into outF, transposed into outT) in one launch.
+hipError_t launch_pack32_both(const float* w, void* outF, void* outT, int precision,
+                              hipStream_t s);
 hipError_t launch_conv_first(const float* contone, const uint64_t* seeds, const float* w, int B,
                              int H, int W, int kind, uint32_t step, int precision, void* out,
                              float* zout, float* cout, hipStream_t s);
