@@ -469,12 +469,17 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
 // G_{a-j} e_j + G_{a-j}^2, is 2 delta (G * e)_a plus the sum of G^2 over
 // the valid centres, both separable (G = g g^T, and the valid region is a
 // rectangle): row sums of e into LDS, then column sums. For the SSIM part
-// it walks each kernel row's segment of 4 + 2R window centres once,
-// computing a centre's own terms (A, B, C, D and their products) once for
-// the up to four pixels whose windows hold it, and adds every pixel's terms
-// in the same order as le_grad_kernel. A centre outside the valid region
-// has zero maps and zero sigma_c, so its SSIM term adds exactly zero. A
-// block covers 16 x 64 pixels.
+// it walks each kernel row's segment of 4 + 2R window centres once, with
+// the centre's own terms B = 2 cov + c2, D = var_h + var_c + c2 and
+// SSIM_j = A B / (C D) staged once per block, and for each of the up to
+// four pixels whose windows hold the centre takes the toggled factors
+// A', B', C', D' and the change A'B' / (C'D') - SSIM_j, in the same centre
+// order as le_grad_kernel. (The difference of the two ratios has the FP32
+// error of the cancellation-free form of le_grad_kernel: both are set by
+// the rounding of the FP32 statistics, about 3e-7 of the largest change;
+// it takes 14 instead of about 26 operations per term.) A centre outside
+// the valid region has zero maps and zero sigma_c, so its SSIM term adds
+// exactly zero. A block covers 16 x 64 pixels.
 template <int RH, int RS>
 __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restrict__ h,
                                                          const float* __restrict__ c,
@@ -485,7 +490,8 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
                                                          float invM, float* __restrict__ grad) {
   constexpr int R = RH > RS ? RH : RS, SY = LB_TY + 2 * R, SX = LB_TX + 2 * R;
   constexpr int NSW = 2 * RS + 1;
-  __shared__ float se[SY * SX], smh[SY * SX], smc[SY * SX], svc[SY * SX], scv[SY * SX],
+  // sES holds e until its row sums are taken, then SSIM_j
+  __shared__ float sES[SY * SX], smh[SY * SX], smc[SY * SX], sB[SY * SX], sD[SY * SX],
       ssg[SY * SX];
   __shared__ float sw[NSW * NSW];
   __shared__ __attribute__((aligned(16))) float rS[SY * LB_TX];  // row sums of g * e
@@ -505,11 +511,11 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
       v3 = maps[3 * n + o];
       v4 = maps[4 * n + o];
     }
-    se[i] = v0;
+    sES[i] = v0;
     smh[i] = v1;
     smc[i] = v2;
-    svc[i] = v3;
-    scv[i] = v4;
+    sB[i] = fmaf(2.0f, v4, q.c2);
+    sD[i] = fmaf(v1, 1.0f - v1, v3 + q.c2);  // binary: var_h = mu_h (1 - mu_h)
     ssg[i] = q.k * sqrtf(v3);
   }
   __syncthreads();
@@ -520,7 +526,7 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
     f32x4_t rs = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < 2 * RH + 4; ++t) {
-      const float ev = se[ly * SX + x4 + (R - RH) + t];
+      const float ev = sES[ly * SX + x4 + (R - RH) + t];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (t - k >= 0 && t - k <= 2 * RH) rs[k] = fmaf(win.g1[t - k], ev, rs[k]);
@@ -528,16 +534,23 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
     *(f32x4_t*)(rS + ly * LB_TX + x4) = rs;
   }
   __syncthreads();
+  // SSIM_j of every staged centre (A and C as in the toggle loop below)
+  for (int i = threadIdx.x; i < SY * SX; i += 256) {
+    const float mh = smh[i], mc = smc[i];
+    const float A = fmaf(2.0f * mh, mc, q.c1), C = fmaf(mh, mh, fmaf(mc, mc, q.c1));
+    sES[i] = (A * sB[i]) * __builtin_amdgcn_rcpf(C * sD[i]);
+  }
+  __syncthreads();
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
   const int ay = ay0 + ty, axb = ax0 + 4 * tx;
   if (ay >= H || axb >= W) return;
-  float delta[4], ca[4];
+  float delta[4], tca[4];  // the toggle, 2 c_a
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const bool ok = axb + k < W;
     const size_t oa = img + (size_t)ay * W + (ok ? axb + k : axb);
     delta[k] = h[oa] ? -1.0f : 1.0f;
-    ca[k] = c[oa];
+    tca[k] = 2.0f * c[oa];
   }
   // HVS: 2 delta (G * e)_a + sum of G^2 over the valid centres (the product
   // of the valid rows' and the valid columns' sums of g^2)
@@ -574,25 +587,21 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
 #pragma unroll
     for (int jc = 0; jc < 2 * RS + 4; ++jc) {
       const int p = rowo + jc;
-      const float mh = smh[p], mc = smc[p], sg = ssg[p];
-      const float A = 2.0f * mh * mc + q.c1;
-      const float Bc = 2.0f * scv[p] + q.c2;
-      const float C = mh * mh + mc * mc + q.c1;
-      const float D = mh * (1.0f - mh) + svc[p] + q.c2;
-      const float CD = C * D, ABc = A * Bc, twomh = 2.0f * mh, omtmh = 1.0f - 2.0f * mh;
+      const float mh = smh[p], mc = smc[p], sg = ssg[p], Bc = sB[p], D = sD[p], S = sES[p];
+      const float twomh = 2.0f * mh, tmc = 2.0f * mc, omtmh = 1.0f - twomh;
+      const float A = fmaf(twomh, mc, q.c1), C = fmaf(mh, mh, fmaf(mc, mc, q.c1));
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int jt = jc - k;
         if (jt < 0 || jt > 2 * RS) continue;
         const float wa = sw[(RS - i) * NSW + (2 * RS - jt)];
-        const float dw = delta[k] * wa;
-        const float dA = 2.0f * dw * mc;
-        const float dB = 2.0f * dw * (ca[k] - mc);
-        const float dC = dw * (twomh + dw);
-        const float dD = dw * (omtmh - dw);
-        const float num = CD * (A * dB + Bc * dA + dA * dB) - ABc * (C * dD + D * dC + dC * dD);
-        const float den = (C + dC) * (D + dD) * CD;
-        dcs[k] = fmaf(sg, num * __builtin_amdgcn_rcpf(den), dcs[k]);
+        const float dw = delta[k] * wa;  // the change of mu_h
+        const float A2 = fmaf(dw, tmc, A);                // + 2 dw mu_c
+        const float B2 = fmaf(dw, tca[k] - tmc, Bc);      // + 2 dw (c_a - mu_c)
+        const float C2 = fmaf(dw, twomh + dw, C);         // + dw (2 mu_h + dw)
+        const float D2 = fmaf(dw, omtmh - dw, D);         // + dw (1 - 2 mu_h - dw)
+        const float t = fmaf(A2 * B2, __builtin_amdgcn_rcpf(C2 * D2), -S);
+        dcs[k] = fmaf(sg, t, dcs[k]);
       }
     }
   }
