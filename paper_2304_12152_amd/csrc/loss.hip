@@ -239,25 +239,54 @@ __global__ __launch_bounds__(256) void loss_stats_rb_kernel(const uint8_t* __res
     }
   }
   float vh[4] = {0.f, 0.f, 0.f, 0.f}, vc[4] = {0.f, 0.f, 0.f, 0.f}, cov[4] = {0.f, 0.f, 0.f, 0.f};
+  if (q.levels == 2) {
+    // binary h (0 or 1) and window weights summing to 1: var_h = mu_h (1 -
+    // mu_h) and cov = sum w h (c - mu_c), the h - mu_h centring adding
+    // mu_h sum w (c - mu_c) = 0; c stays centred for var_c and cov
 #pragma unroll 1
-  for (int i = R - RS; i <= R + RS; ++i) {
-    const int wi = i - (R - RS);
-    float hv[NS], cv[NS];
+    for (int i = R - RS; i <= R + RS; ++i) {
+      const int wi = i - (R - RS);
+      float hv[NS], cv[NS];
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      hv[j] = hr0[i * SX + j];
-      cv[j] = cr0[i * SX + j];
+      for (int j = 0; j < NS; ++j) {
+        hv[j] = hr0[i * SX + j];
+        cv[j] = cr0[i * SX + j];
+      }
+#pragma unroll
+      for (int j = 0; j < 2 * RS + 1; ++j) {
+        const float wv = sw[wi * (2 * RS + 1) + j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int p = k + j + (R - RS);
+          const float dc = cv[p] - mc[k], wdc = wv * dc;
+          vc[k] = fmaf(wdc, dc, vc[k]);
+          cov[k] = fmaf(wdc, hv[p], cov[k]);
+        }
+      }
     }
 #pragma unroll
-    for (int j = 0; j < 2 * RS + 1; ++j) {
-      const float wv = sw[wi * (2 * RS + 1) + j];
+    for (int k = 0; k < 4; ++k) vh[k] = mh[k] * (1.0f - mh[k]);
+  } else {
+#pragma unroll 1
+    for (int i = R - RS; i <= R + RS; ++i) {
+      const int wi = i - (R - RS);
+      float hv[NS], cv[NS];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int p = k + j + (R - RS);
-        const float dh = hv[p] - mh[k], dc = cv[p] - mc[k];
-        vh[k] = fmaf(wv * dh, dh, vh[k]);
-        vc[k] = fmaf(wv * dc, dc, vc[k]);
-        cov[k] = fmaf(wv * dh, dc, cov[k]);
+      for (int j = 0; j < NS; ++j) {
+        hv[j] = hr0[i * SX + j];
+        cv[j] = cr0[i * SX + j];
+      }
+#pragma unroll
+      for (int j = 0; j < 2 * RS + 1; ++j) {
+        const float wv = sw[wi * (2 * RS + 1) + j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int p = k + j + (R - RS);
+          const float dh = hv[p] - mh[k], dc = cv[p] - mc[k];
+          vh[k] = fmaf(wv * dh, dh, vh[k]);
+          vc[k] = fmaf(wv * dc, dc, vc[k]);
+          cov[k] = fmaf(wv * dh, dc, cov[k]);
+        }
       }
     }
   }
