@@ -1303,6 +1303,8 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
   HS_TRY(launch_le_grad(act, contones, probs, 1, B, H, W, lp, win, lw.maps, gradp, s));
   const long M = (long)(H - 2 * m) * (W - 2 * m);
   const size_t nact = (size_t)B * H * W;
+  // the rows of the 32->32 layers' weight-gradient partial sums per batch
+  const int rows32 = precision == HS_BF16 ? bwd32_grid(num_cus()) : WGRAD_BLOCKS;
   if (Bg > 0) {
     // the second stream also takes the reported metrics' action count and
     // the loss sums (both after the batch's loss statistics), off the
@@ -1320,15 +1322,15 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
                               s2));
     const FwdInput gin{gray, gray_seeds, kind, st};
     HS_TRY(run_backward(weights, gradg, nullptr, Bg, Hg, Wg, precision, pwg, 0, s2, &gin, false));
+    // its weight-gradient rows' group sums, beside the batch's backward
+    HS_TRY(launch_reduce_rows(pwg.partials, WGRAD_BLOCKS, rows32, pwg.rtmp, s2));
     HS_TRY(hipEventRecord(side->join, s2));
   }
   // batch: backward
   const FwdInput fin{contones, seeds, kind, st};
   HS_TRY(run_backward(weights, gradp, nullptr, B, H, W, precision, pw, 0, s, &fin, false));
+  HS_TRY(launch_reduce_rows(pw.partials, WGRAD_BLOCKS, rows32, pw.rtmp, s));
   if (Bg > 0) HS_TRY(hipStreamWaitEvent(s, side->join, 0));
-  HS_TRY(launch_reduce_partials(pw.partials, Bg > 0 ? 2 * WGRAD_BLOCKS : WGRAD_BLOCKS,
-                                precision == HS_BF16 ? bwd32_grid(num_cus()) : WGRAD_BLOCKS,
-                                pw.rtmp, grad, s));
   if (Bg == 0) {
     HS_TRY(launch_loss_reduce(lw.tiles, B, lw.ntiles, lw.patches, npatch, lp.w_s, M, loss_out,
                               s));
@@ -1341,12 +1343,15 @@ int policy_train_step(float* weights, float* adam_m, float* adam_v, const float*
                           : (double)tp->lr_max;
   const double c1 = 1.0 - pow((double)tp->beta1, (double)(step + 1));
   const double c2 = 1.0 - pow((double)tp->beta2, (double)(step + 1));
+  // the gradient (the batch's group sums, then the side batch's) and Adam
+  float* gsq = pw.rtmp + (size_t)REDUCE_GROUPS * NPARAM;
+  HS_TRY(launch_reduce_adam(pw.rtmp, Bg > 0 ? pwg.rtmp : nullptr, grad, gsq, weights, adam_m,
+                            adam_v, (float)lr, tp->beta1, tp->beta2, tp->eps, (float)c1,
+                            (float)c2, s));
   if (grad_out_or_null)
     HS_TRY(hipMemcpyAsync(grad_out_or_null, grad, (size_t)NPARAM * 4, hipMemcpyDeviceToDevice, s));
-  HS_TRY(launch_train_metrics(loss_out, B, pw.rtmp + (size_t)REDUCE_GROUPS * NPARAM,
-                              pw.counter, nact, lp.levels, (float)lr, lp.w_a, metrics, s));
-  HS_TRY(launch_adam(weights, adam_m, adam_v, grad, NPARAM, (float)lr, tp->beta1, tp->beta2,
-                     tp->eps, (float)c1, (float)c2, s));
+  HS_TRY(launch_train_metrics(loss_out, B, gsq, pw.counter, nact, lp.levels, (float)lr, lp.w_a,
+                              metrics, s));
   if (actions_out_or_null)
     HS_TRY(hipMemcpyAsync(actions_out_or_null, act, (size_t)B * H * W, hipMemcpyDeviceToDevice, s));
   return HS_OK;

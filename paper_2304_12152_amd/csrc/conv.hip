@@ -1787,4 +1787,14 @@ hipError_t launch_reduce_partials(const float* partials, int rows, int rows32, f
   return hipGetLastError();
 }
 
+hipError_t launch_reduce_rows(const float* partials, int rows, int rows32, float* tmp,
+                              hipStream_t s) {
+  if (rows <= 0 || rows % WGRAD_BLOCKS != 0 || rows32 <= 0 || rows32 > WGRAD_BLOCKS)
+    return hipErrorInvalidValue;
+  reduce_partials_kernel<<<dim3((NPARAM + 255) / 256, REDUCE_GROUPS), 256, 0, s>>>(
+      partials, rows, rows32, tmp);
+  return hipGetLastError();
+}
+
+
 }  // namespace hs

@@ -221,6 +221,16 @@ constexpr int REDUCE_BLOCKS = (NPARAM + 255) / 256;
 int bwd32_grid(int num_cus);
 hipError_t launch_reduce_partials(const float* partials, int rows, int rows32, float* tmp,
                                   float* grad, hipStream_t s);
+// The two levels apart, for the train step: the group sums of the rows into
+// tmp[0..REDUCE_GROUPS) (launch_reduce_rows), then the gradient as tmp0's
+// group sums and then tmp1's (null: none) into grad, the per-block sums of
+// grad^2 into gsq, and the Adam update of w, m, v with it (train.hip; c1,
+// c2 the bias corrections 1 - beta^t).
+hipError_t launch_reduce_rows(const float* partials, int rows, int rows32, float* tmp,
+                              hipStream_t s);
+hipError_t launch_reduce_adam(const float* tmp0, const float* tmp1, float* grad, float* gsq,
+                              float* w, float* m, float* v, float lr, float b1, float b2,
+                              float eps, float c1, float c2, hipStream_t s);
 
 // loss.hip
 struct LossDev {  // the two normalised windows, passed to kernels by value
@@ -247,8 +257,6 @@ hipError_t launch_as(const float* pg, int Bg, int Hg, int Wg, float scale, int l
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t s);
 
 // train.hip
-hipError_t launch_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1,
-                       float b2, float eps, float c1, float c2, hipStream_t s);
 // the number of actions' ones (levels: the sum of the level indices) into
 // *counter
 hipError_t launch_count_actions(const uint8_t* actions, size_t nact,

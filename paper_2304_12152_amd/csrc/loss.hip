@@ -507,8 +507,8 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
 // error of the cancellation-free form of le_grad_kernel: both are set by
 // the rounding of the FP32 statistics, about 3e-7 of the largest change;
 // it takes 14 instead of about 26 operations per term.) A centre outside
-// the valid region has zero maps and zero sigma_c, so its SSIM term adds
-// exactly zero. A block covers 16 x 64 pixels.
+// the valid region has zero maps, zero sigma_c and a staged D of 1, so its
+// SSIM term adds exactly zero. A block covers 16 x 64 pixels.
 template <int RH, int RS>
 __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restrict__ h,
                                                          const float* __restrict__ c,
@@ -544,7 +544,9 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
     smh[i] = v1;
     smc[i] = v2;
     sB[i] = fmaf(2.0f, v4, q.c2);
-    sD[i] = fmaf(v1, 1.0f - v1, v3 + q.c2);  // binary: var_h = mu_h (1 - mu_h)
+    // binary: var_h = mu_h (1 - mu_h); outside the valid region D = 1 keeps
+    // the toggled C'D' away from zero (such a centre's term has sigma_c = 0)
+    sD[i] = in ? fmaf(v1, 1.0f - v1, v3 + q.c2) : 1.0f;
     ssg[i] = q.k * sqrtf(v3);
   }
   __syncthreads();

@@ -8,18 +8,36 @@
 
 namespace {
 
-__global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
-                            const float* __restrict__ g, int n, float lr, float b1, float b2,
-                            float eps, float inv_c1, float inv_c2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float mh = mi * inv_c1, vh = vi * inv_c2;
-  w[i] -= lr * mh / (sqrtf(vh) + eps);
+// The train step's last reduction level fused with Adam: parameter p's
+// gradient is the sum of the group sums tmp0[0..G) and then, if tmp1 is
+// given (the side batch's), tmp1[0..G), in that order; it goes to grad[p],
+// the block's sum of grad^2 to gsq[blockIdx.x] (waves in order), and Adam
+// updates w, m, v at p with it.
+__global__ __launch_bounds__(256) void reduce_groups_adam_kernel(
+    const float* __restrict__ tmp0, const float* __restrict__ tmp1, float* __restrict__ grad,
+    float* __restrict__ gsq, float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+    float lr, float b1, float b2, float eps, float inv_c1, float inv_c2) {
+  __shared__ float part[4];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  float s = 0.0f;
+  if (p < hs::NPARAM) {
+    for (int gi = 0; gi < hs::REDUCE_GROUPS; ++gi) s += tmp0[(size_t)gi * hs::NPARAM + p];
+    if (tmp1)
+      for (int gi = 0; gi < hs::REDUCE_GROUPS; ++gi) s += tmp1[(size_t)gi * hs::NPARAM + p];
+    grad[p] = s;
+    const float mi = b1 * m[p] + (1.0f - b1) * s;
+    const float vi = b2 * v[p] + (1.0f - b2) * s * s;
+    m[p] = mi;
+    v[p] = vi;
+    const float mh = mi * inv_c1, vh = vi * inv_c2;
+    w[p] -= lr * mh / (sqrtf(vh) + eps);
+  }
+  float q = s * s;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) gsq[blockIdx.x] = ((part[0] + part[1]) + part[2]) + part[3];
 }
 
 // Sum of the action bytes (bits, or level indices below 64). Each block sums
@@ -86,10 +104,11 @@ __global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
 
 namespace hs {
 
-hipError_t launch_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1,
-                       float b2, float eps, float c1, float c2, hipStream_t s) {
-  adam_kernel<<<(n + 255) / 256, 256, 0, s>>>(w, m, v, g, n, lr, b1, b2, eps, 1.0f / c1,
-                                              1.0f / c2);
+hipError_t launch_reduce_adam(const float* tmp0, const float* tmp1, float* grad, float* gsq,
+                              float* w, float* m, float* v, float lr, float b1, float b2,
+                              float eps, float c1, float c2, hipStream_t s) {
+  reduce_groups_adam_kernel<<<REDUCE_BLOCKS, 256, 0, s>>>(tmp0, tmp1, grad, gsq, w, m, v, lr, b1,
+                                                          b2, eps, 1.0f / c1, 1.0f / c2);
   return hipGetLastError();
 }
 
