@@ -573,6 +573,26 @@ def main():
                          "bits_differing_off_margin": mism}
         log("fp32: %.1f Mpx/s, speedup %.2f, mismatches %d" % (v32, value / v32, mism))
         del ws32, b32, l32
+        # the speedup split into precision and fusion: the training-mode
+        # forward (per-layer kernels, every activation map written to HBM)
+        # in FP32 and in BF16 on the same batch, beside the fused kernel
+        per_layer = {}
+        for name, prec in (("fp32", hb.HS_FP32), ("bf16", hb.HS_BF16)):
+            wsp = torch.empty(hb.lib().halftone_policy_workspace_size(B, H, W, prec),
+                              dtype=torch.uint8, device=dev)
+            hb.halftone_policy_forward(wt, ct, st, precision=prec, workspace=wsp)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(n32):
+                hb.halftone_policy_forward(wt, ct, st, precision=prec, workspace=wsp)
+            torch.cuda.synchronize()
+            per_layer[name] = (time.perf_counter() - t1) / n32 * 1e3
+            del wsp
+        extra["fp32"]["per_layer_forward_ms"] = {k: round(v, 3) for k, v in per_layer.items()}
+        extra["fp32"]["precision_factor"] = round(per_layer["fp32"] / per_layer["bf16"], 2)
+        extra["fp32"]["fusion_factor"] = round(per_layer["bf16"] / (avg_kernel_s * 1e3), 2)
+        log("per-layer forward: fp32 %.3f ms, bf16 %.3f ms, fused bf16 kernel %.3f ms"
+            % (per_layer["fp32"], per_layer["bf16"], avg_kernel_s * 1e3))
     if not args.no_train:
         Bt, Ht, Wt, Bg = 32, 256, 256, 64
         log("training step: 32 x 256 x 256 + 64 gray 64 x 64")
