@@ -73,6 +73,21 @@ def test_le_gradient_matches_oracle(orc, prm):
     assert np.abs(gl.cpu().numpy() - refl).max() <= 1e-4 * np.abs(refl).max()
 
 
+@pytest.mark.parametrize("level", [0.0, 0.37, 1.0])
+def test_le_gradient_on_flat_contones(orc, level):
+    # sigma_c = 0 at every window centre, so the SSIM part of every toggle
+    # is weighted by zero and only the HVS part remains (black, a mid gray
+    # and white; the binary kernel of the default windows)
+    B, H, W = 2, 40, 70
+    c = np.full((B, H, W), level, np.float32)
+    h = (np.random.default_rng(11).uniform(size=c.shape) < 0.4).astype(np.uint8)
+    gp, _ = hb.halftone_loss_backward(to_dev(h), to_dev(c))
+    gp = gp.cpu().numpy()
+    assert np.isfinite(gp).all()
+    ref = orc.le_grad_probs(h.astype(np.float64), c.astype(np.float64))
+    assert np.abs(gp - ref).max() <= 1e-4 * np.abs(ref).max()
+
+
 def test_le_gradient_c3_shape(orc):
     # 16 x 256 x 256 (the loss workload): every image's full map against the
     # oracle's, the whole batch in one oracle call (same -dR/B scaling)
