@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 METRIC = "halftone Mpixels/s (BF16 vs FP32 CNN, oracle-matched bits); train steps/s"
 FLOP_PER_PX = 75456          # 2 x (2*32*9 + 4*32*32*9 + 32*9) multiply-adds per pixel
 PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak (published)
+PEAK_HBM_TBS = 8.0           # MI355X HBM3E bandwidth (published)
 PEAK_FP8_TFLOPS = 5000.0     # MI355X dense FP8 matrix peak (published)
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (published)
 KERNEL_SRC = os.path.join(ROOT, "paper_2304_12152_amd", "csrc", "infer.hip")
@@ -613,9 +614,23 @@ def main():
         # conv work per step: forward 75,456 + input gradient 74,304 + weight
         # gradient 75,456 FLOP per pixel of the batch and of the gray side batch
         conv_flop = (Bt * Ht * Wt + Bg * 64 * 64) * (75456 + 74304 + 75456)
+        # HBM bytes per step of the per-layer design (each map, loss input
+        # and gradient read and written once, halos and the weight
+        # gradient's partial rows not counted), per pixel of the batch:
+        # first layer 76 (c in; a1, z, c out), four 32->32 layers 4 x 128,
+        # head 69 (a5 in; p, action out), loss statistics 25, LE gradient
+        # 33, action count 1, head backward 132 (g, a5 in; g5 out), four
+        # fused 32->32 backward passes 4 x 192 (g, a in; g out), first-layer
+        # weight gradient 72: 1,688 B; per pixel of the gray batch the same
+        # forward without actions (656), its anisotropy gradient 12 and the
+        # backward (972): 1,640 B
+        train_bytes = Bt * Ht * Wt * 1688 + Bg * 64 * 64 * 1640
         extra["train"] = {"value": round(sps, 2), "unit": "steps/s",
                           "conv_tflops": round(conv_flop * sps / 1e12, 1),
                           "mfma_frac": round(conv_flop * sps / 1e12 / PEAK_BF16_TFLOPS, 4),
+                          "hbm_gb_per_step": round(train_bytes / 1e9, 3),
+                          "hbm_tb_s": round(train_bytes * sps / 1e12, 2),
+                          "hbm_frac": round(train_bytes * sps / 1e12 / PEAK_HBM_TBS, 4),
                           "config": "32 x 256x256 crops + 64 constant-gray 64x64, BF16 "
                                     "activations, FP32 master weights, Adam"}
         log("train: %.2f steps/s" % sps)
