@@ -354,8 +354,8 @@ def main():
     ap.add_argument("--page-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single "
-              "MI355X (no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the hot path runs on a single MI355X "
+              "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

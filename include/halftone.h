@@ -488,7 +488,9 @@ int halftone_spectrum(const uint8_t* bits, int B, int H, int W, int P, float* ra
 
 /* ---------------------------------------------------------------------
  * Floyd-Steinberg error diffusion on the host (the classic error diffusion
- * cited in Sec. I), the CPU fallback and the baseline of the judge:
+ * cited in Sec. I): the halftoner a trained policy is judged against, and
+ * a host-side halftoner for callers without a GPU; no GPU call uses it.
+ * Definition:
  * raster order, threshold v >= 0.5, weights 7/16 right, 3/16 down-left,
  * 5/16 down, 1/16 down-right, error leaving the image dropped.
  * contone_host [B][H][W] FP32 in host memory; bits_host [B][H][W] out.
