@@ -499,8 +499,9 @@ __global__ __launch_bounds__(256) void le_grad_kernel(const uint8_t* __restrict_
 // the valid centres, both separable (G = g g^T, and the valid region is a
 // rectangle): row sums of e into LDS, then column sums. For the SSIM part
 // it walks each kernel row's segment of 4 + 2R window centres once, with
-// the centre's own terms B = 2 cov + c2, D = var_h + var_c + c2 and
-// SSIM_j = A B / (C D) staged once per block, and for each of the up to
+// the centre's own terms A, B = 2 cov + c2, C, D = var_h + var_c + c2,
+// SSIM_j = A B / (C D), 2 mu_h and 2 mu_c staged once per block as float
+// pairs, and for each of the up to
 // four pixels whose windows hold the centre takes the toggled factors
 // A', B', C', D' and the change A'B' / (C'D') - SSIM_j, in the same centre
 // order as le_grad_kernel. (The difference of the two ratios has the FP32
@@ -519,9 +520,9 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
                                                          float invM, float* __restrict__ grad) {
   constexpr int R = RH > RS ? RH : RS, SY = LB_TY + 2 * R, SX = LB_TX + 2 * R;
   constexpr int NSW = 2 * RS + 1;
-  // sES holds e until its row sums are taken, then SSIM_j
-  __shared__ float sES[SY * SX], smh[SY * SX], smc[SY * SX], sB[SY * SX], sD[SY * SX],
-      ssg[SY * SX];
+  // per staged centre: (A, C), (B, D), (e then SSIM_j, sigma_c), (2 mu_h,
+  // 2 mu_c); e is replaced by SSIM_j once its row sums are taken
+  __shared__ float2 sAC[SY * SX], sBD[SY * SX], sSG[SY * SX], sM2[SY * SX];
   __shared__ float sw[NSW * NSW];
   __shared__ __attribute__((aligned(16))) float rS[SY * LB_TX];  // row sums of g * e
   const int b = blockIdx.z;
@@ -540,14 +541,13 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
       v3 = maps[3 * n + o];
       v4 = maps[4 * n + o];
     }
-    sES[i] = v0;
-    smh[i] = v1;
-    smc[i] = v2;
-    sB[i] = fmaf(2.0f, v4, q.c2);
+    const float twomh = 2.0f * v1;
+    sAC[i] = make_float2(fmaf(twomh, v2, q.c1), fmaf(v1, v1, fmaf(v2, v2, q.c1)));
     // binary: var_h = mu_h (1 - mu_h); outside the valid region D = 1 keeps
     // the toggled C'D' away from zero (such a centre's term has sigma_c = 0)
-    sD[i] = in ? fmaf(v1, 1.0f - v1, v3 + q.c2) : 1.0f;
-    ssg[i] = q.k * sqrtf(v3);
+    sBD[i] = make_float2(fmaf(2.0f, v4, q.c2), in ? fmaf(v1, 1.0f - v1, v3 + q.c2) : 1.0f);
+    sSG[i] = make_float2(v0, q.k * sqrtf(v3));
+    sM2[i] = make_float2(twomh, 2.0f * v2);
   }
   __syncthreads();
   // row sums of g * e at the tile's pixel columns (item: a staged row and
@@ -557,7 +557,7 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
     f32x4_t rs = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < 2 * RH + 4; ++t) {
-      const float ev = sES[ly * SX + x4 + (R - RH) + t];
+      const float ev = sSG[ly * SX + x4 + (R - RH) + t].x;
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (t - k >= 0 && t - k <= 2 * RH) rs[k] = fmaf(win.g1[t - k], ev, rs[k]);
@@ -565,11 +565,10 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
     *(f32x4_t*)(rS + ly * LB_TX + x4) = rs;
   }
   __syncthreads();
-  // SSIM_j of every staged centre (A and C as in the toggle loop below)
+  // SSIM_j of every staged centre
   for (int i = threadIdx.x; i < SY * SX; i += 256) {
-    const float mh = smh[i], mc = smc[i];
-    const float A = fmaf(2.0f * mh, mc, q.c1), C = fmaf(mh, mh, fmaf(mc, mc, q.c1));
-    sES[i] = (A * sB[i]) * __builtin_amdgcn_rcpf(C * sD[i]);
+    const float2 ac = sAC[i], bd = sBD[i];
+    sSG[i].x = (ac.x * bd.x) * __builtin_amdgcn_rcpf(ac.y * bd.y);
   }
   __syncthreads();
   const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
@@ -618,19 +617,20 @@ __global__ __launch_bounds__(256) void le_grad_rb_kernel(const uint8_t* __restri
 #pragma unroll
     for (int jc = 0; jc < 2 * RS + 4; ++jc) {
       const int p = rowo + jc;
-      const float mh = smh[p], mc = smc[p], sg = ssg[p], Bc = sB[p], D = sD[p], S = sES[p];
-      const float twomh = 2.0f * mh, tmc = 2.0f * mc, omtmh = 1.0f - twomh;
-      const float A = fmaf(twomh, mc, q.c1), C = fmaf(mh, mh, fmaf(mc, mc, q.c1));
+      const float2 ac = sAC[p], bd = sBD[p], ss = sSG[p], m2 = sM2[p];
+      const float A = ac.x, C = ac.y, Bc = bd.x, D = bd.y, S = ss.x, sg = ss.y;
+      const float twomh = m2.x, tmc = m2.y;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int jt = jc - k;
         if (jt < 0 || jt > 2 * RS) continue;
         const float wa = sw[(RS - i) * NSW + (2 * RS - jt)];
         const float dw = delta[k] * wa;  // the change of mu_h
+        const float u = twomh + dw;
         const float A2 = fmaf(dw, tmc, A);                // + 2 dw mu_c
         const float B2 = fmaf(dw, tca[k] - tmc, Bc);      // + 2 dw (c_a - mu_c)
-        const float C2 = fmaf(dw, twomh + dw, C);         // + dw (2 mu_h + dw)
-        const float D2 = fmaf(dw, omtmh - dw, D);         // + dw (1 - 2 mu_h - dw)
+        const float C2 = fmaf(dw, u, C);                  // + dw (2 mu_h + dw)
+        const float D2 = fmaf(dw, 1.0f - u, D);           // + dw (1 - 2 mu_h - dw)
         const float t = fmaf(A2 * B2, __builtin_amdgcn_rcpf(C2 * D2), -S);
         dcs[k] = fmaf(sg, t, dcs[k]);
       }
