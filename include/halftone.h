@@ -435,6 +435,11 @@ int halftone_loss_backward(const uint8_t* actions, const float* contone,
  * tp->loss.flags & HS_CHECK_FINITE checks the contones (and gray levels).
  * actions_out_or_null [B][H][W] uint8: the sampled actions.
  * grad_out_or_null [HS_PARAM_COUNT] FP32: the total gradient before Adam.
+ * Streams: with Bg > 0 the side batch runs on a second stream that the
+ *          library owns per device (default priority), forked from
+ *          `stream` after the step's weight packing and joined back into
+ *          it before the gradient is summed, so every output is ordered on
+ *          `stream`; calls on one device take turns on that second stream.
  * --------------------------------------------------------------------- */
 size_t halftone_train_workspace_size(int B, int H, int W, int Bg, int Hg, int Wg,
                                      int precision);
